@@ -1,0 +1,128 @@
+"""Seeded synthetic inputs shaped like the paper's test matrices.
+
+This module holds only input generation: random orthogonal factors, singular
+value profiles, right-hand sides.  It contains none of the method's arithmetic
+(no multiplier, no elimination, no solve), and both the GPU tests and the CPU
+oracle draw their inputs from it.
+
+Recipes (Pan, Qian, Yan, arXiv:1406.5802, Section 8.1 builds test matrices as
+U Sigma V^T with U, V the Q factors of QR factorizations of random matrices):
+
+* ``haar(n, rng)``: Q of a Gaussian matrix with the diagonal of R made
+  positive, which makes Q Haar-distributed.
+* ``conditioned(n, kappa, seed)``: Q1 diag(sigma) Q2^T with
+  sigma_i = kappa^(-i/(n-1)), so ||A||_2 = 1 and kappa_2(A) = kappa exactly
+  (up to the rounding of the product).
+* ``breakdown_case(seed)``: n = 256, kappa = 1e4, then row 63 of the leading
+  64 x 64 block is zeroed (entries A[63, 0:64]); the leading 64 x 64 block is
+  singular while A stays nonsingular, so plain GENP meets an exactly zero pivot.
+* ``paper_e1(n, seed)``: the Section 8.1 family A = [[A_k, B], [C, D]] with
+  k = n/2, A_k = U diag(1,..,1,0,0,0,0) V^T (nullity 4) and B, C, D Gaussian
+  Toeplitz matrices scaled to unit spectral norm.
+* ``precision_kappa(seed)``: kappa = 10^(1 + 7 u), u uniform on [0, 1).
+* ``rhs(n, nrhs, seed)``: i.i.d. N(0, 1).
+
+The torch variants build the same recipes on a GPU for sizes where a CPU QR
+would take minutes; they are not bitwise equal to the numpy ones.
+"""
+from __future__ import annotations
+
+import numpy as np
+
+
+def _rng(seed: int, salt: int) -> np.random.Generator:
+    return np.random.default_rng([int(seed), int(salt)])
+
+
+def haar(n: int, rng: np.random.Generator) -> np.ndarray:
+    X = rng.standard_normal((n, n))
+    Q, R = np.linalg.qr(X)
+    s = np.sign(np.diag(R))
+    s[s == 0] = 1.0
+    return Q * s[None, :]
+
+
+def sigma_profile(n: int, kappa: float) -> np.ndarray:
+    if n == 1:
+        return np.ones(1)
+    return float(kappa) ** (-np.arange(n, dtype=np.float64) / (n - 1))
+
+
+def conditioned(n: int, kappa: float, seed: int) -> np.ndarray:
+    rng = _rng(seed, 1)
+    Q1 = haar(n, rng)
+    Q2 = haar(n, rng)
+    return (Q1 * sigma_profile(n, kappa)[None, :]) @ Q2.T
+
+
+def breakdown_case(seed: int, n: int = 256, kappa: float = 1e4, lead: int = 64) -> np.ndarray:
+    A = conditioned(n, kappa, seed)
+    A[lead - 1, 0:lead] = 0.0
+    return A
+
+
+def _toeplitz_gaussian(m: int, rng: np.random.Generator) -> np.ndarray:
+    t = rng.standard_normal(2 * m - 1)
+    idx = np.arange(m)[:, None] - np.arange(m)[None, :]
+    T = t[idx + (m - 1)]
+    return T / np.linalg.norm(T, 2)
+
+
+def paper_e1(n: int, seed: int) -> np.ndarray:
+    k = n // 2
+    rng = _rng(seed, 2)
+    U = haar(k, rng)
+    V = haar(k, rng)
+    s = np.ones(k)
+    s[k - 4:] = 0.0
+    Ak = (U * s[None, :]) @ V.T
+    B = _toeplitz_gaussian(k, rng)
+    C = _toeplitz_gaussian(k, rng)
+    D = _toeplitz_gaussian(k, rng)
+    return np.block([[Ak, B], [C, D]])
+
+
+def precision_kappa(seed: int) -> float:
+    return float(10.0 ** (1.0 + 7.0 * _rng(seed, 3).random()))
+
+
+def rhs(n: int, nrhs: int, seed: int) -> np.ndarray:
+    return _rng(seed, 4).standard_normal((n, nrhs))
+
+
+def integer_matrix(n: int, seed: int, lo: int = -3, hi: int = 3) -> np.ndarray:
+    """Small-integer matrix (exact-arithmetic tests)."""
+    return _rng(seed, 5).integers(lo, hi + 1, size=(n, n)).astype(np.float64)
+
+
+# ---------------------------------------------------------------------------
+# GPU-side generation of the same recipes for large n (torch, seeded).
+# ---------------------------------------------------------------------------
+
+def conditioned_torch(n: int, kappa: float, seed: int, device="cuda"):
+    import torch
+
+    g = torch.Generator(device=device)
+    g.manual_seed(int(seed) * 1000003 + 17)
+
+    def _haar():
+        X = torch.randn((n, n), generator=g, dtype=torch.float64, device=device)
+        Q, R = torch.linalg.qr(X)
+        s = torch.sign(torch.diagonal(R))
+        s[s == 0] = 1.0
+        return Q * s[None, :]
+
+    Q1 = _haar()
+    Q2 = _haar()
+    sig = torch.as_tensor(sigma_profile(n, kappa), dtype=torch.float64, device=device)
+    A = torch.matmul(Q1 * sig[None, :], Q2.T.contiguous())
+    del Q1, Q2
+    return A.contiguous()
+
+
+def rhs_torch(n: int, nrhs: int, seed: int, device="cuda"):
+    import torch
+
+    g = torch.Generator(device=device)
+    g.manual_seed(int(seed) * 1000003 + 29)
+    return torch.randn((n, nrhs), generator=g, dtype=torch.float64, device=device)
