@@ -1,0 +1,159 @@
+/*
+ * rmge.h -- random-multiplier Gaussian elimination on AMD Instinct MI355X (gfx950).
+ *
+ * Solves A x = b for a nonsingular n x n matrix A by the method of Pan, Qian
+ * and Yan, "Random multipliers numerically stabilize Gaussian and block
+ * Gaussian elimination" (arXiv:1406.5802):
+ *
+ *   1. draw a random multiplier H (Definition defrndm: a standard Gaussian
+ *      matrix; or a circulant matrix with a Gaussian first column, Section 6;
+ *      or a Toeplitz matrix, the leading block of a larger random circulant);
+ *   2. form M = A H (post-multiplication, Fact faprepr);
+ *   3. factor M = L U by block Gaussian elimination with no pivoting
+ *      (Section 3, eq. eqgenp applied to pivot blocks of `block` columns;
+ *      in exact arithmetic the result does not depend on the block size,
+ *      by the order-independence argument after eq. eqgenpin);
+ *   4. solve L U y = b and return x = H y (Fact faprepr), optionally followed
+ *      by FP64 iterative refinement (Section 8.1 protocol).
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ * - All matrix and vector pointers are DEVICE pointers on the current HIP
+ *   device, row-major, with the given leading dimension (in elements).
+ *   Right-hand sides B and solutions X are n x nrhs, row-major.
+ * - `hip_stream` is a hipStream_t passed as void*; NULL means the legacy
+ *   default stream.  All work is enqueued on that stream.  Calls that return a
+ *   numerical status (factor, solve) synchronise that stream before returning.
+ * - Ownership: the caller owns A, B, X, W, Y.  The handle owns the factors,
+ *   the multiplier state and its workspace.  The handle BORROWS A: A must stay
+ *   alive and unchanged until rmge_destroy (it is read by refinement).
+ *   A itself is never written.
+ * - Errors are returned as rmge_status; nothing is thrown across the ABI.
+ *   Device or allocation failures leave *out untouched (NULL-initialised by
+ *   the caller is recommended).  On RMGE_ZERO_PIVOT / RMGE_NONFINITE the handle
+ *   IS returned, with stats.info set; solves on such a handle return the same
+ *   status without computing.
+ * - Threads: handles are independent; calls on one handle must not overlap.
+ */
+#ifndef RMGE_H
+#define RMGE_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* Multiplier kinds (the right multiplier H; post-multiplication only, the
+ * case the paper proves, Section 4 after Fact faprepr). */
+typedef enum {
+    RMGE_MULT_NONE = 0,      /* H = I: plain GENP, shows breakdown (Corollary corec) */
+    RMGE_MULT_GAUSSIAN = 1,  /* n x n i.i.d. N(0,1) (Definition defrndm), dense product */
+    RMGE_MULT_CIRCULANT = 2, /* H[i][j] = c[(i-j) mod n], c i.i.d. N(0,1) (Section 6), FFT */
+    RMGE_MULT_TOEPLITZ = 3   /* H[i][j] = t_{i-j}, 2n-1 i.i.d. N(0,1) parameters, FFT */
+} rmge_mult;
+
+/* Precision of the factors L, U (and of the multiplier product M = A H).
+ * Residuals and solution updates of refinement are always FP64. */
+typedef enum {
+    RMGE_F64 = 0, /* FP64 MFMA */
+    RMGE_F32 = 1  /* FP32 MFMA with FP32 accumulation; refine in FP64 */
+} rmge_prec;
+
+typedef enum {
+    RMGE_OK = 0,
+    RMGE_EINVAL = 1,        /* bad argument (size, leading dimension, kind, block) */
+    RMGE_ENOMEM = 2,        /* device allocation failed */
+    RMGE_EDEVICE = 3,       /* HIP runtime error, or no gfx950 device */
+    RMGE_ZERO_PIVOT = 4,    /* a pivot is exactly 0: M is not strongly nonsingular */
+    RMGE_NONFINITE = 5,     /* a pivot is Inf or NaN */
+    RMGE_NOT_CONVERGED = 6  /* refinement stopped above tol; X holds the last iterate */
+} rmge_status;
+
+typedef struct rmge_factors rmge_factors; /* opaque; owned by the library */
+
+typedef struct {
+    int64_t info;          /* 0-based index of the first zero / non-finite pivot, -1 if none */
+    int32_t status;        /* RMGE_OK, RMGE_ZERO_PIVOT or RMGE_NONFINITE */
+    int32_t block;         /* panel width used */
+    double min_abs_pivot;  /* min_k |u_kk| (computed on demand, see rmge_factor_stats_get) */
+    double growth;         /* max |U| / max |M| */
+    double ms_multiplier;  /* device time: multiplier generation + M = A H */
+    double ms_factor;      /* device time: elimination */
+} rmge_factor_stats;
+
+typedef struct {
+    int32_t iters;     /* refinement steps performed */
+    int32_t converged; /* 1 if eta <= tol (or tol <= 0) */
+    double eta0;       /* backward error before refinement */
+    double eta;        /* final eta = max_r ||b_r - A x_r||_inf / (||A||_inf ||x_r||_inf + ||b_r||_inf) */
+    double eta_hist[17]; /* eta after 0, 1, ... refinement steps (first iters + 1 entries) */
+} rmge_solve_stats;
+
+/* Factor A H = L U with the defaults: FP64, lda = n, default stream.
+ * A: device, n x n row-major.  kind: rmge_mult.  seed: the multiplier's
+ * random-number seed.  block: panel width, 1..256 (0 selects 256; 1 is
+ * column-by-column GENP).  On success *out receives a new handle. */
+rmge_status rmge_factor(const double *A, int64_t n, int32_t kind, uint64_t seed, int32_t block,
+                        rmge_factors **out);
+
+/* As rmge_factor with a leading dimension lda >= n, a factor precision
+ * (rmge_prec) and a stream. */
+rmge_status rmge_factor_ex(const double *A, int64_t n, int64_t lda, int32_t kind, uint64_t seed,
+                           int32_t block, int32_t prec, void *hip_stream, rmge_factors **out);
+
+/* Re-run the factorization of an existing handle on a new A of the same size
+ * (same kind, precision, block and stream), reusing every allocation.  The new
+ * A replaces the borrowed one. */
+rmge_status rmge_refactor(rmge_factors *f, const double *A, int64_t lda, uint64_t seed);
+
+/* X = A^{-1} B through A H Y = B, X = H Y (Fact faprepr), then refinement:
+ * while step < max_refine and (tol <= 0 or eta > tol):
+ *     R = B - A X (FP64);  D = H U^{-1} L^{-1} R (factor precision);  X += D (FP64).
+ * tol <= 0 runs exactly max_refine steps (the paper's protocol: one).
+ * B, X: device, n x nrhs, row-major, ldb, ldx >= nrhs; X may not alias B.
+ * max_refine <= 16.  st may be NULL.  Returns RMGE_NOT_CONVERGED if tol > 0
+ * and eta > tol after max_refine steps. */
+rmge_status rmge_solve(const rmge_factors *f, const double *B, int64_t nrhs, int64_t ldb,
+                       double *X, int64_t ldx, int32_t max_refine, double tol,
+                       rmge_solve_stats *st);
+
+/* Y = A^{-T} W = L^{-T} U^{-T} H^T W (the adjoint, from A^{-1} = H (A H)^{-1},
+ * Fact faprepr).  Reuses L and U.  W, Y: device, n x nrhs, row-major. */
+rmge_status rmge_solve_adjoint(const rmge_factors *f, const double *W, int64_t nrhs, int64_t ldw,
+                               double *Y, int64_t ldy);
+
+/* Factor statistics.  min_abs_pivot and growth are computed on the device at
+ * the first call (one pass over M's diagonal and U) and cached. */
+rmge_status rmge_factor_stats_get(const rmge_factors *f, rmge_factor_stats *s);
+
+/* Copy the packed factors (unit L strictly below the diagonal, U on and above)
+ * into LU (device, n x n, ld >= n), converted to FP64. */
+rmge_status rmge_factors_lu(const rmge_factors *f, double *LU, int64_t ld);
+
+/* The multiplier's random parameters as drawn by the library: kind GAUSSIAN
+ * gives n*n values (G row-major), CIRCULANT n (c), TOEPLITZ 2n-1 (tau, with
+ * tau[0..n-1] = t_0..t_{n-1} and tau[n-1+d] = t_{-d}).  out: device, FP64. */
+rmge_status rmge_multiplier_params(int32_t kind, int64_t n, uint64_t seed, double *out,
+                                   void *hip_stream);
+
+/* Number of parameters rmge_multiplier_params writes (0 for NONE or bad kind). */
+int64_t rmge_param_count(int32_t kind, int64_t n);
+
+/* M = A H in FP64 (the preprocessing product alone): dense MFMA product for
+ * GAUSSIAN, FFT correlation for CIRCULANT and TOEPLITZ, copy for NONE.
+ * A, M: device n x n, lda, ldm >= n; M may not alias A. */
+rmge_status rmge_precondition(const double *A, int64_t n, int64_t lda, int32_t kind,
+                              uint64_t seed, double *M, int64_t ldm, void *hip_stream);
+
+void rmge_destroy(rmge_factors *f);
+
+const char *rmge_status_string(int32_t s);
+
+/* Library version as major*10000 + minor*100 + patch. */
+int32_t rmge_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* RMGE_H */

@@ -1,0 +1,160 @@
+"""ctypes declarations of the C ABI in include/rmge.h (same names, same arguments).
+
+Loading fails loudly if ``librmge.so`` has not been built: there is no CPU
+fallback for any step of the method.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "librmge.so")
+
+RMGE_MULT_NONE, RMGE_MULT_GAUSSIAN, RMGE_MULT_CIRCULANT, RMGE_MULT_TOEPLITZ = 0, 1, 2, 3
+RMGE_F64, RMGE_F32 = 0, 1
+(RMGE_OK, RMGE_EINVAL, RMGE_ENOMEM, RMGE_EDEVICE, RMGE_ZERO_PIVOT, RMGE_NONFINITE,
+ RMGE_NOT_CONVERGED) = range(7)
+
+STATUS_NAMES = {
+    0: "RMGE_OK", 1: "RMGE_EINVAL", 2: "RMGE_ENOMEM", 3: "RMGE_EDEVICE",
+    4: "RMGE_ZERO_PIVOT", 5: "RMGE_NONFINITE", 6: "RMGE_NOT_CONVERGED",
+}
+
+# Every function the header declares, for the export check.
+EXPORTS = (
+    "rmge_factor", "rmge_factor_ex", "rmge_refactor", "rmge_solve", "rmge_solve_adjoint",
+    "rmge_factor_stats_get", "rmge_factors_lu", "rmge_multiplier_params", "rmge_param_count",
+    "rmge_precondition", "rmge_destroy", "rmge_status_string", "rmge_version",
+)
+
+
+class rmge_factor_stats(ctypes.Structure):
+    _fields_ = [("info", ctypes.c_int64), ("status", ctypes.c_int32), ("block", ctypes.c_int32),
+                ("min_abs_pivot", ctypes.c_double), ("growth", ctypes.c_double),
+                ("ms_multiplier", ctypes.c_double), ("ms_factor", ctypes.c_double)]
+
+
+class rmge_solve_stats(ctypes.Structure):
+    _fields_ = [("iters", ctypes.c_int32), ("converged", ctypes.c_int32),
+                ("eta0", ctypes.c_double), ("eta", ctypes.c_double),
+                ("eta_hist", ctypes.c_double * 17)]
+
+
+_lib = None
+
+
+def lib() -> ctypes.CDLL:
+    """The loaded library; raises if it was never built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(
+            "librmge.so is not built (expected %s); build it with "
+            "`python paper_1406_5802_amd/build.py` -- there is no fallback" % LIB_PATH)
+    L = ctypes.CDLL(LIB_PATH)
+    i64, i32, u64, vp, dp = (ctypes.c_int64, ctypes.c_int32, ctypes.c_uint64, ctypes.c_void_p,
+                             ctypes.c_void_p)
+    hp = ctypes.POINTER(ctypes.c_void_p)
+    L.rmge_factor.argtypes = [dp, i64, i32, u64, i32, hp]
+    L.rmge_factor_ex.argtypes = [dp, i64, i64, i32, u64, i32, i32, vp, hp]
+    L.rmge_refactor.argtypes = [vp, dp, i64, u64]
+    L.rmge_solve.argtypes = [vp, dp, i64, i64, dp, i64, i32, ctypes.c_double,
+                             ctypes.POINTER(rmge_solve_stats)]
+    L.rmge_solve_adjoint.argtypes = [vp, dp, i64, i64, dp, i64]
+    L.rmge_factor_stats_get.argtypes = [vp, ctypes.POINTER(rmge_factor_stats)]
+    L.rmge_factors_lu.argtypes = [vp, dp, i64]
+    L.rmge_multiplier_params.argtypes = [i32, i64, u64, dp, vp]
+    L.rmge_param_count.argtypes = [i32, i64]
+    L.rmge_param_count.restype = i64
+    L.rmge_precondition.argtypes = [dp, i64, i64, i32, u64, dp, i64, vp]
+    L.rmge_destroy.argtypes = [vp]
+    L.rmge_destroy.restype = None
+    L.rmge_status_string.argtypes = [i32]
+    L.rmge_status_string.restype = ctypes.c_char_p
+    L.rmge_version.restype = i32
+    for name in ("rmge_factor", "rmge_factor_ex", "rmge_refactor", "rmge_solve",
+                 "rmge_solve_adjoint", "rmge_factor_stats_get", "rmge_factors_lu",
+                 "rmge_multiplier_params", "rmge_precondition"):
+        getattr(L, name).restype = ctypes.c_int
+    _lib = L
+    return L
+
+
+def status_string(s: int) -> str:
+    return lib().rmge_status_string(int(s)).decode()
+
+
+class RMGEError(RuntimeError):
+    def __init__(self, status: int, what: str = ""):
+        self.status = int(status)
+        name = STATUS_NAMES.get(self.status, str(status))
+        super().__init__("%s%s: %s" % (what + " -> " if what else "", name,
+                                       status_string(self.status) if _lib else name))
+
+
+# Thin wrappers with the C names: pointers are ints (device addresses).
+
+def rmge_factor_ex(A: int, n: int, lda: int, kind: int, seed: int, block: int, prec: int,
+                   stream: int):
+    h = ctypes.c_void_p()
+    rc = lib().rmge_factor_ex(A, n, lda, kind, ctypes.c_uint64(seed & (2**64 - 1)), block, prec,
+                              stream, ctypes.byref(h))
+    return rc, h
+
+
+def rmge_factor(A: int, n: int, kind: int, seed: int, block: int):
+    h = ctypes.c_void_p()
+    rc = lib().rmge_factor(A, n, kind, ctypes.c_uint64(seed & (2**64 - 1)), block, ctypes.byref(h))
+    return rc, h
+
+
+def rmge_refactor(h, A: int, lda: int, seed: int) -> int:
+    return lib().rmge_refactor(h, A, lda, ctypes.c_uint64(seed & (2**64 - 1)))
+
+
+def rmge_solve(h, B: int, nrhs: int, ldb: int, X: int, ldx: int, max_refine: int, tol: float):
+    st = rmge_solve_stats()
+    rc = lib().rmge_solve(h, B, nrhs, ldb, X, ldx, max_refine, tol, ctypes.byref(st))
+    return rc, st
+
+
+def rmge_solve_adjoint(h, W: int, nrhs: int, ldw: int, Y: int, ldy: int) -> int:
+    return lib().rmge_solve_adjoint(h, W, nrhs, ldw, Y, ldy)
+
+
+def rmge_factor_stats_get(h):
+    st = rmge_factor_stats()
+    rc = lib().rmge_factor_stats_get(h, ctypes.byref(st))
+    return rc, st
+
+
+def rmge_factors_lu(h, LU: int, ld: int) -> int:
+    return lib().rmge_factors_lu(h, LU, ld)
+
+
+def rmge_multiplier_params(kind: int, n: int, seed: int, out: int, stream: int) -> int:
+    return lib().rmge_multiplier_params(kind, n, ctypes.c_uint64(seed & (2**64 - 1)), out, stream)
+
+
+def rmge_param_count(kind: int, n: int) -> int:
+    return int(lib().rmge_param_count(kind, n))
+
+
+def rmge_precondition(A: int, n: int, lda: int, kind: int, seed: int, M: int, ldm: int,
+                      stream: int) -> int:
+    return lib().rmge_precondition(A, n, lda, kind, ctypes.c_uint64(seed & (2**64 - 1)), M, ldm,
+                                   stream)
+
+
+def rmge_destroy(h) -> None:
+    lib().rmge_destroy(h)
+
+
+def rmge_status_string(s: int) -> str:
+    return status_string(s)
+
+
+def rmge_version() -> int:
+    return int(lib().rmge_version())

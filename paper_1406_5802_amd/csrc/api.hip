@@ -1,0 +1,664 @@
+// C ABI of the library: handle management and the order of the method's steps.
+//
+//   factor:  H from the seed  ->  M = A H  ->  block elimination with no
+//            pivoting on M (eq. eqgenp with pivot blocks of `block` columns);
+//   solve:   x = H U^{-1} L^{-1} b (Fact faprepr), then refinement
+//            r = b - A x (FP64), x += H U^{-1} L^{-1} r (Section 8.1);
+//   adjoint: y = L^{-T} U^{-T} H^T w.
+//
+// Device memory layout (one handle, factor precision T):
+//   lu    n x ld  (ld = n rounded up to 64)  the packed factors, over M
+//   mult  GAUSSIAN: n x n of T, G row-major; CIRCULANT/TOEPLITZ: parameters,
+//         the period-m kernel h, its half spectrum and the twiddle table
+//   inv   two 256 x 256 arrays holding, on their diagonals, the inverses of the
+//         32 x 32 diagonal sub-blocks of the current pivot block's L and U
+//   solve workspace, grown on demand: two n x nrhs of T, one n x nrhs FP64
+//         residual, norms
+#include <hip/hip_runtime.h>
+
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <new>
+#include <vector>
+
+#include "../../include/rmge.h"
+#include "rmge_impl.h"
+
+using namespace rmge;
+
+struct rmge_factors {
+    int64_t n = 0, lda = 0, ld = 0;
+    int32_t kind = 0, prec = 0, block = 0;
+    uint64_t seed = 0;
+    hipStream_t stream = nullptr;
+    const double *A = nullptr;
+    void *lu = nullptr;
+    void *G = nullptr;         // GAUSSIAN multiplier (T)
+    double *params = nullptr;  // structured multiplier parameters
+    double *hker = nullptr;    // period-m kernel
+    double *hhat = nullptr;    // half spectrum (m/2 + 1 complex)
+    double *tw = nullptr;      // twiddles (m/2 + 1 complex)
+    int m = 0;
+    void *inv = nullptr;
+    DevStatus *st = nullptr;
+    double *scal = nullptr;  // [0] max|U| [1] min|u_kk| [2] max|M| [3] ||A||_inf
+    // solve workspace
+    int64_t ws_nrhs = 0;
+    void *wy = nullptr, *wx = nullptr;
+    double *wr = nullptr, *wnorm = nullptr;
+    double *wt = nullptr;
+    int64_t wt_size = 0;
+    // host copies
+    DevStatus host_st{-1, 0, 0};
+    bool stats_done = false;
+    bool anorm_done = false;
+    double anorm = 0.0;
+    rmge_factor_stats stats{};
+    hipEvent_t ev[3] = {nullptr, nullptr, nullptr};
+};
+
+namespace {
+
+constexpr int kSolveBlock = 64;
+constexpr int kInvLd = kMaxBlock;
+
+int64_t round_up(int64_t x, int64_t m) { return (x + m - 1) / m * m; }
+
+rmge_status from_hip(hipError_t e) {
+    if (e == hipSuccess) return RMGE_OK;
+    if (e == hipErrorOutOfMemory) return RMGE_ENOMEM;
+    return RMGE_EDEVICE;
+}
+
+#define RMGE_TRY(expr)                                         \
+    do {                                                       \
+        hipError_t _e = (expr);                                \
+        if (_e != hipSuccess) {                                \
+            if (std::getenv("RMGE_DEBUG"))                     \
+                std::fprintf(stderr, "rmge: %s failed: %s\n", #expr, hipGetErrorString(_e)); \
+            return from_hip(_e);                               \
+        }                                                      \
+    } while (0)
+
+#define HIP_TRY(expr)                      \
+    do {                                   \
+        hipError_t _e = (expr);            \
+        if (_e != hipSuccess) return _e;   \
+    } while (0)
+
+size_t elem_size(int prec) { return prec == RMGE_F32 ? sizeof(float) : sizeof(double); }
+
+bool is_pow2(int64_t x) { return x > 0 && (x & (x - 1)) == 0; }
+
+int64_t next_pow2(int64_t x) {
+    int64_t p = 1;
+    while (p < x) p <<= 1;
+    return p;
+}
+
+// FFT period for the structured multipliers (0 if unsupported).
+int fft_period(int kind, int64_t n) {
+    int64_t m;
+    if (kind == RMGE_MULT_CIRCULANT && n >= 2 && is_pow2(n))
+        m = n;
+    else
+        m = next_pow2(2 * n - 1);
+    if (m < 2) m = 2;
+    return m <= 16384 ? static_cast<int>(m) : 0;
+}
+
+bool device_ok() {
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return false;
+    hipDeviceProp_t p;
+    if (hipGetDeviceProperties(&p, dev) != hipSuccess) return false;
+    return std::strncmp(p.gcnArchName, "gfx950", 6) == 0;
+}
+
+__global__ void k_reset(DevStatus *st, double *scal) {
+    st->info = -1;
+    st->code = 0;
+    st->pad = 0;
+    scal[0] = 0.0;
+    scal[1] = INFINITY;
+    scal[2] = 0.0;
+}
+
+template <typename T>
+struct Prec;
+template <>
+struct Prec<double> {
+    static hipError_t gemm(int shape, int64_t M, int64_t N, int64_t K, double alpha,
+                           const double *A, int64_t lda, const double *B, int64_t ldb, double beta,
+                           double *C, int64_t ldc, const int *abort, hipStream_t s) {
+        return gemm_f64(shape, M, N, K, alpha, A, lda, B, ldb, beta, C, ldc, abort, s);
+    }
+    static hipError_t gemm_a64(int64_t M, int64_t N, int64_t K, const double *A, int64_t lda,
+                               const double *B, int64_t ldb, double *C, int64_t ldc,
+                               hipStream_t s) {
+        return gemm_f64(kGemmSquare, M, N, K, 1.0, A, lda, B, ldb, 0.0, C, ldc, nullptr, s);
+    }
+    static hipError_t normals(double *out, int64_t count, uint64_t seed, uint64_t stream,
+                              hipStream_t s) {
+        return launch_normals_f64(out, count, seed, stream, s);
+    }
+};
+template <>
+struct Prec<float> {
+    static hipError_t gemm(int shape, int64_t M, int64_t N, int64_t K, float alpha, const float *A,
+                           int64_t lda, const float *B, int64_t ldb, float beta, float *C,
+                           int64_t ldc, const int *abort, hipStream_t s) {
+        return gemm_f32(shape, M, N, K, alpha, A, lda, B, ldb, beta, C, ldc, abort, s);
+    }
+    static hipError_t gemm_a64(int64_t M, int64_t N, int64_t K, const double *A, int64_t lda,
+                               const float *B, int64_t ldb, float *C, int64_t ldc, hipStream_t s) {
+        return gemm_f32_a64(kGemmSquare, M, N, K, 1.0f, A, lda, B, ldb, 0.0f, C, ldc, nullptr, s);
+    }
+    static hipError_t normals(float *out, int64_t count, uint64_t seed, uint64_t stream,
+                              hipStream_t s) {
+        return launch_normals_f32(out, count, seed, stream, s);
+    }
+};
+
+// ------------------------------------------------------------------ factor
+
+// Factor the b x b pivot block at `a` in place and leave the inverses of the
+// 32 x 32 diagonal sub-blocks of its factors in Linv, Uinv (ld kInvLd).
+// Blocks wider than the LDS leaf are split once: B = [[Ba, Bab], [Bba, Bb]] is
+// eliminated as in eq. eqgenp with pivot block Ba.
+template <typename T>
+hipError_t factor_pivot_block(rmge_factors *f, T *a, int b, int64_t k0) {
+    const int64_t ld = f->ld;
+    T *Linv = static_cast<T *>(f->inv);
+    T *Uinv = Linv + kInvLd * kInvLd;
+    const int *abort = &f->st->code;
+    hipStream_t s = f->stream;
+    if (b <= kLeaf) return leaf_lu<T>(a, ld, b, Linv, Uinv, kInvLd, k0, f->st, s);
+    const int b1 = kLeaf, b2 = b - kLeaf;
+    HIP_TRY(leaf_lu<T>(a, ld, b1, Linv, Uinv, kInvLd, k0, f->st, s));
+    // Bab <- La^{-1} Bab ; Bba <- Bba Ua^{-1} ; Bb <- Bb - Bba Bab
+    HIP_TRY(trsm<T>(0, a, ld, b1, a + b1, ld, b2, Linv, abort, s));
+    HIP_TRY(trsm<T>(1, a, ld, b1, a + b1 * ld, ld, b2, Uinv, abort, s));
+    HIP_TRY(Prec<T>::gemm(kGemmSquare, b2, b2, b1, T(-1), a + b1 * ld, ld, a + b1, ld, T(1),
+                          a + b1 * ld + b1, ld, abort, s));
+    return leaf_lu<T>(a + b1 * ld + b1, ld, b2, Linv + b1 * kInvLd + b1, Uinv + b1 * kInvLd + b1,
+                      kInvLd, k0 + b1, f->st, s);
+}
+
+// Right-looking block elimination with no pivoting (eq. eqgenp applied to
+// pivot blocks of f->block columns): per step, factor the pivot block B,
+// replace C by L_B^{-1} C and D by D U_B^{-1} in place, and update E to the
+// Schur complement E - (D U_B^{-1})(L_B^{-1} C) = E - D B^{-1} C.
+template <typename T>
+hipError_t genp_blocked(rmge_factors *f) {
+    T *a = static_cast<T *>(f->lu);
+    const int64_t n = f->n, ld = f->ld;
+    const int nb = f->block;
+    T *Linv = static_cast<T *>(f->inv);
+    T *Uinv = Linv + kInvLd * kInvLd;
+    const int *abort = &f->st->code;
+    hipStream_t s = f->stream;
+    for (int64_t k = 0; k < n; k += nb) {
+        const int b = static_cast<int>((n - k) < nb ? (n - k) : nb);
+        T *akk = a + k * ld + k;
+        HIP_TRY(factor_pivot_block<T>(f, akk, b, k));
+        if (k + b >= n) break;
+        const int64_t r = n - k - b;
+        T *a12 = akk + b, *a21 = akk + b * ld, *a22 = akk + b * ld + b;
+        HIP_TRY(trsm<T>(0, akk, ld, b, a12, ld, r, Linv, abort, s));
+        HIP_TRY(trsm<T>(1, akk, ld, b, a21, ld, r, Uinv, abort, s));
+        HIP_TRY(Prec<T>::gemm(kGemmSquare, r, r, b, T(-1), a21, ld, a12, ld, T(1), a22, ld, abort,
+                              s));
+    }
+    return hipSuccess;
+}
+
+// M = A H into f->lu (precision T).
+template <typename T>
+hipError_t precondition(rmge_factors *f) {
+    const int64_t n = f->n;
+    hipStream_t s = f->stream;
+    T *lu = static_cast<T *>(f->lu);
+    switch (f->kind) {
+    case RMGE_MULT_NONE:
+        return convert_2d<double, T>(f->A, f->lda, lu, f->ld, n, n, s);
+    case RMGE_MULT_GAUSSIAN: {
+        T *G = static_cast<T *>(f->G);
+        hipError_t e = Prec<T>::normals(G, n * n, f->seed, 1, s);
+        if (e != hipSuccess) return e;
+        return Prec<T>::gemm_a64(n, n, n, f->A, f->lda, G, n, lu, f->ld, s);
+    }
+    default: {
+        hipError_t e = launch_normals_f64(f->params, f->kind == RMGE_MULT_CIRCULANT ? n : 2 * n - 1,
+                                          f->seed, static_cast<uint64_t>(f->kind), s);
+        if (e != hipSuccess) return e;
+        if ((e = fft_embed(f->kind, f->params, n, f->m, f->hker, s)) != hipSuccess) return e;
+        if ((e = fft_spectrum(f->hker, f->m, f->tw, f->hhat, s)) != hipSuccess) return e;
+        return fft_rows<double, T>(f->A, f->lda, 1, n, n, f->m, f->tw, f->hhat, 1, 0.0, lu, f->ld,
+                                   1, s);
+    }
+    }
+}
+
+template <typename T>
+rmge_status run_factor(rmge_factors *f) {
+    hipStream_t s = f->stream;
+    f->stats_done = false;
+    f->anorm_done = false;
+    hipLaunchKernelGGL(k_reset, dim3(1), dim3(1), 0, s, f->st, f->scal);
+    RMGE_TRY(hipGetLastError());
+    RMGE_TRY(hipEventRecord(f->ev[0], s));
+    RMGE_TRY(precondition<T>(f));
+    RMGE_TRY(abs_max<T>(static_cast<const T *>(f->lu), f->ld, f->n, f->scal, s));
+    RMGE_TRY(hipEventRecord(f->ev[1], s));
+    RMGE_TRY(genp_blocked<T>(f));
+    RMGE_TRY(hipEventRecord(f->ev[2], s));
+    RMGE_TRY(hipMemcpyAsync(&f->host_st, f->st, sizeof(DevStatus), hipMemcpyDeviceToHost, s));
+    RMGE_TRY(hipStreamSynchronize(s));
+    float t01 = 0.f, t12 = 0.f;
+    (void)hipEventElapsedTime(&t01, f->ev[0], f->ev[1]);
+    (void)hipEventElapsedTime(&t12, f->ev[1], f->ev[2]);
+    f->stats.ms_multiplier = t01;
+    f->stats.ms_factor = t12;
+    f->stats.info = f->host_st.code ? f->host_st.info : -1;
+    f->stats.status = f->host_st.code;
+    f->stats.block = f->block;
+    if (f->host_st.code == 4) return RMGE_ZERO_PIVOT;
+    if (f->host_st.code == 5) return RMGE_NONFINITE;
+    return RMGE_OK;
+}
+
+void free_handle(rmge_factors *f) {
+    if (!f) return;
+    void *ptrs[] = {f->lu, f->G, f->params, f->hker, f->hhat, f->tw, f->inv, f->st, f->scal,
+                    f->wy, f->wx, f->wr, f->wnorm, f->wt};
+    for (void *p : ptrs)
+        if (p) (void)hipFree(p);
+    for (hipEvent_t &e : f->ev)
+        if (e) (void)hipEventDestroy(e);
+    delete f;
+}
+
+rmge_status alloc_handle(rmge_factors *f) {
+    const int64_t n = f->n;
+    const size_t es = elem_size(f->prec);
+    RMGE_TRY(hipMalloc(&f->lu, es * static_cast<size_t>(n) * f->ld));
+    if (f->kind == RMGE_MULT_GAUSSIAN) RMGE_TRY(hipMalloc(&f->G, es * static_cast<size_t>(n * n)));
+    if (f->kind == RMGE_MULT_CIRCULANT || f->kind == RMGE_MULT_TOEPLITZ) {
+        const int L = f->m / 2;
+        RMGE_TRY(hipMalloc(&f->params, sizeof(double) * static_cast<size_t>(2 * n)));
+        RMGE_TRY(hipMalloc(&f->hker, sizeof(double) * static_cast<size_t>(f->m)));
+        RMGE_TRY(hipMalloc(&f->hhat, sizeof(double) * 2 * static_cast<size_t>(L + 1)));
+        RMGE_TRY(hipMalloc(&f->tw, sizeof(double) * 2 * static_cast<size_t>(L + 1)));
+        RMGE_TRY(fft_twiddles(f->m, f->tw, f->stream));
+    }
+    const size_t inv_elems = 2 * kInvLd * kInvLd;
+    RMGE_TRY(hipMalloc(&f->inv, es * inv_elems));
+    RMGE_TRY(hipMemsetAsync(f->inv, 0, es * inv_elems, f->stream));
+    RMGE_TRY(hipMalloc(&f->st, sizeof(DevStatus)));
+    RMGE_TRY(hipMalloc(&f->scal, sizeof(double) * 8));
+    for (hipEvent_t &e : f->ev) RMGE_TRY(hipEventCreate(&e));
+    return RMGE_OK;
+}
+
+// ------------------------------------------------------------------- solve
+
+rmge_status ensure_solve_ws(rmge_factors *f, int64_t nrhs, bool need_t) {
+    const int64_t n = f->n;
+    if (nrhs > f->ws_nrhs) {
+        for (void **p : {&f->wy, &f->wx}) {
+            if (*p) (void)hipFree(*p);
+            *p = nullptr;
+        }
+        if (f->wr) (void)hipFree(f->wr);
+        if (f->wnorm) (void)hipFree(f->wnorm);
+        f->wr = f->wnorm = nullptr;
+        f->ws_nrhs = 0;
+        const size_t es = elem_size(f->prec);
+        RMGE_TRY(hipMalloc(&f->wy, es * static_cast<size_t>(n * nrhs)));
+        RMGE_TRY(hipMalloc(&f->wx, es * static_cast<size_t>(n * nrhs)));
+        RMGE_TRY(hipMalloc(&f->wr, sizeof(double) * static_cast<size_t>(n * nrhs)));
+        RMGE_TRY(hipMalloc(&f->wnorm, sizeof(double) * static_cast<size_t>(4 * nrhs + 8)));
+        f->ws_nrhs = nrhs;
+    }
+    if (need_t && f->kind == RMGE_MULT_GAUSSIAN) {
+        const int64_t want = ((n + 255) / 256) * n * (nrhs < 16 ? nrhs : 16);
+        if (want > f->wt_size) {
+            if (f->wt) (void)hipFree(f->wt);
+            f->wt = nullptr;
+            f->wt_size = 0;
+            RMGE_TRY(hipMalloc(&f->wt, sizeof(double) * static_cast<size_t>(want)));
+            f->wt_size = want;
+        }
+    }
+    return RMGE_OK;
+}
+
+// Triangular solves on the workspace: src (T, n x nrhs) -> U^{-1} L^{-1} src,
+// result left in f->wy; `adjoint` solves U^T then L^T instead.
+template <typename T>
+hipError_t tri_solves(rmge_factors *f, int64_t nrhs, bool adjoint) {
+    const int64_t n = f->n, ld = f->ld;
+    const T *lu = static_cast<const T *>(f->lu);
+    T *Y = static_cast<T *>(f->wy), *X = static_cast<T *>(f->wx);
+    const int64_t nblk = (n + kSolveBlock - 1) / kSolveBlock;
+    hipStream_t s = f->stream;
+    const int first = adjoint ? 2 : 0, second = adjoint ? 3 : 1;
+    for (int64_t g = 0; g < nrhs; g += 16) {
+        const int nr = static_cast<int>((nrhs - g) < 16 ? (nrhs - g) : 16);
+        for (int64_t b = 0; b < nblk; ++b) {
+            hipError_t e = trsv_step<T>(first, lu, ld, n, b, Y + g, X + g, nrhs, nr, nullptr, s);
+            if (e != hipSuccess) return e;
+        }
+        for (int64_t b = nblk - 1; b >= 0; --b) {
+            hipError_t e = trsv_step<T>(second, lu, ld, n, b, X + g, Y + g, nrhs, nr, nullptr, s);
+            if (e != hipSuccess) return e;
+        }
+    }
+    return hipSuccess;
+}
+
+// X = beta X + H U^{-1} L^{-1} src   (src FP64 n x nrhs, lds)
+template <typename T>
+hipError_t apply_inverse(rmge_factors *f, const double *src, int64_t lds, int64_t nrhs, double *X,
+                         int64_t ldx, double beta) {
+    const int64_t n = f->n;
+    hipStream_t s = f->stream;
+    T *Y = static_cast<T *>(f->wy);
+    hipError_t e = convert_2d<double, T>(src, lds, Y, nrhs, n, nrhs, s);
+    if (e != hipSuccess) return e;
+    if ((e = tri_solves<T>(f, nrhs, false)) != hipSuccess) return e;
+    switch (f->kind) {
+    case RMGE_MULT_NONE: return axpby_2d<T>(Y, nrhs, X, ldx, n, static_cast<int>(nrhs), beta, s);
+    case RMGE_MULT_GAUSSIAN:
+        for (int64_t g = 0; g < nrhs; g += 16) {
+            const int nr = static_cast<int>((nrhs - g) < 16 ? (nrhs - g) : 16);
+            e = gemv_n<T, T, double>(n, n, 1.0, static_cast<const T *>(f->G), n, Y + g, nrhs,
+                                     beta, X + g, ldx, nr, s);
+            if (e != hipSuccess) return e;
+        }
+        return hipSuccess;
+    default:
+        return fft_rows<T, double>(Y, 1, nrhs, nrhs, n, f->m, f->tw, f->hhat, 0, beta, X, 1, ldx,
+                                   s);
+    }
+}
+
+// R = B - A X; returns eta = max_r ||R_r||_inf / (||A||_inf ||X_r||_inf + ||B_r||_inf).
+rmge_status residual_eta(rmge_factors *f, const double *B, int64_t ldb, int64_t nrhs,
+                         const double *X, int64_t ldx, double *eta) {
+    const int64_t n = f->n;
+    hipStream_t s = f->stream;
+    double *R = f->wr, *nrm = f->wnorm;
+    RMGE_TRY((convert_2d<double, double>(B, ldb, R, nrhs, n, nrhs, s)));
+    for (int64_t g = 0; g < nrhs; g += 16) {
+        const int nr = static_cast<int>((nrhs - g) < 16 ? (nrhs - g) : 16);
+        RMGE_TRY((gemv_n<double, double, double>(n, n, -1.0, f->A, f->lda, X + g, ldx, 1.0, R + g,
+                                                 nrhs, nr, s)));
+    }
+    RMGE_TRY(fill_f64(nrm, 3 * nrhs, 0.0, s));
+    RMGE_TRY(colmax_abs(R, nrhs, n, static_cast<int>(nrhs), nrm, s));
+    RMGE_TRY(colmax_abs(X, ldx, n, static_cast<int>(nrhs), nrm + nrhs, s));
+    RMGE_TRY(colmax_abs(B, ldb, n, static_cast<int>(nrhs), nrm + 2 * nrhs, s));
+    if (!f->anorm_done) {
+        RMGE_TRY(fill_f64(f->scal + 3, 1, 0.0, s));
+        RMGE_TRY(norm_inf(f->A, f->lda, n, f->scal + 3, s));
+    }
+    std::vector<double> h(static_cast<size_t>(3 * nrhs));
+    RMGE_TRY(hipMemcpyAsync(h.data(), nrm, sizeof(double) * 3 * nrhs, hipMemcpyDeviceToHost, s));
+    if (!f->anorm_done)
+        RMGE_TRY(hipMemcpyAsync(&f->anorm, f->scal + 3, sizeof(double), hipMemcpyDeviceToHost, s));
+    RMGE_TRY(hipStreamSynchronize(s));
+    f->anorm_done = true;
+    double worst = 0.0;
+    for (int64_t r = 0; r < nrhs; ++r) {
+        const double e = h[r] / (f->anorm * h[nrhs + r] + h[2 * nrhs + r]);
+        if (e > worst || e != e) worst = e;
+    }
+    *eta = worst;
+    return RMGE_OK;
+}
+
+template <typename T>
+rmge_status run_solve(rmge_factors *f, const double *B, int64_t nrhs, int64_t ldb, double *X,
+                      int64_t ldx, int32_t max_refine, double tol, rmge_solve_stats *st) {
+    rmge_status rs = ensure_solve_ws(f, nrhs, false);
+    if (rs != RMGE_OK) return rs;
+    RMGE_TRY(apply_inverse<T>(f, B, ldb, nrhs, X, ldx, 0.0));
+    double eta = 0.0;
+    rs = residual_eta(f, B, ldb, nrhs, X, ldx, &eta);
+    if (rs != RMGE_OK) return rs;
+    rmge_solve_stats loc{};
+    loc.eta0 = eta;
+    loc.eta_hist[0] = eta;
+    int it = 0;
+    while (it < max_refine && !(tol > 0.0 && eta <= tol)) {
+        RMGE_TRY(apply_inverse<T>(f, f->wr, nrhs, nrhs, X, ldx, 1.0));
+        ++it;
+        rs = residual_eta(f, B, ldb, nrhs, X, ldx, &eta);
+        if (rs != RMGE_OK) return rs;
+        loc.eta_hist[it] = eta;
+    }
+    loc.iters = it;
+    loc.eta = eta;
+    loc.converged = (tol <= 0.0 || eta <= tol) ? 1 : 0;
+    if (st) *st = loc;
+    return loc.converged ? RMGE_OK : RMGE_NOT_CONVERGED;
+}
+
+template <typename T>
+rmge_status run_adjoint(rmge_factors *f, const double *W, int64_t nrhs, int64_t ldw, double *Y,
+                        int64_t ldy) {
+    rmge_status rs = ensure_solve_ws(f, nrhs, true);
+    if (rs != RMGE_OK) return rs;
+    const int64_t n = f->n;
+    hipStream_t s = f->stream;
+    T *Z = static_cast<T *>(f->wy);
+    switch (f->kind) {
+    case RMGE_MULT_NONE: RMGE_TRY((convert_2d<double, T>(W, ldw, Z, nrhs, n, nrhs, s))); break;
+    case RMGE_MULT_GAUSSIAN:
+        for (int64_t g = 0; g < nrhs; g += 16) {
+            const int nr = static_cast<int>((nrhs - g) < 16 ? (nrhs - g) : 16);
+            RMGE_TRY((gemv_t<T, double, T>(n, n, static_cast<const T *>(f->G), n, W + g, ldw,
+                                           Z + g, nrhs, nr, f->wt, s)));
+        }
+        break;
+    default:
+        RMGE_TRY((fft_rows<double, T>(W, 1, ldw, nrhs, n, f->m, f->tw, f->hhat, 1, 0.0, Z, 1, nrhs,
+                                      s)));
+    }
+    RMGE_TRY(tri_solves<T>(f, nrhs, true));
+    RMGE_TRY((convert_2d<T, double>(Z, nrhs, Y, ldy, n, nrhs, s)));
+    RMGE_TRY(hipStreamSynchronize(s));
+    return RMGE_OK;
+}
+
+rmge_status check_factor_args(const double *A, int64_t n, int64_t lda, int32_t kind,
+                              int32_t block, int32_t prec) {
+    if (!A || n < 1 || lda < n || n > (int64_t(1) << 20)) return RMGE_EINVAL;
+    if (kind < RMGE_MULT_NONE || kind > RMGE_MULT_TOEPLITZ) return RMGE_EINVAL;
+    if (block < 0 || block > kMaxBlock) return RMGE_EINVAL;
+    if (prec != RMGE_F64 && prec != RMGE_F32) return RMGE_EINVAL;
+    if ((kind == RMGE_MULT_CIRCULANT || kind == RMGE_MULT_TOEPLITZ) && fft_period(kind, n) == 0)
+        return RMGE_EINVAL;
+    return RMGE_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+rmge_status rmge_factor_ex(const double *A, int64_t n, int64_t lda, int32_t kind, uint64_t seed,
+                           int32_t block, int32_t prec, void *hip_stream, rmge_factors **out) {
+    if (!out) return RMGE_EINVAL;
+    rmge_status rs = check_factor_args(A, n, lda, kind, block, prec);
+    if (rs != RMGE_OK) return rs;
+    if (!device_ok()) return RMGE_EDEVICE;
+    rmge_factors *f = new (std::nothrow) rmge_factors();
+    if (!f) return RMGE_ENOMEM;
+    f->n = n;
+    f->lda = lda;
+    f->ld = round_up(n, 64);
+    f->kind = kind;
+    f->prec = prec;
+    f->block = block == 0 ? kMaxBlock : block;
+    f->seed = seed;
+    f->stream = static_cast<hipStream_t>(hip_stream);
+    f->A = A;
+    f->m = (kind == RMGE_MULT_CIRCULANT || kind == RMGE_MULT_TOEPLITZ) ? fft_period(kind, n) : 0;
+    rs = alloc_handle(f);
+    if (rs != RMGE_OK) {
+        free_handle(f);
+        return rs;
+    }
+    rs = (prec == RMGE_F32) ? run_factor<float>(f) : run_factor<double>(f);
+    if (rs == RMGE_OK || rs == RMGE_ZERO_PIVOT || rs == RMGE_NONFINITE) {
+        *out = f;
+        return rs;
+    }
+    free_handle(f);
+    return rs;
+}
+
+rmge_status rmge_factor(const double *A, int64_t n, int32_t kind, uint64_t seed, int32_t block,
+                        rmge_factors **out) {
+    return rmge_factor_ex(A, n, n, kind, seed, block, RMGE_F64, nullptr, out);
+}
+
+rmge_status rmge_refactor(rmge_factors *f, const double *A, int64_t lda, uint64_t seed) {
+    if (!f || !A || lda < f->n) return RMGE_EINVAL;
+    f->A = A;
+    f->lda = lda;
+    f->seed = seed;
+    return (f->prec == RMGE_F32) ? run_factor<float>(f) : run_factor<double>(f);
+}
+
+rmge_status rmge_solve(const rmge_factors *fc, const double *B, int64_t nrhs, int64_t ldb,
+                       double *X, int64_t ldx, int32_t max_refine, double tol,
+                       rmge_solve_stats *st) {
+    rmge_factors *f = const_cast<rmge_factors *>(fc);
+    if (!f || !B || !X || nrhs < 1 || ldb < nrhs || ldx < nrhs || max_refine < 0 ||
+        max_refine > 16 || X == B)
+        return RMGE_EINVAL;
+    if (f->host_st.code == 4) return RMGE_ZERO_PIVOT;
+    if (f->host_st.code == 5) return RMGE_NONFINITE;
+    return (f->prec == RMGE_F32) ? run_solve<float>(f, B, nrhs, ldb, X, ldx, max_refine, tol, st)
+                                 : run_solve<double>(f, B, nrhs, ldb, X, ldx, max_refine, tol, st);
+}
+
+rmge_status rmge_solve_adjoint(const rmge_factors *fc, const double *W, int64_t nrhs,
+                               int64_t ldw, double *Y, int64_t ldy) {
+    rmge_factors *f = const_cast<rmge_factors *>(fc);
+    if (!f || !W || !Y || nrhs < 1 || ldw < nrhs || ldy < nrhs) return RMGE_EINVAL;
+    if (f->host_st.code == 4) return RMGE_ZERO_PIVOT;
+    if (f->host_st.code == 5) return RMGE_NONFINITE;
+    return (f->prec == RMGE_F32) ? run_adjoint<float>(f, W, nrhs, ldw, Y, ldy)
+                                 : run_adjoint<double>(f, W, nrhs, ldw, Y, ldy);
+}
+
+rmge_status rmge_factor_stats_get(const rmge_factors *fc, rmge_factor_stats *s) {
+    rmge_factors *f = const_cast<rmge_factors *>(fc);
+    if (!f || !s) return RMGE_EINVAL;
+    if (!f->stats_done && f->host_st.code == 0) {
+        hipError_t e = (f->prec == RMGE_F32)
+                           ? lu_stats<float>(static_cast<const float *>(f->lu), f->ld, f->n,
+                                             f->scal, f->stream)
+                           : lu_stats<double>(static_cast<const double *>(f->lu), f->ld, f->n,
+                                              f->scal, f->stream);
+        if (e != hipSuccess) return from_hip(e);
+        double h[3];
+        RMGE_TRY(hipMemcpyAsync(h, f->scal, sizeof(h), hipMemcpyDeviceToHost, f->stream));
+        RMGE_TRY(hipStreamSynchronize(f->stream));
+        f->stats.min_abs_pivot = h[1];
+        f->stats.growth = h[2] > 0.0 ? h[0] / h[2] : 0.0;
+        f->stats_done = true;
+    }
+    *s = f->stats;
+    return RMGE_OK;
+}
+
+rmge_status rmge_factors_lu(const rmge_factors *f, double *LU, int64_t ld) {
+    if (!f || !LU || ld < f->n) return RMGE_EINVAL;
+    hipError_t e = (f->prec == RMGE_F32)
+                       ? convert_2d<float, double>(static_cast<const float *>(f->lu), f->ld, LU,
+                                                   ld, f->n, f->n, f->stream)
+                       : convert_2d<double, double>(static_cast<const double *>(f->lu), f->ld, LU,
+                                                    ld, f->n, f->n, f->stream);
+    if (e != hipSuccess) return from_hip(e);
+    return from_hip(hipStreamSynchronize(f->stream));
+}
+
+int64_t rmge_param_count(int32_t kind, int64_t n) {
+    if (n < 1) return 0;
+    switch (kind) {
+    case RMGE_MULT_GAUSSIAN: return n * n;
+    case RMGE_MULT_CIRCULANT: return n;
+    case RMGE_MULT_TOEPLITZ: return 2 * n - 1;
+    default: return 0;
+    }
+}
+
+rmge_status rmge_multiplier_params(int32_t kind, int64_t n, uint64_t seed, double *out,
+                                   void *hip_stream) {
+    const int64_t cnt = rmge_param_count(kind, n);
+    if (!out || cnt == 0) return RMGE_EINVAL;
+    if (!device_ok()) return RMGE_EDEVICE;
+    hipStream_t s = static_cast<hipStream_t>(hip_stream);
+    RMGE_TRY(launch_normals_f64(out, cnt, seed, static_cast<uint64_t>(kind), s));
+    return from_hip(hipStreamSynchronize(s));
+}
+
+rmge_status rmge_precondition(const double *A, int64_t n, int64_t lda, int32_t kind,
+                              uint64_t seed, double *M, int64_t ldm, void *hip_stream) {
+    if (!M || ldm < n || M == A) return RMGE_EINVAL;
+    rmge_status rs = check_factor_args(A, n, lda, kind, 0, RMGE_F64);
+    if (rs != RMGE_OK) return rs;
+    if (!device_ok()) return RMGE_EDEVICE;
+    rmge_factors f;
+    f.n = n;
+    f.lda = lda;
+    f.ld = ldm;
+    f.kind = kind;
+    f.seed = seed;
+    f.stream = static_cast<hipStream_t>(hip_stream);
+    f.A = A;
+    f.lu = M;
+    f.m = (kind == RMGE_MULT_CIRCULANT || kind == RMGE_MULT_TOEPLITZ) ? fft_period(kind, n) : 0;
+    hipError_t e = hipSuccess;
+    if (kind == RMGE_MULT_GAUSSIAN) e = hipMalloc(&f.G, sizeof(double) * static_cast<size_t>(n * n));
+    if (e == hipSuccess && f.m) {
+        const int L = f.m / 2;
+        e = hipMalloc(&f.params, sizeof(double) * static_cast<size_t>(2 * n));
+        if (e == hipSuccess) e = hipMalloc(&f.hker, sizeof(double) * static_cast<size_t>(f.m));
+        if (e == hipSuccess) e = hipMalloc(&f.hhat, sizeof(double) * 2 * static_cast<size_t>(L + 1));
+        if (e == hipSuccess) e = hipMalloc(&f.tw, sizeof(double) * 2 * static_cast<size_t>(L + 1));
+        if (e == hipSuccess) e = fft_twiddles(f.m, f.tw, f.stream);
+    }
+    if (e == hipSuccess) e = precondition<double>(&f);
+    if (e == hipSuccess) e = hipStreamSynchronize(f.stream);
+    void *tmp[] = {f.G, f.params, f.hker, f.hhat, f.tw};
+    for (void *p : tmp)
+        if (p) (void)hipFree(p);
+    f.lu = nullptr;
+    return from_hip(e);
+}
+
+void rmge_destroy(rmge_factors *f) { free_handle(f); }
+
+const char *rmge_status_string(int32_t s) {
+    switch (s) {
+    case RMGE_OK: return "ok";
+    case RMGE_EINVAL: return "invalid argument";
+    case RMGE_ENOMEM: return "device allocation failed";
+    case RMGE_EDEVICE: return "HIP runtime error or no gfx950 device";
+    case RMGE_ZERO_PIVOT: return "zero pivot: the preprocessed matrix is not strongly nonsingular";
+    case RMGE_NONFINITE: return "non-finite pivot";
+    case RMGE_NOT_CONVERGED: return "refinement did not reach the tolerance";
+    default: return "unknown status";
+    }
+}
+
+int32_t rmge_version(void) { return 100; }
+
+}  // extern "C"

@@ -1,0 +1,231 @@
+// Dense products on the matrix cores of gfx950.
+//
+// Three places of the method are dense contractions and run here:
+//   * the preprocessing product M = A G with a Gaussian multiplier
+//     (Fact faprepr; 2n^3 - n^2 flops, the cost the paper states in Section 6);
+//   * the two off-diagonal solves of each block step of eq. eqgenp,
+//     B^{-1} C and D B^{-1}, done as products with the explicit inverses of
+//     the pivot block's triangular factors;
+//   * the Schur-complement update S = E - (D B^{-1})(B^{-1} C) of eq. eqgenp.
+//
+// Kernel: C = alpha A B + beta C, row-major, one workgroup of four waves per
+// output tile, each wave a 64 x 64 sub-tile made of 16 x 16 MFMA blocks
+// (v_mfma_f64_16x16x4_f64 or v_mfma_f32_16x16x4_f32).  K advances in chunks of
+// 16 through double-buffered LDS (A stored m-major, B k-major, one element of
+// padding per row), with the next chunk's global loads issued before the
+// current chunk's MFMAs.  Workgroup ids are remapped so that each XCD (ids
+// are dealt round-robin over the 8 XCDs) gets a contiguous run of tiles, and
+// runs are ordered in groups of 8 tile-rows, so the operand panels a wave of
+// workgroups touches stay in that XCD's L2.
+//
+// Bound: MFMA (2 flops per multiply-add) for the square tile at K >= 256;
+// the tall/wide shapes are used where a workgroup must own whole rows or
+// whole columns of C so that C may overwrite its own input (in-place solves).
+#include "rmge_impl.h"
+
+namespace rmge {
+namespace {
+
+typedef double v4d __attribute__((ext_vector_type(4)));
+typedef float v4f __attribute__((ext_vector_type(4)));
+
+template <typename T>
+struct Mma;
+// Operand layouts of both 16x16x4 MFMAs: lane l holds A[l & 15][l >> 4] and
+// B[l >> 4][l & 15].  Result: lane l, item r holds D[row(l, r)][l & 15], with
+// row = (l >> 4) + 4 r for f64 and 4 (l >> 4) + r for f32 (measured on gfx950).
+template <>
+struct Mma<double> {
+    using acc = v4d;
+    __device__ static acc step(double a, double b, acc c) {
+        return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+    }
+    __device__ static int row(int lane, int r) { return (lane >> 4) + 4 * r; }
+};
+template <>
+struct Mma<float> {
+    using acc = v4f;
+    __device__ static acc step(float a, float b, acc c) {
+        return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+    }
+    __device__ static int row(int lane, int r) { return 4 * (lane >> 4) + r; }
+};
+
+__device__ inline void tile_coords(int bid, int tiles_m, int tiles_n, int &tm, int &tn) {
+    const int tiles = tiles_m * tiles_n;
+    const int q = tiles / 8, r = tiles % 8;
+    const int x = bid % 8, i = bid / 8;
+    const int logical = x * q + (x < r ? x : r) + i;
+    const int G = 8;
+    const int per_group = G * tiles_n;
+    const int g = logical / per_group;
+    const int first = g * G;
+    const int gs = (tiles_m - first) < G ? (tiles_m - first) : G;
+    const int within = logical - g * per_group;
+    tm = first + within % gs;
+    tn = within / gs;
+}
+
+// T: arithmetic type, TA: storage type of A (double A may feed a float product).
+template <typename T, typename TA, int BM, int BN, int WGM, int WGN>
+__global__ __launch_bounds__(WGM *WGN * 64) void k_gemm(int M, int N, int K, T alpha, const TA *A,
+                                                        int64_t lda, const T *B, int64_t ldb,
+                                                        T beta, T *C, int64_t ldc,
+                                                        const int *abort) {
+    constexpr int BK = 16;
+    constexpr int NT = WGM * WGN * 64;
+    constexpr int WM = BM / WGM, WN = BN / WGN;
+    constexpr int TM = WM / 16, TN = WN / 16;
+    constexpr int A_PER = BM * BK / NT;
+    constexpr int B_PER = BK * BN / NT;
+    constexpr int LDA_S = BK + 1;
+    constexpr int LDB_S = BN + 1;
+    static_assert(A_PER * NT == BM * BK && B_PER * NT == BK * BN, "tile/threads mismatch");
+    using acc_t = typename Mma<T>::acc;
+
+    __shared__ T As[2][BM * LDA_S];
+    __shared__ T Bs[2][BK * LDB_S];
+
+    if (abort != nullptr && *abort != 0) return;
+
+    const int tiles_m = (M + BM - 1) / BM, tiles_n = (N + BN - 1) / BN;
+    int tm, tn;
+    tile_coords(blockIdx.x, tiles_m, tiles_n, tm, tn);
+    const int m0 = tm * BM, n0 = tn * BN;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int wm = wave / WGN, wn = wave % WGN;
+
+    acc_t acc[TM][TN];
+#pragma unroll
+    for (int i = 0; i < TM; ++i)
+#pragma unroll
+        for (int j = 0; j < TN; ++j) acc[i][j] = acc_t{0, 0, 0, 0};
+
+    TA ra[A_PER];
+    T rb[B_PER];
+    auto load = [&](int k0) {
+#pragma unroll
+        for (int p = 0; p < A_PER; ++p) {
+            const int e = tid + p * NT;
+            const int m = m0 + e / BK, k = k0 + e % BK;
+            ra[p] = (m < M && k < K) ? A[static_cast<int64_t>(m) * lda + k] : TA(0);
+        }
+#pragma unroll
+        for (int p = 0; p < B_PER; ++p) {
+            const int e = tid + p * NT;
+            const int k = k0 + e / BN, n = n0 + e % BN;
+            rb[p] = (k < K && n < N) ? B[static_cast<int64_t>(k) * ldb + n] : T(0);
+        }
+    };
+    auto store = [&](int buf) {
+#pragma unroll
+        for (int p = 0; p < A_PER; ++p) {
+            const int e = tid + p * NT;
+            As[buf][(e / BK) * LDA_S + e % BK] = static_cast<T>(ra[p]);
+        }
+#pragma unroll
+        for (int p = 0; p < B_PER; ++p) {
+            const int e = tid + p * NT;
+            Bs[buf][(e / BN) * LDB_S + e % BN] = rb[p];
+        }
+    };
+
+    const int nk = (K + BK - 1) / BK;
+    if (nk > 0) {
+        load(0);
+        store(0);
+    }
+    __syncthreads();
+    const int arow = wm * WM + (lane & 15);
+    const int bcol = wn * WN + (lane & 15);
+    const int ksub = lane >> 4;
+    for (int kt = 0; kt < nk; ++kt) {
+        const int cur = kt & 1;
+        if (kt + 1 < nk) load((kt + 1) * BK);
+#pragma unroll
+        for (int kk = 0; kk < BK; kk += 4) {
+            T af[TM], bf[TN];
+#pragma unroll
+            for (int i = 0; i < TM; ++i) af[i] = As[cur][(arow + i * 16) * LDA_S + kk + ksub];
+#pragma unroll
+            for (int j = 0; j < TN; ++j) bf[j] = Bs[cur][(kk + ksub) * LDB_S + bcol + j * 16];
+#pragma unroll
+            for (int i = 0; i < TM; ++i)
+#pragma unroll
+                for (int j = 0; j < TN; ++j) acc[i][j] = Mma<T>::step(af[i], bf[j], acc[i][j]);
+        }
+        if (kt + 1 < nk) store(cur ^ 1);
+        __syncthreads();
+    }
+
+    const int crow0 = m0 + wm * WM;
+    const int ccol0 = n0 + wn * WN + (lane & 15);
+#pragma unroll
+    for (int i = 0; i < TM; ++i)
+#pragma unroll
+        for (int j = 0; j < TN; ++j)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int row = crow0 + i * 16 + Mma<T>::row(lane, r), col = ccol0 + j * 16;
+                if (row < M && col < N) {
+                    T *c = C + static_cast<int64_t>(row) * ldc + col;
+                    const T v = alpha * acc[i][j][r];
+                    *c = (beta == T(0)) ? v : v + beta * (*c);
+                }
+            }
+}
+
+template <typename T, typename TA>
+hipError_t run_gemm(int shape, int64_t M, int64_t N, int64_t K, T alpha, const TA *A, int64_t lda,
+                    const T *B, int64_t ldb, T beta, T *C, int64_t ldc, const int *abort,
+                    hipStream_t s) {
+    if (M <= 0 || N <= 0) return hipSuccess;
+    if (M > INT32_MAX || N > INT32_MAX || K > INT32_MAX) return hipErrorInvalidValue;
+    const int m = static_cast<int>(M), n = static_cast<int>(N), k = static_cast<int>(K);
+    switch (shape) {
+    case kGemmRows: {
+        constexpr int BM = 64, BN = 256;
+        const int64_t tiles = ((M + BM - 1) / BM) * ((N + BN - 1) / BN);
+        hipLaunchKernelGGL((k_gemm<T, TA, BM, BN, 1, 4>), dim3(static_cast<unsigned>(tiles)),
+                           dim3(256), 0, s, m, n, k, alpha, A, lda, B, ldb, beta, C, ldc, abort);
+        break;
+    }
+    case kGemmCols: {
+        constexpr int BM = 256, BN = 64;
+        const int64_t tiles = ((M + BM - 1) / BM) * ((N + BN - 1) / BN);
+        hipLaunchKernelGGL((k_gemm<T, TA, BM, BN, 4, 1>), dim3(static_cast<unsigned>(tiles)),
+                           dim3(256), 0, s, m, n, k, alpha, A, lda, B, ldb, beta, C, ldc, abort);
+        break;
+    }
+    default: {
+        constexpr int BM = 128, BN = 128;
+        const int64_t tiles = ((M + BM - 1) / BM) * ((N + BN - 1) / BN);
+        hipLaunchKernelGGL((k_gemm<T, TA, BM, BN, 2, 2>), dim3(static_cast<unsigned>(tiles)),
+                           dim3(256), 0, s, m, n, k, alpha, A, lda, B, ldb, beta, C, ldc, abort);
+        break;
+    }
+    }
+    return hipGetLastError();
+}
+
+}  // namespace
+
+hipError_t gemm_f64(int shape, int64_t M, int64_t N, int64_t K, double alpha, const double *A,
+                    int64_t lda, const double *B, int64_t ldb, double beta, double *C, int64_t ldc,
+                    const int *abort, hipStream_t s) {
+    return run_gemm<double, double>(shape, M, N, K, alpha, A, lda, B, ldb, beta, C, ldc, abort, s);
+}
+
+hipError_t gemm_f32(int shape, int64_t M, int64_t N, int64_t K, float alpha, const float *A,
+                    int64_t lda, const float *B, int64_t ldb, float beta, float *C, int64_t ldc,
+                    const int *abort, hipStream_t s) {
+    return run_gemm<float, float>(shape, M, N, K, alpha, A, lda, B, ldb, beta, C, ldc, abort, s);
+}
+
+hipError_t gemm_f32_a64(int shape, int64_t M, int64_t N, int64_t K, float alpha, const double *A,
+                        int64_t lda, const float *B, int64_t ldb, float beta, float *C,
+                        int64_t ldc, const int *abort, hipStream_t s) {
+    return run_gemm<float, double>(shape, M, N, K, alpha, A, lda, B, ldb, beta, C, ldc, abort, s);
+}
+
+}  // namespace rmge

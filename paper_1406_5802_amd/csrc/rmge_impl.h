@@ -1,0 +1,126 @@
+// Internal declarations of the gfx950 library: device status word, launchers.
+// Every launcher enqueues on the given stream and returns the launch status.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace rmge {
+
+// Device-resident status of a factorization.  `code` is 0 while every pivot
+// seen so far is finite and nonzero; the first kernel that meets a zero or
+// non-finite pivot stores its global index in `info` and sets `code`
+// (4 = zero pivot, 5 = non-finite).  Later kernels read `code` and exit early.
+struct DevStatus {
+    long long info;
+    int code;
+    int pad;
+};
+
+constexpr int kLeaf = 128;      // largest diagonal block factored in LDS
+constexpr int kMaxBlock = 256;  // largest panel width
+
+// ---------------------------------------------------------------- rng.hip
+hipError_t launch_normals_f64(double *out, int64_t count, uint64_t seed, uint64_t stream,
+                              hipStream_t s);
+hipError_t launch_normals_f32(float *out, int64_t count, uint64_t seed, uint64_t stream,
+                              hipStream_t s);
+
+// --------------------------------------------------------------- gemm.hip
+// C = alpha * A * B + beta * C, row-major.  A is M x K (lda), B is K x N (ldb),
+// C is M x N (ldc).  `shape` picks the tile: 0 = 128 x 128 (general),
+// 1 = 64 x 256 (a workgroup owns whole rows of C: C may alias A when N <= 256),
+// 2 = 256 x 64 (a workgroup owns whole columns: C may alias B when M <= 256).
+// `abort` (device int, may be null): if nonzero at kernel start, do nothing.
+enum GemmShape { kGemmSquare = 0, kGemmRows = 1, kGemmCols = 2 };
+hipError_t gemm_f64(int shape, int64_t M, int64_t N, int64_t K, double alpha, const double *A,
+                    int64_t lda, const double *B, int64_t ldb, double beta, double *C, int64_t ldc,
+                    const int *abort, hipStream_t s);
+hipError_t gemm_f32(int shape, int64_t M, int64_t N, int64_t K, float alpha, const float *A,
+                    int64_t lda, const float *B, int64_t ldb, float beta, float *C, int64_t ldc,
+                    const int *abort, hipStream_t s);
+// FP32 product whose A operand is stored in FP64 (rounded to FP32 on load).
+hipError_t gemm_f32_a64(int shape, int64_t M, int64_t N, int64_t K, float alpha, const double *A,
+                        int64_t lda, const float *B, int64_t ldb, float beta, float *C,
+                        int64_t ldc, const int *abort, hipStream_t s);
+
+// ----------------------------------------------------------------- lu.hip
+// Factor the b x b diagonal block at `a` (b <= kLeaf) in place (GENP) and
+// write the inverses of the 32 x 32 diagonal sub-blocks of its unit-lower and
+// upper factors into the matching diagonal positions of Linv and Uinv (ldw).
+// k0 = global index of the block's first pivot.
+template <typename T>
+hipError_t leaf_lu(T *a, int64_t lda, int b, T *Linv, T *Uinv, int64_t ldw, int64_t k0,
+                   DevStatus *st, hipStream_t s);
+// In-place triangular solves with the factored pivot block at `lu` (width
+// b <= kMaxBlock), by blocked substitution with the 32 x 32 diagonal inverses
+// in Dinv (ld kMaxBlock):
+//   side 0: C (b x count, ldc) <- L^{-1} C      (Dinv = Linv)
+//   side 1: C (count x b, ldc) <- C U^{-1}      (Dinv = Uinv)
+template <typename T>
+hipError_t trsm(int side, const T *lu, int64_t ld, int b, T *C, int64_t ldc, int64_t count,
+                const T *Dinv, const int *abort, hipStream_t s);
+// Element-wise helpers.
+template <typename T>
+hipError_t set_identity(T *a, int64_t ld, int64_t n, hipStream_t s);
+template <typename T, typename U>
+hipError_t convert_2d(const T *src, int64_t lds, U *dst, int64_t ldd, int64_t rows, int64_t cols,
+                      hipStream_t s);
+// out3[0] = max |U|, out3[1] = min |u_kk| (preset to 0, +Inf); atomics.
+template <typename T>
+hipError_t lu_stats(const T *lu, int64_t ld, int64_t n, double *out3, hipStream_t s);
+// out3[2] = max |M| over the n x n matrix (preset to 0); atomics.
+template <typename T>
+hipError_t abs_max(const T *m, int64_t ld, int64_t n, double *out3, hipStream_t s);
+
+// -------------------------------------------------------------- solve.hip
+// One block step of a triangular solve with the packed factors LU (ld):
+//   mode 0: L y = b (unit lower, forward)      mode 1: U y = b (upper, backward)
+//   mode 2: U^T y = b (lower, forward)         mode 3: L^T y = b (unit upper, backward)
+// Solves diagonal block `blk` (rows blk*64 ..) of Y into X and updates the
+// not-yet-solved rows of Y.
+// Y, X: n x ldyx; this call handles nr <= 16 right-hand sides starting at Y, X.
+template <typename T>
+hipError_t trsv_step(int mode, const T *LU, int64_t ld, int64_t n, int64_t blk, T *Y, T *X,
+                     int64_t ldyx, int nr, const int *abort, hipStream_t s);
+// y = beta * y + alpha * M x  (rows of M; FP64 accumulation).  M: rows x cols (ldm),
+// x: cols x nrhs (ldx), y: rows x nrhs (ldy).
+template <typename TM, typename TX, typename TY>
+hipError_t gemv_n(int64_t rows, int64_t cols, double alpha, const TM *Mat, int64_t ldm,
+                  const TX *x, int64_t ldx, double beta, TY *y, int64_t ldy, int nrhs,
+                  hipStream_t s);
+// y = M^T x (two passes, deterministic).  work: >= ceil(rows/256) * cols * nrhs doubles.
+template <typename TM, typename TX, typename TY>
+hipError_t gemv_t(int64_t rows, int64_t cols, const TM *Mat, int64_t ldm, const TX *x,
+                  int64_t ldx, TY *y, int64_t ldy, int nrhs, double *work, hipStream_t s);
+// norms[0..nrhs) = max_i |v[i][r]| for v = n x nrhs (ld), atomically maxed into norms.
+hipError_t colmax_abs(const double *v, int64_t ld, int64_t n, int nrhs, double *norms,
+                      hipStream_t s);
+// out[0] = max_i sum_j |A[i][j]|.
+hipError_t norm_inf(const double *A, int64_t lda, int64_t n, double *out, hipStream_t s);
+// x = beta x + d (both n x nrhs, own leading dimensions)
+template <typename TS>
+hipError_t axpby_2d(const TS *d, int64_t ldd, double *x, int64_t ldx, int64_t n, int nrhs,
+                    double beta, hipStream_t s);
+hipError_t fill_f64(double *p, int64_t count, double value, hipStream_t s);
+
+// ---------------------------------------------------------------- fft.hip
+// Real FFT correlation / convolution of vectors with a fixed real kernel h of
+// period m (a power of two, 2 <= m <= 16384), through a complex FFT of length
+// L = m/2 staged in LDS.
+//   tw:       twiddle table e^{-i pi j / L}, j = 0..L (complex, built by fft_twiddles).
+//   hhat:     half spectrum hhat[f] = sum_d h[d] e^{-2 pi i f d / m}, f = 0..L.
+//   vectors:  for each of `count` inputs x (length n <= m, zero padded),
+//             y_j = sum_k x_k h[(k - j) mod m]   (correlate, conj = 1)
+//             y_j = sum_k h[(j - k) mod m] x_k   (convolve,  conj = 0)
+//             for j < n, written as out = beta * out + y.
+//   Vector v, element k lives at in[v * vstride_in + k * estride_in].
+hipError_t fft_twiddles(int m, double *tw, hipStream_t s);
+hipError_t fft_embed(int kind, const double *params, int64_t n, int m, double *h, hipStream_t s);
+hipError_t fft_spectrum(const double *h, int m, const double *tw, double *hhat, hipStream_t s);
+template <typename TI, typename TO>
+hipError_t fft_rows(const TI *in, int64_t vstride_in, int64_t estride_in, int64_t count,
+                    int64_t n, int m, const double *tw, const double *hhat, int conj, double beta,
+                    TO *out, int64_t vstride_out, int64_t estride_out, hipStream_t s);
+
+}  // namespace rmge
