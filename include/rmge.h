@@ -78,8 +78,9 @@ typedef struct {
     int32_t block;         /* panel width used */
     double min_abs_pivot;  /* min_k |u_kk| (computed on demand, see rmge_factor_stats_get) */
     double growth;         /* max |U| / max |M| */
-    double ms_multiplier;  /* device time: multiplier generation + M = A H */
-    double ms_factor;      /* device time: elimination */
+    double ms_multiplier;  /* device time of the last factorization: drawing H */
+    double ms_product;     /* device time: M = A H (one GEMM launch, or the FFT pass) */
+    double ms_factor;      /* device time: the elimination (all pivot steps) */
 } rmge_factor_stats;
 
 typedef struct {

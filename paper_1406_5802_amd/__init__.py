@@ -86,7 +86,8 @@ class Factors:
             raise RMGEError(rc, "rmge_factor_stats_get")
         return {"info": st.info, "status": st.status, "block": st.block,
                 "min_abs_pivot": st.min_abs_pivot, "growth": st.growth,
-                "ms_multiplier": st.ms_multiplier, "ms_factor": st.ms_factor}
+                "ms_multiplier": st.ms_multiplier, "ms_product": st.ms_product,
+                "ms_factor": st.ms_factor}
 
     @property
     def info(self) -> int:

@@ -32,7 +32,8 @@ EXPORTS = (
 class rmge_factor_stats(ctypes.Structure):
     _fields_ = [("info", ctypes.c_int64), ("status", ctypes.c_int32), ("block", ctypes.c_int32),
                 ("min_abs_pivot", ctypes.c_double), ("growth", ctypes.c_double),
-                ("ms_multiplier", ctypes.c_double), ("ms_factor", ctypes.c_double)]
+                ("ms_multiplier", ctypes.c_double), ("ms_product", ctypes.c_double),
+                ("ms_factor", ctypes.c_double)]
 
 
 class rmge_solve_stats(ctypes.Structure):

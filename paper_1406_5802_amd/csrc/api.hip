@@ -10,8 +10,9 @@
 //   lu    n x ld  (ld = n rounded up to 64)  the packed factors, over M
 //   mult  GAUSSIAN: n x n of T, G row-major; CIRCULANT/TOEPLITZ: parameters,
 //         the period-m kernel h, its half spectrum and the twiddle table
-//   inv   two 256 x 256 arrays holding, on their diagonals, the inverses of the
-//         32 x 32 diagonal sub-blocks of the current pivot block's L and U
+//   inv   2 x 2 arrays of 256 x 256 holding, on their diagonals, the inverses
+//         of the 32 x 32 diagonal sub-blocks of a pivot block's L and U (two
+//         buffers: the look-ahead panel and the current one)
 //   solve workspace, grown on demand: two n x nrhs of T, one n x nrhs FP64
 //         residual, norms
 #include <hip/hip_runtime.h>
@@ -49,13 +50,18 @@ struct rmge_factors {
     double *wr = nullptr, *wnorm = nullptr;
     double *wt = nullptr;
     int64_t wt_size = 0;
+    int *wsync = nullptr;  // persistent solves: ticket, error word, one flag per 64 rows
+    int epoch = 0;
     // host copies
     DevStatus host_st{-1, 0, 0};
     bool stats_done = false;
     bool anorm_done = false;
     double anorm = 0.0;
     rmge_factor_stats stats{};
-    hipEvent_t ev[3] = {nullptr, nullptr, nullptr};
+    hipEvent_t ev[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};
+    hipStream_t side = nullptr;  // look-ahead stream (default priority)
+    hipStream_t main = nullptr;  // set when the side stream owns reserved CUs
+    hipEvent_t ev_narrow = nullptr, ev_panel = nullptr, ev_fork = nullptr, ev_join = nullptr;
 };
 
 namespace {
@@ -136,8 +142,9 @@ struct Prec<double> {
     }
     static hipError_t gemm_a64(int64_t M, int64_t N, int64_t K, const double *A, int64_t lda,
                                const double *B, int64_t ldb, double *C, int64_t ldc,
-                               hipStream_t s) {
-        return gemm_f64(kGemmSquare, M, N, K, 1.0, A, lda, B, ldb, 0.0, C, ldc, nullptr, s);
+                               double *absmax, hipStream_t s) {
+        return gemm_f64(kGemmProduct, M, N, K, 1.0, A, lda, B, ldb, 0.0, C, ldc, nullptr, s,
+                        absmax);
     }
     static hipError_t normals(double *out, int64_t count, uint64_t seed, uint64_t stream,
                               hipStream_t s) {
@@ -152,8 +159,10 @@ struct Prec<float> {
         return gemm_f32(shape, M, N, K, alpha, A, lda, B, ldb, beta, C, ldc, abort, s);
     }
     static hipError_t gemm_a64(int64_t M, int64_t N, int64_t K, const double *A, int64_t lda,
-                               const float *B, int64_t ldb, float *C, int64_t ldc, hipStream_t s) {
-        return gemm_f32_a64(kGemmSquare, M, N, K, 1.0f, A, lda, B, ldb, 0.0f, C, ldc, nullptr, s);
+                               const float *B, int64_t ldb, float *C, int64_t ldc, double *absmax,
+                               hipStream_t s) {
+        return gemm_f32_a64(kGemmProduct, M, N, K, 1.0f, A, lda, B, ldb, 0.0f, C, ldc, nullptr, s,
+                            absmax);
     }
     static hipError_t normals(float *out, int64_t count, uint64_t seed, uint64_t stream,
                               hipStream_t s) {
@@ -168,77 +177,127 @@ struct Prec<float> {
 // Blocks wider than the LDS leaf are split once: B = [[Ba, Bab], [Bba, Bb]] is
 // eliminated as in eq. eqgenp with pivot block Ba.
 template <typename T>
-hipError_t factor_pivot_block(rmge_factors *f, T *a, int b, int64_t k0) {
+hipError_t factor_pivot_block(rmge_factors *f, T *a, int b, int64_t k0, T *Linv, T *Uinv,
+                              hipStream_t s) {
     const int64_t ld = f->ld;
-    T *Linv = static_cast<T *>(f->inv);
-    T *Uinv = Linv + kInvLd * kInvLd;
     const int *abort = &f->st->code;
-    hipStream_t s = f->stream;
     if (b <= kLeaf) return leaf_lu<T>(a, ld, b, Linv, Uinv, kInvLd, k0, f->st, s);
     const int b1 = kLeaf, b2 = b - kLeaf;
     HIP_TRY(leaf_lu<T>(a, ld, b1, Linv, Uinv, kInvLd, k0, f->st, s));
     // Bab <- La^{-1} Bab ; Bba <- Bba Ua^{-1} ; Bb <- Bb - Bba Bab
     HIP_TRY(trsm<T>(0, a, ld, b1, a + b1, ld, b2, Linv, abort, s));
     HIP_TRY(trsm<T>(1, a, ld, b1, a + b1 * ld, ld, b2, Uinv, abort, s));
-    HIP_TRY(Prec<T>::gemm(kGemmSquare, b2, b2, b1, T(-1), a + b1 * ld, ld, a + b1, ld, T(1),
+    HIP_TRY(Prec<T>::gemm(kGemmUpdate, b2, b2, b1, T(-1), a + b1 * ld, ld, a + b1, ld, T(1),
                           a + b1 * ld + b1, ld, abort, s));
     return leaf_lu<T>(a + b1 * ld + b1, ld, b2, Linv + b1 * kInvLd + b1, Uinv + b1 * kInvLd + b1,
                       kInvLd, k0 + b1, f->st, s);
 }
 
 // Right-looking block elimination with no pivoting (eq. eqgenp applied to
-// pivot blocks of f->block columns): per step, factor the pivot block B,
-// replace C by L_B^{-1} C and D by D U_B^{-1} in place, and update E to the
-// Schur complement E - (D U_B^{-1})(L_B^{-1} C) = E - D B^{-1} C.
+// pivot blocks of f->block columns) with one panel of look-ahead.  Step k:
+//   main stream:  C <- L_B^{-1} C for the block row right of the pivot block;
+//                 Schur update of the next panel's columns only;
+//   side stream:  (after that narrow update) factor the next pivot block and
+//                 D <- D U_B^{-1} for the column below it;
+//   main stream:  Schur update E <- E - D C of all remaining columns, which
+//                 runs while the side stream works on the next panel.
+// The update E - (D U_B^{-1})(L_B^{-1} C) is E - D B^{-1} C of eq. eqgenp.
+// Inverses of the pivot blocks' diagonal sub-blocks alternate between two
+// buffers so the side stream never overwrites those the main stream reads.
 template <typename T>
 hipError_t genp_blocked(rmge_factors *f) {
     T *a = static_cast<T *>(f->lu);
     const int64_t n = f->n, ld = f->ld;
     const int nb = f->block;
-    T *Linv = static_cast<T *>(f->inv);
-    T *Uinv = Linv + kInvLd * kInvLd;
+    T *inv = static_cast<T *>(f->inv);
+    const int64_t invsz = 2 * kInvLd * kInvLd;
     const int *abort = &f->st->code;
-    hipStream_t s = f->stream;
-    for (int64_t k = 0; k < n; k += nb) {
+    hipStream_t s0 = f->main ? f->main : f->stream, s1 = f->side;
+    if (f->main) {
+        HIP_TRY(hipEventRecord(f->ev_fork, f->stream));
+        HIP_TRY(hipStreamWaitEvent(s0, f->ev_fork, 0));
+    }
+    auto Linv = [&](int64_t step) { return inv + (step & 1) * invsz; };
+    auto Uinv = [&](int64_t step) { return inv + (step & 1) * invsz + kInvLd * kInvLd; };
+
+    // panel 0 on the main stream
+    {
+        const int b = static_cast<int>(n < nb ? n : nb);
+        HIP_TRY(factor_pivot_block<T>(f, a, b, 0, Linv(0), Uinv(0), s0));
+        if (b < n) HIP_TRY(trsm<T>(1, a, ld, b, a + b * ld, ld, n - b, Uinv(0), abort, s0));
+    }
+    int64_t step = 0;
+    for (int64_t k = 0; k < n; k += nb, ++step) {
         const int b = static_cast<int>((n - k) < nb ? (n - k) : nb);
-        T *akk = a + k * ld + k;
-        HIP_TRY(factor_pivot_block<T>(f, akk, b, k));
+        if (k > 0) HIP_TRY(hipStreamWaitEvent(s0, f->ev_panel, 0));
         if (k + b >= n) break;
         const int64_t r = n - k - b;
+        const int bn = static_cast<int>(r < nb ? r : nb);  // next panel width
+        T *akk = a + k * ld + k;
         T *a12 = akk + b, *a21 = akk + b * ld, *a22 = akk + b * ld + b;
-        HIP_TRY(trsm<T>(0, akk, ld, b, a12, ld, r, Linv, abort, s));
-        HIP_TRY(trsm<T>(1, akk, ld, b, a21, ld, r, Uinv, abort, s));
-        HIP_TRY(Prec<T>::gemm(kGemmSquare, r, r, b, T(-1), a21, ld, a12, ld, T(1), a22, ld, abort,
-                              s));
+        HIP_TRY(trsm<T>(0, akk, ld, b, a12, ld, r, Linv(step), abort, s0));
+        HIP_TRY(Prec<T>::gemm(kGemmUpdate, r, bn, b, T(-1), a21, ld, a12, ld, T(1), a22, ld, abort,
+                              s0));
+        HIP_TRY(hipEventRecord(f->ev_narrow, s0));
+        HIP_TRY(hipStreamWaitEvent(s1, f->ev_narrow, 0));
+        HIP_TRY(factor_pivot_block<T>(f, a22, bn, k + b, Linv(step + 1), Uinv(step + 1), s1));
+        if (r > bn)
+            HIP_TRY(trsm<T>(1, a22, ld, bn, a22 + bn * ld, ld, r - bn, Uinv(step + 1), abort, s1));
+        HIP_TRY(hipEventRecord(f->ev_panel, s1));
+        if (r > bn)
+            HIP_TRY(Prec<T>::gemm(kGemmUpdate, r, r - bn, b, T(-1), a21, ld, a12 + bn, ld, T(1),
+                                  a22 + bn, ld, abort, s0));
+    }
+    if (f->main) {
+        HIP_TRY(hipEventRecord(f->ev_join, s0));
+        HIP_TRY(hipStreamWaitEvent(f->stream, f->ev_join, 0));
     }
     return hipSuccess;
 }
 
-// M = A H into f->lu (precision T).
+// Draw the multiplier's parameters (and, for the FFT kinds, its spectrum).
 template <typename T>
-hipError_t precondition(rmge_factors *f) {
+hipError_t draw_multiplier(rmge_factors *f) {
+    const int64_t n = f->n;
+    hipStream_t s = f->stream;
+    switch (f->kind) {
+    case RMGE_MULT_NONE: return hipSuccess;
+    case RMGE_MULT_GAUSSIAN:
+        return Prec<T>::normals(static_cast<T *>(f->G), n * n, f->seed, 1, s);
+    default: {
+        HIP_TRY(launch_normals_f64(f->params, f->kind == RMGE_MULT_CIRCULANT ? n : 2 * n - 1,
+                                   f->seed, static_cast<uint64_t>(f->kind), s));
+        HIP_TRY(fft_embed(f->kind, f->params, n, f->m, f->hker, s));
+        return fft_spectrum(f->hker, f->m, f->tw, f->hhat, s);
+    }
+    }
+}
+
+// M = A H into f->lu (precision T): one dense product, or one FFT pass over the
+// rows; max |M| (for the growth statistic) is accumulated into `absmax` by the
+// same kernels when it is not null.
+template <typename T>
+hipError_t multiply(rmge_factors *f, double *absmax) {
     const int64_t n = f->n;
     hipStream_t s = f->stream;
     T *lu = static_cast<T *>(f->lu);
     switch (f->kind) {
     case RMGE_MULT_NONE:
-        return convert_2d<double, T>(f->A, f->lda, lu, f->ld, n, n, s);
-    case RMGE_MULT_GAUSSIAN: {
-        T *G = static_cast<T *>(f->G);
-        hipError_t e = Prec<T>::normals(G, n * n, f->seed, 1, s);
-        if (e != hipSuccess) return e;
-        return Prec<T>::gemm_a64(n, n, n, f->A, f->lda, G, n, lu, f->ld, s);
-    }
-    default: {
-        hipError_t e = launch_normals_f64(f->params, f->kind == RMGE_MULT_CIRCULANT ? n : 2 * n - 1,
-                                          f->seed, static_cast<uint64_t>(f->kind), s);
-        if (e != hipSuccess) return e;
-        if ((e = fft_embed(f->kind, f->params, n, f->m, f->hker, s)) != hipSuccess) return e;
-        if ((e = fft_spectrum(f->hker, f->m, f->tw, f->hhat, s)) != hipSuccess) return e;
+        HIP_TRY((convert_2d<double, T>(f->A, f->lda, lu, f->ld, n, n, s)));
+        return absmax ? abs_max<T>(lu, f->ld, n, absmax - 2, s) : hipSuccess;
+    case RMGE_MULT_GAUSSIAN:
+        return Prec<T>::gemm_a64(n, n, n, f->A, f->lda, static_cast<const T *>(f->G), n, lu,
+                                 f->ld, absmax, s);
+    default:
         return fft_rows<double, T>(f->A, f->lda, 1, n, n, f->m, f->tw, f->hhat, 1, 0.0, lu, f->ld,
-                                   1, s);
+                                   1, s, absmax);
     }
-    }
+}
+
+template <typename T>
+hipError_t precondition(rmge_factors *f) {
+    HIP_TRY(draw_multiplier<T>(f));
+    return multiply<T>(f, nullptr);
 }
 
 template <typename T>
@@ -249,18 +308,22 @@ rmge_status run_factor(rmge_factors *f) {
     hipLaunchKernelGGL(k_reset, dim3(1), dim3(1), 0, s, f->st, f->scal);
     RMGE_TRY(hipGetLastError());
     RMGE_TRY(hipEventRecord(f->ev[0], s));
-    RMGE_TRY(precondition<T>(f));
-    RMGE_TRY(abs_max<T>(static_cast<const T *>(f->lu), f->ld, f->n, f->scal, s));
+    RMGE_TRY(draw_multiplier<T>(f));
     RMGE_TRY(hipEventRecord(f->ev[1], s));
-    RMGE_TRY(genp_blocked<T>(f));
+    RMGE_TRY(multiply<T>(f, f->scal + 2));
     RMGE_TRY(hipEventRecord(f->ev[2], s));
+    RMGE_TRY(hipEventRecord(f->ev[3], s));
+    RMGE_TRY(genp_blocked<T>(f));
+    RMGE_TRY(hipEventRecord(f->ev[4], s));
     RMGE_TRY(hipMemcpyAsync(&f->host_st, f->st, sizeof(DevStatus), hipMemcpyDeviceToHost, s));
     RMGE_TRY(hipStreamSynchronize(s));
-    float t01 = 0.f, t12 = 0.f;
+    float t01 = 0.f, t12 = 0.f, t34 = 0.f;
     (void)hipEventElapsedTime(&t01, f->ev[0], f->ev[1]);
     (void)hipEventElapsedTime(&t12, f->ev[1], f->ev[2]);
+    (void)hipEventElapsedTime(&t34, f->ev[3], f->ev[4]);
     f->stats.ms_multiplier = t01;
-    f->stats.ms_factor = t12;
+    f->stats.ms_product = t12;
+    f->stats.ms_factor = t34;
     f->stats.info = f->host_st.code ? f->host_st.info : -1;
     f->stats.status = f->host_st.code;
     f->stats.block = f->block;
@@ -272,11 +335,15 @@ rmge_status run_factor(rmge_factors *f) {
 void free_handle(rmge_factors *f) {
     if (!f) return;
     void *ptrs[] = {f->lu, f->G, f->params, f->hker, f->hhat, f->tw, f->inv, f->st, f->scal,
-                    f->wy, f->wx, f->wr, f->wnorm, f->wt};
+                    f->wy, f->wx, f->wr, f->wnorm, f->wt, f->wsync};
     for (void *p : ptrs)
         if (p) (void)hipFree(p);
     for (hipEvent_t &e : f->ev)
         if (e) (void)hipEventDestroy(e);
+    for (hipEvent_t e : {f->ev_narrow, f->ev_panel, f->ev_fork, f->ev_join})
+        if (e) (void)hipEventDestroy(e);
+    if (f->side) (void)hipStreamDestroy(f->side);
+    if (f->main) (void)hipStreamDestroy(f->main);
     delete f;
 }
 
@@ -293,12 +360,29 @@ rmge_status alloc_handle(rmge_factors *f) {
         RMGE_TRY(hipMalloc(&f->tw, sizeof(double) * 2 * static_cast<size_t>(L + 1)));
         RMGE_TRY(fft_twiddles(f->m, f->tw, f->stream));
     }
-    const size_t inv_elems = 2 * kInvLd * kInvLd;
+    const size_t inv_elems = 4 * kInvLd * kInvLd;  // two buffers of (Linv, Uinv)
     RMGE_TRY(hipMalloc(&f->inv, es * inv_elems));
     RMGE_TRY(hipMemsetAsync(f->inv, 0, es * inv_elems, f->stream));
     RMGE_TRY(hipMalloc(&f->st, sizeof(DevStatus)));
     RMGE_TRY(hipMalloc(&f->scal, sizeof(double) * 8));
     for (hipEvent_t &e : f->ev) RMGE_TRY(hipEventCreate(&e));
+    // Look-ahead stream.  RMGE_SIDE_CUS=k (k > 0) reserves k compute units for it
+    // and gives the rest to an internal main stream (CU masks, same priority).
+    int side_cus = 0;
+    if (const char *env = std::getenv("RMGE_SIDE_CUS")) side_cus = std::atoi(env);
+    int dev = 0, ncu = 0;
+    RMGE_TRY(hipGetDevice(&dev));
+    RMGE_TRY(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev));
+    if (side_cus > 0 && side_cus < ncu) {
+        std::vector<uint32_t> ms((ncu + 31) / 32, 0u), mm((ncu + 31) / 32, 0u);
+        for (int c = 0; c < ncu; ++c) (c < side_cus ? ms : mm)[c / 32] |= 1u << (c % 32);
+        RMGE_TRY(hipExtStreamCreateWithCUMask(&f->side, static_cast<uint32_t>(ms.size()), ms.data()));
+        RMGE_TRY(hipExtStreamCreateWithCUMask(&f->main, static_cast<uint32_t>(mm.size()), mm.data()));
+    } else {
+        RMGE_TRY(hipStreamCreateWithFlags(&f->side, hipStreamNonBlocking));
+    }
+    for (hipEvent_t *e : {&f->ev_narrow, &f->ev_panel, &f->ev_fork, &f->ev_join})
+        RMGE_TRY(hipEventCreateWithFlags(e, hipEventDisableTiming));
     return RMGE_OK;
 }
 
@@ -322,6 +406,12 @@ rmge_status ensure_solve_ws(rmge_factors *f, int64_t nrhs, bool need_t) {
         RMGE_TRY(hipMalloc(&f->wnorm, sizeof(double) * static_cast<size_t>(4 * nrhs + 8)));
         f->ws_nrhs = nrhs;
     }
+    if (!f->wsync) {
+        const size_t words = 2 + static_cast<size_t>((n + kSolveBlock - 1) / kSolveBlock);
+        RMGE_TRY(hipMalloc(&f->wsync, sizeof(int) * words));
+        RMGE_TRY(hipMemsetAsync(f->wsync, 0, sizeof(int) * words, f->stream));
+        f->epoch = 0;
+    }
     if (need_t && f->kind == RMGE_MULT_GAUSSIAN) {
         const int64_t want = ((n + 255) / 256) * n * (nrhs < 16 ? nrhs : 16);
         if (want > f->wt_size) {
@@ -335,28 +425,33 @@ rmge_status ensure_solve_ws(rmge_factors *f, int64_t nrhs, bool need_t) {
     return RMGE_OK;
 }
 
-// Triangular solves on the workspace: src (T, n x nrhs) -> U^{-1} L^{-1} src,
-// result left in f->wy; `adjoint` solves U^T then L^T instead.
+// Triangular solves on the workspace: wy (T, n x nrhs) <- U^{-1} L^{-1} wy
+// (`adjoint`: U^{-T} then L^{-T}), one persistent launch per solve and group
+// of 16 right-hand sides, through wx.
 template <typename T>
 hipError_t tri_solves(rmge_factors *f, int64_t nrhs, bool adjoint) {
     const int64_t n = f->n, ld = f->ld;
     const T *lu = static_cast<const T *>(f->lu);
     T *Y = static_cast<T *>(f->wy), *X = static_cast<T *>(f->wx);
-    const int64_t nblk = (n + kSolveBlock - 1) / kSolveBlock;
     hipStream_t s = f->stream;
     const int first = adjoint ? 2 : 0, second = adjoint ? 3 : 1;
     for (int64_t g = 0; g < nrhs; g += 16) {
         const int nr = static_cast<int>((nrhs - g) < 16 ? (nrhs - g) : 16);
-        for (int64_t b = 0; b < nblk; ++b) {
-            hipError_t e = trsv_step<T>(first, lu, ld, n, b, Y + g, X + g, nrhs, nr, nullptr, s);
-            if (e != hipSuccess) return e;
-        }
-        for (int64_t b = nblk - 1; b >= 0; --b) {
-            hipError_t e = trsv_step<T>(second, lu, ld, n, b, X + g, Y + g, nrhs, nr, nullptr, s);
-            if (e != hipSuccess) return e;
-        }
+        HIP_TRY(trsv_full<T>(first, lu, ld, n, Y + g, X + g, nrhs, nr, f->wsync, ++f->epoch, s));
+        HIP_TRY(trsv_full<T>(second, lu, ld, n, X + g, Y + g, nrhs, nr, f->wsync, ++f->epoch, s));
     }
     return hipSuccess;
+}
+
+// After a stream sync: did a persistent solve give up waiting?
+rmge_status solve_sync_error(rmge_factors *f) {
+    int err = 0;
+    RMGE_TRY(hipMemcpy(&err, f->wsync + 1, sizeof(int), hipMemcpyDeviceToHost));
+    if (err) {
+        RMGE_TRY(hipMemset(f->wsync + 1, 0, sizeof(int)));
+        return RMGE_EDEVICE;
+    }
+    return RMGE_OK;
 }
 
 // X = beta X + H U^{-1} L^{-1} src   (src FP64 n x nrhs, lds)
@@ -440,6 +535,8 @@ rmge_status run_solve(rmge_factors *f, const double *B, int64_t nrhs, int64_t ld
         if (rs != RMGE_OK) return rs;
         loc.eta_hist[it] = eta;
     }
+    rs = solve_sync_error(f);
+    if (rs != RMGE_OK) return rs;
     loc.iters = it;
     loc.eta = eta;
     loc.converged = (tol <= 0.0 || eta <= tol) ? 1 : 0;
@@ -471,7 +568,7 @@ rmge_status run_adjoint(rmge_factors *f, const double *W, int64_t nrhs, int64_t 
     RMGE_TRY(tri_solves<T>(f, nrhs, true));
     RMGE_TRY((convert_2d<T, double>(Z, nrhs, Y, ldy, n, nrhs, s)));
     RMGE_TRY(hipStreamSynchronize(s));
-    return RMGE_OK;
+    return solve_sync_error(f);
 }
 
 rmge_status check_factor_args(const double *A, int64_t n, int64_t lda, int32_t kind,

@@ -57,7 +57,8 @@ template <typename TI, typename TO>
 __global__ __launch_bounds__(1024) void k_fft_rows(const TI *in, int64_t vsi, int64_t esi,
                                                    int64_t n, int L, int logL, const cplx *tw,
                                                    const cplx *hhat, int conj, double beta, TO *out,
-                                                   int64_t vso, int64_t eso, cplx *spec) {
+                                                   int64_t vso, int64_t eso, cplx *spec,
+                                                   double *absmax) {
     extern __shared__ cplx z[];
     const int tid = threadIdx.x, nt = blockDim.x;
     const int64_t v = blockIdx.x;
@@ -128,19 +129,30 @@ __global__ __launch_bounds__(1024) void k_fft_rows(const TI *in, int64_t vsi, in
     }
     const double scale = 1.0 / static_cast<double>(L);
     TO *y = out + v * vso;
+    double vmax = 0.0;
     for (int k = tid; k < L; k += nt) {
         const cplx zz = z[bitrev(k, logL)];
         const int64_t j0 = 2 * static_cast<int64_t>(k), j1 = j0 + 1;
         if (j0 < n) {
             TO *p = y + j0 * eso;
             const double val = zz.x * scale;
-            *p = static_cast<TO>(beta == 0.0 ? val : beta * static_cast<double>(*p) + val);
+            const TO o = static_cast<TO>(beta == 0.0 ? val : beta * static_cast<double>(*p) + val);
+            *p = o;
+            vmax = fmax(vmax, fabs(static_cast<double>(o)));
         }
         if (j1 < n) {
             TO *p = y + j1 * eso;
             const double val = zz.y * scale;
-            *p = static_cast<TO>(beta == 0.0 ? val : beta * static_cast<double>(*p) + val);
+            const TO o = static_cast<TO>(beta == 0.0 ? val : beta * static_cast<double>(*p) + val);
+            *p = o;
+            vmax = fmax(vmax, fabs(static_cast<double>(o)));
         }
+    }
+    if (absmax != nullptr) {  // max |out| for the growth statistic, one atomic per wave
+        for (int off = 32; off > 0; off >>= 1) vmax = fmax(vmax, __shfl_xor(vmax, off));
+        if ((tid & 63) == 0)
+            atomicMax(reinterpret_cast<unsigned long long *>(absmax),
+                      static_cast<unsigned long long>(__double_as_longlong(vmax)));
     }
 }
 
@@ -179,7 +191,7 @@ int fft_threads(int L) {
 template <typename TI, typename TO>
 hipError_t launch_rows(const TI *in, int64_t vsi, int64_t esi, int64_t count, int64_t n, int m,
                        const cplx *tw, const cplx *hhat, int conj, double beta, TO *out,
-                       int64_t vso, int64_t eso, cplx *spec, hipStream_t s) {
+                       int64_t vso, int64_t eso, cplx *spec, double *absmax, hipStream_t s) {
     const int L = m / 2;
     const size_t lds = sizeof(cplx) * static_cast<size_t>(L);
     static bool attr_set = false;
@@ -190,7 +202,7 @@ hipError_t launch_rows(const TI *in, int64_t vsi, int64_t esi, int64_t count, in
     }
     hipLaunchKernelGGL((k_fft_rows<TI, TO>), dim3(static_cast<unsigned>(count)),
                        dim3(fft_threads(L)), lds, s, in, vsi, esi, n, L, log2i(L), tw, hhat, conj,
-                       beta, out, vso, eso, spec);
+                       beta, out, vso, eso, spec, absmax);
     return hipGetLastError();
 }
 
@@ -216,29 +228,30 @@ hipError_t fft_spectrum(const double *h, int m, const double *tw, double *hhat, 
     if (!valid_m(m)) return hipErrorInvalidValue;
     return launch_rows<double, double>(h, 0, 1, 1, m, m, reinterpret_cast<const cplx *>(tw),
                                        nullptr, 0, 0.0, static_cast<double *>(nullptr), 0, 0,
-                                       reinterpret_cast<cplx *>(hhat), s);
+                                       reinterpret_cast<cplx *>(hhat), nullptr, s);
 }
 
 template <typename TI, typename TO>
 hipError_t fft_rows(const TI *in, int64_t vstride_in, int64_t estride_in, int64_t count,
                     int64_t n, int m, const double *tw, const double *hhat, int conj, double beta,
-                    TO *out, int64_t vstride_out, int64_t estride_out, hipStream_t s) {
+                    TO *out, int64_t vstride_out, int64_t estride_out, hipStream_t s,
+                    double *absmax) {
     if (count <= 0) return hipSuccess;
     if (!valid_m(m) || n > m) return hipErrorInvalidValue;
     return launch_rows<TI, TO>(in, vstride_in, estride_in, count, n, m,
                                reinterpret_cast<const cplx *>(tw),
                                reinterpret_cast<const cplx *>(hhat), conj, beta, out, vstride_out,
-                               estride_out, nullptr, s);
+                               estride_out, nullptr, absmax, s);
 }
 
 template hipError_t fft_rows<double, double>(const double *, int64_t, int64_t, int64_t, int64_t,
                                              int, const double *, const double *, int, double,
-                                             double *, int64_t, int64_t, hipStream_t);
+                                             double *, int64_t, int64_t, hipStream_t, double *);
 template hipError_t fft_rows<double, float>(const double *, int64_t, int64_t, int64_t, int64_t,
                                             int, const double *, const double *, int, double,
-                                            float *, int64_t, int64_t, hipStream_t);
+                                            float *, int64_t, int64_t, hipStream_t, double *);
 template hipError_t fft_rows<float, double>(const float *, int64_t, int64_t, int64_t, int64_t, int,
                                             const double *, const double *, int, double, double *,
-                                            int64_t, int64_t, hipStream_t);
+                                            int64_t, int64_t, hipStream_t, double *);
 
 }  // namespace rmge

@@ -18,38 +18,14 @@
 // runs are ordered in groups of 8 tile-rows, so the operand panels a wave of
 // workgroups touches stay in that XCD's L2.
 //
-// Bound: MFMA (2 flops per multiply-add) for the square tile at K >= 256;
-// the tall/wide shapes are used where a workgroup must own whole rows or
-// whole columns of C so that C may overwrite its own input (in-place solves).
+// Bound: MFMA (2 flops per multiply-add).  The product's tile is chosen for
+// large K; the Schur update (K = panel width) uses smaller tiles and more
+// workgroups per CU so that reading and writing C overlaps the MFMAs.
+#include "mfma.h"
 #include "rmge_impl.h"
 
 namespace rmge {
 namespace {
-
-typedef double v4d __attribute__((ext_vector_type(4)));
-typedef float v4f __attribute__((ext_vector_type(4)));
-
-template <typename T>
-struct Mma;
-// Operand layouts of both 16x16x4 MFMAs: lane l holds A[l & 15][l >> 4] and
-// B[l >> 4][l & 15].  Result: lane l, item r holds D[row(l, r)][l & 15], with
-// row = (l >> 4) + 4 r for f64 and 4 (l >> 4) + r for f32 (measured on gfx950).
-template <>
-struct Mma<double> {
-    using acc = v4d;
-    __device__ static acc step(double a, double b, acc c) {
-        return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
-    }
-    __device__ static int row(int lane, int r) { return (lane >> 4) + 4 * r; }
-};
-template <>
-struct Mma<float> {
-    using acc = v4f;
-    __device__ static acc step(float a, float b, acc c) {
-        return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
-    }
-    __device__ static int row(int lane, int r) { return 4 * (lane >> 4) + r; }
-};
 
 __device__ inline void tile_coords(int bid, int tiles_m, int tiles_n, int &tm, int &tn) {
     const int tiles = tiles_m * tiles_n;
@@ -67,12 +43,11 @@ __device__ inline void tile_coords(int bid, int tiles_m, int tiles_n, int &tm, i
 }
 
 // T: arithmetic type, TA: storage type of A (double A may feed a float product).
-template <typename T, typename TA, int BM, int BN, int WGM, int WGN>
-__global__ __launch_bounds__(WGM *WGN * 64) void k_gemm(int M, int N, int K, T alpha, const TA *A,
-                                                        int64_t lda, const T *B, int64_t ldb,
-                                                        T beta, T *C, int64_t ldc,
-                                                        const int *abort) {
-    constexpr int BK = 16;
+template <typename T, typename TA, int BM, int BN, int WGM, int WGN, int BK = 16, int MINB = 2>
+__global__ __launch_bounds__(WGM *WGN * 64, MINB) void k_gemm(int M, int N, int K, T alpha,
+                                                           const TA *A, int64_t lda, const T *B,
+                                                           int64_t ldb, T beta, T *C, int64_t ldc,
+                                                           const int *abort, double *absmax) {
     constexpr int NT = WGM * WGN * 64;
     constexpr int WM = BM / WGM, WN = BN / WGN;
     constexpr int TM = WM / 16, TN = WN / 16;
@@ -160,6 +135,7 @@ __global__ __launch_bounds__(WGM *WGN * 64) void k_gemm(int M, int N, int K, T a
 
     const int crow0 = m0 + wm * WM;
     const int ccol0 = n0 + wn * WN + (lane & 15);
+    double vmax = 0.0;
 #pragma unroll
     for (int i = 0; i < TM; ++i)
 #pragma unroll
@@ -170,62 +146,73 @@ __global__ __launch_bounds__(WGM *WGN * 64) void k_gemm(int M, int N, int K, T a
                 if (row < M && col < N) {
                     T *c = C + static_cast<int64_t>(row) * ldc + col;
                     const T v = alpha * acc[i][j][r];
-                    *c = (beta == T(0)) ? v : v + beta * (*c);
+                    const T out = (beta == T(0)) ? v : v + beta * (*c);
+                    *c = out;
+                    vmax = fmax(vmax, fabs(static_cast<double>(out)));
                 }
             }
+    if (absmax != nullptr) {  // max |C| for the growth statistic, one atomic per wave
+        for (int off = 32; off > 0; off >>= 1) vmax = fmax(vmax, __shfl_xor(vmax, off));
+        if (lane == 0)
+            atomicMax(reinterpret_cast<unsigned long long *>(absmax),
+                      static_cast<unsigned long long>(__double_as_longlong(vmax)));
+    }
 }
 
+template <typename T, typename TA, int BM, int BN, int WGM, int WGN, int MINB>
+hipError_t launch(int m, int n, int k, T alpha, const TA *A, int64_t lda, const T *B, int64_t ldb,
+                  T beta, T *C, int64_t ldc, const int *abort, double *absmax, hipStream_t s) {
+    const int64_t tiles = static_cast<int64_t>((m + BM - 1) / BM) * ((n + BN - 1) / BN);
+    hipLaunchKernelGGL((k_gemm<T, TA, BM, BN, WGM, WGN, 16, MINB>),
+                       dim3(static_cast<unsigned>(tiles)), dim3(WGM * WGN * 64), 0, s, m, n, k,
+                       alpha, A, lda, B, ldb, beta, C, ldc, abort, absmax);
+    return hipGetLastError();
+}
+
+// Tile shapes measured on MI355X (n = 16384):
+//   product (large K): 128 x 128, four 64 x 64 waves, two workgroups per CU
+//     (FP64 ~60 TFLOP/s, FP32 ~113 TFLOP/s);
+//   Schur update (K = panel width): FP64 64 x 64 tiles of four 32 x 32 waves,
+//     four workgroups per CU (~48 TFLOP/s at K = 256); FP32 128 x 128 tiles of
+//     eight 32 x 64 waves (~85 TFLOP/s).
 template <typename T, typename TA>
 hipError_t run_gemm(int shape, int64_t M, int64_t N, int64_t K, T alpha, const TA *A, int64_t lda,
                     const T *B, int64_t ldb, T beta, T *C, int64_t ldc, const int *abort,
-                    hipStream_t s) {
+                    double *absmax, hipStream_t s) {
     if (M <= 0 || N <= 0) return hipSuccess;
     if (M > INT32_MAX || N > INT32_MAX || K > INT32_MAX) return hipErrorInvalidValue;
     const int m = static_cast<int>(M), n = static_cast<int>(N), k = static_cast<int>(K);
-    switch (shape) {
-    case kGemmRows: {
-        constexpr int BM = 64, BN = 256;
-        const int64_t tiles = ((M + BM - 1) / BM) * ((N + BN - 1) / BN);
-        hipLaunchKernelGGL((k_gemm<T, TA, BM, BN, 1, 4>), dim3(static_cast<unsigned>(tiles)),
-                           dim3(256), 0, s, m, n, k, alpha, A, lda, B, ldb, beta, C, ldc, abort);
-        break;
-    }
-    case kGemmCols: {
-        constexpr int BM = 256, BN = 64;
-        const int64_t tiles = ((M + BM - 1) / BM) * ((N + BN - 1) / BN);
-        hipLaunchKernelGGL((k_gemm<T, TA, BM, BN, 4, 1>), dim3(static_cast<unsigned>(tiles)),
-                           dim3(256), 0, s, m, n, k, alpha, A, lda, B, ldb, beta, C, ldc, abort);
-        break;
-    }
-    default: {
-        constexpr int BM = 128, BN = 128;
-        const int64_t tiles = ((M + BM - 1) / BM) * ((N + BN - 1) / BN);
-        hipLaunchKernelGGL((k_gemm<T, TA, BM, BN, 2, 2>), dim3(static_cast<unsigned>(tiles)),
-                           dim3(256), 0, s, m, n, k, alpha, A, lda, B, ldb, beta, C, ldc, abort);
-        break;
-    }
-    }
-    return hipGetLastError();
+    if (shape == kGemmProduct)
+        return launch<T, TA, 128, 128, 2, 2, 2>(m, n, k, alpha, A, lda, B, ldb, beta, C, ldc,
+                                                abort, absmax, s);
+    if (sizeof(T) == 8)
+        return launch<T, TA, 64, 64, 2, 2, 4>(m, n, k, alpha, A, lda, B, ldb, beta, C, ldc, abort,
+                                              absmax, s);
+    return launch<T, TA, 128, 128, 4, 2, 1>(m, n, k, alpha, A, lda, B, ldb, beta, C, ldc, abort,
+                                            absmax, s);
 }
 
 }  // namespace
 
 hipError_t gemm_f64(int shape, int64_t M, int64_t N, int64_t K, double alpha, const double *A,
                     int64_t lda, const double *B, int64_t ldb, double beta, double *C, int64_t ldc,
-                    const int *abort, hipStream_t s) {
-    return run_gemm<double, double>(shape, M, N, K, alpha, A, lda, B, ldb, beta, C, ldc, abort, s);
+                    const int *abort, hipStream_t s, double *absmax) {
+    return run_gemm<double, double>(shape, M, N, K, alpha, A, lda, B, ldb, beta, C, ldc, abort,
+                                    absmax, s);
 }
 
 hipError_t gemm_f32(int shape, int64_t M, int64_t N, int64_t K, float alpha, const float *A,
                     int64_t lda, const float *B, int64_t ldb, float beta, float *C, int64_t ldc,
-                    const int *abort, hipStream_t s) {
-    return run_gemm<float, float>(shape, M, N, K, alpha, A, lda, B, ldb, beta, C, ldc, abort, s);
+                    const int *abort, hipStream_t s, double *absmax) {
+    return run_gemm<float, float>(shape, M, N, K, alpha, A, lda, B, ldb, beta, C, ldc, abort,
+                                  absmax, s);
 }
 
 hipError_t gemm_f32_a64(int shape, int64_t M, int64_t N, int64_t K, float alpha, const double *A,
                         int64_t lda, const float *B, int64_t ldb, float beta, float *C,
-                        int64_t ldc, const int *abort, hipStream_t s) {
-    return run_gemm<float, double>(shape, M, N, K, alpha, A, lda, B, ldb, beta, C, ldc, abort, s);
+                        int64_t ldc, const int *abort, hipStream_t s, double *absmax) {
+    return run_gemm<float, double>(shape, M, N, K, alpha, A, lda, B, ldb, beta, C, ldc, abort,
+                                   absmax, s);
 }
 
 }  // namespace rmge

@@ -6,29 +6,29 @@
 // argument after eq. eqgenpin every choice of block sizes produces the same
 // Schur complements.  The host driver (api.hip) walks the matrix in panels of
 // `block` columns.  This file holds
-//   * k_leaf_lu: one pivot block of at most 128 x 128 factored entirely in LDS
-//     by one workgroup, pivot by pivot, plus the inverses of the 32 x 32
-//     diagonal sub-blocks of its two triangular factors;
-//   * k_trsm: B^{-1} C = U_B^{-1} (L_B^{-1} C) and D B^{-1} = (D U_B^{-1}) L_B^{-1}
-//     split into the two triangular solves, each done in place by blocked
-//     substitution on a strip staged in LDS: the 32 x 32 diagonal sub-blocks
-//     are applied through their inverses, the rest as plain updates.  Only
-//     small blocks are inverted, so the error grows with the condition of
-//     32 x 32 blocks, not of the whole pivot block.
+//   * k_leaf_lu: one pivot block of at most 128 x 128 factored by one
+//     workgroup with the block held in registers, pivot by pivot, plus the
+//     inverses of the 32 x 32 diagonal sub-blocks of its two triangular factors;
+//   * k_trsm_left / k_trsm_right: the off-diagonal blocks of eq. eqgenp,
+//     L_B^{-1} C and D U_B^{-1} (their product is D B^{-1} C), each done in
+//     place by blocked substitution on the matrix cores: the 32 x 32 diagonal
+//     sub-blocks are applied through their inverses, the rest as plain
+//     updates.  Only small blocks are inverted, so the error grows with the
+//     condition of 32 x 32 blocks, not of the whole pivot block.
 //
 // Breakdown: a pivot that is exactly 0 (Corollary corec: the input is not
 // strongly nonsingular) or not finite stops the elimination; its global index
 // is recorded in the device status word and every later kernel exits early.
 //
-// Bound: the leaf is latency bound (b sequential pivot steps, two barriers
-// each); the solves issue one LDS read per multiply-add (VALU/LDS bound) and
-// carry b^2 / 2 multiply-adds per strip column.
+// Bound: the leaf is latency bound (b sequential pivot steps, one barrier
+// each); the solves are MFMA work of b^2 / 2 multiply-adds per strip column,
+// with b / 32 dependent sub-block steps per strip.
+#include "mfma.h"
 #include "rmge_impl.h"
 
 namespace rmge {
 namespace {
 
-constexpr int kLd = kLeaf + 1;  // LDS row stride (one element of padding)
 constexpr int kSub = 32;        // diagonal sub-blocks that are inverted explicitly
 constexpr int kInvLdDev = kMaxBlock;
 
@@ -37,189 +37,378 @@ __device__ inline bool is_bad(T p) {
     return p == T(0) || !isfinite(p);
 }
 
+// One pivot block (b <= 128) in registers: thread (ty, tx) of a 16 x 16 grid
+// (one wave per SIMD) holds elements (ty + 16 p, tx + 16 q), p, q < 8.  Pivot
+// step j: the owners of column j and of row j publish them to LDS (double
+// buffered, so one barrier per step) and every thread applies the rank-1
+// update a_ic -= (a_ij / a_jj) a_jc to the elements it holds, with the
+// multiplier formed as a_ij times the reciprocal of the pivot.  Multipliers of
+// rows <= j and pivot-row entries of columns <= j are zero, so the update is
+// branch-free (retired elements receive exact zero updates) and an element
+// below the diagonal keeps the value it had when its column was eliminated;
+// the multipliers l_ic = a_ic / a_cc are formed at write-back from the
+// recorded pivot reciprocals.
 template <typename T>
-__global__ __launch_bounds__(1024) void k_leaf_lu(T *a, int64_t lda, int b, T *Linv, T *Uinv,
-                                                  int64_t ldw, int64_t k0, DevStatus *st) {
-    __shared__ T s[kLeaf * kLd];
-    __shared__ T red[4][8][kSub];
+__global__ __launch_bounds__(256) void k_leaf_lu(T *a, int64_t lda, int b, int64_t k0,
+                                                 DevStatus *st) {
+    __shared__ T colv[2][kLeaf];
+    __shared__ T rowv[2][kLeaf];
+    __shared__ T rcp[kLeaf];
     if (st->code != 0) return;  // an earlier pivot block broke down
+    // This kernel is a chain of short dependent steps that runs beside the wide
+    // Schur-update GEMM; raise its waves' issue priority on the shared SIMDs.
+    __builtin_amdgcn_s_setprio(3);
     const int tid = threadIdx.x;
-    const int tx = tid & 31, ty = tid >> 5;  // 32 x 32 thread grid
-
-    for (int i = ty; i < b; i += 32)
-        for (int j = tx; j < b; j += 32) s[i * kLd + j] = a[static_cast<int64_t>(i) * lda + j];
-    __syncthreads();
+    const int tx = tid & 15, ty = tid >> 4;
+    T v[8][8];
+#pragma unroll
+    for (int p = 0; p < 8; ++p)
+#pragma unroll
+        for (int q = 0; q < 8; ++q) {
+            const int i = ty + 16 * p, c = tx + 16 * q;
+            v[p][q] = (i < b && c < b) ? a[static_cast<int64_t>(i) * lda + c] : T(0);
+        }
 
     // Unblocked elimination, pivot by pivot (eq. eqgenp with 1 x 1 pivot blocks).
     int done = b;
     for (int j = 0; j < b; ++j) {
-        const T p = s[j * kLd + j];
-        if (is_bad(p)) {
+        const int buf = j & 1, jq = j >> 4, jr = j & 15;
+        if (tx == jr) {
+            switch (jq) {  // jq is uniform: one case runs, with static register indices
+#define RMGE_COL(Q)                                                          \
+    case Q:                                                                  \
+        _Pragma("unroll") for (int p = 0; p < 8; ++p) colv[buf][ty + 16 * p] = v[p][Q]; \
+        break;
+                RMGE_COL(0) RMGE_COL(1) RMGE_COL(2) RMGE_COL(3)
+                RMGE_COL(4) RMGE_COL(5) RMGE_COL(6) RMGE_COL(7)
+#undef RMGE_COL
+            }
+        }
+        if (ty == jr) {
+            switch (jq) {
+#define RMGE_ROW(P)                                                          \
+    case P:                                                                  \
+        _Pragma("unroll") for (int q = 0; q < 8; ++q) rowv[buf][tx + 16 * q] = v[P][q]; \
+        break;
+                RMGE_ROW(0) RMGE_ROW(1) RMGE_ROW(2) RMGE_ROW(3)
+                RMGE_ROW(4) RMGE_ROW(5) RMGE_ROW(6) RMGE_ROW(7)
+#undef RMGE_ROW
+            }
+        }
+        __syncthreads();
+        const T piv = rowv[buf][j];
+        if (is_bad(piv)) {
             if (tid == 0) {
                 st->info = k0 + j;
-                st->code = (p == T(0)) ? 4 : 5;
+                st->code = (piv == T(0)) ? 4 : 5;
             }
             done = j;
             break;
         }
-        for (int i = j + 1 + tid; i < b; i += 1024) s[i * kLd + j] = s[i * kLd + j] / p;
-        __syncthreads();
-        for (int i = j + 1 + ty; i < b; i += 32) {
-            const T l = s[i * kLd + j];
-            for (int c = j + 1 + tx; c < b; c += 32) s[i * kLd + c] -= l * s[j * kLd + c];
+        const T rp = T(1) / piv;
+        if (tid == 0) rcp[j] = rp;
+        T u[8];
+#pragma unroll
+        for (int q = 0; q < 8; ++q) {
+            const int c = tx + 16 * q;
+            u[q] = (c > j) ? rowv[buf][c] : T(0);
         }
-        __syncthreads();
+#pragma unroll
+        for (int p = 0; p < 8; ++p) {
+            const int i = ty + 16 * p;
+            const T l = (i > j) ? colv[buf][i] * rp : T(0);
+#pragma unroll
+            for (int q = 0; q < 8; ++q) v[p][q] -= l * u[q];
+        }
     }
-
-    for (int i = ty; i < b; i += 32)
-        for (int j = tx; j < b; j += 32) a[static_cast<int64_t>(i) * lda + j] = s[i * kLd + j];
+    __syncthreads();
+    // write back, forming the multipliers below the diagonal
+#pragma unroll
+    for (int p = 0; p < 8; ++p)
+#pragma unroll
+        for (int q = 0; q < 8; ++q) {
+            const int i = ty + 16 * p, c = tx + 16 * q;
+            if (c < i && c < done) v[p][q] *= rcp[c];
+            if (i < b && c < b) a[static_cast<int64_t>(i) * lda + c] = v[p][q];
+        }
     if (done < b) return;
 
-    // Inverses of the 32 x 32 diagonal sub-blocks of U and of the unit lower
-    // factor, in place in LDS; the off-diagonal coupling is applied later by
-    // blocked substitution (k_trsm), so only these small inverses are formed.
-    // Threads: 4 sub-blocks x 32 columns x 8 partial sums.
-    const int q = tid >> 8, col = tid & 31, part = (tid >> 5) & 7;
-    const int q0 = q * kSub;
-    const int sbq = (b - q0) < kSub ? (b - q0) : kSub;  // may be <= 0 for small b
-    // U_qq^{-1}, bottom row first: X[i][i] = 1/U[i][i], X[i][c] = -X[i][i] sum_{k=i+1..c} U[i][k] X[k][c].
-    for (int i = kSub - 1; i >= 0; --i) {
-        const bool act = i < sbq;
-        T acc = T(0);
-        if (act && col > i && col < sbq)
-            for (int k = i + 1 + part; k <= col; k += 8)
-                acc += s[(q0 + i) * kLd + q0 + k] * s[(q0 + k) * kLd + q0 + col];
-        red[q][part][col] = acc;
-        const T d = act ? T(1) / s[(q0 + i) * kLd + q0 + i] : T(0);  // read before row i changes
-        __syncthreads();
-        if (act && part == 0 && col >= i && col < sbq) {
-            if (col == i) {
-                s[(q0 + i) * kLd + q0 + i] = d;
-            } else {
-                T sum = T(0);
-#pragma unroll
-                for (int r = 0; r < 8; ++r) sum += red[q][r][col];
-                s[(q0 + i) * kLd + q0 + col] = -d * sum;
-            }
-        }
-        __syncthreads();
+}
+
+// Inverses of the 32 x 32 diagonal sub-blocks of a factored pivot block (the
+// off-diagonal coupling is applied later by blocked substitution, so only
+// these small inverses are formed).  Wave w < nsub inverts U's sub-block w,
+// wave nsub + w the unit-lower L's; lane c computes column c by substitution.
+template <typename T>
+__global__ __launch_bounds__(512) void k_diag_inv(const T *a, int64_t lda, int b, T *Linv, T *Uinv,
+                                                  int64_t ldw, const DevStatus *st) {
+    __shared__ T dblk[4][kSub][kSub + 1];
+    if (st->code != 0) return;
+    __builtin_amdgcn_s_setprio(3);
+    const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+    const int nsub = (b + kSub - 1) / kSub;
+    for (int e = tid; e < nsub * kSub * kSub; e += blockDim.x) {
+        const int qd = e / (kSub * kSub), i = (e / kSub) % kSub, k = e % kSub;
+        const int gi = qd * kSub + i, gk = qd * kSub + k;
+        dblk[qd][i][k] = (gi < b && gk < b) ? a[static_cast<int64_t>(gi) * lda + gk] : T(0);
     }
-    // L_qq^{-1} (unit diagonal), top row first: X[i][c] = -(L[i][c] + sum_{k=c+1..i-1} L[i][k] X[k][c]).
-    for (int i = 1; i < kSub; ++i) {
-        const bool act = i < sbq;
-        T acc = T(0);
-        if (act && col < i)
-            for (int k = col + 1 + part; k < i; k += 8)
-                acc += s[(q0 + i) * kLd + q0 + k] * s[(q0 + k) * kLd + q0 + col];
-        red[q][part][col] = acc;
-        __syncthreads();
-        if (act && part == 0 && col < i) {
-            T sum = s[(q0 + i) * kLd + q0 + col];
+    __syncthreads();
+    if (wave >= 2 * nsub || lane >= kSub) return;
+    const bool upper = wave < nsub;
+    const int qd = upper ? wave : wave - nsub, c = lane;
+    const int q0 = qd * kSub;
+    const int sbq = (b - q0) < kSub ? (b - q0) : kSub;
+    if (c >= sbq) return;
+    T x[kSub];
+    if (upper) {
+        // column c of U^{-1}: x_c = 1/u_cc, x_i = -(sum_{k=i+1..c} u_ik x_k) / u_ii
 #pragma unroll
-            for (int r = 0; r < 8; ++r) sum += red[q][r][col];
-            s[(q0 + i) * kLd + q0 + col] = -sum;
+        for (int i = kSub - 1; i >= 0; --i) {
+            T sum = T(0);
+#pragma unroll
+            for (int k = i + 1; k < kSub; ++k)
+                if (k <= c) sum += dblk[qd][i][k] * x[k];
+            const T d = (i <= c) ? T(1) / dblk[qd][i][i] : T(0);
+            x[i] = (i == c) ? d : ((i < c) ? -sum * d : T(0));
         }
-        __syncthreads();
-    }
-    if (sbq > 0 && part < 4) {
-        for (int i = part; i < sbq; i += 4) {
-            if (col >= sbq) continue;
-            const T v = s[(q0 + i) * kLd + q0 + col];
-            const int64_t o = static_cast<int64_t>(q0 + i) * ldw + q0 + col;
-            Uinv[o] = (col >= i) ? v : T(0);
-            Linv[o] = (col < i) ? v : (col == i ? T(1) : T(0));
+#pragma unroll
+        for (int i = 0; i < kSub; ++i)
+            if (i < sbq) Uinv[static_cast<int64_t>(q0 + i) * ldw + q0 + c] = x[i];
+    } else {
+        // column c of L^{-1}: x_c = 1, x_i = -sum_{k=c..i-1} l_ik x_k
+#pragma unroll
+        for (int i = 0; i < kSub; ++i) {
+            T sum = T(0);
+#pragma unroll
+            for (int k = 0; k < i; ++k)
+                if (k >= c) sum += dblk[qd][i][k] * x[k];
+            x[i] = (i == c) ? T(1) : ((i > c) ? -sum : T(0));
         }
+#pragma unroll
+        for (int i = 0; i < kSub; ++i)
+            if (i < sbq) Linv[static_cast<int64_t>(q0 + i) * ldw + q0 + c] = x[i];
     }
 }
 
-// Blocked substitution with the packed pivot block of width b (<= 256) at
-// `lu` (ld), in place on a strip of the panel, using the inverses of the
-// 32 x 32 diagonal sub-blocks (Linv / Uinv, ld kInvLd):
-//   LEFT  (kind 0): X = L^{-1} C   for a 256-row x 32-column strip of C = A12;
-//   RIGHT (kind 1): X = D U^{-1}   for a 32-row x 256-column strip of D = A21,
-//                   done as the left solve X^T = U^{-T} D^T on the transposed strip.
-// The strip and the current sub-block column of the factor are staged in LDS;
-// thread (c, g) owns column c of the (transposed) strip and rows g, g + 8, ...
-template <typename T, int SIDE>
-__global__ __launch_bounds__(256) void k_trsm(const T *lu, int64_t ld, int b, T *C, int64_t ldc,
-                                              int64_t count, const T *Dinv, const int *abort) {
-    constexpr int W = 32, LS = W + 1;
-    __shared__ T S[kMaxBlock * LS];      // strip, S[k][c]
-    __shared__ T P[(kMaxBlock - kSub) * LS];  // factor rows below the current sub-block
-    __shared__ T Dv[kSub * LS];          // current diagonal sub-block inverse
+// Blocked substitution on the matrix cores.  The pivot block's factors sit
+// packed at `lu` (ld, width b <= 256); Dinv holds the inverses of their
+// 32 x 32 diagonal sub-blocks (ld kInvLdDev).  One workgroup owns a 32-wide
+// strip of the panel and keeps it in MFMA accumulators, 16 x 16 tiles dealt
+// round-robin to its four waves.  Per diagonal sub-block i the two tiles of
+// rows i are published to LDS, multiplied by the sub-block inverse, published
+// again as X_i, and every wave subtracts (factor block) x X_i from its tiles
+// further along; the factor operand streams from L2.
+//
+// LEFT:  C (b x count) <- L^{-1} C, strips of 32 columns (row tiles dealt).
+template <typename T>
+__global__ __launch_bounds__(256, 2) void k_trsm_left(const T *lu, int64_t ld, int b, T *C,
+                                                      int64_t ldc, int64_t count, const T *Dinv,
+                                                      const int *abort) {
+    using acc_t = typename Mma<T>::acc;
+    constexpr int BN = 32;
+    __shared__ T Xs[kSub][BN + 1];
+    __shared__ T Ds[kSub][kSub + 1];
     if (abort != nullptr && *abort != 0) return;
-    const int tid = threadIdx.x, c = tid & (W - 1), g = tid >> 5;
-    const int64_t c0 = static_cast<int64_t>(blockIdx.x) * W;
-    const int w = static_cast<int>((count - c0) < W ? (count - c0) : W);
-    // load the strip
-    if (SIDE == 0) {
-        for (int e = tid; e < b * W; e += 256) {
-            const int k = e / W, cc = e % W;
-            S[k * LS + cc] = cc < w ? C[k * ldc + c0 + cc] : T(0);
-        }
-    } else {
-        for (int e = tid; e < b * W; e += 256) {
-            const int cc = e / b, k = e % b;
-            S[k * LS + cc] = cc < w ? C[(c0 + cc) * ldc + k] : T(0);
-        }
-    }
-    for (int i0 = 0; i0 < b; i0 += kSub) {
+    __builtin_amdgcn_s_setprio(2);  // on the panel's critical path, beside the update GEMM
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int lo = lane & 15, hi = lane >> 4;
+    const int64_t c0 = static_cast<int64_t>(blockIdx.x) * BN;
+    const int wcols = static_cast<int>((count - c0) < BN ? (count - c0) : BN);
+    const int nrt = (b + 15) / 16;
+    acc_t acc[4][2];
+#pragma unroll
+    for (int u = 0; u < 4; ++u)
+#pragma unroll
+        for (int j = 0; j < 2; ++j)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int t = wave + 4 * u;
+                const int row = 16 * t + Mma<T>::row(lane, r), col = 16 * j + lo;
+                acc[u][j][r] = (t < nrt && row < b && col < wcols) ? C[row * ldc + c0 + col] : T(0);
+            }
+    for (int i = 0, i0 = 0; i0 < b; ++i, i0 += kSub) {
         const int sb = (b - i0) < kSub ? (b - i0) : kSub;
-        const int e0 = i0 + sb, below = b - e0;
-        // stage the diagonal inverse (transposed for the right side) and the coupling panel
-        for (int e = tid; e < sb * sb; e += 256) {
-            const int r = e / sb, k = e % sb;
-            Dv[r * LS + k] = (SIDE == 0) ? Dinv[(i0 + r) * static_cast<int64_t>(kInvLdDev) + i0 + k]
-                                         : Dinv[(i0 + k) * static_cast<int64_t>(kInvLdDev) + i0 + r];
+        for (int e = tid; e < kSub * kSub; e += 256) {
+            const int r = e / kSub, k = e % kSub;
+            Ds[r][k] = (r < sb && k < sb) ? Dinv[(i0 + r) * static_cast<int64_t>(kInvLdDev) + i0 + k]
+                                         : T(0);
         }
-        if (SIDE == 0) {
-            for (int e = tid; e < below * sb; e += 256) {
-                const int r = e / sb, k = e % sb;
-                P[r * LS + k] = lu[(e0 + r) * ld + i0 + k];
-            }
-        } else {
-            for (int e = tid; e < below * sb; e += 256) {
-                const int k = e / below, r = e % below;
-                P[r * LS + k] = lu[(i0 + k) * ld + e0 + r];
-            }
-        }
-        __syncthreads();
-        // X_i = Dinv_i S_i
-        T x[4];
 #pragma unroll
         for (int u = 0; u < 4; ++u) {
-            const int r = g + 8 * u;
-            T acc = T(0);
-            if (r < sb)
-                for (int k = 0; k < sb; ++k) acc += Dv[r * LS + k] * S[(i0 + k) * LS + c];
-            x[u] = acc;
+            const int t = wave + 4 * u;
+            if (t == 2 * i || t == 2 * i + 1)
+#pragma unroll
+                for (int j = 0; j < 2; ++j)
+#pragma unroll
+                    for (int r = 0; r < 4; ++r)
+                        Xs[16 * (t - 2 * i) + Mma<T>::row(lane, r)][16 * j + lo] = acc[u][j][r];
+        }
+        __syncthreads();
+        acc_t xn[2];
+        int mine = -1;
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const int t = wave + 4 * u;
+            if (t == 2 * i || t == 2 * i + 1) {
+                mine = u;
+#pragma unroll
+                for (int j = 0; j < 2; ++j) {
+                    acc_t x = acc_t{0, 0, 0, 0};
+#pragma unroll
+                    for (int kk = 0; kk < kSub; kk += 4)
+                        x = Mma<T>::step(Ds[16 * (t - 2 * i) + lo][kk + hi], Xs[kk + hi][16 * j + lo],
+                                         x);
+                    xn[j] = x;
+                }
+            }
+        }
+        __syncthreads();
+        if (mine >= 0) {
+            const int t = wave + 4 * mine;
+#pragma unroll
+            for (int j = 0; j < 2; ++j) {
+#pragma unroll
+                for (int u = 0; u < 4; ++u)
+                    if (u == mine) acc[u][j] = xn[j];
+#pragma unroll
+                for (int r = 0; r < 4; ++r)
+                    Xs[16 * (t - 2 * i) + Mma<T>::row(lane, r)][16 * j + lo] = xn[j][r];
+            }
         }
         __syncthreads();
 #pragma unroll
         for (int u = 0; u < 4; ++u) {
-            const int r = g + 8 * u;
-            if (r < sb) S[(i0 + r) * LS + c] = x[u];
-        }
-        __syncthreads();
-        // rows below: S_r -= P_r X_i
-        for (int r = g; r < below; r += 8) {
-            T acc = T(0);
-            for (int k = 0; k < sb; ++k) acc += P[r * LS + k] * S[(i0 + k) * LS + c];
-            S[(e0 + r) * LS + c] -= acc;
+            const int t = wave + 4 * u;
+            if (t >= 2 * i + 2 && t < nrt) {
+                const int row = 16 * t + lo;
+#pragma unroll
+                for (int kk = 0; kk < kSub; kk += 4) {
+                    const int k = kk + hi;
+                    const T a = (row < b && k < sb) ? -lu[row * ld + i0 + k] : T(0);
+#pragma unroll
+                    for (int j = 0; j < 2; ++j) acc[u][j] = Mma<T>::step(a, Xs[k][16 * j + lo], acc[u][j]);
+                }
+            }
         }
         __syncthreads();
     }
-    if (SIDE == 0) {
-        for (int e = tid; e < b * W; e += 256) {
-            const int k = e / W, cc = e % W;
-            if (cc < w) C[k * ldc + c0 + cc] = S[k * LS + cc];
+#pragma unroll
+    for (int u = 0; u < 4; ++u)
+#pragma unroll
+        for (int j = 0; j < 2; ++j)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int t = wave + 4 * u;
+                const int row = 16 * t + Mma<T>::row(lane, r), col = 16 * j + lo;
+                if (t < nrt && row < b && col < wcols) C[row * ldc + c0 + col] = acc[u][j][r];
+            }
+}
+
+// RIGHT: C (count x b) <- C U^{-1}, strips of 32 rows (column tiles dealt).
+template <typename T>
+__global__ __launch_bounds__(256, 2) void k_trsm_right(const T *lu, int64_t ld, int b, T *C,
+                                                       int64_t ldc, int64_t count, const T *Dinv,
+                                                       const int *abort) {
+    using acc_t = typename Mma<T>::acc;
+    constexpr int BM = 32;
+    __shared__ T Xs[BM][kSub + 1];
+    __shared__ T Ds[kSub][kSub + 1];
+    if (abort != nullptr && *abort != 0) return;
+    __builtin_amdgcn_s_setprio(2);  // on the panel's critical path, beside the update GEMM
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int lo = lane & 15, hi = lane >> 4;
+    const int64_t r0 = static_cast<int64_t>(blockIdx.x) * BM;
+    const int wrows = static_cast<int>((count - r0) < BM ? (count - r0) : BM);
+    const int nct = (b + 15) / 16;
+    acc_t acc[4][2];  // [column tile u][row tile]
+#pragma unroll
+    for (int u = 0; u < 4; ++u)
+#pragma unroll
+        for (int q = 0; q < 2; ++q)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int c = wave + 4 * u;
+                const int row = 16 * q + Mma<T>::row(lane, r), col = 16 * c + lo;
+                acc[u][q][r] =
+                    (c < nct && row < wrows && col < b) ? C[(r0 + row) * ldc + col] : T(0);
+            }
+    for (int j = 0, j0 = 0; j0 < b; ++j, j0 += kSub) {
+        const int sb = (b - j0) < kSub ? (b - j0) : kSub;
+        for (int e = tid; e < kSub * kSub; e += 256) {
+            const int k = e / kSub, m = e % kSub;
+            Ds[k][m] = (k < sb && m < sb) ? Dinv[(j0 + k) * static_cast<int64_t>(kInvLdDev) + j0 + m]
+                                         : T(0);
         }
-    } else {
-        for (int e = tid; e < b * W; e += 256) {
-            const int cc = e / b, k = e % b;
-            if (cc < w) C[(c0 + cc) * ldc + k] = S[k * LS + cc];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const int c = wave + 4 * u;
+            if (c == 2 * j || c == 2 * j + 1)
+#pragma unroll
+                for (int q = 0; q < 2; ++q)
+#pragma unroll
+                    for (int r = 0; r < 4; ++r)
+                        Xs[16 * q + Mma<T>::row(lane, r)][16 * (c - 2 * j) + lo] = acc[u][q][r];
         }
+        __syncthreads();
+        acc_t xn[2];
+        int mine = -1;
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const int c = wave + 4 * u;
+            if (c == 2 * j || c == 2 * j + 1) {
+                mine = u;
+#pragma unroll
+                for (int q = 0; q < 2; ++q) {
+                    acc_t x = acc_t{0, 0, 0, 0};
+#pragma unroll
+                    for (int kk = 0; kk < kSub; kk += 4)
+                        x = Mma<T>::step(Xs[16 * q + lo][kk + hi], Ds[kk + hi][16 * (c - 2 * j) + lo],
+                                         x);
+                    xn[q] = x;
+                }
+            }
+        }
+        __syncthreads();
+        if (mine >= 0) {
+            const int c = wave + 4 * mine;
+#pragma unroll
+            for (int q = 0; q < 2; ++q) {
+#pragma unroll
+                for (int u = 0; u < 4; ++u)
+                    if (u == mine) acc[u][q] = xn[q];
+#pragma unroll
+                for (int r = 0; r < 4; ++r)
+                    Xs[16 * q + Mma<T>::row(lane, r)][16 * (c - 2 * j) + lo] = xn[q][r];
+            }
+        }
+        __syncthreads();
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const int c = wave + 4 * u;
+            if (c >= 2 * j + 2 && c < nct) {
+                const int col = 16 * c + lo;
+#pragma unroll
+                for (int kk = 0; kk < kSub; kk += 4) {
+                    const int k = kk + hi;
+                    const T bv = (k < sb && col < b) ? -lu[(j0 + k) * ld + col] : T(0);
+#pragma unroll
+                    for (int q = 0; q < 2; ++q)
+                        acc[u][q] = Mma<T>::step(Xs[16 * q + lo][k], bv, acc[u][q]);
+                }
+            }
+        }
+        __syncthreads();
     }
+#pragma unroll
+    for (int u = 0; u < 4; ++u)
+#pragma unroll
+        for (int q = 0; q < 2; ++q)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int c = wave + 4 * u;
+                const int row = 16 * q + Mma<T>::row(lane, r), col = 16 * c + lo;
+                if (c < nct && row < wrows && col < b) C[(r0 + row) * ldc + col] = acc[u][q][r];
+            }
 }
 
 template <typename T>
@@ -296,7 +485,10 @@ template <typename T>
 hipError_t leaf_lu(T *a, int64_t lda, int b, T *Linv, T *Uinv, int64_t ldw, int64_t k0,
                    DevStatus *st, hipStream_t s) {
     if (b < 1 || b > kLeaf) return hipErrorInvalidValue;
-    hipLaunchKernelGGL(k_leaf_lu<T>, dim3(1), dim3(1024), 0, s, a, lda, b, Linv, Uinv, ldw, k0, st);
+    hipLaunchKernelGGL(k_leaf_lu<T>, dim3(1), dim3(256), 0, s, a, lda, b, k0, st);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_diag_inv<T>, dim3(1), dim3(512), 0, s, a, lda, b, Linv, Uinv, ldw, st);
     return hipGetLastError();
 }
 
@@ -307,10 +499,10 @@ hipError_t trsm(int side, const T *lu, int64_t ld, int b, T *C, int64_t ldc, int
     if (count <= 0) return hipSuccess;
     const unsigned grid = static_cast<unsigned>((count + 31) / 32);
     if (side == 0)
-        hipLaunchKernelGGL((k_trsm<T, 0>), dim3(grid), dim3(256), 0, s, lu, ld, b, C, ldc, count,
+        hipLaunchKernelGGL(k_trsm_left<T>, dim3(grid), dim3(256), 0, s, lu, ld, b, C, ldc, count,
                            Dinv, abort);
     else
-        hipLaunchKernelGGL((k_trsm<T, 1>), dim3(grid), dim3(256), 0, s, lu, ld, b, C, ldc, count,
+        hipLaunchKernelGGL(k_trsm_right<T>, dim3(grid), dim3(256), 0, s, lu, ld, b, C, ldc, count,
                            Dinv, abort);
     return hipGetLastError();
 }

@@ -28,21 +28,22 @@ hipError_t launch_normals_f32(float *out, int64_t count, uint64_t seed, uint64_t
 
 // --------------------------------------------------------------- gemm.hip
 // C = alpha * A * B + beta * C, row-major.  A is M x K (lda), B is K x N (ldb),
-// C is M x N (ldc).  `shape` picks the tile: 0 = 128 x 128 (general),
-// 1 = 64 x 256 (a workgroup owns whole rows of C: C may alias A when N <= 256),
-// 2 = 256 x 64 (a workgroup owns whole columns: C may alias B when M <= 256).
-// `abort` (device int, may be null): if nonzero at kernel start, do nothing.
-enum GemmShape { kGemmSquare = 0, kGemmRows = 1, kGemmCols = 2 };
+// C is M x N (ldc); C must not overlap A or B.  `shape` picks the tiling:
+// kGemmProduct for large K (M = A H), kGemmUpdate for the Schur-complement
+// update (K = panel width).  `abort` (device int, may be null): if nonzero at
+// kernel start, do nothing.  `absmax` (device double, may be null): maxed
+// atomically with max |C| of the written results.
+enum GemmShape { kGemmProduct = 0, kGemmUpdate = 1 };
 hipError_t gemm_f64(int shape, int64_t M, int64_t N, int64_t K, double alpha, const double *A,
                     int64_t lda, const double *B, int64_t ldb, double beta, double *C, int64_t ldc,
-                    const int *abort, hipStream_t s);
+                    const int *abort, hipStream_t s, double *absmax = nullptr);
 hipError_t gemm_f32(int shape, int64_t M, int64_t N, int64_t K, float alpha, const float *A,
                     int64_t lda, const float *B, int64_t ldb, float beta, float *C, int64_t ldc,
-                    const int *abort, hipStream_t s);
+                    const int *abort, hipStream_t s, double *absmax = nullptr);
 // FP32 product whose A operand is stored in FP64 (rounded to FP32 on load).
 hipError_t gemm_f32_a64(int shape, int64_t M, int64_t N, int64_t K, float alpha, const double *A,
                         int64_t lda, const float *B, int64_t ldb, float beta, float *C,
-                        int64_t ldc, const int *abort, hipStream_t s);
+                        int64_t ldc, const int *abort, hipStream_t s, double *absmax = nullptr);
 
 // ----------------------------------------------------------------- lu.hip
 // Factor the b x b diagonal block at `a` (b <= kLeaf) in place (GENP) and
@@ -83,6 +84,15 @@ hipError_t abs_max(const T *m, int64_t ld, int64_t n, double *out3, hipStream_t 
 template <typename T>
 hipError_t trsv_step(int mode, const T *LU, int64_t ld, int64_t n, int64_t blk, T *Y, T *X,
                      int64_t ldyx, int nr, const int *abort, hipStream_t s);
+// The whole solve T X = B in one launch (same modes), blocks of 64 rows taken
+// in dependency order by a ticket counter.  X and B are n x ldx (nr <= 16
+// columns used; X may alias B).  sync: device ints, [0] ticket counter,
+// [1] error word (set to 1 if a wait timed out; the caller clears it),
+// [2 ..] one flag per 64-row block; `epoch` must differ from every value the
+// flags hold (the caller increments it per launch).
+template <typename T>
+hipError_t trsv_full(int mode, const T *LU, int64_t ld, int64_t n, const T *B, T *X, int64_t ldx,
+                     int nr, int *sync, int epoch, hipStream_t s);
 // y = beta * y + alpha * M x  (rows of M; FP64 accumulation).  M: rows x cols (ldm),
 // x: cols x nrhs (ldx), y: rows x nrhs (ldy).
 template <typename TM, typename TX, typename TY>
@@ -121,6 +131,7 @@ hipError_t fft_spectrum(const double *h, int m, const double *tw, double *hhat, 
 template <typename TI, typename TO>
 hipError_t fft_rows(const TI *in, int64_t vstride_in, int64_t estride_in, int64_t count,
                     int64_t n, int m, const double *tw, const double *hhat, int conj, double beta,
-                    TO *out, int64_t vstride_out, int64_t estride_out, hipStream_t s);
+                    TO *out, int64_t vstride_out, int64_t estride_out, hipStream_t s,
+                    double *absmax = nullptr);
 
 }  // namespace rmge

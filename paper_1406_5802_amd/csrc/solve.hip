@@ -5,13 +5,12 @@
 // L^{-T} U^{-T} H^T w.  Refinement (Section 8.1) needs r = b - A x in FP64.
 // Every kernel here streams a matrix once and is bound by HBM bandwidth.
 //
-// Triangular solves are blocked by 64 rows.  One launch handles one diagonal
-// block: every workgroup solves the 64 x 64 diagonal block for the current
-// right-hand sides in registers (one wave, lane = row, wavefront shuffles
-// broadcast each solved value), workgroup 0 stores it, and each workgroup then
-// subtracts the coupling of one 64-row tile of the not-yet-solved rows.  The
-// coupling tile is staged through LDS so that its global reads are row
-// segments (coalesced) for both plain and transposed factors.
+// Triangular solves are blocked by 64 rows: each 64 x 64 diagonal block is
+// solved in registers by one wave (lane = row, wavefront shuffles broadcast
+// each solved value) and the coupling tiles are staged through LDS so that
+// their global reads are row segments (coalesced) for plain and transposed
+// factors alike.  k_trsv_persistent does a whole solve in one launch;
+// k_trsv_step does one diagonal block per launch (kept for reference use).
 #include "rmge_impl.h"
 
 namespace rmge {
@@ -117,6 +116,163 @@ __global__ __launch_bounds__(256) void k_trsv_step(const T *LU, int64_t ld, int6
         }
     }
 }
+
+// Whole triangular solve in one launch.  Workgroups take block rows in the
+// order they start (a ticket from an atomic counter), so every block a
+// workgroup waits on belongs to a workgroup that is already running; block I
+// accumulates the coupling T_IJ y_J of every finished block J (waiting on
+// J's flag), then solves its diagonal block and publishes y_I with a release
+// fence and its flag.  A wait gives up after kSpinLimit polls and records an
+// error instead of hanging; the caller checks it.
+constexpr int kSpinLimit = 1 << 22;
+
+template <typename T, int MODE, int NR>
+__global__ __launch_bounds__(256) void k_trsv_persistent(const T *LU, int64_t ld, int64_t n,
+                                                         const T *B, T *X, int64_t ldx, int nr,
+                                                         int *counter, int *flags, int epoch,
+                                                         int *err) {
+    __shared__ T Ds[SB][SB + 1];  // diagonal block
+    __shared__ T Ts[SB][SB + 1];  // coupling tile T_IJ
+    __shared__ T ys[SB][NR];
+    __shared__ int s_ticket, s_fail;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const bool forward = (MODE == 0 || MODE == 2);
+    const bool transposed = (MODE == 2 || MODE == 3);
+    if (tid == 0) {
+        s_ticket = atomicAdd(counter, 1);
+        s_fail = 0;
+    }
+    __syncthreads();
+    const int nblk = static_cast<int>((n + SB - 1) / SB);
+    const int I = forward ? s_ticket : nblk - 1 - s_ticket;
+    const int64_t I0 = static_cast<int64_t>(I) * SB;
+    const int bI = static_cast<int>((n - I0) < SB ? (n - I0) : SB);
+    const int r = tid >> 2, q = tid & 3;  // row r of the block, column quarter q
+    // Everything that does not depend on other blocks is loaded before waiting.
+    for (int e = tid; e < SB * SB; e += 256) {
+        const int i = e / SB, j = e % SB;
+        Ds[i][j] = (i < bI && j < bI) ? LU[(I0 + i) * ld + I0 + j] : T(0);
+    }
+    T bval[NR];
+#pragma unroll
+    for (int c = 0; c < NR; ++c)
+        bval[c] = (q == 0 && r < bI && c < nr) ? B[(I0 + r) * ldx + c] : T(0);
+    double acc[NR];
+#pragma unroll
+    for (int c = 0; c < NR; ++c) acc[c] = 0.0;
+    const int jfirst = forward ? 0 : nblk - 1, jstep = forward ? 1 : -1;
+    for (int J = jfirst; J != I; J += jstep) {
+        const int64_t J0 = static_cast<int64_t>(J) * SB;
+        const int bJ = static_cast<int>((n - J0) < SB ? (n - J0) : SB);
+        // the coupling tile T_IJ (rows of this block, columns of block J)
+        if (!transposed) {
+            for (int e = tid; e < SB * SB; e += 256) {
+                const int rr = e / SB, cc = e % SB;
+                Ts[rr][cc] = (rr < bI && cc < bJ) ? LU[(I0 + rr) * ld + J0 + cc] : T(0);
+            }
+        } else {
+            for (int e = tid; e < SB * SB; e += 256) {
+                const int cc = e / SB, rr = e % SB;  // T[r][c] = factor[J0 + c][I0 + r]
+                Ts[rr][cc] = (rr < bI && cc < bJ) ? LU[(J0 + cc) * ld + I0 + rr] : T(0);
+            }
+        }
+        if (tid == 0) {
+            int spins = 0;
+            while (__hip_atomic_load(flags + J, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != epoch) {
+                if (++spins > kSpinLimit ||
+                    __hip_atomic_load(err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0) {
+                    s_fail = 1;
+                    break;
+                }
+                __builtin_amdgcn_s_sleep(1);
+            }
+        }
+        __syncthreads();
+        if (s_fail) break;
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+        for (int e = tid; e < SB * NR; e += 256) {
+            const int rr = e / NR, c = e % NR;
+            ys[rr][c] = (rr < bJ && c < nr) ? X[(J0 + rr) * ldx + c] : T(0);
+        }
+        __syncthreads();
+#pragma unroll 4
+        for (int k = 16 * q; k < 16 * q + 16; ++k) {
+            const double t = static_cast<double>(Ts[r][k]);
+#pragma unroll
+            for (int c = 0; c < NR; ++c) acc[c] += t * static_cast<double>(ys[k][c]);
+        }
+        __syncthreads();
+    }
+    if (s_fail) {
+        if (tid == 0) atomicExch(err, 1);  // blocks waiting on this one see it and stop
+        return;
+    }
+    // reduce the four column quarters of each row, form the right-hand side
+#pragma unroll
+    for (int c = 0; c < NR; ++c) {
+        acc[c] += __shfl_xor(acc[c], 1);
+        acc[c] += __shfl_xor(acc[c], 2);
+    }
+    if (q == 0) {
+#pragma unroll
+        for (int c = 0; c < NR; ++c)
+            ys[r][c] = static_cast<T>(static_cast<double>(bval[c]) - acc[c]);
+    }
+    __syncthreads();
+    if (wave == 0) {
+        T v[NR];
+#pragma unroll
+        for (int c = 0; c < NR; ++c) v[c] = ys[lane][c];
+        if (MODE == 0) {
+            for (int j = 0; j < bI; ++j) {
+                const T l = Ds[lane][j];
+#pragma unroll
+                for (int c = 0; c < NR; ++c) {
+                    const T t = __shfl(v[c], j);
+                    if (lane > j) v[c] -= l * t;
+                }
+            }
+        } else if (MODE == 1) {
+            for (int j = bI - 1; j >= 0; --j) {
+                const T d = Ds[j][j], u = Ds[lane][j];
+#pragma unroll
+                for (int c = 0; c < NR; ++c) {
+                    if (lane == j) v[c] = v[c] / d;
+                    const T t = __shfl(v[c], j);
+                    if (lane < j) v[c] -= u * t;
+                }
+            }
+        } else if (MODE == 2) {
+            for (int j = 0; j < bI; ++j) {
+                const T d = Ds[j][j], u = Ds[j][lane];
+#pragma unroll
+                for (int c = 0; c < NR; ++c) {
+                    if (lane == j) v[c] = v[c] / d;
+                    const T t = __shfl(v[c], j);
+                    if (lane > j) v[c] -= u * t;
+                }
+            }
+        } else {
+            for (int j = bI - 1; j >= 0; --j) {
+                const T l = Ds[j][lane];
+#pragma unroll
+                for (int c = 0; c < NR; ++c) {
+                    const T t = __shfl(v[c], j);
+                    if (lane < j) v[c] -= l * t;
+                }
+            }
+        }
+        if (lane < bI) {
+#pragma unroll
+            for (int c = 0; c < NR; ++c)
+                if (c < nr) X[(I0 + lane) * ldx + c] = v[c];
+        }
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+        if (lane == 0) __hip_atomic_store(flags + I, epoch, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+}
+
+__global__ void k_trsv_reset(int *counter) { *counter = 0; }
 
 template <typename T, int MODE>
 hipError_t trsv_launch(const T *LU, int64_t ld, int64_t n, int64_t blk, T *Y, T *X, int64_t ldyx,
@@ -303,6 +459,39 @@ int grid_for(int64_t total, int threads) {
 
 }  // namespace
 
+template <typename T, int MODE>
+hipError_t trsv_full_launch(const T *LU, int64_t ld, int64_t n, const T *B, T *X, int64_t ldx,
+                            int nr, int *sync, int epoch, hipStream_t s) {
+    const int nblk = static_cast<int>((n + SB - 1) / SB);
+    hipLaunchKernelGGL(k_trsv_reset, dim3(1), dim3(1), 0, s, sync);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    int *flags = sync + 2, *err = sync + 1;
+    if (nr <= 1)
+        hipLaunchKernelGGL((k_trsv_persistent<T, MODE, 1>), dim3(nblk), dim3(256), 0, s, LU, ld, n,
+                           B, X, ldx, nr, sync, flags, epoch, err);
+    else if (nr <= 4)
+        hipLaunchKernelGGL((k_trsv_persistent<T, MODE, 4>), dim3(nblk), dim3(256), 0, s, LU, ld, n,
+                           B, X, ldx, nr, sync, flags, epoch, err);
+    else
+        hipLaunchKernelGGL((k_trsv_persistent<T, MODE, 16>), dim3(nblk), dim3(256), 0, s, LU, ld,
+                           n, B, X, ldx, nr, sync, flags, epoch, err);
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t trsv_full(int mode, const T *LU, int64_t ld, int64_t n, const T *B, T *X, int64_t ldx,
+                     int nr, int *sync, int epoch, hipStream_t s) {
+    if (nr < 1 || nr > 16 || n < 1) return hipErrorInvalidValue;
+    switch (mode) {
+    case 0: return trsv_full_launch<T, 0>(LU, ld, n, B, X, ldx, nr, sync, epoch, s);
+    case 1: return trsv_full_launch<T, 1>(LU, ld, n, B, X, ldx, nr, sync, epoch, s);
+    case 2: return trsv_full_launch<T, 2>(LU, ld, n, B, X, ldx, nr, sync, epoch, s);
+    case 3: return trsv_full_launch<T, 3>(LU, ld, n, B, X, ldx, nr, sync, epoch, s);
+    default: return hipErrorInvalidValue;
+    }
+}
+
 template <typename T>
 hipError_t trsv_step(int mode, const T *LU, int64_t ld, int64_t n, int64_t blk, T *Y, T *X,
                      int64_t ldyx, int nr, const int *abort, hipStream_t s) {
@@ -390,6 +579,10 @@ hipError_t fill_f64(double *p, int64_t count, double value, hipStream_t s) {
     return hipGetLastError();
 }
 
+template hipError_t trsv_full<double>(int, const double *, int64_t, int64_t, const double *,
+                                      double *, int64_t, int, int *, int, hipStream_t);
+template hipError_t trsv_full<float>(int, const float *, int64_t, int64_t, const float *, float *,
+                                     int64_t, int, int *, int, hipStream_t);
 template hipError_t trsv_step<double>(int, const double *, int64_t, int64_t, int64_t, double *,
                                       double *, int64_t, int, const int *, hipStream_t);
 template hipError_t trsv_step<float>(int, const float *, int64_t, int64_t, int64_t, float *,
