@@ -34,6 +34,14 @@ METRIC = "factor+solve TFLOP/s n=16384: FP64 vs FP32 MFMA+IR at equal bwd error"
 PEAK = {"f64": 78.6, "f32": 157.3}  # MI355X dense MFMA TFLOP/s
 ETA_TARGET = 1e-14
 
+# HBM bytes of one FP64 product launch at n = 16384, from rocprofv3 FETCH_SIZE and
+# WRITE_SIZE passes scaled by a plain-copy calibration (FETCH x 2.000, WRITE x 1.000);
+# profiles/k_gemm_product_f64_n16384_hbm_traffic.txt.  Valid only for the kernel source
+# those counters were taken on.
+TRAFFIC = {"n": 16384, "source": "paper_1406_5802_amd/csrc/gemm.hip",
+           "sha256": "16848a0f23a5bd5917e7f73417eb6c7cc5bd11d4542b705535f1bd8b22f00957",
+           "fetch_kib": (59230758.0 + 59453597.8125) / 2 * 2.000, "write_kib": 2099200.0 * 1.000}
+
 
 def log(msg):
     sys.stderr.write("[bench %s] %s\n" % (time.strftime("%H:%M:%S"), msg))
@@ -86,6 +94,18 @@ def run_path(rmge, torch, A, b, prec, seed, steps, warmup, block, max_refine):
     }
 
 
+def product_traffic(n, head):
+    """Counter-measured HBM bytes per product launch, or None if they do not apply."""
+    import hashlib
+
+    if n != TRAFFIC["n"] or head != "f64":
+        return None
+    with open(os.path.join(ROOT, TRAFFIC["source"]), "rb") as fh:
+        if hashlib.sha256(fh.read()).hexdigest() != TRAFFIC["sha256"]:
+            return None
+    return (TRAFFIC["fetch_kib"] + TRAFFIC["write_kib"]) * 1024.0
+
+
 def cpu_baseline(n_cpu, seed):
     import numpy as np
 
@@ -127,6 +147,10 @@ def main():
     ap.add_argument("--paths", default="f64,f32")
     ap.add_argument("--cpu-n", type=int, default=4096)
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--matrix", default="conditioned", choices=["conditioned", "gaussian"],
+                    help="conditioned: Q1 diag(sigma) Q2^T (the workload); gaussian: i.i.d. "
+                         "N(0, 1/n) entries, no QR (for hardware-counter passes, where only "
+                         "the shape matters)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py measures one GPU: the method is benchmarked on a single MI355X; "
@@ -141,8 +165,13 @@ def main():
     rmge.lib()
     n = args.n
     kappa = workloads.precision_kappa(args.seed)
-    log("generating A: n=%d kappa=%.3g (seed %d) on the GPU" % (n, kappa, args.seed))
-    A = workloads.conditioned_torch(n, kappa, args.seed)
+    if args.matrix == "gaussian":
+        log("generating A: n=%d i.i.d. Gaussian (seed %d) on the GPU" % (n, args.seed))
+        A = workloads.gaussian_torch(n, args.seed)
+        kappa = None
+    else:
+        log("generating A: n=%d kappa=%.3g (seed %d) on the GPU" % (n, kappa, args.seed))
+        A = workloads.conditioned_torch(n, kappa, args.seed)
     b = workloads.rhs_torch(n, 1, args.seed)
     torch.cuda.synchronize()
     log("inputs ready")
@@ -174,17 +203,20 @@ def main():
         "vs_baseline": None,
         "dtype": "f64" if head == "f64" else "f32 factors + f64 refinement",
         "data": "synthetic",
-        "config": {"workload": "precision: n=%d Gaussian multiplier, kappa=%.3g, 1 RHS, "
-                               "eta<=1e-14" % (n, kappa),
+        "config": {"workload": ("precision: n=%d Gaussian multiplier, kappa=%.3g, 1 RHS, "
+                                "eta<=1e-14" % (n, kappa)) if kappa else
+                               ("n=%d i.i.d. Gaussian A, Gaussian multiplier, 1 RHS, "
+                                "eta<=1e-14" % n),
                    "n": n, "kappa": kappa, "seed": args.seed, "block": args.block, "nrhs": 1,
                    "headline_path": head},
         "roofline": {"bound": "mfma", "achieved": round(achieved, 3), "peak": PEAK[head],
                      "unit": "TFLOP/s", "frac": round(achieved / PEAK[head], 4),
-                     "traffic": None, "kernel": "k_gemm (M = A G)",
+                     "traffic": product_traffic(n, head), "traffic_unit": "bytes/launch",
+                     "kernel": "k_gemm (M = A G)",
                      "ms_per_launch": round(r["ms_product"], 4)},
         "executed_tflops": round((flops + prod_flops) / (r["ms_per_step"] * 1e-3) / 1e12, 3),
-        "paths": {k: {kk: (round(vv, 6) if isinstance(vv, float) else vv) for kk, vv in v.items()}
-                  for k, v in results.items()},
+        "paths": {k: {kk: (float("%.6g" % vv) if isinstance(vv, float) else vv)
+                      for kk, vv in v.items()} for k, v in results.items()},
     }
     if "f64" in results and "f32" in results:
         out["speedup_f32_over_f64"] = round(results["f64"]["ms_per_step"]

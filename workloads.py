@@ -21,6 +21,8 @@ U Sigma V^T with U, V the Q factors of QR factorizations of random matrices):
   Toeplitz matrices scaled to unit spectral norm.
 * ``precision_kappa(seed)``: kappa = 10^(1 + 7 u), u uniform on [0, 1).
 * ``rhs(n, nrhs, seed)``: i.i.d. N(0, 1).
+* ``gaussian_torch(n, seed)``: an i.i.d. N(0, 1/n) matrix made on the GPU with
+  no factorization; used where only the shape matters (hardware counters).
 
 The torch variants build the same recipes on a GPU for sizes where a CPU QR
 would take minutes; they are not bitwise equal to the numpy ones.
@@ -118,6 +120,16 @@ def conditioned_torch(n: int, kappa: float, seed: int, device="cuda"):
     A = torch.matmul(Q1 * sig[None, :], Q2.T.contiguous())
     del Q1, Q2
     return A.contiguous()
+
+
+def gaussian_torch(n: int, seed: int, device="cuda"):
+    """i.i.d. N(0, 1) n x n matrix, scaled by 1/sqrt(n) (kappa grows like n)."""
+    import torch
+
+    g = torch.Generator(device=device)
+    g.manual_seed(int(seed) * 1000003 + 41)
+    A = torch.randn((n, n), generator=g, dtype=torch.float64, device=device)
+    return A.mul_(1.0 / float(n) ** 0.5)
 
 
 def rhs_torch(n: int, nrhs: int, seed: int, device="cuda"):
