@@ -60,9 +60,11 @@ def lib() -> ctypes.CDLL:
         L.orc_multiplier_dense.argtypes = [i32, i64, vp, vp]
         L.orc_matmul.argtypes = [i64, i64, i64, vp, vp, vp]
         L.orc_genp.argtypes = [i64, vp, ctypes.POINTER(i64)]
+        L.orc_genp_local.argtypes = [i64, i64, vp, vp, ctypes.POINTER(i64)]
         L.orc_factor.argtypes = [i64, vp, i32, u64, vp, vp, vp]
-        L.orc_solve.argtypes = [i64, i64, vp, vp, vp, vp, vp, i32, vp]
-        L.orc_solve_adjoint.argtypes = [i64, i64, vp, vp, vp, vp]
+        L.orc_factor_ex.argtypes = [i64, vp, i32, u64, i64, vp, vp, vp, vp]
+        L.orc_solve.argtypes = [i64, i64, vp, vp, vp, vp, vp, vp, i32, vp]
+        L.orc_solve_adjoint.argtypes = [i64, i64, vp, vp, vp, vp, vp]
         L.orc_errors.argtypes = [i64, i64, vp, vp, vp, dp, dp]
         L.orc_grad_A.argtypes = [i64, i64, vp, vp, vp]
         L.orc_num_threads.restype = i32
@@ -168,6 +170,20 @@ def genp(M) -> tuple[np.ndarray, int, int]:
     return LU, int(rc), int(info.value)
 
 
+def genp_local(M, block: int) -> tuple[np.ndarray, np.ndarray, int, int]:
+    """Block elimination with partial pivoting confined to the diagonal blocks
+    where the recursion of eq. eqgenp stops (Section 3, after eq. eqgenpin:
+    small blocks go to a black-box method); panels of ``block`` columns, a
+    panel wider than 128 cut into 128 + rest.  Returns (LU, perm, status, info)
+    with (P M)[t] = M[perm[t]] = (L U)[t]."""
+    LU = _f64(M).copy()
+    n = LU.shape[0]
+    perm = np.zeros(n, dtype=np.int64)
+    info = ctypes.c_int64(-1)
+    rc = lib().orc_genp_local(n, int(block), _p(LU), _p(perm), ctypes.byref(info))
+    return LU, perm, int(rc), int(info.value)
+
+
 @dataclass
 class Factors:
     n: int
@@ -181,6 +197,8 @@ class Factors:
     min_abs_pivot: float
     growth: float
     seconds: float = 0.0
+    perm: np.ndarray | None = None  # row order of P M = L U (None: no pivoting)
+    block: int = 0
 
 
 @dataclass
@@ -191,18 +209,26 @@ class Solution:
     seconds: float = 0.0
 
 
-def factor(A, kind: int, seed: int) -> Factors:
-    """M = A H (Fact faprepr), then GENP on M."""
+def factor(A, kind: int, seed: int, local_pivot_block: int = 0) -> Factors:
+    """M = A H (Fact faprepr), then GENP on M; with ``local_pivot_block`` > 0,
+    the locally pivoted block elimination of :func:`genp_local` instead."""
     A = _f64(A)
     n = A.shape[0]
     H = np.zeros((n, n))
     LU = np.zeros((n, n))
+    perm = np.zeros(n, dtype=np.int64) if local_pivot_block > 0 else None
     st = _Stats()
     t0 = time.perf_counter()
-    rc = lib().orc_factor(n, _p(A), kind, seed, _p(H), _p(LU), ctypes.byref(st))
+    rc = lib().orc_factor_ex(n, _p(A), kind, seed, int(local_pivot_block), _p(H), _p(LU),
+                             _p(perm) if perm is not None else None, ctypes.byref(st))
     dt = time.perf_counter() - t0
     return Factors(n, kind, seed, A, H, LU, int(rc), int(st.info),
-                   float(st.min_abs_pivot), float(st.growth), dt)
+                   float(st.min_abs_pivot), float(st.growth), dt, perm,
+                   int(local_pivot_block))
+
+
+def _perm(f: Factors):
+    return _p(f.perm) if f.perm is not None else None
 
 
 def solve(f: Factors, B, refine: int = 1) -> Solution:
@@ -215,7 +241,7 @@ def solve(f: Factors, B, refine: int = 1) -> Solution:
     X = np.zeros_like(B)
     st = _Stats()
     t0 = time.perf_counter()
-    lib().orc_solve(f.n, nrhs, _p(f.A), _p(f.H), _p(f.LU), _p(B), _p(X), refine,
+    lib().orc_solve(f.n, nrhs, _p(f.A), _p(f.H), _p(f.LU), _perm(f), _p(B), _p(X), refine,
                     ctypes.byref(st))
     dt = time.perf_counter() - t0
     X = X[:, 0] if vec else X
@@ -224,13 +250,13 @@ def solve(f: Factors, B, refine: int = 1) -> Solution:
 
 
 def solve_adjoint(f: Factors, W) -> np.ndarray:
-    """Y = A^{-T} W = L^{-T} U^{-T} H^T W."""
+    """Y = A^{-T} W = P^T L^{-T} U^{-T} H^T W."""
     W = _f64(W)
     vec = W.ndim == 1
     if vec:
         W = W[:, None]
     Y = np.zeros_like(W)
-    lib().orc_solve_adjoint(f.n, W.shape[1], _p(f.H), _p(f.LU), _p(W), _p(Y))
+    lib().orc_solve_adjoint(f.n, W.shape[1], _p(f.H), _p(f.LU), _perm(f), _p(W), _p(Y))
     return Y[:, 0] if vec else Y
 
 

@@ -16,7 +16,10 @@
  *   2. the preprocessed matrix M = A H (Fact faprepr, post-multiplication);
  *   3. Gaussian elimination with no pivoting on M (Section 3: the complete
  *      recursive factorization with k = 1, eq. eqgenp), stopping at the first
- *      vanishing pivot (Corollary corec);
+ *      vanishing pivot (Corollary corec); or block Gaussian elimination whose
+ *      recursion stops at small diagonal blocks that are handed to a black-box
+ *      method (Section 3, after eq. eqgenpin), here Gaussian elimination with
+ *      partial pivoting confined to each such block;
  *   4. y = U^{-1} L^{-1} b and x = H y (Fact faprepr);
  *   5. iterative refinement steps r = b - A x, x += H U^{-1} L^{-1} r
  *      (Section 8.1 protocol: one refinement step);
@@ -252,6 +255,58 @@ int orc_genp(int64_t n, double *M, int64_t *info) {
     return ORC_OK;
 }
 
+/* End (exclusive) of the diagonal block that holds row/column k when the
+ * recursion of eq. eqgenp stops at blocks of at most 128: the matrix is cut
+ * into panels of `block` columns (the last one may be narrower); a panel
+ * wider than 128 is cut once more into its first 128 columns and the rest. */
+static int64_t orc_window_end(int64_t n, int64_t block, int64_t k) {
+    int64_t s = (k / block) * block;
+    int64_t b = (n - s) < block ? (n - s) : block;
+    if (b <= 128) return s + b;
+    return k < s + 128 ? s + 128 : s + b;
+}
+
+/* Block Gaussian elimination in which each small diagonal block (see
+ * orc_window_end) is eliminated with partial pivoting inside that block only:
+ * for column k the pivot is the entry of largest magnitude among rows
+ * k .. window_end(k) - 1 of the current matrix (ties: the smallest original row
+ * index), whole rows are exchanged, and every row below k is eliminated.  Rows
+ * never move between blocks, so the leading block of each block boundary is
+ * the same as without pivoting and the Schur complements at the boundaries
+ * are those of eq. eqgenp.  Result: P M = L U with perm[t] = the original
+ * index of the row stored at t.  *info: first block whose candidates are all
+ * exactly zero (the leading block at that boundary is singular), or a
+ * non-finite pivot; -1 otherwise. */
+int orc_genp_local(int64_t n, int64_t block, double *M, int64_t *perm, int64_t *info) {
+    *info = -1;
+    for (int64_t i = 0; i < n; ++i) perm[i] = i;
+    double *tmp = (double *)malloc(sizeof(double) * (size_t)(n > 0 ? n : 1));
+    for (int64_t k = 0; k < n; ++k) {
+        int64_t we = orc_window_end(n, block, k), r = k;
+        for (int64_t i = k + 1; i < we; ++i) {
+            double a = fabs(M[i * n + k]), best = fabs(M[r * n + k]);
+            if (a > best || (a == best && perm[i] < perm[r])) r = i;
+        }
+        if (r != k) {
+            memcpy(tmp, M + r * n, sizeof(double) * (size_t)n);
+            memcpy(M + r * n, M + k * n, sizeof(double) * (size_t)n);
+            memcpy(M + k * n, tmp, sizeof(double) * (size_t)n);
+            int64_t t = perm[r]; perm[r] = perm[k]; perm[k] = t;
+        }
+        double p = M[k * n + k];
+        if (p == 0.0) { *info = k; free(tmp); return ORC_ZERO_PIVOT; }
+        if (!isfinite(p)) { *info = k; free(tmp); return ORC_NONFINITE; }
+#pragma omp parallel for schedule(static)
+        for (int64_t i = k + 1; i < n; ++i) {
+            double l = M[i * n + k] / p;
+            M[i * n + k] = l;
+            for (int64_t j = k + 1; j < n; ++j) M[i * n + j] -= l * M[k * n + j];
+        }
+    }
+    free(tmp);
+    return ORC_OK;
+}
+
 /* Solve L z = b in place (L unit lower, stored strictly below the diagonal). */
 static void orc_lower_unit_solve(int64_t n, int64_t nrhs, const double *LU, double *z) {
     for (int64_t i = 0; i < n; ++i)
@@ -343,9 +398,12 @@ typedef struct {
     double growth;        /* max |U| / max |M| */
 } orc_stats;
 
-/* Factor: M = A H, then GENP on M.  H (n x n) and LU (n x n) are outputs. */
-int orc_factor(int64_t n, const double *A, int kind, uint64_t seed, double *H, double *LU,
-               orc_stats *st) {
+/* Factor: M = A H, then GENP on M (block <= 0), or the locally pivoted block
+ * elimination of orc_genp_local with panels of `block` columns (block > 0;
+ * perm receives the row order).  H (n x n), LU (n x n) are outputs; perm
+ * (n) may be NULL when block <= 0. */
+int orc_factor_ex(int64_t n, const double *A, int kind, uint64_t seed, int64_t block, double *H,
+                  double *LU, int64_t *perm, orc_stats *st) {
     memset(st, 0, sizeof(*st));
     if (kind == ORC_NONE) {
         orc_multiplier_dense(kind, n, NULL, H);
@@ -358,7 +416,8 @@ int orc_factor(int64_t n, const double *A, int kind, uint64_t seed, double *H, d
     orc_matmul(n, n, n, A, H, LU); /* M = A H  (Fact faprepr) */
     double mmax = 0.0;
     for (int64_t e = 0; e < n * n; ++e) mmax = fmax(mmax, fabs(LU[e]));
-    int rc = orc_genp(n, LU, &st->info);
+    int rc = block > 0 ? orc_genp_local(n, block, LU, perm, &st->info)
+                       : orc_genp(n, LU, &st->info);
     st->status = rc;
     if (rc == ORC_OK) {
         double umax = 0.0, pmin = INFINITY;
@@ -372,10 +431,21 @@ int orc_factor(int64_t n, const double *A, int kind, uint64_t seed, double *H, d
     return rc;
 }
 
-/* z = H U^{-1} L^{-1} v : one application of the preprocessed inverse. */
+int orc_factor(int64_t n, const double *A, int kind, uint64_t seed, double *H, double *LU,
+               orc_stats *st) {
+    return orc_factor_ex(n, A, kind, seed, 0, H, LU, NULL, st);
+}
+
+/* z = H U^{-1} L^{-1} P v : one application of the preprocessed inverse
+ * ((P v)[t] = v[perm[t]]; perm NULL means P = I). */
 static void orc_apply_inverse(int64_t n, int64_t nrhs, const double *H, const double *LU,
-                              const double *v, double *z, double *tmp) {
-    memcpy(tmp, v, sizeof(double) * (size_t)(n * nrhs));
+                              const int64_t *perm, const double *v, double *z, double *tmp) {
+    if (perm) {
+        for (int64_t t = 0; t < n; ++t)
+            memcpy(tmp + t * nrhs, v + perm[t] * nrhs, sizeof(double) * (size_t)nrhs);
+    } else {
+        memcpy(tmp, v, sizeof(double) * (size_t)(n * nrhs));
+    }
     orc_lower_unit_solve(n, nrhs, LU, tmp);
     orc_upper_solve(n, nrhs, LU, tmp);
     orc_apply(n, nrhs, H, tmp, z);
@@ -384,11 +454,11 @@ static void orc_apply_inverse(int64_t n, int64_t nrhs, const double *H, const do
 /* Solve A X = B through A H Y = B, X = H Y, then `refine` refinement steps.
  * Records eta and relres after each stage in st. */
 int orc_solve(int64_t n, int64_t nrhs, const double *A, const double *H, const double *LU,
-              const double *B, double *X, int refine, orc_stats *st) {
+              const int64_t *perm, const double *B, double *X, int refine, orc_stats *st) {
     if (refine > 16) refine = 16;
     size_t sz = sizeof(double) * (size_t)(n * nrhs);
     double *tmp = (double *)malloc(sz), *r = (double *)malloc(sz), *d = (double *)malloc(sz);
-    orc_apply_inverse(n, nrhs, H, LU, B, X, tmp);
+    orc_apply_inverse(n, nrhs, H, LU, perm, B, X, tmp);
     orc_errors(n, nrhs, A, B, X, &st->eta[0], &st->relres[0]);
     for (int s = 1; s <= refine; ++s) {
         /* r = B - A X in FP64 */
@@ -399,7 +469,7 @@ int orc_solve(int64_t n, int64_t nrhs, const double *A, const double *H, const d
                 for (int64_t j = 0; j < n; ++j) acc -= A[i * n + j] * X[j * nrhs + c];
                 r[i * nrhs + c] = acc;
             }
-        orc_apply_inverse(n, nrhs, H, LU, r, d, tmp);
+        orc_apply_inverse(n, nrhs, H, LU, perm, r, d, tmp);
         for (int64_t e = 0; e < n * nrhs; ++e) X[e] += d[e];
         orc_errors(n, nrhs, A, B, X, &st->eta[s], &st->relres[s]);
     }
@@ -408,13 +478,22 @@ int orc_solve(int64_t n, int64_t nrhs, const double *A, const double *H, const d
     return 0;
 }
 
-/* Adjoint solve Y = A^{-T} W.  From A^{-1} = H (A H)^{-1} (Fact faprepr):
- * A^{-T} = (L U)^{-T} H^T = L^{-T} U^{-T} H^T. */
+/* Adjoint solve Y = A^{-T} W.  From A^{-1} = H (A H)^{-1} (Fact faprepr) and
+ * P A H = L U: A^{-T} = P^T L^{-T} U^{-T} H^T (perm NULL means P = I). */
 int orc_solve_adjoint(int64_t n, int64_t nrhs, const double *H, const double *LU,
-                      const double *W, double *Y) {
-    orc_apply_t(n, nrhs, H, W, Y);
-    orc_upper_t_solve(n, nrhs, LU, Y);
-    orc_lower_unit_t_solve(n, nrhs, LU, Y);
+                      const int64_t *perm, const double *W, double *Y) {
+    size_t sz = sizeof(double) * (size_t)(n * nrhs);
+    double *g = (double *)malloc(sz > 0 ? sz : 1);
+    orc_apply_t(n, nrhs, H, W, g);
+    orc_upper_t_solve(n, nrhs, LU, g);
+    orc_lower_unit_t_solve(n, nrhs, LU, g);
+    if (perm) {
+        for (int64_t t = 0; t < n; ++t)
+            memcpy(Y + perm[t] * nrhs, g + t * nrhs, sizeof(double) * (size_t)nrhs);
+    } else {
+        memcpy(Y, g, sz);
+    }
+    free(g);
     return 0;
 }
 

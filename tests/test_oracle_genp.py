@@ -130,3 +130,123 @@ def test_pivot_bounds_theorem_thnorms(orc, seed):
     piv = np.abs(np.diag(LU))
     assert np.all(piv <= (N + Nm * N * N) * (1 + 1e-10))
     assert np.all(1.0 / piv <= Nm * (1 + 1e-8))
+
+
+# ---------------------------------------------------------------------------
+# Block elimination with partial pivoting confined to the small diagonal blocks
+# (Section 3, after eq. eqgenpin: the recursion of eq. eqgenp may stop at small
+# blocks that a black-box method handles).
+# ---------------------------------------------------------------------------
+
+def _windows(n, block):
+    """Diagonal blocks [s, e) as the library cuts them: panels of `block`,
+    a panel wider than 128 cut once into 128 + rest."""
+    out = []
+    for s in range(0, n, block):
+        b = min(block, n - s)
+        if b <= 128:
+            out.append((s, s + b))
+        else:
+            out += [(s, s + 128), (s + 128, s + b)]
+    return out
+
+
+def _lapack_perm(piv):
+    perm = np.arange(len(piv))
+    for i, p in enumerate(piv):
+        perm[[i, p]] = perm[[p, i]]
+    return perm
+
+
+@pytest.mark.parametrize("n,seed", [(5, 0), (17, 1), (64, 2), (128, 3)])
+def test_local_pivot_one_window_is_lapack_getrf(orc, n, seed):
+    # one window covering the whole matrix: textbook partial pivoting (LAPACK getrf)
+    import scipy.linalg as sl
+
+    A = np.random.default_rng(seed).standard_normal((n, n))
+    LU, perm, rc, info = orc.genp_local(A, block=n)
+    assert rc == orc.OK and info == -1
+    lu, piv = sl.lu_factor(A)
+    np.testing.assert_array_equal(perm, _lapack_perm(piv))
+    np.testing.assert_allclose(LU, lu, rtol=0, atol=1e-12 * n)
+
+
+@pytest.mark.parametrize("n,block,seed", [(6, 2, 0), (7, 3, 1), (7, 7, 2), (6, 4, 3)])
+def test_local_pivot_products_of_pivots_are_leading_minors(orc, n, block, seed):
+    # Rows move only inside a window, so after each window [s, e) the product of
+    # the pivots so far is +-det M^(e) (det A = det B det S, Corollary corec);
+    # minors by the Leibniz formula.
+    A = _strongly_nonsingular_int(n, seed)
+    LU, perm, rc, info = orc.genp_local(A, block=block)
+    assert rc == orc.OK
+    minors = exact.leading_minors(exact.to_frac(A))
+    d = np.diag(LU)
+    for s, e in _windows(n, block):
+        assert abs(np.prod(d[:e])) == pytest.approx(abs(float(minors[e - 1])), rel=1e-11)
+        # rows never leave their window
+        assert sorted(perm[s:e]) == list(range(s, e))
+
+
+@pytest.mark.parametrize("n,block,seed", [(6, 2, 4), (7, 3, 5), (8, 4, 6)])
+def test_local_pivot_window_blocks_factor_exact_schur_complements(orc, n, block, seed):
+    # The diagonal block of window [s, e) factors the row-permuted leading block
+    # of the exact Schur complement S(M^(s), M) (eq. eqgenp; exact rationals,
+    # Gauss-Jordan inverses of the pivot blocks).
+    A = _strongly_nonsingular_int(n, seed)
+    LU, perm, rc, _ = orc.genp_local(A, block=block)
+    assert rc == orc.OK
+    wins = _windows(n, block)
+    schur = exact.block_schur_sequence(exact.to_frac(A), [e - s for s, e in wins])
+    for idx, (s, e) in enumerate(wins):
+        S = exact.to_frac(A) if idx == 0 else schur[idx - 1]
+        w = e - s
+        Bw = np.array([[float(v) for v in row[:w]] for row in S[:w]])
+        Lw = np.tril(LU[s:e, s:e], -1) + np.eye(w)
+        Uw = np.triu(LU[s:e, s:e])
+        np.testing.assert_allclose(Lw @ Uw, Bw[perm[s:e] - s], rtol=1e-11, atol=1e-11)
+        assert np.all(np.abs(np.tril(LU[s:e, s:e], -1)) <= 1.0 + 1e-15)
+
+
+@pytest.mark.parametrize("n,block", [(64, 16), (100, 32), (300, 256), (257, 200)])
+def test_local_pivot_reconstructs_PM(orc, n, block):
+    A = np.random.default_rng(n).standard_normal((n, n))
+    LU, perm, rc, _ = orc.genp_local(A, block=block)
+    assert rc == orc.OK
+    L = np.tril(LU, -1) + np.eye(n)
+    U = np.triu(LU)
+    np.testing.assert_allclose(L @ U, A[perm], rtol=0, atol=1e-11 * np.abs(A).max() * n)
+    for s, e in _windows(n, block):
+        assert sorted(perm[s:e]) == list(range(s, e))
+
+
+def test_local_pivot_block_one_is_genp(orc):
+    A = _strongly_nonsingular_int(6, 7)
+    LU1, perm, rc1, _ = orc.genp_local(A, block=1)
+    LU0, rc0, _ = orc.genp(A)
+    assert rc1 == rc0 == orc.OK
+    np.testing.assert_array_equal(perm, np.arange(6))
+    np.testing.assert_array_equal(LU1, LU0)
+
+
+def test_local_pivot_breakdown_and_rescue(orc):
+    # leading 1x1 block zero: GENP breaks down at 0, a window of 2 pivots past it
+    A = np.array([[0.0, 1.0, 2.0, 1.0],
+                  [1.0, 0.0, 1.0, 3.0],
+                  [2.0, 1.0, 0.0, 1.0],
+                  [1.0, 2.0, 1.0, 1.0]])
+    _, rc, info = orc.genp(A)
+    assert rc == orc.ZERO_PIVOT and info == 0
+    LU, perm, rc, info = orc.genp_local(A, block=2)
+    assert rc == orc.OK and info == -1
+    assert list(perm[:2]) == [1, 0]
+    # leading 2x2 block singular: every window of 2 ends on an exactly zero pivot
+    B = np.array([[1.0, 2.0, 0.0, 1.0],
+                  [2.0, 4.0, 1.0, 0.0],
+                  [0.0, 1.0, 3.0, 1.0],
+                  [1.0, 0.0, 1.0, 2.0]])
+    _, _, rc, info = orc.genp_local(B, block=2)
+    assert rc == orc.ZERO_PIVOT and info == 1
+    # ties: equal magnitudes choose the smaller original row index
+    C = np.array([[1.0, 1.0], [-1.0, 2.0]])
+    _, perm, rc, _ = orc.genp_local(C, block=2)
+    assert rc == orc.OK and list(perm) == [0, 1]

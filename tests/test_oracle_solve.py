@@ -150,3 +150,38 @@ def test_refinement_reduces_backward_error(orc):
     s = orc.solve(f, b, refine=3)
     assert s.eta[1] <= s.eta[0]
     assert s.eta[-1] <= 1e-15
+
+
+@pytest.mark.parametrize("kind", [0, 1, 2, 3])
+@pytest.mark.parametrize("block", [8, 40, 200])
+def test_local_pivot_solve_and_adjoint_match_lapack(orc, kind, block):
+    # P A H = L U: x = H U^{-1} L^{-1} P b and A^{-T} w = P^T L^{-T} U^{-T} H^T w
+    n = 150
+    A = workloads.conditioned(n, 1e4, seed=9)
+    B = workloads.rhs(n, 2, seed=9)
+    W = workloads.rhs(n, 3, seed=10)
+    f = orc.factor(A, kind, seed=12, local_pivot_block=block)
+    assert f.status == orc.OK
+    s = orc.solve(f, B, refine=1)
+    X = np.linalg.solve(A, B)
+    assert np.linalg.norm(s.X - X) / np.linalg.norm(X) <= 8 * 1e4 * n * EPS
+    assert s.eta[-1] <= 1e-15
+    Y = orc.solve_adjoint(f, W)
+    want = np.linalg.solve(A.T, W)
+    np.testing.assert_allclose(Y, want, rtol=0, atol=1e-10 * np.abs(want).max())
+
+
+@pytest.mark.parametrize("seed", range(2))
+def test_breakdown_case_local_pivot(orc, seed):
+    # the leading 64 x 64 block is singular: windows of 64 meet an exact zero at
+    # 63 without a multiplier; windows of 128 pivot past it; a Gaussian
+    # multiplier makes every window's leading block nonsingular
+    A = workloads.breakdown_case(seed)
+    b = workloads.rhs(256, 1, seed)
+    f = orc.factor(A, orc.NONE, 0, local_pivot_block=64)
+    assert f.status == orc.ZERO_PIVOT and f.info == 63
+    f = orc.factor(A, orc.NONE, 0, local_pivot_block=128)
+    assert f.status == orc.OK
+    f = orc.factor(A, orc.GAUSSIAN, seed + 1000, local_pivot_block=64)
+    assert f.status == orc.OK
+    assert orc.solve(f, b, refine=1).eta[-1] <= 1e-15
