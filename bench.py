@@ -2,11 +2,13 @@
 
 One step is one pass of the whole method on one synthetic system, inputs
 already in HBM: draw the Gaussian multiplier G, form M = A G, block Gaussian
-elimination with no pivoting (panels of 256), the two triangular solves, the
-back-transformation x = G y, and FP64 iterative refinement until the normwise
-backward error eta <= 1e-14 (at most 16 steps).  It runs twice: factors in
-FP64, and factors in FP32 on the matrix cores with FP64 refinement; the
-headline is the faster of the two that reaches eta <= 1e-14.
+elimination (panels of 256), the two triangular solves, the back-transformation
+x = G y, and FP64 iterative refinement until the normwise backward error
+eta <= 1e-14 (at most 16 steps).  Paths: factors in FP64 or in FP32 on the
+matrix cores (refinement always FP64), each with no pivoting (GENP, "f64",
+"f32") or with partial pivoting confined to the diagonal blocks of at most 128
+("f64p", "f32p").  The headline is the fastest path that reaches eta <= 1e-14;
+its speed-up over FP64 GENP is reported beside it.
 
 Rate convention: (2/3 n^3 + 2 n^2 nrhs) flops per step (the standard count for
 an LU solve), divided by the wall time of the whole step; the executed flops
@@ -52,9 +54,13 @@ def lu_solve_flops(n, nrhs):
     return 2.0 / 3.0 * n ** 3 + 2.0 * n * n * nrhs
 
 
-def run_path(rmge, torch, A, b, prec, seed, steps, warmup, block, max_refine):
-    name = "f64" if prec == rmge.F64 else "f32"
-    f = rmge.factor(A, kind=rmge.GAUSSIAN, seed=seed, block=block, prec=prec)
+PATHS = {"f64": ("F64", "PIVOT_NONE"), "f32": ("F32", "PIVOT_NONE"),
+         "f64p": ("F64", "PIVOT_BLOCK"), "f32p": ("F32", "PIVOT_BLOCK")}
+
+
+def run_path(rmge, torch, A, b, name, seed, steps, warmup, block, max_refine):
+    prec, pivot = (getattr(rmge, x) for x in PATHS[name])
+    f = rmge.factor(A, kind=rmge.GAUSSIAN, seed=seed, block=block, prec=prec, pivot=pivot)
     if not f.ok:
         raise RuntimeError("factorization broke down: status %d" % f.status)
     X = torch.empty_like(b)
@@ -106,7 +112,7 @@ def product_traffic(n, head):
     return (TRAFFIC["fetch_kib"] + TRAFFIC["write_kib"]) * 1024.0
 
 
-def cpu_baseline(n_cpu, seed):
+def cpu_baseline(n_cpu, seed, local_pivot_block=0):
     import numpy as np
 
     import oracle
@@ -119,7 +125,7 @@ def cpu_baseline(n_cpu, seed):
     oracle.lib()
     log("cpu baseline: oracle factor + solve on %d threads" % oracle.num_threads())
     t0 = time.perf_counter()
-    f = oracle.factor(A, oracle.GAUSSIAN, seed)
+    f = oracle.factor(A, oracle.GAUSSIAN, seed, local_pivot_block=local_pivot_block)
     s = oracle.solve(f, b, refine=1)
     dt = time.perf_counter() - t0
     log("cpu baseline: %.1f s, eta %.2e" % (dt, s.eta[-1]))
@@ -128,8 +134,10 @@ def cpu_baseline(n_cpu, seed):
         "unit": "TFLOP/s",
         "cores": oracle.num_threads(),
         "kind": "oracle",
-        "sample": "n=%d system of the same recipe (Gaussian multiplier, FP64, 1 RHS, 1 refinement "
-                  "step), plain-loop C oracle; %.1f s wall" % (n_cpu, dt),
+        "sample": "n=%d system of the same recipe (Gaussian multiplier, %s, FP64, 1 RHS, 1 "
+                  "refinement step), plain-loop C oracle; %.1f s wall"
+                  % (n_cpu, "pivoting inside blocks of %d" % local_pivot_block
+                     if local_pivot_block else "no pivoting", dt),
         "eta": float(s.eta[-1]),
         "seconds": dt,
     }
@@ -144,7 +152,7 @@ def main():
     ap.add_argument("--seed", type=int, default=1)
     ap.add_argument("--block", type=int, default=256)
     ap.add_argument("--max-refine", type=int, default=16)
-    ap.add_argument("--paths", default="f64,f32")
+    ap.add_argument("--paths", default="f64,f32,f64p,f32p")
     ap.add_argument("--cpu-n", type=int, default=4096)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--matrix", default="conditioned", choices=["conditioned", "gaussian"],
@@ -178,13 +186,15 @@ def main():
 
     results = {}
     for p in args.paths.split(","):
-        prec = rmge.F64 if p == "f64" else rmge.F32
-        results[p] = run_path(rmge, torch, A, b, prec, args.seed + 1000, args.steps, args.warmup,
+        if p not in PATHS:
+            ap.error("unknown path %r (choose from %s)" % (p, ",".join(PATHS)))
+        results[p] = run_path(rmge, torch, A, b, p, args.seed + 1000, args.steps, args.warmup,
                               args.block, args.max_refine)
 
     ok = {k: v for k, v in results.items() if v["converged"]}
-    head = min(ok, key=lambda k: ok[k]["ms_per_step"]) if ok else "f64"
+    head = min(ok, key=lambda k: ok[k]["ms_per_step"]) if ok else next(iter(results))
     r = results[head]
+    fp32 = head.startswith("f32")
     flops = lu_solve_flops(n, 1)
     value = flops / (r["ms_per_step"] * 1e-3) / 1e12
     # roofline of the dominant kernel: the M = A G product, one launch per step
@@ -201,7 +211,7 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f64" if head == "f64" else "f32 factors + f64 refinement",
+        "dtype": "f32 factors + f64 refinement" if fp32 else "f64",
         "data": "synthetic",
         "config": {"workload": ("precision: n=%d Gaussian multiplier, kappa=%.3g, 1 RHS, "
                                 "eta<=1e-14" % (n, kappa)) if kappa else
@@ -209,20 +219,22 @@ def main():
                                 "eta<=1e-14" % n),
                    "n": n, "kappa": kappa, "seed": args.seed, "block": args.block, "nrhs": 1,
                    "headline_path": head},
-        "roofline": {"bound": "mfma", "achieved": round(achieved, 3), "peak": PEAK[head],
-                     "unit": "TFLOP/s", "frac": round(achieved / PEAK[head], 4),
-                     "traffic": product_traffic(n, head), "traffic_unit": "bytes/launch",
+        "roofline": {"bound": "mfma", "achieved": round(achieved, 3),
+                     "peak": PEAK["f32" if fp32 else "f64"], "unit": "TFLOP/s",
+                     "frac": round(achieved / PEAK["f32" if fp32 else "f64"], 4),
+                     "traffic": product_traffic(n, "f32" if fp32 else "f64"),
+                     "traffic_unit": "bytes/launch",
                      "kernel": "k_gemm (M = A G)",
                      "ms_per_launch": round(r["ms_product"], 4)},
         "executed_tflops": round((flops + prod_flops) / (r["ms_per_step"] * 1e-3) / 1e12, 3),
         "paths": {k: {kk: (float("%.6g" % vv) if isinstance(vv, float) else vv)
                       for kk, vv in v.items()} for k, v in results.items()},
     }
-    if "f64" in results and "f32" in results:
-        out["speedup_f32_over_f64"] = round(results["f64"]["ms_per_step"]
-                                            / results["f32"]["ms_per_step"], 3)
+    if "f64" in results and head != "f64":
+        out["speedup_over_f64_genp"] = round(results["f64"]["ms_per_step"] / r["ms_per_step"], 3)
     if not args.no_cpu:
-        out["cpu_baseline"] = cpu_baseline(args.cpu_n, args.seed)
+        out["cpu_baseline"] = cpu_baseline(args.cpu_n, args.seed,
+                                           args.block if head.endswith("p") else 0)
     print(json.dumps(out))
 
 

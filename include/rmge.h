@@ -12,7 +12,11 @@
  *   3. factor M = L U by block Gaussian elimination with no pivoting
  *      (Section 3, eq. eqgenp applied to pivot blocks of `block` columns;
  *      in exact arithmetic the result does not depend on the block size,
- *      by the order-independence argument after eq. eqgenpin);
+ *      by the order-independence argument after eq. eqgenpin); or, as a
+ *      variant, stop that recursion at small diagonal blocks and factor each
+ *      with partial pivoting confined to the block (the black-box treatment
+ *      of small pivot blocks that Section 3 allows): P M = L U with P a
+ *      block-diagonal permutation;
  *   4. solve L U y = b and return x = H y (Fact faprepr), optionally followed
  *      by FP64 iterative refinement (Section 8.1 protocol).
  *
@@ -60,6 +64,19 @@ typedef enum {
     RMGE_F32 = 1  /* FP32 MFMA with FP32 accumulation; refine in FP64 */
 } rmge_prec;
 
+/* Row exchanges (rmge_factor_pivoted). */
+typedef enum {
+    RMGE_PIVOT_NONE = 0, /* GENP: no row exchanges (the paper's method) */
+    /* Partial pivoting inside each diagonal block where the recursion stops.
+     * The blocks: panels of `block` columns (the last may be narrower); a
+     * panel wider than 128 is cut into its first 128 columns and the rest.
+     * For column k the pivot is the entry of largest magnitude among the rows
+     * of k's block at or below k (ties: the smaller original row index).
+     * Rows never leave their block, so only the leading blocks at block
+     * boundaries must be nonsingular (Theorem thnorms with those blocks). */
+    RMGE_PIVOT_BLOCK = 1
+} rmge_pivot;
+
 typedef enum {
     RMGE_OK = 0,
     RMGE_EINVAL = 1,        /* bad argument (size, leading dimension, kind, block) */
@@ -103,6 +120,15 @@ rmge_status rmge_factor(const double *A, int64_t n, int32_t kind, uint64_t seed,
 rmge_status rmge_factor_ex(const double *A, int64_t n, int64_t lda, int32_t kind, uint64_t seed,
                            int32_t block, int32_t prec, void *hip_stream, rmge_factors **out);
 
+/* As rmge_factor_ex with a choice of row exchanges (rmge_pivot).  With
+ * RMGE_PIVOT_BLOCK the handle holds P M = L U; solves apply P, the adjoint
+ * P^T, and rmge_factors_lu returns the rows in pivoted order.  A zero pivot
+ * (all candidates of a column inside its block exactly 0) means the leading
+ * block at that block boundary is singular; stats.info is its index. */
+rmge_status rmge_factor_pivoted(const double *A, int64_t n, int64_t lda, int32_t kind,
+                                uint64_t seed, int32_t block, int32_t prec, int32_t pivot,
+                                void *hip_stream, rmge_factors **out);
+
 /* Re-run the factorization of an existing handle on a new A of the same size
  * (same kind, precision, block and stream), reusing every allocation.  The new
  * A replaces the borrowed one. */
@@ -120,7 +146,8 @@ rmge_status rmge_solve(const rmge_factors *f, const double *B, int64_t nrhs, int
                        rmge_solve_stats *st);
 
 /* Y = A^{-T} W = L^{-T} U^{-T} H^T W (the adjoint, from A^{-1} = H (A H)^{-1},
- * Fact faprepr).  Reuses L and U.  W, Y: device, n x nrhs, row-major. */
+ * Fact faprepr; P^T L^{-T} U^{-T} H^T W when pivoted).  Reuses L and U.
+ * W, Y: device, n x nrhs, row-major. */
 rmge_status rmge_solve_adjoint(const rmge_factors *f, const double *W, int64_t nrhs, int64_t ldw,
                                double *Y, int64_t ldy);
 
@@ -129,8 +156,13 @@ rmge_status rmge_solve_adjoint(const rmge_factors *f, const double *W, int64_t n
 rmge_status rmge_factor_stats_get(const rmge_factors *f, rmge_factor_stats *s);
 
 /* Copy the packed factors (unit L strictly below the diagonal, U on and above)
- * into LU (device, n x n, ld >= n), converted to FP64. */
+ * into LU (device, n x n, ld >= n), converted to FP64.  Pivoted handles:
+ * L U = P M, rows in the order of rmge_factors_perm. */
 rmge_status rmge_factors_lu(const rmge_factors *f, double *LU, int64_t ld);
+
+/* The row order of the factors: perm[t] = the row of M = A H stored at row t
+ * (the identity without pivoting).  perm: device, n int32 values. */
+rmge_status rmge_factors_perm(const rmge_factors *f, int32_t *perm);
 
 /* The multiplier's random parameters as drawn by the library: kind GAUSSIAN
  * gives n*n values (G row-major), CIRCULANT n (c), TOEPLITZ 2n-1 (tau, with

@@ -14,11 +14,13 @@ from __future__ import annotations
 
 from . import _rmge
 from ._rmge import (RMGE_F32, RMGE_F64, RMGE_MULT_CIRCULANT, RMGE_MULT_GAUSSIAN,
-                    RMGE_MULT_NONE, RMGE_MULT_TOEPLITZ, RMGEError, lib)
+                    RMGE_MULT_NONE, RMGE_MULT_TOEPLITZ, RMGE_PIVOT_BLOCK, RMGE_PIVOT_NONE,
+                    RMGEError, lib)
 
 NONE, GAUSSIAN, CIRCULANT, TOEPLITZ = (RMGE_MULT_NONE, RMGE_MULT_GAUSSIAN, RMGE_MULT_CIRCULANT,
                                        RMGE_MULT_TOEPLITZ)
 F64, F32 = RMGE_F64, RMGE_F32
+PIVOT_NONE, PIVOT_BLOCK = RMGE_PIVOT_NONE, RMGE_PIVOT_BLOCK
 KIND_NAMES = {"none": NONE, "gaussian": GAUSSIAN, "circulant": CIRCULANT, "toeplitz": TOEPLITZ}
 
 
@@ -48,16 +50,17 @@ def _kind(kind) -> int:
 class Factors:
     """A factorization handle: owns L, U and the multiplier; borrows A."""
 
-    def __init__(self, A, kind=GAUSSIAN, seed=0, block=256, prec=F64):
+    def __init__(self, A, kind=GAUSSIAN, seed=0, block=256, prec=F64, pivot=PIVOT_NONE):
         _check_matrix(A)
         n = A.shape[0]
         if A.shape[1] != n:
             raise ValueError("A must be square")
         self.A = A  # kept alive: the library reads it during refinement
         self.n, self.kind, self.seed, self.block, self.prec = n, _kind(kind), seed, block, prec
+        self.pivot = pivot
         self.device = A.device
-        rc, h = _rmge.rmge_factor_ex(A.data_ptr(), n, A.stride(0), self.kind, seed, block, prec,
-                                     _stream_handle(A.device))
+        rc, h = _rmge.rmge_factor_pivoted(A.data_ptr(), n, A.stride(0), self.kind, seed, block,
+                                          prec, pivot, _stream_handle(A.device))
         if rc not in (_rmge.RMGE_OK, _rmge.RMGE_ZERO_PIVOT, _rmge.RMGE_NONFINITE):
             raise RMGEError(rc, "rmge_factor_ex")
         self._h = h
@@ -139,6 +142,16 @@ class Factors:
             raise RMGEError(rc, "rmge_factors_lu")
         return LU
 
+    def perm(self):
+        """Row order of the factors (int32 tensor): row t of L U is row perm[t] of A H."""
+        import torch
+
+        p = torch.empty(self.n, dtype=torch.int32, device=self.device)
+        rc = _rmge.rmge_factors_perm(self._h, p.data_ptr())
+        if rc:
+            raise RMGEError(rc, "rmge_factors_perm")
+        return p
+
     def close(self):
         if getattr(self, "_h", None) is not None and self._h.value:
             _rmge.rmge_destroy(self._h)
@@ -151,8 +164,8 @@ class Factors:
             pass
 
 
-def factor(A, kind=GAUSSIAN, seed=0, block=256, prec=F64) -> Factors:
-    return Factors(A, kind=kind, seed=seed, block=block, prec=prec)
+def factor(A, kind=GAUSSIAN, seed=0, block=256, prec=F64, pivot=PIVOT_NONE) -> Factors:
+    return Factors(A, kind=kind, seed=seed, block=block, prec=prec, pivot=pivot)
 
 
 def multiplier_params(kind, n, seed, device="cuda"):
@@ -184,4 +197,5 @@ def precondition(A, kind, seed):
 
 
 __all__ = ["factor", "Factors", "multiplier_params", "precondition", "RMGEError", "lib",
-           "NONE", "GAUSSIAN", "CIRCULANT", "TOEPLITZ", "F64", "F32"]
+           "NONE", "GAUSSIAN", "CIRCULANT", "TOEPLITZ", "F64", "F32", "PIVOT_NONE",
+           "PIVOT_BLOCK"]

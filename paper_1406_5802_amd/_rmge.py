@@ -13,6 +13,7 @@ LIB_PATH = os.path.join(HERE, "librmge.so")
 
 RMGE_MULT_NONE, RMGE_MULT_GAUSSIAN, RMGE_MULT_CIRCULANT, RMGE_MULT_TOEPLITZ = 0, 1, 2, 3
 RMGE_F64, RMGE_F32 = 0, 1
+RMGE_PIVOT_NONE, RMGE_PIVOT_BLOCK = 0, 1
 (RMGE_OK, RMGE_EINVAL, RMGE_ENOMEM, RMGE_EDEVICE, RMGE_ZERO_PIVOT, RMGE_NONFINITE,
  RMGE_NOT_CONVERGED) = range(7)
 
@@ -23,9 +24,10 @@ STATUS_NAMES = {
 
 # Every function the header declares, for the export check.
 EXPORTS = (
-    "rmge_factor", "rmge_factor_ex", "rmge_refactor", "rmge_solve", "rmge_solve_adjoint",
-    "rmge_factor_stats_get", "rmge_factors_lu", "rmge_multiplier_params", "rmge_param_count",
-    "rmge_precondition", "rmge_destroy", "rmge_status_string", "rmge_version",
+    "rmge_factor", "rmge_factor_ex", "rmge_factor_pivoted", "rmge_refactor", "rmge_solve",
+    "rmge_solve_adjoint", "rmge_factor_stats_get", "rmge_factors_lu", "rmge_factors_perm",
+    "rmge_multiplier_params", "rmge_param_count", "rmge_precondition", "rmge_destroy",
+    "rmge_status_string", "rmge_version",
 )
 
 
@@ -60,6 +62,8 @@ def lib() -> ctypes.CDLL:
     hp = ctypes.POINTER(ctypes.c_void_p)
     L.rmge_factor.argtypes = [dp, i64, i32, u64, i32, hp]
     L.rmge_factor_ex.argtypes = [dp, i64, i64, i32, u64, i32, i32, vp, hp]
+    L.rmge_factor_pivoted.argtypes = [dp, i64, i64, i32, u64, i32, i32, i32, vp, hp]
+    L.rmge_factors_perm.argtypes = [vp, vp]
     L.rmge_refactor.argtypes = [vp, dp, i64, u64]
     L.rmge_solve.argtypes = [vp, dp, i64, i64, dp, i64, i32, ctypes.c_double,
                              ctypes.POINTER(rmge_solve_stats)]
@@ -75,9 +79,9 @@ def lib() -> ctypes.CDLL:
     L.rmge_status_string.argtypes = [i32]
     L.rmge_status_string.restype = ctypes.c_char_p
     L.rmge_version.restype = i32
-    for name in ("rmge_factor", "rmge_factor_ex", "rmge_refactor", "rmge_solve",
-                 "rmge_solve_adjoint", "rmge_factor_stats_get", "rmge_factors_lu",
-                 "rmge_multiplier_params", "rmge_precondition"):
+    for name in ("rmge_factor", "rmge_factor_ex", "rmge_factor_pivoted", "rmge_refactor",
+                 "rmge_solve", "rmge_solve_adjoint", "rmge_factor_stats_get", "rmge_factors_lu",
+                 "rmge_factors_perm", "rmge_multiplier_params", "rmge_precondition"):
         getattr(L, name).restype = ctypes.c_int
     _lib = L
     return L
@@ -102,6 +106,14 @@ def rmge_factor_ex(A: int, n: int, lda: int, kind: int, seed: int, block: int, p
     h = ctypes.c_void_p()
     rc = lib().rmge_factor_ex(A, n, lda, kind, ctypes.c_uint64(seed & (2**64 - 1)), block, prec,
                               stream, ctypes.byref(h))
+    return rc, h
+
+
+def rmge_factor_pivoted(A: int, n: int, lda: int, kind: int, seed: int, block: int, prec: int,
+                        pivot: int, stream: int):
+    h = ctypes.c_void_p()
+    rc = lib().rmge_factor_pivoted(A, n, lda, kind, ctypes.c_uint64(seed & (2**64 - 1)), block,
+                                   prec, pivot, stream, ctypes.byref(h))
     return rc, h
 
 
@@ -133,6 +145,10 @@ def rmge_factor_stats_get(h):
 
 def rmge_factors_lu(h, LU: int, ld: int) -> int:
     return lib().rmge_factors_lu(h, LU, ld)
+
+
+def rmge_factors_perm(h, perm: int) -> int:
+    return lib().rmge_factors_perm(h, perm)
 
 
 def rmge_multiplier_params(kind: int, n: int, seed: int, out: int, stream: int) -> int:

@@ -1,7 +1,9 @@
 // C ABI of the library: handle management and the order of the method's steps.
 //
 //   factor:  H from the seed  ->  M = A H  ->  block elimination with no
-//            pivoting on M (eq. eqgenp with pivot blocks of `block` columns);
+//            pivoting on M (eq. eqgenp with pivot blocks of `block` columns),
+//            or with partial pivoting confined to the small diagonal blocks
+//            where the recursion stops (Section 3, after eq. eqgenpin);
 //   solve:   x = H U^{-1} L^{-1} b (Fact faprepr), then refinement
 //            r = b - A x (FP64), x += H U^{-1} L^{-1} r (Section 8.1);
 //   adjoint: y = L^{-T} U^{-T} H^T w.
@@ -13,6 +15,7 @@
 //   inv   2 x 2 arrays of 256 x 256 holding, on their diagonals, the inverses
 //         of the 32 x 32 diagonal sub-blocks of a pivot block's L and U (two
 //         buffers: the look-ahead panel and the current one)
+//   piv   n ints (pivoted variant): row t of the factors is row piv[t] of M
 //   solve workspace, grown on demand: two n x nrhs of T, one n x nrhs FP64
 //         residual, norms
 #include <hip/hip_runtime.h>
@@ -30,7 +33,7 @@ using namespace rmge;
 
 struct rmge_factors {
     int64_t n = 0, lda = 0, ld = 0;
-    int32_t kind = 0, prec = 0, block = 0;
+    int32_t kind = 0, prec = 0, block = 0, pivot = 0;
     uint64_t seed = 0;
     hipStream_t stream = nullptr;
     const double *A = nullptr;
@@ -42,6 +45,7 @@ struct rmge_factors {
     double *tw = nullptr;      // twiddles (m/2 + 1 complex)
     int m = 0;
     void *inv = nullptr;
+    int *piv = nullptr;  // pivoted variant: P M = L U with row t = row piv[t] of M
     DevStatus *st = nullptr;
     double *scal = nullptr;  // [0] max|U| [1] min|u_kk| [2] max|M| [3] ||A||_inf
     // solve workspace
@@ -181,16 +185,24 @@ hipError_t factor_pivot_block(rmge_factors *f, T *a, int b, int64_t k0, T *Linv,
                               hipStream_t s) {
     const int64_t ld = f->ld;
     const int *abort = &f->st->code;
-    if (b <= kLeaf) return leaf_lu<T>(a, ld, b, Linv, Uinv, kInvLd, k0, f->st, s);
+    int *piv = f->pivot ? f->piv : nullptr;
+    if (b <= kLeaf) return leaf_lu<T>(a, ld, b, Linv, Uinv, kInvLd, k0, f->st, piv, s);
     const int b1 = kLeaf, b2 = b - kLeaf;
-    HIP_TRY(leaf_lu<T>(a, ld, b1, Linv, Uinv, kInvLd, k0, f->st, s));
-    // Bab <- La^{-1} Bab ; Bba <- Bba Ua^{-1} ; Bb <- Bb - Bba Bab
-    HIP_TRY(trsm<T>(0, a, ld, b1, a + b1, ld, b2, Linv, abort, s));
+    HIP_TRY(leaf_lu<T>(a, ld, b1, Linv, Uinv, kInvLd, k0, f->st, piv, s));
+    // Bab <- La^{-1} Pa Bab ; Bba <- Bba Ua^{-1} ; Bb <- Bb - Bba Bab
+    HIP_TRY(trsm<T>(0, a, ld, b1, a + b1, ld, b2, Linv, abort, s, piv ? piv + k0 : nullptr, k0));
     HIP_TRY(trsm<T>(1, a, ld, b1, a + b1 * ld, ld, b2, Uinv, abort, s));
     HIP_TRY(Prec<T>::gemm(kGemmUpdate, b2, b2, b1, T(-1), a + b1 * ld, ld, a + b1, ld, T(1),
                           a + b1 * ld + b1, ld, abort, s));
-    return leaf_lu<T>(a + b1 * ld + b1, ld, b2, Linv + b1 * kInvLd + b1, Uinv + b1 * kInvLd + b1,
-                      kInvLd, k0 + b1, f->st, s);
+    HIP_TRY(leaf_lu<T>(a + b1 * ld + b1, ld, b2, Linv + b1 * kInvLd + b1,
+                       Uinv + b1 * kInvLd + b1, kInvLd, k0 + b1, f->st, piv, s));
+    // the second block's exchanges reach Bba now: the solves with this pivot
+    // block's L (block row, next step) need its rows in pivot order
+    if (piv) {
+        T *base = static_cast<T *>(f->lu);
+        HIP_TRY(permute_rows<T>(base, ld, k0 + b1, b2, k0, k0 + b1, piv, abort, s));
+    }
+    return hipSuccess;
 }
 
 // Right-looking block elimination with no pivoting (eq. eqgenp applied to
@@ -202,6 +214,9 @@ hipError_t factor_pivot_block(rmge_factors *f, T *a, int b, int64_t k0, T *Linv,
 //   main stream:  Schur update E <- E - D C of all remaining columns, which
 //                 runs while the side stream works on the next panel.
 // The update E - (D U_B^{-1})(L_B^{-1} C) is E - D B^{-1} C of eq. eqgenp.
+// Pivoted variant: P_B B = L_B U_B inside the pivot block, the block row is
+// read through P_B (L_B^{-1} P_B C), the rows below are untouched, and one
+// pass at the end applies the exchanges to the multipliers left of each block.
 // Inverses of the pivot blocks' diagonal sub-blocks alternate between two
 // buffers so the side stream never overwrites those the main stream reads.
 template <typename T>
@@ -235,7 +250,8 @@ hipError_t genp_blocked(rmge_factors *f) {
         const int bn = static_cast<int>(r < nb ? r : nb);  // next panel width
         T *akk = a + k * ld + k;
         T *a12 = akk + b, *a21 = akk + b * ld, *a22 = akk + b * ld + b;
-        HIP_TRY(trsm<T>(0, akk, ld, b, a12, ld, r, Linv(step), abort, s0));
+        HIP_TRY(trsm<T>(0, akk, ld, b, a12, ld, r, Linv(step), abort, s0,
+                        f->pivot ? f->piv + k : nullptr, k));
         HIP_TRY(Prec<T>::gemm(kGemmUpdate, r, bn, b, T(-1), a21, ld, a12, ld, T(1), a22, ld, abort,
                               s0));
         HIP_TRY(hipEventRecord(f->ev_narrow, s0));
@@ -248,6 +264,7 @@ hipError_t genp_blocked(rmge_factors *f) {
             HIP_TRY(Prec<T>::gemm(kGemmUpdate, r, r - bn, b, T(-1), a21, ld, a12 + bn, ld, T(1),
                                   a22 + bn, ld, abort, s0));
     }
+    if (f->pivot) HIP_TRY(permute_left<T>(a, ld, n, nb, f->piv, abort, s0));
     if (f->main) {
         HIP_TRY(hipEventRecord(f->ev_join, s0));
         HIP_TRY(hipStreamWaitEvent(f->stream, f->ev_join, 0));
@@ -313,6 +330,7 @@ rmge_status run_factor(rmge_factors *f) {
     RMGE_TRY(multiply<T>(f, f->scal + 2));
     RMGE_TRY(hipEventRecord(f->ev[2], s));
     RMGE_TRY(hipEventRecord(f->ev[3], s));
+    if (f->pivot) RMGE_TRY(iota(f->piv, f->n, s));
     RMGE_TRY(genp_blocked<T>(f));
     RMGE_TRY(hipEventRecord(f->ev[4], s));
     RMGE_TRY(hipMemcpyAsync(&f->host_st, f->st, sizeof(DevStatus), hipMemcpyDeviceToHost, s));
@@ -334,8 +352,8 @@ rmge_status run_factor(rmge_factors *f) {
 
 void free_handle(rmge_factors *f) {
     if (!f) return;
-    void *ptrs[] = {f->lu, f->G, f->params, f->hker, f->hhat, f->tw, f->inv, f->st, f->scal,
-                    f->wy, f->wx, f->wr, f->wnorm, f->wt, f->wsync};
+    void *ptrs[] = {f->lu, f->G, f->params, f->hker, f->hhat, f->tw, f->inv, f->piv, f->st,
+                    f->scal, f->wy, f->wx, f->wr, f->wnorm, f->wt, f->wsync};
     for (void *p : ptrs)
         if (p) (void)hipFree(p);
     for (hipEvent_t &e : f->ev)
@@ -363,6 +381,7 @@ rmge_status alloc_handle(rmge_factors *f) {
     const size_t inv_elems = 4 * kInvLd * kInvLd;  // two buffers of (Linv, Uinv)
     RMGE_TRY(hipMalloc(&f->inv, es * inv_elems));
     RMGE_TRY(hipMemsetAsync(f->inv, 0, es * inv_elems, f->stream));
+    if (f->pivot) RMGE_TRY(hipMalloc(&f->piv, sizeof(int) * static_cast<size_t>(n)));
     RMGE_TRY(hipMalloc(&f->st, sizeof(DevStatus)));
     RMGE_TRY(hipMalloc(&f->scal, sizeof(double) * 8));
     for (hipEvent_t &e : f->ev) RMGE_TRY(hipEventCreate(&e));
@@ -454,14 +473,14 @@ rmge_status solve_sync_error(rmge_factors *f) {
     return RMGE_OK;
 }
 
-// X = beta X + H U^{-1} L^{-1} src   (src FP64 n x nrhs, lds)
+// X = beta X + H U^{-1} L^{-1} P src   (src FP64 n x nrhs, lds; P = I unless pivoted)
 template <typename T>
 hipError_t apply_inverse(rmge_factors *f, const double *src, int64_t lds, int64_t nrhs, double *X,
                          int64_t ldx, double beta) {
     const int64_t n = f->n;
     hipStream_t s = f->stream;
     T *Y = static_cast<T *>(f->wy);
-    hipError_t e = convert_2d<double, T>(src, lds, Y, nrhs, n, nrhs, s);
+    hipError_t e = convert_2d<double, T>(src, lds, Y, nrhs, n, nrhs, s, f->pivot ? f->piv : nullptr);
     if (e != hipSuccess) return e;
     if ((e = tri_solves<T>(f, nrhs, false)) != hipSuccess) return e;
     switch (f->kind) {
@@ -566,14 +585,17 @@ rmge_status run_adjoint(rmge_factors *f, const double *W, int64_t nrhs, int64_t 
                                       s)));
     }
     RMGE_TRY(tri_solves<T>(f, nrhs, true));
-    RMGE_TRY((convert_2d<T, double>(Z, nrhs, Y, ldy, n, nrhs, s)));
+    // Y = P^T (L^{-T} U^{-T} H^T W): row t goes back to row piv[t]
+    RMGE_TRY((convert_2d<T, double>(Z, nrhs, Y, ldy, n, nrhs, s, nullptr,
+                                    f->pivot ? f->piv : nullptr)));
     RMGE_TRY(hipStreamSynchronize(s));
     return solve_sync_error(f);
 }
 
 rmge_status check_factor_args(const double *A, int64_t n, int64_t lda, int32_t kind,
-                              int32_t block, int32_t prec) {
+                              int32_t block, int32_t prec, int32_t pivot = RMGE_PIVOT_NONE) {
     if (!A || n < 1 || lda < n || n > (int64_t(1) << 20)) return RMGE_EINVAL;
+    if (pivot != RMGE_PIVOT_NONE && pivot != RMGE_PIVOT_BLOCK) return RMGE_EINVAL;
     if (kind < RMGE_MULT_NONE || kind > RMGE_MULT_TOEPLITZ) return RMGE_EINVAL;
     if (block < 0 || block > kMaxBlock) return RMGE_EINVAL;
     if (prec != RMGE_F64 && prec != RMGE_F32) return RMGE_EINVAL;
@@ -586,10 +608,11 @@ rmge_status check_factor_args(const double *A, int64_t n, int64_t lda, int32_t k
 
 extern "C" {
 
-rmge_status rmge_factor_ex(const double *A, int64_t n, int64_t lda, int32_t kind, uint64_t seed,
-                           int32_t block, int32_t prec, void *hip_stream, rmge_factors **out) {
+rmge_status rmge_factor_pivoted(const double *A, int64_t n, int64_t lda, int32_t kind,
+                                uint64_t seed, int32_t block, int32_t prec, int32_t pivot,
+                                void *hip_stream, rmge_factors **out) {
     if (!out) return RMGE_EINVAL;
-    rmge_status rs = check_factor_args(A, n, lda, kind, block, prec);
+    rmge_status rs = check_factor_args(A, n, lda, kind, block, prec, pivot);
     if (rs != RMGE_OK) return rs;
     if (!device_ok()) return RMGE_EDEVICE;
     rmge_factors *f = new (std::nothrow) rmge_factors();
@@ -600,6 +623,7 @@ rmge_status rmge_factor_ex(const double *A, int64_t n, int64_t lda, int32_t kind
     f->kind = kind;
     f->prec = prec;
     f->block = block == 0 ? kMaxBlock : block;
+    f->pivot = pivot;
     f->seed = seed;
     f->stream = static_cast<hipStream_t>(hip_stream);
     f->A = A;
@@ -616,6 +640,12 @@ rmge_status rmge_factor_ex(const double *A, int64_t n, int64_t lda, int32_t kind
     }
     free_handle(f);
     return rs;
+}
+
+rmge_status rmge_factor_ex(const double *A, int64_t n, int64_t lda, int32_t kind, uint64_t seed,
+                           int32_t block, int32_t prec, void *hip_stream, rmge_factors **out) {
+    return rmge_factor_pivoted(A, n, lda, kind, seed, block, prec, RMGE_PIVOT_NONE, hip_stream,
+                               out);
 }
 
 rmge_status rmge_factor(const double *A, int64_t n, int32_t kind, uint64_t seed, int32_t block,
@@ -683,6 +713,16 @@ rmge_status rmge_factors_lu(const rmge_factors *f, double *LU, int64_t ld) {
                        : convert_2d<double, double>(static_cast<const double *>(f->lu), f->ld, LU,
                                                     ld, f->n, f->n, f->stream);
     if (e != hipSuccess) return from_hip(e);
+    return from_hip(hipStreamSynchronize(f->stream));
+}
+
+rmge_status rmge_factors_perm(const rmge_factors *f, int32_t *perm) {
+    if (!f || !perm) return RMGE_EINVAL;
+    if (f->pivot)
+        RMGE_TRY(hipMemcpyAsync(perm, f->piv, sizeof(int) * static_cast<size_t>(f->n),
+                                hipMemcpyDeviceToDevice, f->stream));
+    else
+        RMGE_TRY(iota(perm, f->n, f->stream));
     return from_hip(hipStreamSynchronize(f->stream));
 }
 

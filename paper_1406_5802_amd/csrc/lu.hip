@@ -39,21 +39,34 @@ __device__ inline bool is_bad(T p) {
 
 // One pivot block (b <= 128) in registers: thread (ty, tx) of a 16 x 16 grid
 // (one wave per SIMD) holds elements (ty + 16 p, tx + 16 q), p, q < 8.  Pivot
-// step j: the owners of column j and of row j publish them to LDS (double
-// buffered, so one barrier per step) and every thread applies the rank-1
-// update a_ic -= (a_ij / a_jj) a_jc to the elements it holds, with the
-// multiplier formed as a_ij times the reciprocal of the pivot.  Multipliers of
-// rows <= j and pivot-row entries of columns <= j are zero, so the update is
-// branch-free (retired elements receive exact zero updates) and an element
-// below the diagonal keeps the value it had when its column was eliminated;
-// the multipliers l_ic = a_ic / a_cc are formed at write-back from the
-// recorded pivot reciprocals.
-template <typename T>
+// step j: the owners of column j and of the pivot row publish them to LDS and
+// every thread applies the rank-1 update a_ic -= (a_ij / a_pj) a_pc to the
+// elements it holds, with the multiplier formed as a_ij times the reciprocal
+// of the pivot.  Multipliers of retired rows and pivot-row entries of columns
+// <= j are zero, so the update is branch-free (retired elements receive exact
+// zero updates) and an element left of its row's pivot keeps the value it had
+// when its column was eliminated; the multipliers l_ic = a_ic / a_cc are formed
+// at write-back from the recorded pivot reciprocals.
+//
+// PIV = false: GENP, the pivot of step j is row j (one barrier per step, the
+// column and row buffers double-buffered).
+// PIV = true: partial pivoting inside this block (the black-box treatment of a
+// small pivot block that Section 3 allows once the recursion of eq. eqgenp
+// stops).  Rows stay in their registers; the pivot of step j is the active row
+// with the largest |a_ij| (ties: the lower row index), found by a shuffle
+// reduction over the four owner lanes of each wave and a reduction over the
+// four waves' candidates in LDS; a second barrier publishes the pivot row.
+// Row i is written back to position pos[i] (the step that retired it), and
+// piv[k0 + pos[i]] = k0 + i records the exchange.
+template <typename T, bool PIV>
 __global__ __launch_bounds__(256) void k_leaf_lu(T *a, int64_t lda, int b, int64_t k0,
-                                                 DevStatus *st) {
+                                                 DevStatus *st, int *piv) {
     __shared__ T colv[2][kLeaf];
     __shared__ T rowv[2][kLeaf];
     __shared__ T rcp[kLeaf];
+    __shared__ T cand_v[2][4];
+    __shared__ int cand_i[2][4];
+    __shared__ int pos[kLeaf];
     if (st->code != 0) return;  // an earlier pivot block broke down
     // This kernel is a chain of short dependent steps that runs beside the wide
     // Schur-update GEMM; raise its waves' issue priority on the shared SIMDs.
@@ -68,8 +81,12 @@ __global__ __launch_bounds__(256) void k_leaf_lu(T *a, int64_t lda, int b, int64
             const int i = ty + 16 * p, c = tx + 16 * q;
             v[p][q] = (i < b && c < b) ? a[static_cast<int64_t>(i) * lda + c] : T(0);
         }
+    unsigned act = 0;  // PIV: bit p set while row ty + 16 p is still active
+#pragma unroll
+    for (int p = 0; p < 8; ++p)
+        if (ty + 16 * p < b) act |= 1u << p;
+    if (PIV && tid < kLeaf) pos[tid] = -1;
 
-    // Unblocked elimination, pivot by pivot (eq. eqgenp with 1 x 1 pivot blocks).
     int done = b;
     for (int j = 0; j < b; ++j) {
         const int buf = j & 1, jq = j >> 4, jr = j & 15;
@@ -78,14 +95,44 @@ __global__ __launch_bounds__(256) void k_leaf_lu(T *a, int64_t lda, int b, int64
 #define RMGE_COL(Q)                                                          \
     case Q:                                                                  \
         _Pragma("unroll") for (int p = 0; p < 8; ++p) colv[buf][ty + 16 * p] = v[p][Q]; \
+        if (PIV) {                                                           \
+            T bv = T(-1);                                                    \
+            int bi = kLeaf;                                                  \
+            _Pragma("unroll") for (int p = 0; p < 8; ++p) {                  \
+                const T x = v[p][Q];                                         \
+                const T key = (x != x) ? T(INFINITY) : (x < T(0) ? -x : x);  \
+                if (((act >> p) & 1u) && key > bv) { bv = key; bi = ty + 16 * p; } \
+            }                                                                \
+            _Pragma("unroll") for (int o = 16; o <= 32; o <<= 1) {           \
+                const T ov = __shfl_xor(bv, o);                              \
+                const int oi = __shfl_xor(bi, o);                            \
+                if (ov > bv || (ov == bv && oi < bi)) { bv = ov; bi = oi; }  \
+            }                                                                \
+            if ((ty & 3) == 0) { cand_v[buf][ty >> 2] = bv; cand_i[buf][ty >> 2] = bi; } \
+        }                                                                    \
         break;
                 RMGE_COL(0) RMGE_COL(1) RMGE_COL(2) RMGE_COL(3)
                 RMGE_COL(4) RMGE_COL(5) RMGE_COL(6) RMGE_COL(7)
 #undef RMGE_COL
             }
         }
-        if (ty == jr) {
-            switch (jq) {
+        int sel = j;
+        if (PIV) {
+            __syncthreads();
+            T bv = cand_v[buf][0];
+            int bi = cand_i[buf][0];
+#pragma unroll
+            for (int w = 1; w < 4; ++w) {
+                const T ov = cand_v[buf][w];
+                const int oi = cand_i[buf][w];
+                if (ov > bv || (ov == bv && oi < bi)) { bv = ov; bi = oi; }
+            }
+            sel = bi;  // uniform; an active row always exists for j < b
+            if (ty == (sel & 15)) act &= ~(1u << (sel >> 4));
+            if (tid == 0) pos[sel] = j;
+        }
+        if (ty == (sel & 15)) {
+            switch (sel >> 4) {
 #define RMGE_ROW(P)                                                          \
     case P:                                                                  \
         _Pragma("unroll") for (int q = 0; q < 8; ++q) rowv[buf][tx + 16 * q] = v[P][q]; \
@@ -96,16 +143,16 @@ __global__ __launch_bounds__(256) void k_leaf_lu(T *a, int64_t lda, int b, int64
             }
         }
         __syncthreads();
-        const T piv = rowv[buf][j];
-        if (is_bad(piv)) {
+        const T pv = rowv[buf][j];
+        if (is_bad(pv)) {
             if (tid == 0) {
                 st->info = k0 + j;
-                st->code = (piv == T(0)) ? 4 : 5;
+                st->code = (pv == T(0)) ? 4 : 5;
             }
             done = j;
             break;
         }
-        const T rp = T(1) / piv;
+        const T rp = T(1) / pv;
         if (tid == 0) rcp[j] = rp;
         T u[8];
 #pragma unroll
@@ -116,23 +163,34 @@ __global__ __launch_bounds__(256) void k_leaf_lu(T *a, int64_t lda, int b, int64
 #pragma unroll
         for (int p = 0; p < 8; ++p) {
             const int i = ty + 16 * p;
-            const T l = (i > j) ? colv[buf][i] * rp : T(0);
+            const bool live = PIV ? ((act >> p) & 1u) != 0 : (i > j);
+            const T l = live ? colv[buf][i] * rp : T(0);
 #pragma unroll
             for (int q = 0; q < 8; ++q) v[p][q] -= l * u[q];
         }
     }
     __syncthreads();
-    // write back, forming the multipliers below the diagonal
+    if (PIV) {
+        if (done < b && tid == 0) {  // breakdown: keep the row order a permutation
+            int next = done;
+            for (int i = 0; i < b; ++i)
+                if (pos[i] < 0) pos[i] = next++;
+        }
+        __syncthreads();
+        if (tid < b) piv[k0 + pos[tid]] = static_cast<int>(k0 + tid);
+    }
+    // write back (row i to its position), forming the multipliers left of the pivot
 #pragma unroll
-    for (int p = 0; p < 8; ++p)
+    for (int p = 0; p < 8; ++p) {
+        const int i = ty + 16 * p;
+        const int dst = PIV ? (i < b ? pos[i] : i) : i;
 #pragma unroll
         for (int q = 0; q < 8; ++q) {
-            const int i = ty + 16 * p, c = tx + 16 * q;
-            if (c < i && c < done) v[p][q] *= rcp[c];
-            if (i < b && c < b) a[static_cast<int64_t>(i) * lda + c] = v[p][q];
+            const int c = tx + 16 * q;
+            if (c < dst && c < done) v[p][q] *= rcp[c];
+            if (i < b && c < b) a[static_cast<int64_t>(dst) * lda + c] = v[p][q];
         }
-    if (done < b) return;
-
+    }
 }
 
 // Inverses of the 32 x 32 diagonal sub-blocks of a factored pivot block (the
@@ -199,11 +257,14 @@ __global__ __launch_bounds__(512) void k_diag_inv(const T *a, int64_t lda, int b
 // again as X_i, and every wave subtracts (factor block) x X_i from its tiles
 // further along; the factor operand streams from L2.
 //
-// LEFT:  C (b x count) <- L^{-1} C, strips of 32 columns (row tiles dealt).
+// LEFT:  C (b x count) <- L^{-1} P C, strips of 32 columns (row tiles dealt).
+// With `rowsrc` (pivoted blocks) row t of P C is row rowsrc[t] - rowbase of C:
+// the strip is read whole into registers before any of it is written back.
 template <typename T>
 __global__ __launch_bounds__(256, 2) void k_trsm_left(const T *lu, int64_t ld, int b, T *C,
                                                       int64_t ldc, int64_t count, const T *Dinv,
-                                                      const int *abort) {
+                                                      const int *abort, const int *rowsrc,
+                                                      int64_t rowbase) {
     using acc_t = typename Mma<T>::acc;
     constexpr int BN = 32;
     __shared__ T Xs[kSub][BN + 1];
@@ -224,7 +285,9 @@ __global__ __launch_bounds__(256, 2) void k_trsm_left(const T *lu, int64_t ld, i
             for (int r = 0; r < 4; ++r) {
                 const int t = wave + 4 * u;
                 const int row = 16 * t + Mma<T>::row(lane, r), col = 16 * j + lo;
-                acc[u][j][r] = (t < nrt && row < b && col < wcols) ? C[row * ldc + c0 + col] : T(0);
+                const bool in = t < nrt && row < b && col < wcols;
+                const int64_t src = (in && rowsrc) ? rowsrc[row] - rowbase : row;
+                acc[u][j][r] = in ? C[src * ldc + c0 + col] : T(0);
             }
     for (int i = 0, i0 = 0; i0 < b; ++i, i0 += kSub) {
         const int sb = (b - i0) < kSub ? (b - i0) : kSub;
@@ -421,15 +484,88 @@ __global__ void k_set_identity(T *a, int64_t ld, int64_t n) {
     }
 }
 
+// dst[di] = src[si] with si = gather ? gather[i] : i, di = scatter ? scatter[i] : i.
 template <typename T, typename U>
 __global__ void k_convert_2d(const T *src, int64_t lds, U *dst, int64_t ldd, int64_t rows,
-                             int64_t cols) {
+                             int64_t cols, const int *gather, const int *scatter) {
     const int64_t total = rows * cols;
     for (int64_t e = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x; e < total;
          e += static_cast<int64_t>(gridDim.x) * blockDim.x) {
         const int64_t i = e / cols, j = e % cols;
-        dst[i * ldd + j] = static_cast<U>(src[i * lds + j]);
+        const int64_t si = gather ? gather[i] : i, di = scatter ? scatter[i] : i;
+        dst[di * ldd + j] = static_cast<U>(src[si * lds + j]);
     }
+}
+
+__global__ void k_iota(int *p, int64_t n) {
+    for (int64_t e = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x; e < n;
+         e += static_cast<int64_t>(gridDim.x) * blockDim.x)
+        p[e] = static_cast<int>(e);
+}
+
+// Diagonal block (leaf) number `leaf` of the pivoted elimination: panels of nb
+// columns, a panel wider than kLeaf cut into kLeaf + rest.  Returns its width
+// (0 if there is no such block), its first row in *s and its panel's first
+// column in *p0.
+__device__ inline int leaf_span(int64_t n, int nb, int64_t leaf, int64_t *s, int64_t *p0) {
+    if (nb <= kLeaf) {
+        *s = *p0 = leaf * nb;
+        const int64_t w = n - *s;
+        return w <= 0 ? 0 : static_cast<int>(w < nb ? w : nb);
+    }
+    *p0 = (leaf >> 1) * nb;
+    const int64_t pb = (n - *p0) < nb ? (n - *p0) : nb;
+    if (pb <= 0) return 0;
+    if ((leaf & 1) == 0) {
+        *s = *p0;
+        return static_cast<int>(pb < kLeaf ? pb : kLeaf);
+    }
+    *s = *p0 + kLeaf;
+    return pb > kLeaf ? static_cast<int>(pb - kLeaf) : 0;
+}
+
+// Rows s .. s + w - 1 of columns c0 .. c0 + cw - 1 (cw <= 32) take the values of
+// rows piv[s + t]: the strip is read whole into LDS, then written back.
+template <typename T>
+__device__ inline void permute_strip(T *a, int64_t ld, int64_t s, int w, int64_t c0, int cw,
+                                     const int *piv, T (*tile)[33]) {
+    for (int e = threadIdx.x; e < w * 32; e += blockDim.x) {
+        const int t = e >> 5, c = e & 31;
+        if (c < cw) tile[t][c] = a[static_cast<int64_t>(piv[s + t]) * ld + c0 + c];
+    }
+    __syncthreads();
+    for (int e = threadIdx.x; e < w * 32; e += blockDim.x) {
+        const int t = e >> 5, c = e & 31;
+        if (c < cw) a[(s + t) * ld + c0 + c] = tile[t][c];
+    }
+}
+
+// Apply each diagonal block's row exchanges to the multipliers left of its
+// panel, so that the stored factors satisfy P M = L U row by row (the part
+// inside the panel is done when the panel is factored).  Block y of the grid
+// covers leaf y; block x a strip of 32 columns.
+template <typename T>
+__global__ __launch_bounds__(256) void k_permute_left(T *a, int64_t ld, int64_t n, int nb,
+                                                      const int *piv, const int *abort) {
+    __shared__ T tile[kLeaf][33];
+    if (*abort != 0) return;
+    int64_t s = 0, p0 = 0;
+    const int w = leaf_span(n, nb, blockIdx.y, &s, &p0);
+    const int64_t c0 = static_cast<int64_t>(blockIdx.x) * 32;
+    if (w == 0 || c0 >= p0) return;
+    permute_strip(a, ld, s, w, c0, static_cast<int>((p0 - c0) < 32 ? (p0 - c0) : 32), piv, tile);
+}
+
+// One diagonal block's exchanges applied to columns cb .. ce - 1 of its rows.
+template <typename T>
+__global__ __launch_bounds__(256) void k_permute_rows(T *a, int64_t ld, int64_t s, int w,
+                                                      int64_t cb, int64_t ce, const int *piv,
+                                                      const int *abort) {
+    __shared__ T tile[kLeaf][33];
+    if (*abort != 0) return;
+    const int64_t c0 = cb + static_cast<int64_t>(blockIdx.x) * 32;
+    if (c0 >= ce) return;
+    permute_strip(a, ld, s, w, c0, static_cast<int>((ce - c0) < 32 ? (ce - c0) : 32), piv, tile);
 }
 
 __device__ inline void atomic_max_nonneg(double *addr, double v) {
@@ -483,9 +619,13 @@ int grid_for(int64_t total, int threads) {
 
 template <typename T>
 hipError_t leaf_lu(T *a, int64_t lda, int b, T *Linv, T *Uinv, int64_t ldw, int64_t k0,
-                   DevStatus *st, hipStream_t s) {
+                   DevStatus *st, int *piv, hipStream_t s) {
     if (b < 1 || b > kLeaf) return hipErrorInvalidValue;
-    hipLaunchKernelGGL(k_leaf_lu<T>, dim3(1), dim3(256), 0, s, a, lda, b, k0, st);
+    if (piv)
+        hipLaunchKernelGGL((k_leaf_lu<T, true>), dim3(1), dim3(256), 0, s, a, lda, b, k0, st, piv);
+    else
+        hipLaunchKernelGGL((k_leaf_lu<T, false>), dim3(1), dim3(256), 0, s, a, lda, b, k0, st,
+                           piv);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k_diag_inv<T>, dim3(1), dim3(512), 0, s, a, lda, b, Linv, Uinv, ldw, st);
@@ -494,13 +634,15 @@ hipError_t leaf_lu(T *a, int64_t lda, int b, T *Linv, T *Uinv, int64_t ldw, int6
 
 template <typename T>
 hipError_t trsm(int side, const T *lu, int64_t ld, int b, T *C, int64_t ldc, int64_t count,
-                const T *Dinv, const int *abort, hipStream_t s) {
+                const T *Dinv, const int *abort, hipStream_t s, const int *rowsrc,
+                int64_t rowbase) {
     if (b < 1 || b > kMaxBlock) return hipErrorInvalidValue;
     if (count <= 0) return hipSuccess;
+    if (side != 0 && rowsrc) return hipErrorInvalidValue;
     const unsigned grid = static_cast<unsigned>((count + 31) / 32);
     if (side == 0)
         hipLaunchKernelGGL(k_trsm_left<T>, dim3(grid), dim3(256), 0, s, lu, ld, b, C, ldc, count,
-                           Dinv, abort);
+                           Dinv, abort, rowsrc, rowbase);
     else
         hipLaunchKernelGGL(k_trsm_right<T>, dim3(grid), dim3(256), 0, s, lu, ld, b, C, ldc, count,
                            Dinv, abort);
@@ -516,10 +658,41 @@ hipError_t set_identity(T *a, int64_t ld, int64_t n, hipStream_t s) {
 
 template <typename T, typename U>
 hipError_t convert_2d(const T *src, int64_t lds, U *dst, int64_t ldd, int64_t rows, int64_t cols,
-                      hipStream_t s) {
+                      hipStream_t s, const int *gather, const int *scatter) {
     if (rows <= 0 || cols <= 0) return hipSuccess;
     hipLaunchKernelGGL((k_convert_2d<T, U>), dim3(grid_for(rows * cols, 256)), dim3(256), 0, s,
-                       src, lds, dst, ldd, rows, cols);
+                       src, lds, dst, ldd, rows, cols, gather, scatter);
+    return hipGetLastError();
+}
+
+hipError_t iota(int *p, int64_t n, hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_iota, dim3(grid_for(n, 256)), dim3(256), 0, s, p, n);
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t permute_rows(T *a, int64_t ld, int64_t s0, int w, int64_t cb, int64_t ce,
+                        const int *piv, const int *abort, hipStream_t s) {
+    if (w < 1 || w > kLeaf) return hipErrorInvalidValue;
+    if (ce <= cb) return hipSuccess;
+    hipLaunchKernelGGL(k_permute_rows<T>, dim3(static_cast<unsigned>((ce - cb + 31) / 32)),
+                       dim3(256), 0, s, a, ld, s0, w, cb, ce, piv, abort);
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t permute_left(T *a, int64_t ld, int64_t n, int nb, const int *piv, const int *abort,
+                        hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+    if (nb < 1 || nb > kMaxBlock) return hipErrorInvalidValue;
+    const int64_t panels = (n + nb - 1) / nb;
+    const int64_t leaves = nb <= kLeaf ? panels : 2 * panels;
+    const int64_t strips = (n + 31) / 32;
+    if (leaves > 65535) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_permute_left<T>, dim3(static_cast<unsigned>(strips),
+                                               static_cast<unsigned>(leaves)),
+                       dim3(256), 0, s, a, ld, n, nb, piv, abort);
     return hipGetLastError();
 }
 
@@ -541,23 +714,31 @@ hipError_t abs_max(const T *m, int64_t ld, int64_t n, double *out3, hipStream_t 
 }
 
 template hipError_t leaf_lu<double>(double *, int64_t, int, double *, double *, int64_t, int64_t,
-                                    DevStatus *, hipStream_t);
+                                    DevStatus *, int *, hipStream_t);
 template hipError_t leaf_lu<float>(float *, int64_t, int, float *, float *, int64_t, int64_t,
-                                   DevStatus *, hipStream_t);
+                                   DevStatus *, int *, hipStream_t);
 template hipError_t trsm<double>(int, const double *, int64_t, int, double *, int64_t, int64_t,
-                                 const double *, const int *, hipStream_t);
+                                 const double *, const int *, hipStream_t, const int *, int64_t);
 template hipError_t trsm<float>(int, const float *, int64_t, int, float *, int64_t, int64_t,
-                                const float *, const int *, hipStream_t);
+                                const float *, const int *, hipStream_t, const int *, int64_t);
+template hipError_t permute_left<double>(double *, int64_t, int64_t, int, const int *, const int *,
+                                         hipStream_t);
+template hipError_t permute_rows<double>(double *, int64_t, int64_t, int, int64_t, int64_t,
+                                         const int *, const int *, hipStream_t);
+template hipError_t permute_rows<float>(float *, int64_t, int64_t, int, int64_t, int64_t,
+                                        const int *, const int *, hipStream_t);
+template hipError_t permute_left<float>(float *, int64_t, int64_t, int, const int *, const int *,
+                                        hipStream_t);
 template hipError_t set_identity<double>(double *, int64_t, int64_t, hipStream_t);
 template hipError_t set_identity<float>(float *, int64_t, int64_t, hipStream_t);
 template hipError_t convert_2d<double, double>(const double *, int64_t, double *, int64_t, int64_t,
-                                               int64_t, hipStream_t);
+                                               int64_t, hipStream_t, const int *, const int *);
 template hipError_t convert_2d<double, float>(const double *, int64_t, float *, int64_t, int64_t,
-                                              int64_t, hipStream_t);
+                                              int64_t, hipStream_t, const int *, const int *);
 template hipError_t convert_2d<float, double>(const float *, int64_t, double *, int64_t, int64_t,
-                                              int64_t, hipStream_t);
+                                              int64_t, hipStream_t, const int *, const int *);
 template hipError_t convert_2d<float, float>(const float *, int64_t, float *, int64_t, int64_t,
-                                             int64_t, hipStream_t);
+                                             int64_t, hipStream_t, const int *, const int *);
 template hipError_t lu_stats<double>(const double *, int64_t, int64_t, double *, hipStream_t);
 template hipError_t lu_stats<float>(const float *, int64_t, int64_t, double *, hipStream_t);
 template hipError_t abs_max<double>(const double *, int64_t, int64_t, double *, hipStream_t);

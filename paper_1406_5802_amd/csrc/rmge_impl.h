@@ -46,27 +46,45 @@ hipError_t gemm_f32_a64(int shape, int64_t M, int64_t N, int64_t K, float alpha,
                         int64_t ldc, const int *abort, hipStream_t s, double *absmax = nullptr);
 
 // ----------------------------------------------------------------- lu.hip
-// Factor the b x b diagonal block at `a` (b <= kLeaf) in place (GENP) and
-// write the inverses of the 32 x 32 diagonal sub-blocks of its unit-lower and
-// upper factors into the matching diagonal positions of Linv and Uinv (ldw).
-// k0 = global index of the block's first pivot.
+// Factor the b x b diagonal block at `a` (b <= kLeaf) in place and write the
+// inverses of the 32 x 32 diagonal sub-blocks of its unit-lower and upper
+// factors into the matching diagonal positions of Linv and Uinv (ldw).
+// k0 = global index of the block's first pivot (the block sits at rows and
+// columns k0 ..).  piv == nullptr: GENP.  Otherwise partial pivoting inside
+// the block: rows are stored in pivot order and piv[k0 + t] receives the
+// global row index that now sits at k0 + t.
 template <typename T>
 hipError_t leaf_lu(T *a, int64_t lda, int b, T *Linv, T *Uinv, int64_t ldw, int64_t k0,
-                   DevStatus *st, hipStream_t s);
+                   DevStatus *st, int *piv, hipStream_t s);
 // In-place triangular solves with the factored pivot block at `lu` (width
 // b <= kMaxBlock), by blocked substitution with the 32 x 32 diagonal inverses
 // in Dinv (ld kMaxBlock):
-//   side 0: C (b x count, ldc) <- L^{-1} C      (Dinv = Linv)
-//   side 1: C (count x b, ldc) <- C U^{-1}      (Dinv = Uinv)
+//   side 0: C (b x count, ldc) <- L^{-1} P C    (Dinv = Linv; row t of P C is
+//           row rowsrc[t] - rowbase of C, or row t when rowsrc is null)
+//   side 1: C (count x b, ldc) <- C U^{-1}      (Dinv = Uinv; rowsrc must be null)
 template <typename T>
 hipError_t trsm(int side, const T *lu, int64_t ld, int b, T *C, int64_t ldc, int64_t count,
-                const T *Dinv, const int *abort, hipStream_t s);
+                const T *Dinv, const int *abort, hipStream_t s, const int *rowsrc = nullptr,
+                int64_t rowbase = 0);
+// After a pivoted factorization with panels of nb: apply every diagonal
+// block's row exchanges (piv) to the multipliers left of its panel.
+template <typename T>
+hipError_t permute_left(T *a, int64_t ld, int64_t n, int nb, const int *piv, const int *abort,
+                        hipStream_t s);
+// Rows s0 .. s0 + w - 1 (w <= kLeaf) of columns cb .. ce - 1 take the values of
+// rows piv[s0 + t] (one diagonal block's exchanges inside its own panel).
+template <typename T>
+hipError_t permute_rows(T *a, int64_t ld, int64_t s0, int w, int64_t cb, int64_t ce,
+                        const int *piv, const int *abort, hipStream_t s);
+// p[i] = i, i < n.
+hipError_t iota(int *p, int64_t n, hipStream_t s);
 // Element-wise helpers.
 template <typename T>
 hipError_t set_identity(T *a, int64_t ld, int64_t n, hipStream_t s);
+// dst row (scatter ? scatter[i] : i) <- src row (gather ? gather[i] : i), i < rows.
 template <typename T, typename U>
 hipError_t convert_2d(const T *src, int64_t lds, U *dst, int64_t ldd, int64_t rows, int64_t cols,
-                      hipStream_t s);
+                      hipStream_t s, const int *gather = nullptr, const int *scatter = nullptr);
 // out3[0] = max |U|, out3[1] = min |u_kk| (preset to 0, +Inf); atomics.
 template <typename T>
 hipError_t lu_stats(const T *lu, int64_t ld, int64_t n, double *out3, hipStream_t s);

@@ -73,6 +73,10 @@ def test_argument_validation_before_device(rmge):
     # Toeplitz FFT period above the LDS-resident maximum
     assert _rmge.rmge_factor_ex(fake, 9000, 9000, 3, 0, 64, 0, 0)[0] == _rmge.RMGE_EINVAL
     assert _rmge.rmge_solve(None, fake, 1, 1, fake, 1, 1, 0.0)[0] == _rmge.RMGE_EINVAL
+    # row-exchange mode outside rmge_pivot
+    assert _rmge.rmge_factor_pivoted(fake, 8, 8, 1, 0, 64, 0, 2, 0)[0] == _rmge.RMGE_EINVAL
+    assert _rmge.rmge_factor_pivoted(fake, 8, 8, 1, 0, 64, 0, -1, 0)[0] == _rmge.RMGE_EINVAL
+    assert _rmge.rmge_factors_perm(None, fake) == _rmge.RMGE_EINVAL
 
 
 def test_binding_refuses_cpu_tensors(rmge):
