@@ -12,9 +12,11 @@
 //   lu    n x ld  (ld = n rounded up to 64)  the packed factors, over M
 //   mult  GAUSSIAN: n x n of T, G row-major; CIRCULANT/TOEPLITZ: parameters,
 //         the period-m kernel h, its half spectrum and the twiddle table
-//   inv   2 x 2 arrays of 256 x 256 holding, on their diagonals, the inverses
-//         of the 32 x 32 diagonal sub-blocks of a pivot block's L and U (two
-//         buffers: the look-ahead panel and the current one)
+//   inv   two buffers (the look-ahead panel and the current one), each the
+//         inverses of the 32 x 32 diagonal sub-blocks of a pivot block's L and
+//         U, compact (256 x 32 each)
+//   sinv  the same for every aligned 32-row diagonal sub-block of the final
+//         L and U (2 x round_up(n, 256) x 32), used by the solves
 //   piv   n ints (pivoted variant): row t of the factors is row piv[t] of M
 //   solve workspace, grown on demand: two n x nrhs of T, one n x nrhs FP64
 //         residual, norms
@@ -45,6 +47,8 @@ struct rmge_factors {
     double *tw = nullptr;      // twiddles (m/2 + 1 complex)
     int m = 0;
     void *inv = nullptr;
+    void *sinv = nullptr;  // solve inverses: L part, then U part (sinv_rows rows each)
+    int64_t sinv_rows = 0;
     int *piv = nullptr;  // pivoted variant: P M = L U with row t = row piv[t] of M
     DevStatus *st = nullptr;
     double *scal = nullptr;  // [0] max|U| [1] min|u_kk| [2] max|M| [3] ||A||_inf
@@ -54,8 +58,7 @@ struct rmge_factors {
     double *wr = nullptr, *wnorm = nullptr;
     double *wt = nullptr;
     int64_t wt_size = 0;
-    int *wsync = nullptr;  // persistent solves: ticket, error word, one flag per 64 rows
-    int epoch = 0;
+    int *wsync = nullptr;  // persistent solves: ticket counter, error word
     // host copies
     DevStatus host_st{-1, 0, 0};
     bool stats_done = false;
@@ -70,8 +73,7 @@ struct rmge_factors {
 
 namespace {
 
-constexpr int kSolveBlock = 64;
-constexpr int kInvLd = kMaxBlock;
+constexpr int kSub = 32;  // rows of the inverted diagonal sub-blocks
 
 int64_t round_up(int64_t x, int64_t m) { return (x + m - 1) / m * m; }
 
@@ -177,7 +179,7 @@ struct Prec<float> {
 // ------------------------------------------------------------------ factor
 
 // Factor the b x b pivot block at `a` in place and leave the inverses of the
-// 32 x 32 diagonal sub-blocks of its factors in Linv, Uinv (ld kInvLd).
+// 32 x 32 diagonal sub-blocks of its factors in Linv, Uinv (compact, 32 columns).
 // Blocks wider than the LDS leaf are split once: B = [[Ba, Bab], [Bba, Bb]] is
 // eliminated as in eq. eqgenp with pivot block Ba.
 template <typename T>
@@ -186,16 +188,16 @@ hipError_t factor_pivot_block(rmge_factors *f, T *a, int b, int64_t k0, T *Linv,
     const int64_t ld = f->ld;
     const int *abort = &f->st->code;
     int *piv = f->pivot ? f->piv : nullptr;
-    if (b <= kLeaf) return leaf_lu<T>(a, ld, b, Linv, Uinv, kInvLd, k0, f->st, piv, s);
+    if (b <= kLeaf) return leaf_lu<T>(a, ld, b, Linv, Uinv, k0, f->st, piv, s);
     const int b1 = kLeaf, b2 = b - kLeaf;
-    HIP_TRY(leaf_lu<T>(a, ld, b1, Linv, Uinv, kInvLd, k0, f->st, piv, s));
+    HIP_TRY(leaf_lu<T>(a, ld, b1, Linv, Uinv, k0, f->st, piv, s));
     // Bab <- La^{-1} Pa Bab ; Bba <- Bba Ua^{-1} ; Bb <- Bb - Bba Bab
     HIP_TRY(trsm<T>(0, a, ld, b1, a + b1, ld, b2, Linv, abort, s, piv ? piv + k0 : nullptr, k0));
     HIP_TRY(trsm<T>(1, a, ld, b1, a + b1 * ld, ld, b2, Uinv, abort, s));
     HIP_TRY(Prec<T>::gemm(kGemmUpdate, b2, b2, b1, T(-1), a + b1 * ld, ld, a + b1, ld, T(1),
                           a + b1 * ld + b1, ld, abort, s));
-    HIP_TRY(leaf_lu<T>(a + b1 * ld + b1, ld, b2, Linv + b1 * kInvLd + b1,
-                       Uinv + b1 * kInvLd + b1, kInvLd, k0 + b1, f->st, piv, s));
+    HIP_TRY(leaf_lu<T>(a + b1 * ld + b1, ld, b2, Linv + b1 * kSub, Uinv + b1 * kSub, k0 + b1,
+                       f->st, piv, s));
     // the second block's exchanges reach Bba now: the solves with this pivot
     // block's L (block row, next step) need its rows in pivot order
     if (piv) {
@@ -225,7 +227,7 @@ hipError_t genp_blocked(rmge_factors *f) {
     const int64_t n = f->n, ld = f->ld;
     const int nb = f->block;
     T *inv = static_cast<T *>(f->inv);
-    const int64_t invsz = 2 * kInvLd * kInvLd;
+    const int64_t invsz = 2 * kMaxBlock * kSub;
     const int *abort = &f->st->code;
     hipStream_t s0 = f->main ? f->main : f->stream, s1 = f->side;
     if (f->main) {
@@ -233,7 +235,7 @@ hipError_t genp_blocked(rmge_factors *f) {
         HIP_TRY(hipStreamWaitEvent(s0, f->ev_fork, 0));
     }
     auto Linv = [&](int64_t step) { return inv + (step & 1) * invsz; };
-    auto Uinv = [&](int64_t step) { return inv + (step & 1) * invsz + kInvLd * kInvLd; };
+    auto Uinv = [&](int64_t step) { return inv + (step & 1) * invsz + kMaxBlock * kSub; };
 
     // panel 0 on the main stream
     {
@@ -333,6 +335,11 @@ rmge_status run_factor(rmge_factors *f) {
     if (f->pivot) RMGE_TRY(iota(f->piv, f->n, s));
     RMGE_TRY(genp_blocked<T>(f));
     RMGE_TRY(hipEventRecord(f->ev[4], s));
+    {
+        T *sl = static_cast<T *>(f->sinv);
+        RMGE_TRY(diag_inverses<T>(static_cast<const T *>(f->lu), f->ld, f->n, sl,
+                                  sl + f->sinv_rows * kSub, f->st, s));
+    }
     RMGE_TRY(hipMemcpyAsync(&f->host_st, f->st, sizeof(DevStatus), hipMemcpyDeviceToHost, s));
     RMGE_TRY(hipStreamSynchronize(s));
     float t01 = 0.f, t12 = 0.f, t34 = 0.f;
@@ -352,8 +359,8 @@ rmge_status run_factor(rmge_factors *f) {
 
 void free_handle(rmge_factors *f) {
     if (!f) return;
-    void *ptrs[] = {f->lu, f->G, f->params, f->hker, f->hhat, f->tw, f->inv, f->piv, f->st,
-                    f->scal, f->wy, f->wx, f->wr, f->wnorm, f->wt, f->wsync};
+    void *ptrs[] = {f->lu, f->G, f->params, f->hker, f->hhat, f->tw, f->inv, f->sinv, f->piv,
+                    f->st, f->scal, f->wy, f->wx, f->wr, f->wnorm, f->wt, f->wsync};
     for (void *p : ptrs)
         if (p) (void)hipFree(p);
     for (hipEvent_t &e : f->ev)
@@ -378,9 +385,13 @@ rmge_status alloc_handle(rmge_factors *f) {
         RMGE_TRY(hipMalloc(&f->tw, sizeof(double) * 2 * static_cast<size_t>(L + 1)));
         RMGE_TRY(fft_twiddles(f->m, f->tw, f->stream));
     }
-    const size_t inv_elems = 4 * kInvLd * kInvLd;  // two buffers of (Linv, Uinv)
+    const size_t inv_elems = 4 * kMaxBlock * kSub;  // two buffers of (Linv, Uinv)
     RMGE_TRY(hipMalloc(&f->inv, es * inv_elems));
     RMGE_TRY(hipMemsetAsync(f->inv, 0, es * inv_elems, f->stream));
+    f->sinv_rows = round_up(n, 256);
+    const size_t sinv_elems = 2 * static_cast<size_t>(f->sinv_rows) * kSub;
+    RMGE_TRY(hipMalloc(&f->sinv, es * sinv_elems));
+    RMGE_TRY(hipMemsetAsync(f->sinv, 0, es * sinv_elems, f->stream));
     if (f->pivot) RMGE_TRY(hipMalloc(&f->piv, sizeof(int) * static_cast<size_t>(n)));
     RMGE_TRY(hipMalloc(&f->st, sizeof(DevStatus)));
     RMGE_TRY(hipMalloc(&f->scal, sizeof(double) * 8));
@@ -426,10 +437,8 @@ rmge_status ensure_solve_ws(rmge_factors *f, int64_t nrhs, bool need_t) {
         f->ws_nrhs = nrhs;
     }
     if (!f->wsync) {
-        const size_t words = 2 + static_cast<size_t>((n + kSolveBlock - 1) / kSolveBlock);
-        RMGE_TRY(hipMalloc(&f->wsync, sizeof(int) * words));
-        RMGE_TRY(hipMemsetAsync(f->wsync, 0, sizeof(int) * words, f->stream));
-        f->epoch = 0;
+        RMGE_TRY(hipMalloc(&f->wsync, sizeof(int) * 2));
+        RMGE_TRY(hipMemsetAsync(f->wsync, 0, sizeof(int) * 2, f->stream));
     }
     if (need_t && f->kind == RMGE_MULT_GAUSSIAN) {
         const int64_t want = ((n + 255) / 256) * n * (nrhs < 16 ? nrhs : 16);
@@ -452,12 +461,15 @@ hipError_t tri_solves(rmge_factors *f, int64_t nrhs, bool adjoint) {
     const int64_t n = f->n, ld = f->ld;
     const T *lu = static_cast<const T *>(f->lu);
     T *Y = static_cast<T *>(f->wy), *X = static_cast<T *>(f->wx);
+    const T *Linv = static_cast<const T *>(f->sinv), *Uinv = Linv + f->sinv_rows * kSub;
     hipStream_t s = f->stream;
+    // L then U (solve), or U^T then L^T (adjoint)
     const int first = adjoint ? 2 : 0, second = adjoint ? 3 : 1;
+    const T *dfirst = adjoint ? Uinv : Linv, *dsecond = adjoint ? Linv : Uinv;
     for (int64_t g = 0; g < nrhs; g += 16) {
         const int nr = static_cast<int>((nrhs - g) < 16 ? (nrhs - g) : 16);
-        HIP_TRY(trsv_full<T>(first, lu, ld, n, Y + g, X + g, nrhs, nr, f->wsync, ++f->epoch, s));
-        HIP_TRY(trsv_full<T>(second, lu, ld, n, X + g, Y + g, nrhs, nr, f->wsync, ++f->epoch, s));
+        HIP_TRY(trsv_full<T>(first, lu, ld, n, dfirst, Y + g, X + g, nrhs, nr, f->wsync, s));
+        HIP_TRY(trsv_full<T>(second, lu, ld, n, dsecond, X + g, Y + g, nrhs, nr, f->wsync, s));
     }
     return hipSuccess;
 }

@@ -29,8 +29,7 @@
 namespace rmge {
 namespace {
 
-constexpr int kSub = 32;        // diagonal sub-blocks that are inverted explicitly
-constexpr int kInvLdDev = kMaxBlock;
+constexpr int kSub = 32;  // diagonal sub-blocks that are inverted explicitly
 
 template <typename T>
 __device__ inline bool is_bad(T p) {
@@ -193,16 +192,23 @@ __global__ __launch_bounds__(256) void k_leaf_lu(T *a, int64_t lda, int b, int64
     }
 }
 
-// Inverses of the 32 x 32 diagonal sub-blocks of a factored pivot block (the
-// off-diagonal coupling is applied later by blocked substitution, so only
-// these small inverses are formed).  Wave w < nsub inverts U's sub-block w,
-// wave nsub + w the unit-lower L's; lane c computes column c by substitution.
+// Inverses of the 32 x 32 diagonal sub-blocks of factored diagonal blocks
+// (the off-diagonal coupling is applied by blocked substitution, so only these
+// small inverses are formed).  Workgroup g covers rows 128 g .. 128 g + 127 of
+// the b x b block at `a`; wave w < nsub inverts U's sub-block w, wave nsub + w
+// the unit-lower L's; lane c computes column c by substitution.  Compact
+// output: row 32 q + i of Linv / Uinv holds row i of sub-block q's inverse.
 template <typename T>
 __global__ __launch_bounds__(512) void k_diag_inv(const T *a, int64_t lda, int b, T *Linv, T *Uinv,
-                                                  int64_t ldw, const DevStatus *st) {
+                                                  const DevStatus *st) {
     __shared__ T dblk[4][kSub][kSub + 1];
     if (st->code != 0) return;
     __builtin_amdgcn_s_setprio(3);
+    const int64_t g0 = static_cast<int64_t>(blockIdx.x) * 4 * kSub;
+    a += g0 * lda + g0;
+    Linv += g0 * kSub;
+    Uinv += g0 * kSub;
+    b = (b - g0) < 4 * kSub ? static_cast<int>(b - g0) : 4 * kSub;
     const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
     const int nsub = (b + kSub - 1) / kSub;
     for (int e = tid; e < nsub * kSub * kSub; e += blockDim.x) {
@@ -231,7 +237,7 @@ __global__ __launch_bounds__(512) void k_diag_inv(const T *a, int64_t lda, int b
         }
 #pragma unroll
         for (int i = 0; i < kSub; ++i)
-            if (i < sbq) Uinv[static_cast<int64_t>(q0 + i) * ldw + q0 + c] = x[i];
+            if (i < sbq) Uinv[static_cast<int64_t>(q0 + i) * kSub + c] = x[i];
     } else {
         // column c of L^{-1}: x_c = 1, x_i = -sum_{k=c..i-1} l_ik x_k
 #pragma unroll
@@ -244,13 +250,13 @@ __global__ __launch_bounds__(512) void k_diag_inv(const T *a, int64_t lda, int b
         }
 #pragma unroll
         for (int i = 0; i < kSub; ++i)
-            if (i < sbq) Linv[static_cast<int64_t>(q0 + i) * ldw + q0 + c] = x[i];
+            if (i < sbq) Linv[static_cast<int64_t>(q0 + i) * kSub + c] = x[i];
     }
 }
 
 // Blocked substitution on the matrix cores.  The pivot block's factors sit
 // packed at `lu` (ld, width b <= 256); Dinv holds the inverses of their
-// 32 x 32 diagonal sub-blocks (ld kInvLdDev).  One workgroup owns a 32-wide
+// 32 x 32 diagonal sub-blocks (compact: row 32 q + i, 32 columns).  One workgroup owns a 32-wide
 // strip of the panel and keeps it in MFMA accumulators, 16 x 16 tiles dealt
 // round-robin to its four waves.  Per diagonal sub-block i the two tiles of
 // rows i are published to LDS, multiplied by the sub-block inverse, published
@@ -293,8 +299,7 @@ __global__ __launch_bounds__(256, 2) void k_trsm_left(const T *lu, int64_t ld, i
         const int sb = (b - i0) < kSub ? (b - i0) : kSub;
         for (int e = tid; e < kSub * kSub; e += 256) {
             const int r = e / kSub, k = e % kSub;
-            Ds[r][k] = (r < sb && k < sb) ? Dinv[(i0 + r) * static_cast<int64_t>(kInvLdDev) + i0 + k]
-                                         : T(0);
+            Ds[r][k] = (r < sb && k < sb) ? Dinv[(i0 + r) * static_cast<int64_t>(kSub) + k] : T(0);
         }
 #pragma unroll
         for (int u = 0; u < 4; ++u) {
@@ -399,8 +404,7 @@ __global__ __launch_bounds__(256, 2) void k_trsm_right(const T *lu, int64_t ld, 
         const int sb = (b - j0) < kSub ? (b - j0) : kSub;
         for (int e = tid; e < kSub * kSub; e += 256) {
             const int k = e / kSub, m = e % kSub;
-            Ds[k][m] = (k < sb && m < sb) ? Dinv[(j0 + k) * static_cast<int64_t>(kInvLdDev) + j0 + m]
-                                         : T(0);
+            Ds[k][m] = (k < sb && m < sb) ? Dinv[(j0 + k) * static_cast<int64_t>(kSub) + m] : T(0);
         }
 #pragma unroll
         for (int u = 0; u < 4; ++u) {
@@ -618,8 +622,8 @@ int grid_for(int64_t total, int threads) {
 }  // namespace
 
 template <typename T>
-hipError_t leaf_lu(T *a, int64_t lda, int b, T *Linv, T *Uinv, int64_t ldw, int64_t k0,
-                   DevStatus *st, int *piv, hipStream_t s) {
+hipError_t leaf_lu(T *a, int64_t lda, int b, T *Linv, T *Uinv, int64_t k0, DevStatus *st, int *piv,
+                   hipStream_t s) {
     if (b < 1 || b > kLeaf) return hipErrorInvalidValue;
     if (piv)
         hipLaunchKernelGGL((k_leaf_lu<T, true>), dim3(1), dim3(256), 0, s, a, lda, b, k0, st, piv);
@@ -628,7 +632,18 @@ hipError_t leaf_lu(T *a, int64_t lda, int b, T *Linv, T *Uinv, int64_t ldw, int6
                            piv);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_diag_inv<T>, dim3(1), dim3(512), 0, s, a, lda, b, Linv, Uinv, ldw, st);
+    hipLaunchKernelGGL(k_diag_inv<T>, dim3(1), dim3(512), 0, s, a, lda, b, Linv, Uinv, st);
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t diag_inverses(const T *a, int64_t lda, int64_t n, T *Linv, T *Uinv, const DevStatus *st,
+                         hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+    if (n > (int64_t(1) << 30)) return hipErrorInvalidValue;
+    const unsigned grid = static_cast<unsigned>((n + 4 * kSub - 1) / (4 * kSub));
+    hipLaunchKernelGGL(k_diag_inv<T>, dim3(grid), dim3(512), 0, s, a, lda, static_cast<int>(n),
+                       Linv, Uinv, st);
     return hipGetLastError();
 }
 
@@ -713,10 +728,14 @@ hipError_t abs_max(const T *m, int64_t ld, int64_t n, double *out3, hipStream_t 
     return hipGetLastError();
 }
 
-template hipError_t leaf_lu<double>(double *, int64_t, int, double *, double *, int64_t, int64_t,
+template hipError_t leaf_lu<double>(double *, int64_t, int, double *, double *, int64_t,
                                     DevStatus *, int *, hipStream_t);
-template hipError_t leaf_lu<float>(float *, int64_t, int, float *, float *, int64_t, int64_t,
-                                   DevStatus *, int *, hipStream_t);
+template hipError_t leaf_lu<float>(float *, int64_t, int, float *, float *, int64_t, DevStatus *,
+                                   int *, hipStream_t);
+template hipError_t diag_inverses<double>(const double *, int64_t, int64_t, double *, double *,
+                                          const DevStatus *, hipStream_t);
+template hipError_t diag_inverses<float>(const float *, int64_t, int64_t, float *, float *,
+                                         const DevStatus *, hipStream_t);
 template hipError_t trsm<double>(int, const double *, int64_t, int, double *, int64_t, int64_t,
                                  const double *, const int *, hipStream_t, const int *, int64_t);
 template hipError_t trsm<float>(int, const float *, int64_t, int, float *, int64_t, int64_t,

@@ -48,17 +48,24 @@ hipError_t gemm_f32_a64(int shape, int64_t M, int64_t N, int64_t K, float alpha,
 // ----------------------------------------------------------------- lu.hip
 // Factor the b x b diagonal block at `a` (b <= kLeaf) in place and write the
 // inverses of the 32 x 32 diagonal sub-blocks of its unit-lower and upper
-// factors into the matching diagonal positions of Linv and Uinv (ldw).
+// factors into Linv and Uinv (compact: row 32 q + i holds row i of sub-block
+// q's inverse, 32 columns).
 // k0 = global index of the block's first pivot (the block sits at rows and
 // columns k0 ..).  piv == nullptr: GENP.  Otherwise partial pivoting inside
 // the block: rows are stored in pivot order and piv[k0 + t] receives the
 // global row index that now sits at k0 + t.
 template <typename T>
-hipError_t leaf_lu(T *a, int64_t lda, int b, T *Linv, T *Uinv, int64_t ldw, int64_t k0,
-                   DevStatus *st, int *piv, hipStream_t s);
+hipError_t leaf_lu(T *a, int64_t lda, int b, T *Linv, T *Uinv, int64_t k0, DevStatus *st, int *piv,
+                   hipStream_t s);
+// Inverses of all aligned 32 x 32 diagonal sub-blocks of the n x n packed
+// factors at `a` (compact: row 32 q + i of Linv / Uinv holds row i of
+// sub-block q's inverse); skipped if the factorization broke down.
+template <typename T>
+hipError_t diag_inverses(const T *a, int64_t lda, int64_t n, T *Linv, T *Uinv, const DevStatus *st,
+                         hipStream_t s);
 // In-place triangular solves with the factored pivot block at `lu` (width
-// b <= kMaxBlock), by blocked substitution with the 32 x 32 diagonal inverses
-// in Dinv (ld kMaxBlock):
+// b <= kMaxBlock), by blocked substitution with the compact 32 x 32 diagonal
+// inverses in Dinv:
 //   side 0: C (b x count, ldc) <- L^{-1} P C    (Dinv = Linv; row t of P C is
 //           row rowsrc[t] - rowbase of C, or row t when rowsrc is null)
 //   side 1: C (count x b, ldc) <- C U^{-1}      (Dinv = Uinv; rowsrc must be null)
@@ -93,24 +100,19 @@ template <typename T>
 hipError_t abs_max(const T *m, int64_t ld, int64_t n, double *out3, hipStream_t s);
 
 // -------------------------------------------------------------- solve.hip
-// One block step of a triangular solve with the packed factors LU (ld):
+// A whole triangular solve T X = B with the packed factors LU (ld) in one
+// launch:
 //   mode 0: L y = b (unit lower, forward)      mode 1: U y = b (upper, backward)
 //   mode 2: U^T y = b (lower, forward)         mode 3: L^T y = b (unit upper, backward)
-// Solves diagonal block `blk` (rows blk*64 ..) of Y into X and updates the
-// not-yet-solved rows of Y.
-// Y, X: n x ldyx; this call handles nr <= 16 right-hand sides starting at Y, X.
+// Blocks of 64 rows are taken in dependency order by a ticket counter.
+// Dinv: compact inverses of the aligned 32 x 32 diagonal sub-blocks of L
+// (modes 0, 3) or U (modes 1, 2), from diag_inverses, with at least
+// round_up(n, 64) rows.  X and B are n x ldx (nr <= 16 columns used; X may not
+// alias B).  sync: device ints, [0] ticket counter, [1] error word (set to 1 if
+// a wait timed out; the caller clears it).
 template <typename T>
-hipError_t trsv_step(int mode, const T *LU, int64_t ld, int64_t n, int64_t blk, T *Y, T *X,
-                     int64_t ldyx, int nr, const int *abort, hipStream_t s);
-// The whole solve T X = B in one launch (same modes), blocks of 64 rows taken
-// in dependency order by a ticket counter.  X and B are n x ldx (nr <= 16
-// columns used; X may alias B).  sync: device ints, [0] ticket counter,
-// [1] error word (set to 1 if a wait timed out; the caller clears it),
-// [2 ..] one flag per 64-row block; `epoch` must differ from every value the
-// flags hold (the caller increments it per launch).
-template <typename T>
-hipError_t trsv_full(int mode, const T *LU, int64_t ld, int64_t n, const T *B, T *X, int64_t ldx,
-                     int nr, int *sync, int epoch, hipStream_t s);
+hipError_t trsv_full(int mode, const T *LU, int64_t ld, int64_t n, const T *Dinv, const T *B,
+                     T *X, int64_t ldx, int nr, int *sync, hipStream_t s);
 // y = beta * y + alpha * M x  (rows of M; FP64 accumulation).  M: rows x cols (ldm),
 // x: cols x nrhs (ldx), y: rows x nrhs (ldy).
 template <typename TM, typename TX, typename TY>

@@ -5,139 +5,83 @@
 // L^{-T} U^{-T} H^T w.  Refinement (Section 8.1) needs r = b - A x in FP64.
 // Every kernel here streams a matrix once and is bound by HBM bandwidth.
 //
-// Triangular solves are blocked by 64 rows: each 64 x 64 diagonal block is
-// solved in registers by one wave (lane = row, wavefront shuffles broadcast
-// each solved value) and the coupling tiles are staged through LDS so that
-// their global reads are row segments (coalesced) for plain and transposed
-// factors alike.  k_trsv_persistent does a whole solve in one launch;
-// k_trsv_step does one diagonal block per launch (kept for reference use).
+// Triangular solves are blocked by 64 rows and run as one persistent launch
+// (k_trsv); coupling tiles are read as row segments (coalesced) for plain and
+// transposed factors alike.  Their critical path is the chain of 64-row
+// blocks, not HBM bandwidth.
 #include "rmge_impl.h"
 
 namespace rmge {
 namespace {
 
-constexpr int SB = 64;
+constexpr int SB = 64;  // rows per block of the persistent solve
+constexpr int SW = 32;  // its two diagonal sub-blocks, applied through their inverses
 
-template <typename T, int MODE, int NR>
-__global__ __launch_bounds__(256) void k_trsv_step(const T *LU, int64_t ld, int64_t n, int64_t blk,
-                                                   T *Y, T *X, int64_t ldyx, int nr,
-                                                   const int *abort) {
-    __shared__ T Ds[SB][SB + 1];
-    __shared__ T Ts[SB][SB + 1];
-    __shared__ T xs[SB][NR];
-    if (abort != nullptr && *abort != 0) return;
-    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    const int64_t I0 = blk * SB;
-    const int bI = static_cast<int>((n - I0) < SB ? (n - I0) : SB);
-
-    for (int e = tid; e < SB * SB; e += 256) {
-        const int i = e / SB, j = e % SB;
-        Ds[i][j] = (i < bI && j < bI) ? LU[(I0 + i) * ld + I0 + j] : T(0);
-    }
-    __syncthreads();
-
-    if (wave == 0) {
-        T v[NR];
-#pragma unroll
-        for (int r = 0; r < NR; ++r)
-            v[r] = (lane < bI && r < nr) ? Y[(I0 + lane) * ldyx + r] : T(0);
-        if (MODE == 0) {  // L: unit lower, forward
-            for (int j = 0; j < bI; ++j) {
-                const T l = Ds[lane][j];
-#pragma unroll
-                for (int r = 0; r < NR; ++r) {
-                    const T t = __shfl(v[r], j);
-                    if (lane > j) v[r] -= l * t;
-                }
-            }
-        } else if (MODE == 1) {  // U: upper, backward
-            for (int j = bI - 1; j >= 0; --j) {
-                const T d = Ds[j][j], u = Ds[lane][j];
-#pragma unroll
-                for (int r = 0; r < NR; ++r) {
-                    if (lane == j) v[r] = v[r] / d;
-                    const T t = __shfl(v[r], j);
-                    if (lane < j) v[r] -= u * t;
-                }
-            }
-        } else if (MODE == 2) {  // U^T: lower, forward
-            for (int j = 0; j < bI; ++j) {
-                const T d = Ds[j][j], u = Ds[j][lane];
-#pragma unroll
-                for (int r = 0; r < NR; ++r) {
-                    if (lane == j) v[r] = v[r] / d;
-                    const T t = __shfl(v[r], j);
-                    if (lane > j) v[r] -= u * t;
-                }
-            }
-        } else {  // L^T: unit upper, backward
-            for (int j = bI - 1; j >= 0; --j) {
-                const T l = Ds[j][lane];
-#pragma unroll
-                for (int r = 0; r < NR; ++r) {
-                    const T t = __shfl(v[r], j);
-                    if (lane < j) v[r] -= l * t;
-                }
-            }
-        }
-#pragma unroll
-        for (int r = 0; r < NR; ++r) {
-            xs[lane][r] = (lane < bI) ? v[r] : T(0);
-            if (blockIdx.x == 0 && lane < bI && r < nr) X[(I0 + lane) * ldyx + r] = v[r];
-        }
-    }
-    __syncthreads();
-
-    const bool below = (MODE == 0 || MODE == 2);
-    const int64_t R0 = below ? I0 + bI + static_cast<int64_t>(blockIdx.x) * SB
-                             : static_cast<int64_t>(blockIdx.x) * SB;
-    const int64_t rend = below ? n : I0;
-    if (R0 >= rend) return;
-    const int rows = static_cast<int>((rend - R0) < SB ? (rend - R0) : SB);
-    if (MODE == 0 || MODE == 1) {
-        for (int e = tid; e < SB * SB; e += 256) {
-            const int r = e / SB, j = e % SB;
-            Ts[r][j] = (r < rows && j < bI) ? LU[(R0 + r) * ld + I0 + j] : T(0);
-        }
-    } else {
-        for (int e = tid; e < SB * SB; e += 256) {
-            const int j = e / SB, r = e % SB;
-            Ts[r][j] = (r < rows && j < bI) ? LU[(I0 + j) * ld + R0 + r] : T(0);
-        }
-    }
-    __syncthreads();
-    const int r = tid >> 2, q = tid & 3;
-    if (r < rows) {
-        for (int c = q; c < nr; c += 4) {
-            T acc = T(0);
-#pragma unroll 8
-            for (int j = 0; j < SB; ++j) acc += Ts[r][j] * xs[j][c];
-            Y[(R0 + r) * ldyx + c] -= acc;
-        }
-    }
-}
-
-// Whole triangular solve in one launch.  Workgroups take block rows in the
+// Whole triangular solve in one launch.  Workgroups take 64-row blocks in the
 // order they start (a ticket from an atomic counter), so every block a
-// workgroup waits on belongs to a workgroup that is already running; block I
-// accumulates the coupling T_IJ y_J of every finished block J (waiting on
-// J's flag), then solves its diagonal block and publishes y_I with a release
-// fence and its flag.  A wait gives up after kSpinLimit polls and records an
-// error instead of hanging; the caller checks it.
+// workgroup waits on belongs to a workgroup that is already running.  Block I
+// accumulates the coupling T_IJ y_J of every block J before it, then solves
+// its diagonal block through the inverses of its two 32 x 32 sub-blocks
+// (x_a = D_a^{-1} s_a; s_b -= C x_a; x_b = D_b^{-1} s_b), three small parallel
+// products instead of 64 dependent steps.
+//
+// Hand-off without flags: the output is pre-filled with a signalling-NaN
+// mark that arithmetic never produces; a finished block publishes its values
+// with agent-scope atomic stores, and a waiting block polls the values it
+// needs with agent-scope atomic loads until none is the mark.  The data is the
+// flag, so no fence sits on the chain from one block to the next.  Coupling
+// tiles are prefetched one block ahead into registers.  A wait gives up after
+// kSpinLimit polls and records an error instead of hanging; the caller
+// checks it.
 constexpr int kSpinLimit = 1 << 22;
 
+template <typename T>
+struct Mark;
+template <>
+struct Mark<double> {
+    using U = unsigned long long;
+    static constexpr U bits = 0x7FF4D1A6C0DE0001ull;
+};
+template <>
+struct Mark<float> {
+    using U = unsigned int;
+    static constexpr U bits = 0x7FA5C0DEu;
+};
+
+template <typename T>
+__device__ inline T poll_value(const T *p, bool *ready) {
+    using U = typename Mark<T>::U;
+    const U b = __hip_atomic_load(reinterpret_cast<U *>(const_cast<T *>(p)), __ATOMIC_RELAXED,
+                                  __HIP_MEMORY_SCOPE_AGENT);
+    *ready = (b != Mark<T>::bits);
+    return __builtin_bit_cast(T, b);
+}
+
+template <typename T>
+__device__ inline void publish_value(T *p, T v) {
+    using U = typename Mark<T>::U;
+    __hip_atomic_store(reinterpret_cast<U *>(p), __builtin_bit_cast(U, v), __ATOMIC_RELAXED,
+                       __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// modes: 0 L y = b (unit lower, forward)    1 U y = b (upper, backward)
+//        2 U^T y = b (forward)              3 L^T y = b (unit upper, backward)
+// Dinv: the compact inverses of the 32 x 32 diagonal sub-blocks of the factor
+// the mode uses (L for 0 and 3, U for 1 and 2): row 32 q + i holds row i of
+// sub-block q's inverse.
 template <typename T, int MODE, int NR>
-__global__ __launch_bounds__(256) void k_trsv_persistent(const T *LU, int64_t ld, int64_t n,
-                                                         const T *B, T *X, int64_t ldx, int nr,
-                                                         int *counter, int *flags, int epoch,
-                                                         int *err) {
-    __shared__ T Ds[SB][SB + 1];  // diagonal block
-    __shared__ T Ts[SB][SB + 1];  // coupling tile T_IJ
-    __shared__ T ys[SB][NR];
+__global__ __launch_bounds__(256) void k_trsv(const T *LU, int64_t ld, int64_t n, const T *Dinv,
+                                              const T *B, T *X, int64_t ldx, int nr, int *sync) {
+    constexpr bool forward = (MODE == 0 || MODE == 2);
+    constexpr bool transposed = (MODE == 2 || MODE == 3);
+    __shared__ T Ts[transposed ? SB : 1][SB + 1];  // transposed modes stage the tile here
+    __shared__ T Dd[2][SW][SW + 1];                 // sub-block inverses, as applied
+    __shared__ T Cp[SW][SW + 1];                    // first-solved sub-block -> second
+    __shared__ double ys[SB][NR];
+    __shared__ double xs[SB][NR];
     __shared__ int s_ticket, s_fail;
+    int *counter = sync, *err = sync + 1;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    const bool forward = (MODE == 0 || MODE == 2);
-    const bool transposed = (MODE == 2 || MODE == 3);
     if (tid == 0) {
         s_ticket = atomicAdd(counter, 1);
         s_fail = 0;
@@ -147,12 +91,24 @@ __global__ __launch_bounds__(256) void k_trsv_persistent(const T *LU, int64_t ld
     const int I = forward ? s_ticket : nblk - 1 - s_ticket;
     const int64_t I0 = static_cast<int64_t>(I) * SB;
     const int bI = static_cast<int>((n - I0) < SB ? (n - I0) : SB);
-    const int r = tid >> 2, q = tid & 3;  // row r of the block, column quarter q
+
     // Everything that does not depend on other blocks is loaded before waiting.
-    for (int e = tid; e < SB * SB; e += 256) {
-        const int i = e / SB, j = e % SB;
-        Ds[i][j] = (i < bI && j < bI) ? LU[(I0 + i) * ld + I0 + j] : T(0);
+    for (int e = tid; e < 2 * SW * SW; e += 256) {
+        const int sb = e / (SW * SW), i = (e / SW) % SW, j = e % SW;
+        const bool in = (SW * sb + i < bI) && (SW * sb + j < bI);
+        const int64_t row = I0 + SW * sb + (transposed ? j : i);
+        Dd[sb][i][j] = in ? Dinv[row * SW + (transposed ? i : j)] : T(0);
     }
+    for (int e = tid; e < SW * SW; e += 256) {
+        const int i = e / SW, j = e % SW;
+        int rr, cc;  // block-local position in the packed factors
+        if (MODE == 0) { rr = SW + i; cc = j; }       // L_ba
+        else if (MODE == 1) { rr = i; cc = SW + j; }  // U_ab
+        else if (MODE == 2) { rr = j; cc = SW + i; }  // (U^T)_ba = U_ab^T
+        else { rr = SW + j; cc = i; }                 // (L^T)_ab = L_ba^T
+        Cp[i][j] = (rr < bI && cc < bI) ? LU[(I0 + rr) * ld + I0 + cc] : T(0);
+    }
+    const int r = tid >> 2, q = tid & 3;  // tile row r, columns 16 q .. 16 q + 15
     T bval[NR];
 #pragma unroll
     for (int c = 0; c < NR; ++c)
@@ -160,46 +116,70 @@ __global__ __launch_bounds__(256) void k_trsv_persistent(const T *LU, int64_t ld
     double acc[NR];
 #pragma unroll
     for (int c = 0; c < NR; ++c) acc[c] = 0.0;
-    const int jfirst = forward ? 0 : nblk - 1, jstep = forward ? 1 : -1;
-    for (int J = jfirst; J != I; J += jstep) {
+
+    // T_IJ: rows of block I, columns of block J.  Plain modes: thread (r, q)
+    // loads and keeps its own 16 elements.  Transposed modes: it loads 16
+    // consecutive elements of factor row J0 + r (tile column r), staged in LDS.
+    auto load_tile = [&](int J, T (&dst)[16]) {
         const int64_t J0 = static_cast<int64_t>(J) * SB;
         const int bJ = static_cast<int>((n - J0) < SB ? (n - J0) : SB);
-        // the coupling tile T_IJ (rows of this block, columns of block J)
-        if (!transposed) {
-            for (int e = tid; e < SB * SB; e += 256) {
-                const int rr = e / SB, cc = e % SB;
-                Ts[rr][cc] = (rr < bI && cc < bJ) ? LU[(I0 + rr) * ld + J0 + cc] : T(0);
-            }
-        } else {
-            for (int e = tid; e < SB * SB; e += 256) {
-                const int cc = e / SB, rr = e % SB;  // T[r][c] = factor[J0 + c][I0 + r]
-                Ts[rr][cc] = (rr < bI && cc < bJ) ? LU[(J0 + cc) * ld + I0 + rr] : T(0);
-            }
+#pragma unroll
+        for (int i = 0; i < 16; ++i) {
+            const int k = 16 * q + i;
+            if (!transposed)
+                dst[i] = (r < bI && k < bJ) ? LU[(I0 + r) * ld + J0 + k] : T(0);
+            else
+                dst[i] = (r < bJ && k < bI) ? LU[(J0 + r) * ld + I0 + k] : T(0);
         }
-        if (tid == 0) {
+    };
+    const int jfirst = forward ? 0 : nblk - 1, jstep = forward ? 1 : -1;
+    T cur[16], nxt[16];
+    if (I != jfirst) load_tile(jfirst, nxt);
+    for (int J = jfirst; J != I; J += jstep) {
+#pragma unroll
+        for (int i = 0; i < 16; ++i) cur[i] = nxt[i];
+        if (J + jstep != I) load_tile(J + jstep, nxt);
+        if (transposed) {
+#pragma unroll
+            for (int i = 0; i < 16; ++i) Ts[16 * q + i][r] = cur[i];
+        }
+        const int64_t J0 = static_cast<int64_t>(J) * SB;
+        const int bJ = static_cast<int>((n - J0) < SB ? (n - J0) : SB);
+        if (wave == 0) {
+            T v[NR];
             int spins = 0;
-            while (__hip_atomic_load(flags + J, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != epoch) {
-                if (++spins > kSpinLimit ||
-                    __hip_atomic_load(err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0) {
-                    s_fail = 1;
+            while (true) {
+                bool ready = true;
+#pragma unroll
+                for (int c = 0; c < NR; ++c) {
+                    v[c] = T(0);
+                    if (lane < bJ && c < nr) {
+                        bool ok;
+                        v[c] = poll_value(X + (J0 + lane) * ldx + c, &ok);
+                        ready = ready && ok;
+                    }
+                }
+                if (__all(ready)) break;
+                const bool give_up =
+                    (++spins > kSpinLimit) ||
+                    __hip_atomic_load(err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0;
+                if (__any(give_up)) {
+                    if (lane == 0) s_fail = 1;
                     break;
                 }
                 __builtin_amdgcn_s_sleep(1);
             }
+#pragma unroll
+            for (int c = 0; c < NR; ++c) ys[lane][c] = static_cast<double>(v[c]);
         }
         __syncthreads();
         if (s_fail) break;
-        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
-        for (int e = tid; e < SB * NR; e += 256) {
-            const int rr = e / NR, c = e % NR;
-            ys[rr][c] = (rr < bJ && c < nr) ? X[(J0 + rr) * ldx + c] : T(0);
-        }
-        __syncthreads();
-#pragma unroll 4
-        for (int k = 16 * q; k < 16 * q + 16; ++k) {
-            const double t = static_cast<double>(Ts[r][k]);
 #pragma unroll
-            for (int c = 0; c < NR; ++c) acc[c] += t * static_cast<double>(ys[k][c]);
+        for (int i = 0; i < 16; ++i) {
+            const int k = 16 * q + i;
+            const double t = static_cast<double>(transposed ? Ts[r][k] : cur[i]);
+#pragma unroll
+            for (int c = 0; c < NR; ++c) acc[c] += t * ys[k][c];
         }
         __syncthreads();
     }
@@ -207,7 +187,7 @@ __global__ __launch_bounds__(256) void k_trsv_persistent(const T *LU, int64_t ld
         if (tid == 0) atomicExch(err, 1);  // blocks waiting on this one see it and stop
         return;
     }
-    // reduce the four column quarters of each row, form the right-hand side
+    // s = b_I - sum_J T_IJ y_J: reduce the four column quarters of each row
 #pragma unroll
     for (int c = 0; c < NR; ++c) {
         acc[c] += __shfl_xor(acc[c], 1);
@@ -216,82 +196,96 @@ __global__ __launch_bounds__(256) void k_trsv_persistent(const T *LU, int64_t ld
     if (q == 0) {
 #pragma unroll
         for (int c = 0; c < NR; ++c)
-            ys[r][c] = static_cast<T>(static_cast<double>(bval[c]) - acc[c]);
+            ys[r][c] = (r < bI) ? static_cast<double>(bval[c]) - acc[c] : 0.0;
     }
     __syncthreads();
-    if (wave == 0) {
-        T v[NR];
+    // diagonal block: first-solved sub-block f, then the other, g
+    const int f = forward ? 0 : 1, g = 1 - f;
+    const int i = tid >> 3, jq = tid & 7;  // row i of a 32-block, columns 4 jq .. 4 jq + 3
+    {
+        double p[NR];
 #pragma unroll
-        for (int c = 0; c < NR; ++c) v[c] = ys[lane][c];
-        if (MODE == 0) {
-            for (int j = 0; j < bI; ++j) {
-                const T l = Ds[lane][j];
+        for (int c = 0; c < NR; ++c) p[c] = 0.0;
 #pragma unroll
-                for (int c = 0; c < NR; ++c) {
-                    const T t = __shfl(v[c], j);
-                    if (lane > j) v[c] -= l * t;
-                }
-            }
-        } else if (MODE == 1) {
-            for (int j = bI - 1; j >= 0; --j) {
-                const T d = Ds[j][j], u = Ds[lane][j];
+        for (int u = 0; u < 4; ++u) {
+            const int j = 4 * jq + u;
+            const double d = static_cast<double>(Dd[f][i][j]);
 #pragma unroll
-                for (int c = 0; c < NR; ++c) {
-                    if (lane == j) v[c] = v[c] / d;
-                    const T t = __shfl(v[c], j);
-                    if (lane < j) v[c] -= u * t;
-                }
-            }
-        } else if (MODE == 2) {
-            for (int j = 0; j < bI; ++j) {
-                const T d = Ds[j][j], u = Ds[j][lane];
-#pragma unroll
-                for (int c = 0; c < NR; ++c) {
-                    if (lane == j) v[c] = v[c] / d;
-                    const T t = __shfl(v[c], j);
-                    if (lane > j) v[c] -= u * t;
-                }
-            }
-        } else {
-            for (int j = bI - 1; j >= 0; --j) {
-                const T l = Ds[j][lane];
-#pragma unroll
-                for (int c = 0; c < NR; ++c) {
-                    const T t = __shfl(v[c], j);
-                    if (lane < j) v[c] -= l * t;
-                }
-            }
+            for (int c = 0; c < NR; ++c) p[c] += d * ys[SW * f + j][c];
         }
-        if (lane < bI) {
 #pragma unroll
-            for (int c = 0; c < NR; ++c)
-                if (c < nr) X[(I0 + lane) * ldx + c] = v[c];
+        for (int c = 0; c < NR; ++c) {
+            p[c] += __shfl_xor(p[c], 1);
+            p[c] += __shfl_xor(p[c], 2);
+            p[c] += __shfl_xor(p[c], 4);
         }
-        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
-        if (lane == 0) __hip_atomic_store(flags + I, epoch, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        if (jq == 0) {
+#pragma unroll
+            for (int c = 0; c < NR; ++c) xs[SW * f + i][c] = p[c];
+        }
+    }
+    __syncthreads();
+    {
+        double p[NR];
+#pragma unroll
+        for (int c = 0; c < NR; ++c) p[c] = 0.0;
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const int j = 4 * jq + u;
+            const double cv = static_cast<double>(Cp[i][j]);
+#pragma unroll
+            for (int c = 0; c < NR; ++c) p[c] += cv * xs[SW * f + j][c];
+        }
+#pragma unroll
+        for (int c = 0; c < NR; ++c) {
+            p[c] += __shfl_xor(p[c], 1);
+            p[c] += __shfl_xor(p[c], 2);
+            p[c] += __shfl_xor(p[c], 4);
+        }
+        if (jq == 0) {
+#pragma unroll
+            for (int c = 0; c < NR; ++c) ys[SW * g + i][c] -= p[c];
+        }
+    }
+    __syncthreads();
+    {
+        double p[NR];
+#pragma unroll
+        for (int c = 0; c < NR; ++c) p[c] = 0.0;
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const int j = 4 * jq + u;
+            const double d = static_cast<double>(Dd[g][i][j]);
+#pragma unroll
+            for (int c = 0; c < NR; ++c) p[c] += d * ys[SW * g + j][c];
+        }
+#pragma unroll
+        for (int c = 0; c < NR; ++c) {
+            p[c] += __shfl_xor(p[c], 1);
+            p[c] += __shfl_xor(p[c], 2);
+            p[c] += __shfl_xor(p[c], 4);
+        }
+        if (jq == 0) {
+#pragma unroll
+            for (int c = 0; c < NR; ++c) xs[SW * g + i][c] = p[c];
+        }
+    }
+    __syncthreads();
+    if (tid < bI) {
+#pragma unroll
+        for (int c = 0; c < NR; ++c)
+            if (c < nr) publish_value(X + (I0 + tid) * ldx + c, static_cast<T>(xs[tid][c]));
     }
 }
 
-__global__ void k_trsv_reset(int *counter) { *counter = 0; }
-
-template <typename T, int MODE>
-hipError_t trsv_launch(const T *LU, int64_t ld, int64_t n, int64_t blk, T *Y, T *X, int64_t ldyx,
-                       int nr, const int *abort, hipStream_t s) {
-    const int64_t I0 = blk * SB;
-    const int64_t bI = (n - I0) < SB ? (n - I0) : SB;
-    const int64_t span = (MODE == 0 || MODE == 2) ? (n - I0 - bI) : I0;
-    int64_t grid = (span + SB - 1) / SB;
-    if (grid < 1) grid = 1;
-    if (nr <= 1)
-        hipLaunchKernelGGL((k_trsv_step<T, MODE, 1>), dim3(static_cast<unsigned>(grid)), dim3(256),
-                           0, s, LU, ld, n, blk, Y, X, ldyx, nr, abort);
-    else if (nr <= 4)
-        hipLaunchKernelGGL((k_trsv_step<T, MODE, 4>), dim3(static_cast<unsigned>(grid)), dim3(256),
-                           0, s, LU, ld, n, blk, Y, X, ldyx, nr, abort);
-    else
-        hipLaunchKernelGGL((k_trsv_step<T, MODE, 16>), dim3(static_cast<unsigned>(grid)), dim3(256),
-                           0, s, LU, ld, n, blk, Y, X, ldyx, nr, abort);
-    return hipGetLastError();
+// Before a solve: reset the ticket counter and mark every output entry unsolved.
+template <typename T>
+__global__ void k_trsv_prep(T *X, int64_t ldx, int64_t n, int nr, int *sync) {
+    if (blockIdx.x == 0 && threadIdx.x == 0) sync[0] = 0;
+    const int64_t total = n * nr;
+    for (int64_t e = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x; e < total;
+         e += static_cast<int64_t>(gridDim.x) * blockDim.x)
+        X[(e / nr) * ldx + e % nr] = __builtin_bit_cast(T, Mark<T>::bits);
 }
 
 // y = beta y + alpha M x, FP64 accumulation; one wave per two rows.
@@ -460,47 +454,34 @@ int grid_for(int64_t total, int threads) {
 }  // namespace
 
 template <typename T, int MODE>
-hipError_t trsv_full_launch(const T *LU, int64_t ld, int64_t n, const T *B, T *X, int64_t ldx,
-                            int nr, int *sync, int epoch, hipStream_t s) {
+hipError_t trsv_full_launch(const T *LU, int64_t ld, int64_t n, const T *Dinv, const T *B, T *X,
+                            int64_t ldx, int nr, int *sync, hipStream_t s) {
     const int nblk = static_cast<int>((n + SB - 1) / SB);
-    hipLaunchKernelGGL(k_trsv_reset, dim3(1), dim3(1), 0, s, sync);
+    hipLaunchKernelGGL(k_trsv_prep<T>, dim3(grid_for(n * nr, 256)), dim3(256), 0, s, X, ldx, n, nr,
+                       sync);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    int *flags = sync + 2, *err = sync + 1;
     if (nr <= 1)
-        hipLaunchKernelGGL((k_trsv_persistent<T, MODE, 1>), dim3(nblk), dim3(256), 0, s, LU, ld, n,
-                           B, X, ldx, nr, sync, flags, epoch, err);
+        hipLaunchKernelGGL((k_trsv<T, MODE, 1>), dim3(nblk), dim3(256), 0, s, LU, ld, n, Dinv, B, X,
+                           ldx, nr, sync);
     else if (nr <= 4)
-        hipLaunchKernelGGL((k_trsv_persistent<T, MODE, 4>), dim3(nblk), dim3(256), 0, s, LU, ld, n,
-                           B, X, ldx, nr, sync, flags, epoch, err);
+        hipLaunchKernelGGL((k_trsv<T, MODE, 4>), dim3(nblk), dim3(256), 0, s, LU, ld, n, Dinv, B, X,
+                           ldx, nr, sync);
     else
-        hipLaunchKernelGGL((k_trsv_persistent<T, MODE, 16>), dim3(nblk), dim3(256), 0, s, LU, ld,
-                           n, B, X, ldx, nr, sync, flags, epoch, err);
+        hipLaunchKernelGGL((k_trsv<T, MODE, 16>), dim3(nblk), dim3(256), 0, s, LU, ld, n, Dinv, B,
+                           X, ldx, nr, sync);
     return hipGetLastError();
 }
 
 template <typename T>
-hipError_t trsv_full(int mode, const T *LU, int64_t ld, int64_t n, const T *B, T *X, int64_t ldx,
-                     int nr, int *sync, int epoch, hipStream_t s) {
-    if (nr < 1 || nr > 16 || n < 1) return hipErrorInvalidValue;
+hipError_t trsv_full(int mode, const T *LU, int64_t ld, int64_t n, const T *Dinv, const T *B,
+                     T *X, int64_t ldx, int nr, int *sync, hipStream_t s) {
+    if (nr < 1 || nr > 16 || n < 1 || B == X) return hipErrorInvalidValue;
     switch (mode) {
-    case 0: return trsv_full_launch<T, 0>(LU, ld, n, B, X, ldx, nr, sync, epoch, s);
-    case 1: return trsv_full_launch<T, 1>(LU, ld, n, B, X, ldx, nr, sync, epoch, s);
-    case 2: return trsv_full_launch<T, 2>(LU, ld, n, B, X, ldx, nr, sync, epoch, s);
-    case 3: return trsv_full_launch<T, 3>(LU, ld, n, B, X, ldx, nr, sync, epoch, s);
-    default: return hipErrorInvalidValue;
-    }
-}
-
-template <typename T>
-hipError_t trsv_step(int mode, const T *LU, int64_t ld, int64_t n, int64_t blk, T *Y, T *X,
-                     int64_t ldyx, int nr, const int *abort, hipStream_t s) {
-    if (nr < 1 || nr > 16 || blk * SB >= n) return hipErrorInvalidValue;
-    switch (mode) {
-    case 0: return trsv_launch<T, 0>(LU, ld, n, blk, Y, X, ldyx, nr, abort, s);
-    case 1: return trsv_launch<T, 1>(LU, ld, n, blk, Y, X, ldyx, nr, abort, s);
-    case 2: return trsv_launch<T, 2>(LU, ld, n, blk, Y, X, ldyx, nr, abort, s);
-    case 3: return trsv_launch<T, 3>(LU, ld, n, blk, Y, X, ldyx, nr, abort, s);
+    case 0: return trsv_full_launch<T, 0>(LU, ld, n, Dinv, B, X, ldx, nr, sync, s);
+    case 1: return trsv_full_launch<T, 1>(LU, ld, n, Dinv, B, X, ldx, nr, sync, s);
+    case 2: return trsv_full_launch<T, 2>(LU, ld, n, Dinv, B, X, ldx, nr, sync, s);
+    case 3: return trsv_full_launch<T, 3>(LU, ld, n, Dinv, B, X, ldx, nr, sync, s);
     default: return hipErrorInvalidValue;
     }
 }
@@ -580,13 +561,9 @@ hipError_t fill_f64(double *p, int64_t count, double value, hipStream_t s) {
 }
 
 template hipError_t trsv_full<double>(int, const double *, int64_t, int64_t, const double *,
-                                      double *, int64_t, int, int *, int, hipStream_t);
-template hipError_t trsv_full<float>(int, const float *, int64_t, int64_t, const float *, float *,
-                                     int64_t, int, int *, int, hipStream_t);
-template hipError_t trsv_step<double>(int, const double *, int64_t, int64_t, int64_t, double *,
-                                      double *, int64_t, int, const int *, hipStream_t);
-template hipError_t trsv_step<float>(int, const float *, int64_t, int64_t, int64_t, float *,
-                                     float *, int64_t, int, const int *, hipStream_t);
+                                      const double *, double *, int64_t, int, int *, hipStream_t);
+template hipError_t trsv_full<float>(int, const float *, int64_t, int64_t, const float *,
+                                     const float *, float *, int64_t, int, int *, hipStream_t);
 template hipError_t gemv_n<double, double, double>(int64_t, int64_t, double, const double *,
                                                    int64_t, const double *, int64_t, double,
                                                    double *, int64_t, int, hipStream_t);
