@@ -7,7 +7,9 @@ x = G y, and FP64 iterative refinement until the normwise backward error
 eta <= 1e-14 (at most 16 steps).  Paths: factors in FP64 or in FP32 on the
 matrix cores (refinement always FP64), each with no pivoting (GENP, "f64",
 "f32") or with partial pivoting confined to the diagonal blocks of at most 128
-("f64p", "f32p").  The headline is the fastest path that reaches eta <= 1e-14;
+("f64p", "f32p"), refined classically or, for FP32 factors, by GMRES preconditioned
+with the factors ("f32g", "f32pg").  The headline is the fastest path that
+reaches eta <= 1e-14;
 its speed-up over FP64 GENP is reported beside it.
 
 Rate convention: (2/3 n^3 + 2 n^2 nrhs) flops per step (the standard count for
@@ -54,19 +56,28 @@ def lu_solve_flops(n, nrhs):
     return 2.0 / 3.0 * n ** 3 + 2.0 * n * n * nrhs
 
 
-PATHS = {"f64": ("F64", "PIVOT_NONE"), "f32": ("F32", "PIVOT_NONE"),
-         "f64p": ("F64", "PIVOT_BLOCK"), "f32p": ("F32", "PIVOT_BLOCK")}
+# name: (factor precision, row exchanges, refinement)
+PATHS = {"f64": ("F64", "PIVOT_NONE", "ir"), "f32": ("F32", "PIVOT_NONE", "ir"),
+         "f64p": ("F64", "PIVOT_BLOCK", "ir"), "f32p": ("F32", "PIVOT_BLOCK", "ir"),
+         "f32g": ("F32", "PIVOT_NONE", "gmres"), "f32pg": ("F32", "PIVOT_BLOCK", "gmres")}
 
 
-def run_path(rmge, torch, A, b, name, seed, steps, warmup, block, max_refine):
-    prec, pivot = (getattr(rmge, x) for x in PATHS[name])
+def run_path(rmge, torch, A, b, name, seed, steps, warmup, block, max_refine, max_iters):
+    prec, pivot = (getattr(rmge, x) for x in PATHS[name][:2])
+    method = PATHS[name][2]
     f = rmge.factor(A, kind=rmge.GAUSSIAN, seed=seed, block=block, prec=prec, pivot=pivot)
+
+    def solve():
+        if method == "gmres":
+            return f.solve_gmres(b, max_iters=max_iters, restart=32, tol=ETA_TARGET, out=X)
+        return f.solve(b, max_refine=max_refine, tol=ETA_TARGET, out=X)
+
     if not f.ok:
         raise RuntimeError("factorization broke down: status %d" % f.status)
     X = torch.empty_like(b)
     for i in range(warmup):
         f.refactor(A, seed)
-        _, st = f.solve(b, max_refine=max_refine, tol=ETA_TARGET, out=X)
+        _, st = solve()
         log("%s warmup %d: eta %.2e after %d refinement steps" % (name, i, st["eta"], st["iters"]))
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -74,7 +85,7 @@ def run_path(rmge, torch, A, b, name, seed, steps, warmup, block, max_refine):
     for i in range(steps):
         f.refactor(A, seed)
         fs = f.stats()
-        _, st = f.solve(b, max_refine=max_refine, tol=ETA_TARGET, out=X)
+        _, st = solve()
         ms_product.append(fs["ms_product"])
         ms_factor.append(fs["ms_factor"])
         ms_draw.append(fs["ms_multiplier"])
@@ -152,7 +163,8 @@ def main():
     ap.add_argument("--seed", type=int, default=1)
     ap.add_argument("--block", type=int, default=256)
     ap.add_argument("--max-refine", type=int, default=16)
-    ap.add_argument("--paths", default="f64,f32,f64p,f32p")
+    ap.add_argument("--paths", default="f64,f32,f64p,f32p,f32g,f32pg")
+    ap.add_argument("--max-iters", type=int, default=200, help="GMRES inner iterations in all")
     ap.add_argument("--cpu-n", type=int, default=4096)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--matrix", default="conditioned", choices=["conditioned", "gaussian"],
@@ -189,7 +201,7 @@ def main():
         if p not in PATHS:
             ap.error("unknown path %r (choose from %s)" % (p, ",".join(PATHS)))
         results[p] = run_path(rmge, torch, A, b, p, args.seed + 1000, args.steps, args.warmup,
-                              args.block, args.max_refine)
+                              args.block, args.max_refine, args.max_iters)
 
     ok = {k: v for k, v in results.items() if v["converged"]}
     head = min(ok, key=lambda k: ok[k]["ms_per_step"]) if ok else next(iter(results))

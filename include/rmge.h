@@ -145,6 +145,24 @@ rmge_status rmge_solve(const rmge_factors *f, const double *B, int64_t nrhs, int
                        double *X, int64_t ldx, int32_t max_refine, double tol,
                        rmge_solve_stats *st);
 
+/* X = A^{-1} B, refined by restarted flexible GMRES preconditioned by the
+ * factors (GMRES-based iterative refinement; the paper's Section 8.1 uses
+ * classical refinement, which stops contracting once the factors' backward
+ * error times kappa(A H) nears 1, as FP32 factors of A G do at large n).
+ * Per right-hand side: x0 = H U^{-1} L^{-1} P b; then outer steps
+ * r = b - A x (FP64), inner iterations z_j = H U^{-1} L^{-1} P v_j (factor
+ * precision), w = A z_j, FP64 Krylov basis orthogonalised twice, until the
+ * least-squares residual estimate drops below tol (||A||_inf ||x||_inf +
+ * ||b||_inf) / 2 or `restart` vectors are used; x += Z y.  Stops when
+ * eta <= tol or after max_iters inner iterations in all.
+ * restart: 1..64.  tol > 0.  st->iters counts inner iterations;
+ * st->eta_hist holds eta at each outer check (first 17).  Returns
+ * RMGE_NOT_CONVERGED if some right-hand side ends above tol.  Workspace:
+ * (2 restart + 2) n doubles, kept by the handle. */
+rmge_status rmge_solve_gmres(const rmge_factors *f, const double *B, int64_t nrhs, int64_t ldb,
+                             double *X, int64_t ldx, int32_t max_iters, int32_t restart,
+                             double tol, rmge_solve_stats *st);
+
 /* Y = A^{-T} W = L^{-T} U^{-T} H^T W (the adjoint, from A^{-1} = H (A H)^{-1},
  * Fact faprepr; P^T L^{-T} U^{-T} H^T W when pivoted).  Reuses L and U.
  * W, Y: device, n x nrhs, row-major. */

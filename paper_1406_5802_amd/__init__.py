@@ -116,6 +116,27 @@ class Factors:
                  "eta_hist": [st.eta_hist[i] for i in range(st.iters + 1)]}
         return (X.reshape(-1) if vec else X), stats
 
+    def solve_gmres(self, B, max_iters=200, restart=32, tol=1e-14, out=None,
+                    raise_on_not_converged=False):
+        """X = A^{-1} B with GMRES-based refinement preconditioned by the factors."""
+        import torch
+
+        vec = B.dim() == 1
+        B2 = B.reshape(-1, 1) if vec else B
+        _check_matrix(B2, "B")
+        nrhs = B2.shape[1]
+        X = out if out is not None else torch.empty((self.n, nrhs), dtype=torch.float64,
+                                                    device=B.device)
+        rc, st = _rmge.rmge_solve_gmres(self._h, B2.data_ptr(), nrhs, B2.stride(0), X.data_ptr(),
+                                        X.stride(0), max_iters, restart, tol)
+        if rc not in (_rmge.RMGE_OK, _rmge.RMGE_NOT_CONVERGED) or (
+                raise_on_not_converged and rc == _rmge.RMGE_NOT_CONVERGED):
+            raise RMGEError(rc, "rmge_solve_gmres")
+        nh = min(17, max(1, sum(1 for i in range(17) if st.eta_hist[i] != 0.0)))
+        stats = {"status": rc, "iters": st.iters, "converged": bool(st.converged),
+                 "eta0": st.eta0, "eta": st.eta, "eta_hist": [st.eta_hist[i] for i in range(nh)]}
+        return (X.reshape(-1) if vec else X), stats
+
     def solve_adjoint(self, W, out=None):
         """Y = A^{-T} W."""
         import torch

@@ -25,7 +25,7 @@ STATUS_NAMES = {
 # Every function the header declares, for the export check.
 EXPORTS = (
     "rmge_factor", "rmge_factor_ex", "rmge_factor_pivoted", "rmge_refactor", "rmge_solve",
-    "rmge_solve_adjoint", "rmge_factor_stats_get", "rmge_factors_lu", "rmge_factors_perm",
+    "rmge_solve_gmres", "rmge_solve_adjoint", "rmge_factor_stats_get", "rmge_factors_lu", "rmge_factors_perm",
     "rmge_multiplier_params", "rmge_param_count", "rmge_precondition", "rmge_destroy",
     "rmge_status_string", "rmge_version",
 )
@@ -67,6 +67,8 @@ def lib() -> ctypes.CDLL:
     L.rmge_refactor.argtypes = [vp, dp, i64, u64]
     L.rmge_solve.argtypes = [vp, dp, i64, i64, dp, i64, i32, ctypes.c_double,
                              ctypes.POINTER(rmge_solve_stats)]
+    L.rmge_solve_gmres.argtypes = [vp, dp, i64, i64, dp, i64, i32, i32, ctypes.c_double,
+                                   ctypes.POINTER(rmge_solve_stats)]
     L.rmge_solve_adjoint.argtypes = [vp, dp, i64, i64, dp, i64]
     L.rmge_factor_stats_get.argtypes = [vp, ctypes.POINTER(rmge_factor_stats)]
     L.rmge_factors_lu.argtypes = [vp, dp, i64]
@@ -80,7 +82,8 @@ def lib() -> ctypes.CDLL:
     L.rmge_status_string.restype = ctypes.c_char_p
     L.rmge_version.restype = i32
     for name in ("rmge_factor", "rmge_factor_ex", "rmge_factor_pivoted", "rmge_refactor",
-                 "rmge_solve", "rmge_solve_adjoint", "rmge_factor_stats_get", "rmge_factors_lu",
+                 "rmge_solve", "rmge_solve_gmres", "rmge_solve_adjoint", "rmge_factor_stats_get",
+                 "rmge_factors_lu",
                  "rmge_factors_perm", "rmge_multiplier_params", "rmge_precondition"):
         getattr(L, name).restype = ctypes.c_int
     _lib = L
@@ -130,6 +133,13 @@ def rmge_refactor(h, A: int, lda: int, seed: int) -> int:
 def rmge_solve(h, B: int, nrhs: int, ldb: int, X: int, ldx: int, max_refine: int, tol: float):
     st = rmge_solve_stats()
     rc = lib().rmge_solve(h, B, nrhs, ldb, X, ldx, max_refine, tol, ctypes.byref(st))
+    return rc, st
+
+
+def rmge_solve_gmres(h, B: int, nrhs: int, ldb: int, X: int, ldx: int, max_iters: int,
+                     restart: int, tol: float):
+    st = rmge_solve_stats()
+    rc = lib().rmge_solve_gmres(h, B, nrhs, ldb, X, ldx, max_iters, restart, tol, ctypes.byref(st))
     return rc, st
 
 

@@ -22,6 +22,8 @@
 //         residual, norms
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+#include <cmath>
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
@@ -54,11 +56,15 @@ struct rmge_factors {
     double *scal = nullptr;  // [0] max|U| [1] min|u_kk| [2] max|M| [3] ||A||_inf
     // solve workspace
     int64_t ws_nrhs = 0;
-    void *wy = nullptr, *wx = nullptr;
+    double *wy = nullptr, *wx = nullptr;  // solve vectors (FP64 for every factor type)
     double *wr = nullptr, *wnorm = nullptr;
     double *wt = nullptr;
     int64_t wt_size = 0;
     int *wsync = nullptr;  // persistent solves: ticket counter, error word
+    // Krylov workspace (FP64): basis V (restart + 1 vectors), preconditioned
+    // vectors Z (restart), residual, partial sums and small device vectors
+    double *kv = nullptr;
+    int kv_restart = 0;
     // host copies
     DevStatus host_st{-1, 0, 0};
     bool stats_done = false;
@@ -360,7 +366,7 @@ rmge_status run_factor(rmge_factors *f) {
 void free_handle(rmge_factors *f) {
     if (!f) return;
     void *ptrs[] = {f->lu, f->G, f->params, f->hker, f->hhat, f->tw, f->inv, f->sinv, f->piv,
-                    f->st, f->scal, f->wy, f->wx, f->wr, f->wnorm, f->wt, f->wsync};
+                    f->st, f->scal, f->wy, f->wx, f->wr, f->wnorm, f->wt, f->wsync, f->kv};
     for (void *p : ptrs)
         if (p) (void)hipFree(p);
     for (hipEvent_t &e : f->ev)
@@ -421,7 +427,7 @@ rmge_status alloc_handle(rmge_factors *f) {
 rmge_status ensure_solve_ws(rmge_factors *f, int64_t nrhs, bool need_t) {
     const int64_t n = f->n;
     if (nrhs > f->ws_nrhs) {
-        for (void **p : {&f->wy, &f->wx}) {
+        for (double **p : {&f->wy, &f->wx}) {
             if (*p) (void)hipFree(*p);
             *p = nullptr;
         }
@@ -429,9 +435,8 @@ rmge_status ensure_solve_ws(rmge_factors *f, int64_t nrhs, bool need_t) {
         if (f->wnorm) (void)hipFree(f->wnorm);
         f->wr = f->wnorm = nullptr;
         f->ws_nrhs = 0;
-        const size_t es = elem_size(f->prec);
-        RMGE_TRY(hipMalloc(&f->wy, es * static_cast<size_t>(n * nrhs)));
-        RMGE_TRY(hipMalloc(&f->wx, es * static_cast<size_t>(n * nrhs)));
+        RMGE_TRY(hipMalloc(&f->wy, sizeof(double) * static_cast<size_t>(n * nrhs)));
+        RMGE_TRY(hipMalloc(&f->wx, sizeof(double) * static_cast<size_t>(n * nrhs)));
         RMGE_TRY(hipMalloc(&f->wr, sizeof(double) * static_cast<size_t>(n * nrhs)));
         RMGE_TRY(hipMalloc(&f->wnorm, sizeof(double) * static_cast<size_t>(4 * nrhs + 8)));
         f->ws_nrhs = nrhs;
@@ -453,14 +458,14 @@ rmge_status ensure_solve_ws(rmge_factors *f, int64_t nrhs, bool need_t) {
     return RMGE_OK;
 }
 
-// Triangular solves on the workspace: wy (T, n x nrhs) <- U^{-1} L^{-1} wy
+// Triangular solves on the workspace: wy (FP64, n x nrhs) <- U^{-1} L^{-1} wy
 // (`adjoint`: U^{-T} then L^{-T}), one persistent launch per solve and group
 // of 16 right-hand sides, through wx.
 template <typename T>
 hipError_t tri_solves(rmge_factors *f, int64_t nrhs, bool adjoint) {
     const int64_t n = f->n, ld = f->ld;
     const T *lu = static_cast<const T *>(f->lu);
-    T *Y = static_cast<T *>(f->wy), *X = static_cast<T *>(f->wx);
+    double *Y = f->wy, *X = f->wx;
     const T *Linv = static_cast<const T *>(f->sinv), *Uinv = Linv + f->sinv_rows * kSub;
     hipStream_t s = f->stream;
     // L then U (solve), or U^T then L^T (adjoint)
@@ -491,23 +496,25 @@ hipError_t apply_inverse(rmge_factors *f, const double *src, int64_t lds, int64_
                          int64_t ldx, double beta) {
     const int64_t n = f->n;
     hipStream_t s = f->stream;
-    T *Y = static_cast<T *>(f->wy);
-    hipError_t e = convert_2d<double, T>(src, lds, Y, nrhs, n, nrhs, s, f->pivot ? f->piv : nullptr);
+    double *Y = f->wy;
+    hipError_t e = convert_2d<double, double>(src, lds, Y, nrhs, n, nrhs, s,
+                                              f->pivot ? f->piv : nullptr);
     if (e != hipSuccess) return e;
     if ((e = tri_solves<T>(f, nrhs, false)) != hipSuccess) return e;
     switch (f->kind) {
-    case RMGE_MULT_NONE: return axpby_2d<T>(Y, nrhs, X, ldx, n, static_cast<int>(nrhs), beta, s);
+    case RMGE_MULT_NONE:
+        return axpby_2d<double>(Y, nrhs, X, ldx, n, static_cast<int>(nrhs), beta, s);
     case RMGE_MULT_GAUSSIAN:
         for (int64_t g = 0; g < nrhs; g += 16) {
             const int nr = static_cast<int>((nrhs - g) < 16 ? (nrhs - g) : 16);
-            e = gemv_n<T, T, double>(n, n, 1.0, static_cast<const T *>(f->G), n, Y + g, nrhs,
-                                     beta, X + g, ldx, nr, s);
+            e = gemv_n<T, double, double>(n, n, 1.0, static_cast<const T *>(f->G), n, Y + g,
+                                          nrhs, beta, X + g, ldx, nr, s);
             if (e != hipSuccess) return e;
         }
         return hipSuccess;
     default:
-        return fft_rows<T, double>(Y, 1, nrhs, nrhs, n, f->m, f->tw, f->hhat, 0, beta, X, 1, ldx,
-                                   s);
+        return fft_rows<double, double>(Y, 1, nrhs, nrhs, n, f->m, f->tw, f->hhat, 0, beta, X, 1,
+                                        ldx, s);
     }
 }
 
@@ -582,26 +589,175 @@ rmge_status run_adjoint(rmge_factors *f, const double *W, int64_t nrhs, int64_t 
     if (rs != RMGE_OK) return rs;
     const int64_t n = f->n;
     hipStream_t s = f->stream;
-    T *Z = static_cast<T *>(f->wy);
+    double *Z = f->wy;
     switch (f->kind) {
-    case RMGE_MULT_NONE: RMGE_TRY((convert_2d<double, T>(W, ldw, Z, nrhs, n, nrhs, s))); break;
+    case RMGE_MULT_NONE:
+        RMGE_TRY((convert_2d<double, double>(W, ldw, Z, nrhs, n, nrhs, s)));
+        break;
     case RMGE_MULT_GAUSSIAN:
         for (int64_t g = 0; g < nrhs; g += 16) {
             const int nr = static_cast<int>((nrhs - g) < 16 ? (nrhs - g) : 16);
-            RMGE_TRY((gemv_t<T, double, T>(n, n, static_cast<const T *>(f->G), n, W + g, ldw,
-                                           Z + g, nrhs, nr, f->wt, s)));
+            RMGE_TRY((gemv_t<T, double, double>(n, n, static_cast<const T *>(f->G), n, W + g, ldw,
+                                                Z + g, nrhs, nr, f->wt, s)));
         }
         break;
     default:
-        RMGE_TRY((fft_rows<double, T>(W, 1, ldw, nrhs, n, f->m, f->tw, f->hhat, 1, 0.0, Z, 1, nrhs,
-                                      s)));
+        RMGE_TRY((fft_rows<double, double>(W, 1, ldw, nrhs, n, f->m, f->tw, f->hhat, 1, 0.0, Z, 1,
+                                           nrhs, s)));
     }
     RMGE_TRY(tri_solves<T>(f, nrhs, true));
     // Y = P^T (L^{-T} U^{-T} H^T W): row t goes back to row piv[t]
-    RMGE_TRY((convert_2d<T, double>(Z, nrhs, Y, ldy, n, nrhs, s, nullptr,
-                                    f->pivot ? f->piv : nullptr)));
+    RMGE_TRY((convert_2d<double, double>(Z, nrhs, Y, ldy, n, nrhs, s, nullptr,
+                                         f->pivot ? f->piv : nullptr)));
     RMGE_TRY(hipStreamSynchronize(s));
     return solve_sync_error(f);
+}
+
+// ------------------------------------------------------------- GMRES-IR
+//
+// Refinement by restarted flexible GMRES, right-preconditioned by the
+// factors: for each right-hand side, outer steps r = b - A x (FP64), inner
+// Krylov iterations on A d = r with z_j = H U^{-1} L^{-1} P v_j (the same
+// application of the preprocessed inverse as one classical refinement step),
+// w = A z_j, classical Gram-Schmidt applied twice, Givens rotations on the
+// host; then x += Z y.  The FP64 basis makes the iteration converge when the
+// factors are too inaccurate for classical refinement to contract (large
+// growth, or kappa(A H) u_factor near 1).
+
+constexpr int kMaxRestart = 64;
+
+rmge_status ensure_krylov_ws(rmge_factors *f, int restart) {
+    if (f->kv && f->kv_restart >= restart) return RMGE_OK;
+    if (f->kv) (void)hipFree(f->kv);
+    f->kv = nullptr;
+    f->kv_restart = 0;
+    const size_t n = static_cast<size_t>(f->n);
+    const size_t words = (2 * static_cast<size_t>(restart) + 2) * n + 256 * kMaxRestart +
+                         4 * kMaxRestart;
+    RMGE_TRY(hipMalloc(&f->kv, sizeof(double) * words));
+    f->kv_restart = restart;
+    return RMGE_OK;
+}
+
+template <typename T>
+rmge_status run_gmres(rmge_factors *f, const double *B, int64_t nrhs, int64_t ldb, double *X,
+                      int64_t ldx, int32_t max_iters, int32_t restart, double tol,
+                      rmge_solve_stats *st) {
+    rmge_status rs = ensure_solve_ws(f, nrhs, false);
+    if (rs != RMGE_OK) return rs;
+    if ((rs = ensure_krylov_ws(f, restart)) != RMGE_OK) return rs;
+    const int64_t n = f->n;
+    hipStream_t s = f->stream;
+    double *V = f->kv;                             // (restart + 1) x n
+    double *Z = V + (restart + 1) * n;             // restart x n
+    double *R = Z + restart * n;                   // n
+    double *part = R + n;                          // 256 x kMaxRestart
+    double *dv = part + 256 * kMaxRestart;         // [0, 64) h, [64, 128) h2, [128] |w|^2,
+                                                   // [129 ..] norms; [192, 256) y
+    double *hy = dv + 3 * kMaxRestart;
+    // initial solve for every right-hand side (one classical application)
+    RMGE_TRY(apply_inverse<T>(f, B, ldb, nrhs, X, ldx, 0.0));
+    if (!f->anorm_done) {
+        RMGE_TRY(fill_f64(f->scal + 3, 1, 0.0, s));
+        RMGE_TRY(norm_inf(f->A, f->lda, n, f->scal + 3, s));
+        RMGE_TRY(hipMemcpyAsync(&f->anorm, f->scal + 3, sizeof(double), hipMemcpyDeviceToHost, s));
+        RMGE_TRY(hipStreamSynchronize(s));
+        f->anorm_done = true;
+    }
+    rmge_solve_stats loc{};
+    int hist = 0, total = 0;
+    bool all_ok = true;
+    double worst0 = 0.0, worst = 0.0;
+    std::vector<double> H(static_cast<size_t>((restart + 1) * restart)), cs(restart), sn(restart),
+        g(restart + 1), y(restart), hh(3 * kMaxRestart);
+    for (int64_t c = 0; c < nrhs; ++c) {
+        double eta = 0.0;
+        bool first = true;
+        while (true) {
+            // r = b - A x, eta, ||r||_2
+            RMGE_TRY(scale_copy(R, B + c, ldb, n, 1.0, s));
+            RMGE_TRY((gemv_n<double, double, double>(n, n, -1.0, f->A, f->lda, X + c, ldx, 1.0, R,
+                                                     1, 1, s)));
+            RMGE_TRY(fill_f64(dv + 129, 3, 0.0, s));
+            RMGE_TRY(colmax_abs(R, 1, n, 1, dv + 129, s));
+            RMGE_TRY(colmax_abs(X + c, ldx, n, 1, dv + 130, s));
+            RMGE_TRY(colmax_abs(B + c, ldb, n, 1, dv + 131, s));
+            RMGE_TRY(mdot(R, n, 1, R, part, dv + 128, false, s));
+            RMGE_TRY(hipMemcpyAsync(hh.data() + 128, dv + 128, 4 * sizeof(double),
+                                    hipMemcpyDeviceToHost, s));
+            RMGE_TRY(hipStreamSynchronize(s));
+            const double rinf = hh[129], xinf = hh[130], binf = hh[131];
+            const double scale = f->anorm * xinf + binf;
+            eta = rinf / scale;
+            if (first) {
+                worst0 = (eta > worst0 || eta != eta) ? eta : worst0;
+                first = false;
+            }
+            if (hist < 17) loc.eta_hist[hist++] = eta;
+            if (!(eta > tol) || total >= max_iters || eta != eta) break;
+            const double beta = std::sqrt(hh[128]);
+            if (!(beta > 0.0)) break;
+            const double target = 0.5 * tol * scale;  // ||r||_2 <= target => eta <= tol / 2
+            RMGE_TRY(scale_copy(V, R, 1, n, 1.0 / beta, s));
+            std::fill(g.begin(), g.end(), 0.0);
+            g[0] = beta;
+            int k = 0;
+            for (int j = 0; j < restart && total < max_iters; ++j) {
+                double *vj = V + j * n, *w = V + (j + 1) * n, *zj = Z + j * n;
+                RMGE_TRY(apply_inverse<T>(f, vj, 1, 1, zj, 1, 0.0));
+                RMGE_TRY((gemv_n<double, double, double>(n, n, 1.0, f->A, f->lda, zj, 1, 0.0, w,
+                                                         1, 1, s)));
+                RMGE_TRY(mdot(V, n, j + 1, w, part, dv, false, s));
+                RMGE_TRY(lincomb(w, 1, V, n, j + 1, dv, -1.0, s));
+                RMGE_TRY(mdot(V, n, j + 1, w, part, dv + kMaxRestart, false, s));
+                RMGE_TRY(lincomb(w, 1, V, n, j + 1, dv + kMaxRestart, -1.0, s));
+                RMGE_TRY(mdot(w, n, 1, w, part, dv + 2 * kMaxRestart, false, s));
+                RMGE_TRY(hipMemcpyAsync(hh.data(), dv, (2 * kMaxRestart + 1) * sizeof(double),
+                                        hipMemcpyDeviceToHost, s));
+                RMGE_TRY(hipStreamSynchronize(s));
+                ++total;
+                double *col = H.data() + static_cast<size_t>(j) * (restart + 1);
+                for (int i = 0; i <= j; ++i) col[i] = hh[i] + hh[kMaxRestart + i];
+                const double hnext = std::sqrt(hh[2 * kMaxRestart]);
+                col[j + 1] = hnext;
+                if (hnext > 0.0) RMGE_TRY(scale_copy(w, w, 1, n, 1.0 / hnext, s));
+                for (int i = 0; i < j; ++i) {  // earlier rotations
+                    const double a = col[i], b = col[i + 1];
+                    col[i] = cs[i] * a + sn[i] * b;
+                    col[i + 1] = -sn[i] * a + cs[i] * b;
+                }
+                const double a = col[j], b = col[j + 1];
+                const double rr = std::hypot(a, b);
+                cs[j] = rr > 0.0 ? a / rr : 1.0;
+                sn[j] = rr > 0.0 ? b / rr : 0.0;
+                col[j] = rr;
+                col[j + 1] = 0.0;
+                g[j + 1] = -sn[j] * g[j];
+                g[j] = cs[j] * g[j];
+                k = j + 1;
+                if (std::fabs(g[j + 1]) <= target || !(hnext > 1e-300 * beta)) break;
+            }
+            if (k == 0) break;
+            for (int i = k - 1; i >= 0; --i) {  // R y = g
+                double t = g[i];
+                for (int l = i + 1; l < k; ++l) t -= H[static_cast<size_t>(l) * (restart + 1) + i] * y[l];
+                const double d = H[static_cast<size_t>(i) * (restart + 1) + i];
+                y[i] = d != 0.0 ? t / d : 0.0;
+            }
+            RMGE_TRY(hipMemcpyAsync(hy, y.data(), k * sizeof(double), hipMemcpyHostToDevice, s));
+            RMGE_TRY(lincomb(X + c, ldx, Z, n, k, hy, 1.0, s));
+        }
+        worst = (eta > worst || eta != eta) ? eta : worst;
+        if (!(eta <= tol)) all_ok = false;
+    }
+    rs = solve_sync_error(f);
+    if (rs != RMGE_OK) return rs;
+    loc.iters = total;
+    loc.eta0 = worst0;
+    loc.eta = worst;
+    loc.converged = all_ok ? 1 : 0;
+    if (st) *st = loc;
+    return all_ok ? RMGE_OK : RMGE_NOT_CONVERGED;
 }
 
 rmge_status check_factor_args(const double *A, int64_t n, int64_t lda, int32_t kind,
@@ -684,6 +840,20 @@ rmge_status rmge_solve(const rmge_factors *fc, const double *B, int64_t nrhs, in
     if (f->host_st.code == 5) return RMGE_NONFINITE;
     return (f->prec == RMGE_F32) ? run_solve<float>(f, B, nrhs, ldb, X, ldx, max_refine, tol, st)
                                  : run_solve<double>(f, B, nrhs, ldb, X, ldx, max_refine, tol, st);
+}
+
+rmge_status rmge_solve_gmres(const rmge_factors *fc, const double *B, int64_t nrhs, int64_t ldb,
+                             double *X, int64_t ldx, int32_t max_iters, int32_t restart,
+                             double tol, rmge_solve_stats *st) {
+    rmge_factors *f = const_cast<rmge_factors *>(fc);
+    if (!f || !B || !X || nrhs < 1 || ldb < nrhs || ldx < nrhs || max_iters < 0 || X == B ||
+        restart < 1 || restart > kMaxRestart || !(tol > 0.0))
+        return RMGE_EINVAL;
+    if (f->host_st.code == 4) return RMGE_ZERO_PIVOT;
+    if (f->host_st.code == 5) return RMGE_NONFINITE;
+    return (f->prec == RMGE_F32)
+               ? run_gmres<float>(f, B, nrhs, ldb, X, ldx, max_iters, restart, tol, st)
+               : run_gmres<double>(f, B, nrhs, ldb, X, ldx, max_iters, restart, tol, st);
 }
 
 rmge_status rmge_solve_adjoint(const rmge_factors *fc, const double *W, int64_t nrhs,

@@ -107,12 +107,23 @@ hipError_t abs_max(const T *m, int64_t ld, int64_t n, double *out3, hipStream_t 
 // Blocks of 64 rows are taken in dependency order by a ticket counter.
 // Dinv: compact inverses of the aligned 32 x 32 diagonal sub-blocks of L
 // (modes 0, 3) or U (modes 1, 2), from diag_inverses, with at least
-// round_up(n, 64) rows.  X and B are n x ldx (nr <= 16 columns used; X may not
-// alias B).  sync: device ints, [0] ticket counter, [1] error word (set to 1 if
-// a wait timed out; the caller clears it).
+// round_up(n, 64) rows.  X and B are FP64, n x ldx (nr <= 16 columns used; X
+// may not alias B); the arithmetic is FP64 whatever the factors' type.  sync:
+// device ints, [0] ticket counter, [1] error word (set to 1 if a wait timed
+// out; the caller clears it).
 template <typename T>
-hipError_t trsv_full(int mode, const T *LU, int64_t ld, int64_t n, const T *Dinv, const T *B,
-                     T *X, int64_t ldx, int nr, int *sync, hipStream_t s);
+hipError_t trsv_full(int mode, const T *LU, int64_t ld, int64_t n, const T *Dinv, const double *B,
+                     double *X, int64_t ldx, int nr, int *sync, hipStream_t s);
+// Krylov helpers; basis vectors V_j stored contiguously (V + j * n), j < k <= 64.
+// h[j] = V_j . w (+ h[j] if accumulate), deterministic; part: >= 256 * k doubles.
+hipError_t mdot(const double *V, int64_t n, int k, const double *w, double *part, double *h,
+                bool accumulate, hipStream_t s);
+// w[i * ldw] += sign * sum_j V_j[i] h[j]  (h on the device).
+hipError_t lincomb(double *w, int64_t ldw, const double *V, int64_t n, int k, const double *h,
+                   double sign, hipStream_t s);
+// dst[i] = alpha * src[i * lds].
+hipError_t scale_copy(double *dst, const double *src, int64_t lds, int64_t n, double alpha,
+                      hipStream_t s);
 // y = beta * y + alpha * M x  (rows of M; FP64 accumulation).  M: rows x cols (ldm),
 // x: cols x nrhs (ldx), y: rows x nrhs (ldy).
 template <typename TM, typename TX, typename TY>

@@ -35,32 +35,19 @@ constexpr int SW = 32;  // its two diagonal sub-blocks, applied through their in
 // checks it.
 constexpr int kSpinLimit = 1 << 22;
 
-template <typename T>
-struct Mark;
-template <>
-struct Mark<double> {
-    using U = unsigned long long;
-    static constexpr U bits = 0x7FF4D1A6C0DE0001ull;
-};
-template <>
-struct Mark<float> {
-    using U = unsigned int;
-    static constexpr U bits = 0x7FA5C0DEu;
-};
+constexpr unsigned long long kMark = 0x7FF4D1A6C0DE0001ull;  // FP64 signalling NaN
 
-template <typename T>
-__device__ inline T poll_value(const T *p, bool *ready) {
-    using U = typename Mark<T>::U;
-    const U b = __hip_atomic_load(reinterpret_cast<U *>(const_cast<T *>(p)), __ATOMIC_RELAXED,
-                                  __HIP_MEMORY_SCOPE_AGENT);
-    *ready = (b != Mark<T>::bits);
-    return __builtin_bit_cast(T, b);
+__device__ inline double poll_value(const double *p, bool *ready) {
+    const unsigned long long b =
+        __hip_atomic_load(reinterpret_cast<unsigned long long *>(const_cast<double *>(p)),
+                          __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    *ready = (b != kMark);
+    return __builtin_bit_cast(double, b);
 }
 
-template <typename T>
-__device__ inline void publish_value(T *p, T v) {
-    using U = typename Mark<T>::U;
-    __hip_atomic_store(reinterpret_cast<U *>(p), __builtin_bit_cast(U, v), __ATOMIC_RELAXED,
+__device__ inline void publish_value(double *p, double v) {
+    __hip_atomic_store(reinterpret_cast<unsigned long long *>(p),
+                       __builtin_bit_cast(unsigned long long, v), __ATOMIC_RELAXED,
                        __HIP_MEMORY_SCOPE_AGENT);
 }
 
@@ -68,10 +55,13 @@ __device__ inline void publish_value(T *p, T v) {
 //        2 U^T y = b (forward)              3 L^T y = b (unit upper, backward)
 // Dinv: the compact inverses of the 32 x 32 diagonal sub-blocks of the factor
 // the mode uses (L for 0 and 3, U for 1 and 2): row 32 q + i holds row i of
-// sub-block q's inverse.
+// sub-block q's inverse.  Factors in T; vectors and arithmetic in FP64 (the
+// factors are what streams from HBM, so FP32 factors keep their bandwidth
+// advantage while the solve itself adds no FP32 rounding).
 template <typename T, int MODE, int NR>
 __global__ __launch_bounds__(256) void k_trsv(const T *LU, int64_t ld, int64_t n, const T *Dinv,
-                                              const T *B, T *X, int64_t ldx, int nr, int *sync) {
+                                              const double *B, double *X, int64_t ldx, int nr,
+                                              int *sync) {
     constexpr bool forward = (MODE == 0 || MODE == 2);
     constexpr bool transposed = (MODE == 2 || MODE == 3);
     __shared__ T Ts[transposed ? SB : 1][SB + 1];  // transposed modes stage the tile here
@@ -109,10 +99,10 @@ __global__ __launch_bounds__(256) void k_trsv(const T *LU, int64_t ld, int64_t n
         Cp[i][j] = (rr < bI && cc < bI) ? LU[(I0 + rr) * ld + I0 + cc] : T(0);
     }
     const int r = tid >> 2, q = tid & 3;  // tile row r, columns 16 q .. 16 q + 15
-    T bval[NR];
+    double bval[NR];
 #pragma unroll
     for (int c = 0; c < NR; ++c)
-        bval[c] = (q == 0 && r < bI && c < nr) ? B[(I0 + r) * ldx + c] : T(0);
+        bval[c] = (q == 0 && r < bI && c < nr) ? B[(I0 + r) * ldx + c] : 0.0;
     double acc[NR];
 #pragma unroll
     for (int c = 0; c < NR; ++c) acc[c] = 0.0;
@@ -146,13 +136,13 @@ __global__ __launch_bounds__(256) void k_trsv(const T *LU, int64_t ld, int64_t n
         const int64_t J0 = static_cast<int64_t>(J) * SB;
         const int bJ = static_cast<int>((n - J0) < SB ? (n - J0) : SB);
         if (wave == 0) {
-            T v[NR];
+            double v[NR];
             int spins = 0;
             while (true) {
                 bool ready = true;
 #pragma unroll
                 for (int c = 0; c < NR; ++c) {
-                    v[c] = T(0);
+                    v[c] = 0.0;
                     if (lane < bJ && c < nr) {
                         bool ok;
                         v[c] = poll_value(X + (J0 + lane) * ldx + c, &ok);
@@ -170,7 +160,7 @@ __global__ __launch_bounds__(256) void k_trsv(const T *LU, int64_t ld, int64_t n
                 __builtin_amdgcn_s_sleep(1);
             }
 #pragma unroll
-            for (int c = 0; c < NR; ++c) ys[lane][c] = static_cast<double>(v[c]);
+            for (int c = 0; c < NR; ++c) ys[lane][c] = v[c];
         }
         __syncthreads();
         if (s_fail) break;
@@ -196,7 +186,7 @@ __global__ __launch_bounds__(256) void k_trsv(const T *LU, int64_t ld, int64_t n
     if (q == 0) {
 #pragma unroll
         for (int c = 0; c < NR; ++c)
-            ys[r][c] = (r < bI) ? static_cast<double>(bval[c]) - acc[c] : 0.0;
+            ys[r][c] = (r < bI) ? bval[c] - acc[c] : 0.0;
     }
     __syncthreads();
     // diagonal block: first-solved sub-block f, then the other, g
@@ -274,18 +264,17 @@ __global__ __launch_bounds__(256) void k_trsv(const T *LU, int64_t ld, int64_t n
     if (tid < bI) {
 #pragma unroll
         for (int c = 0; c < NR; ++c)
-            if (c < nr) publish_value(X + (I0 + tid) * ldx + c, static_cast<T>(xs[tid][c]));
+            if (c < nr) publish_value(X + (I0 + tid) * ldx + c, xs[tid][c]);
     }
 }
 
 // Before a solve: reset the ticket counter and mark every output entry unsolved.
-template <typename T>
-__global__ void k_trsv_prep(T *X, int64_t ldx, int64_t n, int nr, int *sync) {
+__global__ void k_trsv_prep(double *X, int64_t ldx, int64_t n, int nr, int *sync) {
     if (blockIdx.x == 0 && threadIdx.x == 0) sync[0] = 0;
     const int64_t total = n * nr;
     for (int64_t e = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x; e < total;
          e += static_cast<int64_t>(gridDim.x) * blockDim.x)
-        X[(e / nr) * ldx + e % nr] = __builtin_bit_cast(T, Mark<T>::bits);
+        X[(e / nr) * ldx + e % nr] = __builtin_bit_cast(double, kMark);
 }
 
 // y = beta y + alpha M x, FP64 accumulation; one wave per two rows.
@@ -444,6 +433,60 @@ __global__ void k_fill_f64(double *p, int64_t count, double value) {
         p[e] = value;
 }
 
+// ---- Krylov helpers (basis vectors stored contiguously: V[k * n + i]) ----
+
+constexpr int kMdotChunks = 256;  // partial sums per dot product (fixed: deterministic)
+constexpr int kMaxBasis = 64;
+
+// part[c * k + j] = sum over chunk c of V_j . w  (chunk c: rows c*cs .. c*cs + cs - 1)
+__global__ __launch_bounds__(256) void k_mdot_part(const double *V, int64_t n, int k,
+                                                   const double *w, int64_t cs, double *part) {
+    __shared__ double red[4];
+    const int64_t i0 = static_cast<int64_t>(blockIdx.x) * cs;
+    const int64_t i1 = (i0 + cs) < n ? (i0 + cs) : n;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    for (int j = 0; j < k; ++j) {
+        double acc = 0.0;
+        for (int64_t i = i0 + threadIdx.x; i < i1; i += 256) acc += V[j * n + i] * w[i];
+        for (int off = 32; off > 0; off >>= 1) acc += __shfl_xor(acc, off);
+        if (lane == 0) red[wave] = acc;
+        __syncthreads();
+        if (threadIdx.x == 0)
+            part[static_cast<int64_t>(blockIdx.x) * k + j] = (red[0] + red[1]) + (red[2] + red[3]);
+        __syncthreads();
+    }
+}
+
+// h[j] = sum_c part[c * k + j] (+ h[j] when accumulate), in chunk order.
+__global__ void k_mdot_sum(const double *part, int chunks, int k, double *h, int accumulate) {
+    const int j = threadIdx.x;
+    if (j >= k) return;
+    double s = 0.0;
+    for (int c = 0; c < chunks; ++c) s += part[c * k + j];
+    h[j] = accumulate ? h[j] + s : s;
+}
+
+// w[i] += sign * sum_j V_j[i] h[j]   (h on the device, k <= kMaxBasis)
+__global__ __launch_bounds__(256) void k_lincomb(double *w, int64_t ldw, const double *V, int64_t n,
+                                                 int k, const double *h, double sign) {
+    __shared__ double hs[kMaxBasis];
+    if (threadIdx.x < k) hs[threadIdx.x] = h[threadIdx.x];
+    __syncthreads();
+    for (int64_t i = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x; i < n;
+         i += static_cast<int64_t>(gridDim.x) * blockDim.x) {
+        double s = 0.0;
+        for (int j = 0; j < k; ++j) s += V[j * n + i] * hs[j];
+        w[i * ldw] += sign * s;
+    }
+}
+
+// dst[i] = alpha * src[i * lds]
+__global__ void k_scale_copy(double *dst, const double *src, int64_t lds, int64_t n, double alpha) {
+    for (int64_t i = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x; i < n;
+         i += static_cast<int64_t>(gridDim.x) * blockDim.x)
+        dst[i] = alpha * src[i * lds];
+}
+
 int grid_for(int64_t total, int threads) {
     int64_t g = (total + threads - 1) / threads;
     if (g > 4096) g = 4096;
@@ -454,10 +497,10 @@ int grid_for(int64_t total, int threads) {
 }  // namespace
 
 template <typename T, int MODE>
-hipError_t trsv_full_launch(const T *LU, int64_t ld, int64_t n, const T *Dinv, const T *B, T *X,
-                            int64_t ldx, int nr, int *sync, hipStream_t s) {
+hipError_t trsv_full_launch(const T *LU, int64_t ld, int64_t n, const T *Dinv, const double *B,
+                            double *X, int64_t ldx, int nr, int *sync, hipStream_t s) {
     const int nblk = static_cast<int>((n + SB - 1) / SB);
-    hipLaunchKernelGGL(k_trsv_prep<T>, dim3(grid_for(n * nr, 256)), dim3(256), 0, s, X, ldx, n, nr,
+    hipLaunchKernelGGL(k_trsv_prep, dim3(grid_for(n * nr, 256)), dim3(256), 0, s, X, ldx, n, nr,
                        sync);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
@@ -474,8 +517,8 @@ hipError_t trsv_full_launch(const T *LU, int64_t ld, int64_t n, const T *Dinv, c
 }
 
 template <typename T>
-hipError_t trsv_full(int mode, const T *LU, int64_t ld, int64_t n, const T *Dinv, const T *B,
-                     T *X, int64_t ldx, int nr, int *sync, hipStream_t s) {
+hipError_t trsv_full(int mode, const T *LU, int64_t ld, int64_t n, const T *Dinv, const double *B,
+                     double *X, int64_t ldx, int nr, int *sync, hipStream_t s) {
     if (nr < 1 || nr > 16 || n < 1 || B == X) return hipErrorInvalidValue;
     switch (mode) {
     case 0: return trsv_full_launch<T, 0>(LU, ld, n, Dinv, B, X, ldx, nr, sync, s);
@@ -560,22 +603,57 @@ hipError_t fill_f64(double *p, int64_t count, double value, hipStream_t s) {
     return hipGetLastError();
 }
 
+hipError_t mdot(const double *V, int64_t n, int k, const double *w, double *part, double *h,
+                bool accumulate, hipStream_t s) {
+    if (k < 1 || k > kMaxBasis || n < 1) return hipErrorInvalidValue;
+    const int64_t cs = ((n + kMdotChunks - 1) / kMdotChunks + 255) / 256 * 256;
+    const int chunks = static_cast<int>((n + cs - 1) / cs);
+    hipLaunchKernelGGL(k_mdot_part, dim3(chunks), dim3(256), 0, s, V, n, k, w, cs, part);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_mdot_sum, dim3(1), dim3(kMaxBasis), 0, s, part, chunks, k, h,
+                       accumulate ? 1 : 0);
+    return hipGetLastError();
+}
+
+hipError_t lincomb(double *w, int64_t ldw, const double *V, int64_t n, int k, const double *h,
+                   double sign, hipStream_t s) {
+    if (k < 1 || k > kMaxBasis || n < 1) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_lincomb, dim3(grid_for(n, 256)), dim3(256), 0, s, w, ldw, V, n, k, h,
+                       sign);
+    return hipGetLastError();
+}
+
+hipError_t scale_copy(double *dst, const double *src, int64_t lds, int64_t n, double alpha,
+                      hipStream_t s) {
+    if (n < 1) return hipSuccess;
+    hipLaunchKernelGGL(k_scale_copy, dim3(grid_for(n, 256)), dim3(256), 0, s, dst, src, lds, n,
+                       alpha);
+    return hipGetLastError();
+}
+
 template hipError_t trsv_full<double>(int, const double *, int64_t, int64_t, const double *,
                                       const double *, double *, int64_t, int, int *, hipStream_t);
 template hipError_t trsv_full<float>(int, const float *, int64_t, int64_t, const float *,
-                                     const float *, float *, int64_t, int, int *, hipStream_t);
+                                     const double *, double *, int64_t, int, int *, hipStream_t);
 template hipError_t gemv_n<double, double, double>(int64_t, int64_t, double, const double *,
                                                    int64_t, const double *, int64_t, double,
                                                    double *, int64_t, int, hipStream_t);
 template hipError_t gemv_n<float, float, double>(int64_t, int64_t, double, const float *, int64_t,
                                                  const float *, int64_t, double, double *, int64_t,
                                                  int, hipStream_t);
+template hipError_t gemv_n<float, double, double>(int64_t, int64_t, double, const float *,
+                                                  int64_t, const double *, int64_t, double,
+                                                  double *, int64_t, int, hipStream_t);
 template hipError_t gemv_t<double, double, double>(int64_t, int64_t, const double *, int64_t,
                                                    const double *, int64_t, double *, int64_t, int,
                                                    double *, hipStream_t);
 template hipError_t gemv_t<float, double, float>(int64_t, int64_t, const float *, int64_t,
                                                  const double *, int64_t, float *, int64_t, int,
                                                  double *, hipStream_t);
+template hipError_t gemv_t<float, double, double>(int64_t, int64_t, const float *, int64_t,
+                                                  const double *, int64_t, double *, int64_t, int,
+                                                  double *, hipStream_t);
 template hipError_t axpby_2d<double>(const double *, int64_t, double *, int64_t, int64_t, int,
                                      double, hipStream_t);
 template hipError_t axpby_2d<float>(const float *, int64_t, double *, int64_t, int64_t, int, double,
