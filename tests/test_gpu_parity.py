@@ -90,8 +90,9 @@ def _check_product(kind, n, A, M, seed):
 
 
 @pytest.mark.parametrize("kind", [0, 1, 2, 3])
-@pytest.mark.parametrize("n", [1, 2, 7, 64, 129, 300, 517])
+@pytest.mark.parametrize("n", [1, 2, 7, 64, 128, 129, 300, 384, 512, 517])
 def test_precondition_matches_oracle(rmge, kind, n):
+    # n a multiple of 128 takes the interior (unchecked) product kernel
     A = workloads.conditioned(n, 1e3, seed=n)
     M = host(rmge.precondition(dev(A), kind, seed=77))
     _check_product(kind, n, A, M, 77)
@@ -114,7 +115,8 @@ def _kappa_leading(M):
 
 @pytest.mark.parametrize("kind", [1, 2, 3])
 @pytest.mark.parametrize("n,block", [(64, 64), (129, 32), (300, 256), (300, 100), (517, 256),
-                                     (517, 128), (200, 7), (96, 1), (45, 2), (77, 3)])
+                                     (517, 128), (200, 7), (96, 1), (45, 2), (77, 3), (512, 256),
+                                     (384, 128)])
 def test_factors_match_oracle(rmge, kind, n, block):
     A = workloads.conditioned(n, 1e2, seed=3)
     f = rmge.factor(dev(A), kind=kind, seed=11, block=block)
