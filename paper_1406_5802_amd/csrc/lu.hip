@@ -36,16 +36,18 @@ __device__ inline bool is_bad(T p) {
     return p == T(0) || !isfinite(p);
 }
 
-// One pivot block (b <= 128) in registers: thread (ty, tx) of a 16 x 16 grid
-// (one wave per SIMD) holds elements (ty + 16 p, tx + 16 q), p, q < 8.  Pivot
-// step j: the owners of column j and of the pivot row publish them to LDS and
-// every thread applies the rank-1 update a_ic -= (a_ij / a_pj) a_pc to the
-// elements it holds, with the multiplier formed as a_ij times the reciprocal
-// of the pivot.  Multipliers of retired rows and pivot-row entries of columns
-// <= j are zero, so the update is branch-free (retired elements receive exact
-// zero updates) and an element left of its row's pivot keeps the value it had
-// when its column was eliminated; the multipliers l_ic = a_ic / a_cc are formed
-// at write-back from the recorded pivot reciprocals.
+// One pivot block (b <= 128) in registers: 512 threads (two waves per SIMD,
+// so one wave's barrier and LDS latency overlap the other's arithmetic);
+// thread (ty, tx) of a 32 x 16 grid holds elements (ty + 32 p, tx + 16 q),
+// p < 4, q < 8.  Pivot step j: the owners of column j and of the pivot row
+// publish them to LDS and every thread applies the rank-1 update
+// a_ic -= (a_ij / a_pj) a_pc to the elements it holds, with the multiplier
+// formed as a_ij times the reciprocal of the pivot.  Multipliers of retired
+// rows and pivot-row entries of columns <= j are zero, so the update is
+// branch-free (retired elements receive exact zero updates) and an element
+// left of its row's pivot keeps the value it had when its column was
+// eliminated; the multipliers l_ic = a_ic / a_cc are formed at write-back from
+// the recorded pivot reciprocals.
 //
 // PIV = false: GENP, the pivot of step j is row j (one barrier per step, the
 // column and row buffers double-buffered).
@@ -54,17 +56,21 @@ __device__ inline bool is_bad(T p) {
 // stops).  Rows stay in their registers; the pivot of step j is the active row
 // with the largest |a_ij| (ties: the lower row index), found by a shuffle
 // reduction over the four owner lanes of each wave and a reduction over the
-// four waves' candidates in LDS; a second barrier publishes the pivot row.
+// eight waves' candidates in LDS; a second barrier publishes the pivot row.
 // Row i is written back to position pos[i] (the step that retired it), and
 // piv[k0 + pos[i]] = k0 + i records the exchange.
+constexpr int kLeafThreads = 512;
+constexpr int kLeafRowsPer = kLeaf / 32;  // 4 rows per thread
+constexpr int kLeafWaves = kLeafThreads / 64;
+
 template <typename T, bool PIV>
-__global__ __launch_bounds__(256) void k_leaf_lu(T *a, int64_t lda, int b, int64_t k0,
-                                                 DevStatus *st, int *piv) {
+__global__ __launch_bounds__(kLeafThreads) void k_leaf_lu(T *a, int64_t lda, int b, int64_t k0,
+                                                          DevStatus *st, int *piv) {
     __shared__ T colv[2][kLeaf];
     __shared__ T rowv[2][kLeaf];
     __shared__ T rcp[kLeaf];
-    __shared__ T cand_v[2][4];
-    __shared__ int cand_i[2][4];
+    __shared__ T cand_v[2][kLeafWaves];
+    __shared__ int cand_i[2][kLeafWaves];
     __shared__ int pos[kLeaf];
     if (st->code != 0) return;  // an earlier pivot block broke down
     // This kernel is a chain of short dependent steps that runs beside the wide
@@ -72,18 +78,18 @@ __global__ __launch_bounds__(256) void k_leaf_lu(T *a, int64_t lda, int b, int64
     __builtin_amdgcn_s_setprio(3);
     const int tid = threadIdx.x;
     const int tx = tid & 15, ty = tid >> 4;
-    T v[8][8];
+    T v[kLeafRowsPer][8];
 #pragma unroll
-    for (int p = 0; p < 8; ++p)
+    for (int p = 0; p < kLeafRowsPer; ++p)
 #pragma unroll
         for (int q = 0; q < 8; ++q) {
-            const int i = ty + 16 * p, c = tx + 16 * q;
+            const int i = ty + 32 * p, c = tx + 16 * q;
             v[p][q] = (i < b && c < b) ? a[static_cast<int64_t>(i) * lda + c] : T(0);
         }
-    unsigned act = 0;  // PIV: bit p set while row ty + 16 p is still active
+    unsigned act = 0;  // PIV: bit p set while row ty + 32 p is still active
 #pragma unroll
-    for (int p = 0; p < 8; ++p)
-        if (ty + 16 * p < b) act |= 1u << p;
+    for (int p = 0; p < kLeafRowsPer; ++p)
+        if (ty + 32 * p < b) act |= 1u << p;
     if (PIV && tid < kLeaf) pos[tid] = -1;
 
     int done = b;
@@ -93,14 +99,14 @@ __global__ __launch_bounds__(256) void k_leaf_lu(T *a, int64_t lda, int b, int64
             switch (jq) {  // jq is uniform: one case runs, with static register indices
 #define RMGE_COL(Q)                                                          \
     case Q:                                                                  \
-        _Pragma("unroll") for (int p = 0; p < 8; ++p) colv[buf][ty + 16 * p] = v[p][Q]; \
+        _Pragma("unroll") for (int p = 0; p < kLeafRowsPer; ++p) colv[buf][ty + 32 * p] = v[p][Q]; \
         if (PIV) {                                                           \
             T bv = T(-1);                                                    \
             int bi = kLeaf;                                                  \
-            _Pragma("unroll") for (int p = 0; p < 8; ++p) {                  \
+            _Pragma("unroll") for (int p = 0; p < kLeafRowsPer; ++p) {       \
                 const T x = v[p][Q];                                         \
                 const T key = (x != x) ? T(INFINITY) : (x < T(0) ? -x : x);  \
-                if (((act >> p) & 1u) && key > bv) { bv = key; bi = ty + 16 * p; } \
+                if (((act >> p) & 1u) && key > bv) { bv = key; bi = ty + 32 * p; } \
             }                                                                \
             _Pragma("unroll") for (int o = 16; o <= 32; o <<= 1) {           \
                 const T ov = __shfl_xor(bv, o);                              \
@@ -121,23 +127,22 @@ __global__ __launch_bounds__(256) void k_leaf_lu(T *a, int64_t lda, int b, int64
             T bv = cand_v[buf][0];
             int bi = cand_i[buf][0];
 #pragma unroll
-            for (int w = 1; w < 4; ++w) {
+            for (int w = 1; w < kLeafWaves; ++w) {
                 const T ov = cand_v[buf][w];
                 const int oi = cand_i[buf][w];
                 if (ov > bv || (ov == bv && oi < bi)) { bv = ov; bi = oi; }
             }
             sel = bi;  // uniform; an active row always exists for j < b
-            if (ty == (sel & 15)) act &= ~(1u << (sel >> 4));
+            if (ty == (sel & 31)) act &= ~(1u << (sel >> 5));
             if (tid == 0) pos[sel] = j;
         }
-        if (ty == (sel & 15)) {
-            switch (sel >> 4) {
+        if (ty == (sel & 31)) {
+            switch (sel >> 5) {
 #define RMGE_ROW(P)                                                          \
     case P:                                                                  \
         _Pragma("unroll") for (int q = 0; q < 8; ++q) rowv[buf][tx + 16 * q] = v[P][q]; \
         break;
                 RMGE_ROW(0) RMGE_ROW(1) RMGE_ROW(2) RMGE_ROW(3)
-                RMGE_ROW(4) RMGE_ROW(5) RMGE_ROW(6) RMGE_ROW(7)
 #undef RMGE_ROW
             }
         }
@@ -160,8 +165,8 @@ __global__ __launch_bounds__(256) void k_leaf_lu(T *a, int64_t lda, int b, int64
             u[q] = (c > j) ? rowv[buf][c] : T(0);
         }
 #pragma unroll
-        for (int p = 0; p < 8; ++p) {
-            const int i = ty + 16 * p;
+        for (int p = 0; p < kLeafRowsPer; ++p) {
+            const int i = ty + 32 * p;
             const bool live = PIV ? ((act >> p) & 1u) != 0 : (i > j);
             const T l = live ? colv[buf][i] * rp : T(0);
 #pragma unroll
@@ -180,8 +185,8 @@ __global__ __launch_bounds__(256) void k_leaf_lu(T *a, int64_t lda, int b, int64
     }
     // write back (row i to its position), forming the multipliers left of the pivot
 #pragma unroll
-    for (int p = 0; p < 8; ++p) {
-        const int i = ty + 16 * p;
+    for (int p = 0; p < kLeafRowsPer; ++p) {
+        const int i = ty + 32 * p;
         const int dst = PIV ? (i < b ? pos[i] : i) : i;
 #pragma unroll
         for (int q = 0; q < 8; ++q) {
@@ -626,10 +631,11 @@ hipError_t leaf_lu(T *a, int64_t lda, int b, T *Linv, T *Uinv, int64_t k0, DevSt
                    hipStream_t s) {
     if (b < 1 || b > kLeaf) return hipErrorInvalidValue;
     if (piv)
-        hipLaunchKernelGGL((k_leaf_lu<T, true>), dim3(1), dim3(256), 0, s, a, lda, b, k0, st, piv);
+        hipLaunchKernelGGL((k_leaf_lu<T, true>), dim3(1), dim3(kLeafThreads), 0, s, a, lda, b, k0,
+                           st, piv);
     else
-        hipLaunchKernelGGL((k_leaf_lu<T, false>), dim3(1), dim3(256), 0, s, a, lda, b, k0, st,
-                           piv);
+        hipLaunchKernelGGL((k_leaf_lu<T, false>), dim3(1), dim3(kLeafThreads), 0, s, a, lda, b, k0,
+                           st, piv);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k_diag_inv<T>, dim3(1), dim3(512), 0, s, a, lda, b, Linv, Uinv, st);
