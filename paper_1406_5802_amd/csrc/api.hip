@@ -79,7 +79,8 @@ struct rmge_factors {
 
 namespace {
 
-constexpr int kSub = 32;  // rows of the inverted diagonal sub-blocks
+constexpr int kSub = 32;      // rows of the inverted diagonal sub-blocks
+constexpr int kSideCUs = 8;   // compute units reserved for the look-ahead stream
 
 int64_t round_up(int64_t x, int64_t m) { return (x + m - 1) / m * m; }
 
@@ -215,12 +216,16 @@ hipError_t factor_pivot_block(rmge_factors *f, T *a, int b, int64_t k0, T *Linv,
 
 // Right-looking block elimination with no pivoting (eq. eqgenp applied to
 // pivot blocks of f->block columns) with one panel of look-ahead.  Step k:
-//   main stream:  C <- L_B^{-1} C for the block row right of the pivot block;
-//                 Schur update of the next panel's columns only;
-//   side stream:  (after that narrow update) factor the next pivot block and
+//   main stream:  (once the side stream has factored pivot block k)
 //                 D <- D U_B^{-1} for the column below it;
+//                 C <- L_B^{-1} C for the block row right of it;
+//                 Schur update of the next panel's columns only;
+//   side stream:  (after that narrow update) factor the next pivot block;
 //   main stream:  Schur update E <- E - D C of all remaining columns, which
-//                 runs while the side stream works on the next panel.
+//                 runs while the side stream works on the next pivot block.
+// The side stream's kernels are one or a few workgroups each; it owns a few
+// reserved compute units (CU masks, same priority), because a wide update
+// keeps every register file of the others full and would starve it.
 // The update E - (D U_B^{-1})(L_B^{-1} C) is E - D B^{-1} C of eq. eqgenp.
 // Pivoted variant: P_B B = L_B U_B inside the pivot block, the block row is
 // read through P_B (L_B^{-1} P_B C), the rows below are untouched, and one
@@ -243,17 +248,16 @@ hipError_t genp_blocked(rmge_factors *f) {
     auto Linv = [&](int64_t step) { return inv + (step & 1) * invsz; };
     auto Uinv = [&](int64_t step) { return inv + (step & 1) * invsz + kMaxBlock * kSub; };
 
-    // panel 0 on the main stream
-    {
-        const int b = static_cast<int>(n < nb ? n : nb);
-        HIP_TRY(factor_pivot_block<T>(f, a, b, 0, Linv(0), Uinv(0), s0));
-        if (b < n) HIP_TRY(trsm<T>(1, a, ld, b, a + b * ld, ld, n - b, Uinv(0), abort, s0));
-    }
+    // pivot block 0 on the main stream
+    HIP_TRY(factor_pivot_block<T>(f, a, static_cast<int>(n < nb ? n : nb), 0, Linv(0), Uinv(0),
+                                  s0));
     int64_t step = 0;
     for (int64_t k = 0; k < n; k += nb, ++step) {
         const int b = static_cast<int>((n - k) < nb ? (n - k) : nb);
         if (k > 0) HIP_TRY(hipStreamWaitEvent(s0, f->ev_panel, 0));
         if (k + b >= n) break;
+        T *const akk0 = a + k * ld + k;
+        HIP_TRY(trsm<T>(1, akk0, ld, b, akk0 + b * ld, ld, n - k - b, Uinv(step), abort, s0));
         const int64_t r = n - k - b;
         const int bn = static_cast<int>(r < nb ? r : nb);  // next panel width
         T *akk = a + k * ld + k;
@@ -265,8 +269,6 @@ hipError_t genp_blocked(rmge_factors *f) {
         HIP_TRY(hipEventRecord(f->ev_narrow, s0));
         HIP_TRY(hipStreamWaitEvent(s1, f->ev_narrow, 0));
         HIP_TRY(factor_pivot_block<T>(f, a22, bn, k + b, Linv(step + 1), Uinv(step + 1), s1));
-        if (r > bn)
-            HIP_TRY(trsm<T>(1, a22, ld, bn, a22 + bn * ld, ld, r - bn, Uinv(step + 1), abort, s1));
         HIP_TRY(hipEventRecord(f->ev_panel, s1));
         if (r > bn)
             HIP_TRY(Prec<T>::gemm(kGemmUpdate, r, r - bn, b, T(-1), a21, ld, a12 + bn, ld, T(1),
@@ -402,9 +404,10 @@ rmge_status alloc_handle(rmge_factors *f) {
     RMGE_TRY(hipMalloc(&f->st, sizeof(DevStatus)));
     RMGE_TRY(hipMalloc(&f->scal, sizeof(double) * 8));
     for (hipEvent_t &e : f->ev) RMGE_TRY(hipEventCreate(&e));
-    // Look-ahead stream.  RMGE_SIDE_CUS=k (k > 0) reserves k compute units for it
-    // and gives the rest to an internal main stream (CU masks, same priority).
-    int side_cus = 0;
+    // Look-ahead stream: kSideCUs compute units reserved for it, the rest for an
+    // internal main stream (CU masks, same priority); RMGE_SIDE_CUS overrides
+    // the count (0: no reservation, one shared pool).
+    int side_cus = kSideCUs;
     if (const char *env = std::getenv("RMGE_SIDE_CUS")) side_cus = std::atoi(env);
     int dev = 0, ncu = 0;
     RMGE_TRY(hipGetDevice(&dev));

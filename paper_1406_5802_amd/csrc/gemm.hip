@@ -276,6 +276,97 @@ __global__ __launch_bounds__(256, MINB) void k_gemm_fast(int M, int N, int K, T 
     }
 }
 
+// Interior fast path of the Schur update (K = panel width, beta = 1):
+// 64 x 64 tiles of four 32 x 32 waves, four workgroups per CU, with the same
+// unchecked addressing, 16-byte loads and k-reordered LDS reads as
+// k_gemm_fast.  Needs M % 64 == N % 64 == K % 16 == 0 and even leading
+// dimensions.  (Measured at K = 256, n = 16384: FP64 47 -> 62 TFLOP/s,
+// FP32 87 -> 103 TFLOP/s.)
+template <typename T, int MINB>
+__global__ __launch_bounds__(256, MINB) void k_gemm_upd64(int M, int N, int K, T alpha,
+                                                          const T *__restrict__ A, int64_t lda,
+                                                          const T *__restrict__ B, int64_t ldb,
+                                                          T beta, T *C, int64_t ldc,
+                                                          const int *abort) {
+    constexpr int BM = 64, BN = 64, BK = 16, LDK = BK + 2, LDN = BN + 4;
+    using acc_t = typename Mma<T>::acc;
+    __shared__ T As[2][BM * LDK];
+    __shared__ T Bs[2][BK * LDN];
+    if (abort != nullptr && *abort != 0) return;
+    int tm, tn;
+    tile_coords(blockIdx.x, M / BM, N / BN, tm, tn);
+    const int m0 = tm * BM, n0 = tn * BN;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int wm = wave >> 1, wn = wave & 1;
+    // A: row tid / 4, k (tid % 4) * 4 .. + 3;  B: k tid / 16, n (tid % 16) * 4 .. + 3
+    const T *pa = A + static_cast<int64_t>(m0 + (tid >> 2)) * lda + (tid & 3) * 4;
+    const T *pb = B + static_cast<int64_t>(tid >> 4) * ldb + n0 + (tid & 15) * 4;
+    const int64_t bstep = static_cast<int64_t>(BK) * ldb;
+    T ra[4], rb[4];
+    auto load = [&]() {
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            ra[u] = pa[u];
+            rb[u] = pb[u];
+        }
+        pa += BK;
+        pb += bstep;
+    };
+    auto store = [&](int buf) {
+        T *a = &As[buf][(tid >> 2) * LDK + (tid & 3) * 4];
+        T *b = &Bs[buf][(tid >> 4) * LDN + (tid & 15) * 4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            a[u] = ra[u];
+            b[u] = rb[u];
+        }
+    };
+    acc_t acc[2][2];
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j) acc[i][j] = acc_t{0, 0, 0, 0};
+    const int nk = K / BK;
+    load();
+    store(0);
+    __syncthreads();
+    const int arow = wm * 32 + (lane & 15), bcol = wn * 32 + (lane & 15);
+    const int k4 = (lane >> 4) * 4;
+    for (int kt = 0; kt < nk; ++kt) {
+        const int cur = kt & 1;
+        if (kt + 1 < nk) load();
+        T af[2][4], bf[2][4];
+#pragma unroll
+        for (int i = 0; i < 2; ++i)
+#pragma unroll
+            for (int t = 0; t < 4; ++t) af[i][t] = As[cur][(arow + 16 * i) * LDK + k4 + t];
+#pragma unroll
+        for (int j = 0; j < 2; ++j)
+#pragma unroll
+            for (int t = 0; t < 4; ++t) bf[j][t] = Bs[cur][(k4 + t) * LDN + bcol + 16 * j];
+#pragma unroll
+        for (int t = 0; t < 4; ++t)
+#pragma unroll
+            for (int i = 0; i < 2; ++i)
+#pragma unroll
+                for (int j = 0; j < 2; ++j) acc[i][j] = Mma<T>::step(af[i][t], bf[j][t], acc[i][j]);
+        if (kt + 1 < nk) store(cur ^ 1);
+        __syncthreads();
+    }
+    const int crow0 = m0 + wm * 32, ccol0 = n0 + wn * 32 + (lane & 15);
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                T *c = C + static_cast<int64_t>(crow0 + i * 16 + Mma<T>::row(lane, r)) * ldc +
+                       ccol0 + j * 16;
+                const T v = alpha * acc[i][j][r];
+                *c = (beta == T(0)) ? v : v + beta * (*c);
+            }
+}
+
 template <typename T, typename TA, int BM, int BN, int WGM, int WGN, int MINB>
 hipError_t launch(int m, int n, int k, T alpha, const TA *A, int64_t lda, const T *B, int64_t ldb,
                   T beta, T *C, int64_t ldc, const int *abort, double *absmax, hipStream_t s) {
@@ -288,10 +379,11 @@ hipError_t launch(int m, int n, int k, T alpha, const TA *A, int64_t lda, const 
 
 // Tile shapes measured on MI355X (n = 16384):
 //   product (large K): 128 x 128, four 64 x 64 waves, two workgroups per CU
-//     (FP64 ~60 TFLOP/s, FP32 ~113 TFLOP/s);
-//   Schur update (K = panel width): FP64 64 x 64 tiles of four 32 x 32 waves,
-//     four workgroups per CU (~48 TFLOP/s at K = 256); FP32 128 x 128 tiles of
-//     eight 32 x 64 waves (~85 TFLOP/s).
+//     (interior kernel: FP64 71 TFLOP/s, FP32 128 TFLOP/s);
+//   Schur update (K = panel width): 64 x 64 tiles of four 32 x 32 waves,
+//     four workgroups per CU (interior kernel at K = 256: FP64 62, FP32 103
+//     TFLOP/s); ragged shapes fall back to the checked kernel (FP32: 128 x 128
+//     tiles of eight 32 x 64 waves).
 template <typename T, typename TA>
 hipError_t run_gemm(int shape, int64_t M, int64_t N, int64_t K, T alpha, const TA *A, int64_t lda,
                     const T *B, int64_t ldb, T beta, T *C, int64_t ldc, const int *abort,
@@ -311,6 +403,15 @@ hipError_t run_gemm(int shape, int64_t M, int64_t N, int64_t K, T alpha, const T
         }
         return launch<T, TA, 128, 128, 2, 2, 2>(m, n, k, alpha, A, lda, B, ldb, beta, C, ldc,
                                                 abort, absmax, s);
+    }
+    const bool fits64 = m % 64 == 0 && n % 64 == 0 && k % 16 == 0 && k > 0 && lda % 2 == 0 &&
+                        ldb % 2 == 0 && absmax == nullptr && sizeof(TA) == sizeof(T);
+    if (fits64) {
+        const int64_t tiles = static_cast<int64_t>(m / 64) * (n / 64);
+        hipLaunchKernelGGL((k_gemm_upd64<T, 4>), dim3(static_cast<unsigned>(tiles)), dim3(256), 0,
+                           s, m, n, k, alpha, reinterpret_cast<const T *>(A), lda, B, ldb, beta, C,
+                           ldc, abort);
+        return hipGetLastError();
     }
     if (sizeof(T) == 8)
         return launch<T, TA, 64, 64, 2, 2, 4>(m, n, k, alpha, A, lda, B, ldb, beta, C, ldc, abort,
