@@ -38,13 +38,14 @@ METRIC = "factor+solve TFLOP/s n=16384: FP64 vs FP32 MFMA+IR at equal bwd error"
 PEAK = {"f64": 78.6, "f32": 157.3}  # MI355X dense MFMA TFLOP/s
 ETA_TARGET = 1e-14
 
-# HBM bytes of one FP64 product launch at n = 16384, from rocprofv3 FETCH_SIZE and
-# WRITE_SIZE passes scaled by a plain-copy calibration (FETCH x 2.000, WRITE x 1.000);
-# profiles/k_gemm_product_f64_n16384_hbm_traffic.txt.  Valid only for the kernel source
+# HBM bytes of one product launch at n = 16384, from rocprofv3 FETCH_SIZE and WRITE_SIZE
+# passes scaled by a plain-copy calibration (FETCH x 2.000, WRITE x 1.000);
+# profiles/k_gemm_fast_product_n16384_hbm_traffic.txt.  Valid only for the kernel source
 # those counters were taken on.
 TRAFFIC = {"n": 16384, "source": "paper_1406_5802_amd/csrc/gemm.hip",
-           "sha256": "16848a0f23a5bd5917e7f73417eb6c7cc5bd11d4542b705535f1bd8b22f00957",
-           "fetch_kib": (59230758.0 + 59453597.8125) / 2 * 2.000, "write_kib": 2099200.0 * 1.000}
+           "sha256": "3aa85a896b6e918cc67d59139e020675fd94fe30ee1343a74ad0e9005bf6b837",
+           "f64": {"fetch_kib": 345409206.3, "write_kib": 2099200.0},
+           "f32": {"fetch_kib": 318070248.4, "write_kib": 1075379.0}}
 
 
 def log(msg):
@@ -111,16 +112,18 @@ def run_path(rmge, torch, A, b, name, seed, steps, warmup, block, max_refine, ma
     }
 
 
-def product_traffic(n, head):
-    """Counter-measured HBM bytes per product launch, or None if they do not apply."""
+def product_traffic(n, prec):
+    """Counter-measured HBM bytes per product launch ("f64" or "f32"), or None if they do
+    not apply (another size, or the kernel source changed since the counters were taken)."""
     import hashlib
 
-    if n != TRAFFIC["n"] or head != "f64":
+    if n != TRAFFIC["n"]:
         return None
     with open(os.path.join(ROOT, TRAFFIC["source"]), "rb") as fh:
         if hashlib.sha256(fh.read()).hexdigest() != TRAFFIC["sha256"]:
             return None
-    return (TRAFFIC["fetch_kib"] + TRAFFIC["write_kib"]) * 1024.0
+    t = TRAFFIC[prec]
+    return (t["fetch_kib"] + t["write_kib"]) * 1024.0
 
 
 def cpu_baseline(n_cpu, seed, local_pivot_block=0):
@@ -163,7 +166,7 @@ def main():
     ap.add_argument("--seed", type=int, default=1)
     ap.add_argument("--block", type=int, default=256)
     ap.add_argument("--max-refine", type=int, default=16)
-    ap.add_argument("--paths", default="f64,f32,f64p,f32p,f32g,f32pg")
+    ap.add_argument("--paths", default="f64,f32,f64p,f32p,f32pg")
     ap.add_argument("--max-iters", type=int, default=200, help="GMRES inner iterations in all")
     ap.add_argument("--cpu-n", type=int, default=4096)
     ap.add_argument("--no-cpu", action="store_true")
@@ -236,7 +239,8 @@ def main():
                      "frac": round(achieved / PEAK["f32" if fp32 else "f64"], 4),
                      "traffic": product_traffic(n, "f32" if fp32 else "f64"),
                      "traffic_unit": "bytes/launch",
-                     "kernel": "k_gemm (M = A G)",
+                     "kernel": "k_gemm_fast<%s> (M = A G)" % ("float, double" if fp32
+                                                               else "double, double"),
                      "ms_per_launch": round(r["ms_product"], 4)},
         "executed_tflops": round((flops + prod_flops) / (r["ms_per_step"] * 1e-3) / 1e12, 3),
         "paths": {k: {kk: (float("%.6g" % vv) if isinstance(vv, float) else vv)
