@@ -155,19 +155,33 @@ rmge_status rmge_solve(const rmge_factors *f, const double *B, int64_t nrhs, int
  * least-squares residual estimate drops below tol (||A||_inf ||x||_inf +
  * ||b||_inf) / 2 or `restart` vectors are used; x += Z y.  Stops when
  * eta <= tol or after max_iters inner iterations in all.
+ * trans = 1 solves the adjoint system A^T x = b the same way (operator A^T,
+ * preconditioner P^T L^{-T} U^{-T} H^T, eta with ||A||_1).
  * restart: 1..64.  tol > 0.  st->iters counts inner iterations;
  * st->eta_hist holds eta at each outer check (first 17).  Returns
  * RMGE_NOT_CONVERGED if some right-hand side ends above tol.  Workspace:
  * (2 restart + 2) n doubles, kept by the handle. */
-rmge_status rmge_solve_gmres(const rmge_factors *f, const double *B, int64_t nrhs, int64_t ldb,
-                             double *X, int64_t ldx, int32_t max_iters, int32_t restart,
-                             double tol, rmge_solve_stats *st);
+rmge_status rmge_solve_gmres(const rmge_factors *f, int32_t trans, const double *B, int64_t nrhs,
+                             int64_t ldb, double *X, int64_t ldx, int32_t max_iters,
+                             int32_t restart, double tol, rmge_solve_stats *st);
 
 /* Y = A^{-T} W = L^{-T} U^{-T} H^T W (the adjoint, from A^{-1} = H (A H)^{-1},
  * Fact faprepr; P^T L^{-T} U^{-T} H^T W when pivoted).  Reuses L and U.
  * W, Y: device, n x nrhs, row-major. */
 rmge_status rmge_solve_adjoint(const rmge_factors *f, const double *W, int64_t nrhs, int64_t ldw,
                                double *Y, int64_t ldy);
+
+/* The adjoint with FP64 refinement: Y = A^{-T} W as above, then while
+ * step < max_refine and (tol <= 0 or eta > tol):
+ *     R = W - A^T Y (FP64);  Y += P^T L^{-T} U^{-T} H^T R,
+ * with eta = max_r ||R_r||_inf / (||A||_1 ||Y_r||_inf + ||W_r||_inf) (the normwise
+ * backward error of A^T y = w).  For FP32 factors the plain adjoint carries the
+ * factors' accuracy only; this is how it reaches FP64 accuracy.  W, Y: device,
+ * n x nrhs, Y may not alias W, max_refine <= 16, st may be NULL.  Returns
+ * RMGE_NOT_CONVERGED if tol > 0 and eta > tol after max_refine steps. */
+rmge_status rmge_solve_adjoint_ex(const rmge_factors *f, const double *W, int64_t nrhs,
+                                  int64_t ldw, double *Y, int64_t ldy, int32_t max_refine,
+                                  double tol, rmge_solve_stats *st);
 
 /* Factor statistics.  min_abs_pivot and growth are computed on the device at
  * the first call (one pass over M's diagonal and U) and cached. */

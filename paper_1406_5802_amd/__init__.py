@@ -117,8 +117,9 @@ class Factors:
         return (X.reshape(-1) if vec else X), stats
 
     def solve_gmres(self, B, max_iters=200, restart=32, tol=1e-14, out=None,
-                    raise_on_not_converged=False):
-        """X = A^{-1} B with GMRES-based refinement preconditioned by the factors."""
+                    raise_on_not_converged=False, trans=False):
+        """X = A^{-1} B (A^{-T} B with trans) with GMRES-based refinement preconditioned by
+        the factors."""
         import torch
 
         vec = B.dim() == 1
@@ -127,8 +128,9 @@ class Factors:
         nrhs = B2.shape[1]
         X = out if out is not None else torch.empty((self.n, nrhs), dtype=torch.float64,
                                                     device=B.device)
-        rc, st = _rmge.rmge_solve_gmres(self._h, B2.data_ptr(), nrhs, B2.stride(0), X.data_ptr(),
-                                        X.stride(0), max_iters, restart, tol)
+        rc, st = _rmge.rmge_solve_gmres(self._h, 1 if trans else 0, B2.data_ptr(), nrhs,
+                                        B2.stride(0), X.data_ptr(), X.stride(0), max_iters,
+                                        restart, tol)
         if rc not in (_rmge.RMGE_OK, _rmge.RMGE_NOT_CONVERGED) or (
                 raise_on_not_converged and rc == _rmge.RMGE_NOT_CONVERGED):
             raise RMGEError(rc, "rmge_solve_gmres")
@@ -152,6 +154,25 @@ class Factors:
         if rc:
             raise RMGEError(rc, "rmge_solve_adjoint")
         return Y.reshape(-1) if vec else Y
+
+    def solve_adjoint_refined(self, W, max_refine=16, tol=1e-14, out=None):
+        """Y = A^{-T} W with FP64 refinement.  Returns (Y, stats dict)."""
+        import torch
+
+        vec = W.dim() == 1
+        W2 = W.reshape(-1, 1) if vec else W
+        _check_matrix(W2, "W")
+        nrhs = W2.shape[1]
+        Y = out if out is not None else torch.empty((self.n, nrhs), dtype=torch.float64,
+                                                    device=W.device)
+        rc, st = _rmge.rmge_solve_adjoint_ex(self._h, W2.data_ptr(), nrhs, W2.stride(0),
+                                             Y.data_ptr(), Y.stride(0), max_refine, tol)
+        if rc not in (_rmge.RMGE_OK, _rmge.RMGE_NOT_CONVERGED):
+            raise RMGEError(rc, "rmge_solve_adjoint_ex")
+        stats = {"status": rc, "iters": st.iters, "converged": bool(st.converged),
+                 "eta0": st.eta0, "eta": st.eta,
+                 "eta_hist": [st.eta_hist[i] for i in range(st.iters + 1)]}
+        return (Y.reshape(-1) if vec else Y), stats
 
     def lu(self):
         """Packed factors as an n x n float64 tensor (unit L below, U on and above)."""

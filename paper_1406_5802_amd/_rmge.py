@@ -25,7 +25,7 @@ STATUS_NAMES = {
 # Every function the header declares, for the export check.
 EXPORTS = (
     "rmge_factor", "rmge_factor_ex", "rmge_factor_pivoted", "rmge_refactor", "rmge_solve",
-    "rmge_solve_gmres", "rmge_solve_adjoint", "rmge_factor_stats_get", "rmge_factors_lu", "rmge_factors_perm",
+    "rmge_solve_gmres", "rmge_solve_adjoint", "rmge_solve_adjoint_ex", "rmge_factor_stats_get", "rmge_factors_lu", "rmge_factors_perm",
     "rmge_multiplier_params", "rmge_param_count", "rmge_precondition", "rmge_destroy",
     "rmge_status_string", "rmge_version",
 )
@@ -67,9 +67,11 @@ def lib() -> ctypes.CDLL:
     L.rmge_refactor.argtypes = [vp, dp, i64, u64]
     L.rmge_solve.argtypes = [vp, dp, i64, i64, dp, i64, i32, ctypes.c_double,
                              ctypes.POINTER(rmge_solve_stats)]
-    L.rmge_solve_gmres.argtypes = [vp, dp, i64, i64, dp, i64, i32, i32, ctypes.c_double,
+    L.rmge_solve_gmres.argtypes = [vp, i32, dp, i64, i64, dp, i64, i32, i32, ctypes.c_double,
                                    ctypes.POINTER(rmge_solve_stats)]
     L.rmge_solve_adjoint.argtypes = [vp, dp, i64, i64, dp, i64]
+    L.rmge_solve_adjoint_ex.argtypes = [vp, dp, i64, i64, dp, i64, i32, ctypes.c_double,
+                                        ctypes.POINTER(rmge_solve_stats)]
     L.rmge_factor_stats_get.argtypes = [vp, ctypes.POINTER(rmge_factor_stats)]
     L.rmge_factors_lu.argtypes = [vp, dp, i64]
     L.rmge_multiplier_params.argtypes = [i32, i64, u64, dp, vp]
@@ -82,7 +84,8 @@ def lib() -> ctypes.CDLL:
     L.rmge_status_string.restype = ctypes.c_char_p
     L.rmge_version.restype = i32
     for name in ("rmge_factor", "rmge_factor_ex", "rmge_factor_pivoted", "rmge_refactor",
-                 "rmge_solve", "rmge_solve_gmres", "rmge_solve_adjoint", "rmge_factor_stats_get",
+                 "rmge_solve", "rmge_solve_gmres", "rmge_solve_adjoint", "rmge_solve_adjoint_ex",
+                 "rmge_factor_stats_get",
                  "rmge_factors_lu",
                  "rmge_factors_perm", "rmge_multiplier_params", "rmge_precondition"):
         getattr(L, name).restype = ctypes.c_int
@@ -136,15 +139,23 @@ def rmge_solve(h, B: int, nrhs: int, ldb: int, X: int, ldx: int, max_refine: int
     return rc, st
 
 
-def rmge_solve_gmres(h, B: int, nrhs: int, ldb: int, X: int, ldx: int, max_iters: int,
-                     restart: int, tol: float):
+def rmge_solve_gmres(h, trans: int, B: int, nrhs: int, ldb: int, X: int, ldx: int,
+                     max_iters: int, restart: int, tol: float):
     st = rmge_solve_stats()
-    rc = lib().rmge_solve_gmres(h, B, nrhs, ldb, X, ldx, max_iters, restart, tol, ctypes.byref(st))
+    rc = lib().rmge_solve_gmres(h, trans, B, nrhs, ldb, X, ldx, max_iters, restart, tol,
+                                ctypes.byref(st))
     return rc, st
 
 
 def rmge_solve_adjoint(h, W: int, nrhs: int, ldw: int, Y: int, ldy: int) -> int:
     return lib().rmge_solve_adjoint(h, W, nrhs, ldw, Y, ldy)
+
+
+def rmge_solve_adjoint_ex(h, W: int, nrhs: int, ldw: int, Y: int, ldy: int, max_refine: int,
+                          tol: float):
+    st = rmge_solve_stats()
+    rc = lib().rmge_solve_adjoint_ex(h, W, nrhs, ldw, Y, ldy, max_refine, tol, ctypes.byref(st))
+    return rc, st
 
 
 def rmge_factor_stats_get(h):

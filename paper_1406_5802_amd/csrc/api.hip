@@ -53,7 +53,7 @@ struct rmge_factors {
     int64_t sinv_rows = 0;
     int *piv = nullptr;  // pivoted variant: P M = L U with row t = row piv[t] of M
     DevStatus *st = nullptr;
-    double *scal = nullptr;  // [0] max|U| [1] min|u_kk| [2] max|M| [3] ||A||_inf
+    double *scal = nullptr;  // [0] max|U| [1] min|u_kk| [2] max|M| [3] ||A||_inf [4] ||A||_1
     // solve workspace
     int64_t ws_nrhs = 0;
     double *wy = nullptr, *wx = nullptr;  // solve vectors (FP64 for every factor type)
@@ -68,8 +68,8 @@ struct rmge_factors {
     // host copies
     DevStatus host_st{-1, 0, 0};
     bool stats_done = false;
-    bool anorm_done = false;
-    double anorm = 0.0;
+    bool anorm_done = false, anorm1_done = false;
+    double anorm = 0.0, anorm1 = 0.0;  // ||A||_inf, ||A||_1 (= ||A^T||_inf)
     rmge_factor_stats stats{};
     hipEvent_t ev[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};
     hipStream_t side = nullptr;  // look-ahead stream (default priority)
@@ -332,6 +332,7 @@ rmge_status run_factor(rmge_factors *f) {
     hipStream_t s = f->stream;
     f->stats_done = false;
     f->anorm_done = false;
+    f->anorm1_done = false;
     hipLaunchKernelGGL(k_reset, dim3(1), dim3(1), 0, s, f->st, f->scal);
     RMGE_TRY(hipGetLastError());
     RMGE_TRY(hipEventRecord(f->ev[0], s));
@@ -448,7 +449,7 @@ rmge_status ensure_solve_ws(rmge_factors *f, int64_t nrhs, bool need_t) {
         RMGE_TRY(hipMalloc(&f->wsync, sizeof(int) * 2));
         RMGE_TRY(hipMemsetAsync(f->wsync, 0, sizeof(int) * 2, f->stream));
     }
-    if (need_t && f->kind == RMGE_MULT_GAUSSIAN) {
+    if (need_t) {
         const int64_t want = ((n + 255) / 256) * n * (nrhs < 16 ? nrhs : 16);
         if (want > f->wt_size) {
             if (f->wt) (void)hipFree(f->wt);
@@ -585,35 +586,97 @@ rmge_status run_solve(rmge_factors *f, const double *B, int64_t nrhs, int64_t ld
     return loc.converged ? RMGE_OK : RMGE_NOT_CONVERGED;
 }
 
+// Y = beta Y + P^T L^{-T} U^{-T} H^T src   (src FP64 n x nrhs, lds)
 template <typename T>
-rmge_status run_adjoint(rmge_factors *f, const double *W, int64_t nrhs, int64_t ldw, double *Y,
-                        int64_t ldy) {
-    rmge_status rs = ensure_solve_ws(f, nrhs, true);
-    if (rs != RMGE_OK) return rs;
+hipError_t apply_adjoint(rmge_factors *f, const double *src, int64_t lds, int64_t nrhs,
+                         double *Y, int64_t ldy, double beta) {
     const int64_t n = f->n;
     hipStream_t s = f->stream;
     double *Z = f->wy;
     switch (f->kind) {
     case RMGE_MULT_NONE:
-        RMGE_TRY((convert_2d<double, double>(W, ldw, Z, nrhs, n, nrhs, s)));
+        HIP_TRY((convert_2d<double, double>(src, lds, Z, nrhs, n, nrhs, s)));
         break;
     case RMGE_MULT_GAUSSIAN:
         for (int64_t g = 0; g < nrhs; g += 16) {
             const int nr = static_cast<int>((nrhs - g) < 16 ? (nrhs - g) : 16);
-            RMGE_TRY((gemv_t<T, double, double>(n, n, static_cast<const T *>(f->G), n, W + g, ldw,
-                                                Z + g, nrhs, nr, f->wt, s)));
+            HIP_TRY((gemv_t<T, double, double>(n, n, static_cast<const T *>(f->G), n, src + g, lds,
+                                               Z + g, nrhs, nr, f->wt, s)));
         }
         break;
     default:
-        RMGE_TRY((fft_rows<double, double>(W, 1, ldw, nrhs, n, f->m, f->tw, f->hhat, 1, 0.0, Z, 1,
-                                           nrhs, s)));
+        HIP_TRY((fft_rows<double, double>(src, 1, lds, nrhs, n, f->m, f->tw, f->hhat, 1, 0.0, Z, 1,
+                                          nrhs, s)));
     }
-    RMGE_TRY(tri_solves<T>(f, nrhs, true));
-    // Y = P^T (L^{-T} U^{-T} H^T W): row t goes back to row piv[t]
-    RMGE_TRY((convert_2d<double, double>(Z, nrhs, Y, ldy, n, nrhs, s, nullptr,
-                                         f->pivot ? f->piv : nullptr)));
+    HIP_TRY(tri_solves<T>(f, nrhs, true));
+    // row t of the solution goes back to row piv[t]
+    return axpby_2d<double>(Z, nrhs, Y, ldy, n, static_cast<int>(nrhs), beta, s,
+                            f->pivot ? f->piv : nullptr);
+}
+
+// R = W - A^T Y; eta = max_r ||R_r||_inf / (||A^T||_inf ||Y_r||_inf + ||W_r||_inf).
+rmge_status adjoint_residual_eta(rmge_factors *f, const double *W, int64_t ldw, int64_t nrhs,
+                                 const double *Y, int64_t ldy, double *eta) {
+    const int64_t n = f->n;
+    hipStream_t s = f->stream;
+    double *R = f->wr, *nrm = f->wnorm;
+    for (int64_t g = 0; g < nrhs; g += 16) {
+        const int nr = static_cast<int>((nrhs - g) < 16 ? (nrhs - g) : 16);
+        RMGE_TRY((gemv_t<double, double, double>(n, n, f->A, f->lda, Y + g, ldy, R + g, nrhs, nr,
+                                                 f->wt, s)));
+    }
+    RMGE_TRY(axpby_2d<double>(W, ldw, R, nrhs, n, static_cast<int>(nrhs), -1.0, s));
+    RMGE_TRY(fill_f64(nrm, 3 * nrhs, 0.0, s));
+    RMGE_TRY(colmax_abs(R, nrhs, n, static_cast<int>(nrhs), nrm, s));
+    RMGE_TRY(colmax_abs(Y, ldy, n, static_cast<int>(nrhs), nrm + nrhs, s));
+    RMGE_TRY(colmax_abs(W, ldw, n, static_cast<int>(nrhs), nrm + 2 * nrhs, s));
+    if (!f->anorm1_done) {
+        RMGE_TRY(fill_f64(f->scal + 4, 1, 0.0, s));
+        RMGE_TRY(norm_one(f->A, f->lda, n, f->wt, f->scal + 4, s));
+    }
+    std::vector<double> h(static_cast<size_t>(3 * nrhs));
+    RMGE_TRY(hipMemcpyAsync(h.data(), nrm, sizeof(double) * 3 * nrhs, hipMemcpyDeviceToHost, s));
+    if (!f->anorm1_done)
+        RMGE_TRY(hipMemcpyAsync(&f->anorm1, f->scal + 4, sizeof(double), hipMemcpyDeviceToHost, s));
     RMGE_TRY(hipStreamSynchronize(s));
-    return solve_sync_error(f);
+    f->anorm1_done = true;
+    double worst = 0.0;
+    for (int64_t r = 0; r < nrhs; ++r) {
+        const double e = h[r] / (f->anorm1 * h[nrhs + r] + h[2 * nrhs + r]);
+        if (e > worst || e != e) worst = e;
+    }
+    *eta = worst;
+    return RMGE_OK;
+}
+
+template <typename T>
+rmge_status run_adjoint(rmge_factors *f, const double *W, int64_t nrhs, int64_t ldw, double *Y,
+                        int64_t ldy, int32_t max_refine, double tol, rmge_solve_stats *st) {
+    rmge_status rs = ensure_solve_ws(f, nrhs, true);
+    if (rs != RMGE_OK) return rs;
+    RMGE_TRY(apply_adjoint<T>(f, W, ldw, nrhs, Y, ldy, 0.0));
+    if (!st && max_refine == 0) {  // plain adjoint application
+        RMGE_TRY(hipStreamSynchronize(f->stream));
+        return solve_sync_error(f);
+    }
+    double eta = 0.0;
+    if ((rs = adjoint_residual_eta(f, W, ldw, nrhs, Y, ldy, &eta)) != RMGE_OK) return rs;
+    rmge_solve_stats loc{};
+    loc.eta0 = eta;
+    loc.eta_hist[0] = eta;
+    int it = 0;
+    while (it < max_refine && !(tol > 0.0 && eta <= tol)) {
+        RMGE_TRY(apply_adjoint<T>(f, f->wr, nrhs, nrhs, Y, ldy, 1.0));
+        ++it;
+        if ((rs = adjoint_residual_eta(f, W, ldw, nrhs, Y, ldy, &eta)) != RMGE_OK) return rs;
+        loc.eta_hist[it] = eta;
+    }
+    if ((rs = solve_sync_error(f)) != RMGE_OK) return rs;
+    loc.iters = it;
+    loc.eta = eta;
+    loc.converged = (tol <= 0.0 || eta <= tol) ? 1 : 0;
+    if (st) *st = loc;
+    return loc.converged ? RMGE_OK : RMGE_NOT_CONVERGED;
 }
 
 // ------------------------------------------------------------- GMRES-IR
@@ -623,7 +686,8 @@ rmge_status run_adjoint(rmge_factors *f, const double *W, int64_t nrhs, int64_t 
 // Krylov iterations on A d = r with z_j = H U^{-1} L^{-1} P v_j (the same
 // application of the preprocessed inverse as one classical refinement step),
 // w = A z_j, classical Gram-Schmidt applied twice, Givens rotations on the
-// host; then x += Z y.  The FP64 basis makes the iteration converge when the
+// host; then x += Z y.  The transposed system A^T y = w runs the same way with
+// A^T and the adjoint application P^T L^{-T} U^{-T} H^T.  The FP64 basis makes the iteration converge when the
 // factors are too inaccurate for classical refinement to contract (large
 // growth, or kappa(A H) u_factor near 1).
 
@@ -642,11 +706,13 @@ rmge_status ensure_krylov_ws(rmge_factors *f, int restart) {
     return RMGE_OK;
 }
 
+// trans = 0: A x = b with the preconditioner H U^{-1} L^{-1} P;
+// trans = 1: A^T y = w with the preconditioner P^T L^{-T} U^{-T} H^T.
 template <typename T>
-rmge_status run_gmres(rmge_factors *f, const double *B, int64_t nrhs, int64_t ldb, double *X,
-                      int64_t ldx, int32_t max_iters, int32_t restart, double tol,
+rmge_status run_gmres(rmge_factors *f, bool trans, const double *B, int64_t nrhs, int64_t ldb,
+                      double *X, int64_t ldx, int32_t max_iters, int32_t restart, double tol,
                       rmge_solve_stats *st) {
-    rmge_status rs = ensure_solve_ws(f, nrhs, false);
+    rmge_status rs = ensure_solve_ws(f, nrhs, trans);
     if (rs != RMGE_OK) return rs;
     if ((rs = ensure_krylov_ws(f, restart)) != RMGE_OK) return rs;
     const int64_t n = f->n;
@@ -658,14 +724,40 @@ rmge_status run_gmres(rmge_factors *f, const double *B, int64_t nrhs, int64_t ld
     double *dv = part + 256 * kMaxRestart;         // [0, 64) h, [64, 128) h2, [128] |w|^2,
                                                    // [129 ..] norms; [192, 256) y
     double *hy = dv + 3 * kMaxRestart;
+    auto precond = [&](const double *src, int64_t lds, int64_t nr, double *dst, int64_t ldd) {
+        return trans ? apply_adjoint<T>(f, src, lds, nr, dst, ldd, 0.0)
+                     : apply_inverse<T>(f, src, lds, nr, dst, ldd, 0.0);
+    };
+    // dst = op(A) z for one vector, op(A) = A or A^T
+    auto op = [&](const double *z, int64_t ldz, double *dst) -> hipError_t {
+        if (trans)
+            return gemv_t<double, double, double>(n, n, f->A, f->lda, z, ldz, dst, 1, 1, f->wt,
+                                                  s);
+        return gemv_n<double, double, double>(n, n, 1.0, f->A, f->lda, z, ldz, 0.0, dst, 1, 1, s);
+    };
     // initial solve for every right-hand side (one classical application)
-    RMGE_TRY(apply_inverse<T>(f, B, ldb, nrhs, X, ldx, 0.0));
-    if (!f->anorm_done) {
-        RMGE_TRY(fill_f64(f->scal + 3, 1, 0.0, s));
-        RMGE_TRY(norm_inf(f->A, f->lda, n, f->scal + 3, s));
-        RMGE_TRY(hipMemcpyAsync(&f->anorm, f->scal + 3, sizeof(double), hipMemcpyDeviceToHost, s));
-        RMGE_TRY(hipStreamSynchronize(s));
-        f->anorm_done = true;
+    RMGE_TRY(precond(B, ldb, nrhs, X, ldx));
+    double anorm = 0.0;
+    if (!trans) {
+        if (!f->anorm_done) {
+            RMGE_TRY(fill_f64(f->scal + 3, 1, 0.0, s));
+            RMGE_TRY(norm_inf(f->A, f->lda, n, f->scal + 3, s));
+            RMGE_TRY(hipMemcpyAsync(&f->anorm, f->scal + 3, sizeof(double), hipMemcpyDeviceToHost,
+                                    s));
+            RMGE_TRY(hipStreamSynchronize(s));
+            f->anorm_done = true;
+        }
+        anorm = f->anorm;
+    } else {
+        if (!f->anorm1_done) {
+            RMGE_TRY(fill_f64(f->scal + 4, 1, 0.0, s));
+            RMGE_TRY(norm_one(f->A, f->lda, n, f->wt, f->scal + 4, s));
+            RMGE_TRY(hipMemcpyAsync(&f->anorm1, f->scal + 4, sizeof(double),
+                                    hipMemcpyDeviceToHost, s));
+            RMGE_TRY(hipStreamSynchronize(s));
+            f->anorm1_done = true;
+        }
+        anorm = f->anorm1;
     }
     rmge_solve_stats loc{};
     int hist = 0, total = 0;
@@ -677,10 +769,9 @@ rmge_status run_gmres(rmge_factors *f, const double *B, int64_t nrhs, int64_t ld
         double eta = 0.0;
         bool first = true;
         while (true) {
-            // r = b - A x, eta, ||r||_2
-            RMGE_TRY(scale_copy(R, B + c, ldb, n, 1.0, s));
-            RMGE_TRY((gemv_n<double, double, double>(n, n, -1.0, f->A, f->lda, X + c, ldx, 1.0, R,
-                                                     1, 1, s)));
+            // r = b - op(A) x, eta, ||r||_2
+            RMGE_TRY(op(X + c, ldx, R));
+            RMGE_TRY(axpby_2d<double>(B + c, ldb, R, 1, n, 1, -1.0, s));
             RMGE_TRY(fill_f64(dv + 129, 3, 0.0, s));
             RMGE_TRY(colmax_abs(R, 1, n, 1, dv + 129, s));
             RMGE_TRY(colmax_abs(X + c, ldx, n, 1, dv + 130, s));
@@ -690,7 +781,7 @@ rmge_status run_gmres(rmge_factors *f, const double *B, int64_t nrhs, int64_t ld
                                     hipMemcpyDeviceToHost, s));
             RMGE_TRY(hipStreamSynchronize(s));
             const double rinf = hh[129], xinf = hh[130], binf = hh[131];
-            const double scale = f->anorm * xinf + binf;
+            const double scale = anorm * xinf + binf;
             eta = rinf / scale;
             if (first) {
                 worst0 = (eta > worst0 || eta != eta) ? eta : worst0;
@@ -707,9 +798,8 @@ rmge_status run_gmres(rmge_factors *f, const double *B, int64_t nrhs, int64_t ld
             int k = 0;
             for (int j = 0; j < restart && total < max_iters; ++j) {
                 double *vj = V + j * n, *w = V + (j + 1) * n, *zj = Z + j * n;
-                RMGE_TRY(apply_inverse<T>(f, vj, 1, 1, zj, 1, 0.0));
-                RMGE_TRY((gemv_n<double, double, double>(n, n, 1.0, f->A, f->lda, zj, 1, 0.0, w,
-                                                         1, 1, s)));
+                RMGE_TRY(precond(vj, 1, 1, zj, 1));
+                RMGE_TRY(op(zj, 1, w));
                 RMGE_TRY(mdot(V, n, j + 1, w, part, dv, false, s));
                 RMGE_TRY(lincomb(w, 1, V, n, j + 1, dv, -1.0, s));
                 RMGE_TRY(mdot(V, n, j + 1, w, part, dv + kMaxRestart, false, s));
@@ -845,18 +935,19 @@ rmge_status rmge_solve(const rmge_factors *fc, const double *B, int64_t nrhs, in
                                  : run_solve<double>(f, B, nrhs, ldb, X, ldx, max_refine, tol, st);
 }
 
-rmge_status rmge_solve_gmres(const rmge_factors *fc, const double *B, int64_t nrhs, int64_t ldb,
-                             double *X, int64_t ldx, int32_t max_iters, int32_t restart,
-                             double tol, rmge_solve_stats *st) {
+rmge_status rmge_solve_gmres(const rmge_factors *fc, int32_t trans, const double *B, int64_t nrhs,
+                             int64_t ldb, double *X, int64_t ldx, int32_t max_iters,
+                             int32_t restart, double tol, rmge_solve_stats *st) {
     rmge_factors *f = const_cast<rmge_factors *>(fc);
     if (!f || !B || !X || nrhs < 1 || ldb < nrhs || ldx < nrhs || max_iters < 0 || X == B ||
-        restart < 1 || restart > kMaxRestart || !(tol > 0.0))
+        restart < 1 || restart > kMaxRestart || !(tol > 0.0) || (trans != 0 && trans != 1))
         return RMGE_EINVAL;
     if (f->host_st.code == 4) return RMGE_ZERO_PIVOT;
     if (f->host_st.code == 5) return RMGE_NONFINITE;
     return (f->prec == RMGE_F32)
-               ? run_gmres<float>(f, B, nrhs, ldb, X, ldx, max_iters, restart, tol, st)
-               : run_gmres<double>(f, B, nrhs, ldb, X, ldx, max_iters, restart, tol, st);
+               ? run_gmres<float>(f, trans != 0, B, nrhs, ldb, X, ldx, max_iters, restart, tol, st)
+               : run_gmres<double>(f, trans != 0, B, nrhs, ldb, X, ldx, max_iters, restart, tol,
+                                   st);
 }
 
 rmge_status rmge_solve_adjoint(const rmge_factors *fc, const double *W, int64_t nrhs,
@@ -865,8 +956,23 @@ rmge_status rmge_solve_adjoint(const rmge_factors *fc, const double *W, int64_t 
     if (!f || !W || !Y || nrhs < 1 || ldw < nrhs || ldy < nrhs) return RMGE_EINVAL;
     if (f->host_st.code == 4) return RMGE_ZERO_PIVOT;
     if (f->host_st.code == 5) return RMGE_NONFINITE;
-    return (f->prec == RMGE_F32) ? run_adjoint<float>(f, W, nrhs, ldw, Y, ldy)
-                                 : run_adjoint<double>(f, W, nrhs, ldw, Y, ldy);
+    return (f->prec == RMGE_F32) ? run_adjoint<float>(f, W, nrhs, ldw, Y, ldy, 0, 0.0, nullptr)
+                                 : run_adjoint<double>(f, W, nrhs, ldw, Y, ldy, 0, 0.0, nullptr);
+}
+
+rmge_status rmge_solve_adjoint_ex(const rmge_factors *fc, const double *W, int64_t nrhs,
+                                  int64_t ldw, double *Y, int64_t ldy, int32_t max_refine,
+                                  double tol, rmge_solve_stats *st) {
+    rmge_factors *f = const_cast<rmge_factors *>(fc);
+    if (!f || !W || !Y || nrhs < 1 || ldw < nrhs || ldy < nrhs || W == Y || max_refine < 0 ||
+        max_refine > 16)
+        return RMGE_EINVAL;
+    if (f->host_st.code == 4) return RMGE_ZERO_PIVOT;
+    if (f->host_st.code == 5) return RMGE_NONFINITE;
+    rmge_solve_stats loc{};
+    return (f->prec == RMGE_F32)
+               ? run_adjoint<float>(f, W, nrhs, ldw, Y, ldy, max_refine, tol, st ? st : &loc)
+               : run_adjoint<double>(f, W, nrhs, ldw, Y, ldy, max_refine, tol, st ? st : &loc);
 }
 
 rmge_status rmge_factor_stats_get(const rmge_factors *fc, rmge_factor_stats *s) {

@@ -139,10 +139,15 @@ hipError_t colmax_abs(const double *v, int64_t ld, int64_t n, int nrhs, double *
                       hipStream_t s);
 // out[0] = max_i sum_j |A[i][j]|.
 hipError_t norm_inf(const double *A, int64_t lda, int64_t n, double *out, hipStream_t s);
-// x = beta x + d (both n x nrhs, own leading dimensions)
+// x = beta x + d (both n x nrhs, own leading dimensions); with `scatter`, row i of d
+// goes to row scatter[i] of x.
 template <typename TS>
 hipError_t axpby_2d(const TS *d, int64_t ldd, double *x, int64_t ldx, int64_t n, int nrhs,
-                    double beta, hipStream_t s);
+                    double beta, hipStream_t s, const int *scatter = nullptr);
+// out[0] = max(out[0], ||A||_1) (max column sum of |A|; out preset to 0).
+// work: >= ceil(n / 256) * n doubles.
+hipError_t norm_one(const double *A, int64_t lda, int64_t n, double *work, double *out,
+                    hipStream_t s);
 hipError_t fill_f64(double *p, int64_t count, double value, hipStream_t s);
 
 // ---------------------------------------------------------------- fft.hip

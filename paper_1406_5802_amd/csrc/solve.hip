@@ -402,6 +402,31 @@ __global__ __launch_bounds__(256) void k_colmax(const double *v, int64_t ld, int
     if ((threadIdx.x & 63) == 0) atomic_max_nonneg(norms + r, m);
 }
 
+// work[chunk][c] = sum over the chunk's 256 rows i of |A[i][c]| (pass 1 of ||A||_1).
+__global__ __launch_bounds__(256) void k_colabs_part(int64_t rows, int64_t cols, const double *A,
+                                                     int64_t lda, double *work) {
+    const int64_t i0 = static_cast<int64_t>(blockIdx.y) * 256;
+    const int64_t c = static_cast<int64_t>(blockIdx.x) * 256 + threadIdx.x;
+    if (c >= cols) return;
+    const int64_t i1 = (i0 + 256) < rows ? (i0 + 256) : rows;
+    double acc = 0.0;
+    for (int64_t i = i0; i < i1; ++i) acc += fabs(A[i * lda + c]);
+    work[static_cast<int64_t>(blockIdx.y) * cols + c] = acc;
+}
+
+// out[0] = max(out[0], max_c sum_chunks work[chunk][c]).
+__global__ void k_colabs_max(int64_t chunks, int64_t cols, const double *work, double *out) {
+    double m = 0.0;
+    for (int64_t c = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x; c < cols;
+         c += static_cast<int64_t>(gridDim.x) * blockDim.x) {
+        double sum = 0.0;
+        for (int64_t k = 0; k < chunks; ++k) sum += work[k * cols + c];
+        m = fmax(m, sum);
+    }
+    for (int off = 32; off > 0; off >>= 1) m = fmax(m, __shfl_xor(m, off));
+    if ((threadIdx.x & 63) == 0) atomic_max_nonneg(out, m);
+}
+
 // out[0] = max(out[0], max_i sum_j |A[i][j]|); one wave per row.
 __global__ __launch_bounds__(256) void k_norm_inf(const double *A, int64_t lda, int64_t n,
                                                   double *out) {
@@ -414,15 +439,16 @@ __global__ __launch_bounds__(256) void k_norm_inf(const double *A, int64_t lda, 
     if (lane == 0) atomic_max_nonneg(out, s);
 }
 
+// x[row] = beta x[row] + d[i] with row = scatter ? scatter[i] : i.
 template <typename TS>
 __global__ void k_axpby_2d(const TS *d, int64_t ldd, double *x, int64_t ldx, int64_t n, int nrhs,
-                           double beta) {
+                           double beta, const int *scatter) {
     const int64_t total = n * nrhs;
     for (int64_t e = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x; e < total;
          e += static_cast<int64_t>(gridDim.x) * blockDim.x) {
         const int64_t i = e / nrhs, r = e % nrhs;
         const double v = static_cast<double>(d[i * ldd + r]);
-        double *p = x + i * ldx + r;
+        double *p = x + (scatter ? static_cast<int64_t>(scatter[i]) : i) * ldx + r;
         *p = (beta == 0.0) ? v : beta * (*p) + v;
     }
 }
@@ -590,10 +616,23 @@ hipError_t norm_inf(const double *A, int64_t lda, int64_t n, double *out, hipStr
 
 template <typename TS>
 hipError_t axpby_2d(const TS *d, int64_t ldd, double *x, int64_t ldx, int64_t n, int nrhs,
-                    double beta, hipStream_t s) {
+                    double beta, hipStream_t s, const int *scatter) {
     if (n <= 0 || nrhs <= 0) return hipSuccess;
     hipLaunchKernelGGL(k_axpby_2d<TS>, dim3(grid_for(n * nrhs, 256)), dim3(256), 0, s, d, ldd, x,
-                       ldx, n, nrhs, beta);
+                       ldx, n, nrhs, beta, scatter);
+    return hipGetLastError();
+}
+
+hipError_t norm_one(const double *A, int64_t lda, int64_t n, double *work, double *out,
+                    hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+    const int64_t chunks = (n + 255) / 256;
+    dim3 grid(static_cast<unsigned>((n + 255) / 256), static_cast<unsigned>(chunks));
+    hipLaunchKernelGGL(k_colabs_part, grid, dim3(256), 0, s, n, n, A, lda, work);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_colabs_max, dim3(grid_for(n, 256)), dim3(256), 0, s, chunks, n, work,
+                       out);
     return hipGetLastError();
 }
 
@@ -655,8 +694,8 @@ template hipError_t gemv_t<float, double, double>(int64_t, int64_t, const float 
                                                   const double *, int64_t, double *, int64_t, int,
                                                   double *, hipStream_t);
 template hipError_t axpby_2d<double>(const double *, int64_t, double *, int64_t, int64_t, int,
-                                     double, hipStream_t);
+                                     double, hipStream_t, const int *);
 template hipError_t axpby_2d<float>(const float *, int64_t, double *, int64_t, int64_t, int, double,
-                                    hipStream_t);
+                                    hipStream_t, const int *);
 
 }  // namespace rmge

@@ -78,3 +78,18 @@ def test_gmres_iteration_cap_and_restart(rmge):
     assert st["converged"] and st["eta"] <= 1e-14, st
     assert st["iters"] <= 300
     _check(X, A, b, rmge.CIRCULANT, 5, kappa, st["eta"])
+
+
+@pytest.mark.parametrize("kind", [1, 2, 3])
+@pytest.mark.parametrize("prec", ["F64", "F32"])
+def test_gmres_adjoint_matches_oracle(rmge, kind, prec):
+    n, nrhs, kappa = 300, 2, 1e4
+    A = workloads.conditioned(n, kappa, seed=81)
+    W = workloads.rhs(n, nrhs, seed=82)
+    f = rmge.factor(dev(A), kind=kind, seed=6, block=128, prec=getattr(rmge, prec),
+                    pivot=rmge.PIVOT_BLOCK)
+    Y, st = f.solve_gmres(dev(W), max_iters=200, restart=32, tol=1e-14, trans=True)
+    assert st["converged"] and st["eta"] <= 1e-14, st
+    Yo = np.linalg.solve(A.T, W)
+    rel = np.linalg.norm(host(Y) - Yo) / np.linalg.norm(Yo)
+    assert rel <= max(1e-10, 4 * kappa * n * np.finfo(float).eps), rel

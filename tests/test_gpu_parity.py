@@ -233,3 +233,20 @@ def test_block_size_invariance(rmge):
         X, st = f.solve(dev(b), max_refine=1)
         rel = np.linalg.norm(host(X) - xo) / np.linalg.norm(xo)
         assert rel <= 1e-10, (block, rel)
+
+
+@pytest.mark.parametrize("kind", [0, 1, 2, 3])
+@pytest.mark.parametrize("prec", ["F64", "F32"])
+def test_adjoint_refined_matches_oracle(rmge, kind, prec):
+    n, nrhs, kappa = 300, 3, 1e3
+    A = workloads.conditioned(n, kappa, seed=18)
+    if kind == 0:
+        A = A + n * np.eye(n)
+        kappa = np.linalg.cond(A)
+    W = workloads.rhs(n, nrhs, seed=19)
+    f = rmge.factor(dev(A), kind=kind, seed=4, block=128, prec=getattr(rmge, prec))
+    Y, st = f.solve_adjoint_refined(dev(W), max_refine=16, tol=1e-14)
+    assert st["converged"] and st["eta"] <= 1e-14, st
+    Yo = oracle.solve_adjoint(oracle.factor(A, kind, 4), W)
+    rel = np.linalg.norm(host(Y) - Yo) / np.linalg.norm(Yo)
+    assert rel <= max(1e-10, 4 * kappa * n * EPS), rel
