@@ -154,10 +154,11 @@ rmge_status rmge_solve(const rmge_factors *f, const double *B, int64_t nrhs, int
  * precision), w = A z_j, FP64 Krylov basis orthogonalised twice, until the
  * least-squares residual estimate drops below tol (||A||_inf ||x||_inf +
  * ||b||_inf) / 2 or `restart` vectors are used; x += Z y.  Stops when
- * eta <= tol or after max_iters inner iterations in all.
+ * eta <= tol or after max_iters inner iterations for that right-hand side.
  * trans = 1 solves the adjoint system A^T x = b the same way (operator A^T,
  * preconditioner P^T L^{-T} U^{-T} H^T, eta with ||A||_1).
- * restart: 1..64.  tol > 0.  st->iters counts inner iterations;
+ * restart: 1..64.  tol > 0.  st->iters counts inner iterations over all
+ * right-hand sides;
  * st->eta_hist holds eta at each outer check (first 17).  Returns
  * RMGE_NOT_CONVERGED if some right-hand side ends above tol.  Workspace:
  * (2 restart + 2) n doubles, kept by the handle. */
@@ -182,6 +183,15 @@ rmge_status rmge_solve_adjoint(const rmge_factors *f, const double *W, int64_t n
 rmge_status rmge_solve_adjoint_ex(const rmge_factors *f, const double *W, int64_t nrhs,
                                   int64_t ldw, double *Y, int64_t ldy, int32_t max_refine,
                                   double tol, rmge_solve_stats *st);
+
+/* Gradient with respect to A of a loss L(X) with X = A^{-1} B: given
+ * GB = A^{-T} dL/dX (= dL/dB, from rmge_solve_adjoint), dL/dA = -GB X^T
+ * (differentiating A X = B; the multiplier cancels, A^{-1} = H (A H)^{-1}).
+ * GA = -GB X^T, n x n, ldga >= n; GB, X: n x nrhs (ldgb, ldx >= nrhs),
+ * 1 <= nrhs <= 64.  All device pointers; GA may not alias GB or X.  Enqueued
+ * on hip_stream, which is synchronised before returning. */
+rmge_status rmge_grad_A(const double *GB, int64_t ldgb, const double *X, int64_t ldx, int64_t n,
+                        int64_t nrhs, double *GA, int64_t ldga, void *hip_stream);
 
 /* Factor statistics.  min_abs_pivot and growth are computed on the device at
  * the first call (one pass over M's diagonal and U) and cached. */

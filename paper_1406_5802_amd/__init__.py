@@ -238,6 +238,19 @@ def precondition(A, kind, seed):
     return M
 
 
-__all__ = ["factor", "Factors", "multiplier_params", "precondition", "RMGEError", "lib",
+def grad_A(GB, X):
+    """-GB X^T (the gradient of a loss with respect to A, given GB = A^{-T} dL/dX)."""
+    import torch
+
+    n, nrhs = X.shape
+    GA = torch.empty((n, n), dtype=torch.float64, device=X.device)
+    rc = _rmge.rmge_grad_A(GB.data_ptr(), GB.stride(0), X.data_ptr(), X.stride(0), n, nrhs,
+                           GA.data_ptr(), GA.stride(0), _stream_handle(X.device))
+    if rc:
+        raise RMGEError(rc, "rmge_grad_A")
+    return GA
+
+
+__all__ = ["factor", "Factors", "multiplier_params", "precondition", "grad_A", "RMGEError", "lib",
            "NONE", "GAUSSIAN", "CIRCULANT", "TOEPLITZ", "F64", "F32", "PIVOT_NONE",
            "PIVOT_BLOCK"]

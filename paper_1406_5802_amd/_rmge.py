@@ -25,9 +25,9 @@ STATUS_NAMES = {
 # Every function the header declares, for the export check.
 EXPORTS = (
     "rmge_factor", "rmge_factor_ex", "rmge_factor_pivoted", "rmge_refactor", "rmge_solve",
-    "rmge_solve_gmres", "rmge_solve_adjoint", "rmge_solve_adjoint_ex", "rmge_factor_stats_get", "rmge_factors_lu", "rmge_factors_perm",
-    "rmge_multiplier_params", "rmge_param_count", "rmge_precondition", "rmge_destroy",
-    "rmge_status_string", "rmge_version",
+    "rmge_solve_gmres", "rmge_solve_adjoint", "rmge_solve_adjoint_ex", "rmge_grad_A",
+    "rmge_factor_stats_get", "rmge_factors_lu", "rmge_factors_perm", "rmge_multiplier_params",
+    "rmge_param_count", "rmge_precondition", "rmge_destroy", "rmge_status_string", "rmge_version",
 )
 
 
@@ -64,6 +64,7 @@ def lib() -> ctypes.CDLL:
     L.rmge_factor_ex.argtypes = [dp, i64, i64, i32, u64, i32, i32, vp, hp]
     L.rmge_factor_pivoted.argtypes = [dp, i64, i64, i32, u64, i32, i32, i32, vp, hp]
     L.rmge_factors_perm.argtypes = [vp, vp]
+    L.rmge_grad_A.argtypes = [dp, i64, dp, i64, i64, i64, dp, i64, vp]
     L.rmge_refactor.argtypes = [vp, dp, i64, u64]
     L.rmge_solve.argtypes = [vp, dp, i64, i64, dp, i64, i32, ctypes.c_double,
                              ctypes.POINTER(rmge_solve_stats)]
@@ -85,9 +86,8 @@ def lib() -> ctypes.CDLL:
     L.rmge_version.restype = i32
     for name in ("rmge_factor", "rmge_factor_ex", "rmge_factor_pivoted", "rmge_refactor",
                  "rmge_solve", "rmge_solve_gmres", "rmge_solve_adjoint", "rmge_solve_adjoint_ex",
-                 "rmge_factor_stats_get",
-                 "rmge_factors_lu",
-                 "rmge_factors_perm", "rmge_multiplier_params", "rmge_precondition"):
+                 "rmge_grad_A", "rmge_factor_stats_get", "rmge_factors_lu", "rmge_factors_perm",
+                 "rmge_multiplier_params", "rmge_precondition"):
         getattr(L, name).restype = ctypes.c_int
     _lib = L
     return L
@@ -156,6 +156,11 @@ def rmge_solve_adjoint_ex(h, W: int, nrhs: int, ldw: int, Y: int, ldy: int, max_
     st = rmge_solve_stats()
     rc = lib().rmge_solve_adjoint_ex(h, W, nrhs, ldw, Y, ldy, max_refine, tol, ctypes.byref(st))
     return rc, st
+
+
+def rmge_grad_A(GB: int, ldgb: int, X: int, ldx: int, n: int, nrhs: int, GA: int, ldga: int,
+                stream: int) -> int:
+    return lib().rmge_grad_A(GB, ldgb, X, ldx, n, nrhs, GA, ldga, stream)
 
 
 def rmge_factor_stats_get(h):

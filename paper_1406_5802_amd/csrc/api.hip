@@ -768,6 +768,7 @@ rmge_status run_gmres(rmge_factors *f, bool trans, const double *B, int64_t nrhs
     for (int64_t c = 0; c < nrhs; ++c) {
         double eta = 0.0;
         bool first = true;
+        int used = 0;  // inner iterations spent on this right-hand side
         while (true) {
             // r = b - op(A) x, eta, ||r||_2
             RMGE_TRY(op(X + c, ldx, R));
@@ -788,7 +789,7 @@ rmge_status run_gmres(rmge_factors *f, bool trans, const double *B, int64_t nrhs
                 first = false;
             }
             if (hist < 17) loc.eta_hist[hist++] = eta;
-            if (!(eta > tol) || total >= max_iters || eta != eta) break;
+            if (!(eta > tol) || used >= max_iters || eta != eta) break;
             const double beta = std::sqrt(hh[128]);
             if (!(beta > 0.0)) break;
             const double target = 0.5 * tol * scale;  // ||r||_2 <= target => eta <= tol / 2
@@ -796,7 +797,7 @@ rmge_status run_gmres(rmge_factors *f, bool trans, const double *B, int64_t nrhs
             std::fill(g.begin(), g.end(), 0.0);
             g[0] = beta;
             int k = 0;
-            for (int j = 0; j < restart && total < max_iters; ++j) {
+            for (int j = 0; j < restart && used < max_iters; ++j) {
                 double *vj = V + j * n, *w = V + (j + 1) * n, *zj = Z + j * n;
                 RMGE_TRY(precond(vj, 1, 1, zj, 1));
                 RMGE_TRY(op(zj, 1, w));
@@ -809,6 +810,7 @@ rmge_status run_gmres(rmge_factors *f, bool trans, const double *B, int64_t nrhs
                                         hipMemcpyDeviceToHost, s));
                 RMGE_TRY(hipStreamSynchronize(s));
                 ++total;
+                ++used;
                 double *col = H.data() + static_cast<size_t>(j) * (restart + 1);
                 for (int i = 0; i <= j; ++i) col[i] = hh[i] + hh[kMaxRestart + i];
                 const double hnext = std::sqrt(hh[2 * kMaxRestart]);
@@ -973,6 +975,17 @@ rmge_status rmge_solve_adjoint_ex(const rmge_factors *fc, const double *W, int64
     return (f->prec == RMGE_F32)
                ? run_adjoint<float>(f, W, nrhs, ldw, Y, ldy, max_refine, tol, st ? st : &loc)
                : run_adjoint<double>(f, W, nrhs, ldw, Y, ldy, max_refine, tol, st ? st : &loc);
+}
+
+rmge_status rmge_grad_A(const double *GB, int64_t ldgb, const double *X, int64_t ldx, int64_t n,
+                        int64_t nrhs, double *GA, int64_t ldga, void *hip_stream) {
+    if (!GB || !X || !GA || n < 1 || n > (int64_t(1) << 20) || nrhs < 1 || nrhs > 64 ||
+        ldgb < nrhs || ldx < nrhs || ldga < n)
+        return RMGE_EINVAL;
+    if (!device_ok()) return RMGE_EDEVICE;
+    hipStream_t s = static_cast<hipStream_t>(hip_stream);
+    RMGE_TRY(grad_a(GB, ldgb, X, ldx, n, static_cast<int>(nrhs), GA, ldga, s));
+    return from_hip(hipStreamSynchronize(s));
 }
 
 rmge_status rmge_factor_stats_get(const rmge_factors *fc, rmge_factor_stats *s) {

@@ -149,6 +149,10 @@ hipError_t axpby_2d(const TS *d, int64_t ldd, double *x, int64_t ldx, int64_t n,
 hipError_t norm_one(const double *A, int64_t lda, int64_t n, double *work, double *out,
                     hipStream_t s);
 hipError_t fill_f64(double *p, int64_t count, double value, hipStream_t s);
+// GA = -GB X^T (n x n, ldga; GB, X: n x nrhs with their leading dimensions; nrhs <= 64,
+// n <= 2^20).
+hipError_t grad_a(const double *GB, int64_t ldgb, const double *X, int64_t ldx, int64_t n,
+                  int nrhs, double *GA, int64_t ldga, hipStream_t s);
 
 // ---------------------------------------------------------------- fft.hip
 // Real FFT correlation / convolution of vectors with a fixed real kernel h of

@@ -513,6 +513,36 @@ __global__ void k_scale_copy(double *dst, const double *src, int64_t lds, int64_
         dst[i] = alpha * src[i * lds];
 }
 
+// GA = -GB X^T (n x n; GB, X: n x nrhs, nrhs <= 64): the gradient of
+// sum(W .* X) with respect to A when X = A^{-1} B and GB = A^{-T} W.  One
+// workgroup writes a 16 x 256 tile: the 16 rows of GB and the 256 rows of X it
+// needs sit in LDS; each thread forms 16 outputs of one column.  Bound: HBM
+// writes of GA.
+__global__ __launch_bounds__(256) void k_grad_a(const double *GB, int64_t ldgb, const double *X,
+                                                int64_t ldx, int64_t n, int nrhs, double *GA,
+                                                int64_t ldga) {
+    __shared__ double gb[16][64];
+    __shared__ double xs[256][65];
+    const int64_t i0 = static_cast<int64_t>(blockIdx.y) * 16;
+    const int64_t j0 = static_cast<int64_t>(blockIdx.x) * 256;
+    for (int e = threadIdx.x; e < 16 * nrhs; e += 256) {
+        const int i = e / nrhs, r = e % nrhs;
+        gb[i][r] = (i0 + i < n) ? GB[(i0 + i) * ldgb + r] : 0.0;
+    }
+    for (int e = threadIdx.x; e < 256 * nrhs; e += 256) {
+        const int j = e / nrhs, r = e % nrhs;
+        xs[j][r] = (j0 + j < n) ? X[(j0 + j) * ldx + r] : 0.0;
+    }
+    __syncthreads();
+    const int64_t j = j0 + threadIdx.x;
+    if (j >= n) return;
+    for (int i = 0; i < 16 && i0 + i < n; ++i) {
+        double acc = 0.0;
+        for (int r = 0; r < nrhs; ++r) acc += gb[i][r] * xs[threadIdx.x][r];
+        GA[(i0 + i) * ldga + j] = -acc;
+    }
+}
+
 int grid_for(int64_t total, int threads) {
     int64_t g = (total + threads - 1) / threads;
     if (g > 4096) g = 4096;
@@ -668,6 +698,16 @@ hipError_t scale_copy(double *dst, const double *src, int64_t lds, int64_t n, do
     if (n < 1) return hipSuccess;
     hipLaunchKernelGGL(k_scale_copy, dim3(grid_for(n, 256)), dim3(256), 0, s, dst, src, lds, n,
                        alpha);
+    return hipGetLastError();
+}
+
+hipError_t grad_a(const double *GB, int64_t ldgb, const double *X, int64_t ldx, int64_t n,
+                  int nrhs, double *GA, int64_t ldga, hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+    if (nrhs < 1 || nrhs > 64) return hipErrorInvalidValue;
+    dim3 grid(static_cast<unsigned>((n + 255) / 256), static_cast<unsigned>((n + 15) / 16));
+    if (grid.y > 65535u) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_grad_a, grid, dim3(256), 0, s, GB, ldgb, X, ldx, n, nrhs, GA, ldga);
     return hipGetLastError();
 }
 

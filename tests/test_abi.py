@@ -16,7 +16,7 @@ HEADER = os.path.join(ROOT, "include", "rmge.h")
 def _declared_functions():
     text = open(HEADER).read()
     text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
-    names = re.findall(r"^\s*(?:const\s+)?[A-Za-z_][A-Za-z0-9_]*\s*\*?\s*(rmge_[a-z_]+)\s*\(",
+    names = re.findall(r"^\s*(?:const\s+)?[A-Za-z_][A-Za-z0-9_]*\s*\*?\s*(rmge_[A-Za-z_]+)\s*\(",
                        text, flags=re.M)
     return sorted(set(names))
 
