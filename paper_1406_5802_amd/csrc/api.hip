@@ -363,6 +363,7 @@ rmge_status run_factor(rmge_factors *f) {
     f->stats.block = f->block;
     if (f->host_st.code == 4) return RMGE_ZERO_PIVOT;
     if (f->host_st.code == 5) return RMGE_NONFINITE;
+    if (f->host_st.code != 0) return RMGE_EDEVICE;  // a bounded wait inside a kernel gave up
     return RMGE_OK;
 }
 

@@ -36,118 +36,184 @@ __device__ inline bool is_bad(T p) {
     return p == T(0) || !isfinite(p);
 }
 
-// One pivot block (b <= 128) in registers: 512 threads (two waves per SIMD,
-// so one wave's barrier and LDS latency overlap the other's arithmetic);
-// thread (ty, tx) of a 32 x 16 grid holds elements (ty + 32 p, tx + 16 q),
-// p < 4, q < 8.  Pivot step j: the owners of column j and of the pivot row
-// publish them to LDS and every thread applies the rank-1 update
-// a_ic -= (a_ij / a_pj) a_pc to the elements it holds, with the multiplier
-// formed as a_ij times the reciprocal of the pivot.  Multipliers of retired
-// rows and pivot-row entries of columns <= j are zero, so the update is
-// branch-free (retired elements receive exact zero updates) and an element
-// left of its row's pivot keeps the value it had when its column was
-// eliminated; the multipliers l_ic = a_ic / a_cc are formed at write-back from
-// the recorded pivot reciprocals.
+// One pivot block (b <= 128) in registers, 512 threads: wave w holds columns
+// 16 w .. 16 w + 15 and lane l holds rows l and l + 64 of them (32 elements a
+// thread).  A column therefore lives inside one wave, and every wave holds
+// every row.  Pivot step j (owner wave w = j / 16):
+//   * the owner publishes column j to its own LDS slot (and, with PIV, finds
+//     the pivot row among the active rows by a DPP reduction and ballots
+//     inside the wave), then a flag carrying the pivot row;
+//   * every wave waits only for that flag (no barrier: the waves that own no
+//     upcoming column may run steps behind), reads column j, and takes the
+//     pivot row's values for its own columns from lane (row mod 64) with
+//     readlane;
+//   * each thread applies a_ic -= (a_ij / a_pj) a_pc to its elements, the
+//     multiplier formed as a_ij times the reciprocal of the pivot; the owner
+//     of column j + 1 then publishes it.
+// Multipliers of retired rows and pivot-row entries of columns <= j are zero,
+// so the update is branch-free and an element left of its row's pivot keeps
+// the value it had when its column was eliminated; the multipliers
+// l_ic = a_ic / a_cc are formed at write-back from the recorded reciprocals.
 //
-// PIV = false: GENP, the pivot of step j is row j (one barrier per step, the
-// column and row buffers double-buffered).
+// PIV = false: GENP, the pivot of step j is row j.
 // PIV = true: partial pivoting inside this block (the black-box treatment of a
 // small pivot block that Section 3 allows once the recursion of eq. eqgenp
-// stops).  Rows stay in their registers; the pivot of step j is the active row
-// with the largest |a_ij| (ties: the lower row index), found by a shuffle
-// reduction over the four owner lanes of each wave and a reduction over the
-// eight waves' candidates in LDS; a second barrier publishes the pivot row.
-// Row i is written back to position pos[i] (the step that retired it), and
+// stops): the pivot of step j is the active row with the largest |a_ij|
+// (ties: the lower row index).  Rows stay in their registers; row i is written
+// back to position pos[i] (the step that retired it), and
 // piv[k0 + pos[i]] = k0 + i records the exchange.
 constexpr int kLeafThreads = 512;
-constexpr int kLeafRowsPer = kLeaf / 32;  // 4 rows per thread
-constexpr int kLeafWaves = kLeafThreads / 64;
+
+template <typename T>
+__device__ inline T lane_value(T v, int src);
+template <>
+__device__ inline float lane_value<float>(float v, int src) {
+    return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), src));
+}
+template <>
+__device__ inline double lane_value<double>(double v, int src) {
+    const long long b = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_readlane(static_cast<int>(b & 0xffffffffll), src);
+    const int hi = __builtin_amdgcn_readlane(static_cast<int>(b >> 32), src);
+    return __longlong_as_double((static_cast<long long>(hi) << 32) |
+                                (static_cast<unsigned int>(lo)));
+}
+
+// Maximum of an unsigned value over the 64 lanes of a wave by DPP moves
+// (register to register: quad permutations, row mirrors, row broadcasts), the
+// result read from lane 63.
+__device__ inline unsigned wave_max_u32(unsigned v) {
+    v = max(v, static_cast<unsigned>(__builtin_amdgcn_update_dpp(static_cast<int>(v),
+                                                                 static_cast<int>(v), 0xB1, 0xf,
+                                                                 0xf, false)));  // [1,0,3,2]
+    v = max(v, static_cast<unsigned>(__builtin_amdgcn_update_dpp(static_cast<int>(v),
+                                                                 static_cast<int>(v), 0x4E, 0xf,
+                                                                 0xf, false)));  // [2,3,0,1]
+    v = max(v, static_cast<unsigned>(__builtin_amdgcn_update_dpp(static_cast<int>(v),
+                                                                 static_cast<int>(v), 0x141, 0xf,
+                                                                 0xf, false)));  // row_half_mirror
+    v = max(v, static_cast<unsigned>(__builtin_amdgcn_update_dpp(static_cast<int>(v),
+                                                                 static_cast<int>(v), 0x140, 0xf,
+                                                                 0xf, false)));  // row_mirror
+    v = max(v, static_cast<unsigned>(__builtin_amdgcn_update_dpp(static_cast<int>(v),
+                                                                 static_cast<int>(v), 0x142, 0xa,
+                                                                 0xf, false)));  // row_bcast:15
+    v = max(v, static_cast<unsigned>(__builtin_amdgcn_update_dpp(static_cast<int>(v),
+                                                                 static_cast<int>(v), 0x143, 0xc,
+                                                                 0xf, false)));  // row_bcast:31
+    return static_cast<unsigned>(__builtin_amdgcn_readlane(static_cast<int>(v), 63));
+}
+
+// Pivot election inside the owner wave: keys order the candidates (|value| with
+// bit 31 of the high word set for active rows, so every active row outranks a
+// retired one and a NaN outranks everything); the winner is the largest key,
+// ties going to the lower row index (rows l precede rows l + 64).
+__device__ inline int elect_pivot(unsigned long long k0, unsigned long long k1, int l) {
+    const unsigned long long kb = k0 > k1 ? k0 : k1;
+    const unsigned hi = wave_max_u32(static_cast<unsigned>(kb >> 32));
+    const unsigned lo_cand = (static_cast<unsigned>(kb >> 32) == hi) ? static_cast<unsigned>(kb) : 0u;
+    const unsigned lo = wave_max_u32(lo_cand);
+    const unsigned long long m = (static_cast<unsigned long long>(hi) << 32) | lo;
+    const unsigned long long b0 = __ballot(k0 == m), b1 = __ballot(k1 == m);
+    (void)l;
+    return b0 ? __builtin_ffsll(static_cast<long long>(b0)) - 1
+              : 64 + __builtin_ffsll(static_cast<long long>(b1)) - 1;
+}
+
+template <typename T>
+__device__ inline unsigned long long pivot_key(T x, bool active);
+template <>
+__device__ inline unsigned long long pivot_key<float>(float x, bool active) {
+    if (!active) return 0ull;
+    return static_cast<unsigned long long>(
+               (static_cast<unsigned>(__float_as_int(x)) & 0x7fffffffu) | 0x80000000u)
+           << 32;
+}
+template <>
+__device__ inline unsigned long long pivot_key<double>(double x, bool active) {
+    if (!active) return 0ull;
+    return (static_cast<unsigned long long>(__double_as_longlong(x)) &
+            0x7fffffffffffffffull) | 0x8000000000000000ull;
+}
 
 template <typename T, bool PIV>
 __global__ __launch_bounds__(kLeafThreads) void k_leaf_lu(T *a, int64_t lda, int b, int64_t k0,
                                                           DevStatus *st, int *piv) {
-    __shared__ T colv[2][kLeaf];
-    __shared__ T rowv[2][kLeaf];
+    // Column j is published once, into its own slot: no slot is reused, so a
+    // wave may run any number of steps behind the owners without a barrier.
+    __shared__ T colv[kLeaf][kLeaf];
+    __shared__ int flag[kLeaf];  // 0: not yet; 1 + pivot row: published; -1: breakdown
     __shared__ T rcp[kLeaf];
-    __shared__ T cand_v[2][kLeafWaves];
-    __shared__ int cand_i[2][kLeafWaves];
     __shared__ int pos[kLeaf];
+    __shared__ int s_fail;
     if (st->code != 0) return;  // an earlier pivot block broke down
     // This kernel is a chain of short dependent steps that runs beside the wide
     // Schur-update GEMM; raise its waves' issue priority on the shared SIMDs.
     __builtin_amdgcn_s_setprio(3);
-    const int tid = threadIdx.x;
-    const int tx = tid & 15, ty = tid >> 4;
-    T v[kLeafRowsPer][8];
+    const int tid = threadIdx.x, w = tid >> 6, l = tid & 63;
+    if (tid < kLeaf) {
+        flag[tid] = 0;
+        pos[tid] = -1;
+    }
+    if (tid == 0) s_fail = 0;
+    T v[2][16];
 #pragma unroll
-    for (int p = 0; p < kLeafRowsPer; ++p)
+    for (int p = 0; p < 2; ++p)
 #pragma unroll
-        for (int q = 0; q < 8; ++q) {
-            const int i = ty + 32 * p, c = tx + 16 * q;
+        for (int q = 0; q < 16; ++q) {
+            const int i = l + 64 * p, c = 16 * w + q;
             v[p][q] = (i < b && c < b) ? a[static_cast<int64_t>(i) * lda + c] : T(0);
         }
-    unsigned act = 0;  // PIV: bit p set while row ty + 32 p is still active
+    unsigned act = 0;  // bit p: row l + 64 p is still active (PIV)
 #pragma unroll
-    for (int p = 0; p < kLeafRowsPer; ++p)
-        if (ty + 32 * p < b) act |= 1u << p;
-    if (PIV && tid < kLeaf) pos[tid] = -1;
+    for (int p = 0; p < 2; ++p)
+        if (l + 64 * p < b) act |= 1u << p;
+    __syncthreads();
+
+    // The owner of column j (wave j / 16) publishes it once its own update
+    // through step j - 1 is done: the column, then (after a release fence) the
+    // flag carrying the pivot row.
+    auto publish = [&](int j) {
+        const int qj = j & 15;
+        T x0 = T(0), x1 = T(0);
+        switch (qj) {  // qj is uniform: one case runs, with static register indices
+#define RMGE_COL(Q)   \
+    case Q:           \
+        x0 = v[0][Q]; \
+        x1 = v[1][Q]; \
+        break;
+            RMGE_COL(0) RMGE_COL(1) RMGE_COL(2) RMGE_COL(3) RMGE_COL(4) RMGE_COL(5)
+            RMGE_COL(6) RMGE_COL(7) RMGE_COL(8) RMGE_COL(9) RMGE_COL(10) RMGE_COL(11)
+            RMGE_COL(12) RMGE_COL(13) RMGE_COL(14) RMGE_COL(15)
+#undef RMGE_COL
+        }
+        colv[j][l] = x0;
+        colv[j][l + 64] = x1;
+        int sel = j;
+        if (PIV)
+            sel = elect_pivot(pivot_key<T>(x0, (act & 1u) != 0), pivot_key<T>(x1, (act & 2u) != 0),
+                              l);
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+        if (l == 0) __hip_atomic_store(&flag[j], 1 + sel, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+    };
+    if (w == 0 && b > 0) publish(0);
 
     int done = b;
     for (int j = 0; j < b; ++j) {
-        const int buf = j & 1, jq = j >> 4, jr = j & 15;
-        if (tx == jr) {
-            switch (jq) {  // jq is uniform: one case runs, with static register indices
-#define RMGE_COL(Q)                                                          \
-    case Q:                                                                  \
-        _Pragma("unroll") for (int p = 0; p < kLeafRowsPer; ++p) colv[buf][ty + 32 * p] = v[p][Q]; \
-        if (PIV) {                                                           \
-            T bv = T(-1);                                                    \
-            int bi = kLeaf;                                                  \
-            _Pragma("unroll") for (int p = 0; p < kLeafRowsPer; ++p) {       \
-                const T x = v[p][Q];                                         \
-                const T key = (x != x) ? T(INFINITY) : (x < T(0) ? -x : x);  \
-                if (((act >> p) & 1u) && key > bv) { bv = key; bi = ty + 32 * p; } \
-            }                                                                \
-            _Pragma("unroll") for (int o = 16; o <= 32; o <<= 1) {           \
-                const T ov = __shfl_xor(bv, o);                              \
-                const int oi = __shfl_xor(bi, o);                            \
-                if (ov > bv || (ov == bv && oi < bi)) { bv = ov; bi = oi; }  \
-            }                                                                \
-            if ((ty & 3) == 0) { cand_v[buf][ty >> 2] = bv; cand_i[buf][ty >> 2] = bi; } \
-        }                                                                    \
-        break;
-                RMGE_COL(0) RMGE_COL(1) RMGE_COL(2) RMGE_COL(3)
-                RMGE_COL(4) RMGE_COL(5) RMGE_COL(6) RMGE_COL(7)
-#undef RMGE_COL
-            }
+        // wait for column j (bounded: a wave that gives up records an error)
+        int fv = 0, spins = 0;
+        while ((fv = __hip_atomic_load(&flag[j], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP)) == 0) {
+            if (++spins > (1 << 24)) break;
+            __builtin_amdgcn_s_sleep(1);
         }
-        int sel = j;
-        if (PIV) {
-            __syncthreads();
-            T bv = cand_v[buf][0];
-            int bi = cand_i[buf][0];
-#pragma unroll
-            for (int w = 1; w < kLeafWaves; ++w) {
-                const T ov = cand_v[buf][w];
-                const int oi = cand_i[buf][w];
-                if (ov > bv || (ov == bv && oi < bi)) { bv = ov; bi = oi; }
-            }
-            sel = bi;  // uniform; an active row always exists for j < b
-            if (ty == (sel & 31)) act &= ~(1u << (sel >> 5));
-            if (tid == 0) pos[sel] = j;
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+        if (fv == 0) {  // never published: give up (cannot happen unless the schedule is broken)
+            if (l == 0) s_fail = 1;
+            done = j;
+            break;
         }
-        if (ty == (sel & 31)) {
-            switch (sel >> 5) {
-#define RMGE_ROW(P)                                                          \
-    case P:                                                                  \
-        _Pragma("unroll") for (int q = 0; q < 8; ++q) rowv[buf][tx + 16 * q] = v[P][q]; \
-        break;
-                RMGE_ROW(0) RMGE_ROW(1) RMGE_ROW(2) RMGE_ROW(3)
-#undef RMGE_ROW
-            }
-        }
-        __syncthreads();
-        const T pv = rowv[buf][j];
+        const int sel = fv - 1;
+        const T pv = colv[j][sel];
         if (is_bad(pv)) {
             if (tid == 0) {
                 st->info = k0 + j;
@@ -157,23 +223,32 @@ __global__ __launch_bounds__(kLeafThreads) void k_leaf_lu(T *a, int64_t lda, int
             break;
         }
         const T rp = T(1) / pv;
-        if (tid == 0) rcp[j] = rp;
-        T u[8];
-#pragma unroll
-        for (int q = 0; q < 8; ++q) {
-            const int c = tx + 16 * q;
-            u[q] = (c > j) ? rowv[buf][c] : T(0);
+        if (tid == 0) {
+            rcp[j] = rp;
+            if (PIV) pos[sel] = j;
         }
+        const int sl = sel & 63, sp = sel >> 6;
+        if (PIV && l == sl) act &= ~(1u << sp);
+        if (16 * w + 15 > j) {  // a wave whose columns are all left of the pivot only keeps count
+            T u[16];
 #pragma unroll
-        for (int p = 0; p < kLeafRowsPer; ++p) {
-            const int i = ty + 32 * p;
-            const bool live = PIV ? ((act >> p) & 1u) != 0 : (i > j);
-            const T l = live ? colv[buf][i] * rp : T(0);
+            for (int q = 0; q < 16; ++q) {
+                const T pr = lane_value<T>(sp ? v[1][q] : v[0][q], sl);
+                u[q] = (16 * w + q > j) ? pr : T(0);
+            }
 #pragma unroll
-            for (int q = 0; q < 8; ++q) v[p][q] -= l * u[q];
+            for (int p = 0; p < 2; ++p) {
+                const int i = l + 64 * p;
+                const bool live = PIV ? ((act >> p) & 1u) != 0 : (i > j);
+                const T lm = live ? colv[j][i] * rp : T(0);
+#pragma unroll
+                for (int q = 0; q < 16; ++q) v[p][q] -= lm * u[q];
+            }
         }
+        if (j + 1 < b && ((j + 1) >> 4) == w) publish(j + 1);
     }
     __syncthreads();
+    if (s_fail && tid == 0) st->code = 3;  // reported as a device error
     if (PIV) {
         if (done < b && tid == 0) {  // breakdown: keep the row order a permutation
             int next = done;
@@ -185,14 +260,17 @@ __global__ __launch_bounds__(kLeafThreads) void k_leaf_lu(T *a, int64_t lda, int
     }
     // write back (row i to its position), forming the multipliers left of the pivot
 #pragma unroll
-    for (int p = 0; p < kLeafRowsPer; ++p) {
-        const int i = ty + 32 * p;
-        const int dst = PIV ? (i < b ? pos[i] : i) : i;
+    for (int p = 0; p < 2; ++p) {
+        const int i = l + 64 * p;
+        if (i >= b) continue;
+        const int dst = PIV ? pos[i] : i;
 #pragma unroll
-        for (int q = 0; q < 8; ++q) {
-            const int c = tx + 16 * q;
-            if (c < dst && c < done) v[p][q] *= rcp[c];
-            if (i < b && c < b) a[static_cast<int64_t>(dst) * lda + c] = v[p][q];
+        for (int q = 0; q < 16; ++q) {
+            const int c = 16 * w + q;
+            if (c >= b) continue;
+            T val = v[p][q];
+            if (c < dst && c < done) val *= rcp[c];
+            a[static_cast<int64_t>(dst) * lda + c] = val;
         }
     }
 }
