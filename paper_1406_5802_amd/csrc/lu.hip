@@ -81,59 +81,54 @@ __device__ inline double lane_value<double>(double v, int src) {
 
 // Maximum of an unsigned value over the 64 lanes of a wave by DPP moves
 // (register to register: quad permutations, row mirrors, row broadcasts), the
-// result read from lane 63.
+// result read from lane 63.  Lanes a move does not write read 0, the identity
+// of max, which lets each move fold into its max instruction.
+__device__ inline unsigned dpp_max_step(unsigned v, unsigned moved) { return max(v, moved); }
+#define RMGE_DPP_MAX(v, ctrl, rows)                                                       \
+    v = dpp_max_step(v, static_cast<unsigned>(__builtin_amdgcn_update_dpp(               \
+                            0, static_cast<int>(v), ctrl, rows, 0xf, false)))
 __device__ inline unsigned wave_max_u32(unsigned v) {
-    v = max(v, static_cast<unsigned>(__builtin_amdgcn_update_dpp(static_cast<int>(v),
-                                                                 static_cast<int>(v), 0xB1, 0xf,
-                                                                 0xf, false)));  // [1,0,3,2]
-    v = max(v, static_cast<unsigned>(__builtin_amdgcn_update_dpp(static_cast<int>(v),
-                                                                 static_cast<int>(v), 0x4E, 0xf,
-                                                                 0xf, false)));  // [2,3,0,1]
-    v = max(v, static_cast<unsigned>(__builtin_amdgcn_update_dpp(static_cast<int>(v),
-                                                                 static_cast<int>(v), 0x141, 0xf,
-                                                                 0xf, false)));  // row_half_mirror
-    v = max(v, static_cast<unsigned>(__builtin_amdgcn_update_dpp(static_cast<int>(v),
-                                                                 static_cast<int>(v), 0x140, 0xf,
-                                                                 0xf, false)));  // row_mirror
-    v = max(v, static_cast<unsigned>(__builtin_amdgcn_update_dpp(static_cast<int>(v),
-                                                                 static_cast<int>(v), 0x142, 0xa,
-                                                                 0xf, false)));  // row_bcast:15
-    v = max(v, static_cast<unsigned>(__builtin_amdgcn_update_dpp(static_cast<int>(v),
-                                                                 static_cast<int>(v), 0x143, 0xc,
-                                                                 0xf, false)));  // row_bcast:31
+    RMGE_DPP_MAX(v, 0xB1, 0xf);   // quad_perm [1,0,3,2]
+    RMGE_DPP_MAX(v, 0x4E, 0xf);   // quad_perm [2,3,0,1]
+    RMGE_DPP_MAX(v, 0x141, 0xf);  // row_half_mirror
+    RMGE_DPP_MAX(v, 0x140, 0xf);  // row_mirror
+    RMGE_DPP_MAX(v, 0x142, 0xa);  // row_bcast:15
+    RMGE_DPP_MAX(v, 0x143, 0xc);  // row_bcast:31
     return static_cast<unsigned>(__builtin_amdgcn_readlane(static_cast<int>(v), 63));
 }
+#undef RMGE_DPP_MAX
 
-// Pivot election inside the owner wave: keys order the candidates (|value| with
-// bit 31 of the high word set for active rows, so every active row outranks a
-// retired one and a NaN outranks everything); the winner is the largest key,
-// ties going to the lower row index (rows l precede rows l + 64).
-__device__ inline int elect_pivot(unsigned long long k0, unsigned long long k1, int l) {
-    const unsigned long long kb = k0 > k1 ? k0 : k1;
-    const unsigned hi = wave_max_u32(static_cast<unsigned>(kb >> 32));
-    const unsigned lo_cand = (static_cast<unsigned>(kb >> 32) == hi) ? static_cast<unsigned>(kb) : 0u;
-    const unsigned lo = wave_max_u32(lo_cand);
-    const unsigned long long m = (static_cast<unsigned long long>(hi) << 32) | lo;
+// Pivot election inside the owner wave over the two rows each lane holds
+// (rows l and l + 64): the winner is the active row of largest |value|, ties
+// going to the lower row index; a NaN outranks every number, and every active
+// row outranks a retired one.  Keys: |value|'s bit pattern with the top bit
+// set for active rows, 0 for retired ones (FP32: one 32-bit word; FP64: the
+// high word decides and the low word breaks its ties).
+template <typename T>
+__device__ inline int elect_pivot(T x0, T x1, unsigned act);
+template <>
+__device__ inline int elect_pivot<float>(float x0, float x1, unsigned act) {
+    const unsigned k0 = (act & 1u) ? ((__float_as_uint(x0) & 0x7fffffffu) | 0x80000000u) : 0u;
+    const unsigned k1 = (act & 2u) ? ((__float_as_uint(x1) & 0x7fffffffu) | 0x80000000u) : 0u;
+    const unsigned m = wave_max_u32(max(k0, k1));
     const unsigned long long b0 = __ballot(k0 == m), b1 = __ballot(k1 == m);
-    (void)l;
     return b0 ? __builtin_ffsll(static_cast<long long>(b0)) - 1
               : 64 + __builtin_ffsll(static_cast<long long>(b1)) - 1;
 }
-
-template <typename T>
-__device__ inline unsigned long long pivot_key(T x, bool active);
 template <>
-__device__ inline unsigned long long pivot_key<float>(float x, bool active) {
-    if (!active) return 0ull;
-    return static_cast<unsigned long long>(
-               (static_cast<unsigned>(__float_as_int(x)) & 0x7fffffffu) | 0x80000000u)
-           << 32;
-}
-template <>
-__device__ inline unsigned long long pivot_key<double>(double x, bool active) {
-    if (!active) return 0ull;
-    return (static_cast<unsigned long long>(__double_as_longlong(x)) &
-            0x7fffffffffffffffull) | 0x8000000000000000ull;
+__device__ inline int elect_pivot<double>(double x0, double x1, unsigned act) {
+    const unsigned long long mag = 0x7fffffffffffffffull, top = 0x8000000000000000ull;
+    const unsigned long long k0 =
+        (act & 1u) ? ((static_cast<unsigned long long>(__double_as_longlong(x0)) & mag) | top) : 0ull;
+    const unsigned long long k1 =
+        (act & 2u) ? ((static_cast<unsigned long long>(__double_as_longlong(x1)) & mag) | top) : 0ull;
+    const unsigned long long kb = k0 > k1 ? k0 : k1;
+    const unsigned hi = wave_max_u32(static_cast<unsigned>(kb >> 32));
+    const unsigned lo = wave_max_u32(static_cast<unsigned>(kb >> 32) == hi ? static_cast<unsigned>(kb) : 0u);
+    const unsigned long long m = (static_cast<unsigned long long>(hi) << 32) | lo;
+    const unsigned long long b0 = __ballot(k0 == m), b1 = __ballot(k1 == m);
+    return b0 ? __builtin_ffsll(static_cast<long long>(b0)) - 1
+              : 64 + __builtin_ffsll(static_cast<long long>(b1)) - 1;
 }
 
 template <typename T, bool PIV>
@@ -142,15 +137,16 @@ __global__ __launch_bounds__(kLeafThreads) void k_leaf_lu(T *a, int64_t lda, int
     // Column j is published once, into its own slot: no slot is reused, so a
     // wave may run any number of steps behind the owners without a barrier.
     __shared__ T colv[kLeaf][kLeaf];
-    __shared__ int flag[kLeaf];  // 0: not yet; 1 + pivot row: published; -1: breakdown
-    __shared__ T rcp[kLeaf];
+    __shared__ int flag[kLeaf];  // 0: not yet; 1 + pivot row: published; -(1 + row): breakdown
+    __shared__ T rcp[kLeaf];     // reciprocal of step j's pivot
     __shared__ int pos[kLeaf];
     __shared__ int s_fail;
     if (st->code != 0) return;  // an earlier pivot block broke down
-    // This kernel is a chain of short dependent steps that runs beside the wide
-    // Schur-update GEMM; raise its waves' issue priority on the shared SIMDs.
+    // This kernel is a chain of short dependent steps that may run beside the
+    // wide Schur-update GEMM; raise its waves' issue priority on shared SIMDs.
     __builtin_amdgcn_s_setprio(3);
-    const int tid = threadIdx.x, w = tid >> 6, l = tid & 63;
+    const int tid = threadIdx.x, l = tid & 63;
+    const int w = __builtin_amdgcn_readfirstlane(tid >> 6);  // wave-uniform
     if (tid < kLeaf) {
         flag[tid] = 0;
         pos[tid] = -1;
@@ -171,16 +167,23 @@ __global__ __launch_bounds__(kLeafThreads) void k_leaf_lu(T *a, int64_t lda, int
     __syncthreads();
 
     // The owner of column j (wave j / 16) publishes it once its own update
-    // through step j - 1 is done: the column, then (after a release fence) the
-    // flag carrying the pivot row.
+    // through step j - 1 is done: the column, the pivot's reciprocal and
+    // position, then (after a release fence) the flag carrying the pivot row,
+    // negative if the pivot is zero or not finite (the breakdown is recorded
+    // here).  The owner keeps what it published for its own next step.
+    T pub0 = T(0), pub1 = T(0), pub_rp = T(0);
+    int pub_fv = 0;
     auto publish = [&](int j) {
         const int qj = j & 15;
         T x0 = T(0), x1 = T(0);
         switch (qj) {  // qj is uniform: one case runs, with static register indices
-#define RMGE_COL(Q)   \
-    case Q:           \
-        x0 = v[0][Q]; \
-        x1 = v[1][Q]; \
+// (the empty asm keeps each case a plain register read, so the compiler does
+// not turn the switch into an indexed load from memory)
+#define RMGE_COL(Q)                            \
+    case Q:                                    \
+        x0 = v[0][Q];                          \
+        x1 = v[1][Q];                          \
+        asm volatile("" : "+v"(x0), "+v"(x1)); \
         break;
             RMGE_COL(0) RMGE_COL(1) RMGE_COL(2) RMGE_COL(3) RMGE_COL(4) RMGE_COL(5)
             RMGE_COL(6) RMGE_COL(7) RMGE_COL(8) RMGE_COL(9) RMGE_COL(10) RMGE_COL(11)
@@ -189,63 +192,104 @@ __global__ __launch_bounds__(kLeafThreads) void k_leaf_lu(T *a, int64_t lda, int
         }
         colv[j][l] = x0;
         colv[j][l + 64] = x1;
-        int sel = j;
-        if (PIV)
-            sel = elect_pivot(pivot_key<T>(x0, (act & 1u) != 0), pivot_key<T>(x1, (act & 2u) != 0),
-                              l);
+        const int sel = PIV ? elect_pivot<T>(x0, x1, act) : j;
+        const T pv = lane_value<T>((sel >> 6) ? x1 : x0, sel & 63);
+        const bool ok = !is_bad(pv);
+        const T rp = ok ? T(1) / pv : T(0);
+        if (l == 0) {
+            if (ok) {
+                rcp[j] = rp;
+                if (PIV) pos[sel] = j;
+            } else {
+                st->info = k0 + j;
+                st->code = (pv == T(0)) ? 4 : 5;
+            }
+        }
+        pub0 = x0;
+        pub1 = x1;
+        pub_rp = rp;
+        pub_fv = ok ? 1 + sel : -(1 + sel);
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
-        if (l == 0) __hip_atomic_store(&flag[j], 1 + sel, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+        if (l == 0) __hip_atomic_store(&flag[j], pub_fv, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
     };
-    if (w == 0 && b > 0) publish(0);
-
-    int done = b;
-    for (int j = 0; j < b; ++j) {
-        // wait for column j (bounded: a wave that gives up records an error)
+    // Wait for column j (bounded: a wave that gives up records an error) and
+    // return its flag, or 0.
+    auto await_column = [&](int j) {
         int fv = 0, spins = 0;
-        while ((fv = __hip_atomic_load(&flag[j], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP)) == 0) {
+        while ((fv = __builtin_amdgcn_readfirstlane(__hip_atomic_load(
+                    &flag[j], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP))) == 0) {
             if (++spins > (1 << 24)) break;
             __builtin_amdgcn_s_sleep(1);
         }
         __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
-        if (fv == 0) {  // never published: give up (cannot happen unless the schedule is broken)
-            if (l == 0) s_fail = 1;
+        return fv;
+    };
+
+    bool mine = false;  // this wave published column j and holds it in registers
+    if (w == 0 && b > 0) {
+        publish(0);
+        mine = true;
+    }
+    int done = b, j = 0;
+    // Steps that change this wave's columns: j < 16 w + 15.  A failed step
+    // still runs its (then empty) update and leaves after it, so the loop has
+    // a single exit and the columns are updated in place.
+    const int jw = min(b, 16 * w + 15);
+    for (; j < jw; ++j) {
+        int fv;
+        T c0, c1, rp;
+        if (mine) {
+            fv = pub_fv;
+            c0 = pub0;
+            c1 = pub1;
+            rp = pub_rp;
+        } else {
+            fv = await_column(j);
+            c0 = colv[j][l];
+            c1 = colv[j][l + 64];
+            rp = rcp[j];
+        }
+        const bool ok = fv > 0;
+        if (!ok) {
+            if (fv == 0 && l == 0) s_fail = 1;  // never published (cannot happen unless the schedule is broken)
             done = j;
-            break;
         }
-        const int sel = fv - 1;
-        const T pv = colv[j][sel];
-        if (is_bad(pv)) {
-            if (tid == 0) {
-                st->info = k0 + j;
-                st->code = (pv == T(0)) ? 4 : 5;
-            }
-            done = j;
-            break;
-        }
-        const T rp = T(1) / pv;
-        if (tid == 0) {
-            rcp[j] = rp;
-            if (PIV) pos[sel] = j;
-        }
-        const int sl = sel & 63, sp = sel >> 6;
-        if (PIV && l == sl) act &= ~(1u << sp);
-        if (16 * w + 15 > j) {  // a wave whose columns are all left of the pivot only keeps count
-            T u[16];
+        const int sel = (fv > 0 ? fv : -fv) - 1, sl = sel & 63, sp = sel >> 6;
+        if (PIV && ok && l == sl) act &= ~(1u << sp);
+        const bool live0 = PIV ? (act & 1u) != 0 : l > j;
+        const bool live1 = PIV ? (act & 2u) != 0 : l + 64 > j;
+        const T m0 = (ok && live0) ? c0 * rp : T(0), m1 = (ok && live1) ? c1 * rp : T(0);
+        // the pivot row's entries of this wave's columns (wave-uniform values).
+        // Columns <= j are final in their LDS slots, so their registers take
+        // the update too and are never read again.
+        T u[16];
+        if (sp) {
 #pragma unroll
-            for (int q = 0; q < 16; ++q) {
-                const T pr = lane_value<T>(sp ? v[1][q] : v[0][q], sl);
-                u[q] = (16 * w + q > j) ? pr : T(0);
-            }
+            for (int q = 0; q < 16; ++q) u[q] = lane_value<T>(v[1][q], sl);
+        } else {
 #pragma unroll
-            for (int p = 0; p < 2; ++p) {
-                const int i = l + 64 * p;
-                const bool live = PIV ? ((act >> p) & 1u) != 0 : (i > j);
-                const T lm = live ? colv[j][i] * rp : T(0);
+            for (int q = 0; q < 16; ++q) u[q] = lane_value<T>(v[0][q], sl);
+        }
 #pragma unroll
-                for (int q = 0; q < 16; ++q) v[p][q] -= lm * u[q];
+        for (int q = 0; q < 16; ++q) {
+            v[0][q] -= m0 * u[q];
+            v[1][q] -= m1 * u[q];
+        }
+        if (!ok) break;
+        mine = j + 1 < b && ((j + 1) >> 4) == w;
+        if (mine) publish(j + 1);
+    }
+    // The remaining steps leave this wave's columns alone: follow the flags
+    // and stop where the others stop.
+    if (done == b) {
+        for (; j < b; ++j) {
+            const int fv = await_column(j);
+            if (fv <= 0) {
+                if (fv == 0 && l == 0) s_fail = 1;
+                done = j;
+                break;
             }
         }
-        if (j + 1 < b && ((j + 1) >> 4) == w) publish(j + 1);
     }
     __syncthreads();
     if (s_fail && tid == 0) st->code = 3;  // reported as a device error
@@ -258,7 +302,9 @@ __global__ __launch_bounds__(kLeafThreads) void k_leaf_lu(T *a, int64_t lda, int
         __syncthreads();
         if (tid < b) piv[k0 + pos[tid]] = static_cast<int>(k0 + tid);
     }
-    // write back (row i to its position), forming the multipliers left of the pivot
+    // write back (row i to its position), forming the multipliers left of the
+    // pivot.  A column eliminated before the stop is taken from its LDS slot,
+    // which holds its final values; later columns from the registers.
 #pragma unroll
     for (int p = 0; p < 2; ++p) {
         const int i = l + 64 * p;
@@ -268,7 +314,7 @@ __global__ __launch_bounds__(kLeafThreads) void k_leaf_lu(T *a, int64_t lda, int
         for (int q = 0; q < 16; ++q) {
             const int c = 16 * w + q;
             if (c >= b) continue;
-            T val = v[p][q];
+            T val = c < done ? colv[c][i] : v[p][q];
             if (c < dst && c < done) val *= rcp[c];
             a[static_cast<int64_t>(dst) * lda + c] = val;
         }
