@@ -136,21 +136,33 @@ __global__ __launch_bounds__(WGM *WGN * 64, MINB) void k_gemm(int M, int N, int 
     const int crow0 = m0 + wm * WM;
     const int ccol0 = n0 + wn * WN + (lane & 15);
     double vmax = 0.0;
+    const bool rd = beta != T(0);
 #pragma unroll
-    for (int i = 0; i < TM; ++i)
+    for (int i = 0; i < TM; ++i) {
+        // a row of sub-tiles' C values in flight at once (only when beta != 0)
+        T cv[TN][4];
+        if (rd) {
+#pragma unroll
+            for (int j = 0; j < TN; ++j)
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    const int row = crow0 + i * 16 + Mma<T>::row(lane, r), col = ccol0 + j * 16;
+                    cv[j][r] = load_if(C, static_cast<int64_t>(row) * ldc + col, row < M && col < N);
+                }
+        }
 #pragma unroll
         for (int j = 0; j < TN; ++j)
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
                 const int row = crow0 + i * 16 + Mma<T>::row(lane, r), col = ccol0 + j * 16;
                 if (row < M && col < N) {
-                    T *c = C + static_cast<int64_t>(row) * ldc + col;
                     const T v = alpha * acc[i][j][r];
-                    const T out = (beta == T(0)) ? v : v + beta * (*c);
-                    *c = out;
+                    const T out = rd ? v + beta * cv[j][r] : v;
+                    C[static_cast<int64_t>(row) * ldc + col] = out;
                     vmax = fmax(vmax, fabs(static_cast<double>(out)));
                 }
             }
+    }
     if (absmax != nullptr) {  // max |C| for the growth statistic, one atomic per wave
         for (int off = 32; off > 0; off >>= 1) vmax = fmax(vmax, __shfl_xor(vmax, off));
         if (lane == 0)
@@ -255,19 +267,30 @@ __global__ __launch_bounds__(256, MINB) void k_gemm_fast(int M, int N, int K, T 
     const int crow0 = m0 + wm * 64;
     const int ccol0 = n0 + wn * 64 + (lane & 15);
     double vmax = 0.0;
+    const bool rd = beta != T(0);
 #pragma unroll
-    for (int i = 0; i < 4; ++i)
+    for (int i = 0; i < 4; ++i) {
+        // a row of sub-tiles' C values in flight at once (only when beta != 0)
+        T cv[4][4];
+        if (rd) {
+#pragma unroll
+            for (int j = 0; j < 4; ++j)
+#pragma unroll
+                for (int r = 0; r < 4; ++r)
+                    cv[j][r] = C[static_cast<int64_t>(crow0 + i * 16 + Mma<T>::row(lane, r)) * ldc +
+                                 ccol0 + j * 16];
+        }
 #pragma unroll
         for (int j = 0; j < 4; ++j)
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
                 const int row = crow0 + i * 16 + Mma<T>::row(lane, r), col = ccol0 + j * 16;
-                T *c = C + static_cast<int64_t>(row) * ldc + col;
                 const T v = alpha * acc[i][j][r];
-                const T out = (beta == T(0)) ? v : v + beta * (*c);
-                *c = out;
+                const T out = rd ? v + beta * cv[j][r] : v;
+                C[static_cast<int64_t>(row) * ldc + col] = out;
                 vmax = fmax(vmax, fabs(static_cast<double>(out)));
             }
+    }
     if (absmax != nullptr) {
         for (int off = 32; off > 0; off >>= 1) vmax = fmax(vmax, __shfl_xor(vmax, off));
         if (lane == 0)
@@ -354,17 +377,34 @@ __global__ __launch_bounds__(256, MINB) void k_gemm_upd64(int M, int N, int K, T
         __syncthreads();
     }
     const int crow0 = m0 + wm * 32, ccol0 = n0 + wn * 32 + (lane & 15);
+    auto cptr = [&](int i, int j, int r) {
+        return C + static_cast<int64_t>(crow0 + i * 16 + Mma<T>::row(lane, r)) * ldc + ccol0 +
+               j * 16;
+    };
+    if (beta == T(0)) {
 #pragma unroll
-    for (int i = 0; i < 2; ++i)
+        for (int i = 0; i < 2; ++i)
 #pragma unroll
-        for (int j = 0; j < 2; ++j)
+            for (int j = 0; j < 2; ++j)
 #pragma unroll
-            for (int r = 0; r < 4; ++r) {
-                T *c = C + static_cast<int64_t>(crow0 + i * 16 + Mma<T>::row(lane, r)) * ldc +
-                       ccol0 + j * 16;
-                const T v = alpha * acc[i][j][r];
-                *c = (beta == T(0)) ? v : v + beta * (*c);
-            }
+                for (int r = 0; r < 4; ++r) *cptr(i, j, r) = alpha * acc[i][j][r];
+    } else {
+        // all of the tile's C values in flight at once, then the stores
+        T cv[2][2][4];
+#pragma unroll
+        for (int i = 0; i < 2; ++i)
+#pragma unroll
+            for (int j = 0; j < 2; ++j)
+#pragma unroll
+                for (int r = 0; r < 4; ++r) cv[i][j][r] = *cptr(i, j, r);
+#pragma unroll
+        for (int i = 0; i < 2; ++i)
+#pragma unroll
+            for (int j = 0; j < 2; ++j)
+#pragma unroll
+                for (int r = 0; r < 4; ++r)
+                    *cptr(i, j, r) = alpha * acc[i][j][r] + beta * cv[i][j][r];
+    }
 }
 
 template <typename T, typename TA, int BM, int BN, int WGM, int WGN, int MINB>

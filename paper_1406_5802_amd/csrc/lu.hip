@@ -390,13 +390,39 @@ __global__ __launch_bounds__(512) void k_diag_inv(const T *a, int64_t lda, int b
 // round-robin to its four waves.  Per diagonal sub-block i the two tiles of
 // rows i are published to LDS, multiplied by the sub-block inverse, published
 // again as X_i, and every wave subtracts (factor block) x X_i from its tiles
-// further along; the factor operand streams from L2.
+// further along.
+//
+// The substitution is a chain of b / 32 short steps, so operands are fetched
+// ahead: the next sub-block inverse one step early, a step's factor operands
+// at the start of the step, which hides their memory latency behind the
+// publish / multiply phases of the step.
 //
 // LEFT:  C (b x count) <- L^{-1} P C, strips of 32 columns (row tiles dealt).
 // With `rowsrc` (pivoted blocks) row t of P C is row rowsrc[t] - rowbase of C:
 // the strip is read whole into registers before any of it is written back.
+
+// This thread's four elements (e = tid + 256 m) of sub-block q's inverse, 0 past the block.
 template <typename T>
-__global__ __launch_bounds__(256, 2) void k_trsm_left(const T *lu, int64_t ld, int b, T *C,
+__device__ inline void fetch_dinv(const T *Dinv, int b, int q, int tid, T (&d)[4]) {
+    const int q0 = q * kSub, sb = (b - q0) < kSub ? (b - q0) : kSub;
+#pragma unroll
+    for (int m = 0; m < 4; ++m) {
+        const int e = tid + 256 * m, r = e / kSub, k = e % kSub;
+        d[m] = load_if(Dinv, (q0 + r) * static_cast<int64_t>(kSub) + k, sb > 0 && r < sb && k < sb);
+    }
+}
+template <typename T>
+__device__ inline void store_dinv(T (&Ds)[kSub][kSub + 1], int tid, const T (&d)[4]) {
+#pragma unroll
+    for (int m = 0; m < 4; ++m) {
+        const int e = tid + 256 * m;
+        Ds[e / kSub][e % kSub] = d[m];
+    }
+}
+
+template <typename T>
+// (FP64 holds a step's operands in flight at one workgroup per CU)
+__global__ __launch_bounds__(256, sizeof(T) == 8 ? 1 : 2) void k_trsm_left(const T *lu, int64_t ld, int b, T *C,
                                                       int64_t ldc, int64_t count, const T *Dinv,
                                                       const int *abort, const int *rowsrc,
                                                       int64_t rowbase) {
@@ -411,6 +437,24 @@ __global__ __launch_bounds__(256, 2) void k_trsm_left(const T *lu, int64_t ld, i
     const int64_t c0 = static_cast<int64_t>(blockIdx.x) * BN;
     const int wcols = static_cast<int>((count - c0) < BN ? (count - c0) : BN);
     const int nrt = (b + 15) / 16;
+    T dcur[4], dnext[4];
+    fetch_dinv(Dinv, b, 0, tid, dcur);
+    // source rows of this thread's accumulator rows (all index loads first)
+    int64_t src[4][4];
+    if (rowsrc) {
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int t = wave + 4 * u, row = 16 * t + Mma<T>::row(lane, r);
+                src[u][r] = load_if(rowsrc, row, t < nrt && row < b) - rowbase;
+            }
+    } else {
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) src[u][r] = 16 * (wave + 4 * u) + Mma<T>::row(lane, r);
+    }
     acc_t acc[4][2];
 #pragma unroll
     for (int u = 0; u < 4; ++u)
@@ -421,15 +465,24 @@ __global__ __launch_bounds__(256, 2) void k_trsm_left(const T *lu, int64_t ld, i
                 const int t = wave + 4 * u;
                 const int row = 16 * t + Mma<T>::row(lane, r), col = 16 * j + lo;
                 const bool in = t < nrt && row < b && col < wcols;
-                const int64_t src = (in && rowsrc) ? rowsrc[row] - rowbase : row;
-                acc[u][j][r] = in ? C[src * ldc + c0 + col] : T(0);
+                acc[u][j][r] = load_if(C, src[u][r] * ldc + c0 + col, in);
             }
     for (int i = 0, i0 = 0; i0 < b; ++i, i0 += kSub) {
         const int sb = (b - i0) < kSub ? (b - i0) : kSub;
-        for (int e = tid; e < kSub * kSub; e += 256) {
-            const int r = e / kSub, k = e % kSub;
-            Ds[r][k] = (r < sb && k < sb) ? Dinv[(i0 + r) * static_cast<int64_t>(kSub) + k] : T(0);
+        // this step's factor operands: -L[row][i0 + k], row tiles below sub-block i
+        T f[4][kSub / 4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const int t = wave + 4 * u, row = 16 * t + lo;
+            const bool below = t >= 2 * i + 2 && t < nrt && row < b;
+#pragma unroll
+            for (int kq = 0; kq < kSub / 4; ++kq) {
+                const int k = 4 * kq + hi;
+                f[u][kq] = -load_if(lu, row * ld + i0 + k, below && k < sb);
+            }
         }
+        fetch_dinv(Dinv, b, i + 1, tid, dnext);
+        store_dinv(Ds, tid, dcur);
 #pragma unroll
         for (int u = 0; u < 4; ++u) {
             const int t = wave + 4 * u;
@@ -477,17 +530,18 @@ __global__ __launch_bounds__(256, 2) void k_trsm_left(const T *lu, int64_t ld, i
         for (int u = 0; u < 4; ++u) {
             const int t = wave + 4 * u;
             if (t >= 2 * i + 2 && t < nrt) {
-                const int row = 16 * t + lo;
 #pragma unroll
-                for (int kk = 0; kk < kSub; kk += 4) {
-                    const int k = kk + hi;
-                    const T a = (row < b && k < sb) ? -lu[row * ld + i0 + k] : T(0);
+                for (int kq = 0; kq < kSub / 4; ++kq) {
+                    const int k = 4 * kq + hi;
 #pragma unroll
-                    for (int j = 0; j < 2; ++j) acc[u][j] = Mma<T>::step(a, Xs[k][16 * j + lo], acc[u][j]);
+                    for (int j = 0; j < 2; ++j)
+                        acc[u][j] = Mma<T>::step(f[u][kq], Xs[k][16 * j + lo], acc[u][j]);
                 }
             }
         }
         __syncthreads();
+#pragma unroll
+        for (int m = 0; m < 4; ++m) dcur[m] = dnext[m];
     }
 #pragma unroll
     for (int u = 0; u < 4; ++u)
@@ -503,7 +557,8 @@ __global__ __launch_bounds__(256, 2) void k_trsm_left(const T *lu, int64_t ld, i
 
 // RIGHT: C (count x b) <- C U^{-1}, strips of 32 rows (column tiles dealt).
 template <typename T>
-__global__ __launch_bounds__(256, 2) void k_trsm_right(const T *lu, int64_t ld, int b, T *C,
+// (FP64 holds a step's operands in flight at one workgroup per CU)
+__global__ __launch_bounds__(256, sizeof(T) == 8 ? 1 : 2) void k_trsm_right(const T *lu, int64_t ld, int b, T *C,
                                                        int64_t ldc, int64_t count, const T *Dinv,
                                                        const int *abort) {
     using acc_t = typename Mma<T>::acc;
@@ -517,6 +572,8 @@ __global__ __launch_bounds__(256, 2) void k_trsm_right(const T *lu, int64_t ld, 
     const int64_t r0 = static_cast<int64_t>(blockIdx.x) * BM;
     const int wrows = static_cast<int>((count - r0) < BM ? (count - r0) : BM);
     const int nct = (b + 15) / 16;
+    T dcur[4], dnext[4];
+    fetch_dinv(Dinv, b, 0, tid, dcur);
     acc_t acc[4][2];  // [column tile u][row tile]
 #pragma unroll
     for (int u = 0; u < 4; ++u)
@@ -526,15 +583,24 @@ __global__ __launch_bounds__(256, 2) void k_trsm_right(const T *lu, int64_t ld, 
             for (int r = 0; r < 4; ++r) {
                 const int c = wave + 4 * u;
                 const int row = 16 * q + Mma<T>::row(lane, r), col = 16 * c + lo;
-                acc[u][q][r] =
-                    (c < nct && row < wrows && col < b) ? C[(r0 + row) * ldc + col] : T(0);
+                acc[u][q][r] = load_if(C, (r0 + row) * ldc + col, c < nct && row < wrows && col < b);
             }
     for (int j = 0, j0 = 0; j0 < b; ++j, j0 += kSub) {
         const int sb = (b - j0) < kSub ? (b - j0) : kSub;
-        for (int e = tid; e < kSub * kSub; e += 256) {
-            const int k = e / kSub, m = e % kSub;
-            Ds[k][m] = (k < sb && m < sb) ? Dinv[(j0 + k) * static_cast<int64_t>(kSub) + m] : T(0);
+        // this step's factor operands: -U[j0 + k][col], column tiles right of sub-block j
+        T f[4][kSub / 4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const int c = wave + 4 * u, col = 16 * c + lo;
+            const bool right = c >= 2 * j + 2 && c < nct && col < b;
+#pragma unroll
+            for (int kq = 0; kq < kSub / 4; ++kq) {
+                const int k = 4 * kq + hi;
+                f[u][kq] = -load_if(lu, (j0 + k) * ld + col, right && k < sb);
+            }
         }
+        fetch_dinv(Dinv, b, j + 1, tid, dnext);
+        store_dinv(Ds, tid, dcur);
 #pragma unroll
         for (int u = 0; u < 4; ++u) {
             const int c = wave + 4 * u;
@@ -582,18 +648,18 @@ __global__ __launch_bounds__(256, 2) void k_trsm_right(const T *lu, int64_t ld, 
         for (int u = 0; u < 4; ++u) {
             const int c = wave + 4 * u;
             if (c >= 2 * j + 2 && c < nct) {
-                const int col = 16 * c + lo;
 #pragma unroll
-                for (int kk = 0; kk < kSub; kk += 4) {
-                    const int k = kk + hi;
-                    const T bv = (k < sb && col < b) ? -lu[(j0 + k) * ld + col] : T(0);
+                for (int kq = 0; kq < kSub / 4; ++kq) {
+                    const int k = 4 * kq + hi;
 #pragma unroll
                     for (int q = 0; q < 2; ++q)
-                        acc[u][q] = Mma<T>::step(Xs[16 * q + lo][k], bv, acc[u][q]);
+                        acc[u][q] = Mma<T>::step(Xs[16 * q + lo][k], f[u][kq], acc[u][q]);
                 }
             }
         }
         __syncthreads();
+#pragma unroll
+        for (int m = 0; m < 4; ++m) dcur[m] = dnext[m];
     }
 #pragma unroll
     for (int u = 0; u < 4; ++u)
@@ -605,16 +671,6 @@ __global__ __launch_bounds__(256, 2) void k_trsm_right(const T *lu, int64_t ld, 
                 const int row = 16 * q + Mma<T>::row(lane, r), col = 16 * c + lo;
                 if (c < nct && row < wrows && col < b) C[(r0 + row) * ldc + col] = acc[u][q][r];
             }
-}
-
-template <typename T>
-__global__ void k_set_identity(T *a, int64_t ld, int64_t n) {
-    const int64_t total = n * n;
-    for (int64_t e = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x; e < total;
-         e += static_cast<int64_t>(gridDim.x) * blockDim.x) {
-        const int64_t i = e / n, j = e % n;
-        a[i * ld + j] = (i == j) ? T(1) : T(0);
-    }
 }
 
 // dst[di] = src[si] with si = gather ? gather[i] : i, di = scatter ? scatter[i] : i.
@@ -794,13 +850,6 @@ hipError_t trsm(int side, const T *lu, int64_t ld, int b, T *C, int64_t ldc, int
     return hipGetLastError();
 }
 
-template <typename T>
-hipError_t set_identity(T *a, int64_t ld, int64_t n, hipStream_t s) {
-    if (n <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_set_identity<T>, dim3(grid_for(n * n, 256)), dim3(256), 0, s, a, ld, n);
-    return hipGetLastError();
-}
-
 template <typename T, typename U>
 hipError_t convert_2d(const T *src, int64_t lds, U *dst, int64_t ldd, int64_t rows, int64_t cols,
                       hipStream_t s, const int *gather, const int *scatter) {
@@ -878,8 +927,6 @@ template hipError_t permute_rows<float>(float *, int64_t, int64_t, int, int64_t,
                                         const int *, const int *, hipStream_t);
 template hipError_t permute_left<float>(float *, int64_t, int64_t, int, const int *, const int *,
                                         hipStream_t);
-template hipError_t set_identity<double>(double *, int64_t, int64_t, hipStream_t);
-template hipError_t set_identity<float>(float *, int64_t, int64_t, hipStream_t);
 template hipError_t convert_2d<double, double>(const double *, int64_t, double *, int64_t, int64_t,
                                                int64_t, hipStream_t, const int *, const int *);
 template hipError_t convert_2d<double, float>(const double *, int64_t, float *, int64_t, int64_t,

@@ -17,6 +17,16 @@ struct DevStatus {
     int pad;
 };
 
+// p[i] when `in` holds, else 0.  The load is issued unconditionally (from
+// p[0], which must be readable, when `in` is false): a load under a branch
+// makes the wave wait for it where the branch rejoins, so a run of guarded
+// loads would be serialised one memory latency at a time.
+template <typename T>
+__device__ inline T load_if(const T *p, int64_t i, bool in) {
+    const T x = p[in ? i : 0];
+    return in ? x : T(0);
+}
+
 constexpr int kLeaf = 128;      // largest diagonal block factored in LDS
 constexpr int kMaxBlock = 256;  // largest panel width
 
@@ -85,9 +95,6 @@ hipError_t permute_rows(T *a, int64_t ld, int64_t s0, int w, int64_t cb, int64_t
                         const int *piv, const int *abort, hipStream_t s);
 // p[i] = i, i < n.
 hipError_t iota(int *p, int64_t n, hipStream_t s);
-// Element-wise helpers.
-template <typename T>
-hipError_t set_identity(T *a, int64_t ld, int64_t n, hipStream_t s);
 // dst row (scatter ? scatter[i] : i) <- src row (gather ? gather[i] : i), i < rows.
 template <typename T, typename U>
 hipError_t convert_2d(const T *src, int64_t lds, U *dst, int64_t ldd, int64_t rows, int64_t cols,

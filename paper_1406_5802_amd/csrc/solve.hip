@@ -300,25 +300,26 @@ __global__ __launch_bounds__(256) void k_gemv_n(int64_t rows, int64_t cols, doub
             p0[u] = static_cast<double>(m0[c + 64 * u]);
             p1[u] = static_cast<double>(m1[c + 64 * u]);
         }
+        // (right-hand sides past nrhs read x[0] and accumulate zeros: no
+        // load sits under a branch)
 #pragma unroll
         for (int u = 0; u < 4; ++u)
 #pragma unroll
-            for (int r = 0; r < NR; ++r)
-                if (r < nrhs) {
-                    const double xv = static_cast<double>(x[(c + 64 * u) * ldx + r]);
-                    a0[r] += p0[u] * xv;
-                    a1[r] += p1[u] * xv;
-                }
+            for (int r = 0; r < NR; ++r) {
+                const double xv =
+                    static_cast<double>(load_if(x, (c + 64 * u) * ldx + r, r == 0 || r < nrhs));
+                a0[r] += p0[u] * xv;
+                a1[r] += p1[u] * xv;
+            }
     }
     for (; c < cols; c += 64) {
         const double p0 = static_cast<double>(m0[c]), p1 = static_cast<double>(m1[c]);
 #pragma unroll
-        for (int r = 0; r < NR; ++r)
-            if (r < nrhs) {
-                const double xv = static_cast<double>(x[c * ldx + r]);
-                a0[r] += p0 * xv;
-                a1[r] += p1 * xv;
-            }
+        for (int r = 0; r < NR; ++r) {
+            const double xv = static_cast<double>(load_if(x, c * ldx + r, r == 0 || r < nrhs));
+            a0[r] += p0 * xv;
+            a1[r] += p1 * xv;
+        }
     }
 #pragma unroll
     for (int r = 0; r < NR; ++r) {
