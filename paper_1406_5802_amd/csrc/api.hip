@@ -16,7 +16,11 @@
 //         inverses of the 32 x 32 diagonal sub-blocks of a pivot block's L and
 //         U, compact (256 x 32 each)
 //   sinv  the same for every aligned 32-row diagonal sub-block of the final
-//         L and U (2 x round_up(n, 256) x 32), used by the solves
+//         L and U (2 x round_up(n, 256) x 32), used by the solves with several
+//         right-hand sides and the adjoint solves
+//   binv  FP64 inverses of the 128 x 128 diagonal blocks of L and U
+//         (2 x round_up(n, 128) x 128), used by the single right-hand-side
+//         solves
 //   piv   n ints (pivoted variant): row t of the factors is row piv[t] of M
 //   solve workspace, grown on demand: two n x nrhs of T, one n x nrhs FP64
 //         residual, norms
@@ -51,6 +55,8 @@ struct rmge_factors {
     void *inv = nullptr;
     void *sinv = nullptr;  // solve inverses: L part, then U part (sinv_rows rows each)
     int64_t sinv_rows = 0;
+    double *binv = nullptr;  // block inverses: L part, then U part (binv_rows rows each)
+    int64_t binv_rows = 0;
     int *piv = nullptr;  // pivoted variant: P M = L U with row t = row piv[t] of M
     DevStatus *st = nullptr;
     double *scal = nullptr;  // [0] max|U| [1] min|u_kk| [2] max|M| [3] ||A||_inf [4] ||A||_1
@@ -348,6 +354,8 @@ rmge_status run_factor(rmge_factors *f) {
         T *sl = static_cast<T *>(f->sinv);
         RMGE_TRY(diag_inverses<T>(static_cast<const T *>(f->lu), f->ld, f->n, sl,
                                   sl + f->sinv_rows * kSub, f->st, s));
+        RMGE_TRY(block_inverses128<T>(static_cast<const T *>(f->lu), f->ld, f->n, f->binv,
+                                      f->binv + f->binv_rows * 128, s));
     }
     RMGE_TRY(hipMemcpyAsync(&f->host_st, f->st, sizeof(DevStatus), hipMemcpyDeviceToHost, s));
     RMGE_TRY(hipStreamSynchronize(s));
@@ -369,8 +377,8 @@ rmge_status run_factor(rmge_factors *f) {
 
 void free_handle(rmge_factors *f) {
     if (!f) return;
-    void *ptrs[] = {f->lu, f->G, f->params, f->hker, f->hhat, f->tw, f->inv, f->sinv, f->piv,
-                    f->st, f->scal, f->wy, f->wx, f->wr, f->wnorm, f->wt, f->wsync, f->kv};
+    void *ptrs[] = {f->lu, f->G, f->params, f->hker, f->hhat, f->tw, f->inv, f->sinv, f->binv,
+                    f->piv, f->st, f->scal, f->wy, f->wx, f->wr, f->wnorm, f->wt, f->wsync, f->kv};
     for (void *p : ptrs)
         if (p) (void)hipFree(p);
     for (hipEvent_t &e : f->ev)
@@ -402,6 +410,8 @@ rmge_status alloc_handle(rmge_factors *f) {
     const size_t sinv_elems = 2 * static_cast<size_t>(f->sinv_rows) * kSub;
     RMGE_TRY(hipMalloc(&f->sinv, es * sinv_elems));
     RMGE_TRY(hipMemsetAsync(f->sinv, 0, es * sinv_elems, f->stream));
+    f->binv_rows = round_up(n, 128);
+    RMGE_TRY(hipMalloc(&f->binv, sizeof(double) * 2 * static_cast<size_t>(f->binv_rows) * 128));
     if (f->pivot) RMGE_TRY(hipMalloc(&f->piv, sizeof(int) * static_cast<size_t>(n)));
     RMGE_TRY(hipMalloc(&f->st, sizeof(DevStatus)));
     RMGE_TRY(hipMalloc(&f->scal, sizeof(double) * 8));
@@ -476,6 +486,11 @@ hipError_t tri_solves(rmge_factors *f, int64_t nrhs, bool adjoint) {
     // L then U (solve), or U^T then L^T (adjoint)
     const int first = adjoint ? 2 : 0, second = adjoint ? 3 : 1;
     const T *dfirst = adjoint ? Uinv : Linv, *dsecond = adjoint ? Linv : Uinv;
+    if (nrhs == 1 && !adjoint) {  // 128-row blocks with the FP64 block inverses
+        const double *bl = f->binv, *bu = f->binv + f->binv_rows * 128;
+        HIP_TRY(trsv128<T>(0, lu, ld, n, bl, Y, X, 1, f->wsync, s));
+        return trsv128<T>(1, lu, ld, n, bu, X, Y, 1, f->wsync, s);
+    }
     for (int64_t g = 0; g < nrhs; g += 16) {
         const int nr = static_cast<int>((nrhs - g) < 16 ? (nrhs - g) : 16);
         HIP_TRY(trsv_full<T>(first, lu, ld, n, dfirst, Y + g, X + g, nrhs, nr, f->wsync, s));

@@ -268,6 +268,199 @@ __global__ __launch_bounds__(256) void k_trsv(const T *LU, int64_t ld, int64_t n
     }
 }
 
+// ---------------------------------------------------------------------------
+// Single right-hand-side solves with L and U (the refinement and Krylov
+// preconditioner): 128-row blocks, half as many block-to-block hand-offs as
+// k_trsv, and each diagonal block applied as one product with its FP64
+// inverse, computed once after the factorization (k_blkinv128).
+constexpr int BI = 128;
+
+// FP64 inverses of the 128 x 128 diagonal blocks of the unit-lower L
+// (blockIdx.y = 0) and of the upper U (blockIdx.y = 1), in place in LDS;
+// a short last block is padded with the identity.  Output: row I0 + i of
+// Linv / Uinv holds row i of block I's inverse (128 columns, zeros included).
+//   L: X[i][j] = -(l_ij + sum_{j<k<i} X[i][k] l_kj), columns j from right to
+//      left, so column j still holds l_.j while it is read;
+//   U: X[j][j] = 1 / u_jj, X[i][j] = -(sum_{i<=k<j} X[i][k] u_kj) / u_jj,
+//      columns from left to right.
+// Four threads share a row's dot product.
+template <typename T>
+__global__ __launch_bounds__(512) void k_blkinv128(const T *lu, int64_t ld, int64_t n,
+                                                   double *Linv, double *Uinv) {
+    __shared__ double X[BI][BI + 1];
+    const int64_t I0 = static_cast<int64_t>(blockIdx.x) * BI;
+    const bool upper = blockIdx.y == 1;
+    const int bI = static_cast<int>((n - I0) < BI ? (n - I0) : BI);
+    const int tid = threadIdx.x;
+    {
+        T v[BI * BI / 512];  // all loads in flight before the first store
+#pragma unroll
+        for (int m = 0; m < BI * BI / 512; ++m) {
+            const int e = tid + 512 * m, i = e / BI, j = e % BI;
+            const bool in = i < bI && j < bI && (upper ? j >= i : j < i);
+            v[m] = load_if(lu, (I0 + i) * ld + I0 + j, in);
+        }
+#pragma unroll
+        for (int m = 0; m < BI * BI / 512; ++m) {
+            const int e = tid + 512 * m, i = e / BI, j = e % BI;
+            const bool in = i < bI && j < bI && (upper ? j >= i : j < i);
+            X[i][j] = in ? static_cast<double>(v[m]) : ((i == j && (!upper || i >= bI)) ? 1.0 : 0.0);
+        }
+    }
+    __syncthreads();
+    const int i = tid >> 2, h = tid & 3;
+    if (!upper) {
+        for (int j = BI - 2; j >= 0; --j) {
+            double p = 0.0;
+            if (i > j)
+                for (int k = j + 1 + h; k < i; k += 4) p += X[i][k] * X[k][j];
+            p += __shfl_xor(p, 1);
+            p += __shfl_xor(p, 2);
+            __syncthreads();  // column j has been read everywhere
+            if (i > j && h == 0) X[i][j] = -(X[i][j] + p);
+            __syncthreads();
+        }
+    } else {
+        for (int j = 0; j < BI; ++j) {
+            double p = 0.0;
+            if (i < j)
+                for (int k = i + h; k < j; k += 4) p += X[i][k] * X[k][j];
+            p += __shfl_xor(p, 1);
+            p += __shfl_xor(p, 2);
+            const double d = X[j][j];
+            __syncthreads();  // column j and u_jj have been read everywhere
+            if (h == 0) {
+                if (i < j) X[i][j] = -p / d;
+                else if (i == j) X[j][j] = 1.0 / d;
+            }
+            __syncthreads();
+        }
+    }
+    double *out = upper ? Uinv : Linv;
+    for (int e = tid; e < BI * BI; e += 512) {
+        const int r = e / BI, c = e % BI;
+        out[(I0 + r) * BI + c] = X[r][c];
+    }
+}
+
+// 32 consecutive factor entries from p (32-element aligned).
+template <typename T>
+__device__ inline void load_row32(const T *p, T (&dst)[32]) {
+    typedef T v4 __attribute__((ext_vector_type(16 / sizeof(T))));
+    constexpr int W = 16 / sizeof(T);
+#pragma unroll
+    for (int c = 0; c < 32 / W; ++c) {
+        const v4 v = reinterpret_cast<const v4 *>(p)[c];
+#pragma unroll
+        for (int e = 0; e < W; ++e) dst[W * c + e] = v[e];
+    }
+}
+
+// MODE 0: L y = b (forward), MODE 1: U y = b (backward); one right-hand side.
+// Same ticket order, mark-as-flag hand-off and bounded waits as k_trsv.
+// Thread (r, q) owns row r of its block and columns 32 q .. 32 q + 31 of
+// each coupling tile (prefetched one tile ahead) and of the block inverse.
+template <typename T, int MODE>
+__global__ __launch_bounds__(512) void k_trsv128(const T *LU, int64_t ld, int64_t n,
+                                                 const double *Dinv, const double *B, double *X,
+                                                 int64_t ldx, int *sync) {
+    constexpr bool forward = MODE == 0;
+    __shared__ double ys[2][BI];
+    __shared__ double ss[BI];
+    __shared__ int s_ticket, s_fail;
+    int *counter = sync, *err = sync + 1;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    if (tid == 0) {
+        s_ticket = atomicAdd(counter, 1);
+        s_fail = 0;
+    }
+    __syncthreads();
+    const int nblk = static_cast<int>((n + BI - 1) / BI);
+    const int I = forward ? s_ticket : nblk - 1 - s_ticket;
+    const int64_t I0 = static_cast<int64_t>(I) * BI;
+    const int bI = static_cast<int>((n - I0) < BI ? (n - I0) : BI);
+    const int r = tid >> 2, q = tid & 3;
+    const double bval = load_if(B, (I0 + r) * ldx, q == 0 && r < bI);
+    // this thread's part of the block inverse: fetched in place of the tile
+    // prefetch during the last coupling step (or now, if there is none)
+    double dreg[32];
+    auto load_dinv = [&]() {
+#pragma unroll
+        for (int i = 0; i < 32; ++i) dreg[i] = Dinv[(I0 + r) * BI + 32 * q + i];
+    };
+    auto load_tile = [&](int J, T (&dst)[32]) {
+        const int64_t J0 = static_cast<int64_t>(J) * BI;
+        const int bJ = static_cast<int>((n - J0) < BI ? (n - J0) : BI);
+        if (bI == BI && bJ == BI) {
+            load_row32(LU + (I0 + r) * ld + J0 + 32 * q, dst);
+        } else {
+#pragma unroll
+            for (int i = 0; i < 32; ++i)
+                dst[i] = load_if(LU, (I0 + r) * ld + J0 + 32 * q + i, r < bI && 32 * q + i < bJ);
+        }
+    };
+    const int jfirst = forward ? 0 : nblk - 1, jstep = forward ? 1 : -1;
+    T cur[32], nxt[32];
+    if (I != jfirst)
+        load_tile(jfirst, nxt);
+    else
+        load_dinv();
+    double acc = 0.0;
+    int par = 0;
+    for (int J = jfirst; J != I; J += jstep, par ^= 1) {
+#pragma unroll
+        for (int i = 0; i < 32; ++i) cur[i] = nxt[i];
+        if (J + jstep != I)
+            load_tile(J + jstep, nxt);
+        else
+            load_dinv();
+        if (wave == 0) {
+            // y_J, two entries a lane (lanes past the block poll its first entry)
+            const int64_t J0 = static_cast<int64_t>(J) * BI;
+            const int bJ = static_cast<int>((n - J0) < BI ? (n - J0) : BI);
+            const bool in0 = lane < bJ, in1 = lane + 64 < bJ;
+            const double *p0 = X + (J0 + (in0 ? lane : 0)) * ldx;
+            const double *p1 = X + (J0 + (in1 ? lane + 64 : 0)) * ldx;
+            double v0 = 0.0, v1 = 0.0;
+            int spins = 0;
+            while (true) {
+                bool ok0, ok1;
+                v0 = poll_value(p0, &ok0);
+                v1 = poll_value(p1, &ok1);
+                if (__all(ok0 && ok1)) break;
+                const bool give_up =
+                    (++spins > kSpinLimit) ||
+                    __hip_atomic_load(err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0;
+                if (__any(give_up)) {
+                    if (lane == 0) s_fail = 1;
+                    break;
+                }
+                __builtin_amdgcn_s_sleep(1);
+            }
+            ys[par][lane] = in0 ? v0 : 0.0;
+            ys[par][lane + 64] = in1 ? v1 : 0.0;
+        }
+        __syncthreads();  // (ys[par] is next written two tiles later, after another barrier)
+        if (s_fail) break;
+#pragma unroll
+        for (int i = 0; i < 32; ++i) acc += static_cast<double>(cur[i]) * ys[par][32 * q + i];
+    }
+    if (s_fail) {
+        if (tid == 0) atomicExch(err, 1);  // blocks waiting on this one see it and stop
+        return;
+    }
+    acc += __shfl_xor(acc, 1);
+    acc += __shfl_xor(acc, 2);
+    if (q == 0) ss[r] = (r < bI) ? bval - acc : 0.0;
+    __syncthreads();
+    double x = 0.0;
+#pragma unroll
+    for (int i = 0; i < 32; ++i) x += dreg[i] * ss[32 * q + i];
+    x += __shfl_xor(x, 1);
+    x += __shfl_xor(x, 2);
+    if (q == 0 && r < bI) publish_value(X + (I0 + r) * ldx, x);
+}
+
 // Before a solve: reset the ticket counter and mark every output entry unsolved.
 __global__ void k_trsv_prep(double *X, int64_t ldx, int64_t n, int nr, int *sync) {
     if (blockIdx.x == 0 && threadIdx.x == 0) sync[0] = 0;
@@ -586,6 +779,32 @@ hipError_t trsv_full(int mode, const T *LU, int64_t ld, int64_t n, const T *Dinv
     }
 }
 
+template <typename T>
+hipError_t block_inverses128(const T *lu, int64_t ld, int64_t n, double *Linv, double *Uinv,
+                             hipStream_t s) {
+    if (n < 1) return hipSuccess;
+    const unsigned nblk = static_cast<unsigned>((n + BI - 1) / BI);
+    hipLaunchKernelGGL(k_blkinv128<T>, dim3(nblk, 2), dim3(512), 0, s, lu, ld, n, Linv, Uinv);
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t trsv128(int mode, const T *LU, int64_t ld, int64_t n, const double *Dinv,
+                   const double *B, double *X, int64_t ldx, int *sync, hipStream_t s) {
+    if (n < 1 || B == X || (mode != 0 && mode != 1)) return hipErrorInvalidValue;
+    const int nblk = static_cast<int>((n + BI - 1) / BI);
+    hipLaunchKernelGGL(k_trsv_prep, dim3(grid_for(n, 256)), dim3(256), 0, s, X, ldx, n, 1, sync);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    if (mode == 0)
+        hipLaunchKernelGGL((k_trsv128<T, 0>), dim3(nblk), dim3(512), 0, s, LU, ld, n, Dinv, B, X,
+                           ldx, sync);
+    else
+        hipLaunchKernelGGL((k_trsv128<T, 1>), dim3(nblk), dim3(512), 0, s, LU, ld, n, Dinv, B, X,
+                           ldx, sync);
+    return hipGetLastError();
+}
+
 template <typename TM, typename TX, typename TY>
 hipError_t gemv_n(int64_t rows, int64_t cols, double alpha, const TM *Mat, int64_t ldm,
                   const TX *x, int64_t ldx, double beta, TY *y, int64_t ldy, int nrhs,
@@ -712,6 +931,14 @@ hipError_t grad_a(const double *GB, int64_t ldgb, const double *X, int64_t ldx, 
     return hipGetLastError();
 }
 
+template hipError_t block_inverses128<double>(const double *, int64_t, int64_t, double *,
+                                              double *, hipStream_t);
+template hipError_t block_inverses128<float>(const float *, int64_t, int64_t, double *, double *,
+                                             hipStream_t);
+template hipError_t trsv128<double>(int, const double *, int64_t, int64_t, const double *,
+                                    const double *, double *, int64_t, int *, hipStream_t);
+template hipError_t trsv128<float>(int, const float *, int64_t, int64_t, const double *,
+                                   const double *, double *, int64_t, int *, hipStream_t);
 template hipError_t trsv_full<double>(int, const double *, int64_t, int64_t, const double *,
                                       const double *, double *, int64_t, int, int *, hipStream_t);
 template hipError_t trsv_full<float>(int, const float *, int64_t, int64_t, const float *,
