@@ -716,7 +716,7 @@ rmge_status ensure_krylov_ws(rmge_factors *f, int restart) {
     f->kv_restart = 0;
     const size_t n = static_cast<size_t>(f->n);
     const size_t words = (2 * static_cast<size_t>(restart) + 2) * n + 256 * kMaxRestart +
-                         4 * kMaxRestart;
+                         6 * kMaxRestart;
     RMGE_TRY(hipMalloc(&f->kv, sizeof(double) * words));
     f->kv_restart = restart;
     return RMGE_OK;
@@ -740,6 +740,7 @@ rmge_status run_gmres(rmge_factors *f, bool trans, const double *B, int64_t nrhs
     double *dv = part + 256 * kMaxRestart;         // [0, 64) h, [64, 128) h2, [128] |w|^2,
                                                    // [129 ..] norms; [192, 256) y
     double *hy = dv + 3 * kMaxRestart;
+    double *rc = dv + 4 * kMaxRestart;             // residual coefficients (restart + 1)
     auto precond = [&](const double *src, int64_t lds, int64_t nr, double *dst, int64_t ldd) {
         return trans ? apply_adjoint<T>(f, src, lds, nr, dst, ldd, 0.0)
                      : apply_inverse<T>(f, src, lds, nr, dst, ldd, 0.0);
@@ -780,7 +781,8 @@ rmge_status run_gmres(rmge_factors *f, bool trans, const double *B, int64_t nrhs
     bool all_ok = true;
     double worst0 = 0.0, worst = 0.0;
     std::vector<double> H(static_cast<size_t>((restart + 1) * restart)), cs(restart), sn(restart),
-        g(restart + 1), y(restart), hh(3 * kMaxRestart);
+        g(restart + 1), y(restart), hh(3 * kMaxRestart), u(restart + 1);
+    const double sqrt_n = std::sqrt(static_cast<double>(n));
     for (int64_t c = 0; c < nrhs; ++c) {
         double eta = 0.0;
         bool first = true;
@@ -846,7 +848,31 @@ rmge_status run_gmres(rmge_factors *f, bool trans, const double *B, int64_t nrhs
                 g[j + 1] = -sn[j] * g[j];
                 g[j] = cs[j] * g[j];
                 k = j + 1;
-                if (std::fabs(g[j + 1]) <= target || !(hnext > 1e-300 * beta)) break;
+                const double rn2 = std::fabs(g[j + 1]);
+                if (rn2 <= target || !(hnext > 1e-300 * beta)) break;
+                if (rn2 <= sqrt_n * target && j + 1 < restart) {
+                    // ||r||_inf may already meet the target: form the residual
+                    // from the basis, r = g_{j+1} V_{0..j+1} (G_0^T .. G_j^T e_{j+1}),
+                    // and stop when its max norm does (the outer step then checks
+                    // b - op(A) x itself; the last step of a cycle goes there anyway)
+                    std::fill(u.begin(), u.begin() + (j + 2), 0.0);
+                    u[j + 1] = g[j + 1];
+                    for (int i = j; i >= 0; --i) {
+                        const double a0 = u[i], b0 = u[i + 1];
+                        u[i] = cs[i] * a0 - sn[i] * b0;
+                        u[i + 1] = sn[i] * a0 + cs[i] * b0;
+                    }
+                    RMGE_TRY(hipMemcpyAsync(rc, u.data(), (j + 2) * sizeof(double),
+                                            hipMemcpyHostToDevice, s));
+                    RMGE_TRY(fill_f64(R, n, 0.0, s));
+                    RMGE_TRY(lincomb(R, 1, V, n, j + 2, rc, 1.0, s));
+                    RMGE_TRY(fill_f64(dv + 129, 1, 0.0, s));
+                    RMGE_TRY(colmax_abs(R, 1, n, 1, dv + 129, s));
+                    RMGE_TRY(hipMemcpyAsync(hh.data() + 129, dv + 129, sizeof(double),
+                                            hipMemcpyDeviceToHost, s));
+                    RMGE_TRY(hipStreamSynchronize(s));
+                    if (hh[129] <= target) break;
+                }
             }
             if (k == 0) break;
             for (int i = k - 1; i >= 0; --i) {  // R y = g
