@@ -236,6 +236,16 @@ __global__ __launch_bounds__(kLeafThreads) void k_leaf_lu(T *a, int64_t lda, int
     // a single exit and the columns are updated in place.
     const int jw = min(b, 16 * w + 15);
     for (; j < jw; ++j) {
+        // the wave that publishes the next column (and elects its pivot) is
+        // the chain: let it issue first on its SIMD; the other waves keep a
+        // priority above a GEMM's.  (Measured: faster with pivoting, slower
+        // without, where the next block's owner then lags at block boundaries.)
+        if (PIV) {
+            if (((j + 1) >> 4) == w)
+                __builtin_amdgcn_s_setprio(3);
+            else
+                __builtin_amdgcn_s_setprio(1);
+        }
         int fv;
         T c0, c1, rp;
         if (mine) {
@@ -281,6 +291,7 @@ __global__ __launch_bounds__(kLeafThreads) void k_leaf_lu(T *a, int64_t lda, int
     }
     // The remaining steps leave this wave's columns alone: follow the flags
     // and stop where the others stop.
+    if (PIV) __builtin_amdgcn_s_setprio(1);
     if (done == b) {
         for (; j < b; ++j) {
             const int fv = await_column(j);
@@ -325,12 +336,14 @@ __global__ __launch_bounds__(kLeafThreads) void k_leaf_lu(T *a, int64_t lda, int
 // (the off-diagonal coupling is applied by blocked substitution, so only these
 // small inverses are formed).  Workgroup g covers rows 128 g .. 128 g + 127 of
 // the b x b block at `a`; wave w < nsub inverts U's sub-block w, wave nsub + w
-// the unit-lower L's; lane c computes column c by substitution.  Compact
-// output: row 32 q + i of Linv / Uinv holds row i of sub-block q's inverse.
+// the unit-lower L's.  Lane c (< 32) holds column c of its sub-block in
+// registers and computes column c of the inverse by substitution, reading
+// the entries of factor row i from the lanes that hold their columns.
+// Compact output: row 32 q + i of Linv / Uinv holds row i of sub-block q's
+// inverse.
 template <typename T>
-__global__ __launch_bounds__(512) void k_diag_inv(const T *a, int64_t lda, int b, T *Linv, T *Uinv,
+__global__ __launch_bounds__(512, 1) void k_diag_inv(const T *a, int64_t lda, int b, T *Linv, T *Uinv,
                                                   const DevStatus *st) {
-    __shared__ T dblk[4][kSub][kSub + 1];
     if (st->code != 0) return;
     __builtin_amdgcn_s_setprio(3);
     const int64_t g0 = static_cast<int64_t>(blockIdx.x) * 4 * kSub;
@@ -338,48 +351,46 @@ __global__ __launch_bounds__(512) void k_diag_inv(const T *a, int64_t lda, int b
     Linv += g0 * kSub;
     Uinv += g0 * kSub;
     b = (b - g0) < 4 * kSub ? static_cast<int>(b - g0) : 4 * kSub;
-    const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+    const int tid = threadIdx.x, lane = tid & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
     const int nsub = (b + kSub - 1) / kSub;
-    for (int e = tid; e < nsub * kSub * kSub; e += blockDim.x) {
-        const int qd = e / (kSub * kSub), i = (e / kSub) % kSub, k = e % kSub;
-        const int gi = qd * kSub + i, gk = qd * kSub + k;
-        dblk[qd][i][k] = (gi < b && gk < b) ? a[static_cast<int64_t>(gi) * lda + gk] : T(0);
-    }
-    __syncthreads();
-    if (wave >= 2 * nsub || lane >= kSub) return;
+    if (wave >= 2 * nsub) return;
     const bool upper = wave < nsub;
-    const int qd = upper ? wave : wave - nsub, c = lane;
-    const int q0 = qd * kSub;
+    const int qd = upper ? wave : wave - nsub, q0 = qd * kSub;
     const int sbq = (b - q0) < kSub ? (b - q0) : kSub;
-    if (c >= sbq) return;
-    T x[kSub];
+    const int c = lane & (kSub - 1);  // lanes 32 .. 63 repeat 0 .. 31 and store nothing
+    T col[kSub], x[kSub];
+#pragma unroll
+    for (int k = 0; k < kSub; ++k)
+        col[k] = load_if(a, static_cast<int64_t>(q0 + k) * lda + q0 + c, k < sbq && c < sbq);
+    // (row-oriented substitution, sums in ascending k: the order whose rounding
+    // the blocked solves were validated with; a column sweep was measured to
+    // leave larger errors in the U inverses of strongly growing factors)
     if (upper) {
-        // column c of U^{-1}: x_c = 1/u_cc, x_i = -(sum_{k=i+1..c} u_ik x_k) / u_ii
+        // x_c = 1 / u_cc, x_i = -(sum_{k=i+1..c} u_ik x_k) / u_ii, x_i = 0 for i > c
 #pragma unroll
         for (int i = kSub - 1; i >= 0; --i) {
             T sum = T(0);
 #pragma unroll
-            for (int k = i + 1; k < kSub; ++k)
-                if (k <= c) sum += dblk[qd][i][k] * x[k];
-            const T d = (i <= c) ? T(1) / dblk[qd][i][i] : T(0);
+            for (int k = i + 1; k < kSub; ++k) sum += lane_value<T>(col[i], k) * x[k];
+            const T d = (i <= c && i < sbq) ? T(1) / lane_value<T>(col[i], i) : T(0);
             x[i] = (i == c) ? d : ((i < c) ? -sum * d : T(0));
         }
-#pragma unroll
-        for (int i = 0; i < kSub; ++i)
-            if (i < sbq) Uinv[static_cast<int64_t>(q0 + i) * kSub + c] = x[i];
     } else {
-        // column c of L^{-1}: x_c = 1, x_i = -sum_{k=c..i-1} l_ik x_k
+        // x_c = 1, x_i = -sum_{k=c..i-1} l_ik x_k, x_i = 0 for i < c
 #pragma unroll
         for (int i = 0; i < kSub; ++i) {
             T sum = T(0);
 #pragma unroll
-            for (int k = 0; k < i; ++k)
-                if (k >= c) sum += dblk[qd][i][k] * x[k];
+            for (int k = 0; k < i; ++k) sum += lane_value<T>(col[i], k) * x[k];
             x[i] = (i == c) ? T(1) : ((i > c) ? -sum : T(0));
         }
+    }
+    if (lane < kSub && c < sbq) {
+        T *out = upper ? Uinv : Linv;
 #pragma unroll
-        for (int i = 0; i < kSub; ++i)
-            if (i < sbq) Linv[static_cast<int64_t>(q0 + i) * kSub + c] = x[i];
+        for (int k = 0; k < kSub; ++k)
+            if (k < sbq) out[static_cast<int64_t>(q0 + k) * kSub + c] = x[k];
     }
 }
 
@@ -393,9 +404,8 @@ __global__ __launch_bounds__(512) void k_diag_inv(const T *a, int64_t lda, int b
 // further along.
 //
 // The substitution is a chain of b / 32 short steps, so operands are fetched
-// ahead: the next sub-block inverse one step early, a step's factor operands
-// at the start of the step, which hides their memory latency behind the
-// publish / multiply phases of the step.
+// one step ahead (the next sub-block inverse and the next step's factor
+// operands), which hides their memory latency behind the current step.
 //
 // LEFT:  C (b x count) <- L^{-1} P C, strips of 32 columns (row tiles dealt).
 // With `rowsrc` (pivoted blocks) row t of P C is row rowsrc[t] - rowbase of C:
@@ -467,10 +477,9 @@ __global__ __launch_bounds__(256, sizeof(T) == 8 ? 1 : 2) void k_trsm_left(const
                 const bool in = t < nrt && row < b && col < wcols;
                 acc[u][j][r] = load_if(C, src[u][r] * ldc + c0 + col, in);
             }
-    for (int i = 0, i0 = 0; i0 < b; ++i, i0 += kSub) {
-        const int sb = (b - i0) < kSub ? (b - i0) : kSub;
-        // this step's factor operands: -L[row][i0 + k], row tiles below sub-block i
-        T f[4][kSub / 4];
+    // step i's factor operands: -L[row][32 i + k], row tiles below sub-block i
+    auto fetch_f = [&](int i, T (&f)[4][kSub / 4]) {
+        const int i0 = i * kSub, sb = (b - i0) < kSub ? (b - i0) : kSub;
 #pragma unroll
         for (int u = 0; u < 4; ++u) {
             const int t = wave + 4 * u, row = 16 * t + lo;
@@ -478,9 +487,15 @@ __global__ __launch_bounds__(256, sizeof(T) == 8 ? 1 : 2) void k_trsm_left(const
 #pragma unroll
             for (int kq = 0; kq < kSub / 4; ++kq) {
                 const int k = 4 * kq + hi;
-                f[u][kq] = -load_if(lu, row * ld + i0 + k, below && k < sb);
+                f[u][kq] = -load_if(lu, row * ld + i0 + k, below && sb > 0 && k < sb);
             }
         }
+    };
+    T f[4][kSub / 4], fnext[4][kSub / 4];
+    fetch_f(0, f);
+    for (int i = 0, i0 = 0; i0 < b; ++i, i0 += kSub) {
+        const int sb = (b - i0) < kSub ? (b - i0) : kSub;
+        fetch_f(i + 1, fnext);
         fetch_dinv(Dinv, b, i + 1, tid, dnext);
         store_dinv(Ds, tid, dcur);
 #pragma unroll
@@ -542,6 +557,10 @@ __global__ __launch_bounds__(256, sizeof(T) == 8 ? 1 : 2) void k_trsm_left(const
         __syncthreads();
 #pragma unroll
         for (int m = 0; m < 4; ++m) dcur[m] = dnext[m];
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+#pragma unroll
+            for (int kq = 0; kq < kSub / 4; ++kq) f[u][kq] = fnext[u][kq];
     }
 #pragma unroll
     for (int u = 0; u < 4; ++u)
@@ -585,10 +604,9 @@ __global__ __launch_bounds__(256, sizeof(T) == 8 ? 1 : 2) void k_trsm_right(cons
                 const int row = 16 * q + Mma<T>::row(lane, r), col = 16 * c + lo;
                 acc[u][q][r] = load_if(C, (r0 + row) * ldc + col, c < nct && row < wrows && col < b);
             }
-    for (int j = 0, j0 = 0; j0 < b; ++j, j0 += kSub) {
-        const int sb = (b - j0) < kSub ? (b - j0) : kSub;
-        // this step's factor operands: -U[j0 + k][col], column tiles right of sub-block j
-        T f[4][kSub / 4];
+    // step j's factor operands: -U[32 j + k][col], column tiles right of sub-block j
+    auto fetch_f = [&](int j, T (&f)[4][kSub / 4]) {
+        const int j0 = j * kSub, sb = (b - j0) < kSub ? (b - j0) : kSub;
 #pragma unroll
         for (int u = 0; u < 4; ++u) {
             const int c = wave + 4 * u, col = 16 * c + lo;
@@ -596,9 +614,15 @@ __global__ __launch_bounds__(256, sizeof(T) == 8 ? 1 : 2) void k_trsm_right(cons
 #pragma unroll
             for (int kq = 0; kq < kSub / 4; ++kq) {
                 const int k = 4 * kq + hi;
-                f[u][kq] = -load_if(lu, (j0 + k) * ld + col, right && k < sb);
+                f[u][kq] = -load_if(lu, (j0 + k) * ld + col, right && sb > 0 && k < sb);
             }
         }
+    };
+    T f[4][kSub / 4], fnext[4][kSub / 4];
+    fetch_f(0, f);
+    for (int j = 0, j0 = 0; j0 < b; ++j, j0 += kSub) {
+        const int sb = (b - j0) < kSub ? (b - j0) : kSub;
+        fetch_f(j + 1, fnext);
         fetch_dinv(Dinv, b, j + 1, tid, dnext);
         store_dinv(Ds, tid, dcur);
 #pragma unroll
@@ -660,6 +684,10 @@ __global__ __launch_bounds__(256, sizeof(T) == 8 ? 1 : 2) void k_trsm_right(cons
         __syncthreads();
 #pragma unroll
         for (int m = 0; m < 4; ++m) dcur[m] = dnext[m];
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+#pragma unroll
+            for (int kq = 0; kq < kSub / 4; ++kq) f[u][kq] = fnext[u][kq];
     }
 #pragma unroll
     for (int u = 0; u < 4; ++u)
