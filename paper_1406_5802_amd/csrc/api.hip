@@ -47,6 +47,7 @@ struct rmge_factors {
     const double *A = nullptr;
     void *lu = nullptr;
     void *G = nullptr;         // GAUSSIAN multiplier (T)
+    float *a32 = nullptr;      // FP32 GAUSSIAN: A rounded to FP32 (n x ld) for the product
     double *params = nullptr;  // structured multiplier parameters
     double *hker = nullptr;    // period-m kernel
     double *hhat = nullptr;    // half spectrum (m/2 + 1 complex)
@@ -319,6 +320,14 @@ hipError_t multiply(rmge_factors *f, double *absmax) {
         HIP_TRY((convert_2d<double, T>(f->A, f->lda, lu, f->ld, n, n, s)));
         return absmax ? abs_max<T>(lu, f->ld, n, absmax - 2, s) : hipSuccess;
     case RMGE_MULT_GAUSSIAN:
+        if (f->a32) {
+            // FP32: round A once (the same rounding the product applies on load)
+            // and run the FP32 x FP32 product, halving A's share of its traffic
+            HIP_TRY((convert_2d<double, float>(f->A, f->lda, f->a32, f->ld, n, n, s)));
+            return gemm_f32(kGemmProduct, n, n, n, 1.0f, f->a32, f->ld,
+                            static_cast<const float *>(f->G), n, 0.0f,
+                            reinterpret_cast<float *>(lu), f->ld, nullptr, s, absmax);
+        }
         return Prec<T>::gemm_a64(n, n, n, f->A, f->lda, static_cast<const T *>(f->G), n, lu,
                                  f->ld, absmax, s);
     default:
@@ -378,7 +387,7 @@ rmge_status run_factor(rmge_factors *f) {
 void free_handle(rmge_factors *f) {
     if (!f) return;
     void *ptrs[] = {f->lu, f->G, f->params, f->hker, f->hhat, f->tw, f->inv, f->sinv, f->binv,
-                    f->piv, f->st, f->scal, f->wy, f->wx, f->wr, f->wnorm, f->wt, f->wsync, f->kv};
+                    f->piv, f->st, f->a32, f->scal, f->wy, f->wx, f->wr, f->wnorm, f->wt, f->wsync, f->kv};
     for (void *p : ptrs)
         if (p) (void)hipFree(p);
     for (hipEvent_t &e : f->ev)
@@ -395,6 +404,8 @@ rmge_status alloc_handle(rmge_factors *f) {
     const size_t es = elem_size(f->prec);
     RMGE_TRY(hipMalloc(&f->lu, es * static_cast<size_t>(n) * f->ld));
     if (f->kind == RMGE_MULT_GAUSSIAN) RMGE_TRY(hipMalloc(&f->G, es * static_cast<size_t>(n * n)));
+    if (f->kind == RMGE_MULT_GAUSSIAN && f->prec == RMGE_F32)
+        RMGE_TRY(hipMalloc(&f->a32, sizeof(float) * static_cast<size_t>(n) * f->ld));
     if (f->kind == RMGE_MULT_CIRCULANT || f->kind == RMGE_MULT_TOEPLITZ) {
         const int L = f->m / 2;
         RMGE_TRY(hipMalloc(&f->params, sizeof(double) * static_cast<size_t>(2 * n)));

@@ -494,7 +494,6 @@ __global__ __launch_bounds__(256, sizeof(T) == 8 ? 1 : 2) void k_trsm_left(const
     T f[4][kSub / 4], fnext[4][kSub / 4];
     fetch_f(0, f);
     for (int i = 0, i0 = 0; i0 < b; ++i, i0 += kSub) {
-        const int sb = (b - i0) < kSub ? (b - i0) : kSub;
         fetch_f(i + 1, fnext);
         fetch_dinv(Dinv, b, i + 1, tid, dnext);
         store_dinv(Ds, tid, dcur);
@@ -621,7 +620,6 @@ __global__ __launch_bounds__(256, sizeof(T) == 8 ? 1 : 2) void k_trsm_right(cons
     T f[4][kSub / 4], fnext[4][kSub / 4];
     fetch_f(0, f);
     for (int j = 0, j0 = 0; j0 < b; ++j, j0 += kSub) {
-        const int sb = (b - j0) < kSub ? (b - j0) : kSub;
         fetch_f(j + 1, fnext);
         fetch_dinv(Dinv, b, j + 1, tid, dnext);
         store_dinv(Ds, tid, dcur);
