@@ -95,7 +95,8 @@ typedef struct {
     int32_t block;         /* panel width used */
     double min_abs_pivot;  /* min_k |u_kk| (computed on demand, see rmge_factor_stats_get) */
     double growth;         /* max |U| / max |M| */
-    double ms_multiplier;  /* device time of the last factorization: drawing H */
+    double ms_multiplier;  /* device time of the last factorization: drawing H (and, for
+                              FP32 factors with a Gaussian H, rounding A to FP32 once) */
     double ms_product;     /* device time: M = A H (one GEMM launch, or the FFT pass) */
     double ms_factor;      /* device time: the elimination (all pivot steps) */
 } rmge_factor_stats;

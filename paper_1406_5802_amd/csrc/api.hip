@@ -320,14 +320,10 @@ hipError_t multiply(rmge_factors *f, double *absmax) {
         HIP_TRY((convert_2d<double, T>(f->A, f->lda, lu, f->ld, n, n, s)));
         return absmax ? abs_max<T>(lu, f->ld, n, absmax - 2, s) : hipSuccess;
     case RMGE_MULT_GAUSSIAN:
-        if (f->a32) {
-            // FP32: round A once (the same rounding the product applies on load)
-            // and run the FP32 x FP32 product, halving A's share of its traffic
-            HIP_TRY((convert_2d<double, float>(f->A, f->lda, f->a32, f->ld, n, n, s)));
+        if (f->a32)  // A already rounded to FP32 (round_a): an FP32 x FP32 product
             return gemm_f32(kGemmProduct, n, n, n, 1.0f, f->a32, f->ld,
                             static_cast<const float *>(f->G), n, 0.0f,
                             reinterpret_cast<float *>(lu), f->ld, nullptr, s, absmax);
-        }
         return Prec<T>::gemm_a64(n, n, n, f->A, f->lda, static_cast<const T *>(f->G), n, lu,
                                  f->ld, absmax, s);
     default:
@@ -336,9 +332,18 @@ hipError_t multiply(rmge_factors *f, double *absmax) {
     }
 }
 
+// FP32 factors with a dense multiplier: round A to FP32 once (the same
+// rounding the product would apply on load), so the product streams half the
+// bytes for A.
+hipError_t round_a(rmge_factors *f) {
+    if (!f->a32) return hipSuccess;
+    return convert_2d<double, float>(f->A, f->lda, f->a32, f->ld, f->n, f->n, f->stream);
+}
+
 template <typename T>
 hipError_t precondition(rmge_factors *f) {
     HIP_TRY(draw_multiplier<T>(f));
+    HIP_TRY(round_a(f));
     return multiply<T>(f, nullptr);
 }
 
@@ -352,6 +357,7 @@ rmge_status run_factor(rmge_factors *f) {
     RMGE_TRY(hipGetLastError());
     RMGE_TRY(hipEventRecord(f->ev[0], s));
     RMGE_TRY(draw_multiplier<T>(f));
+    RMGE_TRY(round_a(f));
     RMGE_TRY(hipEventRecord(f->ev[1], s));
     RMGE_TRY(multiply<T>(f, f->scal + 2));
     RMGE_TRY(hipEventRecord(f->ev[2], s));
