@@ -198,6 +198,13 @@ rmge_status rmge_grad_A(const double *GB, int64_t ldgb, const double *X, int64_t
  * the first call (one pass over M's diagonal and U) and cached. */
 rmge_status rmge_factor_stats_get(const rmge_factors *f, rmge_factor_stats *s);
 
+/* The phase times of the last factorization (the ms_* fields of
+ * rmge_factor_stats, recorded by HIP events on the handle's stream), without
+ * the device pass rmge_factor_stats_get makes for the growth: ms3[0] drawing H
+ * (and rounding A), ms3[1] the product M = A H, ms3[2] the elimination.  Host
+ * only; ms3 is a host array of 3 doubles.  EINVAL on a null argument. */
+rmge_status rmge_factor_times(const rmge_factors *f, double *ms3);
+
 /* Copy the packed factors (unit L strictly below the diagonal, U on and above)
  * into LU (device, n x n, ld >= n), converted to FP64.  Pivoted handles:
  * L U = P M, rows in the order of rmge_factors_perm. */

@@ -92,6 +92,13 @@ class Factors:
                 "ms_multiplier": st.ms_multiplier, "ms_product": st.ms_product,
                 "ms_factor": st.ms_factor}
 
+    def times(self):
+        """Phase times (ms) of the last factorization, with no device work."""
+        rc, ms = _rmge.rmge_factor_times(self._h)
+        if rc:
+            raise RMGEError(rc, "rmge_factor_times")
+        return {"ms_multiplier": ms[0], "ms_product": ms[1], "ms_factor": ms[2]}
+
     @property
     def info(self) -> int:
         return self.stats()["info"]

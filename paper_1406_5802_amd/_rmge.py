@@ -26,7 +26,7 @@ STATUS_NAMES = {
 EXPORTS = (
     "rmge_factor", "rmge_factor_ex", "rmge_factor_pivoted", "rmge_refactor", "rmge_solve",
     "rmge_solve_gmres", "rmge_solve_adjoint", "rmge_solve_adjoint_ex", "rmge_grad_A",
-    "rmge_factor_stats_get", "rmge_factors_lu", "rmge_factors_perm", "rmge_multiplier_params",
+    "rmge_factor_stats_get", "rmge_factor_times", "rmge_factors_lu", "rmge_factors_perm", "rmge_multiplier_params",
     "rmge_param_count", "rmge_precondition", "rmge_destroy", "rmge_status_string", "rmge_version",
 )
 
@@ -74,6 +74,7 @@ def lib() -> ctypes.CDLL:
     L.rmge_solve_adjoint_ex.argtypes = [vp, dp, i64, i64, dp, i64, i32, ctypes.c_double,
                                         ctypes.POINTER(rmge_solve_stats)]
     L.rmge_factor_stats_get.argtypes = [vp, ctypes.POINTER(rmge_factor_stats)]
+    L.rmge_factor_times.argtypes = [vp, ctypes.POINTER(ctypes.c_double)]
     L.rmge_factors_lu.argtypes = [vp, dp, i64]
     L.rmge_multiplier_params.argtypes = [i32, i64, u64, dp, vp]
     L.rmge_param_count.argtypes = [i32, i64]
@@ -86,7 +87,8 @@ def lib() -> ctypes.CDLL:
     L.rmge_version.restype = i32
     for name in ("rmge_factor", "rmge_factor_ex", "rmge_factor_pivoted", "rmge_refactor",
                  "rmge_solve", "rmge_solve_gmres", "rmge_solve_adjoint", "rmge_solve_adjoint_ex",
-                 "rmge_grad_A", "rmge_factor_stats_get", "rmge_factors_lu", "rmge_factors_perm",
+                 "rmge_grad_A", "rmge_factor_stats_get", "rmge_factor_times", "rmge_factors_lu",
+                 "rmge_factors_perm",
                  "rmge_multiplier_params", "rmge_precondition"):
         getattr(L, name).restype = ctypes.c_int
     _lib = L
@@ -167,6 +169,12 @@ def rmge_factor_stats_get(h):
     st = rmge_factor_stats()
     rc = lib().rmge_factor_stats_get(h, ctypes.byref(st))
     return rc, st
+
+
+def rmge_factor_times(h):
+    ms = (ctypes.c_double * 3)()
+    rc = lib().rmge_factor_times(h, ms)
+    return rc, (ms[0], ms[1], ms[2])
 
 
 def rmge_factors_lu(h, LU: int, ld: int) -> int:

@@ -1068,6 +1068,14 @@ rmge_status rmge_factor_stats_get(const rmge_factors *fc, rmge_factor_stats *s) 
     return RMGE_OK;
 }
 
+rmge_status rmge_factor_times(const rmge_factors *f, double *ms3) {
+    if (!f || !ms3) return RMGE_EINVAL;
+    ms3[0] = f->stats.ms_multiplier;
+    ms3[1] = f->stats.ms_product;
+    ms3[2] = f->stats.ms_factor;
+    return RMGE_OK;
+}
+
 rmge_status rmge_factors_lu(const rmge_factors *f, double *LU, int64_t ld) {
     if (!f || !LU || ld < f->n) return RMGE_EINVAL;
     hipError_t e = (f->prec == RMGE_F32)

@@ -79,6 +79,7 @@ def test_argument_validation_before_device(rmge):
     assert _rmge.rmge_factors_perm(None, fake) == _rmge.RMGE_EINVAL
     assert _rmge.rmge_solve_gmres(None, 0, fake, 1, 1, fake, 1, 10, 8, 1e-14)[0] == _rmge.RMGE_EINVAL
     assert _rmge.rmge_solve_adjoint_ex(None, fake, 1, 1, fake, 1, 1, 0.0)[0] == _rmge.RMGE_EINVAL
+    assert _rmge.rmge_factor_times(None)[0] == _rmge.RMGE_EINVAL
 
 
 def test_binding_refuses_cpu_tensors(rmge):
