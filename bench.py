@@ -41,9 +41,9 @@ ETA_TARGET = 1e-14
 # HBM bytes of one product launch at n = 16384, from rocprofv3 FETCH_SIZE and WRITE_SIZE
 # passes scaled by a plain-copy calibration (FETCH x 2.000, WRITE x 1.000);
 # profiles/k_gemm_fast_product_n16384_hbm_traffic.txt.  Valid only for the kernel source
-# those counters were taken on.
-TRAFFIC = {"n": 16384, "source": "paper_1406_5802_amd/csrc/gemm.hip",
-           "sha256": "dbacf2a02da30c46e6422d10b8bf8d8e0b335a00ac525480e06bee0588c4eb6b",
+# those counters were taken on (product_fingerprint).
+TRAFFIC = {"n": 16384, "source": "k_gemm_fast + tile_coords (csrc/gemm.hip) + csrc/mfma.h",
+           "sha256": "71346528471534e53f315ea0cc03f0377c4d033bf59237b9e0a0a697eca158a7",
            "f64": {"fetch_kib": 351248006.7, "write_kib": 2099200.0},
            "f32": {"fetch_kib": 199541072.6, "write_kib": 1050845.4}}
 
@@ -110,16 +110,35 @@ def run_path(rmge, torch, A, b, name, seed, steps, warmup, block, max_refine, ma
     }
 
 
-def product_traffic(n, prec):
-    """Counter-measured HBM bytes per product launch ("f64" or "f32"), or None if they do
-    not apply (another size, or the kernel source changed since the counters were taken)."""
+def _function_text(src, signature):
+    """Source text of the function whose definition contains `signature`, from its
+    template line through the closing brace at column 0."""
+    i = src.index(signature)
+    i = src.rfind("\ntemplate", 0, i) + 1
+    return src[i:src.index("\n}\n", i) + 3]
+
+
+def product_fingerprint():
+    """sha256 over what the product kernel is compiled from: its own text, the tile
+    mapping it calls and the matrix-core wrappers (dispatch code is not part of it)."""
     import hashlib
 
-    if n != TRAFFIC["n"]:
+    csrc = os.path.join(ROOT, "paper_1406_5802_amd", "csrc")
+    with open(os.path.join(csrc, "gemm.hip")) as fh:
+        gemm = fh.read()
+    with open(os.path.join(csrc, "mfma.h")) as fh:
+        mfma = fh.read()
+    i = gemm.index("__device__ inline void tile_coords(")
+    tiles = gemm[i:gemm.index("\n}\n", i) + 3]
+    text = _function_text(gemm, "void k_gemm_fast(") + tiles + mfma
+    return hashlib.sha256(text.encode()).hexdigest()
+
+
+def product_traffic(n, prec):
+    """Counter-measured HBM bytes per product launch ("f64" or "f32"), or None if they do
+    not apply (another size, or the kernel changed since the counters were taken)."""
+    if n != TRAFFIC["n"] or product_fingerprint() != TRAFFIC["sha256"]:
         return None
-    with open(os.path.join(ROOT, TRAFFIC["source"]), "rb") as fh:
-        if hashlib.sha256(fh.read()).hexdigest() != TRAFFIC["sha256"]:
-            return None
     t = TRAFFIC[prec]
     return (t["fetch_kib"] + t["write_kib"]) * 1024.0
 

@@ -444,6 +444,18 @@ hipError_t run_gemm(int shape, int64_t M, int64_t N, int64_t K, T alpha, const T
         return launch<T, TA, 128, 128, 2, 2, 2>(m, n, k, alpha, A, lda, B, ldb, beta, C, ldc,
                                                 abort, absmax, s);
     }
+    // Schur update.  FP32 trailing blocks of 4096 and more: the 128 x 128
+    // kernel (measured at K = 256: 110 against 84-100 TFLOP/s for 64 x 64
+    // tiles); smaller blocks, and FP64 (where 64 x 64 tiles win below the
+    // largest blocks), use k_gemm_upd64.
+    const bool fits128 = m % 128 == 0 && n % 128 == 0 && k % 16 == 0 && k > 0 && lda % 2 == 0 &&
+                         ldb % 2 == 0;
+    if (sizeof(T) == 4 && sizeof(TA) == 4 && fits128 && m >= 4096 && n >= 4096) {
+        const int64_t tiles = static_cast<int64_t>(m / 128) * (n / 128);
+        hipLaunchKernelGGL((k_gemm_fast<T, TA, 2>), dim3(static_cast<unsigned>(tiles)), dim3(256),
+                           0, s, m, n, k, alpha, A, lda, B, ldb, beta, C, ldc, abort, absmax);
+        return hipGetLastError();
+    }
     const bool fits64 = m % 64 == 0 && n % 64 == 0 && k % 16 == 0 && k > 0 && lda % 2 == 0 &&
                         ldb % 2 == 0 && absmax == nullptr && sizeof(TA) == sizeof(T);
     if (fits64) {
