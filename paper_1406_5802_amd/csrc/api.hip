@@ -18,8 +18,9 @@
 //   sinv  the same for every aligned 32-row diagonal sub-block of the final
 //         L and U (2 x round_up(n, 256) x 32), used by the solves with several
 //         right-hand sides and the adjoint solves
-//   binv  FP64 inverses of the 128 x 128 diagonal blocks of L and U
-//         (2 x round_up(n, 128) x 128), used by the single right-hand-side
+//   binv  FP64 inverses of the 128 x 128 diagonal blocks of L and U, and
+//         their products with the adjacent coupling blocks
+//         (4 x round_up(n, 128) x 128), used by the single right-hand-side
 //         solves
 //   piv   n ints (pivoted variant): row t of the factors is row piv[t] of M
 //   solve workspace, grown on demand: two n x nrhs of T, one n x nrhs FP64
@@ -369,8 +370,10 @@ rmge_status run_factor(rmge_factors *f) {
         T *sl = static_cast<T *>(f->sinv);
         RMGE_TRY(diag_inverses<T>(static_cast<const T *>(f->lu), f->ld, f->n, sl,
                                   sl + f->sinv_rows * kSub, f->st, s));
-        RMGE_TRY(block_inverses128<T>(static_cast<const T *>(f->lu), f->ld, f->n, f->binv,
-                                      f->binv + f->binv_rows * 128, s));
+        double *bv = f->binv;
+        const int64_t part = f->binv_rows * 128;
+        RMGE_TRY(block_inverses128<T>(static_cast<const T *>(f->lu), f->ld, f->n, bv, bv + part,
+                                      bv + 2 * part, bv + 3 * part, s));
     }
     RMGE_TRY(hipMemcpyAsync(&f->host_st, f->st, sizeof(DevStatus), hipMemcpyDeviceToHost, s));
     RMGE_TRY(hipStreamSynchronize(s));
@@ -428,7 +431,7 @@ rmge_status alloc_handle(rmge_factors *f) {
     RMGE_TRY(hipMalloc(&f->sinv, es * sinv_elems));
     RMGE_TRY(hipMemsetAsync(f->sinv, 0, es * sinv_elems, f->stream));
     f->binv_rows = round_up(n, 128);
-    RMGE_TRY(hipMalloc(&f->binv, sizeof(double) * 2 * static_cast<size_t>(f->binv_rows) * 128));
+    RMGE_TRY(hipMalloc(&f->binv, sizeof(double) * 4 * static_cast<size_t>(f->binv_rows) * 128));
     if (f->pivot) RMGE_TRY(hipMalloc(&f->piv, sizeof(int) * static_cast<size_t>(n)));
     RMGE_TRY(hipMalloc(&f->st, sizeof(DevStatus)));
     RMGE_TRY(hipMalloc(&f->scal, sizeof(double) * 8));
@@ -504,9 +507,10 @@ hipError_t tri_solves(rmge_factors *f, int64_t nrhs, bool adjoint) {
     const int first = adjoint ? 2 : 0, second = adjoint ? 3 : 1;
     const T *dfirst = adjoint ? Uinv : Linv, *dsecond = adjoint ? Linv : Uinv;
     if (nrhs == 1 && !adjoint) {  // 128-row blocks with the FP64 block inverses
-        const double *bl = f->binv, *bu = f->binv + f->binv_rows * 128;
-        HIP_TRY(trsv128<T>(0, lu, ld, n, bl, Y, X, 1, f->wsync, s));
-        return trsv128<T>(1, lu, ld, n, bu, X, Y, 1, f->wsync, s);
+        const int64_t part = f->binv_rows * 128;
+        const double *bl = f->binv, *bu = bl + part, *wl = bl + 2 * part, *wu = bl + 3 * part;
+        HIP_TRY(trsv128<T>(0, lu, ld, n, bl, wl, Y, X, 1, f->wsync, s));
+        return trsv128<T>(1, lu, ld, n, bu, wu, X, Y, 1, f->wsync, s);
     }
     for (int64_t g = 0; g < nrhs; g += 16) {
         const int nr = static_cast<int>((nrhs - g) < 16 ? (nrhs - g) : 16);

@@ -121,17 +121,20 @@ hipError_t abs_max(const T *m, int64_t ld, int64_t n, double *out3, hipStream_t 
 template <typename T>
 hipError_t trsv_full(int mode, const T *LU, int64_t ld, int64_t n, const T *Dinv, const double *B,
                      double *X, int64_t ldx, int nr, int *sync, hipStream_t s);
-// FP64 inverses of the 128 x 128 diagonal blocks of the packed factors (unit
-// lower L, upper U): row I0 + i of Linv / Uinv holds row i of block I's
-// inverse; both hold round_up(n, 128) rows of 128 doubles.
+// FP64 inverses D_I of the 128 x 128 diagonal blocks of the packed factors
+// (unit lower L, upper U), and W_I = D_I C_I with C_I the coupling of block I
+// with its predecessor in the solve (L: block column I - 1; U: I + 1): row
+// I0 + i of each output holds row i of block I's matrix; all four hold
+// round_up(n, 128) rows of 128 doubles.
 template <typename T>
 hipError_t block_inverses128(const T *lu, int64_t ld, int64_t n, double *Linv, double *Uinv,
-                             hipStream_t s);
+                             double *Wl, double *Wu, hipStream_t s);
 // One right-hand side: mode 0 L y = b, mode 1 U y = b, in 128-row blocks with
-// the block inverses above (Linv for mode 0, Uinv for mode 1).  B != X.
+// the block matrices above (Linv, Wl for mode 0; Uinv, Wu for mode 1).  B != X.
 template <typename T>
 hipError_t trsv128(int mode, const T *LU, int64_t ld, int64_t n, const double *Dinv,
-                   const double *B, double *X, int64_t ldx, int *sync, hipStream_t s);
+                   const double *W, const double *B, double *X, int64_t ldx, int *sync,
+                   hipStream_t s);
 // Krylov helpers; basis vectors V_j stored contiguously (V + j * n), j < k <= 64.
 // h[j] = V_j . w (+ h[j] if accumulate), deterministic; part: >= 256 * k doubles.
 hipError_t mdot(const double *V, int64_t n, int k, const double *w, double *part, double *h,

@@ -286,8 +286,10 @@ constexpr int BI = 128;
 // Four threads share a row's dot product.
 template <typename T>
 __global__ __launch_bounds__(512) void k_blkinv128(const T *lu, int64_t ld, int64_t n,
-                                                   double *Linv, double *Uinv) {
+                                                   double *Linv, double *Uinv, double *Wl,
+                                                   double *Wu) {
     __shared__ double X[BI][BI + 1];
+    __shared__ double Ts[16][BI];
     const int64_t I0 = static_cast<int64_t>(blockIdx.x) * BI;
     const bool upper = blockIdx.y == 1;
     const int bI = static_cast<int>((n - I0) < BI ? (n - I0) : BI);
@@ -341,15 +343,72 @@ __global__ __launch_bounds__(512) void k_blkinv128(const T *lu, int64_t ld, int6
         const int r = e / BI, c = e % BI;
         out[(I0 + r) * BI + c] = X[r][c];
     }
+    // W = X C, C the coupling of this block with the one solved just before it
+    // (L: the tile of block row I, block column I - 1; U: block column I + 1),
+    // so the solve can apply x_I = X s' - W y_adjacent once y_adjacent lands.
+    // C is staged 16 rows at a time; thread (i, q) forms W[i][32 q .. 32 q + 31].
+    const int nblk = static_cast<int>((n + BI - 1) / BI);
+    const int Jn = upper ? static_cast<int>(blockIdx.x) + 1 : static_cast<int>(blockIdx.x) - 1;
+    if (Jn < 0 || Jn >= nblk) return;  // no such neighbour: W is never read
+    const int64_t J0 = static_cast<int64_t>(Jn) * BI;
+    const int bJ = static_cast<int>((n - J0) < BI ? (n - J0) : BI);
+    const int wi = tid >> 2, wq = tid & 3;
+    double wacc[32];
+#pragma unroll
+    for (int j = 0; j < 32; ++j) wacc[j] = 0.0;
+    for (int k0 = 0; k0 < BI; k0 += 16) {
+        T v[16 * BI / 512];
+#pragma unroll
+        for (int m = 0; m < 16 * BI / 512; ++m) {
+            const int e = tid + 512 * m, kk = e / BI, j = e % BI;
+            v[m] = load_if(lu, (I0 + k0 + kk) * ld + J0 + j, k0 + kk < bI && j < bJ);
+        }
+#pragma unroll
+        for (int m = 0; m < 16 * BI / 512; ++m) {
+            const int e = tid + 512 * m;
+            Ts[e / BI][e % BI] = static_cast<double>(v[m]);
+        }
+        __syncthreads();
+#pragma unroll 4
+        for (int kk = 0; kk < 16; ++kk) {
+            const double xk = X[wi][k0 + kk];
+#pragma unroll
+            for (int j = 0; j < 32; ++j) wacc[j] += xk * Ts[kk][32 * wq + j];
+        }
+        __syncthreads();
+    }
+    double *wout = upper ? Wu : Wl;
+#pragma unroll
+    for (int j = 0; j < 32; ++j) wout[(I0 + wi) * BI + 32 * wq + j] = wacc[j];
 }
 
-// 32 consecutive factor entries from p (32-element aligned).
+// Sum of v over each row of 16 lanes, in every lane of the row, by DPP moves
+// (register to register): quad permutations [1,0,3,2] and [2,3,0,1], then the
+// half-row and row mirrors.  Each step adds a value and its partner's, so all
+// lanes of a row end with the same sum.
+template <int CTRL>
+__device__ inline double dpp_move(double v) {
+    const long long bits = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_update_dpp(0, static_cast<int>(bits), CTRL, 0xf, 0xf, false);
+    const int hi =
+        __builtin_amdgcn_update_dpp(0, static_cast<int>(bits >> 32), CTRL, 0xf, 0xf, false);
+    return __longlong_as_double((static_cast<long long>(hi) << 32) | static_cast<unsigned>(lo));
+}
+__device__ inline double row16_sum(double v) {
+    v += dpp_move<0xB1>(v);   // quad_perm [1,0,3,2]
+    v += dpp_move<0x4E>(v);   // quad_perm [2,3,0,1]
+    v += dpp_move<0x141>(v);  // row_half_mirror
+    v += dpp_move<0x140>(v);  // row_mirror
+    return v;
+}
+
+// Eight consecutive factor entries from p (8-element aligned).
 template <typename T>
-__device__ inline void load_row32(const T *p, T (&dst)[32]) {
+__device__ inline void load_row8(const T *p, T (&dst)[8]) {
     typedef T v4 __attribute__((ext_vector_type(16 / sizeof(T))));
     constexpr int W = 16 / sizeof(T);
 #pragma unroll
-    for (int c = 0; c < 32 / W; ++c) {
+    for (int c = 0; c < 8 / W; ++c) {
         const v4 v = reinterpret_cast<const v4 *>(p)[c];
 #pragma unroll
         for (int e = 0; e < W; ++e) dst[W * c + e] = v[e];
@@ -358,13 +417,31 @@ __device__ inline void load_row32(const T *p, T (&dst)[32]) {
 
 // MODE 0: L y = b (forward), MODE 1: U y = b (backward); one right-hand side.
 // Same ticket order, mark-as-flag hand-off and bounded waits as k_trsv.
-// Thread (r, q) owns row r of its block and columns 32 q .. 32 q + 31 of
-// each coupling tile (prefetched one tile ahead) and of the block inverse.
+// With D = the block's inverse and W = D C (C its coupling with the adjacent
+// block, solved just before it; both from k_blkinv128),
+//     x_I = D (b_I - sum_{J not adjacent} T_IJ y_J) - W y_adjacent,
+// so everything but the last product is done while the adjacent block is
+// still being solved.  Thread (g, c) owns rows RG g .. RG g + RG - 1 of its
+// block (RG = 4 in FP32 with 512 threads; 2 in FP64 with 1024 threads and D
+// staged in LDS, which keeps the FP64 tiles in registers) and columns
+// 8 c .. 8 c + 7 of each coupling tile (prefetched one tile ahead), of D and of
+// W, so it reads 8 entries of y_J a tile; a row's 16 partial sums sit in 16
+// consecutive lanes and reduce by DPP moves.  Wave 0 polls y_J with one round
+// of loads always in flight, so a result is seen one load latency after it
+// lands.
+template <typename T>
+constexpr int trsv128_threads() { return sizeof(T) == 4 ? 512 : 1024; }
+
 template <typename T, int MODE>
-__global__ __launch_bounds__(512) void k_trsv128(const T *LU, int64_t ld, int64_t n,
-                                                 const double *Dinv, const double *B, double *X,
-                                                 int64_t ldx, int *sync) {
+__global__ __launch_bounds__(trsv128_threads<T>()) void k_trsv128(const T *LU, int64_t ld,
+                                                                  int64_t n, const double *Dinv,
+                                                                  const double *W,
+                                                                  const double *B, double *X,
+                                                                  int64_t ldx, int *sync) {
     constexpr bool forward = MODE == 0;
+    constexpr int CG = 8, RG = BI * 16 / trsv128_threads<T>();  // columns, rows a thread owns
+    constexpr bool kInvLds = sizeof(T) == 8;
+    __shared__ double dl[kInvLds ? BI : 1][BI];
     __shared__ double ys[2][BI];
     __shared__ double ss[BI];
     __shared__ int s_ticket, s_fail;
@@ -379,54 +456,64 @@ __global__ __launch_bounds__(512) void k_trsv128(const T *LU, int64_t ld, int64_
     const int I = forward ? s_ticket : nblk - 1 - s_ticket;
     const int64_t I0 = static_cast<int64_t>(I) * BI;
     const int bI = static_cast<int>((n - I0) < BI ? (n - I0) : BI);
-    const int r = tid >> 2, q = tid & 3;
-    const double bval = load_if(B, (I0 + r) * ldx, q == 0 && r < bI);
-    // this thread's part of the block inverse: fetched in place of the tile
-    // prefetch during the last coupling step (or now, if there is none)
-    double dreg[32];
-    auto load_dinv = [&]() {
+    const int g = tid >> 4, c = tid & 15;  // rows RG g .., columns CG c ..
+    const int r0 = RG * g, c0 = CG * c;
+    if constexpr (kInvLds) {
+        constexpr int kPer = BI * BI / trsv128_threads<T>();
+        double v[kPer];
 #pragma unroll
-        for (int i = 0; i < 32; ++i) dreg[i] = Dinv[(I0 + r) * BI + 32 * q + i];
+        for (int m = 0; m < kPer; ++m) v[m] = Dinv[I0 * BI + tid + trsv128_threads<T>() * m];
+#pragma unroll
+        for (int m = 0; m < kPer; ++m) {
+            const int e = tid + trsv128_threads<T>() * m;
+            dl[e / BI][e % BI] = v[m];
+        }
+    }
+    double bval[RG];
+#pragma unroll
+    for (int k = 0; k < RG; ++k) bval[k] = load_if(B, (I0 + r0 + k) * ldx, c == 0 && r0 + k < bI);
+    // this thread's part of D: fetched in place of the tile prefetch during
+    // the last non-adjacent coupling step (or now, if there is none)
+    double dreg[kInvLds ? 1 : RG][CG];
+    auto load_dinv = [&]() {
+        if constexpr (!kInvLds) {
+#pragma unroll
+            for (int k = 0; k < RG; ++k)
+#pragma unroll
+                for (int e = 0; e < CG; ++e) dreg[k][e] = Dinv[(I0 + r0 + k) * BI + c0 + e];
+        }
     };
-    auto load_tile = [&](int J, T (&dst)[32]) {
+    auto load_tile = [&](int J, T (&dst)[RG][CG]) {
         const int64_t J0 = static_cast<int64_t>(J) * BI;
         const int bJ = static_cast<int>((n - J0) < BI ? (n - J0) : BI);
         if (bI == BI && bJ == BI) {
-            load_row32(LU + (I0 + r) * ld + J0 + 32 * q, dst);
+#pragma unroll
+            for (int k = 0; k < RG; ++k) load_row8(LU + (I0 + r0 + k) * ld + J0 + c0, dst[k]);
         } else {
 #pragma unroll
-            for (int i = 0; i < 32; ++i)
-                dst[i] = load_if(LU, (I0 + r) * ld + J0 + 32 * q + i, r < bI && 32 * q + i < bJ);
+            for (int k = 0; k < RG; ++k)
+#pragma unroll
+                for (int e = 0; e < CG; ++e)
+                    dst[k][e] = load_if(LU, (I0 + r0 + k) * ld + J0 + c0 + e,
+                                        r0 + k < bI && c0 + e < bJ);
         }
     };
-    const int jfirst = forward ? 0 : nblk - 1, jstep = forward ? 1 : -1;
-    T cur[32], nxt[32];
-    if (I != jfirst)
-        load_tile(jfirst, nxt);
-    else
-        load_dinv();
-    double acc = 0.0;
-    int par = 0;
-    for (int J = jfirst; J != I; J += jstep, par ^= 1) {
-#pragma unroll
-        for (int i = 0; i < 32; ++i) cur[i] = nxt[i];
-        if (J + jstep != I)
-            load_tile(J + jstep, nxt);
-        else
-            load_dinv();
+    // Wait for y_J (wave 0, two entries a lane; lanes past the block poll its
+    // first entry) and leave it in ys[par] for all threads; false if a wait
+    // gave up.
+    auto await_block = [&](int J, int par) {
         if (wave == 0) {
-            // y_J, two entries a lane (lanes past the block poll its first entry)
             const int64_t J0 = static_cast<int64_t>(J) * BI;
             const int bJ = static_cast<int>((n - J0) < BI ? (n - J0) : BI);
             const bool in0 = lane < bJ, in1 = lane + 64 < bJ;
             const double *p0 = X + (J0 + (in0 ? lane : 0)) * ldx;
             const double *p1 = X + (J0 + (in1 ? lane + 64 : 0)) * ldx;
-            double v0 = 0.0, v1 = 0.0;
+            bool ok0, ok1, nok0, nok1;
+            double v0 = poll_value(p0, &ok0), v1 = poll_value(p1, &ok1);
             int spins = 0;
             while (true) {
-                bool ok0, ok1;
-                v0 = poll_value(p0, &ok0);
-                v1 = poll_value(p1, &ok1);
+                // the next round goes out before this one is examined
+                const double n0 = poll_value(p0, &nok0), n1 = poll_value(p1, &nok1);
                 if (__all(ok0 && ok1)) break;
                 const bool give_up =
                     (++spins > kSpinLimit) ||
@@ -436,29 +523,102 @@ __global__ __launch_bounds__(512) void k_trsv128(const T *LU, int64_t ld, int64_
                     break;
                 }
                 __builtin_amdgcn_s_sleep(1);
+                v0 = n0;
+                v1 = n1;
+                ok0 = nok0;
+                ok1 = nok1;
             }
             ys[par][lane] = in0 ? v0 : 0.0;
             ys[par][lane + 64] = in1 ? v1 : 0.0;
         }
-        __syncthreads();  // (ys[par] is next written two tiles later, after another barrier)
-        if (s_fail) break;
+        __syncthreads();  // (ys[par] is next written two waits later, after another barrier)
+        return s_fail == 0;
+    };
+    const int jfirst = forward ? 0 : nblk - 1, jstep = forward ? 1 : -1;
+    const bool has_adj = I != jfirst;
+    const int jadj = I - jstep;                       // the adjacent block (through W)
+    const bool has_tiles = has_adj && jfirst != jadj;  // other coupling tiles
+    T cur[RG][CG], nxt[RG][CG];
+    if (has_tiles)
+        load_tile(jfirst, nxt);
+    else
+        load_dinv();
+    double acc[RG];
 #pragma unroll
-        for (int i = 0; i < 32; ++i) acc += static_cast<double>(cur[i]) * ys[par][32 * q + i];
+    for (int k = 0; k < RG; ++k) acc[k] = 0.0;
+    int par = 0;
+    bool ok = true;
+    if (has_tiles) {
+        for (int J = jfirst; J != jadj; J += jstep, par ^= 1) {
+#pragma unroll
+            for (int k = 0; k < RG; ++k)
+#pragma unroll
+                for (int e = 0; e < CG; ++e) cur[k][e] = nxt[k][e];
+            if (J + jstep != jadj)
+                load_tile(J + jstep, nxt);
+            else
+                load_dinv();
+            if (!(ok = await_block(J, par))) break;
+            double y[CG];
+#pragma unroll
+            for (int e = 0; e < CG; ++e) y[e] = ys[par][c0 + e];
+#pragma unroll
+            for (int k = 0; k < RG; ++k)
+#pragma unroll
+                for (int e = 0; e < CG; ++e) acc[k] += static_cast<double>(cur[k][e]) * y[e];
+        }
     }
-    if (s_fail) {
+    double x[RG];
+    if (ok) {
+        // x = D (b_I - sum of the non-adjacent couplings)
+#pragma unroll
+        for (int k = 0; k < RG; ++k) acc[k] = row16_sum(acc[k]);
+        if (c == 0) {
+#pragma unroll
+            for (int k = 0; k < RG; ++k) ss[r0 + k] = (r0 + k < bI) ? bval[k] - acc[k] : 0.0;
+        }
+        __syncthreads();
+        double sv[CG];
+#pragma unroll
+        for (int e = 0; e < CG; ++e) sv[e] = ss[c0 + e];
+#pragma unroll
+        for (int k = 0; k < RG; ++k) {
+            x[k] = 0.0;
+#pragma unroll
+            for (int e = 0; e < CG; ++e)
+                x[k] += (kInvLds ? dl[r0 + k][c0 + e] : dreg[kInvLds ? 0 : k][e]) * sv[e];
+            x[k] = row16_sum(x[k]);
+        }
+        if (has_adj) {
+            // x -= W y_adjacent: W is fetched before the wait
+            double wreg[RG][CG];
+#pragma unroll
+            for (int k = 0; k < RG; ++k)
+#pragma unroll
+                for (int e = 0; e < CG; ++e) wreg[k][e] = W[(I0 + r0 + k) * BI + c0 + e];
+            if ((ok = await_block(jadj, par))) {
+                double y[CG];
+#pragma unroll
+                for (int e = 0; e < CG; ++e) y[e] = ys[par][c0 + e];
+#pragma unroll
+                for (int k = 0; k < RG; ++k) {
+                    double t = 0.0;
+#pragma unroll
+                    for (int e = 0; e < CG; ++e) t += wreg[k][e] * y[e];
+                    x[k] -= row16_sum(t);
+                }
+            }
+        }
+    }
+    if (!ok) {
         if (tid == 0) atomicExch(err, 1);  // blocks waiting on this one see it and stop
         return;
     }
-    acc += __shfl_xor(acc, 1);
-    acc += __shfl_xor(acc, 2);
-    if (q == 0) ss[r] = (r < bI) ? bval - acc : 0.0;
-    __syncthreads();
-    double x = 0.0;
+    if (c == 0) {
 #pragma unroll
-    for (int i = 0; i < 32; ++i) x += dreg[i] * ss[32 * q + i];
-    x += __shfl_xor(x, 1);
-    x += __shfl_xor(x, 2);
-    if (q == 0 && r < bI) publish_value(X + (I0 + r) * ldx, x);
+        for (int k = 0; k < RG; ++k)
+            if (r0 + k < bI) publish_value(X + (I0 + r0 + k) * ldx, x[k]);
+    }
 }
 
 // Before a solve: reset the ticket counter and mark every output entry unsolved.
@@ -781,27 +941,30 @@ hipError_t trsv_full(int mode, const T *LU, int64_t ld, int64_t n, const T *Dinv
 
 template <typename T>
 hipError_t block_inverses128(const T *lu, int64_t ld, int64_t n, double *Linv, double *Uinv,
-                             hipStream_t s) {
+                             double *Wl, double *Wu, hipStream_t s) {
     if (n < 1) return hipSuccess;
     const unsigned nblk = static_cast<unsigned>((n + BI - 1) / BI);
-    hipLaunchKernelGGL(k_blkinv128<T>, dim3(nblk, 2), dim3(512), 0, s, lu, ld, n, Linv, Uinv);
+    hipLaunchKernelGGL(k_blkinv128<T>, dim3(nblk, 2), dim3(512), 0, s, lu, ld, n, Linv, Uinv, Wl,
+                       Wu);
     return hipGetLastError();
 }
 
 template <typename T>
 hipError_t trsv128(int mode, const T *LU, int64_t ld, int64_t n, const double *Dinv,
-                   const double *B, double *X, int64_t ldx, int *sync, hipStream_t s) {
+                   const double *W, const double *B, double *X, int64_t ldx, int *sync,
+                   hipStream_t s) {
     if (n < 1 || B == X || (mode != 0 && mode != 1)) return hipErrorInvalidValue;
     const int nblk = static_cast<int>((n + BI - 1) / BI);
     hipLaunchKernelGGL(k_trsv_prep, dim3(grid_for(n, 256)), dim3(256), 0, s, X, ldx, n, 1, sync);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
+    const unsigned threads = trsv128_threads<T>();
     if (mode == 0)
-        hipLaunchKernelGGL((k_trsv128<T, 0>), dim3(nblk), dim3(512), 0, s, LU, ld, n, Dinv, B, X,
-                           ldx, sync);
+        hipLaunchKernelGGL((k_trsv128<T, 0>), dim3(nblk), dim3(threads), 0, s, LU, ld, n, Dinv, W,
+                           B, X, ldx, sync);
     else
-        hipLaunchKernelGGL((k_trsv128<T, 1>), dim3(nblk), dim3(512), 0, s, LU, ld, n, Dinv, B, X,
-                           ldx, sync);
+        hipLaunchKernelGGL((k_trsv128<T, 1>), dim3(nblk), dim3(threads), 0, s, LU, ld, n, Dinv, W,
+                           B, X, ldx, sync);
     return hipGetLastError();
 }
 
@@ -932,13 +1095,15 @@ hipError_t grad_a(const double *GB, int64_t ldgb, const double *X, int64_t ldx, 
 }
 
 template hipError_t block_inverses128<double>(const double *, int64_t, int64_t, double *,
-                                              double *, hipStream_t);
+                                              double *, double *, double *, hipStream_t);
 template hipError_t block_inverses128<float>(const float *, int64_t, int64_t, double *, double *,
-                                             hipStream_t);
+                                             double *, double *, hipStream_t);
 template hipError_t trsv128<double>(int, const double *, int64_t, int64_t, const double *,
-                                    const double *, double *, int64_t, int *, hipStream_t);
+                                    const double *, const double *, double *, int64_t, int *,
+                                    hipStream_t);
 template hipError_t trsv128<float>(int, const float *, int64_t, int64_t, const double *,
-                                   const double *, double *, int64_t, int *, hipStream_t);
+                                   const double *, const double *, double *, int64_t, int *,
+                                   hipStream_t);
 template hipError_t trsv_full<double>(int, const double *, int64_t, int64_t, const double *,
                                       const double *, double *, int64_t, int, int *, hipStream_t);
 template hipError_t trsv_full<float>(int, const float *, int64_t, int64_t, const float *,
