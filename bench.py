@@ -21,6 +21,8 @@ sigma_i = kappa^(-i/(n-1)), kappa = 10^(1 + 7u) drawn from the seed, one
 N(0, 1) right-hand side.
 
 Usage: python bench.py [--steps K] [--warmup W] [--n N] [--seed S]
+       python bench.py --workload differentiation   (forward + backward through the
+       solve: n = 8192, Toeplitz multiplier, 16 right-hand sides; one JSON line of its own)
 """
 from __future__ import annotations
 
@@ -174,16 +176,112 @@ def cpu_baseline(n_cpu, seed, local_pivot_block=0):
     }
 
 
+DIFF_PATHS = {"f64": ("F64", "PIVOT_NONE"), "f32p": ("F32", "PIVOT_BLOCK")}
+
+
+def differentiation(args):
+    """The differentiation workload: n = 8192, Toeplitz multiplier, 16 right-hand
+    sides, loss sum(W .* X).  One step is the forward solve X = A^{-1} B (factor
+    with the multiplier, solve, refine to eta <= 1e-14) and the backward pass
+    (grad_B = A^{-T} W by the refined adjoint solve reusing the factors, then
+    grad_A = -grad_B X^T), as torch.autograd runs them.  The roofline line is the
+    grad_A kernel (HBM: writes n^2 doubles, reads 2 n nrhs)."""
+    import torch
+
+    import paper_1406_5802_amd as rmge
+    from paper_1406_5802_amd import autograd
+    import workloads
+
+    rmge.lib()
+    n, nrhs, kappa = args.n or 8192, 16, 1e2
+    log("differentiation: n=%d Toeplitz multiplier, %d RHS, kappa=%g" % (n, nrhs, kappa))
+    A = workloads.conditioned_torch(n, kappa, seed=args.seed)
+    B = workloads.rhs_torch(n, nrhs, seed=args.seed)
+    W = workloads.rhs_torch(n, nrhs, seed=args.seed + 1)
+    torch.cuda.synchronize()
+    paths = {}
+    for name in args.paths.split(","):
+        if name not in DIFF_PATHS:
+            raise SystemExit("unknown differentiation path %r (choose from %s)"
+                             % (name, ",".join(DIFF_PATHS)))
+        prec, pivot = (getattr(rmge, x) for x in DIFF_PATHS[name])
+        kw = dict(kind=rmge.TOEPLITZ, seed=args.seed + 1000, block=args.block, prec=prec,
+                  pivot=pivot, tol=ETA_TARGET)
+        fwd, bwd = [], []
+        for i in range(args.warmup + args.steps):
+            At = A.clone().requires_grad_(True)
+            Bt = B.clone().requires_grad_(True)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            X = autograd.solve(At, Bt, **kw)
+            torch.cuda.synchronize()
+            t1 = time.perf_counter()
+            (W * X).sum().backward()
+            torch.cuda.synchronize()
+            t2 = time.perf_counter()
+            if i >= args.warmup:
+                fwd.append((t1 - t0) * 1e3)
+                bwd.append((t2 - t1) * 1e3)
+        paths[name] = {"ms_forward": sum(fwd) / len(fwd), "ms_backward": sum(bwd) / len(bwd)}
+        paths[name]["ms_per_step"] = paths[name]["ms_forward"] + paths[name]["ms_backward"]
+        log("%s: forward %.2f ms, backward %.2f ms" % (name, paths[name]["ms_forward"],
+                                                       paths[name]["ms_backward"]))
+        GB, Xd = Bt.grad.detach(), X.detach()
+    # the grad_A kernel alone, on the stream the library is given
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    rmge.grad_A(GB, Xd)
+    reps = 10
+    e0.record()
+    for _ in range(reps):
+        rmge.grad_A(GB, Xd)
+    e1.record()
+    e1.synchronize()
+    ms_ga = e0.elapsed_time(e1) / reps
+    ga_bytes = 8.0 * n * n + 2 * 8.0 * n * nrhs
+    head = min(paths, key=lambda k: paths[k]["ms_per_step"])
+    out = {
+        "metric": "differentiation: forward+backward time, n=%d Toeplitz, %d RHS" % (n, nrhs),
+        "value": round(paths[head]["ms_per_step"], 3),
+        "unit": "ms",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(paths[head]["ms_per_step"], 3),
+        "higher_is_better": False,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32 factors + f64 refinement" if head.startswith("f32") else "f64",
+        "data": "synthetic",
+        "config": {"workload": "differentiation: n=%d Toeplitz multiplier, %d RHS, kappa=%g, "
+                               "loss sum(W .* X), eta<=1e-14" % (n, nrhs, kappa),
+                   "n": n, "nrhs": nrhs, "kappa": kappa, "seed": args.seed, "block": args.block,
+                   "headline_path": head},
+        "roofline": {"bound": "hbm", "achieved": round(ga_bytes / (ms_ga * 1e-3) / 1e9, 1),
+                     "peak": 8000.0, "unit": "GB/s",
+                     "frac": round(ga_bytes / (ms_ga * 1e-3) / 1e9 / 8000.0, 4),
+                     "traffic": None, "kernel": "k_grad_a (grad_A = -grad_B X^T)",
+                     "ms_per_launch": round(ms_ga, 4)},
+        "paths": {k: {kk: round(vv, 3) for kk, vv in v.items()} for k, v in paths.items()},
+    }
+    print(json.dumps(out))
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--n", type=int, default=16384)
+    ap.add_argument("--workload", default="precision", choices=["precision", "differentiation"],
+                    help="precision: the factor+solve benchmark (default); differentiation: "
+                         "forward and backward through the solve at n = 8192, Toeplitz, 16 RHS")
+    ap.add_argument("--n", type=int, default=None, help="16384 (precision) or 8192 "
+                                                         "(differentiation)")
     ap.add_argument("--seed", type=int, default=1)
     ap.add_argument("--block", type=int, default=256)
     ap.add_argument("--max-refine", type=int, default=16)
-    ap.add_argument("--paths", default="f64,f32,f64p,f32p,f32pg")
+    ap.add_argument("--paths", default=None,
+                    help="precision: f64,f32,f64p,f32p,f32g,f32pg (default f64,f32,f64p,f32p,"
+                         "f32pg); differentiation: f64,f32p (default both)")
     ap.add_argument("--max-iters", type=int, default=200, help="GMRES inner iterations in all")
     ap.add_argument("--cpu-n", type=int, default=8192,
                     help="size of the oracle's CPU sample (about 20 s on 16 host threads)")
@@ -198,13 +296,18 @@ def main():
               "--gpus %d is not supported" % args.gpus, file=sys.stderr)
         sys.exit(2)
 
+    if args.workload == "differentiation":
+        args.paths = args.paths or "f64,f32p"
+        return differentiation(args)
+    args.paths = args.paths or "f64,f32,f64p,f32p,f32pg"
+
     import torch
 
     import paper_1406_5802_amd as rmge
     import workloads
 
     rmge.lib()
-    n = args.n
+    n = args.n or 16384
     kappa = workloads.precision_kappa(args.seed)
     if args.matrix == "gaussian":
         log("generating A: n=%d i.i.d. Gaussian (seed %d) on the GPU" % (n, args.seed))

@@ -206,9 +206,9 @@ hipError_t factor_pivot_block(rmge_factors *f, T *a, int b, int64_t k0, T *Linv,
     if (b <= kLeaf) return leaf_lu<T>(a, ld, b, Linv, Uinv, k0, f->st, piv, s);
     const int b1 = kLeaf, b2 = b - kLeaf;
     HIP_TRY(leaf_lu<T>(a, ld, b1, Linv, Uinv, k0, f->st, piv, s));
-    // Bab <- La^{-1} Pa Bab ; Bba <- Bba Ua^{-1} ; Bb <- Bb - Bba Bab
-    HIP_TRY(trsm<T>(0, a, ld, b1, a + b1, ld, b2, Linv, abort, s, piv ? piv + k0 : nullptr, k0));
-    HIP_TRY(trsm<T>(1, a, ld, b1, a + b1 * ld, ld, b2, Uinv, abort, s));
+    // Bab <- La^{-1} Pa Bab ; Bba <- Bba Ua^{-1} (one launch) ; Bb <- Bb - Bba Bab
+    HIP_TRY(trsm_pair<T>(a, ld, b1, a + b1, ld, b2, Linv, piv ? piv + k0 : nullptr, k0,
+                         a + b1 * ld, ld, b2, Uinv, abort, s));
     HIP_TRY(Prec<T>::gemm(kGemmUpdate, b2, b2, b1, T(-1), a + b1 * ld, ld, a + b1, ld, T(1),
                           a + b1 * ld + b1, ld, abort, s));
     HIP_TRY(leaf_lu<T>(a + b1 * ld + b1, ld, b2, Linv + b1 * kSub, Uinv + b1 * kSub, k0 + b1,
@@ -264,14 +264,13 @@ hipError_t genp_blocked(rmge_factors *f) {
         const int b = static_cast<int>((n - k) < nb ? (n - k) : nb);
         if (k > 0) HIP_TRY(hipStreamWaitEvent(s0, f->ev_panel, 0));
         if (k + b >= n) break;
-        T *const akk0 = a + k * ld + k;
-        HIP_TRY(trsm<T>(1, akk0, ld, b, akk0 + b * ld, ld, n - k - b, Uinv(step), abort, s0));
         const int64_t r = n - k - b;
         const int bn = static_cast<int>(r < nb ? r : nb);  // next panel width
         T *akk = a + k * ld + k;
         T *a12 = akk + b, *a21 = akk + b * ld, *a22 = akk + b * ld + b;
-        HIP_TRY(trsm<T>(0, akk, ld, b, a12, ld, r, Linv(step), abort, s0,
-                        f->pivot ? f->piv + k : nullptr, k));
+        // C <- L_B^{-1} P_B C (block row) and D <- D U_B^{-1} (column below)
+        HIP_TRY(trsm_pair<T>(akk, ld, b, a12, ld, r, Linv(step), f->pivot ? f->piv + k : nullptr,
+                             k, a21, ld, r, Uinv(step), abort, s0));
         HIP_TRY(Prec<T>::gemm(kGemmUpdate, r, bn, b, T(-1), a21, ld, a12, ld, T(1), a22, ld, abort,
                               s0));
         HIP_TRY(hipEventRecord(f->ev_narrow, s0));

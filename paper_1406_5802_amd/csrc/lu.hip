@@ -36,20 +36,24 @@ __device__ inline bool is_bad(T p) {
     return p == T(0) || !isfinite(p);
 }
 
-// One pivot block (b <= 128) in registers, 512 threads: wave w holds columns
-// 16 w .. 16 w + 15 and lane l holds rows l and l + 64 of them (32 elements a
-// thread).  A column therefore lives inside one wave, and every wave holds
-// every row.  Pivot step j (owner wave w = j / 16):
-//   * the owner publishes column j to its own LDS slot (and, with PIV, finds
-//     the pivot row among the active rows by a DPP reduction and ballots
-//     inside the wave), then a flag carrying the pivot row;
-//   * every wave waits only for that flag (no barrier: the waves that own no
-//     upcoming column may run steps behind), reads column j, and takes the
-//     pivot row's values for its own columns from lane (row mod 64) with
-//     readlane;
+// One pivot block (b <= 128) in registers, 512 threads: each wave holds 16
+// columns and lane l holds rows l and l + 64 of them (32 elements a thread).
+// A column therefore lives inside one wave, and every wave holds every row.
+// Pivot step j:
+//   * every wave waits only for the flag of column j (no barrier: waves may
+//     run steps behind), reads the column and the reciprocal of its pivot, and
+//     takes the pivot row's values for its own columns from lane (row mod 64)
+//     with readlane;
 //   * each thread applies a_ic -= (a_ij / a_pj) a_pc to its elements, the
-//     multiplier formed as a_ij times the reciprocal of the pivot; the owner
-//     of column j + 1 then publishes it.
+//     multiplier formed as a_ij times the reciprocal of the pivot;
+//   * the owner of column j + 1 publishes that column (with PIV, electing its
+//     pivot by a DPP reduction and ballots inside the wave).
+// With pivoting the columns are dealt cyclically (wave w holds w, w + 8, ...,
+// w + 120), so consecutive columns belong to different waves, and the owner
+// of column j + 1 applies step j to that column first and publishes it before
+// updating the rest: the chain from one pivot to the next is one column's
+// update and one election.  Without pivoting (no election on the chain)
+// wave w holds the block 16 w .. 16 w + 15 and publishes after its update.
 // Multipliers of retired rows and pivot-row entries of columns <= j are zero,
 // so the update is branch-free and an element left of its row's pivot keeps
 // the value it had when its column was eliminated; the multipliers
@@ -131,6 +135,13 @@ __device__ inline int elect_pivot<double>(double x0, double x1, unsigned act) {
               : 64 + __builtin_ffsll(static_cast<long long>(b1)) - 1;
 }
 
+// Column of register q in wave w, and the wave that owns column c: cyclic
+// (c = 8 q + w) with pivoting, blocks of 16 (c = 16 w + q) without.
+template <bool CYCLIC>
+__device__ inline int leaf_col(int w, int q) { return CYCLIC ? 8 * q + w : 16 * w + q; }
+template <bool CYCLIC>
+__device__ inline int leaf_owner(int c) { return CYCLIC ? (c & 7) : (c >> 4); }
+
 template <typename T, bool PIV>
 __global__ __launch_bounds__(kLeafThreads) void k_leaf_lu(T *a, int64_t lda, int b, int64_t k0,
                                                           DevStatus *st, int *piv) {
@@ -157,7 +168,7 @@ __global__ __launch_bounds__(kLeafThreads) void k_leaf_lu(T *a, int64_t lda, int
     for (int p = 0; p < 2; ++p)
 #pragma unroll
         for (int q = 0; q < 16; ++q) {
-            const int i = l + 64 * p, c = 16 * w + q;
+            const int i = l + 64 * p, c = leaf_col<PIV>(w, q);
             v[p][q] = (i < b && c < b) ? a[static_cast<int64_t>(i) * lda + c] : T(0);
         }
     unsigned act = 0;  // bit p: row l + 64 p is still active (PIV)
@@ -166,30 +177,14 @@ __global__ __launch_bounds__(kLeafThreads) void k_leaf_lu(T *a, int64_t lda, int
         if (l + 64 * p < b) act |= 1u << p;
     __syncthreads();
 
-    // The owner of column j (wave j / 16) publishes it once its own update
-    // through step j - 1 is done: the column, the pivot's reciprocal and
-    // position, then (after a release fence) the flag carrying the pivot row,
-    // negative if the pivot is zero or not finite (the breakdown is recorded
-    // here).  The owner keeps what it published for its own next step.
+    // The owner of column j publishes it once step j - 1 has reached it: the
+    // column, the pivot's reciprocal and position, then (after a release
+    // fence) the flag carrying the pivot row, negative if the pivot is zero or
+    // not finite (the breakdown is recorded here).  The owner keeps what it
+    // published for its own next step.
     T pub0 = T(0), pub1 = T(0), pub_rp = T(0);
     int pub_fv = 0;
-    auto publish = [&](int j) {
-        const int qj = j & 15;
-        T x0 = T(0), x1 = T(0);
-        switch (qj) {  // qj is uniform: one case runs, with static register indices
-// (the empty asm keeps each case a plain register read, so the compiler does
-// not turn the switch into an indexed load from memory)
-#define RMGE_COL(Q)                            \
-    case Q:                                    \
-        x0 = v[0][Q];                          \
-        x1 = v[1][Q];                          \
-        asm volatile("" : "+v"(x0), "+v"(x1)); \
-        break;
-            RMGE_COL(0) RMGE_COL(1) RMGE_COL(2) RMGE_COL(3) RMGE_COL(4) RMGE_COL(5)
-            RMGE_COL(6) RMGE_COL(7) RMGE_COL(8) RMGE_COL(9) RMGE_COL(10) RMGE_COL(11)
-            RMGE_COL(12) RMGE_COL(13) RMGE_COL(14) RMGE_COL(15)
-#undef RMGE_COL
-        }
+    auto publish = [&](int j, T x0, T x1) {
         colv[j][l] = x0;
         colv[j][l + 64] = x1;
         const int sel = PIV ? elect_pivot<T>(x0, x1, act) : j;
@@ -227,21 +222,22 @@ __global__ __launch_bounds__(kLeafThreads) void k_leaf_lu(T *a, int64_t lda, int
 
     bool mine = false;  // this wave published column j and holds it in registers
     if (w == 0 && b > 0) {
-        publish(0);
+        publish(0, v[0][0], v[1][0]);
         mine = true;
     }
     int done = b, j = 0;
-    // Steps that change this wave's columns: j < 16 w + 15.  A failed step
-    // still runs its (then empty) update and leaves after it, so the loop has
-    // a single exit and the columns are updated in place.
-    const int jw = min(b, 16 * w + 15);
+    // Steps that change this wave's columns: j < its last column.  A failed
+    // step still runs its (then empty) update and leaves after it, so the loop
+    // has a single exit and the columns are updated in place.
+    const int jw = min(b, leaf_col<PIV>(w, 15));
     for (; j < jw; ++j) {
-        // the wave that publishes the next column (and elects its pivot) is
-        // the chain: let it issue first on its SIMD; the other waves keep a
-        // priority above a GEMM's.  (Measured: faster with pivoting, slower
-        // without, where the next block's owner then lags at block boundaries.)
+        // with pivoting, the wave that publishes the next column (and elects
+        // its pivot) is the chain: let it issue first on its SIMD; the other
+        // waves keep a priority above a GEMM's.  (Measured: slower without
+        // pivoting, where all waves keep the kernel's raised priority.)
+        const bool next = j + 1 < b && leaf_owner<PIV>(j + 1) == w;
         if (PIV) {
-            if (((j + 1) >> 4) == w)
+            if (next)
                 __builtin_amdgcn_s_setprio(3);
             else
                 __builtin_amdgcn_s_setprio(1);
@@ -269,9 +265,35 @@ __global__ __launch_bounds__(kLeafThreads) void k_leaf_lu(T *a, int64_t lda, int
         const bool live0 = PIV ? (act & 1u) != 0 : l > j;
         const bool live1 = PIV ? (act & 2u) != 0 : l + 64 > j;
         const T m0 = (ok && live0) ? c0 * rp : T(0), m1 = (ok && live1) ? c1 * rp : T(0);
+        if (PIV && ok && next) {
+            // with pivoting, column j + 1 is updated first and published
+            // before the rest of the update.  It sits in register (j + 1) / 8,
+            // a uniform index: one case runs, with static register numbers
+            // (the empty asm keeps each case a plain register read rather
+            // than an indexed load)
+            T x0 = T(0), x1 = T(0);
+            switch ((j + 1) >> 3) {
+#define RMGE_COL(Q)                                        \
+    case Q: {                                              \
+        x0 = v[0][Q];                                      \
+        x1 = v[1][Q];                                      \
+        asm volatile("" : "+v"(x0), "+v"(x1));             \
+        const T uq = lane_value<T>(sp ? x1 : x0, sl);      \
+        x0 -= m0 * uq;                                     \
+        x1 -= m1 * uq;                                     \
+        break;                                             \
+    }
+                RMGE_COL(0) RMGE_COL(1) RMGE_COL(2) RMGE_COL(3) RMGE_COL(4) RMGE_COL(5)
+                RMGE_COL(6) RMGE_COL(7) RMGE_COL(8) RMGE_COL(9) RMGE_COL(10) RMGE_COL(11)
+                RMGE_COL(12) RMGE_COL(13) RMGE_COL(14) RMGE_COL(15)
+#undef RMGE_COL
+            }
+            publish(j + 1, x0, x1);
+        }
         // the pivot row's entries of this wave's columns (wave-uniform values).
         // Columns <= j are final in their LDS slots, so their registers take
-        // the update too and are never read again.
+        // the update too and are never read again; column j + 1 gets exactly
+        // the values just published.
         T u[16];
         if (sp) {
 #pragma unroll
@@ -286,8 +308,25 @@ __global__ __launch_bounds__(kLeafThreads) void k_leaf_lu(T *a, int64_t lda, int
             v[1][q] -= m1 * u[q];
         }
         if (!ok) break;
-        mine = j + 1 < b && ((j + 1) >> 4) == w;
-        if (mine) publish(j + 1);
+        if (!PIV && next) {
+            // without pivoting, column j + 1 is published after the full
+            // update (its owner is mostly the owner of column j as well)
+            T x0 = T(0), x1 = T(0);
+            switch ((j + 1) & 15) {
+#define RMGE_COL(Q)                            \
+    case Q:                                    \
+        x0 = v[0][Q];                          \
+        x1 = v[1][Q];                          \
+        asm volatile("" : "+v"(x0), "+v"(x1)); \
+        break;
+                RMGE_COL(0) RMGE_COL(1) RMGE_COL(2) RMGE_COL(3) RMGE_COL(4) RMGE_COL(5)
+                RMGE_COL(6) RMGE_COL(7) RMGE_COL(8) RMGE_COL(9) RMGE_COL(10) RMGE_COL(11)
+                RMGE_COL(12) RMGE_COL(13) RMGE_COL(14) RMGE_COL(15)
+#undef RMGE_COL
+            }
+            publish(j + 1, x0, x1);
+        }
+        mine = next;
     }
     // The remaining steps leave this wave's columns alone: follow the flags
     // and stop where the others stop.
@@ -323,7 +362,7 @@ __global__ __launch_bounds__(kLeafThreads) void k_leaf_lu(T *a, int64_t lda, int
         const int dst = PIV ? pos[i] : i;
 #pragma unroll
         for (int q = 0; q < 16; ++q) {
-            const int c = 16 * w + q;
+            const int c = leaf_col<PIV>(w, q);
             if (c >= b) continue;
             T val = c < done ? colv[c][i] : v[p][q];
             if (c < dst && c < done) val *= rcp[c];
@@ -332,40 +371,21 @@ __global__ __launch_bounds__(kLeafThreads) void k_leaf_lu(T *a, int64_t lda, int
     }
 }
 
-// Inverses of the 32 x 32 diagonal sub-blocks of factored diagonal blocks
-// (the off-diagonal coupling is applied by blocked substitution, so only these
-// small inverses are formed).  Workgroup g covers rows 128 g .. 128 g + 127 of
-// the b x b block at `a`; wave w < nsub inverts U's sub-block w, wave nsub + w
-// the unit-lower L's.  Lane c (< 32) holds column c of its sub-block in
-// registers and computes column c of the inverse by substitution, reading
-// the entries of factor row i from the lanes that hold their columns.
-// Compact output: row 32 q + i of Linv / Uinv holds row i of sub-block q's
-// inverse.
+// Inverse of one 32 x 32 diagonal sub-block (rows q0 .. q0 + sbq - 1) of a
+// factored block, by substitution: lane c (< 32; lanes 32 .. 63 repeat 0 .. 31
+// and store nothing) holds column c of the packed factors in col[] (row k in
+// col[k], zero past the sub-block), computes column c of the inverse of U
+// (upper) or of the unit-lower L, reading the entries of factor row i from
+// the lanes that hold their columns, and stores it.  Compact output: row
+// 32 q + i of Linv / Uinv holds row i of sub-block q's inverse.
+// (row-oriented substitution, sums in ascending k: the order whose rounding
+// the blocked solves were validated with; a column sweep was measured to
+// leave larger errors in the U inverses of strongly growing factors)
 template <typename T>
-__global__ __launch_bounds__(512, 1) void k_diag_inv(const T *a, int64_t lda, int b, T *Linv, T *Uinv,
-                                                  const DevStatus *st) {
-    if (st->code != 0) return;
-    __builtin_amdgcn_s_setprio(3);
-    const int64_t g0 = static_cast<int64_t>(blockIdx.x) * 4 * kSub;
-    a += g0 * lda + g0;
-    Linv += g0 * kSub;
-    Uinv += g0 * kSub;
-    b = (b - g0) < 4 * kSub ? static_cast<int>(b - g0) : 4 * kSub;
-    const int tid = threadIdx.x, lane = tid & 63;
-    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
-    const int nsub = (b + kSub - 1) / kSub;
-    if (wave >= 2 * nsub) return;
-    const bool upper = wave < nsub;
-    const int qd = upper ? wave : wave - nsub, q0 = qd * kSub;
-    const int sbq = (b - q0) < kSub ? (b - q0) : kSub;
-    const int c = lane & (kSub - 1);  // lanes 32 .. 63 repeat 0 .. 31 and store nothing
-    T col[kSub], x[kSub];
-#pragma unroll
-    for (int k = 0; k < kSub; ++k)
-        col[k] = load_if(a, static_cast<int64_t>(q0 + k) * lda + q0 + c, k < sbq && c < sbq);
-    // (row-oriented substitution, sums in ascending k: the order whose rounding
-    // the blocked solves were validated with; a column sweep was measured to
-    // leave larger errors in the U inverses of strongly growing factors)
+__device__ inline void sub_block_inverse(bool upper, int lane, int q0, int sbq,
+                                         const T (&col)[kSub], T *Linv, T *Uinv) {
+    const int c = lane & (kSub - 1);
+    T x[kSub];
     if (upper) {
         // x_c = 1 / u_cc, x_i = -(sum_{k=i+1..c} u_ik x_k) / u_ii, x_i = 0 for i > c
 #pragma unroll
@@ -394,6 +414,36 @@ __global__ __launch_bounds__(512, 1) void k_diag_inv(const T *a, int64_t lda, in
     }
 }
 
+// Inverses of the 32 x 32 diagonal sub-blocks of factored diagonal blocks
+// (the off-diagonal coupling is applied by blocked substitution, so only these
+// small inverses are formed).  Workgroup g covers rows 128 g .. 128 g + 127 of
+// the b x b block at `a`; wave w < nsub inverts U's sub-block w, wave nsub + w
+// the unit-lower L's.
+template <typename T>
+__global__ __launch_bounds__(512, 1) void k_diag_inv(const T *a, int64_t lda, int b, T *Linv, T *Uinv,
+                                                  const DevStatus *st) {
+    if (st->code != 0) return;
+    __builtin_amdgcn_s_setprio(3);
+    const int64_t g0 = static_cast<int64_t>(blockIdx.x) * 4 * kSub;
+    a += g0 * lda + g0;
+    Linv += g0 * kSub;
+    Uinv += g0 * kSub;
+    b = (b - g0) < 4 * kSub ? static_cast<int>(b - g0) : 4 * kSub;
+    const int tid = threadIdx.x, lane = tid & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const int nsub = (b + kSub - 1) / kSub;
+    if (wave >= 2 * nsub) return;
+    const bool upper = wave < nsub;
+    const int qd = upper ? wave : wave - nsub, q0 = qd * kSub;
+    const int sbq = (b - q0) < kSub ? (b - q0) : kSub;
+    const int c = lane & (kSub - 1);
+    T col[kSub];
+#pragma unroll
+    for (int k = 0; k < kSub; ++k)
+        col[k] = load_if(a, static_cast<int64_t>(q0 + k) * lda + q0 + c, k < sbq && c < sbq);
+    sub_block_inverse<T>(upper, lane, q0, sbq, col, Linv, Uinv);
+}
+
 // Blocked substitution on the matrix cores.  The pivot block's factors sit
 // packed at `lu` (ld, width b <= 256); Dinv holds the inverses of their
 // 32 x 32 diagonal sub-blocks (compact: row 32 q + i, 32 columns).  One workgroup owns a 32-wide
@@ -411,44 +461,43 @@ __global__ __launch_bounds__(512, 1) void k_diag_inv(const T *a, int64_t lda, in
 // With `rowsrc` (pivoted blocks) row t of P C is row rowsrc[t] - rowbase of C:
 // the strip is read whole into registers before any of it is written back.
 
-// This thread's four elements (e = tid + 256 m) of sub-block q's inverse, 0 past the block.
-template <typename T>
-__device__ inline void fetch_dinv(const T *Dinv, int b, int q, int tid, T (&d)[4]) {
+// This thread's four elements (e = tid + 256 m) of sub-block q's inverse:
+// fetched raw (clamped address), zeroed past the block when stored to LDS.
+__device__ inline bool dinv_in(int b, int q, int e) {
     const int q0 = q * kSub, sb = (b - q0) < kSub ? (b - q0) : kSub;
-#pragma unroll
-    for (int m = 0; m < 4; ++m) {
-        const int e = tid + 256 * m, r = e / kSub, k = e % kSub;
-        d[m] = load_if(Dinv, (q0 + r) * static_cast<int64_t>(kSub) + k, sb > 0 && r < sb && k < sb);
-    }
+    return sb > 0 && e / kSub < sb && e % kSub < sb;
 }
 template <typename T>
-__device__ inline void store_dinv(T (&Ds)[kSub][kSub + 1], int tid, const T (&d)[4]) {
+__device__ inline void fetch_dinv(const T *Dinv, int b, int q, int tid, T (&d)[4]) {
 #pragma unroll
     for (int m = 0; m < 4; ++m) {
         const int e = tid + 256 * m;
-        Ds[e / kSub][e % kSub] = d[m];
+        d[m] = Dinv[dinv_in(b, q, e) ? q * kSub * static_cast<int64_t>(kSub) + e : 0];
+    }
+}
+template <typename T>
+__device__ inline void store_dinv(T (&Ds)[kSub][kSub + 1], int b, int q, int tid, const T (&d)[4]) {
+#pragma unroll
+    for (int m = 0; m < 4; ++m) {
+        const int e = tid + 256 * m;
+        Ds[e / kSub][e % kSub] = dinv_in(b, q, e) ? d[m] : T(0);
     }
 }
 
+// Strip `blk` (columns 32 blk ..) of the left solve, one workgroup of 256 threads.
 template <typename T>
-// (FP64 holds a step's operands in flight at one workgroup per CU)
-__global__ __launch_bounds__(256, sizeof(T) == 8 ? 1 : 2) void k_trsm_left(const T *lu, int64_t ld, int b, T *C,
-                                                      int64_t ldc, int64_t count, const T *Dinv,
-                                                      const int *abort, const int *rowsrc,
-                                                      int64_t rowbase) {
+__device__ inline void trsm_left_strip(const T *lu, int64_t ld, int b, T *C, int64_t ldc,
+                                       int64_t count, const T *Dinv, const int *rowsrc,
+                                       int64_t rowbase, int64_t blk) {
     using acc_t = typename Mma<T>::acc;
     constexpr int BN = 32;
     __shared__ T Xs[kSub][BN + 1];
     __shared__ T Ds[kSub][kSub + 1];
-    if (abort != nullptr && *abort != 0) return;
-    __builtin_amdgcn_s_setprio(2);  // on the panel's critical path, beside the update GEMM
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int lo = lane & 15, hi = lane >> 4;
-    const int64_t c0 = static_cast<int64_t>(blockIdx.x) * BN;
+    const int64_t c0 = blk * BN;
     const int wcols = static_cast<int>((count - c0) < BN ? (count - c0) : BN);
     const int nrt = (b + 15) / 16;
-    T dcur[4], dnext[4];
-    fetch_dinv(Dinv, b, 0, tid, dcur);
     // source rows of this thread's accumulator rows (all index loads first)
     int64_t src[4][4];
     if (rowsrc) {
@@ -477,7 +526,9 @@ __global__ __launch_bounds__(256, sizeof(T) == 8 ? 1 : 2) void k_trsm_left(const
                 const bool in = t < nrt && row < b && col < wcols;
                 acc[u][j][r] = load_if(C, src[u][r] * ldc + c0 + col, in);
             }
-    // step i's factor operands: -L[row][32 i + k], row tiles below sub-block i
+    // step i's factor operands L[row][32 i + k] for the row tiles below
+    // sub-block i, loaded raw (clamped address) and masked and negated where
+    // they are used, so a load still in flight is never copied or selected
     auto fetch_f = [&](int i, T (&f)[4][kSub / 4]) {
         const int i0 = i * kSub, sb = (b - i0) < kSub ? (b - i0) : kSub;
 #pragma unroll
@@ -487,16 +538,18 @@ __global__ __launch_bounds__(256, sizeof(T) == 8 ? 1 : 2) void k_trsm_left(const
 #pragma unroll
             for (int kq = 0; kq < kSub / 4; ++kq) {
                 const int k = 4 * kq + hi;
-                f[u][kq] = -load_if(lu, row * ld + i0 + k, below && sb > 0 && k < sb);
+                f[u][kq] = lu[(below && k < sb) ? row * ld + i0 + k : 0];
             }
         }
     };
-    T f[4][kSub / 4], fnext[4][kSub / 4];
-    fetch_f(0, f);
-    for (int i = 0, i0 = 0; i0 < b; ++i, i0 += kSub) {
-        fetch_f(i + 1, fnext);
-        fetch_dinv(Dinv, b, i + 1, tid, dnext);
-        store_dinv(Ds, tid, dcur);
+    // sub-block step i with its operands in (f, d); the next step's are
+    // fetched into (fn, dn).  Steps alternate between two register sets.
+    auto step = [&](int i, const T (&f)[4][kSub / 4], T (&fn)[4][kSub / 4], const T (&d)[4],
+                    T (&dn)[4]) {
+        const int i0 = i * kSub, sb = (b - i0) < kSub ? (b - i0) : kSub;
+        fetch_f(i + 1, fn);
+        fetch_dinv(Dinv, b, i + 1, tid, dn);
+        store_dinv(Ds, b, i, tid, d);
 #pragma unroll
         for (int u = 0; u < 4; ++u) {
             const int t = wave + 4 * u;
@@ -544,22 +597,25 @@ __global__ __launch_bounds__(256, sizeof(T) == 8 ? 1 : 2) void k_trsm_left(const
         for (int u = 0; u < 4; ++u) {
             const int t = wave + 4 * u;
             if (t >= 2 * i + 2 && t < nrt) {
+                const bool rin = 16 * t + lo < b;
 #pragma unroll
                 for (int kq = 0; kq < kSub / 4; ++kq) {
                     const int k = 4 * kq + hi;
+                    const T fv = (rin && k < sb) ? -f[u][kq] : T(0);
 #pragma unroll
                     for (int j = 0; j < 2; ++j)
-                        acc[u][j] = Mma<T>::step(f[u][kq], Xs[k][16 * j + lo], acc[u][j]);
+                        acc[u][j] = Mma<T>::step(fv, Xs[k][16 * j + lo], acc[u][j]);
                 }
             }
         }
         __syncthreads();
-#pragma unroll
-        for (int m = 0; m < 4; ++m) dcur[m] = dnext[m];
-#pragma unroll
-        for (int u = 0; u < 4; ++u)
-#pragma unroll
-            for (int kq = 0; kq < kSub / 4; ++kq) f[u][kq] = fnext[u][kq];
+    };
+    T fa[4][kSub / 4], fb[4][kSub / 4], da[4], db[4];
+    fetch_dinv(Dinv, b, 0, tid, da);
+    fetch_f(0, fa);
+    for (int i = 0; kSub * i < b; i += 2) {
+        step(i, fa, fb, da, db);
+        if (kSub * (i + 1) < b) step(i + 1, fb, fa, db, da);
     }
 #pragma unroll
     for (int u = 0; u < 4; ++u)
@@ -574,24 +630,19 @@ __global__ __launch_bounds__(256, sizeof(T) == 8 ? 1 : 2) void k_trsm_left(const
 }
 
 // RIGHT: C (count x b) <- C U^{-1}, strips of 32 rows (column tiles dealt).
+// Strip `blk` (rows 32 blk ..), one workgroup of 256 threads.
 template <typename T>
-// (FP64 holds a step's operands in flight at one workgroup per CU)
-__global__ __launch_bounds__(256, sizeof(T) == 8 ? 1 : 2) void k_trsm_right(const T *lu, int64_t ld, int b, T *C,
-                                                       int64_t ldc, int64_t count, const T *Dinv,
-                                                       const int *abort) {
+__device__ inline void trsm_right_strip(const T *lu, int64_t ld, int b, T *C, int64_t ldc,
+                                        int64_t count, const T *Dinv, int64_t blk) {
     using acc_t = typename Mma<T>::acc;
     constexpr int BM = 32;
     __shared__ T Xs[BM][kSub + 1];
     __shared__ T Ds[kSub][kSub + 1];
-    if (abort != nullptr && *abort != 0) return;
-    __builtin_amdgcn_s_setprio(2);  // on the panel's critical path, beside the update GEMM
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int lo = lane & 15, hi = lane >> 4;
-    const int64_t r0 = static_cast<int64_t>(blockIdx.x) * BM;
+    const int64_t r0 = blk * BM;
     const int wrows = static_cast<int>((count - r0) < BM ? (count - r0) : BM);
     const int nct = (b + 15) / 16;
-    T dcur[4], dnext[4];
-    fetch_dinv(Dinv, b, 0, tid, dcur);
     acc_t acc[4][2];  // [column tile u][row tile]
 #pragma unroll
     for (int u = 0; u < 4; ++u)
@@ -603,7 +654,9 @@ __global__ __launch_bounds__(256, sizeof(T) == 8 ? 1 : 2) void k_trsm_right(cons
                 const int row = 16 * q + Mma<T>::row(lane, r), col = 16 * c + lo;
                 acc[u][q][r] = load_if(C, (r0 + row) * ldc + col, c < nct && row < wrows && col < b);
             }
-    // step j's factor operands: -U[32 j + k][col], column tiles right of sub-block j
+    // step j's factor operands U[32 j + k][col] for the column tiles right
+    // of sub-block j, loaded raw (clamped address) and masked and negated
+    // where they are used
     auto fetch_f = [&](int j, T (&f)[4][kSub / 4]) {
         const int j0 = j * kSub, sb = (b - j0) < kSub ? (b - j0) : kSub;
 #pragma unroll
@@ -613,16 +666,16 @@ __global__ __launch_bounds__(256, sizeof(T) == 8 ? 1 : 2) void k_trsm_right(cons
 #pragma unroll
             for (int kq = 0; kq < kSub / 4; ++kq) {
                 const int k = 4 * kq + hi;
-                f[u][kq] = -load_if(lu, (j0 + k) * ld + col, right && sb > 0 && k < sb);
+                f[u][kq] = lu[(right && k < sb) ? (j0 + k) * ld + col : 0];
             }
         }
     };
-    T f[4][kSub / 4], fnext[4][kSub / 4];
-    fetch_f(0, f);
-    for (int j = 0, j0 = 0; j0 < b; ++j, j0 += kSub) {
-        fetch_f(j + 1, fnext);
-        fetch_dinv(Dinv, b, j + 1, tid, dnext);
-        store_dinv(Ds, tid, dcur);
+    auto step = [&](int j, const T (&f)[4][kSub / 4], T (&fn)[4][kSub / 4], const T (&d)[4],
+                    T (&dn)[4]) {
+        const int j0 = j * kSub, sb = (b - j0) < kSub ? (b - j0) : kSub;
+        fetch_f(j + 1, fn);
+        fetch_dinv(Dinv, b, j + 1, tid, dn);
+        store_dinv(Ds, b, j, tid, d);
 #pragma unroll
         for (int u = 0; u < 4; ++u) {
             const int c = wave + 4 * u;
@@ -670,22 +723,25 @@ __global__ __launch_bounds__(256, sizeof(T) == 8 ? 1 : 2) void k_trsm_right(cons
         for (int u = 0; u < 4; ++u) {
             const int c = wave + 4 * u;
             if (c >= 2 * j + 2 && c < nct) {
+                const bool cin = 16 * c + lo < b;
 #pragma unroll
                 for (int kq = 0; kq < kSub / 4; ++kq) {
                     const int k = 4 * kq + hi;
+                    const T fv = (cin && k < sb) ? -f[u][kq] : T(0);
 #pragma unroll
                     for (int q = 0; q < 2; ++q)
-                        acc[u][q] = Mma<T>::step(Xs[16 * q + lo][k], f[u][kq], acc[u][q]);
+                        acc[u][q] = Mma<T>::step(Xs[16 * q + lo][k], fv, acc[u][q]);
                 }
             }
         }
         __syncthreads();
-#pragma unroll
-        for (int m = 0; m < 4; ++m) dcur[m] = dnext[m];
-#pragma unroll
-        for (int u = 0; u < 4; ++u)
-#pragma unroll
-            for (int kq = 0; kq < kSub / 4; ++kq) f[u][kq] = fnext[u][kq];
+    };
+    T fa[4][kSub / 4], fb[4][kSub / 4], da[4], db[4];
+    fetch_dinv(Dinv, b, 0, tid, da);
+    fetch_f(0, fa);
+    for (int j = 0; kSub * j < b; j += 2) {
+        step(j, fa, fb, da, db);
+        if (kSub * (j + 1) < b) step(j + 1, fb, fa, db, da);
     }
 #pragma unroll
     for (int u = 0; u < 4; ++u)
@@ -697,6 +753,42 @@ __global__ __launch_bounds__(256, sizeof(T) == 8 ? 1 : 2) void k_trsm_right(cons
                 const int row = 16 * q + Mma<T>::row(lane, r), col = 16 * c + lo;
                 if (c < nct && row < wrows && col < b) C[(r0 + row) * ldc + col] = acc[u][q][r];
             }
+}
+
+// (FP64 holds a step's operands in flight at one workgroup per CU)
+template <typename T>
+__global__ __launch_bounds__(256, sizeof(T) == 8 ? 1 : 2) void k_trsm_left(
+    const T *lu, int64_t ld, int b, T *C, int64_t ldc, int64_t count, const T *Dinv,
+    const int *abort, const int *rowsrc, int64_t rowbase) {
+    if (abort != nullptr && *abort != 0) return;
+    __builtin_amdgcn_s_setprio(2);  // on the panel's critical path, beside the update GEMM
+    trsm_left_strip<T>(lu, ld, b, C, ldc, count, Dinv, rowsrc, rowbase, blockIdx.x);
+}
+
+template <typename T>
+__global__ __launch_bounds__(256, sizeof(T) == 8 ? 1 : 2) void k_trsm_right(
+    const T *lu, int64_t ld, int b, T *C, int64_t ldc, int64_t count, const T *Dinv,
+    const int *abort) {
+    if (abort != nullptr && *abort != 0) return;
+    __builtin_amdgcn_s_setprio(2);
+    trsm_right_strip<T>(lu, ld, b, C, ldc, count, Dinv, blockIdx.x);
+}
+
+// Both solves of one pivot block in one launch (they touch disjoint blocks
+// and only read the factors): workgroups below `nl` take the strips of
+// L_B^{-1} P Cl, the others those of Cr U_B^{-1}.
+template <typename T>
+__global__ __launch_bounds__(256, sizeof(T) == 8 ? 1 : 2) void k_trsm_pair(
+    const T *lu, int64_t ld, int b, T *Cl, int64_t ldcl, int64_t countl, const T *Linv,
+    const int *rowsrc, int64_t rowbase, T *Cr, int64_t ldcr, int64_t countr, const T *Uinv,
+    const int *abort, int64_t nl) {
+    if (*abort != 0) return;
+    __builtin_amdgcn_s_setprio(2);
+    const int64_t g = blockIdx.x;
+    if (g < nl)
+        trsm_left_strip<T>(lu, ld, b, Cl, ldcl, countl, Linv, rowsrc, rowbase, g);
+    else
+        trsm_right_strip<T>(lu, ld, b, Cr, ldcr, countr, Uinv, g - nl);
 }
 
 // dst[di] = src[si] with si = gather ? gather[i] : i, di = scatter ? scatter[i] : i.
@@ -876,6 +968,20 @@ hipError_t trsm(int side, const T *lu, int64_t ld, int b, T *C, int64_t ldc, int
     return hipGetLastError();
 }
 
+template <typename T>
+hipError_t trsm_pair(const T *lu, int64_t ld, int b, T *Cl, int64_t ldcl, int64_t countl,
+                     const T *Linv, const int *rowsrc, int64_t rowbase, T *Cr, int64_t ldcr,
+                     int64_t countr, const T *Uinv, const int *abort, hipStream_t s) {
+    if (b < 1 || b > kMaxBlock || countl < 0 || countr < 0 || abort == nullptr)
+        return hipErrorInvalidValue;
+    const int64_t nl = (countl + 31) / 32, nr = (countr + 31) / 32;
+    if (nl + nr == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_trsm_pair<T>, dim3(static_cast<unsigned>(nl + nr)), dim3(256), 0, s, lu,
+                       ld, b, Cl, ldcl, countl, Linv, rowsrc, rowbase, Cr, ldcr, countr, Uinv,
+                       abort, nl);
+    return hipGetLastError();
+}
+
 template <typename T, typename U>
 hipError_t convert_2d(const T *src, int64_t lds, U *dst, int64_t ldd, int64_t rows, int64_t cols,
                       hipStream_t s, const int *gather, const int *scatter) {
@@ -945,6 +1051,12 @@ template hipError_t trsm<double>(int, const double *, int64_t, int, double *, in
                                  const double *, const int *, hipStream_t, const int *, int64_t);
 template hipError_t trsm<float>(int, const float *, int64_t, int, float *, int64_t, int64_t,
                                 const float *, const int *, hipStream_t, const int *, int64_t);
+template hipError_t trsm_pair<double>(const double *, int64_t, int, double *, int64_t, int64_t,
+                                      const double *, const int *, int64_t, double *, int64_t,
+                                      int64_t, const double *, const int *, hipStream_t);
+template hipError_t trsm_pair<float>(const float *, int64_t, int, float *, int64_t, int64_t,
+                                     const float *, const int *, int64_t, float *, int64_t,
+                                     int64_t, const float *, const int *, hipStream_t);
 template hipError_t permute_left<double>(double *, int64_t, int64_t, int, const int *, const int *,
                                          hipStream_t);
 template hipError_t permute_rows<double>(double *, int64_t, int64_t, int, int64_t, int64_t,

@@ -83,6 +83,13 @@ template <typename T>
 hipError_t trsm(int side, const T *lu, int64_t ld, int b, T *C, int64_t ldc, int64_t count,
                 const T *Dinv, const int *abort, hipStream_t s, const int *rowsrc = nullptr,
                 int64_t rowbase = 0);
+// Both of the above for one pivot block in a single launch: Cl (b x countl)
+// <- L^{-1} P Cl and Cr (countr x b) <- Cr U^{-1}.  The two blocks must not
+// overlap; abort must not be null.
+template <typename T>
+hipError_t trsm_pair(const T *lu, int64_t ld, int b, T *Cl, int64_t ldcl, int64_t countl,
+                     const T *Linv, const int *rowsrc, int64_t rowbase, T *Cr, int64_t ldcr,
+                     int64_t countr, const T *Uinv, const int *abort, hipStream_t s);
 // After a pivoted factorization with panels of nb: apply every diagonal
 // block's row exchanges (piv) to the multipliers left of its panel.
 template <typename T>

@@ -867,33 +867,35 @@ __global__ void k_scale_copy(double *dst, const double *src, int64_t lds, int64_
         dst[i] = alpha * src[i * lds];
 }
 
-// GA = -GB X^T (n x n; GB, X: n x nrhs, nrhs <= 64): the gradient of
+// GA = -GB X^T (n x n; GB, X: n x nrhs, nrhs <= K <= 64): the gradient of
 // sum(W .* X) with respect to A when X = A^{-1} B and GB = A^{-T} W.  One
-// workgroup writes a 16 x 256 tile: the 16 rows of GB and the 256 rows of X it
-// needs sit in LDS; each thread forms 16 outputs of one column.  Bound: HBM
-// writes of GA.
+// workgroup writes a 32 x 256 tile, one column per thread: the thread keeps
+// its row of X in registers (zero past nrhs), the 32 rows of GB sit in LDS
+// and are read as broadcasts, and every output row is one coalesced 2 KiB
+// store.  Bound: HBM writes of GA (8 n^2 bytes).
+template <int K>
 __global__ __launch_bounds__(256) void k_grad_a(const double *GB, int64_t ldgb, const double *X,
                                                 int64_t ldx, int64_t n, int nrhs, double *GA,
                                                 int64_t ldga) {
-    __shared__ double gb[16][64];
-    __shared__ double xs[256][65];
-    const int64_t i0 = static_cast<int64_t>(blockIdx.y) * 16;
-    const int64_t j0 = static_cast<int64_t>(blockIdx.x) * 256;
-    for (int e = threadIdx.x; e < 16 * nrhs; e += 256) {
-        const int i = e / nrhs, r = e % nrhs;
-        gb[i][r] = (i0 + i < n) ? GB[(i0 + i) * ldgb + r] : 0.0;
+    constexpr int R = 32;
+    __shared__ double gb[R][K];
+    const int64_t i0 = static_cast<int64_t>(blockIdx.y) * R;
+    const int64_t j = static_cast<int64_t>(blockIdx.x) * 256 + threadIdx.x;
+    for (int e = threadIdx.x; e < R * K; e += 256) {
+        const int i = e / K, r = e % K;
+        gb[i][r] = load_if(GB, (i0 + i) * ldgb + r, i0 + i < n && r < nrhs);
     }
-    for (int e = threadIdx.x; e < 256 * nrhs; e += 256) {
-        const int j = e / nrhs, r = e % nrhs;
-        xs[j][r] = (j0 + j < n) ? X[(j0 + j) * ldx + r] : 0.0;
-    }
+    double x[K];
+#pragma unroll
+    for (int r = 0; r < K; ++r) x[r] = load_if(X, j * ldx + r, j < n && r < nrhs);
     __syncthreads();
-    const int64_t j = j0 + threadIdx.x;
     if (j >= n) return;
-    for (int i = 0; i < 16 && i0 + i < n; ++i) {
+    const int rows = (n - i0) < R ? static_cast<int>(n - i0) : R;
+    for (int i = 0; i < rows; ++i) {
         double acc = 0.0;
-        for (int r = 0; r < nrhs; ++r) acc += gb[i][r] * xs[threadIdx.x][r];
-        GA[(i0 + i) * ldga + j] = -acc;
+#pragma unroll
+        for (int r = 0; r < K; ++r) acc += gb[i][r] * x[r];
+        __builtin_nontemporal_store(-acc, GA + (i0 + i) * ldga + j);  // written once, not reread
     }
 }
 
@@ -1088,9 +1090,14 @@ hipError_t grad_a(const double *GB, int64_t ldgb, const double *X, int64_t ldx, 
                   int nrhs, double *GA, int64_t ldga, hipStream_t s) {
     if (n <= 0) return hipSuccess;
     if (nrhs < 1 || nrhs > 64) return hipErrorInvalidValue;
-    dim3 grid(static_cast<unsigned>((n + 255) / 256), static_cast<unsigned>((n + 15) / 16));
+    dim3 grid(static_cast<unsigned>((n + 255) / 256), static_cast<unsigned>((n + 31) / 32));
     if (grid.y > 65535u) return hipErrorInvalidValue;
-    hipLaunchKernelGGL(k_grad_a, grid, dim3(256), 0, s, GB, ldgb, X, ldx, n, nrhs, GA, ldga);
+    if (nrhs <= 16)
+        hipLaunchKernelGGL(k_grad_a<16>, grid, dim3(256), 0, s, GB, ldgb, X, ldx, n, nrhs, GA, ldga);
+    else if (nrhs <= 32)
+        hipLaunchKernelGGL(k_grad_a<32>, grid, dim3(256), 0, s, GB, ldgb, X, ldx, n, nrhs, GA, ldga);
+    else
+        hipLaunchKernelGGL(k_grad_a<64>, grid, dim3(256), 0, s, GB, ldgb, X, ldx, n, nrhs, GA, ldga);
     return hipGetLastError();
 }
 

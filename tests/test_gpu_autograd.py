@@ -60,7 +60,8 @@ def test_gradients_match_oracle(rmge, kind):
 
 def test_grad_a_kernel_matches_outer_product(rmge):
     rng = np.random.default_rng(5)
-    for n, nrhs in ((1, 1), (17, 3), (300, 16), (513, 64)):
+    # nrhs in each of the kernel's register widths (16, 32, 64), ragged tiles
+    for n, nrhs in ((1, 1), (17, 3), (300, 16), (129, 17), (1000, 32), (513, 64), (33, 40)):
         GB = rng.standard_normal((n, nrhs))
         X = rng.standard_normal((n, nrhs))
         GA = host(rmge.grad_A(dev(GB), dev(X)))
