@@ -182,7 +182,9 @@ __global__ __launch_bounds__(WGM *WGN * 64, MINB) void k_gemm(int M, int N, int 
 //     contiguous), read as two 16-byte LDS loads; B stays k-major (its
 //     16-byte stores stay contiguous) with a row pitch of 132 elements, which
 //     puts the four k-rows a wave reads at once on different LDS banks.
-template <typename T, typename TA, int MINB>
+// ROLE only names the launch (0: the product M = A H, 1: a Schur update), so
+// that the two uses show up as separate kernels in a trace; the code is the same.
+template <typename T, typename TA, int MINB, int ROLE>
 __global__ __launch_bounds__(256, MINB) void k_gemm_fast(int M, int N, int K, T alpha,
                                                          const TA *__restrict__ A, int64_t lda,
                                                          const T *__restrict__ B, int64_t ldb,
@@ -436,7 +438,7 @@ hipError_t run_gemm(int shape, int64_t M, int64_t N, int64_t K, T alpha, const T
                           ldb % 2 == 0;
         if (fits) {
             const int64_t tiles = static_cast<int64_t>(m / 128) * (n / 128);
-            hipLaunchKernelGGL((k_gemm_fast<T, TA, 2>), dim3(static_cast<unsigned>(tiles)),
+            hipLaunchKernelGGL((k_gemm_fast<T, TA, 2, 0>), dim3(static_cast<unsigned>(tiles)),
                                dim3(256), 0, s, m, n, k, alpha, A, lda, B, ldb, beta, C, ldc,
                                abort, absmax);
             return hipGetLastError();
@@ -452,8 +454,9 @@ hipError_t run_gemm(int shape, int64_t M, int64_t N, int64_t K, T alpha, const T
                          ldb % 2 == 0;
     if (sizeof(T) == 4 && sizeof(TA) == 4 && fits128 && m >= 4096 && n >= 4096) {
         const int64_t tiles = static_cast<int64_t>(m / 128) * (n / 128);
-        hipLaunchKernelGGL((k_gemm_fast<T, TA, 2>), dim3(static_cast<unsigned>(tiles)), dim3(256),
-                           0, s, m, n, k, alpha, A, lda, B, ldb, beta, C, ldc, abort, absmax);
+        hipLaunchKernelGGL((k_gemm_fast<T, TA, 2, 1>), dim3(static_cast<unsigned>(tiles)),
+                           dim3(256), 0, s, m, n, k, alpha, A, lda, B, ldb, beta, C, ldc, abort,
+                           absmax);
         return hipGetLastError();
     }
     const bool fits64 = m % 64 == 0 && n % 64 == 0 && k % 16 == 0 && k > 0 && lda % 2 == 0 &&
