@@ -175,6 +175,11 @@ __global__ __launch_bounds__(kLeafThreads) void k_leaf_lu(T *a, int64_t lda, int
 #pragma unroll
     for (int p = 0; p < 2; ++p)
         if (l + 64 * p < b) act |= 1u << p;
+    // Let the block's loads land here.  (A wave whose columns the loop never
+    // updates reaches the write-back with them still outstanding as far as
+    // the compiler can tell, and it would then wait for all memory traffic,
+    // its own stores included, before every store of the write-back.)
+    __builtin_amdgcn_s_waitcnt(0);
     __syncthreads();
 
     // The owner of column j publishes it once step j - 1 has reached it: the

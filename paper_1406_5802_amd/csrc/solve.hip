@@ -138,16 +138,19 @@ __global__ __launch_bounds__(256) void k_trsv(const T *LU, int64_t ld, int64_t n
         if (wave == 0) {
             double v[NR];
             int spins = 0;
+            const bool inl = lane < bJ;
             while (true) {
+                // one round: every entry's load issued before any is examined
+                // (clamped addresses, no load under a branch)
                 bool ready = true;
 #pragma unroll
                 for (int c = 0; c < NR; ++c) {
-                    v[c] = 0.0;
-                    if (lane < bJ && c < nr) {
-                        bool ok;
-                        v[c] = poll_value(X + (J0 + lane) * ldx + c, &ok);
-                        ready = ready && ok;
-                    }
+                    const bool in = inl && c < nr;
+                    bool ok;
+                    const double pv =
+                        poll_value(X + (J0 + (inl ? lane : 0)) * ldx + (c < nr ? c : 0), &ok);
+                    v[c] = in ? pv : 0.0;
+                    ready = ready && (ok || !in);
                 }
                 if (__all(ready)) break;
                 const bool give_up =
@@ -261,10 +264,17 @@ __global__ __launch_bounds__(256) void k_trsv(const T *LU, int64_t ld, int64_t n
         }
     }
     __syncthreads();
+    // (all right-hand sides store with no branch between the stores: at a
+    // branch's join the compiler waits for every store issued before it)
     if (tid < bI) {
+        if (nr == NR) {
 #pragma unroll
-        for (int c = 0; c < NR; ++c)
-            if (c < nr) publish_value(X + (I0 + tid) * ldx + c, xs[tid][c]);
+            for (int c = 0; c < NR; ++c) publish_value(X + (I0 + tid) * ldx + c, xs[tid][c]);
+        } else {
+#pragma unroll
+            for (int c = 0; c < NR; ++c)
+                if (c < nr) publish_value(X + (I0 + tid) * ldx + c, xs[tid][c]);
+        }
     }
 }
 
@@ -426,9 +436,8 @@ __device__ inline void load_row8(const T *p, T (&dst)[8]) {
 // staged in LDS, which keeps the FP64 tiles in registers) and columns
 // 8 c .. 8 c + 7 of each coupling tile (prefetched one tile ahead), of D and of
 // W, so it reads 8 entries of y_J a tile; a row's 16 partial sums sit in 16
-// consecutive lanes and reduce by DPP moves.  Wave 0 polls y_J with one round
-// of loads always in flight, so a result is seen one load latency after it
-// lands.
+// consecutive lanes and reduce by DPP moves.  Wave 0 polls y_J, one round of
+// loads at a time.
 template <typename T>
 constexpr int trsv128_threads() { return sizeof(T) == 4 ? 512 : 1024; }
 
@@ -500,7 +509,9 @@ __global__ __launch_bounds__(trsv128_threads<T>()) void k_trsv128(const T *LU, i
     };
     // Wait for y_J (wave 0, two entries a lane; lanes past the block poll its
     // first entry) and leave it in ys[par] for all threads; false if a wait
-    // gave up.
+    // gave up.  One round of polls at a time: a round left in flight when the
+    // wait ends would make a later instruction wait for it (its registers
+    // are reused), which measured ~1 us per block on the publication.
     auto await_block = [&](int J, int par) {
         if (wave == 0) {
             const int64_t J0 = static_cast<int64_t>(J) * BI;
@@ -508,12 +519,12 @@ __global__ __launch_bounds__(trsv128_threads<T>()) void k_trsv128(const T *LU, i
             const bool in0 = lane < bJ, in1 = lane + 64 < bJ;
             const double *p0 = X + (J0 + (in0 ? lane : 0)) * ldx;
             const double *p1 = X + (J0 + (in1 ? lane + 64 : 0)) * ldx;
-            bool ok0, ok1, nok0, nok1;
-            double v0 = poll_value(p0, &ok0), v1 = poll_value(p1, &ok1);
+            bool ok0, ok1;
+            double v0, v1;
             int spins = 0;
             while (true) {
-                // the next round goes out before this one is examined
-                const double n0 = poll_value(p0, &nok0), n1 = poll_value(p1, &nok1);
+                v0 = poll_value(p0, &ok0);
+                v1 = poll_value(p1, &ok1);
                 if (__all(ok0 && ok1)) break;
                 const bool give_up =
                     (++spins > kSpinLimit) ||
@@ -523,10 +534,6 @@ __global__ __launch_bounds__(trsv128_threads<T>()) void k_trsv128(const T *LU, i
                     break;
                 }
                 __builtin_amdgcn_s_sleep(1);
-                v0 = n0;
-                v1 = n1;
-                ok0 = nok0;
-                ok1 = nok1;
             }
             ys[par][lane] = in0 ? v0 : 0.0;
             ys[par][lane + 64] = in1 ? v1 : 0.0;
@@ -614,10 +621,14 @@ __global__ __launch_bounds__(trsv128_threads<T>()) void k_trsv128(const T *LU, i
         if (tid == 0) atomicExch(err, 1);  // blocks waiting on this one see it and stop
         return;
     }
-    if (c == 0) {
+    // Every lane of a row group holds the group's RG sums (row16_sum leaves a
+    // row's total in all 16 lanes), so lane c < RG publishes row r0 + c: one
+    // store instruction a wave.
+    if (c < RG && r0 + c < bI) {
+        double xv = x[0];
 #pragma unroll
-        for (int k = 0; k < RG; ++k)
-            if (r0 + k < bI) publish_value(X + (I0 + r0 + k) * ldx, x[k]);
+        for (int k = 1; k < RG; ++k) xv = (c == k) ? x[k] : xv;
+        publish_value(X + (I0 + r0 + c) * ldx, xv);
     }
 }
 
@@ -921,6 +932,9 @@ hipError_t trsv_full_launch(const T *LU, int64_t ld, int64_t n, const T *Dinv, c
                            ldx, nr, sync);
     else if (nr <= 4)
         hipLaunchKernelGGL((k_trsv<T, MODE, 4>), dim3(nblk), dim3(256), 0, s, LU, ld, n, Dinv, B, X,
+                           ldx, nr, sync);
+    else if (nr <= 8)
+        hipLaunchKernelGGL((k_trsv<T, MODE, 8>), dim3(nblk), dim3(256), 0, s, LU, ld, n, Dinv, B, X,
                            ldx, nr, sync);
     else
         hipLaunchKernelGGL((k_trsv<T, MODE, 16>), dim3(nblk), dim3(256), 0, s, LU, ld, n, Dinv, B,
