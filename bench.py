@@ -8,8 +8,10 @@ eta <= 1e-14 (at most 16 steps).  Paths: factors in FP64 or in FP32 on the
 matrix cores (refinement always FP64), each with no pivoting (GENP, "f64",
 "f32") or with partial pivoting confined to the diagonal blocks of at most 128
 ("f64p", "f32p"), refined classically or, for FP32 factors, by GMRES preconditioned
-with the factors ("f32g", "f32pg").  The headline is the fastest path that
-reaches eta <= 1e-14;
+with the factors ("f32g", "f32pg"), and "f32xg": as "f32pg" with the product
+M = A G on the BF16 matrix cores (G rounded to BF16, A split into two BF16
+terms, FP32 accumulation).  The headline is the fastest path that reaches
+eta <= 1e-14;
 its speed-up over FP64 GENP is reported beside it.
 
 Rate convention: (2/3 n^3 + 2 n^2 nrhs) flops per step (the standard count for
@@ -37,7 +39,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 METRIC = "factor+solve TFLOP/s n=16384: FP64 vs FP32 MFMA+IR at equal bwd error"
-PEAK = {"f64": 78.6, "f32": 157.3}  # MI355X dense MFMA TFLOP/s
+PEAK = {"f64": 78.6, "f32": 157.3, "bf16": 2500.0}  # MI355X dense MFMA TFLOP/s
 ETA_TARGET = 1e-14
 
 # HBM bytes of one product launch at n = 16384, from rocprofv3 FETCH_SIZE and WRITE_SIZE
@@ -62,7 +64,8 @@ def lu_solve_flops(n, nrhs):
 # name: (factor precision, row exchanges, refinement)
 PATHS = {"f64": ("F64", "PIVOT_NONE", "ir"), "f32": ("F32", "PIVOT_NONE", "ir"),
          "f64p": ("F64", "PIVOT_BLOCK", "ir"), "f32p": ("F32", "PIVOT_BLOCK", "ir"),
-         "f32g": ("F32", "PIVOT_NONE", "gmres"), "f32pg": ("F32", "PIVOT_BLOCK", "gmres")}
+         "f32g": ("F32", "PIVOT_NONE", "gmres"), "f32pg": ("F32", "PIVOT_BLOCK", "gmres"),
+         "f32xg": ("F32_BF16X2", "PIVOT_BLOCK", "gmres")}
 
 
 def run_path(rmge, torch, A, b, name, seed, steps, warmup, block, max_refine, max_iters):
@@ -281,8 +284,8 @@ def main():
     ap.add_argument("--block", type=int, default=256)
     ap.add_argument("--max-refine", type=int, default=16)
     ap.add_argument("--paths", default=None,
-                    help="precision: f64,f32,f64p,f32p,f32g,f32pg (default f64,f32,f64p,f32p,"
-                         "f32pg); differentiation: f64,f32p (default both)")
+                    help="precision: f64,f32,f64p,f32p,f32g,f32pg,f32xg (default f64,f32,f64p,"
+                         "f32p,f32pg,f32xg); differentiation: f64,f32p (default both)")
     ap.add_argument("--max-iters", type=int, default=200, help="GMRES inner iterations in all")
     ap.add_argument("--cpu-n", type=int, default=8192,
                     help="size of the oracle's CPU sample (about 20 s on 16 host threads)")
@@ -300,7 +303,7 @@ def main():
     if args.workload == "differentiation":
         args.paths = args.paths or "f64,f32p"
         return differentiation(args)
-    args.paths = args.paths or "f64,f32,f64p,f32p,f32pg"
+    args.paths = args.paths or "f64,f32,f64p,f32p,f32pg,f32xg"
 
     import torch
 
@@ -332,11 +335,21 @@ def main():
     head = min(ok, key=lambda k: ok[k]["ms_per_step"]) if ok else next(iter(results))
     r = results[head]
     fp32 = head.startswith("f32")
+    split = PATHS[head][0] == "F32_BF16X2"
     flops = lu_solve_flops(n, 1)
     value = flops / (r["ms_per_step"] * 1e-3) / 1e12
-    # roofline of the dominant kernel: the M = A G product, one launch per step
+    # roofline of the dominant kernel: the M = A G product, one launch per step.
+    # Algorithmic flops 2 n^3 - n^2 in every case; the split-BF16 product executes
+    # two BF16 products and is priced against the dense BF16 peak.
     prod_flops = 2.0 * n ** 3 - n * n
     achieved = prod_flops / (r["ms_product"] * 1e-3) / 1e12
+    peak_key = "bf16" if split else ("f32" if fp32 else "f64")
+    if split:
+        kernel = "k_gemm_bf16x2 (M = A_h G + A_l G, BF16 MFMA, FP32 accumulation)"
+        traffic = None
+    else:
+        kernel = "k_gemm_fast<%s, 2, 0> (M = A G)" % ("float, float" if fp32 else "double, double")
+        traffic = product_traffic(n, "f32" if fp32 else "f64")
     out = {
         "metric": METRIC,
         "value": round(value, 3),
@@ -348,7 +361,8 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f32 factors + f64 refinement" if fp32 else "f64",
+        "dtype": ("bf16x2 product + f32 factors + f64 refinement" if split else
+                  "f32 factors + f64 refinement" if fp32 else "f64"),
         "data": "synthetic",
         "config": {"workload": ("precision: n=%d Gaussian multiplier, kappa=%.3g, 1 RHS, "
                                 "eta<=1e-14" % (n, kappa)) if kappa else
@@ -357,12 +371,11 @@ def main():
                    "n": n, "kappa": kappa, "seed": args.seed, "block": args.block, "nrhs": 1,
                    "headline_path": head},
         "roofline": {"bound": "mfma", "achieved": round(achieved, 3),
-                     "peak": PEAK["f32" if fp32 else "f64"], "unit": "TFLOP/s",
-                     "frac": round(achieved / PEAK["f32" if fp32 else "f64"], 4),
-                     "traffic": product_traffic(n, "f32" if fp32 else "f64"),
+                     "peak": PEAK[peak_key], "unit": "TFLOP/s",
+                     "frac": round(achieved / PEAK[peak_key], 4),
+                     "traffic": traffic,
                      "traffic_unit": "bytes/launch",
-                     "kernel": "k_gemm_fast<%s, 2, 0> (M = A G)" % ("float, float" if fp32
-                                                               else "double, double"),
+                     "kernel": kernel,
                      "ms_per_launch": round(r["ms_product"], 4)},
         "executed_tflops": round((flops + prod_flops) / (r["ms_per_step"] * 1e-3) / 1e12, 3),
         "paths": {k: {kk: (float("%.6g" % vv) if isinstance(vv, float) else vv)

@@ -60,8 +60,15 @@ typedef enum {
 /* Precision of the factors L, U (and of the multiplier product M = A H).
  * Residuals and solution updates of refinement are always FP64. */
 typedef enum {
-    RMGE_F64 = 0, /* FP64 MFMA */
-    RMGE_F32 = 1  /* FP32 MFMA with FP32 accumulation; refine in FP64 */
+    RMGE_F64 = 0,       /* FP64 MFMA */
+    RMGE_F32 = 1,       /* FP32 MFMA with FP32 accumulation; refine in FP64 */
+    RMGE_F32_BF16X2 = 3 /* as RMGE_F32, but with a GAUSSIAN multiplier the product
+                           M = A H runs on the BF16 matrix cores: H is drawn, then
+                           rounded to BF16 (that rounded H is the multiplier, used
+                           by the solves too), and A is split into two BF16 terms,
+                           A = A_h + A_l + O(2^-18 |A|); M = A_h H + A_l H with FP32
+                           accumulation.  The factors are FP32 as for RMGE_F32.
+                           Other multiplier kinds behave as RMGE_F32. */
 } rmge_prec;
 
 /* Row exchanges (rmge_factor_pivoted). */

@@ -13,13 +13,16 @@ adjoint) runs in the library's HIP kernels.
 from __future__ import annotations
 
 from . import _rmge
-from ._rmge import (RMGE_F32, RMGE_F64, RMGE_MULT_CIRCULANT, RMGE_MULT_GAUSSIAN,
+from ._rmge import (RMGE_F32, RMGE_F32_BF16X2, RMGE_F64, RMGE_MULT_CIRCULANT, RMGE_MULT_GAUSSIAN,
                     RMGE_MULT_NONE, RMGE_MULT_TOEPLITZ, RMGE_PIVOT_BLOCK, RMGE_PIVOT_NONE,
                     RMGEError, lib)
 
 NONE, GAUSSIAN, CIRCULANT, TOEPLITZ = (RMGE_MULT_NONE, RMGE_MULT_GAUSSIAN, RMGE_MULT_CIRCULANT,
                                        RMGE_MULT_TOEPLITZ)
 F64, F32 = RMGE_F64, RMGE_F32
+# FP32 factors with the product A H on the BF16 matrix cores (H rounded to BF16,
+# A split into two BF16 terms); other multiplier kinds behave as F32
+F32_BF16X2 = RMGE_F32_BF16X2
 PIVOT_NONE, PIVOT_BLOCK = RMGE_PIVOT_NONE, RMGE_PIVOT_BLOCK
 KIND_NAMES = {"none": NONE, "gaussian": GAUSSIAN, "circulant": CIRCULANT, "toeplitz": TOEPLITZ}
 
@@ -259,5 +262,5 @@ def grad_A(GB, X):
 
 
 __all__ = ["factor", "Factors", "multiplier_params", "precondition", "grad_A", "RMGEError", "lib",
-           "NONE", "GAUSSIAN", "CIRCULANT", "TOEPLITZ", "F64", "F32", "PIVOT_NONE",
+           "NONE", "GAUSSIAN", "CIRCULANT", "TOEPLITZ", "F64", "F32", "F32_BF16X2", "PIVOT_NONE",
            "PIVOT_BLOCK"]

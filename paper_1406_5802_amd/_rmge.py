@@ -12,7 +12,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "librmge.so")
 
 RMGE_MULT_NONE, RMGE_MULT_GAUSSIAN, RMGE_MULT_CIRCULANT, RMGE_MULT_TOEPLITZ = 0, 1, 2, 3
-RMGE_F64, RMGE_F32 = 0, 1
+RMGE_F64, RMGE_F32, RMGE_F32_BF16X2 = 0, 1, 3
 RMGE_PIVOT_NONE, RMGE_PIVOT_BLOCK = 0, 1
 (RMGE_OK, RMGE_EINVAL, RMGE_ENOMEM, RMGE_EDEVICE, RMGE_ZERO_PIVOT, RMGE_NONFINITE,
  RMGE_NOT_CONVERGED) = range(7)

@@ -21,7 +21,7 @@ from ._rmge import RMGEError
 class RmgeSolve(torch.autograd.Function):
     @staticmethod
     def forward(ctx, A, B, kind, seed, block, prec, pivot, tol, max_iters):
-        from . import F32, Factors
+        from . import F32, F32_BF16X2, Factors
 
         A = A.detach().contiguous()
         B = B.detach().contiguous()
@@ -29,7 +29,7 @@ class RmgeSolve(torch.autograd.Function):
         if not f.ok:
             f.close()
             raise RMGEError(f.status, "RmgeSolve.forward (factor)")
-        if prec == F32:
+        if prec in (F32, F32_BF16X2):
             X, st = f.solve_gmres(B, max_iters=max_iters, restart=32, tol=tol)
         else:
             X, st = f.solve(B, max_refine=16, tol=tol)
@@ -43,12 +43,12 @@ class RmgeSolve(torch.autograd.Function):
 
     @staticmethod
     def backward(ctx, gX):
-        from . import F32
+        from . import F32, F32_BF16X2
 
         f = ctx.f
         (X,) = ctx.saved_tensors
         gX = gX.contiguous()
-        if ctx.prec == F32:
+        if ctx.prec in (F32, F32_BF16X2):
             GB, st = f.solve_gmres(gX, max_iters=ctx.max_iters, restart=32, tol=ctx.tol,
                                    trans=True)
         else:

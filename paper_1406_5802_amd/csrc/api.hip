@@ -49,6 +49,10 @@ struct rmge_factors {
     void *lu = nullptr;
     void *G = nullptr;         // GAUSSIAN multiplier (T)
     float *a32 = nullptr;      // FP32 GAUSSIAN: A rounded to FP32 (n x ld) for the product
+    bool split16 = false;       // RMGE_F32_BF16X2 with a GAUSSIAN multiplier
+    uint16_t *a16 = nullptr;    // split16: A_h then A_l, BF16 bits, rows16 x ldk16 each
+    uint16_t *ht16 = nullptr;   // split16: H^T as BF16 bits, rows16 x ldk16
+    int64_t rows16 = 0, ldk16 = 0;
     double *params = nullptr;  // structured multiplier parameters
     double *hker = nullptr;    // period-m kernel
     double *hhat = nullptr;    // half spectrum (m/2 + 1 complex)
@@ -297,7 +301,10 @@ hipError_t draw_multiplier(rmge_factors *f) {
     switch (f->kind) {
     case RMGE_MULT_NONE: return hipSuccess;
     case RMGE_MULT_GAUSSIAN:
-        return Prec<T>::normals(static_cast<T *>(f->G), n * n, f->seed, 1, s);
+        HIP_TRY(Prec<T>::normals(static_cast<T *>(f->G), n * n, f->seed, 1, s));
+        if (f->split16)  // the multiplier is the BF16-rounded draw (also used by the solves)
+            return round_h_bf16(reinterpret_cast<float *>(f->G), n, f->ht16, f->ldk16, s);
+        return hipSuccess;
     default: {
         HIP_TRY(launch_normals_f64(f->params, f->kind == RMGE_MULT_CIRCULANT ? n : 2 * n - 1,
                                    f->seed, static_cast<uint64_t>(f->kind), s));
@@ -320,6 +327,10 @@ hipError_t multiply(rmge_factors *f, double *absmax) {
         HIP_TRY((convert_2d<double, T>(f->A, f->lda, lu, f->ld, n, n, s)));
         return absmax ? abs_max<T>(lu, f->ld, n, absmax - 2, s) : hipSuccess;
     case RMGE_MULT_GAUSSIAN:
+        if (f->split16)  // A split into two BF16 terms, H in BF16 (round_a, draw_multiplier)
+            return gemm_bf16x2(n, n, round_up(n, 32), f->a16, f->a16 + f->rows16 * f->ldk16,
+                               f->ldk16, f->ht16, f->ldk16, reinterpret_cast<float *>(lu), f->ld,
+                               s, absmax);
         if (f->a32)  // A already rounded to FP32 (round_a): an FP32 x FP32 product
             return gemm_f32(kGemmProduct, n, n, n, 1.0f, f->a32, f->ld,
                             static_cast<const float *>(f->G), n, 0.0f,
@@ -336,6 +347,9 @@ hipError_t multiply(rmge_factors *f, double *absmax) {
 // rounding the product would apply on load), so the product streams half the
 // bytes for A.
 hipError_t round_a(rmge_factors *f) {
+    if (f->split16)
+        return split_bf16(f->A, f->lda, f->n, f->a16, f->a16 + f->rows16 * f->ldk16, f->ldk16,
+                          f->stream);
     if (!f->a32) return hipSuccess;
     return convert_2d<double, float>(f->A, f->lda, f->a32, f->ld, f->n, f->n, f->stream);
 }
@@ -395,7 +409,8 @@ rmge_status run_factor(rmge_factors *f) {
 void free_handle(rmge_factors *f) {
     if (!f) return;
     void *ptrs[] = {f->lu, f->G, f->params, f->hker, f->hhat, f->tw, f->inv, f->sinv, f->binv,
-                    f->piv, f->st, f->a32, f->scal, f->wy, f->wx, f->wr, f->wnorm, f->wt, f->wsync, f->kv};
+                    f->piv, f->st, f->a32, f->a16, f->ht16, f->scal, f->wy, f->wx, f->wr,
+                    f->wnorm, f->wt, f->wsync, f->kv};
     for (void *p : ptrs)
         if (p) (void)hipFree(p);
     for (hipEvent_t &e : f->ev)
@@ -412,8 +427,17 @@ rmge_status alloc_handle(rmge_factors *f) {
     const size_t es = elem_size(f->prec);
     RMGE_TRY(hipMalloc(&f->lu, es * static_cast<size_t>(n) * f->ld));
     if (f->kind == RMGE_MULT_GAUSSIAN) RMGE_TRY(hipMalloc(&f->G, es * static_cast<size_t>(n * n)));
-    if (f->kind == RMGE_MULT_GAUSSIAN && f->prec == RMGE_F32)
+    if (f->kind == RMGE_MULT_GAUSSIAN && f->prec == RMGE_F32 && !f->split16)
         RMGE_TRY(hipMalloc(&f->a32, sizeof(float) * static_cast<size_t>(n) * f->ld));
+    if (f->split16) {  // zero padding to whole tiles and K chunks, written once
+        f->rows16 = round_up(n, 128);
+        f->ldk16 = round_up(n, 64);
+        const size_t one = sizeof(uint16_t) * static_cast<size_t>(f->rows16) * f->ldk16;
+        RMGE_TRY(hipMalloc(&f->a16, 2 * one));
+        RMGE_TRY(hipMalloc(&f->ht16, one));
+        RMGE_TRY(hipMemsetAsync(f->a16, 0, 2 * one, f->stream));
+        RMGE_TRY(hipMemsetAsync(f->ht16, 0, one, f->stream));
+    }
     if (f->kind == RMGE_MULT_CIRCULANT || f->kind == RMGE_MULT_TOEPLITZ) {
         const int L = f->m / 2;
         RMGE_TRY(hipMalloc(&f->params, sizeof(double) * static_cast<size_t>(2 * n)));
@@ -923,7 +947,7 @@ rmge_status check_factor_args(const double *A, int64_t n, int64_t lda, int32_t k
     if (pivot != RMGE_PIVOT_NONE && pivot != RMGE_PIVOT_BLOCK) return RMGE_EINVAL;
     if (kind < RMGE_MULT_NONE || kind > RMGE_MULT_TOEPLITZ) return RMGE_EINVAL;
     if (block < 0 || block > kMaxBlock) return RMGE_EINVAL;
-    if (prec != RMGE_F64 && prec != RMGE_F32) return RMGE_EINVAL;
+    if (prec != RMGE_F64 && prec != RMGE_F32 && prec != RMGE_F32_BF16X2) return RMGE_EINVAL;
     if ((kind == RMGE_MULT_CIRCULANT || kind == RMGE_MULT_TOEPLITZ) && fft_period(kind, n) == 0)
         return RMGE_EINVAL;
     return RMGE_OK;
@@ -946,7 +970,8 @@ rmge_status rmge_factor_pivoted(const double *A, int64_t n, int64_t lda, int32_t
     f->lda = lda;
     f->ld = round_up(n, 64);
     f->kind = kind;
-    f->prec = prec;
+    f->prec = prec == RMGE_F32_BF16X2 ? RMGE_F32 : prec;
+    f->split16 = prec == RMGE_F32_BF16X2 && kind == RMGE_MULT_GAUSSIAN;
     f->block = block == 0 ? kMaxBlock : block;
     f->pivot = pivot;
     f->seed = seed;
@@ -958,7 +983,7 @@ rmge_status rmge_factor_pivoted(const double *A, int64_t n, int64_t lda, int32_t
         free_handle(f);
         return rs;
     }
-    rs = (prec == RMGE_F32) ? run_factor<float>(f) : run_factor<double>(f);
+    rs = (f->prec == RMGE_F32) ? run_factor<float>(f) : run_factor<double>(f);
     if (rs == RMGE_OK || rs == RMGE_ZERO_PIVOT || rs == RMGE_NONFINITE) {
         *out = f;
         return rs;

@@ -498,4 +498,216 @@ hipError_t gemm_f32_a64(int shape, int64_t M, int64_t N, int64_t K, float alpha,
                                    absmax, s);
 }
 
+
+// ---------------------------------------------------------------------------
+// The product M = A H of the FP32 path on the BF16 matrix cores (precision
+// RMGE_F32_BF16X2).  H is a random multiplier chosen by the library, so it is
+// drawn and then rounded to BF16, which makes it exact in BF16 (the same
+// rounded H is used by the solves); A is split into two BF16 terms,
+// A = A_h + A_l + O(2^-18 |A|).  Then M = A_h H + A_l H: one GEMM over both
+// terms with FP32 accumulation, on v_mfma_f32_16x16x32_bf16 (eight times the
+// FP32 rate per instruction), leaving a product error of the FP32 product's
+// order, far below the FP32 factorization's own.
+//
+// Operands are K-contiguous: A_h, A_l row-major (rows x ldk) and H stored
+// transposed (Ht[j][k] = H[k][j]), all zero-padded to whole 128-row tiles and
+// 32-wide K chunks, so no load is checked; only the C store is.  One
+// workgroup: a 128 x 128 tile, four waves of 64 x 64 (4 x 4 MFMA tiles of
+// 16 x 16); lane (lo, hi) = (l & 15, l >> 4) supplies A[m0 + lo][8 hi .. +7]
+// and Ht[n0 + lo][8 hi .. +7] of a 32-wide chunk (any k assignment shared by
+// both operands gives the same product) and receives C[4 hi + r][lo].  Chunks
+// are double-buffered in LDS with the next chunk's global loads in flight.
+namespace {
+
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
+__global__ __launch_bounds__(256, 2) void k_gemm_bf16x2(int M, int N, int Kp,
+                                                        const uint16_t *__restrict__ Ah,
+                                                        const uint16_t *__restrict__ Al,
+                                                        int64_t lda,
+                                                        const uint16_t *__restrict__ Ht,
+                                                        int64_t ldh, float *C, int64_t ldc,
+                                                        double *absmax) {
+    constexpr int BM = 128, BN = 128, BK = 32, PAD = 8, LDK = BK + PAD;  // LDS row: 80 bytes
+    __shared__ __attribute__((aligned(16))) uint16_t sa[2][2][BM][LDK];
+    __shared__ __attribute__((aligned(16))) uint16_t sb[2][BN][LDK];
+    const int tiles_m = (M + BM - 1) / BM, tiles_n = (N + BN - 1) / BN;
+    int tm, tn;
+    tile_coords(blockIdx.x, tiles_m, tiles_n, tm, tn);
+    const int m0 = tm * BM, n0 = tn * BN;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int lo = lane & 15, hi = lane >> 4;
+    const int wm = wave >> 1, wn = wave & 1;
+    // global -> LDS: 128 rows x 4 pieces of 8 values per operand; thread t
+    // takes pieces t and t + 256 (row p >> 2, piece p & 3) of each
+    const int pr0 = tid >> 2, pr1 = (tid + 256) >> 2, pk = 8 * (tid & 3);
+    const uint16_t *gah0 = Ah + static_cast<int64_t>(m0 + pr0) * lda + pk;
+    const uint16_t *gah1 = Ah + static_cast<int64_t>(m0 + pr1) * lda + pk;
+    const uint16_t *gal0 = Al + static_cast<int64_t>(m0 + pr0) * lda + pk;
+    const uint16_t *gal1 = Al + static_cast<int64_t>(m0 + pr1) * lda + pk;
+    const uint16_t *gb0 = Ht + static_cast<int64_t>(n0 + pr0) * ldh + pk;
+    const uint16_t *gb1 = Ht + static_cast<int64_t>(n0 + pr1) * ldh + pk;
+    uint4 r0, r1, r2, r3, r4, r5;  // one chunk's global loads in flight
+#define RMGE_FETCH(k0)                                          \
+    r0 = *reinterpret_cast<const uint4 *>(gah0 + (k0));         \
+    r1 = *reinterpret_cast<const uint4 *>(gah1 + (k0));         \
+    r2 = *reinterpret_cast<const uint4 *>(gal0 + (k0));         \
+    r3 = *reinterpret_cast<const uint4 *>(gal1 + (k0));         \
+    r4 = *reinterpret_cast<const uint4 *>(gb0 + (k0));          \
+    r5 = *reinterpret_cast<const uint4 *>(gb1 + (k0));
+#define RMGE_STASH(b)                                           \
+    *reinterpret_cast<uint4 *>(&sa[b][0][pr0][pk]) = r0;        \
+    *reinterpret_cast<uint4 *>(&sa[b][0][pr1][pk]) = r1;        \
+    *reinterpret_cast<uint4 *>(&sa[b][1][pr0][pk]) = r2;        \
+    *reinterpret_cast<uint4 *>(&sa[b][1][pr1][pk]) = r3;        \
+    *reinterpret_cast<uint4 *>(&sb[b][pr0][pk]) = r4;           \
+    *reinterpret_cast<uint4 *>(&sb[b][pr1][pk]) = r5;
+    f32x4 acc[4][4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
+    RMGE_FETCH(0)
+    RMGE_STASH(0)
+    __syncthreads();
+    int buf = 0;
+    for (int k0 = 0; k0 < Kp; k0 += BK) {
+        const bool more = k0 + BK < Kp;
+        if (more) {
+            RMGE_FETCH(k0 + BK)
+        }
+        bf16x8 fb[4];
+#pragma unroll
+        for (int j = 0; j < 4; ++j)
+            fb[j] = *reinterpret_cast<const bf16x8 *>(&sb[buf][wn * 64 + j * 16 + lo][8 * hi]);
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const bf16x8 fh =
+                *reinterpret_cast<const bf16x8 *>(&sa[buf][0][wm * 64 + i * 16 + lo][8 * hi]);
+            const bf16x8 fl =
+                *reinterpret_cast<const bf16x8 *>(&sa[buf][1][wm * 64 + i * 16 + lo][8 * hi]);
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fh, fb[j], acc[i][j], 0, 0, 0);
+                acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fl, fb[j], acc[i][j], 0, 0, 0);
+            }
+        }
+        if (more) {
+            RMGE_STASH(buf ^ 1)
+        }
+        __syncthreads();
+        buf ^= 1;
+    }
+#undef RMGE_FETCH
+#undef RMGE_STASH
+    double vmax = 0.0;
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j)
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const int row = m0 + wm * 64 + i * 16 + 4 * hi + q;
+                const int col = n0 + wn * 64 + j * 16 + lo;
+                if (row < M && col < N) {
+                    const float v = acc[i][j][q];
+                    C[static_cast<int64_t>(row) * ldc + col] = v;
+                    vmax = fmax(vmax, fabs(static_cast<double>(v)));
+                }
+            }
+    if (absmax != nullptr) {
+        for (int off = 32; off > 0; off >>= 1) vmax = fmax(vmax, __shfl_xor(vmax, off));
+        if (lane == 0)
+            atomicMax(reinterpret_cast<unsigned long long *>(absmax),
+                      static_cast<unsigned long long>(__double_as_longlong(vmax)));
+    }
+}
+
+}  // namespace
+
+namespace {
+
+// BF16 (1 sign, 8 exponent, 7 mantissa bits) from FP32 by rounding to nearest,
+// ties to even; NaN stays NaN.
+__device__ inline uint16_t bf16_bits(float x) {
+    const uint32_t b = __float_as_uint(x);
+    if ((b & 0x7fffffffu) > 0x7f800000u) return static_cast<uint16_t>((b >> 16) | 0x40u);
+    return static_cast<uint16_t>((b + 0x7fffu + ((b >> 16) & 1u)) >> 16);
+}
+__device__ inline float bf16_value(uint16_t h) { return __uint_as_float(static_cast<uint32_t>(h) << 16); }
+
+// A (n x n, lda, FP64) -> A_h = bf16(A), A_l = bf16(A - A_h) (n x ldk each;
+// the padding is left as allocated, zero).
+__global__ void k_split_bf16(const double *A, int64_t lda, int64_t n, uint16_t *ah, uint16_t *al,
+                             int64_t ldk) {
+    const int64_t total = n * n;
+    for (int64_t e = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x; e < total;
+         e += static_cast<int64_t>(gridDim.x) * blockDim.x) {
+        const int64_t i = e / n, j = e % n;
+        const double a = A[i * lda + j];
+        const uint16_t h = bf16_bits(static_cast<float>(a));
+        const uint16_t l = bf16_bits(static_cast<float>(a - static_cast<double>(bf16_value(h))));
+        ah[i * ldk + j] = h;
+        al[i * ldk + j] = l;
+    }
+}
+
+// H (n x n row-major FP32) rounded to BF16 in place, and its transpose as BF16
+// bits into Ht (n x ldk): 32 x 32 tiles through LDS so both sides coalesce.
+__global__ __launch_bounds__(256) void k_round_h_bf16(float *H, int64_t n, uint16_t *Ht,
+                                                      int64_t ldk) {
+    __shared__ uint16_t t[32][33];
+    const int64_t r0 = static_cast<int64_t>(blockIdx.y) * 32, c0 = static_cast<int64_t>(blockIdx.x) * 32;
+    const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;  // 32 x 8
+    for (int k = ty; k < 32; k += 8) {
+        const int64_t r = r0 + k, c = c0 + tx;
+        if (r < n && c < n) {
+            const uint16_t h = bf16_bits(H[r * n + c]);
+            H[r * n + c] = bf16_value(h);
+            t[k][tx] = h;
+        }
+    }
+    __syncthreads();
+    for (int k = ty; k < 32; k += 8) {
+        const int64_t c = c0 + k, r = r0 + tx;  // Ht[c][r] = H[r][c]
+        if (r < n && c < n) Ht[c * ldk + r] = t[tx][k];
+    }
+}
+
+}  // namespace
+
+hipError_t split_bf16(const double *A, int64_t lda, int64_t n, uint16_t *ah, uint16_t *al,
+                      int64_t ldk, hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+    int64_t g = (n * n + 255) / 256;
+    if (g > 8192) g = 8192;
+    hipLaunchKernelGGL(k_split_bf16, dim3(static_cast<unsigned>(g)), dim3(256), 0, s, A, lda, n,
+                       ah, al, ldk);
+    return hipGetLastError();
+}
+
+hipError_t round_h_bf16(float *H, int64_t n, uint16_t *Ht, int64_t ldk, hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+    const int64_t nb = (n + 31) / 32;
+    if (nb > 65535) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_round_h_bf16, dim3(static_cast<unsigned>(nb), static_cast<unsigned>(nb)),
+                       dim3(256), 0, s, H, n, Ht, ldk);
+    return hipGetLastError();
+}
+
+hipError_t gemm_bf16x2(int64_t M, int64_t N, int64_t Kp, const uint16_t *Ah, const uint16_t *Al,
+                       int64_t lda, const uint16_t *Ht, int64_t ldh, float *C, int64_t ldc,
+                       hipStream_t s, double *absmax) {
+    if (M <= 0 || N <= 0) return hipSuccess;
+    if (M > INT32_MAX || N > INT32_MAX || Kp > INT32_MAX || Kp % 32 != 0 || lda % 8 != 0 ||
+        ldh % 8 != 0 || lda < Kp || ldh < Kp)
+        return hipErrorInvalidValue;
+    const int64_t tiles = ((M + 127) / 128) * ((N + 127) / 128);
+    hipLaunchKernelGGL(k_gemm_bf16x2, dim3(static_cast<unsigned>(tiles)), dim3(256), 0, s,
+                       static_cast<int>(M), static_cast<int>(N), static_cast<int>(Kp), Ah, Al, lda,
+                       Ht, ldh, C, ldc, absmax);
+    return hipGetLastError();
+}
+
 }  // namespace rmge
