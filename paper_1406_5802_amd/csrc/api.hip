@@ -430,7 +430,7 @@ rmge_status alloc_handle(rmge_factors *f) {
     if (f->kind == RMGE_MULT_GAUSSIAN && f->prec == RMGE_F32 && !f->split16)
         RMGE_TRY(hipMalloc(&f->a32, sizeof(float) * static_cast<size_t>(n) * f->ld));
     if (f->split16) {  // zero padding to whole tiles and K chunks, written once
-        f->rows16 = round_up(n, 128);
+        f->rows16 = round_up(n, 256);
         f->ldk16 = round_up(n, 64);
         const size_t one = sizeof(uint16_t) * static_cast<size_t>(f->rows16) * f->ldk16;
         RMGE_TRY(hipMalloc(&f->a16, 2 * one));

@@ -52,7 +52,7 @@ hipError_t gemm_f32(int shape, int64_t M, int64_t N, int64_t K, float alpha, con
                     const int *abort, hipStream_t s, double *absmax = nullptr);
 // FP32 product whose A operand is stored in FP64 (rounded to FP32 on load).
 // The split-BF16 product C (M x N FP32) = (A_h + A_l) Ht^T on BF16 matrix cores:
-// A_h, A_l (>= round_up(M, 128) rows x lda) and Ht (>= round_up(N, 128) rows x
+// A_h, A_l (>= round_up(M, 256) rows x lda) and Ht (>= round_up(N, 256) rows x
 // ldh) BF16 bit patterns, zero-padded; Kp % 32 == 0, lda, ldh % 8 == 0.
 hipError_t gemm_bf16x2(int64_t M, int64_t N, int64_t Kp, const uint16_t *Ah, const uint16_t *Al,
                        int64_t lda, const uint16_t *Ht, int64_t ldh, float *C, int64_t ldc,
