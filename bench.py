@@ -48,8 +48,12 @@ ETA_TARGET = 1e-14
 # those counters were taken on (product_fingerprint).
 TRAFFIC = {"n": 16384, "source": "k_gemm_fast + tile_coords (csrc/gemm.hip) + csrc/mfma.h",
            "sha256": "58b45b88b2ba4d113ec5a823e40f81d15f171ca135f8ccbf0c171f9a67185d88",
-           "f64": {"fetch_kib": 353540709.8, "write_kib": 2099200.0},
-           "f32": {"fetch_kib": 197427532.9, "write_kib": 1050856.8}}
+           "f64": {"fetch_kib": 351848686.4, "write_kib": 2099200.0},
+           "f32": {"fetch_kib": 199430821.6, "write_kib": 1050836.8}}
+# the same for the split-BF16 product (k_gemm_bf16x2, path f32xg)
+TRAFFIC_BF16 = {"n": 16384, "source": "k_gemm_bf16x2 + tile_coords (csrc/gemm.hip)",
+                "sha256": "84e34bad2ce2417152b2ab9234b22cb2ab011987019de5d783b4c87f9550ff8c",
+                "fetch_kib": 45956590.5, "write_kib": 1061462.2}
 
 
 def log(msg):
@@ -139,9 +143,27 @@ def product_fingerprint():
     return hashlib.sha256(text.encode()).hexdigest()
 
 
+def bf16_fingerprint():
+    """sha256 over what the split-BF16 product kernel is compiled from: its own text
+    and the tile mapping it calls."""
+    import hashlib
+
+    csrc = os.path.join(ROOT, "paper_1406_5802_amd", "csrc")
+    with open(os.path.join(csrc, "gemm.hip")) as fh:
+        gemm = fh.read()
+    i = gemm.index("__device__ inline void tile_coords(")
+    tiles = gemm[i:gemm.index("\n}\n", i) + 3]
+    text = _function_text(gemm, "void k_gemm_bf16x2(") + tiles
+    return hashlib.sha256(text.encode()).hexdigest()
+
+
 def product_traffic(n, prec):
-    """Counter-measured HBM bytes per product launch ("f64" or "f32"), or None if they do
-    not apply (another size, or the kernel changed since the counters were taken)."""
+    """Counter-measured HBM bytes per product launch ("f64", "f32" or "bf16"), or None if
+    they do not apply (another size, or the kernel changed since the counters were taken)."""
+    if prec == "bf16":
+        if n != TRAFFIC_BF16["n"] or bf16_fingerprint() != TRAFFIC_BF16["sha256"]:
+            return None
+        return (TRAFFIC_BF16["fetch_kib"] + TRAFFIC_BF16["write_kib"]) * 1024.0
     if n != TRAFFIC["n"] or product_fingerprint() != TRAFFIC["sha256"]:
         return None
     t = TRAFFIC[prec]
@@ -346,7 +368,7 @@ def main():
     peak_key = "bf16" if split else ("f32" if fp32 else "f64")
     if split:
         kernel = "k_gemm_bf16x2 (M = A_h G + A_l G, BF16 MFMA, FP32 accumulation)"
-        traffic = None
+        traffic = product_traffic(n, "bf16")
     else:
         kernel = "k_gemm_fast<%s, 2, 0> (M = A G)" % ("float, float" if fp32 else "double, double")
         traffic = product_traffic(n, "f32" if fp32 else "f64")
