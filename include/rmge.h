@@ -67,7 +67,12 @@ typedef enum {
                            rounded to BF16 (that rounded H is the multiplier, used
                            by the solves too), and A is split into two BF16 terms,
                            A = A_h + A_l + O(2^-18 |A|); M = A_h H + A_l H with FP32
-                           accumulation.  The factors are FP32 as for RMGE_F32.
+                           accumulation.  The factors are FP32 as for RMGE_F32;
+                           the Schur updates of trailing blocks of 2048 rows and
+                           more also run on the BF16 matrix cores, each FP32
+                           operand cut into three BF16 terms and the six leading
+                           cross products formed (dropped terms below 2^-26 of
+                           the product, under FP32's rounding unit).
                            Other multiplier kinds behave as RMGE_F32. */
 } rmge_prec;
 

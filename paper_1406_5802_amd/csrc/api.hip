@@ -53,6 +53,8 @@ struct rmge_factors {
     uint16_t *a16 = nullptr;    // split16: A_h then A_l, BF16 bits, rows16 x ldk16 each
     uint16_t *ht16 = nullptr;   // split16: H^T as BF16 bits, rows16 x ldk16
     int64_t rows16 = 0, ldk16 = 0;
+    uint16_t *u16 = nullptr;    // split16: BF16 terms of the Schur update's operands
+    int64_t urows = 0, uldk = 0;  // (six slabs of urows x uldk)
     double *params = nullptr;  // structured multiplier parameters
     double *hker = nullptr;    // period-m kernel
     double *hhat = nullptr;    // half spectrum (m/2 + 1 complex)
@@ -93,6 +95,10 @@ namespace {
 
 constexpr int kSub = 32;      // rows of the inverted diagonal sub-blocks
 constexpr int kSideCUs = 8;   // compute units reserved for the look-ahead stream
+// Split-BF16 handles: trailing blocks of at least this many rows take the
+// three-term BF16 Schur update (smaller ones fill too few 256 x 256 tiles to
+// beat the FP32 kernels)
+constexpr int64_t kSplitUpdateMin = 2048;
 
 int64_t round_up(int64_t x, int64_t m) { return (x + m - 1) / m * m; }
 
@@ -281,7 +287,12 @@ hipError_t genp_blocked(rmge_factors *f) {
         HIP_TRY(hipStreamWaitEvent(s1, f->ev_narrow, 0));
         HIP_TRY(factor_pivot_block<T>(f, a22, bn, k + b, Linv(step + 1), Uinv(step + 1), s1));
         HIP_TRY(hipEventRecord(f->ev_panel, s1));
-        if (r > bn)
+        if (r > bn && sizeof(T) == 4 && f->u16 != nullptr && r >= kSplitUpdateMin)
+            HIP_TRY(update_bf16x3(r, r - bn, b, reinterpret_cast<const float *>(a21), ld,
+                                  reinterpret_cast<const float *>(a12 + bn), ld,
+                                  reinterpret_cast<float *>(a22 + bn), ld, f->u16, f->uldk,
+                                  f->urows, abort, s0));
+        else if (r > bn)
             HIP_TRY(Prec<T>::gemm(kGemmUpdate, r, r - bn, b, T(-1), a21, ld, a12 + bn, ld, T(1),
                                   a22 + bn, ld, abort, s0));
     }
@@ -409,7 +420,7 @@ rmge_status run_factor(rmge_factors *f) {
 void free_handle(rmge_factors *f) {
     if (!f) return;
     void *ptrs[] = {f->lu, f->G, f->params, f->hker, f->hhat, f->tw, f->inv, f->sinv, f->binv,
-                    f->piv, f->st, f->a32, f->a16, f->ht16, f->scal, f->wy, f->wx, f->wr,
+                    f->piv, f->st, f->a32, f->a16, f->ht16, f->u16, f->scal, f->wy, f->wx, f->wr,
                     f->wnorm, f->wt, f->wsync, f->kv};
     for (void *p : ptrs)
         if (p) (void)hipFree(p);
@@ -437,6 +448,13 @@ rmge_status alloc_handle(rmge_factors *f) {
         RMGE_TRY(hipMalloc(&f->ht16, one));
         RMGE_TRY(hipMemsetAsync(f->a16, 0, 2 * one, f->stream));
         RMGE_TRY(hipMemsetAsync(f->ht16, 0, one, f->stream));
+        f->urows = round_up(n, 256);
+        f->uldk = round_up(f->block, 32);
+        const size_t ubytes = 6 * sizeof(uint16_t) * static_cast<size_t>(f->urows) * f->uldk;
+        if (ubytes <= INT32_MAX) {  // else the updates stay in FP32
+            RMGE_TRY(hipMalloc(&f->u16, ubytes));
+            RMGE_TRY(hipMemsetAsync(f->u16, 0, ubytes, f->stream));
+        }
     }
     if (f->kind == RMGE_MULT_CIRCULANT || f->kind == RMGE_MULT_TOEPLITZ) {
         const int L = f->m / 2;

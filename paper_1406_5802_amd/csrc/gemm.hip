@@ -686,6 +686,261 @@ hipError_t round_h_bf16(float *H, int64_t n, uint16_t *Ht, int64_t ldk, hipStrea
     return hipGetLastError();
 }
 
+// ---------------------------------------------------------------------------
+// Schur update of the split-BF16 path, C <- C - D E (eq. eqgenp with the
+// pivot block's solves already applied: D = D U_B^{-1}, E = L_B^{-1} C), on
+// the BF16 matrix cores at the FP32 product's accuracy.  Each FP32 value is
+// cut into three BF16 terms, x = x_1 + x_2 + x_3 exactly (x_1 = bf16(x),
+// x_2 = bf16(x - x_1), x_3 = x - x_1 - x_2: each takes the next 8 bits of
+// the 24-bit significand).  Of the nine cross products x_i y_j the six with
+// i + j <= 4 are formed; the three left out are below 2^-26 |x y|, under
+// FP32's rounding unit, and every product kept is exact in FP32.  Six BF16
+// instructions do the work of one FP32 product at 16 times the FP32 rate.
+//
+// The accumulators start from C (so the result is C + sum (-D) E with -D
+// split), and the terms enter from the largest down.  Operands come from a
+// workspace the split kernel fills each step: the terms of -D as rows
+// (row i, k contiguous) and those of E transposed (row j = column j of E),
+// each term a (rows x ldk) slab, pstride apart; rows beyond M or N may hold
+// anything finite (they reach only the outputs that are not stored), k in
+// [K, Kp) holds zeros.  One workgroup per CU: a 256 x 256 tile, four waves
+// of 128 x 128 (8 x 8 MFMA tiles), one a SIMD, so that each has 512
+// registers: a 256-register accumulator, the next chunk's 24 loads and one
+// term's fragments of both operands.  The six terms of a 32-wide chunk take
+// 120 KB of LDS, so it is single-buffered: the next chunk's global loads are
+// in flight during this chunk's 384 MFMAs a wave and are written after a
+// barrier.
+namespace {
+
+typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+
+// 16 bytes at byte offset voff + soff of a buffer (soff wave-uniform).
+__device__ inline uint4 buf_load16(__amdgpu_buffer_rsrc_t r, int voff, int soff) {
+    const u32x4 v = __builtin_amdgcn_raw_buffer_load_b128(r, voff, soff, 0);
+    return uint4{v.x, v.y, v.z, v.w};
+}
+
+// ws: the terms of -D (rows, three slabs) then those of E^T (three slabs);
+// bytes: its size, below 2^31, so every offset fits a buffer load's 32 bits.
+__global__ __launch_bounds__(256, 1) void k_update_bf16x3(int M, int N, int Kp,
+                                                          const uint16_t *__restrict__ ws,
+                                                          int bytes, int ldk, int pstride,
+                                                          float *C, int64_t ldc,
+                                                          const int *abort) {
+    constexpr int BM = 256, BN = 256, BK = 32, LDK = BK + 8;  // LDS row: 80 bytes
+    __shared__ __attribute__((aligned(16))) uint16_t sa[3][BM][LDK];
+    __shared__ __attribute__((aligned(16))) uint16_t sb[3][BN][LDK];
+    if (abort != nullptr && *abort != 0) return;
+    const int tiles_m = (M + BM - 1) / BM, tiles_n = (N + BN - 1) / BN;
+    int tm, tn;
+    tile_coords(blockIdx.x, tiles_m, tiles_n, tm, tn);
+    const int m0 = tm * BM, n0 = tn * BN;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int lo = lane & 15, hi = lane >> 4;
+    const int wm = wave >> 1, wn = wave & 1;  // 2 x 2 waves of 128 x 128
+    // global -> LDS: per term and operand 256 rows x 4 pieces of 8 values;
+    // this thread moves rows pr + 64 h, h < 4
+    // (buffer loads: one address register an operand, the rest in scalars)
+    const int pr = tid >> 2, pk = 8 * (tid & 3);
+    const __amdgpu_buffer_rsrc_t rs =
+        __builtin_amdgcn_make_buffer_rsrc(const_cast<uint16_t *>(ws), 0, bytes, 0x00020000);
+    const int va = 2 * ((m0 + pr) * ldk + pk);
+    const int vb = 2 * ((n0 + pr) * ldk + pk + 3 * pstride);
+    auto soff = [&](int p, int h, int k) { return 2 * (p * pstride + h * 64 * ldk + k); };
+    uint4 ra[3][4], rb[3][4];
+#pragma unroll
+    for (int p = 0; p < 3; ++p)
+#pragma unroll
+        for (int h = 0; h < 4; ++h) {
+            ra[p][h] = buf_load16(rs, va, soff(p, h, 0));
+            rb[p][h] = buf_load16(rs, vb, soff(p, h, 0));
+        }
+    // the accumulators start from C; outside M x N they read a clamped
+    // (in-range) address and are never stored
+    f32x4 acc[8][8];
+#pragma unroll
+    for (int i = 0; i < 8; ++i)
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const int row = m0 + wm * 128 + i * 16 + 4 * hi + q;
+            const float *crow = C + static_cast<int64_t>(row < M ? row : M - 1) * ldc;
+#pragma unroll
+            for (int j = 0; j < 8; ++j) {
+                const int col = n0 + wn * 128 + j * 16 + lo;
+                acc[i][j][q] = crow[col < N ? col : N - 1];
+            }
+        }
+#pragma unroll
+    for (int p = 0; p < 3; ++p)
+#pragma unroll
+        for (int h = 0; h < 4; ++h) {
+            *reinterpret_cast<uint4 *>(&sa[p][pr + 64 * h][pk]) = ra[p][h];
+            *reinterpret_cast<uint4 *>(&sb[p][pr + 64 * h][pk]) = rb[p][h];
+        }
+    // drain the C loads here: left pending into the loop, they would make the
+    // compiler wait for every load (the next chunk's too) before each chunk's MFMAs
+    __builtin_amdgcn_s_waitcnt(0);
+    __syncthreads();
+    for (int k0 = 0; k0 < Kp; k0 += BK) {
+        const bool more = k0 + BK < Kp;
+        if (more) {
+#pragma unroll
+            for (int p = 0; p < 3; ++p)
+#pragma unroll
+                for (int h = 0; h < 4; ++h) {
+                    ra[p][h] = buf_load16(rs, va, soff(p, h, k0 + BK));
+                    rb[p][h] = buf_load16(rs, vb, soff(p, h, k0 + BK));
+                }
+        }
+#pragma unroll
+        for (int p = 0; p < 3; ++p) {
+            bf16x8 fa[8];
+#pragma unroll
+            for (int i = 0; i < 8; ++i)
+                fa[i] = *reinterpret_cast<const bf16x8 *>(&sa[p][wm * 128 + i * 16 + lo][8 * hi]);
+#pragma unroll
+            for (int q = 0; p + q < 3; ++q) {
+                bf16x8 fb[8];
+#pragma unroll
+                for (int j = 0; j < 8; ++j)
+                    fb[j] =
+                        *reinterpret_cast<const bf16x8 *>(&sb[q][wn * 128 + j * 16 + lo][8 * hi]);
+#pragma unroll
+                for (int i = 0; i < 8; ++i)
+#pragma unroll
+                    for (int j = 0; j < 8; ++j)
+                        acc[i][j] =
+                            __builtin_amdgcn_mfma_f32_16x16x32_bf16(fa[i], fb[j], acc[i][j], 0, 0, 0);
+            }
+        }
+        __syncthreads();
+        if (more) {
+#pragma unroll
+            for (int p = 0; p < 3; ++p)
+#pragma unroll
+                for (int h = 0; h < 4; ++h) {
+                    *reinterpret_cast<uint4 *>(&sa[p][pr + 64 * h][pk]) = ra[p][h];
+                    *reinterpret_cast<uint4 *>(&sb[p][pr + 64 * h][pk]) = rb[p][h];
+                }
+        }
+        __syncthreads();
+    }
+    if (m0 + BM <= M && n0 + BN <= N) {
+#pragma unroll
+        for (int i = 0; i < 8; ++i)
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                float *crow = C + static_cast<int64_t>(m0 + wm * 128 + i * 16 + 4 * hi + q) * ldc;
+#pragma unroll
+                for (int j = 0; j < 8; ++j) crow[n0 + wn * 128 + j * 16 + lo] = acc[i][j][q];
+            }
+        return;
+    }
+#pragma unroll
+    for (int i = 0; i < 8; ++i)
+#pragma unroll
+        for (int j = 0; j < 8; ++j)
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const int row = m0 + wm * 128 + i * 16 + 4 * hi + q;
+                const int col = n0 + wn * 128 + j * 16 + lo;
+                if (row < M && col < N) C[static_cast<int64_t>(row) * ldc + col] = acc[i][j][q];
+            }
+}
+
+// x = t[0] + t[1] + t[2], each a BF16 bit pattern (exact for finite x away
+// from the bottom of the exponent range).
+__device__ inline void split3(float x, uint16_t &t0, uint16_t &t1, uint16_t &t2) {
+    t0 = bf16_bits(x);
+    const float r1 = x - bf16_value(t0);
+    t1 = bf16_bits(r1);
+    t2 = bf16_bits(r1 - bf16_value(t1));
+}
+
+__device__ inline uint4 pack8(const uint16_t *v) {
+    return uint4{v[0] | (static_cast<uint32_t>(v[1]) << 16), v[2] | (static_cast<uint32_t>(v[3]) << 16),
+                 v[4] | (static_cast<uint32_t>(v[5]) << 16), v[6] | (static_cast<uint32_t>(v[7]) << 16)};
+}
+
+// The update's operands: blocks [0, nbd) cut -D (M x K, ldd) into its three
+// terms as rows of dp (eight k a thread); the rest cut E (K x N, lde) into
+// those of E^T in ep, 32 k x 64 columns a block through LDS so that both the
+// row reads and the k-contiguous writes coalesce.  k in [K, Kp) gets zeros.
+__global__ __launch_bounds__(256) void k_split3_panels(const float *__restrict__ D, int64_t ldd,
+                                                       int M, const float *__restrict__ E,
+                                                       int64_t lde, int N, int K, int Kp,
+                                                       uint16_t *dp, uint16_t *ep, int64_t ldk,
+                                                       int64_t pstride, int nbd,
+                                                       const int *abort) {
+    __shared__ float t[32][65];
+    if (abort != nullptr && *abort != 0) return;
+    const int kc = Kp / 8;  // pieces of eight a row
+    if (static_cast<int>(blockIdx.x) < nbd) {
+        const int64_t e = static_cast<int64_t>(blockIdx.x) * 256 + threadIdx.x;
+        const int i = static_cast<int>(e / kc), k = 8 * static_cast<int>(e % kc);
+        if (i >= M) return;
+        uint16_t v0[8], v1[8], v2[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            const float x = k + u < K ? -D[static_cast<int64_t>(i) * ldd + k + u] : 0.f;
+            split3(x, v0[u], v1[u], v2[u]);
+        }
+        uint16_t *o = dp + static_cast<int64_t>(i) * ldk + k;
+        *reinterpret_cast<uint4 *>(o) = pack8(v0);
+        *reinterpret_cast<uint4 *>(o + pstride) = pack8(v1);
+        *reinterpret_cast<uint4 *>(o + 2 * pstride) = pack8(v2);
+        return;
+    }
+    const int b = static_cast<int>(blockIdx.x) - nbd;
+    const int nbj = (N + 63) / 64;
+    const int j0 = (b % nbj) * 64, k0 = (b / nbj) * 32;
+    const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;  // 64 x 4
+    for (int kk = ty; kk < 32; kk += 4) {
+        const int k = k0 + kk, j = j0 + tx;
+        t[kk][tx] = (k < K && j < N) ? E[static_cast<int64_t>(k) * lde + j] : 0.f;
+    }
+    __syncthreads();
+    const int jj = threadIdx.x >> 2, c = 8 * (threadIdx.x & 3);
+    const int j = j0 + jj;
+    if (j >= N) return;
+    uint16_t v0[8], v1[8], v2[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) split3(t[c + u][jj], v0[u], v1[u], v2[u]);
+    uint16_t *o = ep + static_cast<int64_t>(j) * ldk + k0 + c;
+    *reinterpret_cast<uint4 *>(o) = pack8(v0);
+    *reinterpret_cast<uint4 *>(o + pstride) = pack8(v1);
+    *reinterpret_cast<uint4 *>(o + 2 * pstride) = pack8(v2);
+}
+
+}  // namespace
+
+hipError_t update_bf16x3(int64_t M, int64_t N, int64_t K, const float *D, int64_t ldd,
+                         const float *E, int64_t lde, float *C, int64_t ldc, uint16_t *ws,
+                         int64_t ldk, int64_t rows, const int *abort, hipStream_t s) {
+    if (M <= 0 || N <= 0 || K <= 0) return hipSuccess;
+    const int64_t Kp = (K + 31) / 32 * 32;
+    if (M > INT32_MAX || N > INT32_MAX || ldk % 8 != 0 || ldk < Kp || rows % 256 != 0 ||
+        rows < (M + 255) / 256 * 256 || rows < (N + 255) / 256 * 256)
+        return hipErrorInvalidValue;
+    const int64_t pstride = rows * ldk;
+    if (12 * pstride > INT32_MAX) return hipErrorInvalidValue;  // buffer offsets are 32-bit
+    uint16_t *dp = ws, *ep = ws + 3 * pstride;
+    const int64_t nbd = (M * (Kp / 8) + 255) / 256;
+    const int64_t nbe = ((N + 63) / 64) * (Kp / 32);
+    if (nbd + nbe > INT32_MAX) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_split3_panels, dim3(static_cast<unsigned>(nbd + nbe)), dim3(256), 0, s, D,
+                       ldd, static_cast<int>(M), E, lde, static_cast<int>(N), static_cast<int>(K),
+                       static_cast<int>(Kp), dp, ep, ldk, pstride, static_cast<int>(nbd), abort);
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    const int64_t tiles = ((M + 255) / 256) * ((N + 255) / 256);
+    hipLaunchKernelGGL(k_update_bf16x3, dim3(static_cast<unsigned>(tiles)), dim3(256), 0, s,
+                       static_cast<int>(M), static_cast<int>(N), static_cast<int>(Kp),
+                       static_cast<const uint16_t *>(ws), static_cast<int>(12 * pstride),
+                       static_cast<int>(ldk), static_cast<int>(pstride), C, ldc, abort);
+    return hipGetLastError();
+}
+
 hipError_t gemm_bf16x2(int64_t M, int64_t N, int64_t Kp, const uint16_t *Ah, const uint16_t *Al,
                        int64_t lda, const uint16_t *Ht, int64_t ldh, float *C, int64_t ldc,
                        hipStream_t s, double *absmax) {

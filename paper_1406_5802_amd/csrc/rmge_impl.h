@@ -62,6 +62,14 @@ hipError_t gemm_bf16x2(int64_t M, int64_t N, int64_t Kp, const uint16_t *Ah, con
 hipError_t split_bf16(const double *A, int64_t lda, int64_t n, uint16_t *ah, uint16_t *al,
                       int64_t ldk, hipStream_t s);
 hipError_t round_h_bf16(float *H, int64_t n, uint16_t *Ht, int64_t ldk, hipStream_t s);
+// Schur update C <- C - D E (D: M x K, E: K x N, C: M x N, all FP32 row-major)
+// with each operand cut into three BF16 terms and the six leading cross
+// products on the BF16 matrix cores.  ws: workspace of 6 * rows * ldk BF16
+// values, rows % 256 == 0 and >= round_up(max(M, N), 256), ldk % 8 == 0 and
+// >= round_up(K, 32); its contents on entry do not matter.
+hipError_t update_bf16x3(int64_t M, int64_t N, int64_t K, const float *D, int64_t ldd,
+                         const float *E, int64_t lde, float *C, int64_t ldc, uint16_t *ws,
+                         int64_t ldk, int64_t rows, const int *abort, hipStream_t s);
 hipError_t gemm_f32_a64(int shape, int64_t M, int64_t N, int64_t K, float alpha, const double *A,
                         int64_t lda, const float *B, int64_t ldb, float beta, float *C,
                         int64_t ldc, const int *abort, hipStream_t s, double *absmax = nullptr);

@@ -47,13 +47,19 @@ def test_bf16_rounding_helper():
     np.testing.assert_array_equal(_bf16(x), want)
 
 
-@pytest.mark.parametrize("n,block", [(256, 128), (300, 256), (517, 128), (640, 256)])
-def test_split16_factors_of_rounded_multiplier(rmge, n, block):
+# Trailing blocks of 2048 rows and more take the three-term BF16 Schur update
+# (n = 2300 with 128-column blocks: one step; n = 2600 with 256: two, both
+# with ragged 256 x 256 tiles), smaller ones the FP32 kernels.
+@pytest.mark.parametrize("n,block,pivot", [(256, 128, "PIVOT_BLOCK"), (300, 256, "PIVOT_BLOCK"),
+                                           (517, 128, "PIVOT_BLOCK"), (640, 256, "PIVOT_BLOCK"),
+                                           (2300, 128, "PIVOT_BLOCK"), (2600, 256, "PIVOT_BLOCK"),
+                                           (2300, 256, "PIVOT_NONE")])
+def test_split16_factors_of_rounded_multiplier(rmge, n, block, pivot):
     A = workloads.conditioned(n, 1e2, seed=31)
     f = rmge.factor(dev(A), kind=rmge.GAUSSIAN, seed=17, block=block, prec=rmge.F32_BF16X2,
-                    pivot=rmge.PIVOT_BLOCK)
+                    pivot=getattr(rmge, pivot))
     assert f.ok, f.status
-    G = oracle.factor(A, oracle.GAUSSIAN, 17, local_pivot_block=block).H
+    G = oracle.multiplier(oracle.GAUSSIAN, n, 17)
     Gb = _bf16(G)
     Mb = oracle.matmul(A, Gb)
     perm = host(f.perm()).astype(np.int64)
@@ -66,7 +72,7 @@ def test_split16_factors_of_rounded_multiplier(rmge, n, block):
     assert back <= bound, (back, bound)
 
 
-@pytest.mark.parametrize("n,kappa", [(300, 1e2), (512, 1e3), (1000, 1e2)])
+@pytest.mark.parametrize("n,kappa", [(300, 1e2), (512, 1e3), (1000, 1e2), (2600, 1e2)])
 def test_split16_gmres_matches_oracle(rmge, n, kappa):
     A = workloads.conditioned(n, kappa, seed=51)
     B = workloads.rhs(n, 2, seed=52)
