@@ -55,6 +55,7 @@ struct rmge_factors {
     int64_t rows16 = 0, ldk16 = 0;
     uint16_t *u16 = nullptr;    // split16: BF16 terms of the Schur update's operands
     int64_t urows = 0, uldk = 0;  // (six slabs of urows x uldk)
+    double *wht = nullptr;      // split16: partial sums of H y over Ht
     double *params = nullptr;  // structured multiplier parameters
     double *hker = nullptr;    // period-m kernel
     double *hhat = nullptr;    // half spectrum (m/2 + 1 complex)
@@ -420,7 +421,7 @@ rmge_status run_factor(rmge_factors *f) {
 void free_handle(rmge_factors *f) {
     if (!f) return;
     void *ptrs[] = {f->lu, f->G, f->params, f->hker, f->hhat, f->tw, f->inv, f->sinv, f->binv,
-                    f->piv, f->st, f->a32, f->a16, f->ht16, f->u16, f->scal, f->wy, f->wx, f->wr,
+                    f->piv, f->st, f->a32, f->a16, f->ht16, f->u16, f->wht, f->scal, f->wy, f->wx, f->wr,
                     f->wnorm, f->wt, f->wsync, f->kv};
     for (void *p : ptrs)
         if (p) (void)hipFree(p);
@@ -451,6 +452,7 @@ rmge_status alloc_handle(rmge_factors *f) {
         f->urows = round_up(n, 256);
         f->uldk = round_up(f->block, 32);
         const size_t ubytes = 6 * sizeof(uint16_t) * static_cast<size_t>(f->urows) * f->uldk;
+        RMGE_TRY(hipMalloc(&f->wht, sizeof(double) * static_cast<size_t>(gemv_ht_blocks(n) * n)));
         if (ubytes <= INT32_MAX) {  // else the updates stay in FP32
             RMGE_TRY(hipMalloc(&f->u16, ubytes));
             RMGE_TRY(hipMemsetAsync(f->u16, 0, ubytes, f->stream));
@@ -587,6 +589,9 @@ hipError_t apply_inverse(rmge_factors *f, const double *src, int64_t lds, int64_
     case RMGE_MULT_NONE:
         return axpby_2d<double>(Y, nrhs, X, ldx, n, static_cast<int>(nrhs), beta, s);
     case RMGE_MULT_GAUSSIAN:
+        // split16: the BF16 copy of H (exact, half the bytes of the FP32 one)
+        if (f->split16 && nrhs == 1)
+            return gemv_ht(n, f->ht16, f->ldk16, Y, 1, beta, X, ldx, f->wht, s);
         for (int64_t g = 0; g < nrhs; g += 16) {
             const int nr = static_cast<int>((nrhs - g) < 16 ? (nrhs - g) : 16);
             e = gemv_n<T, double, double>(n, n, 1.0, static_cast<const T *>(f->G), n, Y + g,

@@ -196,6 +196,13 @@ hipError_t axpby_2d(const TS *d, int64_t ldd, double *x, int64_t ldx, int64_t n,
 hipError_t norm_one(const double *A, int64_t lda, int64_t n, double *work, double *out,
                     hipStream_t s);
 hipError_t fill_f64(double *p, int64_t count, double value, hipStream_t s);
+// y = beta y + H x (one right-hand side, FP64 accumulation; x, y strided by
+// ldx, ldy) with H given transposed as BF16 bits: Ht (>= n rows x ldk, ldk % 8
+// == 0 and >= round_up(n, 8), zero in columns [n, ldk)).  part: >=
+// gemv_ht_blocks(n) * n doubles of scratch.
+int64_t gemv_ht_blocks(int64_t n);
+hipError_t gemv_ht(int64_t n, const uint16_t *Ht, int64_t ldk, const double *x, int64_t ldx,
+                   double beta, double *y, int64_t ldy, double *part, hipStream_t s);
 // GA = -GB X^T (n x n, ldga; GB, X: n x nrhs with their leading dimensions; nrhs <= 64,
 // n <= 2^20).
 hipError_t grad_a(const double *GB, int64_t ldgb, const double *X, int64_t ldx, int64_t n,

@@ -1065,6 +1065,79 @@ hipError_t norm_one(const double *A, int64_t lda, int64_t n, double *work, doubl
     return hipGetLastError();
 }
 
+// y = beta y + H x for one right-hand side, H held transposed as BF16 bit
+// patterns (Ht[k][i] = H[i][k], row pitch ldk, zero past column n): the
+// multiplier of the split-BF16 path, exact in BF16, read at half the bytes
+// of its FP32 copy.  FP64 accumulation.  Pass 1: workgroup (ib, kb) takes
+// rows k of one block of Ht (kbsize of them) for 2048 consecutive i, eight a
+// thread (one 16-byte load a row), into part[kb][i]; pass 2 adds the blocks
+// in order, so the result does not depend on scheduling.
+constexpr int kHtMaxKB = 4096;
+
+__global__ __launch_bounds__(256) void k_gemv_ht_part(int64_t n, const uint16_t *__restrict__ Ht,
+                                                      int64_t ldk, const double *__restrict__ x,
+                                                      int64_t ldx, int kbsize, double *part) {
+    __shared__ double xs[kHtMaxKB];
+    const int64_t i0 = static_cast<int64_t>(blockIdx.x) * 2048 + 8 * threadIdx.x;
+    const int64_t k0 = static_cast<int64_t>(blockIdx.y) * kbsize;
+    const int kc = static_cast<int>((n - k0) < kbsize ? (n - k0) : kbsize);
+    for (int t = threadIdx.x; t < kc; t += 256) xs[t] = x[(k0 + t) * ldx];
+    __syncthreads();
+    if (i0 >= n) return;
+    double acc[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) acc[u] = 0.0;
+    const uint16_t *p = Ht + k0 * ldk + i0;
+#pragma unroll 4
+    for (int t = 0; t < kc; ++t) {
+        const uint4 v = *reinterpret_cast<const uint4 *>(p + t * ldk);
+        const double xv = xs[t];
+        const uint32_t w[4] = {v.x, v.y, v.z, v.w};
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            acc[2 * q] += static_cast<double>(__uint_as_float(w[q] << 16)) * xv;
+            acc[2 * q + 1] += static_cast<double>(__uint_as_float(w[q] & 0xffff0000u)) * xv;
+        }
+    }
+    double *o = part + static_cast<int64_t>(blockIdx.y) * n + i0;
+#pragma unroll
+    for (int u = 0; u < 8; ++u)
+        if (i0 + u < n) o[u] = acc[u];
+}
+
+__global__ __launch_bounds__(256) void k_gemv_ht_sum(int64_t n, int nkb,
+                                                     const double *__restrict__ part, double beta,
+                                                     double *y, int64_t ldy) {
+    const int64_t i = static_cast<int64_t>(blockIdx.x) * 256 + threadIdx.x;
+    if (i >= n) return;
+    double s = 0.0;
+    for (int kb = 0; kb < nkb; ++kb) s += part[kb * n + i];
+    y[i * ldy] = beta == 0.0 ? s : beta * y[i * ldy] + s;
+}
+
+int64_t gemv_ht_blocks(int64_t n) {
+    int64_t kb = (n + 63) / 64;
+    if (kb < 256) kb = 256;
+    if (kb > kHtMaxKB) kb = kHtMaxKB;
+    return (n + kb - 1) / kb;
+}
+
+hipError_t gemv_ht(int64_t n, const uint16_t *Ht, int64_t ldk, const double *x, int64_t ldx,
+                   double beta, double *y, int64_t ldy, double *part, hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+    if (ldk % 8 != 0 || ldk < (n + 7) / 8 * 8) return hipErrorInvalidValue;
+    const int64_t nkb = gemv_ht_blocks(n), kbsize = (n + nkb - 1) / nkb;
+    const int64_t nib = (n + 2047) / 2048;
+    if (nib > 65535 || nkb > 65535 || kbsize > kHtMaxKB) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_gemv_ht_part, dim3(static_cast<unsigned>(nib), static_cast<unsigned>(nkb)),
+                       dim3(256), 0, s, n, Ht, ldk, x, ldx, static_cast<int>(kbsize), part);
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_gemv_ht_sum, dim3(grid_for(n, 256)), dim3(256), 0, s, n,
+                       static_cast<int>(nkb), part, beta, y, ldy);
+    return hipGetLastError();
+}
+
 hipError_t fill_f64(double *p, int64_t count, double value, hipStream_t s) {
     if (count <= 0) return hipSuccess;
     hipLaunchKernelGGL(k_fill_f64, dim3(grid_for(count, 256)), dim3(256), 0, s, p, count, value);
