@@ -71,8 +71,9 @@ typedef enum {
                            the Schur updates of trailing blocks of 2048 rows and
                            more also run on the BF16 matrix cores, each FP32
                            operand cut into three BF16 terms and the six leading
-                           cross products formed (dropped terms below 2^-26 of
-                           the product, under FP32's rounding unit).
+                           cross products formed (the dropped terms total at most
+                           (2^-24 + 2^-34) of the product, one unit of FP32
+                           rounding: the accuracy of an FP32 product).
                            Other multiplier kinds behave as RMGE_F32. */
 } rmge_prec;
 

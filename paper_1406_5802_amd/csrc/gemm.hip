@@ -692,10 +692,12 @@ hipError_t round_h_bf16(float *H, int64_t n, uint16_t *Ht, int64_t ldk, hipStrea
 // the BF16 matrix cores at the FP32 product's accuracy.  Each FP32 value is
 // cut into three BF16 terms, x = x_1 + x_2 + x_3 exactly (x_1 = bf16(x),
 // x_2 = bf16(x - x_1), x_3 = x - x_1 - x_2: each takes the next 8 bits of
-// the 24-bit significand).  Of the nine cross products x_i y_j the six with
-// i + j <= 4 are formed; the three left out are below 2^-26 |x y|, under
-// FP32's rounding unit, and every product kept is exact in FP32.  Six BF16
-// instructions do the work of one FP32 product at 16 times the FP32 rate.
+// the 24-bit significand; |x_2| <= 2^-8 |x|, |x_3| <= 2^-17 |x|).  Of the
+// nine cross products x_i y_j the six with i + j <= 4 are formed; the three
+// left out total at most (2^-24 + 2^-34) |x y|, one unit of FP32 rounding,
+// the error FP32 itself makes in rounding each product, while every product
+// kept is exact and accumulates in FP32.  Six BF16 instructions do the work
+// of one FP32 product at 16 times the FP32 rate.
 //
 // The accumulators start from C (so the result is C + sum (-D) E with -D
 // split), and the terms enter from the largest down.  Operands come from a
