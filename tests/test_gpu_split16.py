@@ -49,11 +49,14 @@ def test_bf16_rounding_helper():
 
 # Trailing blocks of 2048 rows and more take the three-term BF16 Schur update
 # (n = 2300 with 128-column blocks: one step; n = 2600 with 256: two, both
-# with ragged 256 x 256 tiles), smaller ones the FP32 kernels.
+# with ragged 256 x 256 tiles), smaller ones the FP32 kernels.  Blocks of 100
+# and 48 columns give update depths that are not whole 32-wide chunks (the
+# split zero-fills k up to 128 and 64).
 @pytest.mark.parametrize("n,block,pivot", [(256, 128, "PIVOT_BLOCK"), (300, 256, "PIVOT_BLOCK"),
                                            (517, 128, "PIVOT_BLOCK"), (640, 256, "PIVOT_BLOCK"),
                                            (2300, 128, "PIVOT_BLOCK"), (2600, 256, "PIVOT_BLOCK"),
-                                           (2300, 256, "PIVOT_NONE")])
+                                           (2300, 256, "PIVOT_NONE"), (2300, 100, "PIVOT_BLOCK"),
+                                           (2150, 48, "PIVOT_NONE")])
 def test_split16_factors_of_rounded_multiplier(rmge, n, block, pivot):
     A = workloads.conditioned(n, 1e2, seed=31)
     f = rmge.factor(dev(A), kind=rmge.GAUSSIAN, seed=17, block=block, prec=rmge.F32_BF16X2,
