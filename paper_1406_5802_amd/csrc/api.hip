@@ -313,8 +313,12 @@ hipError_t draw_multiplier(rmge_factors *f) {
     switch (f->kind) {
     case RMGE_MULT_NONE: return hipSuccess;
     case RMGE_MULT_GAUSSIAN:
+        // split16: the multiplier is the BF16-rounded draw (also used by the solves)
+        if (f->split16 && n % 4 == 0)
+            return normals_bf16t(reinterpret_cast<float *>(f->G), f->ht16, n, f->ldk16, f->seed,
+                                 1, s);
         HIP_TRY(Prec<T>::normals(static_cast<T *>(f->G), n * n, f->seed, 1, s));
-        if (f->split16)  // the multiplier is the BF16-rounded draw (also used by the solves)
+        if (f->split16)
             return round_h_bf16(reinterpret_cast<float *>(f->G), n, f->ht16, f->ldk16, s);
         return hipSuccess;
     default: {

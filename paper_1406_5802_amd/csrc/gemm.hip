@@ -21,6 +21,7 @@
 // Bound: MFMA (2 flops per multiply-add).  The product's tile is chosen for
 // large K; the Schur update (K = panel width) uses smaller tiles and more
 // workgroups per CU so that reading and writing C overlaps the MFMAs.
+#include "bf16.h"
 #include "mfma.h"
 #include "rmge_impl.h"
 
@@ -618,28 +619,39 @@ __global__ __launch_bounds__(1024, 1) void k_gemm_bf16x2(int M, int N, int Kp,
 
 namespace {
 
-// BF16 (1 sign, 8 exponent, 7 mantissa bits) from FP32 by rounding to nearest,
-// ties to even; NaN stays NaN.
-__device__ inline uint16_t bf16_bits(float x) {
-    const uint32_t b = __float_as_uint(x);
-    if ((b & 0x7fffffffu) > 0x7f800000u) return static_cast<uint16_t>((b >> 16) | 0x40u);
-    return static_cast<uint16_t>((b + 0x7fffu + ((b >> 16) & 1u)) >> 16);
-}
-__device__ inline float bf16_value(uint16_t h) { return __uint_as_float(static_cast<uint32_t>(h) << 16); }
 
-// A (n x n, lda, FP64) -> A_h = bf16(A), A_l = bf16(A - A_h) (n x ldk each;
-// the padding is left as allocated, zero).
-__global__ void k_split_bf16(const double *A, int64_t lda, int64_t n, uint16_t *ah, uint16_t *al,
-                             int64_t ldk) {
-    const int64_t total = n * n;
-    for (int64_t e = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x; e < total;
-         e += static_cast<int64_t>(gridDim.x) * blockDim.x) {
-        const int64_t i = e / n, j = e % n;
-        const double a = A[i * lda + j];
-        const uint16_t h = bf16_bits(static_cast<float>(a));
-        const uint16_t l = bf16_bits(static_cast<float>(a - static_cast<double>(bf16_value(h))));
-        ah[i * ldk + j] = h;
-        al[i * ldk + j] = l;
+// A (n x n, lda, FP64) -> A_h = bf16(A), A_l = bf16(A - A_h) (n x ldk each,
+// ldk >= round_up(n, 8); a column n written as zero when n is odd, the rest
+// of the padding left as allocated, zero).  Two consecutive columns a thread,
+// so a wave reads 1 KB and writes 256 bytes per term contiguously (16-byte
+// loads when A's rows are 16-byte aligned, `vec`); rows by blockIdx.y with a
+// stride for n beyond the grid's y limit.
+__global__ __launch_bounds__(256) void k_split_bf16(const double *__restrict__ A, int64_t lda,
+                                                    int64_t n, uint16_t *ah, uint16_t *al,
+                                                    int64_t ldk, int vec) {
+    const int64_t j = 2 * (static_cast<int64_t>(blockIdx.x) * 256 + threadIdx.x);
+    if (j >= n) return;
+    const bool two = j + 1 < n;
+    for (int64_t i = blockIdx.y; i < n; i += gridDim.y) {
+        const double *p = A + i * lda + j;
+        double a[2];
+        if (vec && two) {
+            const double2 v = *reinterpret_cast<const double2 *>(p);
+            a[0] = v.x;
+            a[1] = v.y;
+        } else {
+            a[0] = p[0];
+            a[1] = two ? p[1] : 0.0;
+        }
+        uint32_t h[2], l[2];
+#pragma unroll
+        for (int u = 0; u < 2; ++u) {
+            const uint16_t hb = bf16_bits(static_cast<float>(a[u]));
+            h[u] = hb;
+            l[u] = bf16_bits(static_cast<float>(a[u] - static_cast<double>(bf16_value(hb))));
+        }
+        *reinterpret_cast<uint32_t *>(ah + i * ldk + j) = h[0] | (h[1] << 16);
+        *reinterpret_cast<uint32_t *>(al + i * ldk + j) = l[0] | (l[1] << 16);
     }
 }
 
@@ -670,10 +682,11 @@ __global__ __launch_bounds__(256) void k_round_h_bf16(float *H, int64_t n, uint1
 hipError_t split_bf16(const double *A, int64_t lda, int64_t n, uint16_t *ah, uint16_t *al,
                       int64_t ldk, hipStream_t s) {
     if (n <= 0) return hipSuccess;
-    int64_t g = (n * n + 255) / 256;
-    if (g > 8192) g = 8192;
-    hipLaunchKernelGGL(k_split_bf16, dim3(static_cast<unsigned>(g)), dim3(256), 0, s, A, lda, n,
-                       ah, al, ldk);
+    if (ldk % 8 != 0 || ldk < (n + 7) / 8 * 8) return hipErrorInvalidValue;
+    const int64_t gx = (n + 511) / 512, gy = n < 65535 ? n : 65535;
+    const int vec = (reinterpret_cast<uintptr_t>(A) % 16 == 0 && lda % 2 == 0) ? 1 : 0;
+    hipLaunchKernelGGL(k_split_bf16, dim3(static_cast<unsigned>(gx), static_cast<unsigned>(gy)),
+                       dim3(256), 0, s, A, lda, n, ah, al, ldk, vec);
     return hipGetLastError();
 }
 
@@ -857,11 +870,6 @@ __device__ inline void split3(float x, uint16_t &t0, uint16_t &t1, uint16_t &t2)
     const float r1 = x - bf16_value(t0);
     t1 = bf16_bits(r1);
     t2 = bf16_bits(r1 - bf16_value(t1));
-}
-
-__device__ inline uint4 pack8(const uint16_t *v) {
-    return uint4{v[0] | (static_cast<uint32_t>(v[1]) << 16), v[2] | (static_cast<uint32_t>(v[3]) << 16),
-                 v[4] | (static_cast<uint32_t>(v[5]) << 16), v[6] | (static_cast<uint32_t>(v[7]) << 16)};
 }
 
 // The update's operands: blocks [0, nbd) cut -D (M x K, ldd) into its three

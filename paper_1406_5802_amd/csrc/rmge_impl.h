@@ -62,6 +62,11 @@ hipError_t gemm_bf16x2(int64_t M, int64_t N, int64_t Kp, const uint16_t *Ah, con
 hipError_t split_bf16(const double *A, int64_t lda, int64_t n, uint16_t *ah, uint16_t *al,
                       int64_t ldk, hipStream_t s);
 hipError_t round_h_bf16(float *H, int64_t n, uint16_t *Ht, int64_t ldk, hipStream_t s);
+// The same H as launch_normals_f32 followed by round_h_bf16, in one pass:
+// G (n x n FP32, BF16-rounded values) and Ht (transposed BF16 bits, pitch
+// ldk >= round_up(n, 64), ldk % 8 == 0); needs n % 4 == 0.
+hipError_t normals_bf16t(float *G, uint16_t *Ht, int64_t n, int64_t ldk, uint64_t seed,
+                         uint64_t stream, hipStream_t s);
 // Schur update C <- C - D E (D: M x K, E: K x N, C: M x N, all FP32 row-major)
 // with each operand cut into three BF16 terms and the six leading cross
 // products on the BF16 matrix cores.  ws: workspace of 6 * rows * ldk BF16

@@ -14,6 +14,7 @@
 //
 // Bound: HBM write of the output (8 or 4 bytes per element) plus ~300 VALU
 // operations per block of four; one thread computes one block.
+#include "bf16.h"
 #include "rmge_impl.h"
 
 namespace rmge {
@@ -99,6 +100,55 @@ hipError_t launch_normals(T *out, int64_t count, uint64_t seed, uint64_t stream,
     return hipGetLastError();
 }
 
+// The Gaussian multiplier of the split-BF16 path in one pass: each element
+// drawn as above (stream `stream`, element i n + j), rounded FP64 -> FP32 ->
+// BF16 (nearest, ties to even), and written both as its FP32 value into G
+// (n x n) and, transposed, as BF16 bits into Ht (Ht[j][i] = H[i][j], row
+// pitch ldk >= round_up(n, 64)).  64 x 64 tiles through LDS so both writes
+// coalesce; n % 4 == 0, so each block of four lies in one row.
+__global__ __launch_bounds__(256) void k_normals_bf16t(float *__restrict__ G,
+                                                       uint16_t *__restrict__ Ht, int64_t n,
+                                                       int64_t ldk, uint64_t seed,
+                                                       uint64_t stream) {
+    __shared__ uint16_t t[64][66];
+    const int64_t i0 = static_cast<int64_t>(blockIdx.y) * 64, j0 = static_cast<int64_t>(blockIdx.x) * 64;
+    const int tid = threadIdx.x, r = tid >> 4, cg = tid & 15;
+#pragma unroll
+    for (int rr = 0; rr < 4; ++rr) {
+        const int row = r + 16 * rr;
+        const int64_t i = i0 + row, j = j0 + 4 * cg;
+        uint16_t h[4] = {0, 0, 0, 0};
+        if (i < n && j < n) {
+            uint64_t w[4];
+            Philox4x64::block(static_cast<uint64_t>((i * n + j) / 4), stream, seed, w);
+            double z[4];
+            box_muller(w, z);
+            float v[4];
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                h[q] = bf16_bits(static_cast<float>(z[q]));
+                v[q] = bf16_value(h[q]);
+            }
+            *reinterpret_cast<float4 *>(G + i * n + j) = float4{v[0], v[1], v[2], v[3]};
+        }
+#pragma unroll
+        for (int q = 0; q < 4; ++q) t[row][4 * cg + q] = h[q];
+    }
+    __syncthreads();
+    const int jj = tid >> 2, ic = 8 * (tid & 3);
+    const int64_t j = j0 + jj;
+    if (j >= n) return;
+#pragma unroll
+    for (int half = 0; half < 2; ++half) {
+        const int ib = ic + 32 * half;
+        if (i0 + ib >= n) continue;  // rows past n: the padding keeps its zeros
+        uint16_t v[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) v[u] = t[ib + u][jj];  // rows past n hold 0
+        *reinterpret_cast<uint4 *>(Ht + j * ldk + i0 + ib) = pack8(v);
+    }
+}
+
 }  // namespace
 
 hipError_t launch_normals_f64(double *out, int64_t count, uint64_t seed, uint64_t stream,
@@ -109,6 +159,16 @@ hipError_t launch_normals_f64(double *out, int64_t count, uint64_t seed, uint64_
 hipError_t launch_normals_f32(float *out, int64_t count, uint64_t seed, uint64_t stream,
                               hipStream_t s) {
     return launch_normals<float>(out, count, seed, stream, s);
+}
+
+hipError_t normals_bf16t(float *G, uint16_t *Ht, int64_t n, int64_t ldk, uint64_t seed,
+                         uint64_t stream, hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+    const int64_t nb = (n + 63) / 64;
+    if (n % 4 != 0 || ldk % 8 != 0 || ldk < nb * 64 || nb > 65535) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_normals_bf16t, dim3(static_cast<unsigned>(nb), static_cast<unsigned>(nb)),
+                       dim3(256), 0, s, G, Ht, n, ldk, seed, stream);
+    return hipGetLastError();
 }
 
 }  // namespace rmge

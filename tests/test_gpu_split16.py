@@ -98,3 +98,28 @@ def test_split16_other_kinds_are_fp32(rmge, kind):
     f1 = rmge.factor(A, kind=k, seed=4, block=128, prec=rmge.F32)
     f2 = rmge.factor(A, kind=k, seed=4, block=128, prec=rmge.F32_BF16X2)
     np.testing.assert_array_equal(host(f1.lu()), host(f2.lu()))
+
+
+@pytest.mark.parametrize("n", [300, 517])
+def test_split16_both_copies_of_h_apply_the_multiplier(rmge, n):
+    # The split path keeps H twice: FP32 values (applied for several right-hand
+    # sides at once) and BF16 bits transposed (the product, and one right-hand
+    # side).  n = 300 draws both in one pass, n = 517 (not a multiple of 4)
+    # draws and then rounds.  An unrefined solve x = H U^{-1} L^{-1} b through
+    # either copy is as accurate as the FP32 factors allow (~1e-3 here); a copy
+    # that is not the multiplier of the factors (misplaced or transposed
+    # entries) gives an O(1) error.  (The one- and several-right-hand-side
+    # triangular solves round differently, so the two are not compared to
+    # each other.)
+    A = workloads.conditioned(n, 1e2, seed=61)
+    B = workloads.rhs(n, 2, seed=62)
+    f = rmge.factor(dev(A), kind=rmge.GAUSSIAN, seed=63, block=128, prec=rmge.F32_BF16X2,
+                    pivot=rmge.PIVOT_BLOCK)
+    assert f.ok, f.status
+    X2, _ = f.solve(dev(B), max_refine=0)                               # FP32 copy
+    X1, _ = f.solve(dev(np.ascontiguousarray(B[:, :1])), max_refine=0)  # BF16 copy
+    xt = np.linalg.solve(A, B)
+    for x, want in ((host(X2)[:, 0], xt[:, 0]), (host(X2)[:, 1], xt[:, 1]),
+                    (host(X1)[:, 0], xt[:, 0])):
+        err = np.abs(x - want).max() / np.abs(want).max()
+        assert err <= 2e-2, err
