@@ -123,3 +123,23 @@ def test_split16_both_copies_of_h_apply_the_multiplier(rmge, n):
                     (host(X1)[:, 0], xt[:, 0])):
         err = np.abs(x - want).max() / np.abs(want).max()
         assert err <= 2e-2, err
+
+
+def test_split16_refactor_reuses_workspaces(rmge):
+    # A handle re-factored with a second matrix gives the factors a fresh
+    # handle gives (every kernel of the path is deterministic): the BF16
+    # operand slabs, the transposed H and the update's term slabs are rewritten
+    # where they are read, whatever the first factorization left in them.
+    n = 2300
+    A1 = workloads.conditioned(n, 1e2, seed=71)
+    A2 = workloads.conditioned(n, 1e3, seed=72)
+    f = rmge.factor(dev(A1), kind=rmge.GAUSSIAN, seed=73, block=128, prec=rmge.F32_BF16X2,
+                    pivot=rmge.PIVOT_BLOCK)
+    assert f.ok
+    f.refactor(dev(A2))
+    assert f.ok
+    g = rmge.factor(dev(A2), kind=rmge.GAUSSIAN, seed=73, block=128, prec=rmge.F32_BF16X2,
+                    pivot=rmge.PIVOT_BLOCK)
+    assert g.ok
+    np.testing.assert_array_equal(host(f.lu()), host(g.lu()))
+    np.testing.assert_array_equal(host(f.perm()), host(g.perm()))
