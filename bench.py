@@ -383,7 +383,7 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": ("bf16x2 product + f32 factors + f64 refinement" if split else
+        "dtype": ("bf16x2 product + f32 factors (bf16x3 Schur updates) + f64 refinement" if split else
                   "f32 factors + f64 refinement" if fp32 else "f64"),
         "data": "synthetic",
         "config": {"workload": ("precision: n=%d Gaussian multiplier, kappa=%.3g, 1 RHS, "
