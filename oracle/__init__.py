@@ -60,9 +60,9 @@ def lib() -> ctypes.CDLL:
         L.orc_multiplier_dense.argtypes = [i32, i64, vp, vp]
         L.orc_matmul.argtypes = [i64, i64, i64, vp, vp, vp]
         L.orc_genp.argtypes = [i64, vp, ctypes.POINTER(i64)]
-        L.orc_genp_local.argtypes = [i64, i64, vp, vp, ctypes.POINTER(i64)]
+        L.orc_genp_local.argtypes = [i64, i64, vp, vp, vp, ctypes.POINTER(i64)]
         L.orc_factor.argtypes = [i64, vp, i32, u64, vp, vp, vp]
-        L.orc_factor_ex.argtypes = [i64, vp, i32, u64, i64, vp, vp, vp, vp]
+        L.orc_factor_ex.argtypes = [i64, vp, i32, u64, i64, vp, vp, vp, vp, vp]
         L.orc_solve.argtypes = [i64, i64, vp, vp, vp, vp, vp, vp, i32, vp]
         L.orc_solve_adjoint.argtypes = [i64, i64, vp, vp, vp, vp, vp]
         L.orc_errors.argtypes = [i64, i64, vp, vp, vp, dp, dp]
@@ -170,18 +170,33 @@ def genp(M) -> tuple[np.ndarray, int, int]:
     return LU, int(rc), int(info.value)
 
 
-def genp_local(M, block: int) -> tuple[np.ndarray, np.ndarray, int, int]:
-    """Block elimination with partial pivoting confined to the diagonal blocks
-    where the recursion of eq. eqgenp stops (Section 3, after eq. eqgenpin:
-    small blocks go to a black-box method); panels of ``block`` columns, a
-    panel wider than 128 cut into 128 + rest.  Returns (LU, perm, status, info)
-    with (P M)[t] = M[perm[t]] = (L U)[t]."""
+def _ends(blocks, n: int) -> np.ndarray:
+    """Block ends as int64, checked to partition 0..n."""
+    e = np.asarray(list(blocks), dtype=np.int64)
+    if e.size == 0 or e[-1] != n or np.any(np.diff(np.concatenate([[0], e])) <= 0):
+        raise ValueError("pivot blocks must be strictly increasing ends reaching n=%d" % n)
+    return e
+
+
+def genp_local(M, blocks) -> tuple[np.ndarray, np.ndarray, int, int]:
+    """Block elimination whose recursion (eq. eqgenp) stops at the given diagonal
+    blocks, each eliminated with partial pivoting confined to the block (Section 3,
+    after eq. eqgenpin: small blocks go to a black-box method).  ``blocks`` lists
+    the blocks' ends (strictly increasing, the last = n): the caller chooses the
+    partition.  Returns (LU, perm, status, info) with (P M)[t] = M[perm[t]] =
+    (L U)[t]."""
     LU = _f64(M).copy()
     n = LU.shape[0]
+    ends = _ends(blocks, n)
     perm = np.zeros(n, dtype=np.int64)
     info = ctypes.c_int64(-1)
-    rc = lib().orc_genp_local(n, int(block), _p(LU), _p(perm), ctypes.byref(info))
+    rc = lib().orc_genp_local(n, len(ends), _p(ends), _p(LU), _p(perm), ctypes.byref(info))
     return LU, perm, int(rc), int(info.value)
+
+
+def uniform_blocks(n: int, w: int) -> list:
+    """Ends of consecutive diagonal blocks of width w (the last may be narrower)."""
+    return list(range(w, n, w)) + [n]
 
 
 @dataclass
@@ -198,7 +213,7 @@ class Factors:
     growth: float
     seconds: float = 0.0
     perm: np.ndarray | None = None  # row order of P M = L U (None: no pivoting)
-    block: int = 0
+    pivot_blocks: tuple = ()        # ends of the pivoting blocks (empty: no pivoting)
 
 
 @dataclass
@@ -209,22 +224,25 @@ class Solution:
     seconds: float = 0.0
 
 
-def factor(A, kind: int, seed: int, local_pivot_block: int = 0) -> Factors:
-    """M = A H (Fact faprepr), then GENP on M; with ``local_pivot_block`` > 0,
-    the locally pivoted block elimination of :func:`genp_local` instead."""
+def factor(A, kind: int, seed: int, pivot_blocks=None) -> Factors:
+    """M = A H (Fact faprepr), then GENP on M; with ``pivot_blocks`` (the ends of
+    the diagonal blocks), the locally pivoted block elimination of
+    :func:`genp_local` instead."""
     A = _f64(A)
     n = A.shape[0]
     H = np.zeros((n, n))
     LU = np.zeros((n, n))
-    perm = np.zeros(n, dtype=np.int64) if local_pivot_block > 0 else None
+    ends = _ends(pivot_blocks, n) if pivot_blocks is not None else None
+    perm = np.zeros(n, dtype=np.int64) if ends is not None else None
     st = _Stats()
     t0 = time.perf_counter()
-    rc = lib().orc_factor_ex(n, _p(A), kind, seed, int(local_pivot_block), _p(H), _p(LU),
+    rc = lib().orc_factor_ex(n, _p(A), kind, seed, 0 if ends is None else len(ends),
+                             _p(ends) if ends is not None else None, _p(H), _p(LU),
                              _p(perm) if perm is not None else None, ctypes.byref(st))
     dt = time.perf_counter() - t0
     return Factors(n, kind, seed, A, H, LU, int(rc), int(st.info),
                    float(st.min_abs_pivot), float(st.growth), dt, perm,
-                   int(local_pivot_block))
+                   tuple(int(e) for e in ends) if ends is not None else ())
 
 
 def _perm(f: Factors):

@@ -255,34 +255,33 @@ int orc_genp(int64_t n, double *M, int64_t *info) {
     return ORC_OK;
 }
 
-/* End (exclusive) of the diagonal block that holds row/column k when the
- * recursion of eq. eqgenp stops at blocks of at most 128: the matrix is cut
- * into panels of `block` columns (the last one may be narrower); a panel
- * wider than 128 is cut once more into its first 128 columns and the rest. */
-static int64_t orc_window_end(int64_t n, int64_t block, int64_t k) {
-    int64_t s = (k / block) * block;
-    int64_t b = (n - s) < block ? (n - s) : block;
-    if (b <= 128) return s + b;
-    return k < s + 128 ? s + 128 : s + b;
-}
-
-/* Block Gaussian elimination in which each small diagonal block (see
- * orc_window_end) is eliminated with partial pivoting inside that block only:
- * for column k the pivot is the entry of largest magnitude among rows
- * k .. window_end(k) - 1 of the current matrix (ties: the smallest original row
- * index), whole rows are exchanged, and every row below k is eliminated.  Rows
- * never move between blocks, so the leading block of each block boundary is
- * the same as without pivoting and the Schur complements at the boundaries
- * are those of eq. eqgenp.  Result: P M = L U with perm[t] = the original
- * index of the row stored at t.  *info: first block whose candidates are all
- * exactly zero (the leading block at that boundary is singular), or a
- * non-finite pivot; -1 otherwise. */
-int orc_genp_local(int64_t n, int64_t block, double *M, int64_t *perm, int64_t *info) {
+/* Block Gaussian elimination in which the recursion of eq. eqgenp stops at
+ * the diagonal blocks [ends[q-1], ends[q]) (ends[-1] = 0, ends strictly
+ * increasing, ends[nblk-1] = n), each handed to a black-box method (Section 3,
+ * after eq. eqgenpin): here Gaussian elimination with partial pivoting confined
+ * to that block.  For column k in block [s, e) the pivot is the entry of
+ * largest magnitude among rows k .. e-1 of the current matrix (ties: the
+ * smallest original row index), whole rows are exchanged, and every row below
+ * k is eliminated.  Rows never move between blocks, so the leading block of
+ * each block boundary is the same as without pivoting and the Schur
+ * complements at the boundaries are those of eq. eqgenp.  The partition is the
+ * caller's: any partition gives the same Schur complements at its boundaries.
+ * Result: P M = L U with perm[t] = the original index of the row stored at t.
+ * *info: first column whose candidates are all exactly zero (the leading block
+ * at that boundary is singular), or a non-finite pivot; -1 otherwise.
+ * Returns 1 (and leaves M untouched) if `ends` is not a valid partition. */
+int orc_genp_local(int64_t n, int64_t nblk, const int64_t *ends, double *M, int64_t *perm,
+                   int64_t *info) {
     *info = -1;
+    if (nblk < 1 || ends[nblk - 1] != n) return 1;
+    for (int64_t q = 0; q < nblk; ++q)
+        if (ends[q] <= (q ? ends[q - 1] : 0)) return 1;
     for (int64_t i = 0; i < n; ++i) perm[i] = i;
     double *tmp = (double *)malloc(sizeof(double) * (size_t)(n > 0 ? n : 1));
+    int64_t q = 0;
     for (int64_t k = 0; k < n; ++k) {
-        int64_t we = orc_window_end(n, block, k), r = k;
+        while (ends[q] <= k) ++q;
+        int64_t we = ends[q], r = k;
         for (int64_t i = k + 1; i < we; ++i) {
             double a = fabs(M[i * n + k]), best = fabs(M[r * n + k]);
             if (a > best || (a == best && perm[i] < perm[r])) r = i;
@@ -398,12 +397,12 @@ typedef struct {
     double growth;        /* max |U| / max |M| */
 } orc_stats;
 
-/* Factor: M = A H, then GENP on M (block <= 0), or the locally pivoted block
- * elimination of orc_genp_local with panels of `block` columns (block > 0;
- * perm receives the row order).  H (n x n), LU (n x n) are outputs; perm
- * (n) may be NULL when block <= 0. */
-int orc_factor_ex(int64_t n, const double *A, int kind, uint64_t seed, int64_t block, double *H,
-                  double *LU, int64_t *perm, orc_stats *st) {
+/* Factor: M = A H, then GENP on M (nblk == 0), or the locally pivoted block
+ * elimination of orc_genp_local with the diagonal blocks ending at ends[0 ..
+ * nblk) (perm receives the row order).  H (n x n), LU (n x n) are outputs;
+ * perm (n) and ends may be NULL when nblk == 0. */
+int orc_factor_ex(int64_t n, const double *A, int kind, uint64_t seed, int64_t nblk,
+                  const int64_t *ends, double *H, double *LU, int64_t *perm, orc_stats *st) {
     memset(st, 0, sizeof(*st));
     if (kind == ORC_NONE) {
         orc_multiplier_dense(kind, n, NULL, H);
@@ -416,8 +415,8 @@ int orc_factor_ex(int64_t n, const double *A, int kind, uint64_t seed, int64_t b
     orc_matmul(n, n, n, A, H, LU); /* M = A H  (Fact faprepr) */
     double mmax = 0.0;
     for (int64_t e = 0; e < n * n; ++e) mmax = fmax(mmax, fabs(LU[e]));
-    int rc = block > 0 ? orc_genp_local(n, block, LU, perm, &st->info)
-                       : orc_genp(n, LU, &st->info);
+    int rc = nblk > 0 ? orc_genp_local(n, nblk, ends, LU, perm, &st->info)
+                      : orc_genp(n, LU, &st->info);
     st->status = rc;
     if (rc == ORC_OK) {
         double umax = 0.0, pmin = INFINITY;
@@ -433,7 +432,7 @@ int orc_factor_ex(int64_t n, const double *A, int kind, uint64_t seed, int64_t b
 
 int orc_factor(int64_t n, const double *A, int kind, uint64_t seed, double *H, double *LU,
                orc_stats *st) {
-    return orc_factor_ex(n, A, kind, seed, 0, H, LU, NULL, st);
+    return orc_factor_ex(n, A, kind, seed, 0, NULL, H, LU, NULL, st);
 }
 
 /* z = H U^{-1} L^{-1} P v : one application of the preprocessed inverse

@@ -13,6 +13,7 @@ import pytest
 
 import oracle
 import workloads
+from partition import library_blocks
 from test_gpu_parity import _kappa32, _kappa_leading, dev, host
 
 pytestmark = pytest.mark.gpu
@@ -37,7 +38,7 @@ def test_pivoted_factors_match_oracle(rmge, kind, n, block):
     A = workloads.conditioned(n, 1e2, seed=31)
     f = rmge.factor(dev(A), kind=kind, seed=17, block=block, pivot=rmge.PIVOT_BLOCK)
     assert f.ok, f.status
-    fo = oracle.factor(A, kind, 17, local_pivot_block=block)
+    fo = oracle.factor(A, kind, 17, pivot_blocks=library_blocks(A.shape[0], block))
     assert fo.status == oracle.OK
     perm = host(f.perm()).astype(np.int64)
     np.testing.assert_array_equal(perm, fo.perm)
@@ -69,7 +70,7 @@ def test_pivoted_breakdown_on_singular_boundary_block(rmge, block):
     A = workloads.breakdown_case(seed=0)
     f = rmge.factor(dev(A), kind=rmge.NONE, seed=0, block=block, pivot=rmge.PIVOT_BLOCK)
     assert f.status == 4 and f.info == 63
-    fo = oracle.factor(A, oracle.NONE, 0, local_pivot_block=block)
+    fo = oracle.factor(A, oracle.NONE, 0, pivot_blocks=library_blocks(A.shape[0], block))
     assert fo.status == oracle.ZERO_PIVOT and fo.info == 63
 
 
@@ -82,7 +83,7 @@ def test_pivoted_elimination_passes_singular_inner_block(rmge, block):
     assert f.ok, f.status
     X, st = f.solve(dev(b), max_refine=1)
     assert st["eta"] <= 1e-13, st
-    fo = oracle.factor(A, oracle.NONE, 0, local_pivot_block=block)
+    fo = oracle.factor(A, oracle.NONE, 0, pivot_blocks=library_blocks(A.shape[0], block))
     so = oracle.solve(fo, b, refine=1)
     kappa = np.linalg.cond(A)
     rel = np.linalg.norm(host(X) - so.X) / np.linalg.norm(so.X)
@@ -100,7 +101,7 @@ def test_pivoted_solve_and_adjoint_match_oracle(rmge, kind, n, nrhs, kappa, bloc
     assert f.ok
     X, st = f.solve(dev(B), max_refine=1)
     assert st["eta"] <= 1e-13, st
-    fo = oracle.factor(A, kind, 23, local_pivot_block=block)
+    fo = oracle.factor(A, kind, 23, pivot_blocks=library_blocks(A.shape[0], block))
     so = oracle.solve(fo, B, refine=1)
     rel = np.linalg.norm(host(X) - so.X) / np.linalg.norm(so.X)
     assert rel <= max(1e-10, 2 * kappa * (st["eta"] + so.eta[-1])), rel
@@ -121,7 +122,7 @@ def test_pivoted_fp32_refined_to_fp64(rmge, kind, n, kappa):
     assert f.ok
     X, st = f.solve(dev(B), max_refine=16, tol=1e-14)
     assert st["converged"] and st["eta"] <= 1e-14, st
-    fo = oracle.factor(A, kind, 5, local_pivot_block=256)
+    fo = oracle.factor(A, kind, 5, pivot_blocks=library_blocks(A.shape[0], 256))
     so = oracle.solve(fo, B, refine=1)
     rel = np.linalg.norm(host(X) - so.X) / np.linalg.norm(so.X)
     assert rel <= max(1e-10, 2 * kappa * (st["eta"] + so.eta[-1])), rel
@@ -131,7 +132,7 @@ def test_pivoted_block_sizes_agree_on_the_solution(rmge):
     n = 300
     A = workloads.conditioned(n, 1e3, seed=14)
     b = workloads.rhs(n, 1, seed=15)
-    fo = oracle.factor(A, oracle.GAUSSIAN, 9, local_pivot_block=64)
+    fo = oracle.factor(A, oracle.GAUSSIAN, 9, pivot_blocks=library_blocks(A.shape[0], 64))
     xo = oracle.solve(fo, b, refine=1).X
     for block in (1, 2, 3, 7, 32, 64, 128, 200, 256):
         f = rmge.factor(dev(A), kind=rmge.GAUSSIAN, seed=9, block=block, pivot=rmge.PIVOT_BLOCK)

@@ -16,6 +16,8 @@ import pytest
 
 import workloads
 from oracle import exact
+from oracle import uniform_blocks
+from partition import library_blocks, spans
 
 
 def _strongly_nonsingular_int(n, seed):
@@ -139,16 +141,8 @@ def test_pivot_bounds_theorem_thnorms(orc, seed):
 # ---------------------------------------------------------------------------
 
 def _windows(n, block):
-    """Diagonal blocks [s, e) as the library cuts them: panels of `block`,
-    a panel wider than 128 cut once into 128 + rest."""
-    out = []
-    for s in range(0, n, block):
-        b = min(block, n - s)
-        if b <= 128:
-            out.append((s, s + b))
-        else:
-            out += [(s, s + 128), (s + 128, s + b)]
-    return out
+    """Diagonal blocks [s, e) of width `block` (the last may be narrower)."""
+    return spans(uniform_blocks(n, block))
 
 
 def _lapack_perm(piv):
@@ -164,38 +158,40 @@ def test_local_pivot_one_window_is_lapack_getrf(orc, n, seed):
     import scipy.linalg as sl
 
     A = np.random.default_rng(seed).standard_normal((n, n))
-    LU, perm, rc, info = orc.genp_local(A, block=n)
+    LU, perm, rc, info = orc.genp_local(A, [n])
     assert rc == orc.OK and info == -1
     lu, piv = sl.lu_factor(A)
     np.testing.assert_array_equal(perm, _lapack_perm(piv))
     np.testing.assert_allclose(LU, lu, rtol=0, atol=1e-12 * n)
 
 
-@pytest.mark.parametrize("n,block,seed", [(6, 2, 0), (7, 3, 1), (7, 7, 2), (6, 4, 3)])
-def test_local_pivot_products_of_pivots_are_leading_minors(orc, n, block, seed):
+@pytest.mark.parametrize("n,ends,seed", [(6, [2, 4, 6], 0), (7, [3, 6, 7], 1), (7, [7], 2),
+                                         (6, [4, 6], 3), (7, [1, 4, 5, 7], 8)])
+def test_local_pivot_products_of_pivots_are_leading_minors(orc, n, ends, seed):
     # Rows move only inside a window, so after each window [s, e) the product of
     # the pivots so far is +-det M^(e) (det A = det B det S, Corollary corec);
     # minors by the Leibniz formula.
     A = _strongly_nonsingular_int(n, seed)
-    LU, perm, rc, info = orc.genp_local(A, block=block)
+    LU, perm, rc, info = orc.genp_local(A, ends)
     assert rc == orc.OK
     minors = exact.leading_minors(exact.to_frac(A))
     d = np.diag(LU)
-    for s, e in _windows(n, block):
+    for s, e in spans(ends):
         assert abs(np.prod(d[:e])) == pytest.approx(abs(float(minors[e - 1])), rel=1e-11)
         # rows never leave their window
         assert sorted(perm[s:e]) == list(range(s, e))
 
 
-@pytest.mark.parametrize("n,block,seed", [(6, 2, 4), (7, 3, 5), (8, 4, 6)])
-def test_local_pivot_window_blocks_factor_exact_schur_complements(orc, n, block, seed):
+@pytest.mark.parametrize("n,ends,seed", [(6, [2, 4, 6], 4), (7, [3, 6, 7], 5), (8, [4, 8], 6),
+                                         (8, [1, 4, 6, 8], 7)])
+def test_local_pivot_window_blocks_factor_exact_schur_complements(orc, n, ends, seed):
     # The diagonal block of window [s, e) factors the row-permuted leading block
     # of the exact Schur complement S(M^(s), M) (eq. eqgenp; exact rationals,
     # Gauss-Jordan inverses of the pivot blocks).
     A = _strongly_nonsingular_int(n, seed)
-    LU, perm, rc, _ = orc.genp_local(A, block=block)
+    LU, perm, rc, _ = orc.genp_local(A, ends)
     assert rc == orc.OK
-    wins = _windows(n, block)
+    wins = spans(ends)
     schur = exact.block_schur_sequence(exact.to_frac(A), [e - s for s, e in wins])
     for idx, (s, e) in enumerate(wins):
         S = exact.to_frac(A) if idx == 0 else schur[idx - 1]
@@ -209,19 +205,27 @@ def test_local_pivot_window_blocks_factor_exact_schur_complements(orc, n, block,
 
 @pytest.mark.parametrize("n,block", [(64, 16), (100, 32), (300, 256), (257, 200)])
 def test_local_pivot_reconstructs_PM(orc, n, block):
+    # the library's partition (panels of `block`, wider than 128 cut once)
     A = np.random.default_rng(n).standard_normal((n, n))
-    LU, perm, rc, _ = orc.genp_local(A, block=block)
+    LU, perm, rc, _ = orc.genp_local(A, library_blocks(n, block))
     assert rc == orc.OK
     L = np.tril(LU, -1) + np.eye(n)
     U = np.triu(LU)
     np.testing.assert_allclose(L @ U, A[perm], rtol=0, atol=1e-11 * np.abs(A).max() * n)
-    for s, e in _windows(n, block):
+    for s, e in spans(library_blocks(n, block)):
         assert sorted(perm[s:e]) == list(range(s, e))
+
+
+def test_local_pivot_rejects_bad_partitions(orc):
+    A = np.eye(4)
+    for bad in ([], [2, 3], [3, 2, 4], [0, 4], [2, 2, 4]):
+        with pytest.raises(ValueError):
+            orc.genp_local(A, bad)
 
 
 def test_local_pivot_block_one_is_genp(orc):
     A = _strongly_nonsingular_int(6, 7)
-    LU1, perm, rc1, _ = orc.genp_local(A, block=1)
+    LU1, perm, rc1, _ = orc.genp_local(A, uniform_blocks(6, 1))
     LU0, rc0, _ = orc.genp(A)
     assert rc1 == rc0 == orc.OK
     np.testing.assert_array_equal(perm, np.arange(6))
@@ -236,7 +240,7 @@ def test_local_pivot_breakdown_and_rescue(orc):
                   [1.0, 2.0, 1.0, 1.0]])
     _, rc, info = orc.genp(A)
     assert rc == orc.ZERO_PIVOT and info == 0
-    LU, perm, rc, info = orc.genp_local(A, block=2)
+    LU, perm, rc, info = orc.genp_local(A, [2, 4])
     assert rc == orc.OK and info == -1
     assert list(perm[:2]) == [1, 0]
     # leading 2x2 block singular: every window of 2 ends on an exactly zero pivot
@@ -244,9 +248,9 @@ def test_local_pivot_breakdown_and_rescue(orc):
                   [2.0, 4.0, 1.0, 0.0],
                   [0.0, 1.0, 3.0, 1.0],
                   [1.0, 0.0, 1.0, 2.0]])
-    _, _, rc, info = orc.genp_local(B, block=2)
+    _, _, rc, info = orc.genp_local(B, [2, 4])
     assert rc == orc.ZERO_PIVOT and info == 1
     # ties: equal magnitudes choose the smaller original row index
     C = np.array([[1.0, 1.0], [-1.0, 2.0]])
-    _, perm, rc, _ = orc.genp_local(C, block=2)
+    _, perm, rc, _ = orc.genp_local(C, [2])
     assert rc == orc.OK and list(perm) == [0, 1]

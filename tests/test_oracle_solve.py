@@ -15,6 +15,7 @@ import pytest
 import sympy
 
 import workloads
+from partition import library_blocks
 
 EPS = np.finfo(float).eps
 
@@ -160,7 +161,7 @@ def test_local_pivot_solve_and_adjoint_match_lapack(orc, kind, block):
     A = workloads.conditioned(n, 1e4, seed=9)
     B = workloads.rhs(n, 2, seed=9)
     W = workloads.rhs(n, 3, seed=10)
-    f = orc.factor(A, kind, seed=12, local_pivot_block=block)
+    f = orc.factor(A, kind, seed=12, pivot_blocks=library_blocks(n, block))
     assert f.status == orc.OK
     s = orc.solve(f, B, refine=1)
     X = np.linalg.solve(A, B)
@@ -178,10 +179,10 @@ def test_breakdown_case_local_pivot(orc, seed):
     # multiplier makes every window's leading block nonsingular
     A = workloads.breakdown_case(seed)
     b = workloads.rhs(256, 1, seed)
-    f = orc.factor(A, orc.NONE, 0, local_pivot_block=64)
+    f = orc.factor(A, orc.NONE, 0, pivot_blocks=library_blocks(256, 64))
     assert f.status == orc.ZERO_PIVOT and f.info == 63
-    f = orc.factor(A, orc.NONE, 0, local_pivot_block=128)
+    f = orc.factor(A, orc.NONE, 0, pivot_blocks=library_blocks(256, 128))
     assert f.status == orc.OK
-    f = orc.factor(A, orc.GAUSSIAN, seed + 1000, local_pivot_block=64)
+    f = orc.factor(A, orc.GAUSSIAN, seed + 1000, pivot_blocks=library_blocks(256, 64))
     assert f.status == orc.OK
     assert orc.solve(f, b, refine=1).eta[-1] <= 1e-15
