@@ -22,7 +22,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "rmge_oracle.c")
 _LIB = os.path.join(_HERE, "librmge_oracle.so")
 
-NONE, GAUSSIAN, CIRCULANT, TOEPLITZ = 0, 1, 2, 3
+NONE, GAUSSIAN, CIRCULANT, TOEPLITZ, UNITARY_CIRCULANT = 0, 1, 2, 3, 4
 OK, ZERO_PIVOT, NONFINITE = 0, 4, 5
 
 
@@ -58,6 +58,8 @@ def lib() -> ctypes.CDLL:
         L.orc_param_count.restype = i64
         L.orc_multiplier_params.argtypes = [i32, i64, u64, vp]
         L.orc_multiplier_dense.argtypes = [i32, i64, vp, vp]
+        L.orc_unitary_spectrum.argtypes = [i64, u64, vp, vp]
+        L.orc_unitary_column.argtypes = [i64, vp, vp, vp, dp]
         L.orc_matmul.argtypes = [i64, i64, i64, vp, vp, vp]
         L.orc_genp.argtypes = [i64, vp, ctypes.POINTER(i64)]
         L.orc_genp_local.argtypes = [i64, i64, vp, vp, vp, ctypes.POINTER(i64)]
@@ -130,6 +132,26 @@ def multiplier_params(kind: int, n: int, seed: int) -> np.ndarray:
     if out.size:
         lib().orc_multiplier_params(kind, n, seed, _p(out))
     return out
+
+
+def unitary_spectrum(n: int, seed: int) -> np.ndarray:
+    """The unit-modulus, conjugate-symmetric spectrum u of the random unitary
+    circulant (Section 6, Example exunc, step (i)), as complex values."""
+    re = np.zeros(n, dtype=np.float64)
+    im = np.zeros(n, dtype=np.float64)
+    lib().orc_unitary_spectrum(n, seed, _p(re), _p(im))
+    return re + 1j * im
+
+
+def unitary_column(u) -> tuple[np.ndarray, float]:
+    """c = Omega^{-1} u by the plain O(n^2) sum (Example exunc, step (ii));
+    returns c and the largest imaginary part that cancelled."""
+    u = np.asarray(u, dtype=np.complex128)
+    re, im = _f64(u.real), _f64(u.imag)
+    c = np.zeros(u.size, dtype=np.float64)
+    worst = ctypes.c_double(0.0)
+    lib().orc_unitary_column(u.size, _p(re), _p(im), _p(c), ctypes.byref(worst))
+    return c, float(worst.value)
 
 
 def multiplier_dense(kind: int, n: int, params=None) -> np.ndarray:

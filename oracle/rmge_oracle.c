@@ -11,8 +11,9 @@
  * Gaussian and block Gaussian elimination", arXiv:1406.5802):
  *   1. a random multiplier H: Gaussian (Definition defrndm), circulant with a
  *      Gaussian first column (Section 6, definition of C and the "Gaussian
- *      circulant" remark after Theorem thcpw) or Toeplitz (a leading block of a
- *      larger random circulant, Section 1.1 and Remark remsrtft);
+ *      circulant" remark after Theorem thcpw), Toeplitz (a leading block of a
+ *      larger random circulant, Section 1.1 and Remark remsrtft) or a random
+ *      unitary circulant (Section 6, Example exunc; real orthogonal here);
  *   2. the preprocessed matrix M = A H (Fact faprepr, post-multiplication);
  *   3. Gaussian elimination with no pivoting on M (Section 3: the complete
  *      recursive factorization with k = 1, eq. eqgenp), stopping at the first
@@ -89,7 +90,8 @@ void orc_philox4x64_10(const uint64_t ctr[4], const uint64_t key[2], uint64_t ou
  *       z2 = sqrt(-2 ln u2) cos(2 pi u3),  z3 = sqrt(-2 ln u2) sin(2 pi u3)
  *   element e of a stream is output (e mod 4) of block e / 4.
  * Streams: 1 = Gaussian multiplier G (element i*n + j is G[i][j]),
- *          2 = circulant first column c, 3 = Toeplitz parameters tau. */
+ *          2 = circulant first column c, 3 = Toeplitz parameters tau,
+ *          4 = phases of the unitary circulant (uniforms, element j is phi_j). */
 static void orc_block(uint64_t seed, uint64_t stream, uint64_t m, uint64_t w[4]) {
     uint64_t ctr[4] = {m, stream, 0, 0};
     uint64_t key[2] = {seed, 0};
@@ -140,28 +142,91 @@ void orc_normals(uint64_t seed, uint64_t stream, int64_t count, double *out) {
 /* Multipliers, written out as dense n x n matrices.                        */
 /* ------------------------------------------------------------------------ */
 
-enum { ORC_NONE = 0, ORC_GAUSSIAN = 1, ORC_CIRCULANT = 2, ORC_TOEPLITZ = 3 };
+enum { ORC_NONE = 0, ORC_GAUSSIAN = 1, ORC_CIRCULANT = 2, ORC_TOEPLITZ = 3,
+       ORC_UNITARY_CIRCULANT = 4 };
 
-/* Number of random parameters each multiplier kind draws. */
+/* Number of parameters that define each multiplier kind (for the unitary
+ * circulant: its first column, computed from n random phases). */
 int64_t orc_param_count(int kind, int64_t n) {
     switch (kind) {
     case ORC_GAUSSIAN: return n * n;
     case ORC_CIRCULANT: return n;
     case ORC_TOEPLITZ: return 2 * n - 1;
+    case ORC_UNITARY_CIRCULANT: return n;
     default: return 0;
     }
 }
 
-/* The parameters of the multiplier: G row-major, c, or tau. */
+/* The spectrum u of the random unitary circulant (Example exunc, step (i)),
+ * made conjugate-symmetric so that the circulant is real: from n uniforms
+ * phi_0..phi_{n-1} of stream 4,
+ *   u_j = exp(2 pi i phi_j) and u_{n-j} = conj(u_j) for 0 < j < n/2,
+ *   u_0 = +1 if phi_0 < 1/2 else -1, and for even n u_{n/2} = +1 if
+ *   phi_{n/2} < 1/2 else -1 (the two entries that must be real);
+ * phi_j for j > n/2 are drawn and not used.  Every |u_j| = 1. */
+void orc_unitary_spectrum(int64_t n, uint64_t seed, double *ure, double *uim) {
+    const double two_pi = 6.283185307179586476925286766559;
+    double *phi = (double *)malloc(sizeof(double) * (size_t)n);
+    orc_uniforms(seed, (uint64_t)ORC_UNITARY_CIRCULANT, n, phi);
+    for (int64_t j = 0; j < n; ++j) { ure[j] = 0.0; uim[j] = 0.0; }
+    ure[0] = phi[0] < 0.5 ? 1.0 : -1.0;
+    for (int64_t j = 1; 2 * j < n; ++j) {
+        ure[j] = cos(two_pi * phi[j]);
+        uim[j] = sin(two_pi * phi[j]);
+        ure[n - j] = ure[j];
+        uim[n - j] = -uim[j];
+    }
+    if (n % 2 == 0 && n >= 2) ure[n / 2] = phi[n / 2] < 0.5 ? 1.0 : -1.0;
+    free(phi);
+}
+
+/* First column c = Omega^{-1} u of the unitary circulant (Example exunc,
+ * step (ii)), with Omega = (w^{jk}), w = exp(2 pi i / n) and
+ * Omega^{-1} = Omega^H / n (Section 6): c_k = (1/n) sum_j u_j w^{-jk}, by
+ * the plain O(n^2) sum.  w^{-jk} is taken as w^{-(jk mod n)} (w^n = 1), which
+ * keeps the cosine's argument below 2 pi.  The imaginary parts cancel for a
+ * conjugate-symmetric u; their largest magnitude is returned in *imag_max. */
+void orc_unitary_column(int64_t n, const double *ure, const double *uim, double *c,
+                        double *imag_max) {
+    const double two_pi = 6.283185307179586476925286766559;
+    double worst = 0.0;
+#pragma omp parallel for schedule(static) reduction(max : worst)
+    for (int64_t k = 0; k < n; ++k) {
+        double sre = 0.0, sim = 0.0;
+        for (int64_t j = 0; j < n; ++j) {
+            const int64_t t = (j * k) % n;
+            const double ang = -two_pi * (double)t / (double)n;
+            const double wr = cos(ang), wi = sin(ang);
+            sre += ure[j] * wr - uim[j] * wi;
+            sim += ure[j] * wi + uim[j] * wr;
+        }
+        c[k] = sre / (double)n;
+        if (fabs(sim / (double)n) > worst) worst = fabs(sim / (double)n);
+    }
+    if (imag_max) *imag_max = worst;
+}
+
+/* The parameters of the multiplier: G row-major, c, tau, or the unitary
+ * circulant's first column. */
 int orc_multiplier_params(int kind, int64_t n, uint64_t seed, double *p) {
-    if (kind < ORC_GAUSSIAN || kind > ORC_TOEPLITZ) return 1;
+    if (kind < ORC_GAUSSIAN || kind > ORC_UNITARY_CIRCULANT) return 1;
+    if (kind == ORC_UNITARY_CIRCULANT) {
+        double *ure = (double *)malloc(sizeof(double) * (size_t)n);
+        double *uim = (double *)malloc(sizeof(double) * (size_t)n);
+        orc_unitary_spectrum(n, seed, ure, uim);
+        orc_unitary_column(n, ure, uim, p, NULL);
+        free(ure);
+        free(uim);
+        return 0;
+    }
     orc_normals(seed, (uint64_t)kind, orc_param_count(kind, n), p);
     return 0;
 }
 
 /* Dense H from its parameters.
  *   GAUSSIAN : H = G.
- *   CIRCULANT: H[i][j] = c[(i - j) mod n]  (Section 6, definition of C).
+ *   CIRCULANT, UNITARY_CIRCULANT: H[i][j] = c[(i - j) mod n]  (Section 6,
+ *              definition of C).
  *   TOEPLITZ : H[i][j] = t_{i-j}, with tau[0..n-1] = t_0..t_{n-1} (first column)
  *              and tau[n-1+d] = t_{-d} for d = 1..n-1 (first row).  This is the
  *              leading n x n block of a circulant of size 2n-1 whose first column
@@ -175,7 +240,7 @@ int orc_multiplier_dense(int kind, int64_t n, const double *p, double *H) {
                 v = (i == j) ? 1.0 : 0.0;
             } else if (kind == ORC_GAUSSIAN) {
                 v = p[i * n + j];
-            } else if (kind == ORC_CIRCULANT) {
+            } else if (kind == ORC_CIRCULANT || kind == ORC_UNITARY_CIRCULANT) {
                 int64_t d = ((i - j) % n + n) % n;
                 v = p[d];
             } else if (kind == ORC_TOEPLITZ) {
