@@ -242,6 +242,23 @@ int64_t rmge_param_count(int32_t kind, int64_t n);
 rmge_status rmge_precondition(const double *A, int64_t n, int64_t lda, int32_t kind,
                               uint64_t seed, double *M, int64_t ldm, void *hip_stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): M = A H
+ * exactly as rmge_precondition computes it (the same kernels, so the same
+ * values), with the multiplier's workspace in a fixed library-owned device
+ * array of 8 MiB per GPU instead of an allocation.  It calls no hipMalloc,
+ * hipFree or allocating library routine.  Sizes: NONE, CIRCULANT and
+ * TOEPLITZ for every n rmge_precondition accepts (at most 0.7 MiB of
+ * workspace); GAUSSIAN only while n * n doubles fit (n <= 1024); larger
+ * sizes return RMGE_EINVAL.  The work is only enqueued on hip_stream (no
+ * synchronisation; launch errors are returned).  Every call on one GPU uses
+ * that GPU's one array, so calls whose work overlaps on one GPU (other
+ * streams or threads, before the previous call's work has finished) race and
+ * give undefined M; calls on one stream are ordered.  The array keeps the
+ * last call's contents; every value a call reads is first written by it. */
+rmge_status rmge_precondition_noalloc(const double *A, int64_t n, int64_t lda, int32_t kind,
+                                      uint64_t seed, double *M, int64_t ldm, void *hip_stream);
+
 void rmge_destroy(rmge_factors *f);
 
 const char *rmge_status_string(int32_t s);

@@ -27,7 +27,7 @@ EXPORTS = (
     "rmge_factor", "rmge_factor_ex", "rmge_factor_pivoted", "rmge_refactor", "rmge_solve",
     "rmge_solve_gmres", "rmge_solve_adjoint", "rmge_solve_adjoint_ex", "rmge_grad_A",
     "rmge_factor_stats_get", "rmge_factor_times", "rmge_factors_lu", "rmge_factors_perm", "rmge_multiplier_params",
-    "rmge_param_count", "rmge_precondition", "rmge_destroy", "rmge_status_string", "rmge_version",
+    "rmge_param_count", "rmge_precondition", "rmge_precondition_noalloc", "rmge_destroy", "rmge_status_string", "rmge_version",
 )
 
 
@@ -80,6 +80,7 @@ def lib() -> ctypes.CDLL:
     L.rmge_param_count.argtypes = [i32, i64]
     L.rmge_param_count.restype = i64
     L.rmge_precondition.argtypes = [dp, i64, i64, i32, u64, dp, i64, vp]
+    L.rmge_precondition_noalloc.argtypes = [dp, i64, i64, i32, u64, dp, i64, vp]
     L.rmge_destroy.argtypes = [vp]
     L.rmge_destroy.restype = None
     L.rmge_status_string.argtypes = [i32]
@@ -89,7 +90,7 @@ def lib() -> ctypes.CDLL:
                  "rmge_solve", "rmge_solve_gmres", "rmge_solve_adjoint", "rmge_solve_adjoint_ex",
                  "rmge_grad_A", "rmge_factor_stats_get", "rmge_factor_times", "rmge_factors_lu",
                  "rmge_factors_perm",
-                 "rmge_multiplier_params", "rmge_precondition"):
+                 "rmge_multiplier_params", "rmge_precondition", "rmge_precondition_noalloc"):
         getattr(L, name).restype = ctypes.c_int
     _lib = L
     return L
@@ -209,3 +210,9 @@ def rmge_status_string(s: int) -> str:
 
 def rmge_version() -> int:
     return int(lib().rmge_version())
+
+
+def rmge_precondition_noalloc(A: int, n: int, lda: int, kind: int, seed: int, M: int, ldm: int,
+                              stream: int) -> int:
+    return lib().rmge_precondition_noalloc(A, n, lda, kind, ctypes.c_uint64(seed & (2**64 - 1)),
+                                           M, ldm, stream)

@@ -32,6 +32,7 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <vector>
 
@@ -980,6 +981,44 @@ rmge_status check_factor_args(const double *A, int64_t n, int64_t lda, int32_t k
     return RMGE_OK;
 }
 
+// ------------------------------------------------- no-allocation scratch
+//
+// rmge_precondition_noalloc keeps the multiplier's workspace in this fixed
+// array instead of an allocation (for callers that cannot allocate: code under
+// graph capture, serving loops).  In host code `scratch` is only a stand-in
+// symbol: kernels receive the device address that hipGetSymbolAddress gives,
+// looked up once per device (each GPU holds its own copy of the array).
+constexpr int64_t kNoallocScratchDoubles = int64_t(1) << 20;  // 8 MiB
+__device__ __align__(256) double scratch[kNoallocScratchDoubles];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+double *g_scratch_ptr[kMaxDevices] = {};
+
+rmge_status noalloc_scratch(double **out) {
+    int dev = 0;
+    RMGE_TRY(hipGetDevice(&dev));
+    if (dev < 0 || dev >= kMaxDevices) return RMGE_EDEVICE;
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void *p = nullptr;
+        RMGE_TRY(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+        if (!p) return RMGE_EDEVICE;
+        g_scratch_ptr[dev] = static_cast<double *>(p);
+    }
+    *out = g_scratch_ptr[dev];
+    return RMGE_OK;
+}
+
+// Doubles of workspace rmge_precondition needs for (kind, n) with FFT period m:
+// G for a dense Gaussian multiplier; parameters, period-m kernel, half
+// spectrum and twiddles for the FFT kinds.
+int64_t noalloc_doubles(int32_t kind, int64_t n, int m) {
+    if (kind == RMGE_MULT_GAUSSIAN) return n * n;
+    if (m) return 2 * n + m + 4 * (m / 2 + 1);
+    return 0;
+}
+
 }  // namespace
 
 extern "C" {
@@ -1203,6 +1242,42 @@ rmge_status rmge_precondition(const double *A, int64_t n, int64_t lda, int32_t k
     void *tmp[] = {f.G, f.params, f.hker, f.hhat, f.tw};
     for (void *p : tmp)
         if (p) (void)hipFree(p);
+    f.lu = nullptr;
+    return from_hip(e);
+}
+
+rmge_status rmge_precondition_noalloc(const double *A, int64_t n, int64_t lda, int32_t kind,
+                                      uint64_t seed, double *M, int64_t ldm, void *hip_stream) {
+    if (!M || ldm < n || M == A) return RMGE_EINVAL;
+    rmge_status rs = check_factor_args(A, n, lda, kind, 0, RMGE_F64);
+    if (rs != RMGE_OK) return rs;
+    const int m = (kind == RMGE_MULT_CIRCULANT || kind == RMGE_MULT_TOEPLITZ) ? fft_period(kind, n)
+                                                                              : 0;
+    if (noalloc_doubles(kind, n, m) > kNoallocScratchDoubles) return RMGE_EINVAL;
+    if (!device_ok()) return RMGE_EDEVICE;
+    double *scr = nullptr;
+    if ((rs = noalloc_scratch(&scr)) != RMGE_OK) return rs;
+    rmge_factors f;
+    f.n = n;
+    f.lda = lda;
+    f.ld = ldm;
+    f.kind = kind;
+    f.seed = seed;
+    f.stream = static_cast<hipStream_t>(hip_stream);
+    f.A = A;
+    f.lu = M;
+    f.m = m;
+    if (kind == RMGE_MULT_GAUSSIAN) {
+        f.G = scr;
+    } else if (m) {  // the same carving as the handle's buffers, end to end
+        const int L = m / 2;
+        f.params = scr;
+        f.hker = f.params + 2 * n;
+        f.hhat = f.hker + m;
+        f.tw = f.hhat + 2 * (L + 1);
+    }
+    hipError_t e = m ? fft_twiddles(m, f.tw, f.stream) : hipSuccess;
+    if (e == hipSuccess) e = precondition<double>(&f);
     f.lu = nullptr;
     return from_hip(e);
 }
