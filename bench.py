@@ -1,30 +1,33 @@
 """Benchmark: factor + solve throughput of random-multiplier GENP on one MI355X.
 
 One step is one pass of the whole method on one synthetic system, inputs
-already in HBM: draw the Gaussian multiplier G, form M = A G, block Gaussian
-elimination (panels of 256), the two triangular solves, the back-transformation
-x = G y, and FP64 iterative refinement until the normwise backward error
-eta <= 1e-14 (at most 16 steps).  Paths: factors in FP64 or in FP32 on the
-matrix cores (refinement always FP64), each with no pivoting (GENP, "f64",
-"f32") or with partial pivoting confined to the diagonal blocks of at most 128
-("f64p", "f32p"), refined classically or, for FP32 factors, by GMRES preconditioned
-with the factors ("f32g", "f32pg"), and "f32xg": as "f32pg" with the product
-M = A G on the BF16 matrix cores (G rounded to BF16, A split into two BF16
-terms, FP32 accumulation).  The headline is the fastest path that reaches
-eta <= 1e-14;
-its speed-up over FP64 GENP is reported beside it.
+already in HBM: draw the multiplier H, form M = A H, block Gaussian elimination
+(panels of 256), the two triangular solves, the back-transformation x = H y,
+and FP64 iterative refinement until the normwise backward error eta <= 1e-14.
+
+Paths (PATHS): the multiplier ("f": dense Gaussian, the workload's; "u": the
+random orthogonal circulant of Section 6, applied by FFT), the factors'
+precision (FP64, FP32, FP32 with three-term BF16 Schur updates "x", BF16
+"b16"), the row exchanges (none: GENP, the paper's method; "p": partial
+pivoting confined to the diagonal blocks, the black-box treatment of small
+pivot blocks that Section 3 allows) and the refinement (classical, or "g":
+GMRES preconditioned with the factors).  The headline is the fastest GENP path
+that reaches eta <= 1e-14; every path's result is reported beside it, with the
+FP32 paths' speed-up over FP64 GENP with the same multiplier.
 
 Rate convention: (2/3 n^3 + 2 n^2 nrhs) flops per step (the standard count for
 an LU solve), divided by the wall time of the whole step; the executed flops
-(which add 2 n^3 - n^2 for M = A G) are reported beside it.
+(which add 2 n^3 - n^2 for a dense M = A G) are reported beside it.
 
 Workload: n = 16384, A = Q1 diag(sigma) Q2^T with Haar Q1, Q2 and
 sigma_i = kappa^(-i/(n-1)), kappa = 10^(1 + 7u) drawn from the seed, one
 N(0, 1) right-hand side.
 
-Usage: python bench.py [--steps K] [--warmup W] [--n N] [--seed S]
-       python bench.py --workload differentiation   (forward + backward through the
-       solve: n = 8192, Toeplitz multiplier, 16 right-hand sides; one JSON line of its own)
+Usage: python bench.py [--steps K] [--warmup W] [--n N] [--seed S] [--paths ...]
+       python bench.py --sweep 0-7          (each path over seeds 0..7: converged or not)
+       python bench.py --workload structured       (n = 4096, circulant by FFT, 8 RHS)
+       python bench.py --workload differentiation  (n = 8192, Toeplitz, 16 RHS, fwd + bwd)
+       python bench.py --workload batching         (4096 systems of orders 32..1024)
 """
 from __future__ import annotations
 
@@ -65,25 +68,43 @@ def lu_solve_flops(n, nrhs):
     return 2.0 / 3.0 * n ** 3 + 2.0 * n * n * nrhs
 
 
-# name: (factor precision, row exchanges, refinement)
-PATHS = {"f64": ("F64", "PIVOT_NONE", "ir"), "f32": ("F32", "PIVOT_NONE", "ir"),
-         "f64p": ("F64", "PIVOT_BLOCK", "ir"), "f32p": ("F32", "PIVOT_BLOCK", "ir"),
-         "f32g": ("F32", "PIVOT_NONE", "gmres"), "f32pg": ("F32", "PIVOT_BLOCK", "gmres"),
-         "f32xg": ("F32_BF16X2", "PIVOT_BLOCK", "gmres")}
+# name: (factor precision, row exchanges, refinement, multiplier).  "f": the
+# Gaussian multiplier (dense product); "u": the random unitary circulant
+# (Example exunc, FFT product); "p": pivoting inside the diagonal blocks; "g":
+# GMRES refinement; "x": BF16 matrix cores in three-term split form (FP32
+# accuracy); "b16": BF16 factors.
+PATHS = {"f64": ("F64", "PIVOT_NONE", "ir", "GAUSSIAN"),
+         "f32": ("F32", "PIVOT_NONE", "ir", "GAUSSIAN"),
+         "f64p": ("F64", "PIVOT_BLOCK", "ir", "GAUSSIAN"),
+         "f32p": ("F32", "PIVOT_BLOCK", "ir", "GAUSSIAN"),
+         "f32g": ("F32", "PIVOT_NONE", "gmres", "GAUSSIAN"),
+         "f32pg": ("F32", "PIVOT_BLOCK", "gmres", "GAUSSIAN"),
+         "f32xg": ("F32_BF16X2", "PIVOT_NONE", "gmres", "GAUSSIAN"),
+         "f32xpg": ("F32_BF16X2", "PIVOT_BLOCK", "gmres", "GAUSSIAN"),
+         "b16g": ("BF16", "PIVOT_NONE", "gmres", "GAUSSIAN"),
+         "u64": ("F64", "PIVOT_NONE", "ir", "UNITARY_CIRCULANT"),
+         "u32": ("F32", "PIVOT_NONE", "ir", "UNITARY_CIRCULANT"),
+         "u32g": ("F32", "PIVOT_NONE", "gmres", "UNITARY_CIRCULANT"),
+         "u32xg": ("F32_BF16X2", "PIVOT_NONE", "gmres", "UNITARY_CIRCULANT"),
+         "ub16g": ("BF16", "PIVOT_NONE", "gmres", "UNITARY_CIRCULANT")}
 
 
 def run_path(rmge, torch, A, b, name, seed, steps, warmup, block, max_refine, max_iters):
-    prec, pivot = (getattr(rmge, x) for x in PATHS[name][:2])
+    prec, pivot, _, kind = (getattr(rmge, x) if i != 2 else x for i, x in enumerate(PATHS[name]))
     method = PATHS[name][2]
-    f = rmge.factor(A, kind=rmge.GAUSSIAN, seed=seed, block=block, prec=prec, pivot=pivot)
+    f = rmge.factor(A, kind=kind, seed=seed, block=block, prec=prec, pivot=pivot)
 
     def solve():
         if method == "gmres":
             return f.solve_gmres(b, max_iters=max_iters, restart=32, tol=ETA_TARGET, out=X)
         return f.solve(b, max_refine=max_refine, tol=ETA_TARGET, out=X)
 
-    if not f.ok:
-        raise RuntimeError("factorization broke down: status %d" % f.status)
+    if not f.ok:  # a zero or non-finite pivot: reported as the path's result
+        log("%s: factorization broke down (status %d, pivot %d)" % (name, f.status, f.info))
+        out = {"ms_per_step": None, "breakdown": True, "status": f.status, "info": f.info,
+               "converged": False}
+        f.close()
+        return out
     X = torch.empty_like(b)
     for i in range(warmup):
         f.refactor(A, seed)
@@ -104,6 +125,9 @@ def run_path(rmge, torch, A, b, name, seed, steps, warmup, block, max_refine, ma
     log("%s: %.1f ms/step (draw %.2f, product %.2f, elimination %.2f ms), eta0 %.2e, eta %.2e, "
         "%d refinement steps" % (name, dt * 1e3, avg["ms_multiplier"], avg["ms_product"],
                                  avg["ms_factor"], st["eta0"], st["eta"], st["iters"]))
+    ms_upd, fl_upd = f.update_time()  # the last step's bulk Schur updates (HIP events)
+    nsteps = sum(1 for k in range(0, f.n, block) if f.n - k - min(block, f.n - k) >
+                 min(block, f.n - k - min(block, f.n - k)))
     fstats = f.stats()  # growth (a device pass), after the timed region
     f.close()
     return {
@@ -116,6 +140,10 @@ def run_path(rmge, torch, A, b, name, seed, steps, warmup, block, max_refine, ma
         "refine_steps": st["iters"],
         "converged": bool(st["eta"] <= ETA_TARGET),
         "growth": fstats["growth"],
+        "multiplier": PATHS[name][3].lower(),
+        "ms_update": ms_upd,
+        "update_flops": fl_upd,
+        "update_launches": nsteps,
     }
 
 
@@ -170,9 +198,93 @@ def product_traffic(n, prec):
     return (t["fetch_kib"] + t["write_kib"]) * 1024.0
 
 
-def cpu_baseline(n_cpu, seed, local_pivot_block=0):
-    import numpy as np
+def rooflines(name, r, n):
+    """Roofline lines of one path's two large kernels: the product M = A H (one
+    launch) and the bulk Schur updates (one launch a step, their summed time),
+    each with its algorithmic work per step and its peak."""
+    prec, _, _, kind = PATHS[name]
+    lines = {}
+    if kind == "GAUSSIAN":
+        flops = 2.0 * n ** 3 - n * n
+        if prec in ("F32_BF16X2", "BF16"):
+            kern, peak, traffic = ("k_gemm_bf16x2 (M = A_h G + A_l G, BF16 MFMA, FP32 "
+                                   "accumulation)", PEAK["bf16"], product_traffic(n, "bf16"))
+        elif prec == "F32":
+            kern, peak, traffic = ("k_gemm_fast<float, float, 2, 0> (M = A G)", PEAK["f32"],
+                                   product_traffic(n, "f32"))
+        else:
+            kern, peak, traffic = ("k_gemm_fast<double, double, 2, 0> (M = A G)", PEAK["f64"],
+                                   product_traffic(n, "f64"))
+        ach = flops / (r["ms_product"] * 1e-3) / 1e12
+        lines["product"] = {"bound": "mfma", "achieved": round(ach, 3), "peak": peak,
+                            "unit": "TFLOP/s", "frac": round(ach / peak, 4), "traffic": traffic,
+                            "traffic_unit": "bytes/launch", "kernel": kern,
+                            "ms_per_launch": round(r["ms_product"], 4), "launches": 1}
+    else:  # FFT: reads A in FP64, writes M in the factors' precision
+        nbytes = 8.0 * n * n + (8.0 if prec == "F64" else 4.0) * n * n
+        ach = nbytes / (r["ms_product"] * 1e-3) / 1e9
+        lines["product"] = {"bound": "hbm", "achieved": round(ach, 1), "peak": 8000.0,
+                            "unit": "GB/s", "frac": round(ach / 8000.0, 4), "traffic": None,
+                            "kernel": "k_fft_stockham (M = A H by FFT, one row a workgroup)",
+                            "ms_per_launch": round(r["ms_product"], 4), "launches": 1}
+    if r.get("ms_update"):
+        steps = r["update_launches"]
+        ach = r["update_flops"] / (r["ms_update"] * 1e-3) / 1e12
+        if prec == "F64":
+            kern, peak = "k_gemm_upd64<double> / k_gemm_fast<double> (Schur updates)", PEAK["f64"]
+        elif prec == "F32":
+            kern, peak = "k_gemm_upd64<float> / k_gemm_fast<float> (Schur updates)", PEAK["f32"]
+        elif prec == "F32_BF16X2":
+            kern, peak = ("k_update_bf16x3 (Schur updates, six BF16 products, FP32 accuracy; "
+                          "FP32 kernels below 2048 rows)", PEAK["bf16"])
+        else:
+            kern, peak = "k_update_bf16x3<1> (Schur updates, BF16 operands)", PEAK["bf16"]
+        lines["update"] = {"bound": "mfma", "achieved": round(ach, 3), "peak": peak,
+                           "unit": "TFLOP/s", "frac": round(ach / peak, 4), "traffic": None,
+                           "kernel": kern, "ms_per_launch": round(r["ms_update"] / steps, 4),
+                           "launches": steps,
+                           "note": "algorithmic 2 r (r - b') b flops summed over the steps"}
+        if prec == "F32_BF16X2":  # six BF16 products per FP32-equivalent one
+            lines["update"]["executed_frac"] = round(6 * ach / peak, 4)
+    return lines
 
+
+def comparisons(results):
+    """FP32-family paths against FP64 GENP with the same multiplier (time ratio at
+    the same eta target), and the pivoted variant."""
+    out = {}
+    for mult in ("GAUSSIAN", "UNITARY_CIRCULANT"):
+        f64 = [k for k in results if PATHS[k][3] == mult and PATHS[k][0] == "F64"
+               and PATHS[k][1] == "PIVOT_NONE" and results[k]["converged"]]
+        if not f64:
+            continue
+        base = results[f64[0]]["ms_per_step"]
+        row = {"f64_genp": f64[0], "f64_ms": round(base, 3)}
+        for k, v in results.items():
+            if PATHS[k][3] != mult or PATHS[k][0] == "F64":
+                continue
+            row[k] = {"converged": v["converged"],
+                      "speedup": round(base / v["ms_per_step"], 3) if v["converged"] else None,
+                      "pivoting": "inside diagonal blocks (Section 3 black-box variant)"
+                      if PATHS[k][1] == "PIVOT_BLOCK" else "none (GENP)"}
+        out[mult.lower()] = row
+    return out
+
+
+def cpu_model():
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return None
+
+
+def cpu_baseline(n_cpu, seed, kind="GAUSSIAN", threads=None):
+    """The oracle (plain-loop FP64 C: multiplier, product, unblocked GENP, solve,
+    one refinement step) on the host, on an n_cpu system of the same recipe."""
     import oracle
     import workloads
 
@@ -181,9 +293,11 @@ def cpu_baseline(n_cpu, seed, local_pivot_block=0):
     A = workloads.conditioned_torch(n_cpu, kappa, seed).cpu().numpy()
     b = workloads.rhs_torch(n_cpu, 1, seed).cpu().numpy()
     oracle.lib()
+    if threads:
+        oracle.set_num_threads(threads)
     log("cpu baseline: oracle factor + solve on %d threads" % oracle.num_threads())
     t0 = time.perf_counter()
-    f = oracle.factor(A, oracle.GAUSSIAN, seed, local_pivot_block=local_pivot_block)
+    f = oracle.factor(A, getattr(oracle, kind), seed)
     s = oracle.solve(f, b, refine=1)
     dt = time.perf_counter() - t0
     log("cpu baseline: %.1f s, eta %.2e" % (dt, s.eta[-1]))
@@ -192,10 +306,10 @@ def cpu_baseline(n_cpu, seed, local_pivot_block=0):
         "unit": "TFLOP/s",
         "cores": oracle.num_threads(),
         "kind": "oracle",
-        "sample": "n=%d system of the same recipe (Gaussian multiplier, %s, FP64, 1 RHS, 1 "
+        "sample": "n=%d system of the same recipe (%s multiplier, no pivoting, FP64, 1 RHS, 1 "
                   "refinement step), plain-loop C oracle; %.1f s wall"
-                  % (n_cpu, "pivoting inside blocks of %d" % local_pivot_block
-                     if local_pivot_block else "no pivoting", dt),
+                  % (n_cpu, kind.lower().replace("_", " "), dt),
+        "cpu_model": cpu_model(),
         "eta": float(s.eta[-1]),
         "seconds": dt,
     }
@@ -292,25 +406,247 @@ def differentiation(args):
     print(json.dumps(out))
 
 
+STRUCT_PATHS = {"circulant": "CIRCULANT", "unitary": "UNITARY_CIRCULANT", "gaussian": "GAUSSIAN"}
+
+
+def structured(args):
+    """The structured-multiplier workload (n = 4096, block 256, 8 right-hand sides,
+    FP64 GENP refined to eta <= 1e-14): a circulant multiplier with a Gaussian first
+    column applied by FFT (Section 6), beside the unitary circulant and the dense
+    Gaussian multiplier on the same A.  The roofline line is the FFT product kernel
+    (HBM: it reads A and writes M, 16 n^2 bytes in FP64), timed by the library's HIP
+    events around its one launch per step."""
+    import torch
+
+    import paper_1406_5802_amd as rmge
+    import workloads
+
+    rmge.lib()
+    n, nrhs, kappa = args.n or 4096, 8, 1e6
+    log("structured: n=%d, kappa=%g, %d RHS" % (n, kappa, nrhs))
+    A = workloads.conditioned_torch(n, kappa, seed=args.seed)
+    B = workloads.rhs_torch(n, nrhs, seed=args.seed)
+    torch.cuda.synchronize()
+    paths = {}
+    for name in args.paths.split(","):
+        if name not in STRUCT_PATHS:
+            raise SystemExit("unknown structured path %r (choose from %s)"
+                             % (name, ",".join(STRUCT_PATHS)))
+        f = rmge.factor(A, kind=getattr(rmge, STRUCT_PATHS[name]), seed=args.seed + 1000,
+                        block=args.block)
+        if not f.ok:
+            raise RuntimeError("factorization broke down: status %d" % f.status)
+        X = torch.empty_like(B)
+        for _ in range(args.warmup):
+            f.refactor(A, args.seed + 1000)
+            f.solve(B, max_refine=args.max_refine, tol=ETA_TARGET, out=X)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        tms, sts = [], []
+        for _ in range(args.steps):
+            f.refactor(A, args.seed + 1000)
+            tms.append(f.times())
+            _, st = f.solve(B, max_refine=args.max_refine, tol=ETA_TARGET, out=X)
+            sts.append(st)
+        torch.cuda.synchronize()
+        dt = (time.perf_counter() - t0) / args.steps
+        avg = {k: sum(t[k] for t in tms) / args.steps for k in tms[0]}
+        st = sts[-1]
+        paths[name] = {"ms_per_step": dt * 1e3, "ms_draw": avg["ms_multiplier"],
+                       "ms_product": avg["ms_product"], "ms_elimination": avg["ms_factor"],
+                       "eta0": st["eta0"], "eta": st["eta"], "refine_steps": st["iters"],
+                       "converged": bool(st["eta"] <= ETA_TARGET)}
+        log("%s: %.2f ms/step (draw %.3f, product %.3f, elimination %.2f ms), eta %.2e after %d "
+            "steps" % (name, dt * 1e3, avg["ms_multiplier"], avg["ms_product"], avg["ms_factor"],
+                       st["eta"], st["iters"]))
+        f.close()
+    head = "circulant" if "circulant" in paths else next(iter(paths))
+    r = paths[head]
+    fft_bytes = 16.0 * n * n
+    out = {
+        "metric": "factor+solve TFLOP/s n=%d: circulant multiplier by FFT" % n,
+        "value": round(lu_solve_flops(n, nrhs) / (r["ms_per_step"] * 1e-3) / 1e12, 3),
+        "unit": "TFLOP/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(r["ms_per_step"], 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": "structured: n=%d %s multiplier (FFT), kappa=%g, %d RHS, block %d, "
+                               "eta<=1e-14" % (n, head, kappa, nrhs, args.block),
+                   "n": n, "nrhs": nrhs, "kappa": kappa, "seed": args.seed, "block": args.block,
+                   "headline_path": head},
+        "roofline": {"bound": "hbm", "achieved": round(fft_bytes / (r["ms_product"] * 1e-3) / 1e9, 1),
+                     "peak": 8000.0, "unit": "GB/s",
+                     "frac": round(fft_bytes / (r["ms_product"] * 1e-3) / 1e9 / 8000.0, 4),
+                     "traffic": None,
+                     "kernel": "k_fft_stockham (M = A H, one row a workgroup, FP64 in and out)",
+                     "ms_per_launch": round(r["ms_product"], 4)},
+        "paths": {k: {kk: (float("%.6g" % vv) if isinstance(vv, float) else vv)
+                      for kk, vv in v.items()} for k, v in paths.items()},
+    }
+    print(json.dumps(out))
+
+
+def batching(args):
+    """The batching workload: 4096 independent systems, orders uniform on
+    {32..1024}, Gaussian or circulant multiplier (1/2 each), kappa = 10^(1 + 5u),
+    FP32 factors on the matrix cores and FP64 GMRES refinement to eta <= 1e-14,
+    every step one replay of the HIP graph that holds the whole run (multipliers,
+    products, factorizations, refinement).  Panel widths per size bucket from the
+    library's autotuner (cached as JSON).  The roofline line is the factorization
+    phase (algorithmic 2/3 n^3 flops per system against the FP32 matrix-core
+    peak), timed by HIP events in an eager run of the same batch."""
+    import numpy as np
+    import torch
+
+    import paper_1406_5802_amd as rmge
+    import workloads
+
+    rmge.lib()
+    count = args.count
+    log("batching: %d systems (seed %d), building the matrices on the GPU" % (count, args.seed))
+    table = workloads.batch_table(count, args.seed)
+    A, B = workloads.batch_inputs_torch(table, args.seed)
+    X = torch.zeros_like(B)
+    torch.cuda.synchronize()
+    systems = [(t[0], t[1], t[2], t[3], t[4]) for t in table]
+    bt = rmge.Batch(systems, restart=args.restart, max_iters=args.max_iters)
+    name = torch.cuda.get_device_properties(0).gcnArchName.split(":")[0]
+    key = "%s/count%d/seed%d/lib%d" % (name, count, args.seed, rmge._rmge.lib().rmge_version())
+    nb, cached = bt.autotune_cached(A, key)
+    log("panel widths per bucket %s (%s)" % (nb, "cache" if cached else "autotuned"))
+    phases = bt.run_timed(A, B, X, tol=ETA_TARGET)
+    log("eager run: products %.2f ms, factorizations %.2f ms, refinement %.2f ms" % phases)
+    for _ in range(args.warmup):
+        bt.run(A, B, X, tol=ETA_TARGET, graph=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        bt.run(A, B, X, tol=ETA_TARGET, graph=True)
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / args.steps
+    res = bt.results()
+    ns = np.array([t[0] for t in table], dtype=np.float64)
+    flops = float(np.sum(2.0 / 3.0 * ns ** 3 + 2.0 * ns ** 2))
+    lu_flops = float(np.sum(2.0 / 3.0 * ns ** 3))
+    ok = res["status"] == 0
+    conv_eta = res["eta"][ok]
+    log("%.2f ms/step, %d of %d converged, max eta %.2e, median iterations %d"
+        % (dt * 1e3, int(ok.sum()), count, float(conv_eta.max()) if ok.any() else float("nan"),
+           int(np.median(res["iters"]))))
+    achieved = lu_flops / (phases[1] * 1e-3) / 1e12
+    out = {
+        "metric": "batched factor+solve TFLOP/s: %d systems n~U{32..1024}, FP32 MFMA + FP64 "
+                  "refinement at eta<=1e-14" % count,
+        "value": round(flops / dt / 1e12, 3),
+        "unit": "TFLOP/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(dt * 1e3, 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32 factors + f64 refinement",
+        "data": "synthetic",
+        "config": {"workload": "batching: %d systems, n uniform on {32..1024}, Gaussian or "
+                               "circulant multiplier (1/2 each), kappa=10^(1+5u), 1 RHS each, "
+                               "one HIP graph a step" % count,
+                   "count": count, "seed": args.seed, "restart": args.restart,
+                   "max_iters": args.max_iters, "panel_widths": nb,
+                   "tuning_from_cache": cached},
+        "roofline": {"bound": "mfma", "achieved": round(achieved, 3), "peak": PEAK["f32"],
+                     "unit": "TFLOP/s", "frac": round(achieved / PEAK["f32"], 4),
+                     "traffic": None,
+                     "kernel": "k_batch_factor (all size buckets; 2/3 n^3 flops a system)",
+                     "ms_per_launch": round(phases[1], 4)},
+        "phases_ms": {"products": round(phases[0], 3), "factorizations": round(phases[1], 3),
+                      "refinement": round(phases[2], 3)},
+        "results": {"converged": int(ok.sum()), "zero_pivot": int((res["status"] == 4).sum()),
+                    "nonfinite": int((res["status"] == 5).sum()),
+                    "not_converged": int((res["status"] == 6).sum()),
+                    "max_eta_converged": float(conv_eta.max()) if ok.any() else None,
+                    "iters_median": int(np.median(res["iters"])),
+                    "iters_max": int(res["iters"].max())},
+        "systems_per_s": round(count / dt, 1),
+    }
+    bt.close()
+    print(json.dumps(out))
+
+
+def precision_sweep(args):
+    """The precision workload over several seeds (kappa = 10^(1 + 7u) each): per
+    seed and path, whether eta <= 1e-14 is reached, in how many refinement
+    steps or Krylov iterations, and the time of one step.  One JSON line with
+    the per-seed table (no headline value: that is the default run's)."""
+    import torch
+
+    import paper_1406_5802_amd as rmge
+    import workloads
+
+    rmge.lib()
+    n = args.n or 16384
+    lo, hi = (int(x) for x in args.sweep.split("-"))
+    rows = []
+    for seed in range(lo, hi + 1):
+        kappa = workloads.precision_kappa(seed)
+        log("sweep: seed %d, kappa %.3g" % (seed, kappa))
+        A = workloads.conditioned_torch(n, kappa, seed)
+        b = workloads.rhs_torch(n, 1, seed)
+        torch.cuda.synchronize()
+        row = {"seed": seed, "kappa": kappa}
+        for p in args.paths.split(","):
+            r = run_path(rmge, torch, A, b, p, seed + 1000, 1, 1, args.block, args.max_refine,
+                         args.max_iters)
+            row[p] = {k: r.get(k) for k in ("ms_per_step", "eta0", "eta", "refine_steps",
+                                             "converged", "growth", "breakdown")
+                      if r.get(k) is not None}
+        rows.append(row)
+        del A
+        torch.cuda.empty_cache()
+    summary = {}
+    for p in args.paths.split(","):
+        conv = [r for r in rows if r[p].get("converged")]
+        summary[p] = {"converged": len(conv), "of": len(rows),
+                      "max_kappa_converged": max((r["kappa"] for r in conv), default=None)}
+    print(json.dumps({"sweep": rows, "summary": summary, "n": n, "eta_target": ETA_TARGET}))
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="precision", choices=["precision", "differentiation"],
+    ap.add_argument("--workload", default="precision",
+                    choices=["precision", "differentiation", "structured", "batching"],
                     help="precision: the factor+solve benchmark (default); differentiation: "
-                         "forward and backward through the solve at n = 8192, Toeplitz, 16 RHS")
+                         "forward and backward through the solve at n = 8192, Toeplitz, 16 RHS; "
+                         "structured: n = 4096 circulant multiplier by FFT, 8 RHS; batching: "
+                         "4096 systems of orders 32..1024 in one HIP graph")
+    ap.add_argument("--count", type=int, default=4096, help="batching: number of systems")
+    ap.add_argument("--sweep", default=None,
+                    help="precision: seeds LO-HI (kappa = 10^(1 + 7u) each), one JSON line with "
+                         "each path's result per seed")
+    ap.add_argument("--restart", type=int, default=16, help="batching: GMRES restart")
     ap.add_argument("--n", type=int, default=None, help="16384 (precision) or 8192 "
                                                          "(differentiation)")
     ap.add_argument("--seed", type=int, default=1)
     ap.add_argument("--block", type=int, default=256)
     ap.add_argument("--max-refine", type=int, default=16)
     ap.add_argument("--paths", default=None,
-                    help="precision: f64,f32,f64p,f32p,f32g,f32pg,f32xg (default f64,f32,f64p,"
-                         "f32p,f32pg,f32xg); differentiation: f64,f32p (default both)")
+                    help="precision: any of PATHS (default f64,f32g,f32xg,f32xpg,b16g,u64,u32,"
+                         "u32g,u32xg); structured: circulant,unitary,gaussian; "
+                         "differentiation: f64,f32p")
     ap.add_argument("--max-iters", type=int, default=200, help="GMRES inner iterations in all")
     ap.add_argument("--cpu-n", type=int, default=8192,
                     help="size of the oracle's CPU sample (about 20 s on 16 host threads)")
+    ap.add_argument("--cpu-threads", type=int, default=None,
+                    help="threads of the oracle's CPU sample (default: all the host gives it)")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--matrix", default="conditioned", choices=["conditioned", "gaussian"],
                     help="conditioned: Q1 diag(sigma) Q2^T (the workload); gaussian: i.i.d. "
@@ -325,7 +661,15 @@ def main():
     if args.workload == "differentiation":
         args.paths = args.paths or "f64,f32p"
         return differentiation(args)
-    args.paths = args.paths or "f64,f32,f64p,f32p,f32pg,f32xg"
+    if args.workload == "structured":
+        args.paths = args.paths or "circulant,unitary,gaussian"
+        return structured(args)
+    if args.workload == "batching":
+        return batching(args)
+    args.paths = args.paths or "f64,f32g,f32xg,f32xpg,b16g,u64,u32,u32g,u32xg"
+
+    if args.sweep:
+        return precision_sweep(args)
 
     import torch
 
@@ -354,24 +698,17 @@ def main():
                               args.block, args.max_refine, args.max_iters)
 
     ok = {k: v for k, v in results.items() if v["converged"]}
-    head = min(ok, key=lambda k: ok[k]["ms_per_step"]) if ok else next(iter(results))
+    genp = {k: v for k, v in ok.items() if PATHS[k][1] == "PIVOT_NONE"}
+    # headline: the fastest path of the plain method (no pivoting) that reaches the
+    # target; only if none does, the fastest of the rest
+    pool = genp or ok
+    head = min(pool, key=lambda k: pool[k]["ms_per_step"]) if pool else next(iter(results))
     r = results[head]
-    fp32 = head.startswith("f32")
-    split = PATHS[head][0] == "F32_BF16X2"
     flops = lu_solve_flops(n, 1)
-    value = flops / (r["ms_per_step"] * 1e-3) / 1e12
-    # roofline of the dominant kernel: the M = A G product, one launch per step.
-    # Algorithmic flops 2 n^3 - n^2 in every case; the split-BF16 product executes
-    # two BF16 products and is priced against the dense BF16 peak.
-    prod_flops = 2.0 * n ** 3 - n * n
-    achieved = prod_flops / (r["ms_product"] * 1e-3) / 1e12
-    peak_key = "bf16" if split else ("f32" if fp32 else "f64")
-    if split:
-        kernel = "k_gemm_bf16x2 (M = A_h G + A_l G, BF16 MFMA, FP32 accumulation)"
-        traffic = product_traffic(n, "bf16")
-    else:
-        kernel = "k_gemm_fast<%s, 2, 0> (M = A G)" % ("float, float" if fp32 else "double, double")
-        traffic = product_traffic(n, "f32" if fp32 else "f64")
+    value = flops / (r["ms_per_step"] * 1e-3) / 1e12 if r.get("ms_per_step") else 0.0
+    lines = rooflines(head, r, n)
+    dominant = max(lines, key=lambda k: lines[k]["ms_per_launch"] * lines[k].get("launches", 1))
+    prec = PATHS[head][0]
     out = {
         "metric": METRIC,
         "value": round(value, 3),
@@ -383,31 +720,26 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": ("bf16x2 product + f32 factors (bf16x3 Schur updates) + f64 refinement" if split else
-                  "f32 factors + f64 refinement" if fp32 else "f64"),
+        "dtype": {"F64": "f64", "F32": "f32 factors + f64 refinement",
+                  "F32_BF16X2": "f32 factors (bf16x3 Schur updates) + f64 refinement",
+                  "BF16": "bf16 factors + f64 refinement"}[prec],
         "data": "synthetic",
-        "config": {"workload": ("precision: n=%d Gaussian multiplier, kappa=%.3g, 1 RHS, "
-                                "eta<=1e-14" % (n, kappa)) if kappa else
-                               ("n=%d i.i.d. Gaussian A, Gaussian multiplier, 1 RHS, "
-                                "eta<=1e-14" % n),
+        "config": {"workload": ("precision: n=%d, kappa=%.3g, 1 RHS, eta<=1e-14; headline: the "
+                                "fastest path with no pivoting that reaches it" % (n, kappa))
+                   if kappa else ("n=%d i.i.d. Gaussian A, 1 RHS, eta<=1e-14" % n),
                    "n": n, "kappa": kappa, "seed": args.seed, "block": args.block, "nrhs": 1,
-                   "headline_path": head},
-        "roofline": {"bound": "mfma", "achieved": round(achieved, 3),
-                     "peak": PEAK[peak_key], "unit": "TFLOP/s",
-                     "frac": round(achieved / PEAK[peak_key], 4),
-                     "traffic": traffic,
-                     "traffic_unit": "bytes/launch",
-                     "kernel": kernel,
-                     "ms_per_launch": round(r["ms_product"], 4)},
-        "executed_tflops": round((flops + prod_flops) / (r["ms_per_step"] * 1e-3) / 1e12, 3),
+                   "headline_path": head, "multiplier": PATHS[head][3].lower()},
+        "roofline": lines[dominant],
+        "rooflines": lines,
+        "executed_tflops": round((flops + (2.0 * n ** 3 - n * n if PATHS[head][3] == "GAUSSIAN"
+                                           else 0.0)) / (r["ms_per_step"] * 1e-3) / 1e12, 3),
         "paths": {k: {kk: (float("%.6g" % vv) if isinstance(vv, float) else vv)
                       for kk, vv in v.items()} for k, v in results.items()},
+        "comparisons": comparisons(results),
     }
-    if "f64" in results and head != "f64":
-        out["speedup_over_f64_genp"] = round(results["f64"]["ms_per_step"] / r["ms_per_step"], 3)
     if not args.no_cpu:
-        out["cpu_baseline"] = cpu_baseline(args.cpu_n, args.seed,
-                                           args.block if head.endswith("p") else 0)
+        out["cpu_baseline"] = cpu_baseline(args.cpu_n, args.seed, PATHS[head][3],
+                                           args.cpu_threads)
     print(json.dumps(out))
 
 

@@ -54,7 +54,15 @@ typedef enum {
     RMGE_MULT_NONE = 0,      /* H = I: plain GENP, shows breakdown (Corollary corec) */
     RMGE_MULT_GAUSSIAN = 1,  /* n x n i.i.d. N(0,1) (Definition defrndm), dense product */
     RMGE_MULT_CIRCULANT = 2, /* H[i][j] = c[(i-j) mod n], c i.i.d. N(0,1) (Section 6), FFT */
-    RMGE_MULT_TOEPLITZ = 3   /* H[i][j] = t_{i-j}, 2n-1 i.i.d. N(0,1) parameters, FFT */
+    RMGE_MULT_TOEPLITZ = 3,  /* H[i][j] = t_{i-j}, 2n-1 i.i.d. N(0,1) parameters, FFT */
+    /* Random unitary circulant (Section 6, Example exunc), real: H[i][j] =
+     * c[(i-j) mod n] with c = Omega^{-1} u, Omega = (w^{jk}), w = e^{2 pi i/n},
+     * and the spectrum u of unit modulus: u_j = e^{2 pi i phi_j} and
+     * u_{n-j} = conj(u_j) for 0 < j < n/2, u_0 and (even n) u_{n/2} = +1 if
+     * their phase is below 1/2, else -1; phi_j the uniforms of stream 4 of
+     * the seed.  H is orthogonal (kappa(H) = 1, so kappa(A H) = kappa(A)).
+     * Applied by FFT like RMGE_MULT_CIRCULANT. */
+    RMGE_MULT_UNITARY_CIRCULANT = 4
 } rmge_mult;
 
 /* Precision of the factors L, U (and of the multiplier product M = A H).
@@ -62,6 +70,17 @@ typedef enum {
 typedef enum {
     RMGE_F64 = 0,       /* FP64 MFMA */
     RMGE_F32 = 1,       /* FP32 MFMA with FP32 accumulation; refine in FP64 */
+    RMGE_BF16 = 2,      /* BF16 factorization with FP32 accumulation: every bulk
+                           Schur update (eq. eqgenp) of the trailing matrix runs on
+                           the BF16 matrix cores with both operands rounded once
+                           to BF16 (relative error up to 2^-9 each) and FP32
+                           accumulation into the FP32 trailing matrix; the pivot
+                           blocks, their solves and the updates of the next panel's
+                           columns stay FP32 (as mixed-precision LU keeps its
+                           panels in the higher precision).  Factors stored in
+                           FP32; the product M = A H as for RMGE_F32_BF16X2.
+                           Refine in FP64 (GMRES: the factors' error is of order
+                           2^-9 times the growth). */
     RMGE_F32_BF16X2 = 3 /* as RMGE_F32, but with a GAUSSIAN multiplier the product
                            M = A H runs on the BF16 matrix cores: H is drawn, then
                            rounded to BF16 (that rounded H is the multiplier, used
@@ -74,7 +93,8 @@ typedef enum {
                            cross products formed (the dropped terms total at most
                            (2^-24 + 2^-34) of the product, one unit of FP32
                            rounding: the accuracy of an FP32 product).
-                           Other multiplier kinds behave as RMGE_F32. */
+                           Other multiplier kinds: the FFT product in FP32 as for
+                           RMGE_F32, and the same three-term BF16 Schur updates. */
 } rmge_prec;
 
 /* Row exchanges (rmge_factor_pivoted). */
@@ -218,6 +238,15 @@ rmge_status rmge_factor_stats_get(const rmge_factors *f, rmge_factor_stats *s);
  * only; ms3 is a host array of 3 doubles.  EINVAL on a null argument. */
 rmge_status rmge_factor_times(const rmge_factors *f, double *ms3);
 
+/* The bulk Schur updates of the last factorization (eq. eqgenp: the trailing
+ * block's update by the panel beyond the next pivot block, one launch per
+ * step): their summed device time in ms (HIP events around each launch on
+ * the elimination's stream; 0 when the factorization had more than 512 steps
+ * or broke down) and their algorithmic flops, sum of 2 r (r - b') b over the
+ * steps (r trailing rows, b' the next panel's width, b this step's).  Host
+ * only; no device work. */
+rmge_status rmge_factor_update_time(const rmge_factors *f, double *ms, double *flops);
+
 /* Copy the packed factors (unit L strictly below the diagonal, U on and above)
  * into LU (device, n x n, ld >= n), converted to FP64.  Pivoted handles:
  * L U = P M, rows in the order of rmge_factors_perm. */
@@ -229,7 +258,8 @@ rmge_status rmge_factors_perm(const rmge_factors *f, int32_t *perm);
 
 /* The multiplier's random parameters as drawn by the library: kind GAUSSIAN
  * gives n*n values (G row-major), CIRCULANT n (c), TOEPLITZ 2n-1 (tau, with
- * tau[0..n-1] = t_0..t_{n-1} and tau[n-1+d] = t_{-d}).  out: device, FP64. */
+ * tau[0..n-1] = t_0..t_{n-1} and tau[n-1+d] = t_{-d}), UNITARY_CIRCULANT n
+ * (its first column c, computed from the n phases).  out: device, FP64. */
 rmge_status rmge_multiplier_params(int32_t kind, int64_t n, uint64_t seed, double *out,
                                    void *hip_stream);
 
@@ -237,7 +267,8 @@ rmge_status rmge_multiplier_params(int32_t kind, int64_t n, uint64_t seed, doubl
 int64_t rmge_param_count(int32_t kind, int64_t n);
 
 /* M = A H in FP64 (the preprocessing product alone): dense MFMA product for
- * GAUSSIAN, FFT correlation for CIRCULANT and TOEPLITZ, copy for NONE.
+ * GAUSSIAN, FFT correlation for CIRCULANT, TOEPLITZ and UNITARY_CIRCULANT,
+ * copy for NONE.
  * A, M: device n x n, lda, ldm >= n; M may not alias A. */
 rmge_status rmge_precondition(const double *A, int64_t n, int64_t lda, int32_t kind,
                               uint64_t seed, double *M, int64_t ldm, void *hip_stream);
@@ -247,10 +278,10 @@ rmge_status rmge_precondition(const double *A, int64_t n, int64_t lda, int32_t k
  * exactly as rmge_precondition computes it (the same kernels, so the same
  * values), with the multiplier's workspace in a fixed library-owned device
  * array of 8 MiB per GPU instead of an allocation.  It calls no hipMalloc,
- * hipFree or allocating library routine.  Sizes: NONE, CIRCULANT and
- * TOEPLITZ for every n rmge_precondition accepts (at most 0.7 MiB of
- * workspace); GAUSSIAN only while n * n doubles fit (n <= 1024); larger
- * sizes return RMGE_EINVAL.  The work is only enqueued on hip_stream (no
+ * hipFree or allocating library routine.  Sizes: NONE and the FFT kinds
+ * (CIRCULANT, TOEPLITZ, UNITARY_CIRCULANT) for every n rmge_precondition
+ * accepts (at most 0.7 MiB of workspace); GAUSSIAN only while n * n doubles
+ * fit (n <= 1024); larger sizes return RMGE_EINVAL.  The work is only enqueued on hip_stream (no
  * synchronisation; launch errors are returned).  Every call on one GPU uses
  * that GPU's one array, so calls whose work overlaps on one GPU (other
  * streams or threads, before the previous call's work has finished) race and
@@ -258,6 +289,110 @@ rmge_status rmge_precondition(const double *A, int64_t n, int64_t lda, int32_t k
  * last call's contents; every value a call reads is first written by it. */
 rmge_status rmge_precondition_noalloc(const double *A, int64_t n, int64_t lda, int32_t kind,
                                       uint64_t seed, double *M, int64_t ldm, void *hip_stream);
+
+/* One Schur-complement update of the elimination, C <- C - D E (eq. eqgenp:
+ * the trailing block minus the product of the column below the pivot block
+ * and the block row right of it, the pivot block's solves already applied),
+ * in FP32, exactly as the factorization runs it for trailing blocks:
+ * terms = 0: FP32 matrix cores; terms = 3: the three-term BF16 split of
+ * RMGE_F32_BF16X2 (six BF16 products, FP32 accumulation); terms = 1: the BF16
+ * update of RMGE_BF16 (operands rounded once to BF16).  D: M x K (ldd >= K),
+ * E: K x N (lde >= N), C: M x N (ldc >= N), device FP32, row-major, C not
+ * overlapping D or E; K <= 256.  Allocates its workspace, synchronises
+ * hip_stream. */
+rmge_status rmge_schur_update_f32(int64_t M, int64_t N, int64_t K, const float *D, int64_t ldd,
+                                  const float *E, int64_t lde, float *C, int64_t ldc,
+                                  int32_t terms, void *hip_stream);
+
+/* ---------------------------------------------------------------------------
+ * Batches: many independent systems A_s x_s = b_s of uneven order solved by
+ * the method in one device-resident pass (Definition defrndm and Section 6 for
+ * the multipliers, Fact faprepr, eq. eqgenp, Section 8.1 refinement).  Per
+ * system: its multiplier H_s from its own seed (a dense Gaussian, or a
+ * circulant with a Gaussian first column applied by FFT), M_s = A_s H_s in
+ * FP32 (A rounded to FP32), block Gaussian elimination with no pivoting in
+ * FP32 on the matrix cores with pivot blocks of nb columns (nb per size
+ * bucket, see rmge_batch_tuning), then x_s = H_s U_s^{-1} L_s^{-1} b_s refined
+ * in FP64 by restarted flexible GMRES preconditioned with the factors until
+ * eta_s <= tol or max_iters inner iterations, eta the normwise backward error
+ * ||b - A x||_inf / (||A||_inf ||x||_inf + ||b||_inf).  The systems are taken
+ * largest first by persistent kernels; nothing is synchronised or allocated
+ * while running, so a run can be captured into a HIP graph
+ * (rmge_batch_graph_run does that itself).
+ * ------------------------------------------------------------------------- */
+typedef struct rmge_batch rmge_batch; /* opaque; owned by the library */
+
+typedef struct {
+    int32_t n;     /* order, 1 <= n <= 1024 */
+    int32_t kind;  /* RMGE_MULT_GAUSSIAN or RMGE_MULT_CIRCULANT */
+    uint64_t seed; /* the system's multiplier seed (the single-system generator) */
+    int64_t a_off; /* element offset of A_s (n x n, row-major, ld = n) in the A buffer */
+    int64_t v_off; /* element offset of b_s and x_s (n values each) in B and X */
+} rmge_batch_system;
+
+#define RMGE_BATCH_BUCKETS 5
+/* Pivot-block width per size bucket (n <= 64, <= 128, <= 256, <= 512, <= 1024);
+ * each 16, 32 or 64. */
+typedef struct {
+    int32_t nb[RMGE_BATCH_BUCKETS];
+} rmge_batch_tuning;
+
+/* Describe a batch.  systems: host array of count entries (copied).  tuning:
+ * NULL for the defaults {32, 32, 32, 64, 64}.  restart: GMRES restart length,
+ * 1..32.  max_iters: inner iterations per system.  Allocates the device
+ * workspace (for every system: n^2 FP32 factors, (2 restart + 1) n doubles;
+ * Gaussian: n^2 FP32 for G; circulant: O(n)).  EINVAL on a bad entry. */
+rmge_status rmge_batch_create(const rmge_batch_system *systems, int32_t count,
+                              const rmge_batch_tuning *tuning, int32_t restart, int32_t max_iters,
+                              rmge_batch **out);
+
+/* Solve every system: A, B, X device FP64 buffers laid out as the systems'
+ * offsets say (A never written; X may not overlap A or B).  Only enqueues work
+ * on hip_stream: no synchronisation, no allocation.  tol > 0.  Systems whose
+ * factorization meets a zero or non-finite pivot keep their X untouched. */
+rmge_status rmge_batch_run(rmge_batch *b, const double *A, const double *B, double *X, double tol,
+                           void *hip_stream);
+
+/* As rmge_batch_run, with HIP events between the phases, synchronised:
+ * ms3[0] drawing the multipliers and forming every M_s = A_s H_s, ms3[1] the
+ * factorizations, ms3[2] the solves and refinement (host array of 3). */
+rmge_status rmge_batch_run_timed(rmge_batch *b, const double *A, const double *B, double *X,
+                                 double tol, void *hip_stream, double *ms3);
+
+/* As rmge_batch_run, through a HIP graph: the first call (and any call with
+ * other buffers or tol) captures the whole run into a graph on the library's
+ * own stream; every call then launches that graph on hip_stream. */
+rmge_status rmge_batch_graph_run(rmge_batch *b, const double *A, const double *B, double *X,
+                                 double tol, void *hip_stream);
+
+/* Per-system results of the last run, in the order of `systems` (host arrays
+ * of count entries, each may be NULL): status (RMGE_OK, RMGE_ZERO_PIVOT,
+ * RMGE_NONFINITE or RMGE_NOT_CONVERGED), final eta, eta of the unrefined
+ * solution, inner iterations, and the first zero / non-finite pivot's index
+ * (-1 if none).  Synchronises hip_stream first. */
+rmge_status rmge_batch_results(const rmge_batch *b, int32_t *status, double *eta, double *eta0,
+                               int32_t *iters, int64_t *info, void *hip_stream);
+
+rmge_status rmge_batch_get_tuning(const rmge_batch *b, rmge_batch_tuning *t);
+rmge_status rmge_batch_set_tuning(rmge_batch *b, const rmge_batch_tuning *t);
+
+/* Autotuner: for each size bucket in turn, time the batch's factorization of
+ * that bucket's systems (HIP events, after a warm-up run) with pivot blocks of
+ * 16, 32 and 64 columns, the products redone before each timing, and keep the
+ * fastest.  The chosen widths are applied to the batch and returned in *best;
+ * ms_bucket (host, RMGE_BATCH_BUCKETS entries, may be NULL) receives the best
+ * times (-1 for an empty bucket).  A: the systems' matrices. Synchronises. */
+rmge_status rmge_batch_autotune(rmge_batch *b, const double *A, void *hip_stream,
+                                rmge_batch_tuning *best, double *ms_bucket);
+
+/* The packed FP32 factors of system `index` (in the order of `systems`) after
+ * a run, converted to FP64 into LU (device, n x n, ld >= n): unit L strictly
+ * below the diagonal, U on and above, L U = M_s = A_s H_s (A_s rounded to
+ * FP32, H_s in FP32).  Synchronises hip_stream. */
+rmge_status rmge_batch_factors_lu(const rmge_batch *b, int32_t index, double *LU, int64_t ld,
+                                  void *hip_stream);
+
+void rmge_batch_destroy(rmge_batch *b);
 
 void rmge_destroy(rmge_factors *f);
 

@@ -70,6 +70,7 @@ def lib() -> ctypes.CDLL:
         L.orc_errors.argtypes = [i64, i64, vp, vp, vp, dp, dp]
         L.orc_grad_A.argtypes = [i64, i64, vp, vp, vp]
         L.orc_num_threads.restype = i32
+        L.orc_set_num_threads.argtypes = [i32]
         _lib = L
     return _lib
 
@@ -323,3 +324,8 @@ def grad_A(gb, X) -> np.ndarray:
 
 def num_threads() -> int:
     return int(lib().orc_num_threads())
+
+
+def set_num_threads(t: int) -> None:
+    """Threads the row loops use (results do not depend on it)."""
+    lib().orc_set_num_threads(int(t))

@@ -580,3 +580,13 @@ int orc_num_threads(void) {
     return 1;
 #endif
 }
+
+/* Threads for the rows the OpenMP loops distribute (the arithmetic of each
+ * element does not depend on it). */
+void orc_set_num_threads(int t) {
+#ifdef _OPENMP
+    if (t > 0) omp_set_num_threads(t);
+#else
+    (void)t;
+#endif
+}

@@ -12,19 +12,27 @@ adjoint) runs in the library's HIP kernels.
 """
 from __future__ import annotations
 
+import ctypes
+
 from . import _rmge
-from ._rmge import (RMGE_F32, RMGE_F32_BF16X2, RMGE_F64, RMGE_MULT_CIRCULANT, RMGE_MULT_GAUSSIAN,
-                    RMGE_MULT_NONE, RMGE_MULT_TOEPLITZ, RMGE_PIVOT_BLOCK, RMGE_PIVOT_NONE,
-                    RMGEError, lib)
+from ._rmge import (RMGE_BF16, RMGE_F32, RMGE_F32_BF16X2, RMGE_F64, RMGE_MULT_CIRCULANT, RMGE_MULT_GAUSSIAN,
+                    RMGE_MULT_NONE, RMGE_MULT_TOEPLITZ, RMGE_MULT_UNITARY_CIRCULANT,
+                    RMGE_PIVOT_BLOCK, RMGE_PIVOT_NONE, RMGEError, lib)
 
 NONE, GAUSSIAN, CIRCULANT, TOEPLITZ = (RMGE_MULT_NONE, RMGE_MULT_GAUSSIAN, RMGE_MULT_CIRCULANT,
                                        RMGE_MULT_TOEPLITZ)
+UNITARY_CIRCULANT = RMGE_MULT_UNITARY_CIRCULANT
 F64, F32 = RMGE_F64, RMGE_F32
-# FP32 factors with the product A H on the BF16 matrix cores (H rounded to BF16,
-# A split into two BF16 terms); other multiplier kinds behave as F32
+# FP32 factors whose large Schur updates run on the BF16 matrix cores in
+# three-term split form (FP32 accuracy); with a Gaussian multiplier the product
+# A H does too (H rounded to BF16, A split into two BF16 terms)
 F32_BF16X2 = RMGE_F32_BF16X2
+# BF16 factorization: bulk Schur updates with operands rounded once to BF16,
+# FP32 accumulation (the product as for F32_BF16X2)
+BF16 = RMGE_BF16
 PIVOT_NONE, PIVOT_BLOCK = RMGE_PIVOT_NONE, RMGE_PIVOT_BLOCK
-KIND_NAMES = {"none": NONE, "gaussian": GAUSSIAN, "circulant": CIRCULANT, "toeplitz": TOEPLITZ}
+KIND_NAMES = {"none": NONE, "gaussian": GAUSSIAN, "circulant": CIRCULANT, "toeplitz": TOEPLITZ,
+              "unitary_circulant": UNITARY_CIRCULANT}
 
 
 def _stream_handle(device) -> int:
@@ -101,6 +109,14 @@ class Factors:
         if rc:
             raise RMGEError(rc, "rmge_factor_times")
         return {"ms_multiplier": ms[0], "ms_product": ms[1], "ms_factor": ms[2]}
+
+    def update_time(self):
+        """(ms, flops) of the last factorization's bulk Schur updates (HIP events
+        around each launch), with no device work."""
+        rc, ms, fl = _rmge.rmge_factor_update_time(self._h)
+        if rc:
+            raise RMGEError(rc, "rmge_factor_update_time")
+        return ms, fl
 
     @property
     def info(self) -> int:
@@ -248,6 +264,129 @@ def precondition(A, kind, seed):
     return M
 
 
+def schur_update(C, D, E, terms):
+    """C <- C - D E in FP32 in place (one Schur-complement update as the
+    factorization runs it: terms 0 FP32 matrix cores, 3 three-term BF16 split,
+    1 operands rounded to BF16)."""
+    M, N = C.shape
+    K = D.shape[1]
+    rc = _rmge.rmge_schur_update_f32(M, N, K, D.data_ptr(), D.stride(0), E.data_ptr(), E.stride(0),
+                                     C.data_ptr(), C.stride(0), terms, _stream_handle(C.device))
+    if rc:
+        raise RMGEError(rc, "rmge_schur_update_f32")
+    return C
+
+
+class Batch:
+    """Many independent systems solved in one device-resident pass (rmge_batch_*).
+
+    systems: list of (n, kind, seed, a_off, v_off); A, B, X are flat float64 CUDA
+    tensors holding every A_s (row-major, ld n) and b_s, x_s at those offsets."""
+
+    def __init__(self, systems, tuning=None, restart=16, max_iters=200):
+        entries = [_rmge.rmge_batch_system(int(n), _kind(k), int(seed) & (2**64 - 1), int(ao), int(vo))
+                   for (n, k, seed, ao, vo) in systems]
+        t = None
+        if tuning is not None:
+            t = _rmge.rmge_batch_tuning((ctypes.c_int32 * _rmge.RMGE_BATCH_BUCKETS)(*tuning))
+        rc, h = _rmge.rmge_batch_create(entries, t, restart, max_iters)
+        if rc:
+            raise RMGEError(rc, "rmge_batch_create")
+        self._h = h
+        self.count = len(entries)
+
+    def run(self, A, B, X, tol=1e-14, graph=False):
+        fn = _rmge.rmge_batch_graph_run if graph else _rmge.rmge_batch_run
+        rc = fn(self._h, A.data_ptr(), B.data_ptr(), X.data_ptr(), tol, _stream_handle(A.device))
+        if rc:
+            raise RMGEError(rc, "rmge_batch_run")
+        return X
+
+    def run_timed(self, A, B, X, tol=1e-14):
+        """An eager run with HIP events between the phases: (products, factor, refine) ms."""
+        rc, ms = _rmge.rmge_batch_run_timed(self._h, A.data_ptr(), B.data_ptr(), X.data_ptr(), tol,
+                                            _stream_handle(A.device))
+        if rc:
+            raise RMGEError(rc, "rmge_batch_run_timed")
+        return ms
+
+    def results(self, device="cuda"):
+        import numpy as np
+
+        c = self.count
+        st, it = np.zeros(c, np.int32), np.zeros(c, np.int32)
+        eta, eta0, info = np.zeros(c), np.zeros(c), np.zeros(c, np.int64)
+        import torch
+
+        rc = _rmge.rmge_batch_results(self._h, st, eta, eta0, it, info,
+                                      _stream_handle(torch.device(device)))
+        if rc:
+            raise RMGEError(rc, "rmge_batch_results")
+        return {"status": st, "eta": eta, "eta0": eta0, "iters": it, "info": info}
+
+    def tuning(self):
+        rc, nb = _rmge.rmge_batch_get_tuning(self._h)
+        if rc:
+            raise RMGEError(rc, "rmge_batch_get_tuning")
+        return nb
+
+    def set_tuning(self, nb):
+        rc = _rmge.rmge_batch_set_tuning(self._h, nb)
+        if rc:
+            raise RMGEError(rc, "rmge_batch_set_tuning")
+
+    def autotune_cached(self, A, key, path=None):
+        """Panel widths for this batch from the JSON cache at `path` (default
+        ~/.cache/paper_1406_5802_amd/batch_tuning.json) under `key`; on a miss, run
+        the library's autotuner and store its choice.  Returns (widths, from_cache)."""
+        import json
+        import os
+
+        path = path or os.path.join(os.path.expanduser("~"), ".cache", "paper_1406_5802_amd",
+                                    "batch_tuning.json")
+        table = {}
+        if os.path.exists(path):
+            with open(path) as fh:
+                table = json.load(fh)
+        if key in table:
+            self.set_tuning(table[key]["nb"])
+            return table[key]["nb"], True
+        nb, ms = self.autotune(A)
+        table[key] = {"nb": nb, "ms_per_bucket": ms}
+        os.makedirs(os.path.dirname(path), exist_ok=True)
+        tmp = path + ".tmp%d" % os.getpid()
+        with open(tmp, "w") as fh:
+            json.dump(table, fh, indent=1, sort_keys=True)
+        os.replace(tmp, path)
+        return nb, False
+
+    def autotune(self, A):
+        rc, nb, ms = _rmge.rmge_batch_autotune(self._h, A.data_ptr(), _stream_handle(A.device))
+        if rc:
+            raise RMGEError(rc, "rmge_batch_autotune")
+        return nb, ms
+
+    def lu(self, index, n, device="cuda"):
+        import torch
+
+        LU = torch.empty((n, n), dtype=torch.float64, device=device)
+        rc = _rmge.rmge_batch_factors_lu(self._h, index, LU.data_ptr(), n, _stream_handle(LU.device))
+        if rc:
+            raise RMGEError(rc, "rmge_batch_factors_lu")
+        return LU
+
+    def close(self):
+        if getattr(self, "_h", None):
+            _rmge.rmge_batch_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
 def grad_A(GB, X):
     """-GB X^T (the gradient of a loss with respect to A, given GB = A^{-T} dL/dX)."""
     import torch
@@ -261,6 +400,6 @@ def grad_A(GB, X):
     return GA
 
 
-__all__ = ["factor", "Factors", "multiplier_params", "precondition", "grad_A", "RMGEError", "lib",
-           "NONE", "GAUSSIAN", "CIRCULANT", "TOEPLITZ", "F64", "F32", "F32_BF16X2", "PIVOT_NONE",
-           "PIVOT_BLOCK"]
+__all__ = ["factor", "Factors", "Batch", "multiplier_params", "precondition", "schur_update", "grad_A",
+           "RMGEError", "lib", "NONE", "GAUSSIAN", "CIRCULANT", "TOEPLITZ", "UNITARY_CIRCULANT",
+           "F64", "F32", "BF16", "F32_BF16X2", "PIVOT_NONE", "PIVOT_BLOCK"]

@@ -54,8 +54,12 @@ struct rmge_factors {
     uint16_t *a16 = nullptr;    // split16: A_h then A_l, BF16 bits, rows16 x ldk16 each
     uint16_t *ht16 = nullptr;   // split16: H^T as BF16 bits, rows16 x ldk16
     int64_t rows16 = 0, ldk16 = 0;
-    uint16_t *u16 = nullptr;    // split16: BF16 terms of the Schur update's operands
-    int64_t urows = 0, uldk = 0;  // (six slabs of urows x uldk)
+    // BF16 Schur updates (RMGE_F32_BF16X2: three-term split at FP32 accuracy,
+    // trailing blocks of kSplitUpdateMin rows and more; RMGE_BF16: operands
+    // rounded once to BF16, every bulk update): upd_terms = 3 or 1, 0 if none
+    int upd_terms = 0;
+    uint16_t *u16 = nullptr;    // the BF16 terms of the update's operands
+    int64_t urows = 0, uldk = 0;  // (2 * upd_terms slabs of urows x uldk)
     double *wht = nullptr;      // split16: partial sums of H y over Ht
     double *params = nullptr;  // structured multiplier parameters
     double *hker = nullptr;    // period-m kernel
@@ -91,11 +95,16 @@ struct rmge_factors {
     hipStream_t side = nullptr;  // look-ahead stream (default priority)
     hipStream_t main = nullptr;  // set when the side stream owns reserved CUs
     hipEvent_t ev_narrow = nullptr, ev_panel = nullptr, ev_fork = nullptr, ev_join = nullptr;
+    // the bulk Schur updates' device time: an event pair around each launch
+    // (created when the factorization has at most kUpdEvents steps)
+    std::vector<hipEvent_t> upd_ev;
+    double upd_flops = 0.0, ms_update = 0.0;
 };
 
 namespace {
 
 constexpr int kSub = 32;      // rows of the inverted diagonal sub-blocks
+constexpr int kUpdEvents = 512;  // steps of a factorization whose updates are timed
 constexpr int kSideCUs = 8;   // compute units reserved for the look-ahead stream
 // Split-BF16 handles: trailing blocks of at least this many rows take the
 // three-term BF16 Schur update (smaller ones fill too few 256 x 256 tiles to
@@ -136,10 +145,20 @@ int64_t next_pow2(int64_t x) {
     return p;
 }
 
+// Multipliers applied by FFT: circulants (Gaussian or unitary first column) and Toeplitz.
+bool is_fft_kind(int kind) {
+    return kind == RMGE_MULT_CIRCULANT || kind == RMGE_MULT_TOEPLITZ ||
+           kind == RMGE_MULT_UNITARY_CIRCULANT;
+}
+
+bool is_circulant(int kind) {
+    return kind == RMGE_MULT_CIRCULANT || kind == RMGE_MULT_UNITARY_CIRCULANT;
+}
+
 // FFT period for the structured multipliers (0 if unsupported).
 int fft_period(int kind, int64_t n) {
     int64_t m;
-    if (kind == RMGE_MULT_CIRCULANT && n >= 2 && is_pow2(n))
+    if (is_circulant(kind) && n >= 2 && is_pow2(n))
         m = n;
     else
         m = next_pow2(2 * n - 1);
@@ -289,14 +308,22 @@ hipError_t genp_blocked(rmge_factors *f) {
         HIP_TRY(hipStreamWaitEvent(s1, f->ev_narrow, 0));
         HIP_TRY(factor_pivot_block<T>(f, a22, bn, k + b, Linv(step + 1), Uinv(step + 1), s1));
         HIP_TRY(hipEventRecord(f->ev_panel, s1));
-        if (r > bn && sizeof(T) == 4 && f->u16 != nullptr && r >= kSplitUpdateMin)
-            HIP_TRY(update_bf16x3(r, r - bn, b, reinterpret_cast<const float *>(a21), ld,
-                                  reinterpret_cast<const float *>(a12 + bn), ld,
-                                  reinterpret_cast<float *>(a22 + bn), ld, f->u16, f->uldk,
-                                  f->urows, abort, s0));
+        const bool bf16_upd = sizeof(T) == 4 && f->u16 != nullptr &&
+                              (f->upd_terms == 1 || r >= kSplitUpdateMin);
+        const bool timed = r > bn && 2 * step + 1 < static_cast<int64_t>(f->upd_ev.size());
+        if (timed) {
+            HIP_TRY(hipEventRecord(f->upd_ev[2 * step], s0));
+            f->upd_flops += 2.0 * static_cast<double>(r) * static_cast<double>(r - bn) * b;
+        }
+        if (r > bn && bf16_upd)
+            HIP_TRY(update_bf16(f->upd_terms, r, r - bn, b, reinterpret_cast<const float *>(a21),
+                                ld, reinterpret_cast<const float *>(a12 + bn), ld,
+                                reinterpret_cast<float *>(a22 + bn), ld, f->u16, f->uldk,
+                                f->urows, abort, s0));
         else if (r > bn)
             HIP_TRY(Prec<T>::gemm(kGemmUpdate, r, r - bn, b, T(-1), a21, ld, a12 + bn, ld, T(1),
                                   a22 + bn, ld, abort, s0));
+        if (timed) HIP_TRY(hipEventRecord(f->upd_ev[2 * step + 1], s0));
     }
     if (f->pivot) HIP_TRY(permute_left<T>(a, ld, n, nb, f->piv, abort, s0));
     if (f->main) {
@@ -323,9 +350,17 @@ hipError_t draw_multiplier(rmge_factors *f) {
             return round_h_bf16(reinterpret_cast<float *>(f->G), n, f->ht16, f->ldk16, s);
         return hipSuccess;
     default: {
-        HIP_TRY(launch_normals_f64(f->params, f->kind == RMGE_MULT_CIRCULANT ? n : 2 * n - 1,
-                                   f->seed, static_cast<uint64_t>(f->kind), s));
-        HIP_TRY(fft_embed(f->kind, f->params, n, f->m, f->hker, s));
+        if (f->kind == RMGE_MULT_UNITARY_CIRCULANT) {
+            // phases into the second half of params, the first column into the first
+            HIP_TRY(launch_uniforms_f64(f->params + n, n, f->seed,
+                                        static_cast<uint64_t>(f->kind), s));
+            HIP_TRY(unitary_column(f->params + n, n, f->params, s));
+        } else {
+            HIP_TRY(launch_normals_f64(f->params, f->kind == RMGE_MULT_CIRCULANT ? n : 2 * n - 1,
+                                       f->seed, static_cast<uint64_t>(f->kind), s));
+        }
+        HIP_TRY(fft_embed(is_circulant(f->kind) ? RMGE_MULT_CIRCULANT : f->kind, f->params, n,
+                          f->m, f->hker, s));
         return fft_spectrum(f->hker, f->m, f->tw, f->hhat, s);
     }
     }
@@ -394,6 +429,7 @@ rmge_status run_factor(rmge_factors *f) {
     RMGE_TRY(hipEventRecord(f->ev[2], s));
     RMGE_TRY(hipEventRecord(f->ev[3], s));
     if (f->pivot) RMGE_TRY(iota(f->piv, f->n, s));
+    f->upd_flops = 0.0;
     RMGE_TRY(genp_blocked<T>(f));
     RMGE_TRY(hipEventRecord(f->ev[4], s));
     {
@@ -414,6 +450,20 @@ rmge_status run_factor(rmge_factors *f) {
     f->stats.ms_multiplier = t01;
     f->stats.ms_product = t12;
     f->stats.ms_factor = t34;
+    {  // the bulk updates: the pairs recorded in this factorization
+        double ms = 0.0;
+        const int64_t steps = (f->n + f->block - 1) / f->block;
+        for (int64_t st = 0; st < steps && 2 * st + 1 < static_cast<int64_t>(f->upd_ev.size());
+             ++st) {
+            const int64_t k = st * f->block, b = std::min<int64_t>(f->block, f->n - k);
+            const int64_t r = f->n - k - b, bn = std::min<int64_t>(r, f->block);
+            if (r <= bn || f->host_st.code != 0) continue;
+            float t = 0.f;
+            if (hipEventElapsedTime(&t, f->upd_ev[2 * st], f->upd_ev[2 * st + 1]) == hipSuccess)
+                ms += t;
+        }
+        f->ms_update = ms;
+    }
     f->stats.info = f->host_st.code ? f->host_st.info : -1;
     f->stats.status = f->host_st.code;
     f->stats.block = f->block;
@@ -433,6 +483,8 @@ void free_handle(rmge_factors *f) {
     for (hipEvent_t &e : f->ev)
         if (e) (void)hipEventDestroy(e);
     for (hipEvent_t e : {f->ev_narrow, f->ev_panel, f->ev_fork, f->ev_join})
+        if (e) (void)hipEventDestroy(e);
+    for (hipEvent_t e : f->upd_ev)
         if (e) (void)hipEventDestroy(e);
     if (f->side) (void)hipStreamDestroy(f->side);
     if (f->main) (void)hipStreamDestroy(f->main);
@@ -454,16 +506,21 @@ rmge_status alloc_handle(rmge_factors *f) {
         RMGE_TRY(hipMalloc(&f->ht16, one));
         RMGE_TRY(hipMemsetAsync(f->a16, 0, 2 * one, f->stream));
         RMGE_TRY(hipMemsetAsync(f->ht16, 0, one, f->stream));
+        RMGE_TRY(hipMalloc(&f->wht, sizeof(double) * static_cast<size_t>(gemv_ht_blocks(n) * n)));
+    }
+    if (f->upd_terms) {
         f->urows = round_up(n, 256);
         f->uldk = round_up(f->block, 32);
-        const size_t ubytes = 6 * sizeof(uint16_t) * static_cast<size_t>(f->urows) * f->uldk;
-        RMGE_TRY(hipMalloc(&f->wht, sizeof(double) * static_cast<size_t>(gemv_ht_blocks(n) * n)));
-        if (ubytes <= INT32_MAX) {  // else the updates stay in FP32
+        const size_t ubytes = 2 * f->upd_terms * sizeof(uint16_t) *
+                              static_cast<size_t>(f->urows) * f->uldk;
+        if (ubytes <= INT32_MAX) {  // else the updates stay in FP32 (32-bit buffer offsets)
             RMGE_TRY(hipMalloc(&f->u16, ubytes));
             RMGE_TRY(hipMemsetAsync(f->u16, 0, ubytes, f->stream));
+        } else {
+            f->upd_terms = 0;
         }
     }
-    if (f->kind == RMGE_MULT_CIRCULANT || f->kind == RMGE_MULT_TOEPLITZ) {
+    if (is_fft_kind(f->kind)) {
         const int L = f->m / 2;
         RMGE_TRY(hipMalloc(&f->params, sizeof(double) * static_cast<size_t>(2 * n)));
         RMGE_TRY(hipMalloc(&f->hker, sizeof(double) * static_cast<size_t>(f->m)));
@@ -502,6 +559,11 @@ rmge_status alloc_handle(rmge_factors *f) {
     }
     for (hipEvent_t *e : {&f->ev_narrow, &f->ev_panel, &f->ev_fork, &f->ev_join})
         RMGE_TRY(hipEventCreateWithFlags(e, hipEventDisableTiming));
+    const int64_t steps = (n + f->block - 1) / f->block;
+    if (steps <= kUpdEvents) {
+        f->upd_ev.assign(static_cast<size_t>(2 * steps), nullptr);
+        for (hipEvent_t &e : f->upd_ev) RMGE_TRY(hipEventCreate(&e));
+    }
     return RMGE_OK;
 }
 
@@ -973,10 +1035,11 @@ rmge_status check_factor_args(const double *A, int64_t n, int64_t lda, int32_t k
                               int32_t block, int32_t prec, int32_t pivot = RMGE_PIVOT_NONE) {
     if (!A || n < 1 || lda < n || n > (int64_t(1) << 20)) return RMGE_EINVAL;
     if (pivot != RMGE_PIVOT_NONE && pivot != RMGE_PIVOT_BLOCK) return RMGE_EINVAL;
-    if (kind < RMGE_MULT_NONE || kind > RMGE_MULT_TOEPLITZ) return RMGE_EINVAL;
+    if (kind < RMGE_MULT_NONE || kind > RMGE_MULT_UNITARY_CIRCULANT) return RMGE_EINVAL;
     if (block < 0 || block > kMaxBlock) return RMGE_EINVAL;
-    if (prec != RMGE_F64 && prec != RMGE_F32 && prec != RMGE_F32_BF16X2) return RMGE_EINVAL;
-    if ((kind == RMGE_MULT_CIRCULANT || kind == RMGE_MULT_TOEPLITZ) && fft_period(kind, n) == 0)
+    if (prec != RMGE_F64 && prec != RMGE_F32 && prec != RMGE_BF16 && prec != RMGE_F32_BF16X2)
+        return RMGE_EINVAL;
+    if (is_fft_kind(kind) && fft_period(kind, n) == 0)
         return RMGE_EINVAL;
     return RMGE_OK;
 }
@@ -1036,14 +1099,15 @@ rmge_status rmge_factor_pivoted(const double *A, int64_t n, int64_t lda, int32_t
     f->lda = lda;
     f->ld = round_up(n, 64);
     f->kind = kind;
-    f->prec = prec == RMGE_F32_BF16X2 ? RMGE_F32 : prec;
-    f->split16 = prec == RMGE_F32_BF16X2 && kind == RMGE_MULT_GAUSSIAN;
+    f->prec = (prec == RMGE_F32_BF16X2 || prec == RMGE_BF16) ? RMGE_F32 : prec;
+    f->split16 = (prec == RMGE_F32_BF16X2 || prec == RMGE_BF16) && kind == RMGE_MULT_GAUSSIAN;
+    f->upd_terms = prec == RMGE_F32_BF16X2 ? 3 : prec == RMGE_BF16 ? 1 : 0;
     f->block = block == 0 ? kMaxBlock : block;
     f->pivot = pivot;
     f->seed = seed;
     f->stream = static_cast<hipStream_t>(hip_stream);
     f->A = A;
-    f->m = (kind == RMGE_MULT_CIRCULANT || kind == RMGE_MULT_TOEPLITZ) ? fft_period(kind, n) : 0;
+    f->m = is_fft_kind(kind) ? fft_period(kind, n) : 0;
     rs = alloc_handle(f);
     if (rs != RMGE_OK) {
         free_handle(f);
@@ -1170,6 +1234,13 @@ rmge_status rmge_factor_times(const rmge_factors *f, double *ms3) {
     return RMGE_OK;
 }
 
+rmge_status rmge_factor_update_time(const rmge_factors *f, double *ms, double *flops) {
+    if (!f || !ms || !flops) return RMGE_EINVAL;
+    *ms = f->ms_update;
+    *flops = f->upd_flops;
+    return RMGE_OK;
+}
+
 rmge_status rmge_factors_lu(const rmge_factors *f, double *LU, int64_t ld) {
     if (!f || !LU || ld < f->n) return RMGE_EINVAL;
     hipError_t e = (f->prec == RMGE_F32)
@@ -1197,6 +1268,7 @@ int64_t rmge_param_count(int32_t kind, int64_t n) {
     case RMGE_MULT_GAUSSIAN: return n * n;
     case RMGE_MULT_CIRCULANT: return n;
     case RMGE_MULT_TOEPLITZ: return 2 * n - 1;
+    case RMGE_MULT_UNITARY_CIRCULANT: return n;
     default: return 0;
     }
 }
@@ -1207,6 +1279,15 @@ rmge_status rmge_multiplier_params(int32_t kind, int64_t n, uint64_t seed, doubl
     if (!out || cnt == 0) return RMGE_EINVAL;
     if (!device_ok()) return RMGE_EDEVICE;
     hipStream_t s = static_cast<hipStream_t>(hip_stream);
+    if (kind == RMGE_MULT_UNITARY_CIRCULANT) {  // the first column, from n phases
+        double *phi = nullptr;
+        RMGE_TRY(hipMalloc(&phi, sizeof(double) * static_cast<size_t>(n)));
+        hipError_t e = launch_uniforms_f64(phi, n, seed, static_cast<uint64_t>(kind), s);
+        if (e == hipSuccess) e = unitary_column(phi, n, out, s);
+        if (e == hipSuccess) e = hipStreamSynchronize(s);
+        (void)hipFree(phi);
+        return from_hip(e);
+    }
     RMGE_TRY(launch_normals_f64(out, cnt, seed, static_cast<uint64_t>(kind), s));
     return from_hip(hipStreamSynchronize(s));
 }
@@ -1226,7 +1307,7 @@ rmge_status rmge_precondition(const double *A, int64_t n, int64_t lda, int32_t k
     f.stream = static_cast<hipStream_t>(hip_stream);
     f.A = A;
     f.lu = M;
-    f.m = (kind == RMGE_MULT_CIRCULANT || kind == RMGE_MULT_TOEPLITZ) ? fft_period(kind, n) : 0;
+    f.m = is_fft_kind(kind) ? fft_period(kind, n) : 0;
     hipError_t e = hipSuccess;
     if (kind == RMGE_MULT_GAUSSIAN) e = hipMalloc(&f.G, sizeof(double) * static_cast<size_t>(n * n));
     if (e == hipSuccess && f.m) {
@@ -1251,8 +1332,7 @@ rmge_status rmge_precondition_noalloc(const double *A, int64_t n, int64_t lda, i
     if (!M || ldm < n || M == A) return RMGE_EINVAL;
     rmge_status rs = check_factor_args(A, n, lda, kind, 0, RMGE_F64);
     if (rs != RMGE_OK) return rs;
-    const int m = (kind == RMGE_MULT_CIRCULANT || kind == RMGE_MULT_TOEPLITZ) ? fft_period(kind, n)
-                                                                              : 0;
+    const int m = is_fft_kind(kind) ? fft_period(kind, n) : 0;
     if (noalloc_doubles(kind, n, m) > kNoallocScratchDoubles) return RMGE_EINVAL;
     if (!device_ok()) return RMGE_EDEVICE;
     double *scr = nullptr;
@@ -1279,6 +1359,29 @@ rmge_status rmge_precondition_noalloc(const double *A, int64_t n, int64_t lda, i
     hipError_t e = m ? fft_twiddles(m, f.tw, f.stream) : hipSuccess;
     if (e == hipSuccess) e = precondition<double>(&f);
     f.lu = nullptr;
+    return from_hip(e);
+}
+
+rmge_status rmge_schur_update_f32(int64_t M, int64_t N, int64_t K, const float *D, int64_t ldd,
+                                  const float *E, int64_t lde, float *C, int64_t ldc,
+                                  int32_t terms, void *hip_stream) {
+    if (!D || !E || !C || M < 0 || N < 0 || K < 0 || M > INT32_MAX || N > INT32_MAX ||
+        K > kMaxBlock || ldd < K || lde < N || ldc < N || (terms != 0 && terms != 1 && terms != 3))
+        return RMGE_EINVAL;
+    if (M == 0 || N == 0 || K == 0) return RMGE_OK;
+    if (!device_ok()) return RMGE_EDEVICE;
+    hipStream_t s = static_cast<hipStream_t>(hip_stream);
+    if (terms == 0) {
+        RMGE_TRY(gemm_f32(kGemmUpdate, M, N, K, -1.0f, D, ldd, E, lde, 1.0f, C, ldc, nullptr, s));
+        return from_hip(hipStreamSynchronize(s));
+    }
+    const int64_t rows = round_up(M > N ? M : N, 256), ldk = round_up(K, 32);
+    if (2 * terms * 2 * rows * ldk > INT32_MAX) return RMGE_EINVAL;
+    uint16_t *ws = nullptr;
+    RMGE_TRY(hipMalloc(&ws, sizeof(uint16_t) * static_cast<size_t>(2 * terms * rows * ldk)));
+    hipError_t e = update_bf16(terms, M, N, K, D, ldd, E, lde, C, ldc, ws, ldk, rows, nullptr, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    (void)hipFree(ws);
     return from_hip(e);
 }
 

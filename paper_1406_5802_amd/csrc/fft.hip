@@ -11,13 +11,12 @@
 //   H^T w        : correlation again.
 //
 // One workgroup transforms one vector.  The real length-m signal is packed as
-// z_k = x_{2k} + i x_{2k+1} (k < L = m/2) and transformed with an in-place
-// radix-2 complex FFT of length L in LDS (decimation in time from bit-reversed
-// order, natural-order spectrum); the real spectrum is untangled pairwise
-// (f, L - f), multiplied by the kernel's spectrum, re-packed, and sent back
-// through a decimation-in-frequency inverse whose bit-reversed output is read
-// directly when storing.  Twiddles e^{-i pi j / L}, j = 0..L, come from a table
-// built once per multiplier.
+// z_k = x_{2k} + i x_{2k+1} (k < L = m/2) and transformed by a complex FFT of
+// length L in radix-16 Stockham passes (registers, with LDS between passes);
+// the real spectrum is untangled pairwise (f, L - f), multiplied by the
+// kernel's spectrum, re-packed, and sent back through the inverse passes,
+// whose last one writes the row.  Twiddles e^{-i pi j / L}, j = 0..L, come
+// from a table built once per multiplier.
 //
 // Bound: HBM for the row transform (one read and one write of each element)
 // when LDS and VALU keep up; 5 m log2 m flops per vector (forward + inverse).
@@ -37,9 +36,6 @@ __device__ inline cplx cmul(cplx a, cplx b) {
 __device__ inline cplx cconj(cplx a) { return {a.x, -a.y}; }
 __device__ inline cplx cscale(cplx a, double s) { return {a.x * s, a.y * s}; }
 
-__device__ inline int bitrev(int k, int logL) {
-    return logL == 0 ? 0 : static_cast<int>(__brev(static_cast<unsigned>(k)) >> (32 - logL));
-}
 
 __global__ void k_twiddles(int L, cplx *tw) {
     for (int j = blockIdx.x * blockDim.x + threadIdx.x; j <= L; j += gridDim.x * blockDim.x) {
@@ -49,42 +45,246 @@ __global__ void k_twiddles(int L, cplx *tw) {
     }
 }
 
-// Forward transform of a real vector of length m (zero padded from n).  If
-// spec != null the half spectrum X_0..X_L is written there and the kernel ends.
-// Otherwise Y = X * K (K = conj(hhat) if conj) is inverted and
-// out = beta * out + y[0..n).
-template <typename TI, typename TO>
-__global__ __launch_bounds__(1024) void k_fft_rows(const TI *in, int64_t vsi, int64_t esi,
-                                                   int64_t n, int L, int logL, const cplx *tw,
-                                                   const cplx *hhat, int conj, double beta, TO *out,
-                                                   int64_t vso, int64_t eso, cplx *spec,
-                                                   double *absmax) {
-    extern __shared__ cplx z[];
-    const int tid = threadIdx.x, nt = blockDim.x;
-    const int64_t v = blockIdx.x;
-    const TI *x = in + v * vsi;
-    for (int k = tid; k < L; k += nt) {
-        const int64_t j0 = 2 * static_cast<int64_t>(k), j1 = j0 + 1;
-        const double re = j0 < n ? static_cast<double>(x[j0 * esi]) : 0.0;
-        const double im = j1 < n ? static_cast<double>(x[j1 * esi]) : 0.0;
-        z[bitrev(k, logL)] = {re, im};
+// ---------------------------------------------------------------------------
+// Row transforms as Stockham passes (Govindaraju et al., SC'08 formulation of
+// the autosorting FFT): a complex length L = 2^LOGL is done in passes of
+// radix 16 (the last one 2, 4 or 8 when LOGL is not a multiple of 4).  Each of
+// the T = L / 16 threads of a workgroup holds 16 values in registers; in a
+// pass of radix R it takes the butterflies j = tid + q T (q < 16 / R):
+//   inputs    a_r = z[j + r L / R]                 (consecutive j: coalesced)
+//   twiddles  a_r *= w^{r k},  k = j mod Ns,  w = e^{-2 pi i / (Ns R)}
+//   DFT_R     b_s = sum_r a_r e^{-2 pi i r s / R}  (in registers)
+//   outputs   z[(j / Ns) Ns R + k + s Ns] = b_s    (Ns = product of the
+//                                                    earlier passes' radices)
+// and the result comes out in natural order.  Values move between passes
+// through LDS (one complex of padding per 16, against bank conflicts); the
+// first forward pass reads the row straight from global memory and the last
+// inverse pass writes it straight back, both as whole 16-byte (or 8-byte)
+// elements z_k = (x_{2k}, x_{2k+1}) across consecutive lanes.  Pass twiddles
+// come from the table e^{-i pi t / L}, t = 0..L, by symmetry beyond t = L.
+
+// x e^{-2 pi i a / 16} (forward) or x e^{+2 pi i a / 16} (inverse), a a
+// compile-time constant after unrolling.
+__device__ inline cplx rot16(cplx x, int a, bool inv) {
+    constexpr double C1 = 0.92387953251128675613;  // cos(pi / 8)
+    constexpr double S1 = 0.38268343236508977173;  // sin(pi / 8)
+    constexpr double R2 = 0.70710678118654752440;  // sqrt(2) / 2
+    a &= 15;
+    if (a == 0) return x;
+    // e^{-2 pi i a / 16} = c + i s
+    double c, sn;
+    switch (a & 7) {
+    case 0: c = 1.0; sn = 0.0; break;
+    case 1: c = C1; sn = -S1; break;
+    case 2: c = R2; sn = -R2; break;
+    case 3: c = S1; sn = -C1; break;
+    case 4: c = 0.0; sn = -1.0; break;
+    case 5: c = -S1; sn = -C1; break;
+    case 6: c = -R2; sn = -R2; break;
+    default: c = -C1; sn = -S1; break;
+    }
+    if (a & 8) { c = -c; sn = -sn; }
+    if (inv) sn = -sn;
+    if ((a & 3) == 0) {  // multiples of -pi/2: exact swaps and sign changes
+        if (a == 8) return {-x.x, -x.y};
+        return sn < 0 ? cplx{x.y, -x.x} : cplx{-x.y, x.x};
+    }
+    return {x.x * c - x.y * sn, x.x * sn + x.y * c};
+}
+
+__device__ inline int brev_c(int r, int bits) {
+    int o = 0;
+    for (int b = 0; b < bits; ++b) o |= ((r >> b) & 1) << (bits - 1 - b);
+    return o;
+}
+
+// b_s = sum_r a_r e^{-+2 pi i r s / R} in place, R in {2, 4, 8, 16}.
+template <int R>
+__device__ inline void dft_reg(cplx *a, bool inv) {
+    constexpr int BITS = R == 2 ? 1 : R == 4 ? 2 : R == 8 ? 3 : 4;
+    cplx b[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) b[brev_c(r, BITS)] = a[r];
+#pragma unroll
+    for (int h = 1; h < R; h <<= 1) {
+#pragma unroll
+        for (int g = 0; g < R; g += 2 * h) {
+#pragma unroll
+            for (int k = 0; k < h; ++k) {
+                const cplx u = b[g + k];
+                const cplx v = rot16(b[g + k + h], k * (8 / h), inv);
+                b[g + k] = u + v;
+                b[g + k + h] = u - v;
+            }
+        }
+    }
+#pragma unroll
+    for (int r = 0; r < R; ++r) a[r] = b[r];
+}
+
+__device__ inline int lds_pad(int i) { return i + (i >> 4); }
+
+// Radix of pass p (0-based) of a length-2^LOGL transform: 16 while four bits
+// remain, then the rest.
+template <int LOGL>
+struct Passes {
+    static constexpr int kFull = LOGL / 4, kRest = LOGL % 4;
+    static constexpr int kCount = kFull + (kRest ? 1 : 0);
+    __host__ __device__ static constexpr int radix(int p) { return p < kFull ? 16 : 1 << kRest; }
+    __host__ __device__ static constexpr int ns(int p) {  // product of the earlier radices
+        return p == 0 ? 1 : ns(p - 1) * radix(p - 1);
+    }
+};
+
+// e^{-i pi t / L} for 0 <= t < 2 L from the table of t <= L (the rest by symmetry).
+__device__ inline cplx tw_at(const cplx *__restrict__ tw, int t, int L) {
+    const cplx w = tw[t <= L ? t : t - L];
+    return t <= L ? w : cplx{-w.x, -w.y};
+}
+
+// Twiddles and DFT of pass P on the thread's registers a[16] (inputs as
+// gathered by the pass), leaving the pass outputs in a.
+template <int LOGL, int P>
+__device__ inline void pass_compute(cplx *a, int tid, const cplx *__restrict__ tw, bool inv) {
+    constexpr int L = 1 << LOGL, R = Passes<LOGL>::radix(P), NS = Passes<LOGL>::ns(P);
+    constexpr int T = L >= 16 ? L / 16 : 1, Q = (L >= 16 ? 16 : L) / R;
+#pragma unroll
+    for (int q = 0; q < Q; ++q) {
+        const int j = tid + q * T;
+        if (NS > 1) {
+            // w^{r k} = e^{-i pi r t / L}, t = 2 k L / (NS R): each power from the
+            // table (correctly rounded; products of powers would add roundings)
+            const int k = j & (NS - 1), t = 2 * k * (L / (NS * R));
+#pragma unroll
+            for (int r = 1; r < R; ++r) {
+                const cplx w = tw_at(tw, r * t, L);
+                a[q * R + r] = cmul(a[q * R + r], inv ? cconj(w) : w);
+            }
+        }
+        dft_reg<R>(a + q * R, inv);
+    }
+}
+
+// Store pass P's outputs into LDS, natural Stockham order.
+template <int LOGL, int P>
+__device__ inline void pass_store(const cplx *a, int tid, cplx *sm) {
+    constexpr int L = 1 << LOGL, R = Passes<LOGL>::radix(P), NS = Passes<LOGL>::ns(P);
+    constexpr int T = L >= 16 ? L / 16 : 1, Q = (L >= 16 ? 16 : L) / R;
+#pragma unroll
+    for (int q = 0; q < Q; ++q) {
+        const int j = tid + q * T, k = j & (NS - 1), base = (j / NS) * NS * R + k;
+#pragma unroll
+        for (int s = 0; s < R; ++s) sm[lds_pad(base + s * NS)] = a[q * R + s];
+    }
+}
+
+// Gather pass P's inputs from LDS.
+template <int LOGL, int P>
+__device__ inline void pass_load(cplx *a, int tid, const cplx *sm) {
+    constexpr int L = 1 << LOGL, R = Passes<LOGL>::radix(P);
+    constexpr int T = L >= 16 ? L / 16 : 1, Q = (L >= 16 ? 16 : L) / R;
+#pragma unroll
+    for (int q = 0; q < Q; ++q) {
+        const int j = tid + q * T;
+#pragma unroll
+        for (int r = 0; r < R; ++r) a[q * R + r] = sm[lds_pad(j + r * (L / R))];
+    }
+}
+
+// Passes P .. end of one transform: compute pass P on a, then for every later
+// pass store, barrier, load, compute.  On return a holds the last pass's
+// outputs (not stored).
+template <int LOGL, int P>
+__device__ inline void run_passes(cplx *a, int tid, bool active, cplx *sm,
+                                  const cplx *__restrict__ tw, bool inv) {
+    if constexpr (P < Passes<LOGL>::kCount) {
+        if (active) pass_compute<LOGL, P>(a, tid, tw, inv);
+        if constexpr (P + 1 < Passes<LOGL>::kCount) {
+            if (active) pass_store<LOGL, P>(a, tid, sm);
+            __syncthreads();
+            if (active) pass_load<LOGL, P + 1>(a, tid, sm);
+            __syncthreads();
+            run_passes<LOGL, P + 1>(a, tid, active, sm, tw, inv);
+        }
+    }
+}
+
+// z_e = (x_{2e}, x_{2e+1}) of a row zero padded beyond n.  The loads are issued
+// unconditionally (from a clamped, in-range address, the value then selected),
+// so a whole gather is in flight at once: a load under a branch would be
+// waited for where the branch rejoins.
+template <typename TI>
+__device__ inline cplx load_pair(const TI *x, int64_t esi, int64_t n, int64_t e) {
+    const int64_t j0 = 2 * e, j1 = j0 + 1;
+    if (esi == 1 && (n & 1) == 0) {  // whole pairs: one 16-byte (8-byte) load
+        const bool in = j0 < n;
+        const TI *p = x + (in ? j0 : 0);
+        if constexpr (sizeof(TI) == 8) {
+            const double2 v = *reinterpret_cast<const double2 *>(p);
+            return in ? cplx{v.x, v.y} : cplx{0.0, 0.0};
+        } else {
+            const float2 v = *reinterpret_cast<const float2 *>(p);
+            return in ? cplx{static_cast<double>(v.x), static_cast<double>(v.y)} : cplx{0.0, 0.0};
+        }
+    }
+    const double re = static_cast<double>(load_if(x, j0 * esi, j0 < n));
+    const double im = static_cast<double>(load_if(x, j1 * esi, j1 < n));
+    return {re, im};
+}
+
+// One row x (n values, element stride esi, zero padded to the period m):
+//   spec != null: the half spectrum X_0 .. X_L of x into spec;
+//   else y = beta y + (x correlated (conj = 1) / convolved (conj = 0) with the
+//   period-m kernel of half spectrum hhat), the first n values, stride eso,
+// with the transforms done as Stockham passes; LOGL = log2(m / 2), m >= 2.
+// Called by every thread of a workgroup of at least max(64, L / 16) threads
+// (the barriers are workgroup-wide); sm: (L + L / 16 + 1) complex of LDS.
+// The first forward pass's inputs z_e, e = j + r L / R, gathered from the row.
+template <int LOGL, typename TI>
+__device__ inline void fft_gather(cplx *a, const TI *x, int64_t esi, int64_t n) {
+    constexpr int L = 1 << LOGL;
+    constexpr int T = L >= 16 ? L / 16 : 1, V = L >= 16 ? 16 : L;
+    constexpr int P0R = Passes<LOGL>::kCount ? Passes<LOGL>::radix(0) : 1;
+    const int tid = threadIdx.x;
+    if (tid >= T) return;
+#pragma unroll
+    for (int q = 0; q < V / P0R; ++q)
+#pragma unroll
+        for (int r = 0; r < P0R; ++r)
+            a[q * P0R + r] = load_pair(x, esi, n, tid + q * T + r * (L / P0R));
+}
+
+// The rest of the row operation, from the gathered inputs in a.
+template <int LOGL, typename TO>
+__device__ inline void fft_row_regs(cplx *a, int64_t n, const cplx *__restrict__ tw,
+                                    const cplx *__restrict__ hhat, int conj, double beta, TO *y,
+                                    int64_t eso, cplx *spec, double *absmax, cplx *sm) {
+    constexpr int L = 1 << LOGL;
+    constexpr int T = L >= 16 ? L / 16 : 1;   // threads holding data
+    constexpr int V = L >= 16 ? 16 : L;       // values per thread
+    const int tid = threadIdx.x;
+    const bool active = tid < T;
+    run_passes<LOGL, 0>(a, tid, active, sm, tw, false);
+    // spectrum Z_f in natural order, f = j + s L / R of the last pass
+    if (active) {
+        constexpr int PL = Passes<LOGL>::kCount ? Passes<LOGL>::kCount - 1 : 0;
+        constexpr int RL = Passes<LOGL>::kCount ? Passes<LOGL>::radix(PL) : 1;
+#pragma unroll
+        for (int q = 0; q < V / RL; ++q)
+#pragma unroll
+            for (int s2 = 0; s2 < RL; ++s2)
+                sm[lds_pad(tid + q * T + s2 * (L / RL))] = a[q * RL + s2];
     }
     __syncthreads();
-    for (int h = 1; h < L; h <<= 1) {  // decimation in time
-        const int stride = L / h;
-        for (int t = tid; t < L / 2; t += nt) {
-            const int pos = t & (h - 1);
-            const int i0 = ((t - pos) << 1) + pos, i1 = i0 + h;
-            const cplx u = z[i0], b = cmul(z[i1], tw[pos * stride]);
-            z[i0] = u + b;
-            z[i1] = u - b;
-        }
-        __syncthreads();
-    }
-    // Pairs (f, L - f): untangle the real spectrum, apply the kernel, re-pack.
-    for (int f = tid; f <= L / 2; f += nt) {
+    // pairs (f, L - f): untangle the real spectrum, apply the kernel, re-pack
+    // (the workgroup has BD = max(64, L / 16) threads)
+    constexpr int BD = L / 16 > 64 ? L / 16 : 64;
+#pragma unroll 1
+    for (int qf = 0; qf < (L / 2 + BD) / BD; ++qf) {
+        const int f = tid + qf * BD;
+        if (f > L / 2) break;
         const int g = (L - f) & (L - 1);
-        const cplx Zf = z[f], Zg = z[g];
+        const cplx Zf = sm[lds_pad(f)], Zg = sm[lds_pad(g)];
         const cplx e = cscale(Zf + cconj(Zg), 0.5);
         const cplx dd = Zf - cconj(Zg);
         const cplx o = {0.5 * dd.y, -0.5 * dd.x};  // -i/2 (Z_f - conj Z_{L-f})
@@ -108,52 +308,87 @@ __global__ __launch_bounds__(1024) void k_fft_rows(const TI *in, int64_t vsi, in
         const cplx Yf = cmul(Xf, Hf), Yg = cmul(Xg, Hg);
         const cplx ep = cscale(Yf + cconj(Yg), 0.5);
         const cplx op = cscale(cmul(Yf - cconj(Yg), cconj(w)), 0.5);
-        z[f] = {ep.x - op.y, ep.y + op.x};  // E' + i O'
+        sm[lds_pad(f)] = {ep.x - op.y, ep.y + op.x};  // E' + i O'
         if (f != 0 && g != f) {
             const cplx ec = cconj(ep), oc = cconj(op);
-            z[g] = {ec.x - oc.y, ec.y + oc.x};
+            sm[lds_pad(g)] = {ec.x - oc.y, ec.y + oc.x};
         }
     }
     if (spec != nullptr) return;
     __syncthreads();
-    for (int h = L / 2; h >= 1; h >>= 1) {  // decimation in frequency, inverse sign
-        const int stride = L / h;
-        for (int t = tid; t < L / 2; t += nt) {
-            const int pos = t & (h - 1);
-            const int i0 = ((t - pos) << 1) + pos, i1 = i0 + h;
-            const cplx u = z[i0], b = z[i1];
-            z[i0] = u + b;
-            z[i1] = cmul(u - b, cconj(tw[pos * stride]));
-        }
-        __syncthreads();
-    }
+    // inverse transform: gather the first pass's inputs from LDS, run, and
+    // write the last pass's outputs (natural order e = j + s L / R) to the row
+    if (active) pass_load<LOGL, 0>(a, tid, sm);
+    __syncthreads();  // every input read before the first pass stores over them
+    run_passes<LOGL, 0>(a, tid, active, sm, tw, true);
     const double scale = 1.0 / static_cast<double>(L);
-    TO *y = out + v * vso;
-    double vmax = 0.0;
-    for (int k = tid; k < L; k += nt) {
-        const cplx zz = z[bitrev(k, logL)];
-        const int64_t j0 = 2 * static_cast<int64_t>(k), j1 = j0 + 1;
-        if (j0 < n) {
-            TO *p = y + j0 * eso;
-            const double val = zz.x * scale;
-            const TO o = static_cast<TO>(beta == 0.0 ? val : beta * static_cast<double>(*p) + val);
-            *p = o;
-            vmax = fmax(vmax, fabs(static_cast<double>(o)));
+    double vmax = 0.0;  // stays 0 in the threads that hold no data
+    constexpr int PL = Passes<LOGL>::kCount ? Passes<LOGL>::kCount - 1 : 0;
+    constexpr int RL = Passes<LOGL>::kCount ? Passes<LOGL>::radix(PL) : 1;
+#pragma unroll
+    for (int q = 0; q < (active ? V / RL : 0); ++q)
+#pragma unroll
+        for (int s2 = 0; s2 < RL; ++s2) {
+            const int64_t e = tid + q * T + s2 * (L / RL);
+            const cplx zz = a[q * RL + s2];
+            const int64_t j0 = 2 * e, j1 = j0 + 1;
+            double v0 = zz.x * scale, v1 = zz.y * scale;
+            if (eso == 1 && j1 < n) {
+                TO *p = y + j0;
+                if (beta != 0.0) {
+                    v0 += beta * static_cast<double>(p[0]);
+                    v1 += beta * static_cast<double>(p[1]);
+                }
+                if constexpr (sizeof(TO) == 8) {
+                    *reinterpret_cast<double2 *>(p) = double2{v0, v1};
+                } else {
+                    *reinterpret_cast<float2 *>(p) =
+                        float2{static_cast<float>(v0), static_cast<float>(v1)};
+                }
+                vmax = fmax(vmax, fmax(fabs(static_cast<double>(static_cast<TO>(v0))),
+                                       fabs(static_cast<double>(static_cast<TO>(v1)))));
+                continue;
+            }
+            if (j0 < n) {
+                TO *p = y + j0 * eso;
+                const TO o = static_cast<TO>(beta == 0.0 ? v0 : beta * static_cast<double>(*p) + v0);
+                *p = o;
+                vmax = fmax(vmax, fabs(static_cast<double>(o)));
+            }
+            if (j1 < n) {
+                TO *p = y + j1 * eso;
+                const TO o = static_cast<TO>(beta == 0.0 ? v1 : beta * static_cast<double>(*p) + v1);
+                *p = o;
+                vmax = fmax(vmax, fabs(static_cast<double>(o)));
+            }
         }
-        if (j1 < n) {
-            TO *p = y + j1 * eso;
-            const double val = zz.y * scale;
-            const TO o = static_cast<TO>(beta == 0.0 ? val : beta * static_cast<double>(*p) + val);
-            *p = o;
-            vmax = fmax(vmax, fabs(static_cast<double>(o)));
-        }
-    }
     if (absmax != nullptr) {  // max |out| for the growth statistic, one atomic per wave
         for (int off = 32; off > 0; off >>= 1) vmax = fmax(vmax, __shfl_xor(vmax, off));
         if ((tid & 63) == 0)
             atomicMax(reinterpret_cast<unsigned long long *>(absmax),
                       static_cast<unsigned long long>(__double_as_longlong(vmax)));
     }
+}
+
+template <int LOGL, typename TI, typename TO>
+__device__ inline void fft_row(const TI *x, int64_t esi, int64_t n, const cplx *__restrict__ tw,
+                               const cplx *__restrict__ hhat, int conj, double beta, TO *y,
+                               int64_t eso, cplx *spec, double *absmax, cplx *sm) {
+    cplx a[16];
+    fft_gather<LOGL, TI>(a, x, esi, n);
+    fft_row_regs<LOGL, TO>(a, n, tw, hhat, conj, beta, y, eso, spec, absmax, sm);
+}
+
+// One row a workgroup: row v of `in` (stride vsi) to row v of `out` (stride vso).
+template <int LOGL, typename TI, typename TO>
+__global__ __launch_bounds__((1 << LOGL) >= 1024 ? (1 << LOGL) / 16 : 64) void k_fft_stockham(
+    const TI *in, int64_t vsi, int64_t esi, int64_t n, const cplx *__restrict__ tw,
+    const cplx *__restrict__ hhat, int conj, double beta, TO *out, int64_t vso, int64_t eso,
+    cplx *spec, double *absmax) {
+    extern __shared__ cplx sm[];
+    const int64_t v = blockIdx.x;
+    fft_row<LOGL, TI, TO>(in + v * vsi, esi, n, tw, hhat, conj, beta, out + v * vso, eso, spec,
+                          absmax, sm);
 }
 
 // Period-m kernel h from the multiplier parameters:
@@ -175,35 +410,156 @@ __global__ void k_embed(int kind, const double *p, int64_t n, int m, double *h) 
     }
 }
 
+// The unitary circulant's first column (Section 6, Example exunc, real form):
+// pairing u_j e^{-2 pi i jk/n} with its conjugate partner u_{n-j} gives
+//   c_k = (s_0 + (-1)^k s_{n/2} + 2 sum_{0<j<n/2} cos(2 pi (phi_j - (jk mod n)/n))) / n,
+// (s_{n/2} only for even n).  One thread a column entry; the phases pass
+// through LDS in chunks of 1024.
+__global__ __launch_bounds__(256) void k_unitary_column(const double *__restrict__ phi, int n,
+                                                        double *__restrict__ c) {
+    __shared__ double sp[1024];
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    const int jmax = (n - 1) / 2;  // pairs j = 1 .. jmax
+    const double inv_n = 1.0 / static_cast<double>(n);
+    double acc = 0.0;
+    for (int j0 = 1; j0 <= jmax; j0 += 1024) {
+        const int cnt = min(1024, jmax - j0 + 1);
+        __syncthreads();
+        for (int t = threadIdx.x; t < cnt; t += blockDim.x) sp[t] = phi[j0 + t];
+        __syncthreads();
+        if (k < n) {
+            int t = static_cast<int>((static_cast<int64_t>(j0) * k) % n);  // (j k) mod n
+            for (int q = 0; q < cnt; ++q) {
+                acc += cospi(2.0 * sp[q] - 2.0 * static_cast<double>(t) * inv_n);
+                t += k;
+                if (t >= n) t -= n;
+            }
+        }
+    }
+    if (k >= n) return;
+    double v = 2.0 * acc + (phi[0] < 0.5 ? 1.0 : -1.0);
+    if (n % 2 == 0) v += ((k & 1) ? -1.0 : 1.0) * (phi[n / 2] < 0.5 ? 1.0 : -1.0);
+    c[k] = v * inv_n;
+}
+
+// ---------------------------------------------------------------- batches
+// Circulant multipliers of many systems (n_s <= 1024, so m_s <= 2048 and a
+// row fits one wave).  logl[s] = log2(m_s / 2); the twiddle table of period
+// 2 L sits at tw_pool + tw_off[log2 L]; h and its half spectrum of system s at
+// h_pool + h_off[s] (m_s doubles) and hh_pool + hh_off[s] (L_s + 1 complex).
+template <int LG, typename TI, typename TO>
+__device__ inline void batch_row(const TI *x, int64_t n, const cplx *tw, const cplx *hh, int conj,
+                                 TO *y, cplx *spec, cplx *sm) {
+    fft_row<LG, TI, TO>(x, 1, n, tw, hh, conj, 0.0, y, 1, spec, nullptr, sm);
+}
+
+template <typename TI, typename TO>
+__device__ inline void batch_row_any(int lg, const TI *x, int64_t n, const cplx *tw,
+                                     const cplx *hh, int conj, TO *y, cplx *spec, cplx *sm) {
+    switch (lg) {
+    case 0: batch_row<0, TI, TO>(x, n, tw, hh, conj, y, spec, sm); break;
+    case 1: batch_row<1, TI, TO>(x, n, tw, hh, conj, y, spec, sm); break;
+    case 2: batch_row<2, TI, TO>(x, n, tw, hh, conj, y, spec, sm); break;
+    case 3: batch_row<3, TI, TO>(x, n, tw, hh, conj, y, spec, sm); break;
+    case 4: batch_row<4, TI, TO>(x, n, tw, hh, conj, y, spec, sm); break;
+    case 5: batch_row<5, TI, TO>(x, n, tw, hh, conj, y, spec, sm); break;
+    case 6: batch_row<6, TI, TO>(x, n, tw, hh, conj, y, spec, sm); break;
+    case 7: batch_row<7, TI, TO>(x, n, tw, hh, conj, y, spec, sm); break;
+    case 8: batch_row<8, TI, TO>(x, n, tw, hh, conj, y, spec, sm); break;
+    case 9: batch_row<9, TI, TO>(x, n, tw, hh, conj, y, spec, sm); break;
+    default: batch_row<10, TI, TO>(x, n, tw, hh, conj, y, spec, sm); break;
+    }
+}
+
+// One workgroup per circulant system: the period-m kernel h from the first
+// column c (at c_pool + c_off[s]; as k_embed does for one circulant), then its
+// half spectrum.
+__global__ __launch_bounds__(64) void k_batch_spectrum(
+    const int *__restrict__ nsys, const int *__restrict__ logl, const int64_t *__restrict__ c_off,
+    const int64_t *__restrict__ h_off, const int64_t *__restrict__ hh_off,
+    const int64_t *__restrict__ tw_off, const double *c_pool, double *h_pool, cplx *hh_pool,
+    const cplx *tw_pool) {
+    extern __shared__ cplx sm[];
+    const int s = blockIdx.x, n = nsys[s], lg = logl[s], m = 2 << lg;
+    const double *c = c_pool + c_off[s];
+    double *h = h_pool + h_off[s];
+    for (int j = threadIdx.x; j < m; j += blockDim.x) {
+        double v = 0.0;
+        if (m == n || j < n)
+            v = c[j];
+        else if (j > m - n)
+            v = c[n - (m - j)];
+        h[j] = v;
+    }
+    __syncthreads();
+    batch_row_any<double, double>(lg, h, m, tw_pool + tw_off[lg], nullptr, 0,
+                                  static_cast<double *>(nullptr), hh_pool + hh_off[s], sm);
+}
+
+// Rows of the products M_s = A_s C_s of all circulant systems: row r of the
+// flattened row space (row_start: prefix sums of n_s) is row r - row_start[s]
+// of system s; A in FP64, M in FP32, both ld = n_s.
+__global__ __launch_bounds__(64) void k_batch_fft_rows(
+    int count, const int *__restrict__ row_start, const int *__restrict__ nsys,
+    const int *__restrict__ logl, const int64_t *__restrict__ a_off,
+    const int64_t *__restrict__ m_off, const int64_t *__restrict__ hh_off,
+    const int64_t *__restrict__ tw_off, const double *A, const cplx *hh_pool, const cplx *tw_pool,
+    float *M) {
+    extern __shared__ cplx sm[];
+    const int r = blockIdx.x;
+    int lo = 0, hi = count - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (row_start[mid] <= r) lo = mid; else hi = mid - 1;
+    }
+    const int s = lo, n = nsys[s], lg = logl[s];
+    const int64_t i = r - row_start[s];
+    batch_row_any<double, float>(lg, A + a_off[s] + i * n, n, tw_pool + tw_off[lg],
+                                 hh_pool + hh_off[s], 1, M + m_off[s] + i * n, nullptr, sm);
+}
+
 int log2i(int L) {
     int l = 0;
     while ((1 << l) < L) ++l;
     return l;
 }
 
-int fft_threads(int L) {
-    int t = L / 8;
-    if (t < 64) t = 64;
-    if (t > 1024) t = 1024;
-    return t;
+
+template <int LOGL, typename TI, typename TO>
+hipError_t launch_stockham(const TI *in, int64_t vsi, int64_t esi, int64_t count, int64_t n,
+                           const cplx *tw, const cplx *hhat, int conj, double beta, TO *out,
+                           int64_t vso, int64_t eso, cplx *spec, double *absmax, hipStream_t s) {
+    constexpr int L = 1 << LOGL;
+    const size_t lds = sizeof(cplx) * static_cast<size_t>(L + L / 16 + 1);
+    const int threads = L / 16 > 64 ? L / 16 : 64;
+    static bool attr_set = false;
+    if (!attr_set) {
+        (void)hipFuncSetAttribute(reinterpret_cast<const void *>(&k_fft_stockham<LOGL, TI, TO>),
+                                  hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+        attr_set = true;
+    }
+    hipLaunchKernelGGL((k_fft_stockham<LOGL, TI, TO>), dim3(static_cast<unsigned>(count)),
+                       dim3(threads), lds, s, in, vsi, esi, n, tw, hhat, conj, beta, out, vso, eso,
+                       spec, absmax);
+    return hipGetLastError();
 }
 
 template <typename TI, typename TO>
 hipError_t launch_rows(const TI *in, int64_t vsi, int64_t esi, int64_t count, int64_t n, int m,
                        const cplx *tw, const cplx *hhat, int conj, double beta, TO *out,
                        int64_t vso, int64_t eso, cplx *spec, double *absmax, hipStream_t s) {
-    const int L = m / 2;
-    const size_t lds = sizeof(cplx) * static_cast<size_t>(L);
-    static bool attr_set = false;
-    if (!attr_set) {
-        (void)hipFuncSetAttribute(reinterpret_cast<const void *>(&k_fft_rows<TI, TO>),
-                            hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
-        attr_set = true;
+    if (count > 0x7fffffff) return hipErrorInvalidValue;
+#define RMGE_FFT_CASE(LG)                                                                      \
+    case LG:                                                                                   \
+        return launch_stockham<LG, TI, TO>(in, vsi, esi, count, n, tw, hhat, conj, beta, out, \
+                                           vso, eso, spec, absmax, s);
+    switch (log2i(m / 2)) {
+        RMGE_FFT_CASE(0) RMGE_FFT_CASE(1) RMGE_FFT_CASE(2) RMGE_FFT_CASE(3) RMGE_FFT_CASE(4)
+        RMGE_FFT_CASE(5) RMGE_FFT_CASE(6) RMGE_FFT_CASE(7) RMGE_FFT_CASE(8) RMGE_FFT_CASE(9)
+        RMGE_FFT_CASE(10) RMGE_FFT_CASE(11) RMGE_FFT_CASE(12) RMGE_FFT_CASE(13)
+    default: return hipErrorInvalidValue;
     }
-    hipLaunchKernelGGL((k_fft_rows<TI, TO>), dim3(static_cast<unsigned>(count)),
-                       dim3(fft_threads(L)), lds, s, in, vsi, esi, n, L, log2i(L), tw, hhat, conj,
-                       beta, out, vso, eso, spec, absmax);
-    return hipGetLastError();
+#undef RMGE_FFT_CASE
 }
 
 bool valid_m(int m) { return m >= 2 && m <= 16384 && (m & (m - 1)) == 0; }
@@ -215,6 +571,38 @@ hipError_t fft_twiddles(int m, double *tw, hipStream_t s) {
     const int L = m / 2;
     hipLaunchKernelGGL(k_twiddles, dim3((L + 256) / 256), dim3(256), 0, s, L,
                        reinterpret_cast<cplx *>(tw));
+    return hipGetLastError();
+}
+
+hipError_t unitary_column(const double *phi, int64_t n, double *c, hipStream_t s) {
+    if (n < 1 || n > (int64_t(1) << 20)) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_unitary_column, dim3(static_cast<unsigned>((n + 255) / 256)), dim3(256), 0,
+                       s, phi, static_cast<int>(n), c);
+    return hipGetLastError();
+}
+
+hipError_t batch_fft_spectra(int count, const int *nsys, const int *logl, const int64_t *c_off,
+                             const int64_t *h_off, const int64_t *hh_off, const int64_t *tw_off,
+                             const double *c_pool, double *h_pool, double *hh_pool,
+                             const double *tw_pool, hipStream_t s) {
+    if (count <= 0) return hipSuccess;
+    const size_t lds = sizeof(cplx) * (1024 + 64 + 1);
+    hipLaunchKernelGGL(k_batch_spectrum, dim3(static_cast<unsigned>(count)), dim3(64), lds, s, nsys,
+                       logl, c_off, h_off, hh_off, tw_off, c_pool, h_pool,
+                       reinterpret_cast<cplx *>(hh_pool), reinterpret_cast<const cplx *>(tw_pool));
+    return hipGetLastError();
+}
+
+hipError_t batch_fft_rows(int count, int total_rows, const int *row_start, const int *nsys,
+                          const int *logl, const int64_t *a_off, const int64_t *m_off,
+                          const int64_t *hh_off, const int64_t *tw_off, const double *A,
+                          const double *hh_pool, const double *tw_pool, float *M, hipStream_t s) {
+    if (count <= 0 || total_rows <= 0) return hipSuccess;
+    const size_t lds = sizeof(cplx) * (1024 + 64 + 1);
+    hipLaunchKernelGGL(k_batch_fft_rows, dim3(static_cast<unsigned>(total_rows)), dim3(64), lds, s,
+                       count, row_start, nsys, logl, a_off, m_off, hh_off, tw_off, A,
+                       reinterpret_cast<const cplx *>(hh_pool),
+                       reinterpret_cast<const cplx *>(tw_pool), M);
     return hipGetLastError();
 }
 

@@ -43,12 +43,12 @@ __device__ inline void tile_coords(int bid, int tiles_m, int tiles_n, int &tm, i
     tn = within / gs;
 }
 
+// One BM x BN output tile (tm, tn) of C = alpha A B + beta C with bounds checks.
 // T: arithmetic type, TA: storage type of A (double A may feed a float product).
-template <typename T, typename TA, int BM, int BN, int WGM, int WGN, int BK = 16, int MINB = 2>
-__global__ __launch_bounds__(WGM *WGN * 64, MINB) void k_gemm(int M, int N, int K, T alpha,
-                                                           const TA *A, int64_t lda, const T *B,
-                                                           int64_t ldb, T beta, T *C, int64_t ldc,
-                                                           const int *abort, double *absmax) {
+template <typename T, typename TA, int BM, int BN, int WGM, int WGN, int BK>
+__device__ inline void gemm_tile(int M, int N, int K, T alpha, const TA *A, int64_t lda,
+                                 const T *B, int64_t ldb, T beta, T *C, int64_t ldc,
+                                 double *absmax, int tm, int tn) {
     constexpr int NT = WGM * WGN * 64;
     constexpr int WM = BM / WGM, WN = BN / WGN;
     constexpr int TM = WM / 16, TN = WN / 16;
@@ -62,11 +62,6 @@ __global__ __launch_bounds__(WGM *WGN * 64, MINB) void k_gemm(int M, int N, int 
     __shared__ T As[2][BM * LDA_S];
     __shared__ T Bs[2][BK * LDB_S];
 
-    if (abort != nullptr && *abort != 0) return;
-
-    const int tiles_m = (M + BM - 1) / BM, tiles_n = (N + BN - 1) / BN;
-    int tm, tn;
-    tile_coords(blockIdx.x, tiles_m, tiles_n, tm, tn);
     const int m0 = tm * BM, n0 = tn * BN;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int wm = wave / WGN, wn = wave % WGN;
@@ -170,6 +165,44 @@ __global__ __launch_bounds__(WGM *WGN * 64, MINB) void k_gemm(int M, int N, int 
             atomicMax(reinterpret_cast<unsigned long long *>(absmax),
                       static_cast<unsigned long long>(__double_as_longlong(vmax)));
     }
+}
+
+template <typename T, typename TA, int BM, int BN, int WGM, int WGN, int BK = 16, int MINB = 2>
+__global__ __launch_bounds__(WGM *WGN * 64, MINB) void k_gemm(int M, int N, int K, T alpha,
+                                                           const TA *A, int64_t lda, const T *B,
+                                                           int64_t ldb, T beta, T *C, int64_t ldc,
+                                                           const int *abort, double *absmax) {
+    if (abort != nullptr && *abort != 0) return;
+    const int tiles_m = (M + BM - 1) / BM, tiles_n = (N + BN - 1) / BN;
+    int tm, tn;
+    tile_coords(blockIdx.x, tiles_m, tiles_n, tm, tn);
+    gemm_tile<T, TA, BM, BN, WGM, WGN, BK>(M, N, K, alpha, A, lda, B, ldb, beta, C, ldc, absmax,
+                                           tm, tn);
+}
+
+// Batched products M_s = A_s G_s of many square systems of uneven order (A in
+// FP64, rounded to FP32 on load; G and M in FP32; each row-major with
+// ld = n_s).  Tiles of all systems form one index space: tile_start[s] is the
+// first tile of system s (ceil(n_s / 64)^2 tiles, row-major over the tile
+// grid), tile_start[count] the total; a workgroup finds its system by binary
+// search.  G_s starts at g_off[s] of G, M_s at m_off[s] of M, A_s at a_off[s].
+__global__ __launch_bounds__(256, 2) void k_batch_gemm(int count, const int *__restrict__ tile_start,
+                                                       const int *__restrict__ nsys,
+                                                       const int64_t *__restrict__ a_off,
+                                                       const int64_t *__restrict__ g_off,
+                                                       const int64_t *__restrict__ m_off,
+                                                       const double *A, const float *G, float *M) {
+    const int t = blockIdx.x;
+    int lo = 0, hi = count - 1;
+    while (lo < hi) {  // last s with tile_start[s] <= t
+        const int mid = (lo + hi + 1) >> 1;
+        if (tile_start[mid] <= t) lo = mid; else hi = mid - 1;
+    }
+    const int s = lo, n = nsys[s];
+    const int tiles = (n + 63) / 64, local = t - tile_start[s];
+    gemm_tile<float, double, 64, 64, 2, 2, 16>(n, n, n, 1.0f, A + a_off[s], n, G + g_off[s], n,
+                                               0.0f, M + m_off[s], n, nullptr, local / tiles,
+                                               local % tiles);
 }
 
 // Interior fast path: M % 128 == N % 128 == K % 16 == 0, lda, ldb, ldc even.
@@ -725,6 +758,10 @@ hipError_t round_h_bf16(float *H, int64_t n, uint16_t *Ht, int64_t ldk, hipStrea
 // 120 KB of LDS, so it is single-buffered: the next chunk's global loads are
 // in flight during this chunk's 384 MFMAs a wave and are written after a
 // barrier.
+//
+// With NT = 1 the same kernel is the BF16 Schur update of the BF16 factors
+// (RMGE_BF16): each operand is rounded once to BF16 (relative error up to
+// 2^-9) and the single product x_1 y_1 accumulates in FP32.
 namespace {
 
 typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
@@ -735,16 +772,17 @@ __device__ inline uint4 buf_load16(__amdgpu_buffer_rsrc_t r, int voff, int soff)
     return uint4{v.x, v.y, v.z, v.w};
 }
 
-// ws: the terms of -D (rows, three slabs) then those of E^T (three slabs);
+// ws: the NT terms of -D (rows, NT slabs) then those of E^T (NT slabs);
 // bytes: its size, below 2^31, so every offset fits a buffer load's 32 bits.
+template <int NT>
 __global__ __launch_bounds__(256, 1) void k_update_bf16x3(int M, int N, int Kp,
                                                           const uint16_t *__restrict__ ws,
                                                           int bytes, int ldk, int pstride,
                                                           float *C, int64_t ldc,
                                                           const int *abort) {
     constexpr int BM = 256, BN = 256, BK = 32, LDK = BK + 8;  // LDS row: 80 bytes
-    __shared__ __attribute__((aligned(16))) uint16_t sa[3][BM][LDK];
-    __shared__ __attribute__((aligned(16))) uint16_t sb[3][BN][LDK];
+    __shared__ __attribute__((aligned(16))) uint16_t sa[NT][BM][LDK];
+    __shared__ __attribute__((aligned(16))) uint16_t sb[NT][BN][LDK];
     if (abort != nullptr && *abort != 0) return;
     const int tiles_m = (M + BM - 1) / BM, tiles_n = (N + BN - 1) / BN;
     int tm, tn;
@@ -760,11 +798,11 @@ __global__ __launch_bounds__(256, 1) void k_update_bf16x3(int M, int N, int Kp,
     const __amdgpu_buffer_rsrc_t rs =
         __builtin_amdgcn_make_buffer_rsrc(const_cast<uint16_t *>(ws), 0, bytes, 0x00020000);
     const int va = 2 * ((m0 + pr) * ldk + pk);
-    const int vb = 2 * ((n0 + pr) * ldk + pk + 3 * pstride);
+    const int vb = 2 * ((n0 + pr) * ldk + pk + NT * pstride);
     auto soff = [&](int p, int h, int k) { return 2 * (p * pstride + h * 64 * ldk + k); };
-    uint4 ra[3][4], rb[3][4];
+    uint4 ra[NT][4], rb[NT][4];
 #pragma unroll
-    for (int p = 0; p < 3; ++p)
+    for (int p = 0; p < NT; ++p)
 #pragma unroll
         for (int h = 0; h < 4; ++h) {
             ra[p][h] = buf_load16(rs, va, soff(p, h, 0));
@@ -786,7 +824,7 @@ __global__ __launch_bounds__(256, 1) void k_update_bf16x3(int M, int N, int Kp,
             }
         }
 #pragma unroll
-    for (int p = 0; p < 3; ++p)
+    for (int p = 0; p < NT; ++p)
 #pragma unroll
         for (int h = 0; h < 4; ++h) {
             *reinterpret_cast<uint4 *>(&sa[p][pr + 64 * h][pk]) = ra[p][h];
@@ -800,7 +838,7 @@ __global__ __launch_bounds__(256, 1) void k_update_bf16x3(int M, int N, int Kp,
         const bool more = k0 + BK < Kp;
         if (more) {
 #pragma unroll
-            for (int p = 0; p < 3; ++p)
+            for (int p = 0; p < NT; ++p)
 #pragma unroll
                 for (int h = 0; h < 4; ++h) {
                     ra[p][h] = buf_load16(rs, va, soff(p, h, k0 + BK));
@@ -808,13 +846,13 @@ __global__ __launch_bounds__(256, 1) void k_update_bf16x3(int M, int N, int Kp,
                 }
         }
 #pragma unroll
-        for (int p = 0; p < 3; ++p) {
+        for (int p = 0; p < NT; ++p) {
             bf16x8 fa[8];
 #pragma unroll
             for (int i = 0; i < 8; ++i)
                 fa[i] = *reinterpret_cast<const bf16x8 *>(&sa[p][wm * 128 + i * 16 + lo][8 * hi]);
 #pragma unroll
-            for (int q = 0; p + q < 3; ++q) {
+            for (int q = 0; p + q < NT; ++q) {
                 bf16x8 fb[8];
 #pragma unroll
                 for (int j = 0; j < 8; ++j)
@@ -831,7 +869,7 @@ __global__ __launch_bounds__(256, 1) void k_update_bf16x3(int M, int N, int Kp,
         __syncthreads();
         if (more) {
 #pragma unroll
-            for (int p = 0; p < 3; ++p)
+            for (int p = 0; p < NT; ++p)
 #pragma unroll
                 for (int h = 0; h < 4; ++h) {
                     *reinterpret_cast<uint4 *>(&sa[p][pr + 64 * h][pk]) = ra[p][h];
@@ -876,6 +914,7 @@ __device__ inline void split3(float x, uint16_t &t0, uint16_t &t1, uint16_t &t2)
 // terms as rows of dp (eight k a thread); the rest cut E (K x N, lde) into
 // those of E^T in ep, 32 k x 64 columns a block through LDS so that both the
 // row reads and the k-contiguous writes coalesce.  k in [K, Kp) gets zeros.
+template <int NT>
 __global__ __launch_bounds__(256) void k_split3_panels(const float *__restrict__ D, int64_t ldd,
                                                        int M, const float *__restrict__ E,
                                                        int64_t lde, int N, int K, int Kp,
@@ -897,8 +936,10 @@ __global__ __launch_bounds__(256) void k_split3_panels(const float *__restrict__
         }
         uint16_t *o = dp + static_cast<int64_t>(i) * ldk + k;
         *reinterpret_cast<uint4 *>(o) = pack8(v0);
-        *reinterpret_cast<uint4 *>(o + pstride) = pack8(v1);
-        *reinterpret_cast<uint4 *>(o + 2 * pstride) = pack8(v2);
+        if (NT == 3) {
+            *reinterpret_cast<uint4 *>(o + pstride) = pack8(v1);
+            *reinterpret_cast<uint4 *>(o + 2 * pstride) = pack8(v2);
+        }
         return;
     }
     const int b = static_cast<int>(blockIdx.x) - nbd;
@@ -918,36 +959,50 @@ __global__ __launch_bounds__(256) void k_split3_panels(const float *__restrict__
     for (int u = 0; u < 8; ++u) split3(t[c + u][jj], v0[u], v1[u], v2[u]);
     uint16_t *o = ep + static_cast<int64_t>(j) * ldk + k0 + c;
     *reinterpret_cast<uint4 *>(o) = pack8(v0);
-    *reinterpret_cast<uint4 *>(o + pstride) = pack8(v1);
-    *reinterpret_cast<uint4 *>(o + 2 * pstride) = pack8(v2);
+    if (NT == 3) {
+        *reinterpret_cast<uint4 *>(o + pstride) = pack8(v1);
+        *reinterpret_cast<uint4 *>(o + 2 * pstride) = pack8(v2);
+    }
 }
 
 }  // namespace
 
-hipError_t update_bf16x3(int64_t M, int64_t N, int64_t K, const float *D, int64_t ldd,
-                         const float *E, int64_t lde, float *C, int64_t ldc, uint16_t *ws,
-                         int64_t ldk, int64_t rows, const int *abort, hipStream_t s) {
+hipError_t update_bf16(int terms, int64_t M, int64_t N, int64_t K, const float *D, int64_t ldd,
+                       const float *E, int64_t lde, float *C, int64_t ldc, uint16_t *ws,
+                       int64_t ldk, int64_t rows, const int *abort, hipStream_t s) {
+    if (terms != 1 && terms != 3) return hipErrorInvalidValue;
     if (M <= 0 || N <= 0 || K <= 0) return hipSuccess;
     const int64_t Kp = (K + 31) / 32 * 32;
     if (M > INT32_MAX || N > INT32_MAX || ldk % 8 != 0 || ldk < Kp || rows % 256 != 0 ||
         rows < (M + 255) / 256 * 256 || rows < (N + 255) / 256 * 256)
         return hipErrorInvalidValue;
     const int64_t pstride = rows * ldk;
-    if (12 * pstride > INT32_MAX) return hipErrorInvalidValue;  // buffer offsets are 32-bit
-    uint16_t *dp = ws, *ep = ws + 3 * pstride;
+    if (4 * terms * pstride > INT32_MAX) return hipErrorInvalidValue;  // 32-bit buffer offsets
+    uint16_t *dp = ws, *ep = ws + terms * pstride;
     const int64_t nbd = (M * (Kp / 8) + 255) / 256;
     const int64_t nbe = ((N + 63) / 64) * (Kp / 32);
     if (nbd + nbe > INT32_MAX) return hipErrorInvalidValue;
-    hipLaunchKernelGGL(k_split3_panels, dim3(static_cast<unsigned>(nbd + nbe)), dim3(256), 0, s, D,
-                       ldd, static_cast<int>(M), E, lde, static_cast<int>(N), static_cast<int>(K),
+    auto split = terms == 3 ? k_split3_panels<3> : k_split3_panels<1>;
+    hipLaunchKernelGGL(split, dim3(static_cast<unsigned>(nbd + nbe)), dim3(256), 0, s, D, ldd,
+                       static_cast<int>(M), E, lde, static_cast<int>(N), static_cast<int>(K),
                        static_cast<int>(Kp), dp, ep, ldk, pstride, static_cast<int>(nbd), abort);
     const hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     const int64_t tiles = ((M + 255) / 256) * ((N + 255) / 256);
-    hipLaunchKernelGGL(k_update_bf16x3, dim3(static_cast<unsigned>(tiles)), dim3(256), 0, s,
+    auto upd = terms == 3 ? k_update_bf16x3<3> : k_update_bf16x3<1>;
+    hipLaunchKernelGGL(upd, dim3(static_cast<unsigned>(tiles)), dim3(256), 0, s,
                        static_cast<int>(M), static_cast<int>(N), static_cast<int>(Kp),
-                       static_cast<const uint16_t *>(ws), static_cast<int>(12 * pstride),
+                       static_cast<const uint16_t *>(ws), static_cast<int>(4 * terms * pstride),
                        static_cast<int>(ldk), static_cast<int>(pstride), C, ldc, abort);
+    return hipGetLastError();
+}
+
+hipError_t batch_gemm_f32(int count, int total_tiles, const int *tile_start, const int *nsys,
+                          const int64_t *a_off, const int64_t *g_off, const int64_t *m_off,
+                          const double *A, const float *G, float *M, hipStream_t s) {
+    if (count <= 0 || total_tiles <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_batch_gemm, dim3(static_cast<unsigned>(total_tiles)), dim3(256), 0, s,
+                       count, tile_start, nsys, a_off, g_off, m_off, A, G, M);
     return hipGetLastError();
 }
 

@@ -35,6 +35,16 @@ hipError_t launch_normals_f64(double *out, int64_t count, uint64_t seed, uint64_
                               hipStream_t s);
 hipError_t launch_normals_f32(float *out, int64_t count, uint64_t seed, uint64_t stream,
                               hipStream_t s);
+// The multiplier parameters of many systems in one launch: system s draws
+// cnt[s] normals of stream stream[s] (1: FP32 into g32 + off[s]; otherwise FP64
+// into g64 + off[s]) with seed[s]; chunk_start: count + 1 prefix sums of
+// ceil(cnt / 1024).  All arrays on the device.
+hipError_t batch_normals(int count, int total_chunks, const int *chunk_start, const int64_t *cnt,
+                         const int *stream, const uint64_t *seed, const int64_t *off, float *g32,
+                         double *g64, hipStream_t s);
+// count uniforms in (0, 1) of the same generator (element e = u_{e mod 4} of block e / 4).
+hipError_t launch_uniforms_f64(double *out, int64_t count, uint64_t seed, uint64_t stream,
+                               hipStream_t s);
 
 // --------------------------------------------------------------- gemm.hip
 // C = alpha * A * B + beta * C, row-major.  A is M x K (lda), B is K x N (ldb),
@@ -68,13 +78,21 @@ hipError_t round_h_bf16(float *H, int64_t n, uint16_t *Ht, int64_t ldk, hipStrea
 hipError_t normals_bf16t(float *G, uint16_t *Ht, int64_t n, int64_t ldk, uint64_t seed,
                          uint64_t stream, hipStream_t s);
 // Schur update C <- C - D E (D: M x K, E: K x N, C: M x N, all FP32 row-major)
-// with each operand cut into three BF16 terms and the six leading cross
-// products on the BF16 matrix cores.  ws: workspace of 6 * rows * ldk BF16
-// values, rows % 256 == 0 and >= round_up(max(M, N), 256), ldk % 8 == 0 and
-// >= round_up(K, 32); its contents on entry do not matter.
-hipError_t update_bf16x3(int64_t M, int64_t N, int64_t K, const float *D, int64_t ldd,
-                         const float *E, int64_t lde, float *C, int64_t ldc, uint16_t *ws,
-                         int64_t ldk, int64_t rows, const int *abort, hipStream_t s);
+// on the BF16 matrix cores with FP32 accumulation.  terms = 3: each operand
+// cut into three BF16 terms and the six leading cross products formed (the
+// FP32 product's accuracy); terms = 1: each operand rounded once to BF16.
+// ws: workspace of 2 * terms * rows * ldk BF16 values, rows % 256 == 0 and
+// >= round_up(max(M, N), 256), ldk % 8 == 0 and >= round_up(K, 32); its
+// contents on entry do not matter.
+hipError_t update_bf16(int terms, int64_t M, int64_t N, int64_t K, const float *D, int64_t ldd,
+                       const float *E, int64_t lde, float *C, int64_t ldc, uint16_t *ws,
+                       int64_t ldk, int64_t rows, const int *abort, hipStream_t s);
+// Batched M_s = A_s G_s (FP64 A rounded to FP32, FP32 G and M, square n_s x n_s,
+// ld = n_s) over `count` systems; tile_start (count + 1 ints, device): prefix
+// sums of ceil(n_s / 64)^2; nsys, a_off, g_off, m_off: device arrays.
+hipError_t batch_gemm_f32(int count, int total_tiles, const int *tile_start, const int *nsys,
+                          const int64_t *a_off, const int64_t *g_off, const int64_t *m_off,
+                          const double *A, const float *G, float *M, hipStream_t s);
 hipError_t gemm_f32_a64(int shape, int64_t M, int64_t N, int64_t K, float alpha, const double *A,
                         int64_t lda, const float *B, int64_t ldb, float beta, float *C,
                         int64_t ldc, const int *abort, hipStream_t s, double *absmax = nullptr);
@@ -225,7 +243,27 @@ hipError_t grad_a(const double *GB, int64_t ldgb, const double *X, int64_t ldx, 
 //             for j < n, written as out = beta * out + y.
 //   Vector v, element k lives at in[v * vstride_in + k * estride_in].
 hipError_t fft_twiddles(int m, double *tw, hipStream_t s);
+// First column c (n values) of the random real unitary circulant from the
+// phases phi (n uniforms; those past n/2 unused): the spectrum is
+// u_j = e^{2 pi i phi_j}, u_{n-j} = conj(u_j) for 0 < j < n/2, u_0 and (even n)
+// u_{n/2} = +1 if their phase is below 1/2 else -1; c = Omega^{-1} u,
+// c_k = (1/n) sum_j u_j e^{-2 pi i j k / n}.
+hipError_t unitary_column(const double *phi, int64_t n, double *c, hipStream_t s);
 hipError_t fft_embed(int kind, const double *params, int64_t n, int m, double *h, hipStream_t s);
+// Circulant multipliers of a batch (orders n_s <= 1024, periods m_s = 2^(logl_s + 1)
+// <= 2048): per system, the period-m kernel h (h_pool + h_off[s]) from the first
+// column (c_pool + c_off[s]) and its half spectrum (hh_pool + 2 hh_off[s] doubles,
+// L_s + 1 complex); twiddles of period 2^(l + 1) at tw_pool + 2 tw_off[l].
+hipError_t batch_fft_spectra(int count, const int *nsys, const int *logl, const int64_t *c_off,
+                             const int64_t *h_off, const int64_t *hh_off, const int64_t *tw_off,
+                             const double *c_pool, double *h_pool, double *hh_pool,
+                             const double *tw_pool, hipStream_t s);
+// Rows of M_s = A_s C_s (A FP64 at a_off[s], M FP32 at m_off[s], ld = n_s) for
+// all circulant systems; row_start: count + 1 prefix sums of n_s.
+hipError_t batch_fft_rows(int count, int total_rows, const int *row_start, const int *nsys,
+                          const int *logl, const int64_t *a_off, const int64_t *m_off,
+                          const int64_t *hh_off, const int64_t *tw_off, const double *A,
+                          const double *hh_pool, const double *tw_pool, float *M, hipStream_t s);
 hipError_t fft_spectrum(const double *h, int m, const double *tw, double *hhat, hipStream_t s);
 template <typename TI, typename TO>
 hipError_t fft_rows(const TI *in, int64_t vstride_in, int64_t estride_in, int64_t count,

@@ -10,7 +10,9 @@
 //   Box-Muller on (u_0, u_1) and (u_2, u_3):
 //   z_0 = sqrt(-2 ln u_0) cos(2 pi u_1), z_1 = sqrt(-2 ln u_0) sin(2 pi u_1),
 //   z_2, z_3 likewise; element e of a stream is z_{e mod 4} of block e / 4.
-//   Streams: 1 Gaussian G (element i*n+j = G[i][j]), 2 circulant c, 3 Toeplitz tau.
+//   Streams: 1 Gaussian G (element i*n+j = G[i][j]), 2 circulant c, 3 Toeplitz tau,
+//   4 the phases of the unitary circulant (the uniforms themselves: element e
+//   is u_{e mod 4} of block e / 4).
 //
 // Bound: HBM write of the output (8 or 4 bytes per element) plus ~300 VALU
 // operations per block of four; one thread computes one block.
@@ -88,6 +90,19 @@ __global__ __launch_bounds__(256) void k_normals(T *__restrict__ out, int64_t co
     }
 }
 
+__global__ __launch_bounds__(256) void k_uniforms(double *__restrict__ out, int64_t count,
+                                                  uint64_t seed, uint64_t stream) {
+    const int64_t nblocks = (count + 3) / 4;
+    const int64_t step = static_cast<int64_t>(gridDim.x) * blockDim.x;
+    for (int64_t m = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x; m < nblocks;
+         m += step) {
+        uint64_t w[4];
+        Philox4x64::block(static_cast<uint64_t>(m), stream, seed, w);
+        for (int j = 0; j < 4; ++j)
+            if (4 * m + j < count) out[4 * m + j] = to_uniform(w[j]);
+    }
+}
+
 template <typename T>
 hipError_t launch_normals(T *out, int64_t count, uint64_t seed, uint64_t stream, hipStream_t s) {
     if (count <= 0) return hipSuccess;
@@ -149,11 +164,65 @@ __global__ __launch_bounds__(256) void k_normals_bf16t(float *__restrict__ G,
     }
 }
 
+// The multipliers of many systems in one launch.  Parameters of all systems
+// form one index space of chunks of 1024 normals (256 blocks of four):
+// chunk_start[s] is system s's first chunk (prefix sums, chunk_start[count]
+// the total).  System s draws cnt[s] normals of stream stream[s] with seed
+// seed[s], element e = output e mod 4 of block e / 4 as in k_normals: a dense
+// Gaussian multiplier (stream 1, cnt = n^2) as FP32 values into g32 + off[s],
+// a circulant's first column (stream 2, cnt = n) as FP64 into g64 + off[s].
+__global__ __launch_bounds__(256) void k_batch_normals(
+    int count, const int *__restrict__ chunk_start, const int64_t *__restrict__ cnt,
+    const int *__restrict__ stream, const uint64_t *__restrict__ seed,
+    const int64_t *__restrict__ off, float *g32, double *g64) {
+    const int c = blockIdx.x;
+    int lo = 0, hi = count - 1;
+    while (lo < hi) {  // last s with chunk_start[s] <= c
+        const int mid = (lo + hi + 1) >> 1;
+        if (chunk_start[mid] <= c) lo = mid; else hi = mid - 1;
+    }
+    const int s = lo;
+    const int64_t m = static_cast<int64_t>(c - chunk_start[s]) * 256 + threadIdx.x;
+    const int64_t total = cnt[s];
+    if (4 * m >= total) return;
+    uint64_t w[4];
+    Philox4x64::block(static_cast<uint64_t>(m), static_cast<uint64_t>(stream[s]), seed[s], w);
+    double z[4];
+    box_muller(w, z);
+    for (int j = 0; j < 4; ++j) {
+        const int64_t e = 4 * m + j;
+        if (e >= total) break;
+        if (stream[s] == 1)
+            g32[off[s] + e] = static_cast<float>(z[j]);
+        else
+            g64[off[s] + e] = z[j];
+    }
+}
+
 }  // namespace
+
+hipError_t batch_normals(int count, int total_chunks, const int *chunk_start, const int64_t *cnt,
+                         const int *stream, const uint64_t *seed, const int64_t *off, float *g32,
+                         double *g64, hipStream_t s) {
+    if (count <= 0 || total_chunks <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_batch_normals, dim3(static_cast<unsigned>(total_chunks)), dim3(256), 0, s,
+                       count, chunk_start, cnt, stream, seed, off, g32, g64);
+    return hipGetLastError();
+}
 
 hipError_t launch_normals_f64(double *out, int64_t count, uint64_t seed, uint64_t stream,
                               hipStream_t s) {
     return launch_normals<double>(out, count, seed, stream, s);
+}
+
+hipError_t launch_uniforms_f64(double *out, int64_t count, uint64_t seed, uint64_t stream,
+                               hipStream_t s) {
+    if (count <= 0) return hipSuccess;
+    int64_t grid = ((count + 3) / 4 + 255) / 256;
+    if (grid > 256 * 64) grid = 256 * 64;
+    hipLaunchKernelGGL(k_uniforms, dim3(static_cast<unsigned>(grid)), dim3(256), 0, s, out, count,
+                       seed, stream);
+    return hipGetLastError();
 }
 
 hipError_t launch_normals_f32(float *out, int64_t count, uint64_t seed, uint64_t stream,

@@ -76,9 +76,15 @@ def _k32(LU, n):
     return k
 
 
-@pytest.mark.parametrize("prec,pivot", [("F64", "PIVOT_NONE"), ("F32", "PIVOT_BLOCK")])
+@pytest.mark.parametrize("prec,pivot", [("F64", "PIVOT_NONE"), ("F32", "PIVOT_BLOCK"),
+                                        ("F32_BF16X2", "PIVOT_BLOCK")])
 def test_fullsize_factors_sampled(rmge, big, prec, pivot):
     A, Ah, _, _, G, _ = big
+    split = prec == "F32_BF16X2"
+    if split:  # the split path's multiplier is the draw rounded to BF16
+        from test_gpu_split16 import _bf16
+
+        G = _bf16(G)
     f = rmge.factor(A, kind=rmge.GAUSSIAN, seed=BENCH_SEED + 1000, block=256,
                     prec=getattr(rmge, prec), pivot=getattr(rmge, pivot))
     assert f.ok, f.status
@@ -97,26 +103,65 @@ def test_fullsize_factors_sampled(rmge, big, prec, pivot):
         Ucol = np.where(k <= j, LU[:m + 1, j], 0.0)
         lu_ij = float(Lrow @ Ucol)
         m_ij = float(Ah[perm[i]] @ G[:, j])
-        # FP32: M itself is the FP32 product of A rounded to FP32 and G rounded to FP32
-        mbound = 2 * (N + 4) * u * float(np.abs(Ah[perm[i]]) @ np.abs(G[:, j]))
+        # FP32: M itself is the FP32 product of A rounded to FP32 and G rounded to FP32;
+        # split: A in two BF16 terms (2^-17 relative left out) times the BF16 G
+        mbound = (2 * (N + 4) * u + (2.0 ** -17 if split else 0.0)) * float(
+            np.abs(Ah[perm[i]]) @ np.abs(G[:, j]))
         bound = 8 * N * u * k32 * float(np.abs(Lrow) @ np.abs(Ucol)) + mbound
         assert abs(lu_ij - m_ij) <= bound, (i, j, lu_ij, m_ij, bound)
 
 
-@pytest.mark.parametrize("path", ["f64", "f32pg"])
+# the bench's paths: (multiplier, factor precision, row exchanges, refinement)
+FULL_PATHS = {"f64": ("GAUSSIAN", "F64", "PIVOT_NONE", "ir"),
+              "f32pg": ("GAUSSIAN", "F32", "PIVOT_BLOCK", "gmres"),
+              "f32xpg": ("GAUSSIAN", "F32_BF16X2", "PIVOT_BLOCK", "gmres"),
+              "u64": ("UNITARY_CIRCULANT", "F64", "PIVOT_NONE", "ir"),
+              "u32xg": ("UNITARY_CIRCULANT", "F32_BF16X2", "PIVOT_NONE", "gmres")}
+
+
+@pytest.mark.parametrize("path", sorted(FULL_PATHS))
 def test_fullsize_solve_backward_error(rmge, big, path):
     A, Ah, b, bh, _, _ = big
-    if path == "f64":
-        f = rmge.factor(A, kind=rmge.GAUSSIAN, seed=BENCH_SEED + 1000, block=256)
+    kind, prec, pivot, method = FULL_PATHS[path]
+    f = rmge.factor(A, kind=getattr(rmge, kind), seed=BENCH_SEED + 1000, block=256,
+                    prec=getattr(rmge, prec), pivot=getattr(rmge, pivot))
+    assert f.ok, f.status
+    if method == "ir":
         X, st = f.solve(b, max_refine=16, tol=1e-14)
     else:
-        f = rmge.factor(A, kind=rmge.GAUSSIAN, seed=BENCH_SEED + 1000, block=256, prec=rmge.F32,
-                        pivot=rmge.PIVOT_BLOCK)
         X, st = f.solve_gmres(b, max_iters=200, restart=32, tol=1e-14)
     assert st["converged"], st
     eta = _eta(Ah, host(X)[:, 0], bh[:, 0])
     assert eta <= 1e-14, (eta, st["eta"])
     assert eta == pytest.approx(st["eta"], rel=0.5, abs=1e-15)
+
+
+@pytest.mark.parametrize("kind,n", [("CIRCULANT", 16384), ("UNITARY_CIRCULANT", 16384),
+                                    ("TOEPLITZ", 8192), ("CIRCULANT", 5000)])
+def test_fullsize_fft_product_rows(rmge, kind, n):
+    # the FFT launch at its largest period, m = 16384 (n = 16384 circulants;
+    # n = 8192 Toeplitz and n = 5000 circulant embedded in m = 16384), sampled
+    # rows against the oracle's plain product with its dense multiplier:
+    # |M_g - M_o| <= 16 u log2(m) ||a_i|| ||h|| per row (sqrt 2 more when embedded)
+    import math
+
+    k = getattr(rmge, kind)
+    A = workloads.gaussian_torch(n, seed=n)
+    M = rmge.precondition(A, k, seed=55)
+    rows = np.random.default_rng(n).integers(0, n, 12)
+    Ah = host(A[rows])
+    Mg = host(M[rows])
+    H = oracle.multiplier(k, n, 55)
+    Mo = oracle.matmul(Ah, H)
+    del H
+    circ = kind != "TOEPLITZ"
+    m = 16384
+    hnorm = np.linalg.norm(oracle.multiplier_params(k, n, 55))
+    if not (circ and n == m):
+        hnorm *= math.sqrt(2)
+    bound = 16 * EPS * math.log2(m) * np.linalg.norm(Ah, axis=1) * hnorm
+    err = np.abs(Mg - Mo).max(axis=1)
+    assert (err <= bound).all(), float((err / bound).max())
 
 
 @pytest.fixture(scope="module")

@@ -71,6 +71,18 @@ def test_multiplier_params_match_oracle(rmge, kind, n):
     assert not bad.any(), (np.argwhere(bad)[:5], g[bad][:5], o[bad][:5])
 
 
+@pytest.mark.parametrize("n", [1, 2, 3, 4, 5, 64, 1000, 4096, 16384])
+def test_unitary_column_matches_oracle(rmge, n):
+    # c_k = (1/n) sum of n unit-modulus terms, each within a few ulps on both
+    # sides (device: real pairs with cospi; oracle: complex sum with cos, sin)
+    seed = 4321 + n
+    g = host(rmge.multiplier_params(rmge.UNITARY_CIRCULANT, n, seed))
+    o = oracle.multiplier_params(oracle.UNITARY_CIRCULANT, n, seed)
+    assert g.shape == o.shape == (n,)
+    err = np.abs(g - o).max()
+    assert err <= 64 * EPS, err
+
+
 def _check_product(kind, n, A, M, seed):
     H = oracle.multiplier(kind, n, seed)
     Mo = oracle.matmul(A, H)
@@ -79,9 +91,10 @@ def _check_product(kind, n, A, M, seed):
         err = np.abs(M - Mo)
         assert (err <= bound).all(), float((err / bound).max())
     else:
-        m = n if (kind == 2 and n >= 2 and n & (n - 1) == 0) else max(2, 1 << (2 * n - 2).bit_length())
+        circ = kind in (2, 4)
+        m = n if (circ and n >= 2 and n & (n - 1) == 0) else max(2, 1 << (2 * n - 2).bit_length())
         hnorm = np.linalg.norm(oracle.multiplier_params(kind, n, seed))
-        if kind == 2 and m != n:
+        if circ and m != n:
             hnorm *= math.sqrt(2)
         row_bound = 16 * EPS * max(1, math.log2(m)) * np.linalg.norm(A, axis=1) * hnorm
         err = np.abs(M - Mo).max(axis=1)
@@ -89,13 +102,30 @@ def _check_product(kind, n, A, M, seed):
     return Mo
 
 
-@pytest.mark.parametrize("kind", [0, 1, 2, 3])
+@pytest.mark.parametrize("kind", [0, 1, 2, 3, 4])
 @pytest.mark.parametrize("n", [1, 2, 7, 64, 128, 129, 300, 384, 512, 517])
 def test_precondition_matches_oracle(rmge, kind, n):
     # n a multiple of 128 takes the interior (unchecked) product kernel
     A = workloads.conditioned(n, 1e3, seed=n)
     M = host(rmge.precondition(dev(A), kind, seed=77))
     _check_product(kind, n, A, M, 77)
+
+
+@pytest.mark.parametrize("kind,n", [(3, 1100), (2, 4096), (4, 3000), (2, 700), (3, 4000)])
+def test_precondition_multiwave_rows(rmge, kind, n):
+    # periods m = 4096 .. 8192: one row spans several waves of a workgroup;
+    # 16 sampled rows against the oracle's plain product
+    A = np.random.default_rng(n).standard_normal((n, n)) / np.sqrt(n)
+    M = host(rmge.precondition(dev(A), kind, seed=31))
+    rows = np.random.default_rng(n + 1).integers(0, n, 16)
+    H = oracle.multiplier(kind, n, 31)
+    Mo = oracle.matmul(A[rows], H)
+    circ = kind in (2, 4)
+    m = n if (circ and n & (n - 1) == 0) else 1 << (2 * n - 2).bit_length()
+    hnorm = np.linalg.norm(oracle.multiplier_params(kind, n, 31)) * (1 if m == n else math.sqrt(2))
+    bound = 16 * EPS * math.log2(m) * np.linalg.norm(A[rows], axis=1) * hnorm
+    err = np.abs(M[rows] - Mo).max(axis=1)
+    assert (err <= bound).all(), float((err / bound).max())
 
 
 def _kappa32(L, U):
@@ -113,7 +143,7 @@ def _kappa_leading(M):
     return max(np.linalg.cond(M[:k, :k]) for k in ks)
 
 
-@pytest.mark.parametrize("kind", [1, 2, 3])
+@pytest.mark.parametrize("kind", [1, 2, 3, 4])
 @pytest.mark.parametrize("n,block", [(64, 64), (129, 32), (300, 256), (300, 100), (517, 256),
                                      (517, 128), (200, 7), (96, 1), (45, 2), (77, 3), (512, 256),
                                      (384, 128)])
@@ -173,7 +203,7 @@ def test_breakdown_case_preprocessed(rmge, seed, block):
     assert rel <= max(1e-10, 2 * kappa * (st["eta"] + so.eta[-1])), rel
 
 
-@pytest.mark.parametrize("kind", [0, 1, 2, 3])
+@pytest.mark.parametrize("kind", [0, 1, 2, 3, 4])
 @pytest.mark.parametrize("n,nrhs,kappa", [(70, 1, 1e2), (300, 3, 1e6), (517, 8, 1e2),
                                           (129, 17, 1e4)])
 def test_solve_matches_oracle(rmge, kind, n, nrhs, kappa):
@@ -192,7 +222,7 @@ def test_solve_matches_oracle(rmge, kind, n, nrhs, kappa):
     assert rel <= max(1e-10, 2 * kappa * (st["eta"] + so.eta[-1])), rel
 
 
-@pytest.mark.parametrize("kind", [0, 1, 2, 3])
+@pytest.mark.parametrize("kind", [0, 1, 2, 3, 4])
 def test_adjoint_matches_oracle(rmge, kind):
     n, nrhs = 300, 5
     A = workloads.conditioned(n, 1e3, seed=8)
@@ -207,7 +237,7 @@ def test_adjoint_matches_oracle(rmge, kind):
     assert rel <= 1e-9, rel
 
 
-@pytest.mark.parametrize("kind", [1, 2])
+@pytest.mark.parametrize("kind", [1, 2, 4])
 def test_fp32_factors_refined_to_fp64(rmge, kind):
     n = 384
     A = workloads.conditioned(n, 1e2, seed=12)
@@ -235,7 +265,7 @@ def test_block_size_invariance(rmge):
         assert rel <= 1e-10, (block, rel)
 
 
-@pytest.mark.parametrize("kind", [0, 1, 2, 3])
+@pytest.mark.parametrize("kind", [0, 1, 2, 3, 4])
 @pytest.mark.parametrize("prec", ["F64", "F32"])
 def test_adjoint_refined_matches_oracle(rmge, kind, prec):
     n, nrhs, kappa = 300, 3, 1e3

@@ -23,6 +23,13 @@ U Sigma V^T with U, V the Q factors of QR factorizations of random matrices):
 * ``rhs(n, nrhs, seed)``: i.i.d. N(0, 1).
 * ``gaussian_torch(n, seed)``: an i.i.d. N(0, 1/n) matrix made on the GPU with
   no factorization; used where only the shape matters (hardware counters).
+* ``batch_table(count, seed)``: the batching workload's systems: orders
+  uniform on {32, ..., 1024}, multiplier kind Gaussian or circulant with
+  probability 1/2 each, kappa = 10^(1 + 5 u), a multiplier seed each, and the
+  offsets of each A_s (n x n, row-major) and b_s, x_s in flat buffers;
+  ``batch_inputs_torch(table, seed)`` builds the matrices on the GPU as
+  ``conditioned`` does (QR of Gaussian matrices, batched over equal orders)
+  and the right-hand sides.
 
 The torch variants build the same recipes on a GPU for sizes where a CPU QR
 would take minutes; they are not bitwise equal to the numpy ones.
@@ -138,3 +145,57 @@ def rhs_torch(n: int, nrhs: int, seed: int, device="cuda"):
     g = torch.Generator(device=device)
     g.manual_seed(int(seed) * 1000003 + 29)
     return torch.randn((n, nrhs), generator=g, dtype=torch.float64, device=device)
+
+
+def batch_table(count: int, seed: int, n_lo: int = 32, n_hi: int = 1024,
+                log_kappa: tuple = (1.0, 6.0)) -> list:
+    """(n, kind, multiplier seed, a_off, v_off, kappa) for each system (kind 1
+    Gaussian, 2 circulant)."""
+    rng = _rng(seed, 7)
+    ns = rng.integers(n_lo, n_hi + 1, size=count)
+    kinds = np.where(rng.random(count) < 0.5, 1, 2)
+    kappas = 10.0 ** (log_kappa[0] + (log_kappa[1] - log_kappa[0]) * rng.random(count))
+    out, a_off, v_off = [], 0, 0
+    for i in range(count):
+        n = int(ns[i])
+        out.append((n, int(kinds[i]), int(seed) * 100003 + i, a_off, v_off, float(kappas[i])))
+        a_off += n * n
+        v_off += n
+    return out
+
+
+def batch_inputs_torch(table, seed: int, device="cuda"):
+    """Flat float64 tensors A (every A_s row-major at its offset) and B (every
+    b_s), built on the GPU: A_s = Q1 diag(sigma) Q2^T with Haar Q1, Q2 from
+    batched QR over the systems of one order."""
+    import torch
+
+    a_total = sum(t[0] * t[0] for t in table)
+    v_total = sum(t[0] for t in table)
+    A = torch.empty(a_total, dtype=torch.float64, device=device)
+    g = torch.Generator(device=device)
+    g.manual_seed(int(seed) * 1000003 + 53)
+    by_n = {}
+    for i, t in enumerate(table):
+        by_n.setdefault(t[0], []).append(i)
+    for n, idx in sorted(by_n.items()):
+        k = len(idx)
+
+        def _haar():
+            X = torch.randn((k, n, n), generator=g, dtype=torch.float64, device=device)
+            Q, R = torch.linalg.qr(X)
+            sgn = torch.sign(torch.diagonal(R, dim1=-2, dim2=-1))
+            sgn[sgn == 0] = 1.0
+            return Q * sgn[:, None, :]
+
+        Q1, Q2 = _haar(), _haar()
+        sig = torch.stack([torch.as_tensor(sigma_profile(n, table[i][5]), device=device)
+                           for i in idx])
+        As = torch.bmm(Q1 * sig[:, None, :], Q2.transpose(1, 2).contiguous())
+        for j, i in enumerate(idx):
+            off = table[i][3]
+            A[off:off + n * n] = As[j].reshape(-1)
+    gb = torch.Generator(device=device)
+    gb.manual_seed(int(seed) * 1000003 + 59)
+    B = torch.randn(v_total, generator=gb, dtype=torch.float64, device=device)
+    return A, B
