@@ -498,9 +498,11 @@ def batching(args):
     FP32 factors on the matrix cores and FP64 GMRES refinement to eta <= 1e-14,
     every step one replay of the HIP graph that holds the whole run (multipliers,
     products, factorizations, refinement).  Panel widths per size bucket from the
-    library's autotuner (cached as JSON).  The roofline line is the factorization
-    phase (algorithmic 2/3 n^3 flops per system against the FP32 matrix-core
-    peak), timed by HIP events in an eager run of the same batch."""
+    library's autotuner (cached as JSON).  A system whose FP32-preconditioned
+    refinement stalls is solved again from FP64 factors inside the same graph.
+    The roofline line is the factorization phase (algorithmic 2/3 n^3 flops per
+    system against the FP32 matrix-core peak), timed by HIP events in an eager
+    run of the same batch."""
     import numpy as np
     import torch
 
@@ -515,13 +517,14 @@ def batching(args):
     X = torch.zeros_like(B)
     torch.cuda.synchronize()
     systems = [(t[0], t[1], t[2], t[3], t[4]) for t in table]
-    bt = rmge.Batch(systems, restart=args.restart, max_iters=args.max_iters)
+    bt = rmge.Batch(systems, restart=args.restart, max_iters=args.batch_iters)
     name = torch.cuda.get_device_properties(0).gcnArchName.split(":")[0]
     key = "%s/count%d/seed%d/lib%d" % (name, count, args.seed, rmge._rmge.lib().rmge_version())
     nb, cached = bt.autotune_cached(A, key)
     log("panel widths per bucket %s (%s)" % (nb, "cache" if cached else "autotuned"))
     phases = bt.run_timed(A, B, X, tol=ETA_TARGET)
-    log("eager run: products %.2f ms, factorizations %.2f ms, refinement %.2f ms" % phases)
+    log("eager run: products %.2f ms, factorizations %.2f ms, refinement %.2f ms, FP64 "
+        "fallback %.2f ms" % phases)
     for _ in range(args.warmup):
         bt.run(A, B, X, tol=ETA_TARGET, graph=True)
     torch.cuda.synchronize()
@@ -536,9 +539,11 @@ def batching(args):
     lu_flops = float(np.sum(2.0 / 3.0 * ns ** 3))
     ok = res["status"] == 0
     conv_eta = res["eta"][ok]
-    log("%.2f ms/step, %d of %d converged, max eta %.2e, median iterations %d"
-        % (dt * 1e3, int(ok.sum()), count, float(conv_eta.max()) if ok.any() else float("nan"),
-           int(np.median(res["iters"]))))
+    fb = res["fp64"] == 1
+    log("%.2f ms/step, %d of %d converged (%d of them from FP64 factors after the FP32 stage), "
+        "max eta %.2e, median iterations %d"
+        % (dt * 1e3, int(ok.sum()), count, int((ok & fb).sum()),
+           float(conv_eta.max()) if ok.any() else float("nan"), int(np.median(res["iters"]))))
     achieved = lu_flops / (phases[1] * 1e-3) / 1e12
     out = {
         "metric": "batched factor+solve TFLOP/s: %d systems n~U{32..1024}, FP32 MFMA + FP64 "
@@ -558,7 +563,7 @@ def batching(args):
                                "circulant multiplier (1/2 each), kappa=10^(1+5u), 1 RHS each, "
                                "one HIP graph a step" % count,
                    "count": count, "seed": args.seed, "restart": args.restart,
-                   "max_iters": args.max_iters, "panel_widths": nb,
+                   "max_iters": args.batch_iters, "panel_widths": nb,
                    "tuning_from_cache": cached},
         "roofline": {"bound": "mfma", "achieved": round(achieved, 3), "peak": PEAK["f32"],
                      "unit": "TFLOP/s", "frac": round(achieved / PEAK["f32"], 4),
@@ -566,8 +571,11 @@ def batching(args):
                      "kernel": "k_batch_factor (all size buckets; 2/3 n^3 flops a system)",
                      "ms_per_launch": round(phases[1], 4)},
         "phases_ms": {"products": round(phases[0], 3), "factorizations": round(phases[1], 3),
-                      "refinement": round(phases[2], 3)},
-        "results": {"converged": int(ok.sum()), "zero_pivot": int((res["status"] == 4).sum()),
+                      "refinement": round(phases[2], 3), "fp64_fallback": round(phases[3], 3)},
+        "results": {"converged": int(ok.sum()),
+                    "converged_fp32_factors": int((ok & ~fb).sum()),
+                    "converged_after_fp64_fallback": int((ok & fb).sum()),
+                    "zero_pivot": int((res["status"] == 4).sum()),
                     "nonfinite": int((res["status"] == 5).sum()),
                     "not_converged": int((res["status"] == 6).sum()),
                     "max_eta_converged": float(conv_eta.max()) if ok.any() else None,
@@ -633,6 +641,9 @@ def main():
                     help="precision: seeds LO-HI (kappa = 10^(1 + 7u) each), one JSON line with "
                          "each path's result per seed")
     ap.add_argument("--restart", type=int, default=16, help="batching: GMRES restart")
+    ap.add_argument("--batch-iters", type=int, default=32,
+                    help="batching: GMRES iterations a system gets with FP32 factors before it "
+                         "is solved again from FP64 factors")
     ap.add_argument("--n", type=int, default=None, help="16384 (precision) or 8192 "
                                                          "(differentiation)")
     ap.add_argument("--seed", type=int, default=1)

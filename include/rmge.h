@@ -315,7 +315,10 @@ rmge_status rmge_schur_update_f32(int64_t M, int64_t N, int64_t K, const float *
  * bucket, see rmge_batch_tuning), then x_s = H_s U_s^{-1} L_s^{-1} b_s refined
  * in FP64 by restarted flexible GMRES preconditioned with the factors until
  * eta_s <= tol or max_iters inner iterations, eta the normwise backward error
- * ||b - A x||_inf / (||A||_inf ||x||_inf + ||b||_inf).  The systems are taken
+ * ||b - A x||_inf / (||A||_inf ||x||_inf + ||b||_inf).  A system still above
+ * tol then is solved again from FP64 factors of the same M_s = A_s H_s
+ * (FP64 product, GENP with pivot blocks of 32, the same refinement), and its
+ * result says so.  The systems are taken
  * largest first by persistent kernels; nothing is synchronised or allocated
  * while running, so a run can be captured into a HIP graph
  * (rmge_batch_graph_run does that itself).
@@ -340,8 +343,9 @@ typedef struct {
 /* Describe a batch.  systems: host array of count entries (copied).  tuning:
  * NULL for the defaults {32, 32, 32, 64, 64}.  restart: GMRES restart length,
  * 1..32.  max_iters: inner iterations per system.  Allocates the device
- * workspace (for every system: n^2 FP32 factors, (2 restart + 1) n doubles;
- * Gaussian: n^2 FP32 for G; circulant: O(n)).  EINVAL on a bad entry. */
+ * workspace (for every system: n^2 FP32 factors, n^2 doubles for FP64 factors
+ * should it fall back, (2 restart + 1) n doubles; Gaussian: n^2 FP32 for G;
+ * circulant: O(n)).  EINVAL on a bad entry. */
 rmge_status rmge_batch_create(const rmge_batch_system *systems, int32_t count,
                               const rmge_batch_tuning *tuning, int32_t restart, int32_t max_iters,
                               rmge_batch **out);
@@ -354,10 +358,11 @@ rmge_status rmge_batch_run(rmge_batch *b, const double *A, const double *B, doub
                            void *hip_stream);
 
 /* As rmge_batch_run, with HIP events between the phases, synchronised:
- * ms3[0] drawing the multipliers and forming every M_s = A_s H_s, ms3[1] the
- * factorizations, ms3[2] the solves and refinement (host array of 3). */
+ * ms4[0] drawing the multipliers and forming every M_s = A_s H_s, ms4[1] the
+ * factorizations, ms4[2] the solves and refinement, ms4[3] the FP64 fallback
+ * (host array of 4). */
 rmge_status rmge_batch_run_timed(rmge_batch *b, const double *A, const double *B, double *X,
-                                 double tol, void *hip_stream, double *ms3);
+                                 double tol, void *hip_stream, double *ms4);
 
 /* As rmge_batch_run, through a HIP graph: the first call (and any call with
  * other buffers or tol) captures the whole run into a graph on the library's
@@ -368,10 +373,11 @@ rmge_status rmge_batch_graph_run(rmge_batch *b, const double *A, const double *B
 /* Per-system results of the last run, in the order of `systems` (host arrays
  * of count entries, each may be NULL): status (RMGE_OK, RMGE_ZERO_PIVOT,
  * RMGE_NONFINITE or RMGE_NOT_CONVERGED), final eta, eta of the unrefined
- * solution, inner iterations, and the first zero / non-finite pivot's index
- * (-1 if none).  Synchronises hip_stream first. */
+ * solution, inner iterations (both stages), the first zero / non-finite
+ * pivot's index (-1 if none), and 1 where the system was solved again from
+ * FP64 factors.  Synchronises hip_stream first. */
 rmge_status rmge_batch_results(const rmge_batch *b, int32_t *status, double *eta, double *eta0,
-                               int32_t *iters, int64_t *info, void *hip_stream);
+                               int32_t *iters, int64_t *info, int32_t *fp64, void *hip_stream);
 
 rmge_status rmge_batch_get_tuning(const rmge_batch *b, rmge_batch_tuning *t);
 rmge_status rmge_batch_set_tuning(rmge_batch *b, const rmge_batch_tuning *t);

@@ -303,7 +303,8 @@ class Batch:
         return X
 
     def run_timed(self, A, B, X, tol=1e-14):
-        """An eager run with HIP events between the phases: (products, factor, refine) ms."""
+        """An eager run with HIP events between the phases: (products, factorizations,
+        refinement, FP64 fallback) in ms."""
         rc, ms = _rmge.rmge_batch_run_timed(self._h, A.data_ptr(), B.data_ptr(), X.data_ptr(), tol,
                                             _stream_handle(A.device))
         if rc:
@@ -314,15 +315,15 @@ class Batch:
         import numpy as np
 
         c = self.count
-        st, it = np.zeros(c, np.int32), np.zeros(c, np.int32)
+        st, it, fb = np.zeros(c, np.int32), np.zeros(c, np.int32), np.zeros(c, np.int32)
         eta, eta0, info = np.zeros(c), np.zeros(c), np.zeros(c, np.int64)
         import torch
 
-        rc = _rmge.rmge_batch_results(self._h, st, eta, eta0, it, info,
+        rc = _rmge.rmge_batch_results(self._h, st, eta, eta0, it, info, fb,
                                       _stream_handle(torch.device(device)))
         if rc:
             raise RMGEError(rc, "rmge_batch_results")
-        return {"status": st, "eta": eta, "eta0": eta0, "iters": it, "info": info}
+        return {"status": st, "eta": eta, "eta0": eta0, "iters": it, "info": info, "fp64": fb}
 
     def tuning(self):
         rc, nb = _rmge.rmge_batch_get_tuning(self._h)

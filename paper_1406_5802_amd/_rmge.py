@@ -107,7 +107,7 @@ def lib() -> ctypes.CDLL:
     L.rmge_batch_graph_run.argtypes = [vp, dp, dp, dp, ctypes.c_double, vp]
     L.rmge_batch_run_timed.argtypes = [vp, dp, dp, dp, ctypes.c_double, vp,
                                        ctypes.POINTER(ctypes.c_double)]
-    L.rmge_batch_results.argtypes = [vp, vp, vp, vp, vp, vp, vp]
+    L.rmge_batch_results.argtypes = [vp, vp, vp, vp, vp, vp, vp, vp]
     L.rmge_batch_get_tuning.argtypes = [vp, bp]
     L.rmge_batch_set_tuning.argtypes = [vp, bp]
     L.rmge_batch_autotune.argtypes = [vp, dp, vp, bp, vp]
@@ -280,21 +280,21 @@ def rmge_batch_run(h, A: int, B: int, X: int, tol: float, stream: int) -> int:
 
 
 def rmge_batch_run_timed(h, A: int, B: int, X: int, tol: float, stream: int):
-    ms = (ctypes.c_double * 3)()
+    ms = (ctypes.c_double * 4)()
     rc = lib().rmge_batch_run_timed(h, A, B, X, tol, stream, ms)
-    return rc, (ms[0], ms[1], ms[2])
+    return rc, (ms[0], ms[1], ms[2], ms[3])
 
 
 def rmge_batch_graph_run(h, A: int, B: int, X: int, tol: float, stream: int) -> int:
     return lib().rmge_batch_graph_run(h, A, B, X, tol, stream)
 
 
-def rmge_batch_results(h, status, eta, eta0, iters, info, stream: int) -> int:
-    """Host numpy arrays (int32, float64, float64, int32, int64) or None."""
+def rmge_batch_results(h, status, eta, eta0, iters, info, fp64, stream: int) -> int:
+    """Host numpy arrays (int32, float64, float64, int32, int64, int32) or None."""
     def ptr(a):
         return None if a is None else a.ctypes.data_as(ctypes.c_void_p)
     return lib().rmge_batch_results(h, ptr(status), ptr(eta), ptr(eta0), ptr(iters), ptr(info),
-                                    stream)
+                                    ptr(fp64), stream)
 
 
 def rmge_batch_get_tuning(h):

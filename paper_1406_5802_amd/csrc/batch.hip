@@ -56,7 +56,8 @@ struct BatchOut {
     double *eta;  // final normwise backward error
     double *eta0; // backward error of the unrefined solution
     int64_t *info;  // index of the first zero or non-finite pivot, -1 if none
-    int *tickets; // [0] refinement queue, [1 + k] factor queue of size bucket k
+    int *fp64;      // 1 if the system was solved again from FP64 factors
+    int *tickets;   // [0] refinement, [1 + k] factorization of size bucket k, [6] fallback
 };
 
 __global__ void k_batch_reset(int count, BatchOut out) {
@@ -68,7 +69,18 @@ __global__ void k_batch_reset(int count, BatchOut out) {
         out.eta[i] = 0.0;
         out.eta0[i] = 0.0;
         out.info[i] = -1;
+        out.fp64[i] = 0;
     }
+}
+
+// Lane `src`'s value of x, in every lane (v_readlane; src wave-uniform).
+__device__ inline float lane_value(float x, int src) {
+    return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(x), src));
+}
+__device__ inline double lane_value(double x, int src) {
+    const int lo = __builtin_amdgcn_readlane(__double2loint(x), src);
+    const int hi = __builtin_amdgcn_readlane(__double2hiint(x), src);
+    return __hiloint2double(hi, lo);
 }
 
 // ------------------------------------------------------------------ factor
@@ -90,33 +102,34 @@ __global__ void k_batch_reset(int count, BatchOut out) {
 // These are eq. eqgenp's B^{-1} C and D B^{-1} with B factored, and its Schur
 // update; a zero or non-finite pivot stops the system with its status and
 // index (the pivots' reciprocals multiply, as in the single-system kernels).
-template <int NB>
-__device__ void factor_diag(float *a, int n, int k0, int b, int *status, int64_t *info,
-                            float *sd, float *sinv, int *sflag) {
+// T = float for the batch's factors, double for the FP64 fallback.
+template <int NB, typename T>
+__device__ void factor_diag(T *a, int n, int k0, int b, int *status, int64_t *info, T *sd,
+                            T *sinv, int *sflag) {
     constexpr int LDD = NB + 1;
     const int lane = threadIdx.x & 63;
-    float r[NB];
+    T r[NB];
     const bool in = lane < b;
-    const float *row = a + static_cast<int64_t>(k0 + (in ? lane : 0)) * n + k0;
+    const T *row = a + static_cast<int64_t>(k0 + (in ? lane : 0)) * n + k0;
 #pragma unroll
-    for (int c = 0; c < NB; ++c) r[c] = (c < b && in) ? row[c] : 0.0f;
+    for (int c = 0; c < NB; ++c) r[c] = (c < b && in) ? row[c] : T(0);
     int fail = 0;
 #pragma unroll
     for (int j = 0; j < NB; ++j) {
         if (j < b && fail == 0) {
-            const float p = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(r[j]), j));
-            if (p == 0.0f || !isfinite(p)) {
-                fail = (p == 0.0f) ? RMGE_ZERO_PIVOT : RMGE_NONFINITE;
+            const T p = lane_value(r[j], j);
+            if (p == T(0) || !isfinite(p)) {
+                fail = (p == T(0)) ? RMGE_ZERO_PIVOT : RMGE_NONFINITE;
                 if (lane == 0) {
                     *status = fail;
                     *info = k0 + j;
                 }
             } else {
-                const float inv = 1.0f / p;
+                const T inv = T(1) / p;
                 if (lane > j) r[j] *= inv;
 #pragma unroll
                 for (int c = j + 1; c < NB; ++c) {
-                    const float u = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(r[c]), j));
+                    const T u = lane_value(r[c], j);
                     if (lane > j) r[c] -= r[j] * u;
                 }
             }
@@ -124,7 +137,7 @@ __device__ void factor_diag(float *a, int n, int k0, int b, int *status, int64_t
     }
     if (lane == 0) *sflag = fail;
     if (fail || !in) return;
-    float dg = 1.0f;
+    T dg = T(1);
 #pragma unroll
     for (int c = 0; c < NB; ++c) {
         if (c == lane) dg = r[c];
@@ -133,20 +146,20 @@ __device__ void factor_diag(float *a, int n, int k0, int b, int *status, int64_t
             a[static_cast<int64_t>(k0 + lane) * n + k0 + c] = r[c];
         }
     }
-    sinv[lane] = 1.0f / dg;
+    sinv[lane] = T(1) / dg;
 }
 
 // x <- L11^{-1} x for one column (stride n) of the block row: b unknowns, 16 a
 // round in registers.
-template <int NB>
-__device__ inline void solve_col(float *col, int n, int b, const float *sd) {
+template <int NB, typename T>
+__device__ inline void solve_col(T *col, int n, int b, const T *sd) {
     constexpr int LDD = NB + 1;
     for (int s0 = 0; s0 < b; s0 += 16) {
-        float x[16];
+        T x[16];
 #pragma unroll
         for (int i = 0; i < 16; ++i) x[i] = load_if(col, static_cast<int64_t>(s0 + i) * n, s0 + i < b);
         for (int j = 0; j < s0; ++j) {  // earlier unknowns, already final in memory
-            const float u = col[static_cast<int64_t>(j) * n];
+            const T u = col[static_cast<int64_t>(j) * n];
 #pragma unroll
             for (int i = 0; i < 16; ++i) x[i] -= sd[(s0 + i < b ? s0 + i : 0) * LDD + j] * u;
         }
@@ -161,15 +174,15 @@ __device__ inline void solve_col(float *col, int n, int b, const float *sd) {
 }
 
 // y <- y U11^{-1} for one row of the block column: b unknowns, 16 a round.
-template <int NB>
-__device__ inline void solve_row(float *row, int b, const float *sd, const float *sinv) {
+template <int NB, typename T>
+__device__ inline void solve_row(T *row, int b, const T *sd, const T *sinv) {
     constexpr int LDD = NB + 1;
     for (int s0 = 0; s0 < b; s0 += 16) {
-        float y[16];
+        T y[16];
 #pragma unroll
         for (int j = 0; j < 16; ++j) y[j] = load_if(row, s0 + j, s0 + j < b);
         for (int i = 0; i < s0; ++i) {
-            const float v = row[i];
+            const T v = row[i];
 #pragma unroll
             for (int j = 0; j < 16; ++j) y[j] -= v * sd[i * LDD + (s0 + j < b ? s0 + j : 0)];
         }
@@ -185,14 +198,15 @@ __device__ inline void solve_row(float *row, int b, const float *sd, const float
     }
 }
 
-template <int NB>
-__device__ void factor_system(float *a, int n, int *status, int64_t *info, float *sd, float *sinv,
+template <int NB, typename T>
+__device__ void factor_system(T *a, int n, int *status, int64_t *info, T *sd, T *sinv,
                               int *sflag) {
+    using acc_t = typename Mma<T>::acc;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     constexpr int KS = NB / 4;
     for (int k0 = 0; k0 < n; k0 += NB) {
         const int b = min(NB, n - k0);
-        if (wave == 0) factor_diag<NB>(a, n, k0, b, status, info, sd, sinv, sflag);
+        if (wave == 0) factor_diag<NB, T>(a, n, k0, b, status, info, sd, sinv, sflag);
         __syncthreads();
         if (*sflag != 0) return;
         const int r0 = k0 + b, rest = n - r0;
@@ -200,16 +214,16 @@ __device__ void factor_system(float *a, int n, int *status, int64_t *info, float
         // (b) U12 columns, then L21 rows
         for (int w = tid; w < 2 * rest; w += kBatchThreads) {
             if (w < rest)
-                solve_col<NB>(a + static_cast<int64_t>(k0) * n + r0 + w, n, b, sd);
+                solve_col<NB, T>(a + static_cast<int64_t>(k0) * n + r0 + w, n, b, sd);
             else
-                solve_row<NB>(a + static_cast<int64_t>(r0 + w - rest) * n + k0, b, sd, sinv);
+                solve_row<NB, T>(a + static_cast<int64_t>(r0 + w - rest) * n + k0, b, sd, sinv);
         }
         __syncthreads();
         // (d) A22 -= L21 U12, 32-row bands by wave, 32-column tiles
         const int bands = (rest + 31) / 32;
         for (int band = wave; band < bands; band += kBatchThreads / 64) {
             const int rb = r0 + 32 * band;
-            float af[2][KS];
+            T af[2][KS];
 #pragma unroll
             for (int bi = 0; bi < 2; ++bi) {
                 const int row = rb + 16 * bi + (lane & 15);
@@ -221,14 +235,14 @@ __device__ void factor_system(float *a, int n, int *status, int64_t *info, float
                 }
             }
             for (int cb = r0; cb < n; cb += 32) {
-                v4f acc[2][2];
+                acc_t acc[2][2];
 #pragma unroll
                 for (int bi = 0; bi < 2; ++bi)
 #pragma unroll
                     for (int bj = 0; bj < 2; ++bj)
 #pragma unroll
                         for (int q = 0; q < 4; ++q) {
-                            const int row = rb + 16 * bi + Mma<float>::row(lane, q);
+                            const int row = rb + 16 * bi + Mma<T>::row(lane, q);
                             const int col = cb + 16 * bj + (lane & 15);
                             acc[bi][bj][q] = load_if(a, static_cast<int64_t>(row) * n + col,
                                                      row < n && col < n);
@@ -236,7 +250,7 @@ __device__ void factor_system(float *a, int n, int *status, int64_t *info, float
 #pragma unroll
                 for (int ks = 0; ks < KS; ++ks) {
                     const int k = 4 * ks + (lane >> 4);
-                    float bf[2];
+                    T bf[2];
 #pragma unroll
                     for (int bj = 0; bj < 2; ++bj) {
                         const int col = cb + 16 * bj + (lane & 15);
@@ -247,7 +261,7 @@ __device__ void factor_system(float *a, int n, int *status, int64_t *info, float
                     for (int bi = 0; bi < 2; ++bi)
 #pragma unroll
                         for (int bj = 0; bj < 2; ++bj)
-                            acc[bi][bj] = Mma<float>::step(af[bi][ks], bf[bj], acc[bi][bj]);
+                            acc[bi][bj] = Mma<T>::step(af[bi][ks], bf[bj], acc[bi][bj]);
                 }
 #pragma unroll
                 for (int bi = 0; bi < 2; ++bi)
@@ -255,7 +269,7 @@ __device__ void factor_system(float *a, int n, int *status, int64_t *info, float
                     for (int bj = 0; bj < 2; ++bj)
 #pragma unroll
                         for (int q = 0; q < 4; ++q) {
-                            const int row = rb + 16 * bi + Mma<float>::row(lane, q);
+                            const int row = rb + 16 * bi + Mma<T>::row(lane, q);
                             const int col = cb + 16 * bj + (lane & 15);
                             if (row < n && col < n)
                                 a[static_cast<int64_t>(row) * n + col] = acc[bi][bj][q];
@@ -282,8 +296,8 @@ __global__ __launch_bounds__(kBatchThreads) void k_batch_factor(int count,
         __syncthreads();
         if (q >= count) return;
         const BatchDesc s = d[q];
-        factor_system<NB>(lu_pool + s.m_off, s.n, out.status + s.sys, out.info + s.sys, sd, sinv,
-                          &sflag);
+        factor_system<NB, float>(lu_pool + s.m_off, s.n, out.status + s.sys, out.info + s.sys, sd,
+                                 sinv, &sflag);
         __syncthreads();
     }
 }
@@ -360,58 +374,55 @@ __device__ void block_matvec(const TM *__restrict__ M, int n, const double *x, d
     __syncthreads();
 }
 
-// y <- L^{-1} y (unit lower) or U^{-1} y (upper) with the packed FP32 factors
-// at lu (ld n), y in LDS (FP64): 64-row diagonal blocks solved by wave 0 in
-// registers (each lane one row, the solved values passed by readlane), the
-// coupling to the rows not yet solved taken out by all threads.
-__device__ inline double bcast_lane(double v, int src) {
-    const int lo = __builtin_amdgcn_readlane(__double2loint(v), src);
-    const int hi = __builtin_amdgcn_readlane(__double2hiint(v), src);
-    return __hiloint2double(hi, lo);
-}
-
-template <bool UPPER>
-__device__ void block_trsv(const float *__restrict__ lu, int n, double *y) {
+// y <- L^{-1} y (unit lower) or U^{-1} y (upper) with the packed factors
+// (FP32, or FP64 for the fallback) at lu (ld n), y in LDS (FP64): BLK-row
+// diagonal blocks solved by wave 0 in registers (each lane one row, the solved
+// values passed by readlane), the coupling to the rows not yet solved taken
+// out by all threads.
+template <bool UPPER, typename TF>
+__device__ void block_trsv(const TF *__restrict__ lu, int n, double *y) {
+    constexpr int BLK = 32;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    const int nblk = (n + 63) / 64;
+    const int nblk = (n + BLK - 1) / BLK;
     for (int t = 0; t < nblk; ++t) {
         const int blk = UPPER ? nblk - 1 - t : t;
-        const int b0 = 64 * blk, bs = min(64, n - b0);
+        const int b0 = BLK * blk, bs = min(BLK, n - b0);
         if (wave == 0) {
-            const int row = b0 + (lane < bs ? lane : 0);
-            float lr[64];
-            const float *lp = lu + static_cast<int64_t>(row) * n + b0;
+            const bool in = lane < bs;
+            const int row = b0 + (in ? lane : 0);
+            TF lr[BLK];
+            const TF *lp = lu + static_cast<int64_t>(row) * n + b0;
 #pragma unroll
-            for (int j = 0; j < 64; ++j) lr[j] = (j < bs && lane < bs) ? lp[j] : 0.0f;
-            double yi = lane < bs ? y[b0 + lane] : 0.0;
+            for (int j = 0; j < BLK; ++j) lr[j] = (j < bs && in) ? lp[j] : TF(0);
+            double yi = in ? y[b0 + lane] : 0.0;
             if (UPPER) {
                 double dinv = 1.0;
 #pragma unroll
-                for (int j = 0; j < 64; ++j)
+                for (int j = 0; j < BLK; ++j)
                     if (j == lane) dinv = 1.0 / static_cast<double>(lr[j]);
 #pragma unroll
-                for (int j = 63; j >= 0; --j) {
+                for (int j = BLK - 1; j >= 0; --j) {
                     if (j < bs) {
                         if (lane == j) yi *= dinv;
-                        const double yj = bcast_lane(yi, j);
+                        const double yj = lane_value(yi, j);
                         if (lane < j) yi -= static_cast<double>(lr[j]) * yj;
                     }
                 }
             } else {
 #pragma unroll
-                for (int j = 0; j < 64; ++j) {
+                for (int j = 0; j < BLK; ++j) {
                     if (j < bs) {
-                        const double yj = bcast_lane(yi, j);
+                        const double yj = lane_value(yi, j);
                         if (lane > j) yi -= static_cast<double>(lr[j]) * yj;
                     }
                 }
             }
-            if (lane < bs) y[b0 + lane] = yi;
+            if (in) y[b0 + lane] = yi;
         }
         __syncthreads();
         const int rlo = UPPER ? 0 : b0 + bs, rhi = UPPER ? b0 : n;
         for (int r = rlo + tid; r < rhi; r += kBatchThreads) {
-            const float *l1 = lu + static_cast<int64_t>(r) * n + b0;
+            const TF *l1 = lu + static_cast<int64_t>(r) * n + b0;
             double acc = 0.0;
             for (int j = 0; j < bs; ++j) acc += static_cast<double>(l1[j]) * y[b0 + j];
             y[r] -= acc;
@@ -421,14 +432,14 @@ __device__ void block_trsv(const float *__restrict__ lu, int n, double *y) {
 }
 
 // z = H_s U^{-1} L^{-1} v for one system: v, t, z in LDS (t is overwritten).
-__device__ void block_precond(const BatchDesc &s, const float *lu, const float *G,
-                              const double *cc, const double *v, double *t, double *z,
-                              double *red) {
+template <typename TF>
+__device__ void block_precond(const BatchDesc &s, const TF *lu, const float *G, const double *cc,
+                              const double *v, double *t, double *z, double *red) {
     const int n = s.n;
     for (int i = threadIdx.x; i < n; i += kBatchThreads) t[i] = v[i];
     __syncthreads();
-    block_trsv<false>(lu, n, t);
-    block_trsv<true>(lu, n, t);
+    block_trsv<false, TF>(lu, n, t);
+    block_trsv<true, TF>(lu, n, t);
     if (s.kind == RMGE_MULT_GAUSSIAN) {
         block_matvec<float>(G, n, t, z, nullptr, red);
     } else {  // z_j = sum_k c_{(j - k) mod n} t_k
@@ -451,8 +462,9 @@ __device__ void block_precond(const BatchDesc &s, const float *lu, const float *
 // Gram-Schmidt applied twice, Givens rotations by thread 0), until
 // eta = ||b - A x||_inf / (||A||_inf ||x||_inf + ||b||_inf) <= tol or
 // max_iters inner iterations.
+template <typename TF>
 __device__ void refine_system(const BatchDesc &s, const double *__restrict__ A,
-                              const double *__restrict__ B, double *X, const float *lu,
+                              const double *__restrict__ B, double *X, const TF *lu,
                               const float *G, const double *cpool, double *K,
                               const RefineParams &p, BatchOut out, double *sm) {
     const int n = s.n, tid = threadIdx.x, R = p.restart;
@@ -475,7 +487,7 @@ __device__ void refine_system(const BatchDesc &s, const double *__restrict__ A,
     double bmax = 0.0;
     for (int i = tid; i < n; i += kBatchThreads) bmax = fmax(bmax, fabs(bs[i]));
     const double bnorm = block_reduce(bmax, true, red);
-    block_precond(s, lu, G_s, cc, bs, ts, xs, red);
+    block_precond<TF>(s, lu, G_s, cc, bs, ts, xs, red);
     double anorm = 0.0, eta = 0.0, eta0 = -1.0;
     int used = 0;
     bool first = true;
@@ -516,7 +528,7 @@ __device__ void refine_system(const BatchDesc &s, const double *__restrict__ A,
             double *vj = V + static_cast<int64_t>(j) * n, *zj = Z + static_cast<int64_t>(j) * n;
             for (int i = tid; i < n; i += kBatchThreads) ts[i] = vj[i];
             __syncthreads();
-            block_precond(s, lu, G_s, cc, ts, ts, ws, red);  // ws = M^{-1} v_j
+            block_precond<TF>(s, lu, G_s, cc, ts, ts, ws, red);  // ws = M^{-1} v_j
             for (int i = tid; i < n; i += kBatchThreads) zj[i] = ws[i];
             __syncthreads();
             block_matvec<double>(A_s, n, ws, ts, nullptr, red);  // ts = A z_j
@@ -613,8 +625,8 @@ __global__ __launch_bounds__(kBatchThreads) void k_batch_refine(
         if (q >= count) return;
         const BatchDesc s = d[q];
         if (out.status[s.sys] != RMGE_OK) continue;  // broken down in the factorization
-        refine_system(s, A, B, X, lu_pool + s.m_off, g_pool, c_pool, k_pool + s.k_off, p, out,
-                      sm);
+        refine_system<float>(s, A, B, X, lu_pool + s.m_off, g_pool, c_pool, k_pool + s.k_off, p,
+                             out, sm);
     }
 }
 
@@ -640,6 +652,105 @@ hipError_t upload(T **dst, const std::vector<T> &src) {
     if (src.empty()) return hipSuccess;
     BATCH_TRY(hipMalloc(dst, sizeof(T) * src.size()));
     return hipMemcpy(*dst, src.data(), sizeof(T) * src.size(), hipMemcpyHostToDevice);
+}
+
+// ------------------------------------------------------------ FP64 fallback
+//
+// A system whose FP32-preconditioned refinement has not reached tol within
+// max_iters inner iterations is solved again from FP64 factors (the usual
+// escape of mixed-precision solvers): M = A H in FP64 with the same H (the
+// Gaussian's FP32 values, or the circulant's first column), GENP in FP64 with
+// pivot blocks of 32, and the same GMRES refinement preconditioned with those
+// factors.  Its result records the fallback and counts both stages' iterations.
+
+// M = A H for one system in FP64 on the matrix cores, 32 x 32 tiles a wave, K
+// in steps of 4; the B operand is G (FP32 values) or, for a circulant,
+// H[k][j] = c[(k - j) mod n] from the first column c in LDS.
+__device__ void product64_system(const BatchDesc &s, const double *__restrict__ A,
+                                 const float *__restrict__ G, const double *cc, double *M) {
+    const int n = s.n, lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int tiles = (n + 31) / 32;
+    const bool gauss = s.kind == RMGE_MULT_GAUSSIAN;
+    for (int t = wave; t < tiles * tiles; t += kBatchThreads / 64) {
+        const int rb = 32 * (t / tiles), cb = 32 * (t % tiles);
+        v4d acc[2][2];
+#pragma unroll
+        for (int bi = 0; bi < 2; ++bi)
+#pragma unroll
+            for (int bj = 0; bj < 2; ++bj) acc[bi][bj] = v4d{0.0, 0.0, 0.0, 0.0};
+        for (int k0 = 0; k0 < n; k0 += 4) {
+            const int k = k0 + (lane >> 4);
+            double af[2], bf[2];
+#pragma unroll
+            for (int bi = 0; bi < 2; ++bi) {
+                const int row = rb + 16 * bi + (lane & 15);
+                af[bi] = load_if(A, static_cast<int64_t>(row) * n + k, row < n && k < n);
+            }
+#pragma unroll
+            for (int bj = 0; bj < 2; ++bj) {
+                const int col = cb + 16 * bj + (lane & 15);
+                const bool in = k < n && col < n;
+                if (gauss) {
+                    bf[bj] = static_cast<double>(load_if(G, static_cast<int64_t>(k) * n + col, in));
+                } else {
+                    int d = k - col;
+                    d = d < 0 ? d + n : d;
+                    bf[bj] = in ? cc[d] : 0.0;
+                }
+            }
+#pragma unroll
+            for (int bi = 0; bi < 2; ++bi)
+#pragma unroll
+                for (int bj = 0; bj < 2; ++bj)
+                    acc[bi][bj] = Mma<double>::step(af[bi], bf[bj], acc[bi][bj]);
+        }
+#pragma unroll
+        for (int bi = 0; bi < 2; ++bi)
+#pragma unroll
+            for (int bj = 0; bj < 2; ++bj)
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    const int row = rb + 16 * bi + Mma<double>::row(lane, q);
+                    const int col = cb + 16 * bj + (lane & 15);
+                    if (row < n && col < n) M[static_cast<int64_t>(row) * n + col] = acc[bi][bj][q];
+                }
+    }
+    __syncthreads();
+}
+
+__global__ __launch_bounds__(kBatchThreads) void k_batch_fallback(
+    int count, const BatchDesc *__restrict__ d, const double *A, const double *B, double *X,
+    const float *g_pool, const double *c_pool, double *m64_pool, double *k_pool, RefineParams p,
+    BatchOut out) {
+    __shared__ double sm[kRefineShared];
+    __shared__ double sd[32 * 33], sinv[32];
+    __shared__ int sflag, sq, sit;
+    while (true) {
+        if (threadIdx.x == 0) sq = atomicAdd(out.tickets + 6, 1);
+        __syncthreads();
+        const int q = sq;
+        __syncthreads();
+        if (q >= count) return;
+        const BatchDesc s = d[q];
+        if (out.status[s.sys] != RMGE_NOT_CONVERGED) continue;
+        double *cc = sm + 4 * kBatchMaxN;  // where the refinement keeps the first column too
+        if (s.kind != RMGE_MULT_GAUSSIAN)
+            for (int i = threadIdx.x; i < s.n; i += kBatchThreads) cc[i] = c_pool[s.g_off + i];
+        if (threadIdx.x == 0) {
+            sit = out.iters[s.sys];
+            out.status[s.sys] = RMGE_OK;
+            out.fp64[s.sys] = 1;
+        }
+        __syncthreads();
+        double *m = m64_pool + s.m_off;
+        product64_system(s, A + s.a_off, g_pool + s.g_off, cc, m);
+        factor_system<32, double>(m, s.n, out.status + s.sys, out.info + s.sys, sd, sinv, &sflag);
+        __syncthreads();
+        if (sflag == 0)
+            refine_system<double>(s, A, B, X, m, g_pool, c_pool, k_pool + s.k_off, p, out, sm);
+        if (threadIdx.x == 0) out.iters[s.sys] += sit;
+        __syncthreads();
+    }
 }
 
 }  // namespace
@@ -674,6 +785,7 @@ struct rmge_batch {
     // pools
     float *lu_pool = nullptr, *g_pool = nullptr;
     double *c_pool = nullptr, *h_pool = nullptr, *hh_pool = nullptr, *k_pool = nullptr;
+    double *m64_pool = nullptr;  // FP64 factors of the systems that fall back
     BatchDesc *d_desc = nullptr;
     BatchOut out{};
     // captured graph and what it was captured with
@@ -691,7 +803,8 @@ void batch_free(rmge_batch *b) {
                     b->d_nsys_g, b->d_aoff_g, b->d_goff_g, b->d_moff_g, b->d_row_start,
                     b->d_nsys_c, b->d_logl_c, b->d_aoff_c, b->d_moff_c, b->d_coff_c, b->d_hoff_c,
                     b->d_hhoff_c, b->d_twoff, b->tw_pool, b->lu_pool, b->g_pool, b->c_pool,
-                    b->h_pool, b->hh_pool, b->k_pool, b->d_desc, b->out.status, b->out.iters,
+                    b->h_pool, b->hh_pool, b->k_pool, b->m64_pool, b->out.fp64, b->d_desc,
+                    b->out.status, b->out.iters,
                     b->out.eta, b->out.eta0, b->out.tickets, b->out.info};
     for (void *p : ptrs)
         if (p) (void)hipFree(p);
@@ -770,11 +883,21 @@ hipError_t enqueue_refine(rmge_batch *b, const double *A, const double *B, doubl
     return hipGetLastError();
 }
 
+hipError_t enqueue_fallback(rmge_batch *b, const double *A, const double *B, double *X,
+                            double tol, hipStream_t s) {
+    RefineParams p{b->restart, b->max_iters, tol};
+    hipLaunchKernelGGL(k_batch_fallback, dim3(static_cast<unsigned>(grid_for(b->count, 2))),
+                       dim3(kBatchThreads), 0, s, b->count, b->d_desc, A, B, X, b->g_pool,
+                       b->c_pool, b->m64_pool, b->k_pool, p, b->out);
+    return hipGetLastError();
+}
+
 hipError_t enqueue_all(rmge_batch *b, const double *A, const double *B, double *X, double tol,
                        hipStream_t s) {
     BATCH_TRY(enqueue_products(b, A, s));
     for (int bk = RMGE_BATCH_BUCKETS - 1; bk >= 0; --bk) BATCH_TRY(enqueue_factor_bucket(b, bk, s));
-    return enqueue_refine(b, A, B, X, tol, s);
+    BATCH_TRY(enqueue_refine(b, A, B, X, tol, s));
+    return enqueue_fallback(b, A, B, X, tol, s);
 }
 
 bool device_is_gfx950() {
@@ -884,6 +1007,7 @@ rmge_status batch_build(rmge_batch *b) {
     chk(upload(&b->d_hhoff_c, hhoff_c));
     chk(upload(&b->d_twoff, twoff));
     chk(hipMalloc(&b->lu_pool, sizeof(float) * std::max<int64_t>(1, lu_total)));
+    chk(hipMalloc(&b->m64_pool, sizeof(double) * std::max<int64_t>(1, lu_total)));
     chk(hipMalloc(&b->g_pool, sizeof(float) * std::max<int64_t>(1, g_total)));
     chk(hipMalloc(&b->c_pool, sizeof(double) * std::max<int64_t>(1, c_total)));
     chk(hipMalloc(&b->h_pool, sizeof(double) * std::max<int64_t>(1, h_total)));
@@ -896,6 +1020,7 @@ rmge_status batch_build(rmge_batch *b) {
     chk(hipMalloc(&b->out.eta0, sizeof(double) * count));
     chk(hipMalloc(&b->out.tickets, sizeof(int) * 8));
     chk(hipMalloc(&b->out.info, sizeof(int64_t) * count));
+    chk(hipMalloc(&b->out.fp64, sizeof(int) * count));
     if (e == hipSuccess) e = apply_tuning(b);
     if (e == hipSuccess) e = hipDeviceSynchronize();
     if (e == hipSuccess) e = hipStreamCreateWithFlags(&b->own, hipStreamNonBlocking);
@@ -946,10 +1071,10 @@ rmge_status rmge_batch_run(rmge_batch *b, const double *A, const double *B, doub
 }
 
 rmge_status rmge_batch_run_timed(rmge_batch *b, const double *A, const double *B, double *X,
-                                 double tol, void *hip_stream, double *ms3) {
-    if (!b || !A || !B || !X || !(tol > 0.0) || !ms3) return RMGE_EINVAL;
+                                 double tol, void *hip_stream, double *ms4) {
+    if (!b || !A || !B || !X || !(tol > 0.0) || !ms4) return RMGE_EINVAL;
     hipStream_t s = static_cast<hipStream_t>(hip_stream);
-    hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
+    hipEvent_t ev[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};
     hipError_t e = hipSuccess;
     for (hipEvent_t &x : ev)
         if (e == hipSuccess) e = hipEventCreate(&x);
@@ -961,11 +1086,13 @@ rmge_status rmge_batch_run_timed(rmge_batch *b, const double *A, const double *B
     if (e == hipSuccess) e = hipEventRecord(ev[2], s);
     if (e == hipSuccess) e = enqueue_refine(b, A, B, X, tol, s);
     if (e == hipSuccess) e = hipEventRecord(ev[3], s);
-    if (e == hipSuccess) e = hipEventSynchronize(ev[3]);
-    for (int i = 0; i < 3 && e == hipSuccess; ++i) {
+    if (e == hipSuccess) e = enqueue_fallback(b, A, B, X, tol, s);
+    if (e == hipSuccess) e = hipEventRecord(ev[4], s);
+    if (e == hipSuccess) e = hipEventSynchronize(ev[4]);
+    for (int i = 0; i < 4 && e == hipSuccess; ++i) {
         float ms = 0.0f;
         e = hipEventElapsedTime(&ms, ev[i], ev[i + 1]);
-        ms3[i] = ms;
+        ms4[i] = ms;
     }
     for (hipEvent_t x : ev)
         if (x) (void)hipEventDestroy(x);
@@ -1003,7 +1130,7 @@ rmge_status rmge_batch_graph_run(rmge_batch *b, const double *A, const double *B
 }
 
 rmge_status rmge_batch_results(const rmge_batch *b, int32_t *status, double *eta, double *eta0,
-                               int32_t *iters, int64_t *info, void *hip_stream) {
+                               int32_t *iters, int64_t *info, int32_t *fp64, void *hip_stream) {
     if (!b) return RMGE_EINVAL;
     hipStream_t s = static_cast<hipStream_t>(hip_stream);
     hipError_t e = hipStreamSynchronize(s);
@@ -1013,6 +1140,7 @@ rmge_status rmge_batch_results(const rmge_batch *b, int32_t *status, double *eta
     if (e == hipSuccess && eta0) e = hipMemcpy(eta0, b->out.eta0, 8 * c, hipMemcpyDeviceToHost);
     if (e == hipSuccess && iters) e = hipMemcpy(iters, b->out.iters, 4 * c, hipMemcpyDeviceToHost);
     if (e == hipSuccess && info) e = hipMemcpy(info, b->out.info, 8 * c, hipMemcpyDeviceToHost);
+    if (e == hipSuccess && fp64) e = hipMemcpy(fp64, b->out.fp64, 4 * c, hipMemcpyDeviceToHost);
     return batch_status(e);
 }
 

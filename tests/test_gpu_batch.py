@@ -6,9 +6,11 @@ M = A H, GENP in FP32 with pivot blocks of nb columns, FP64 GMRES refinement.
 Tolerances (as for the single-system FP32 tests):
 * solutions: ||x_g - x_o|| / ||x_o|| <= max(1e-10, 2 kappa (eta_g + eta_o)), the
   oracle's x after one FP64 refinement step; eta_g recomputed here <= 1e-14;
-* factors: ||L U - M||_max <= 8 n u32 kD || |L| |U| ||_max + (product error), M
-  the oracle's product with A (and a Gaussian G) rounded to FP32, kD the largest
-  condition number of the nb x nb diagonal blocks whose inverses the solves apply;
+* factors: ||L U - M||_max <= 8 n u32 || |L| |U| ||_max + (product error), M the
+  oracle's product with A (and a Gaussian G) rounded to FP32 (blocked
+  elimination whose block solves are substitutions is backward stable, Higham,
+  Accuracy and Stability, Thm 9.3 / 13.x);
+* a system whose FP32 stage stalls is solved again from FP64 factors, and says so;
 * a zero leading block gives RMGE_ZERO_PIVOT at index 0 for its system only;
 * a run replayed from the HIP graph gives the eager run's results bit for bit.
 """
@@ -94,15 +96,6 @@ def test_batch_matches_oracle(rmge):
     assert (res["eta0"] >= res["eta"]).all()
 
 
-def _kappa_blocks(L, U, nb):
-    n = L.shape[0]
-    k = 1.0
-    for i in range(0, n, nb):
-        e = min(n, i + nb)
-        k = max(k, np.linalg.cond(L[i:e, i:e]), np.linalg.cond(U[i:e, i:e]))
-    return k
-
-
 @pytest.mark.parametrize("tuning", [[16, 16, 16, 16, 16], [32, 32, 32, 32, 32], [64, 64, 64, 64, 64]])
 def test_batch_factors_match_oracle(rmge, tuning):
     sizes = [33, 100, 129, 300, 520]
@@ -125,9 +118,8 @@ def test_batch_factors_match_oracle(rmge, tuning):
         else:  # FFT of the FP64 row, rounded to FP32 once
             Mo = oracle.matmul(Ah, H)
             mdiff = (U32 + 16 * EPS * np.log2(2 * n)) * (np.abs(Ah) @ np.abs(H)).max()
-        nb = tuning[0]
         back = np.abs(L @ U - Mo).max()
-        bound = 8 * n * U32 * _kappa_blocks(L, U, nb) * (np.abs(L) @ np.abs(U)).max() + mdiff
+        bound = 8 * n * U32 * (np.abs(L) @ np.abs(U)).max() + mdiff
         assert back <= bound, (i, n, kind, back, bound)
 
 
@@ -187,3 +179,23 @@ def test_batch_autotune(rmge):
     assert bt.tuning() == [16, 64, 32, 16, 64]
     bt.run(A, B, X, tol=1e-14)
     _check_solutions(systems, As, bs, host(X), bt.results())
+
+
+def test_batch_fp64_fallback(rmge):
+    # kappa = 1e6 systems with one GMRES iteration allowed for the FP32 stage:
+    # those still above tol are solved again from FP64 factors in the same run
+    sizes = [90, 180, 333, 520]
+    systems, As, bs = _make(sizes, [1e6] * len(sizes), seed0=130)
+    A, B, X = _flat(rmge, As, bs)
+    bt = rmge.Batch(systems, restart=16, max_iters=1)
+    bt.run(A, B, X, tol=1e-14)
+    res = bt.results()
+    assert res["fp64"].sum() >= 1
+    assert (res["iters"] >= 1).all()
+    _check_solutions(systems, As, bs, host(X), res)
+    # and through the graph
+    X.fill_(float("nan"))
+    bt.run(A, B, X, tol=1e-14, graph=True)
+    res2 = bt.results()
+    np.testing.assert_array_equal(res2["fp64"], res["fp64"])
+    _check_solutions(systems, As, bs, host(X), res2)

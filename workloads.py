@@ -28,8 +28,8 @@ U Sigma V^T with U, V the Q factors of QR factorizations of random matrices):
   probability 1/2 each, kappa = 10^(1 + 5 u), a multiplier seed each, and the
   offsets of each A_s (n x n, row-major) and b_s, x_s in flat buffers;
   ``batch_inputs_torch(table, seed)`` builds the matrices on the GPU as
-  ``conditioned`` does (QR of Gaussian matrices, batched over equal orders)
-  and the right-hand sides.
+  ``conditioned`` does (the Q factors of Gaussian matrices by CholeskyQR2,
+  batched over orders within 64 of each other) and the right-hand sides.
 
 The torch variants build the same recipes on a GPU for sizes where a CPU QR
 would take minutes; they are not bitwise equal to the numpy ones.
@@ -166,8 +166,12 @@ def batch_table(count: int, seed: int, n_lo: int = 32, n_hi: int = 1024,
 
 def batch_inputs_torch(table, seed: int, device="cuda"):
     """Flat float64 tensors A (every A_s row-major at its offset) and B (every
-    b_s), built on the GPU: A_s = Q1 diag(sigma) Q2^T with Haar Q1, Q2 from
-    batched QR over the systems of one order."""
+    b_s), built on the GPU: A_s = Q1 diag(sigma) Q2^T with Haar Q1, Q2.  The Q
+    factor of a Gaussian X with R's diagonal positive is X R^{-1} with R the
+    Cholesky factor of X^T X; done twice (CholeskyQR2) it is orthogonal to
+    working precision, and batched over groups of orders within 64 of each
+    other: X_s padded to the group's order P as [[X_s, 0], [0, I]] has the
+    factor [[Q_s, 0], [0, I]]."""
     import torch
 
     a_total = sum(t[0] * t[0] for t in table)
@@ -175,26 +179,38 @@ def batch_inputs_torch(table, seed: int, device="cuda"):
     A = torch.empty(a_total, dtype=torch.float64, device=device)
     g = torch.Generator(device=device)
     g.manual_seed(int(seed) * 1000003 + 53)
-    by_n = {}
+    groups = {}
     for i, t in enumerate(table):
-        by_n.setdefault(t[0], []).append(i)
-    for n, idx in sorted(by_n.items()):
-        k = len(idx)
+        groups.setdefault((t[0] + 63) // 64, []).append(i)
 
-        def _haar():
-            X = torch.randn((k, n, n), generator=g, dtype=torch.float64, device=device)
-            Q, R = torch.linalg.qr(X)
-            sgn = torch.sign(torch.diagonal(R, dim1=-2, dim2=-1))
-            sgn[sgn == 0] = 1.0
-            return Q * sgn[:, None, :]
+    def _chol_qr(X):
+        R = torch.linalg.cholesky(X.transpose(1, 2).contiguous() @ X, upper=True)
+        return torch.linalg.solve_triangular(R, X, upper=True, left=False)
 
-        Q1, Q2 = _haar(), _haar()
-        sig = torch.stack([torch.as_tensor(sigma_profile(n, table[i][5]), device=device)
-                           for i in idx])
-        As = torch.bmm(Q1 * sig[:, None, :], Q2.transpose(1, 2).contiguous())
-        for j, i in enumerate(idx):
-            off = table[i][3]
-            A[off:off + n * n] = As[j].reshape(-1)
+    for key in sorted(groups):
+        P = 64 * key
+        for c0 in range(0, len(groups[key]), 128):  # bounded memory: 128 x P^2 doubles a chunk
+            idx = groups[key][c0:c0 + 128]
+            k = len(idx)
+            ns = torch.tensor([table[i][0] for i in idx], device=device)
+            ar = torch.arange(P, device=device)
+            keep = (ar[None, :, None] < ns[:, None, None]) & (ar[None, None, :] < ns[:, None, None])
+            pad_eye = ((ar[None, :, None] >= ns[:, None, None]) &
+                       (ar[None, :, None] == ar[None, None, :])).to(torch.float64)
+
+            def _haar():
+                X = torch.randn((k, P, P), generator=g, dtype=torch.float64, device=device)
+                X = X * keep + pad_eye
+                return _chol_qr(_chol_qr(X))
+
+            Q1, Q2 = _haar(), _haar()
+            for j, i in enumerate(idx):
+                n = table[i][0]
+                sig = torch.as_tensor(sigma_profile(n, table[i][5]), device=device)
+                As = (Q1[j, :n, :n] * sig[None, :]) @ Q2[j, :n, :n].transpose(0, 1).contiguous()
+                off = table[i][3]
+                A[off:off + n * n] = As.reshape(-1)
+            del Q1, Q2
     gb = torch.Generator(device=device)
     gb.manual_seed(int(seed) * 1000003 + 59)
     B = torch.randn(v_total, generator=gb, dtype=torch.float64, device=device)
