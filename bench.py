@@ -58,6 +58,13 @@ TRAFFIC_BF16 = {"n": 16384, "source": "k_gemm_bf16x2 + tile_coords (csrc/gemm.hi
                 "sha256": "84e34bad2ce2417152b2ab9234b22cb2ab011987019de5d783b4c87f9550ff8c",
                 "fetch_kib": 45956590.5, "write_kib": 1061462.2}
 
+# the same (calibrated KiB) for the FFT product (k_fft_stockham, circulant multiplier,
+# n = 4096, the structured workload): profiles/k_fft_stockham_circulant_n4096_hbm_traffic.txt.  The
+# fingerprint covers the whole FFT source file.
+TRAFFIC_FFT = {"n": 4096, "source": "csrc/fft.hip",
+               "sha256": "e4403c6b81a3aa5ac5d64eb90d3814fc8f7827ad12ab6522384be8f2d243306a",
+               "fetch_kib": 132433.8, "write_kib": 131328.0}
+
 
 def log(msg):
     sys.stderr.write("[bench %s] %s\n" % (time.strftime("%H:%M:%S"), msg))
@@ -198,6 +205,18 @@ def product_traffic(n, prec):
     return (t["fetch_kib"] + t["write_kib"]) * 1024.0
 
 
+def fft_traffic(n):
+    """Counter-measured HBM bytes per FFT product launch (circulant, FP64 in and out), or
+    None for another size or a changed FFT source."""
+    import hashlib
+
+    with open(os.path.join(ROOT, "paper_1406_5802_amd", "csrc", "fft.hip"), "rb") as fh:
+        sha = hashlib.sha256(fh.read()).hexdigest()
+    if n != TRAFFIC_FFT["n"] or sha != TRAFFIC_FFT["sha256"]:
+        return None
+    return (TRAFFIC_FFT["fetch_kib"] + TRAFFIC_FFT["write_kib"]) * 1024.0
+
+
 def rooflines(name, r, n):
     """Roofline lines of one path's two large kernels: the product M = A H (one
     launch) and the bulk Schur updates (one launch a step, their summed time),
@@ -285,6 +304,8 @@ def cpu_model():
 def cpu_baseline(n_cpu, seed, kind="GAUSSIAN", threads=None):
     """The oracle (plain-loop FP64 C: multiplier, product, unblocked GENP, solve,
     one refinement step) on the host, on an n_cpu system of the same recipe."""
+    import numpy as np
+
     import oracle
     import workloads
 
@@ -296,8 +317,21 @@ def cpu_baseline(n_cpu, seed, kind="GAUSSIAN", threads=None):
     if threads:
         oracle.set_num_threads(threads)
     log("cpu baseline: oracle factor + solve on %d threads" % oracle.num_threads())
+    # the oracle's factorization in its three stages (multiplier, product by row blocks,
+    # GENP), each logged as it ends, then its solve with one refinement step
+    kid = getattr(oracle, kind)
+    chunk = n_cpu // 8 if n_cpu >= 8192 else n_cpu
     t0 = time.perf_counter()
-    f = oracle.factor(A, getattr(oracle, kind), seed)
+    H = oracle.multiplier(kid, n_cpu, seed)
+    M = np.empty((n_cpu, n_cpu))
+    for r0 in range(0, n_cpu, chunk):
+        M[r0:r0 + chunk] = oracle.matmul(A[r0:r0 + chunk], H)
+        log("cpu baseline: product rows %d..%d (%.1f s)" % (r0, min(n_cpu, r0 + chunk) - 1,
+                                                           time.perf_counter() - t0))
+    LU, status, info = oracle.genp(M)
+    del M
+    log("cpu baseline: GENP done (%.1f s)" % (time.perf_counter() - t0))
+    f = oracle.Factors(n_cpu, kid, seed, A, H, LU, status, info, 0.0, 0.0)
     s = oracle.solve(f, b, refine=1)
     dt = time.perf_counter() - t0
     log("cpu baseline: %.1f s, eta %.2e" % (dt, s.eta[-1]))
@@ -483,7 +517,7 @@ def structured(args):
         "roofline": {"bound": "hbm", "achieved": round(fft_bytes / (r["ms_product"] * 1e-3) / 1e9, 1),
                      "peak": 8000.0, "unit": "GB/s",
                      "frac": round(fft_bytes / (r["ms_product"] * 1e-3) / 1e9 / 8000.0, 4),
-                     "traffic": None,
+                     "traffic": fft_traffic(n) if head == "circulant" else None,
                      "kernel": "k_fft_stockham (M = A H, one row a workgroup, FP64 in and out)",
                      "ms_per_launch": round(r["ms_product"], 4)},
         "paths": {k: {kk: (float("%.6g" % vv) if isinstance(vv, float) else vv)
@@ -659,6 +693,9 @@ def main():
     ap.add_argument("--cpu-threads", type=int, default=None,
                     help="threads of the oracle's CPU sample (default: all the host gives it)")
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--input-cache", default=None,
+                    help="precision: load A from this file if it exists, else make it and save it "
+                         "there (lets a profiled run use the same input without the QR)")
     ap.add_argument("--matrix", default="conditioned", choices=["conditioned", "gaussian"],
                     help="conditioned: Q1 diag(sigma) Q2^T (the workload); gaussian: i.i.d. "
                          "N(0, 1/n) entries, no QR (for hardware-counter passes, where only "
@@ -694,9 +731,18 @@ def main():
         log("generating A: n=%d i.i.d. Gaussian (seed %d) on the GPU" % (n, args.seed))
         A = workloads.gaussian_torch(n, args.seed)
         kappa = None
+    elif args.input_cache and os.path.exists(args.input_cache):
+        # the same A, made earlier by this script in another process (so that a
+        # profiled run sees the bench's input without running the QR under the profiler)
+        log("loading A from %s" % args.input_cache)
+        A = torch.load(args.input_cache, weights_only=True).to("cuda")
+        assert tuple(A.shape) == (n, n)
     else:
         log("generating A: n=%d kappa=%.3g (seed %d) on the GPU" % (n, kappa, args.seed))
         A = workloads.conditioned_torch(n, kappa, args.seed)
+        if args.input_cache:
+            torch.save(A.cpu(), args.input_cache)
+            log("saved A to %s" % args.input_cache)
     b = workloads.rhs_torch(n, 1, args.seed)
     torch.cuda.synchronize()
     log("inputs ready")

@@ -183,9 +183,38 @@ def batch_inputs_torch(table, seed: int, device="cuda"):
     for i, t in enumerate(table):
         groups.setdefault((t[0] + 63) // 64, []).append(i)
 
+    def _inv_upper(R):
+        # R^{-1} for a batch of upper-triangular R (order a multiple of 32) with
+        # batched products only: the 32 x 32 diagonal blocks are inverted by
+        # substitution all at once, then the block rows of R^{-1} follow from
+        # the bottom up, X_I = R_II^{-1} (E_I - R_{I,>I} X_{>I}).  (The library
+        # triangular solve needs a larger workspace than the BLAS handle has
+        # for batches of large orders.)
+        k, P, _ = R.shape
+        q = P // 32
+        D = R.reshape(k, q, 32, q, 32).diagonal(dim1=1, dim2=3).permute(0, 3, 1, 2)
+        D = D.reshape(k * q, 32, 32)
+        Y = torch.zeros_like(D)
+        eye = torch.eye(32, dtype=R.dtype, device=R.device)
+        for i in range(31, -1, -1):
+            row = eye[i].expand(k * q, 32)
+            if i < 31:
+                row = row - (D[:, i:i + 1, i + 1:] @ Y[:, i + 1:, :])[:, 0, :]
+            Y[:, i, :] = row / D[:, i, i:i + 1]
+        Y = Y.reshape(k, q, 32, 32)
+        X = torch.zeros_like(R)
+        for I in range(q - 1, -1, -1):
+            r0, r1 = 32 * I, 32 * I + 32
+            rhs = torch.zeros((k, 32, P - r0), dtype=R.dtype, device=R.device)
+            rhs[:, :, :32] = eye
+            if r1 < P:
+                rhs[:, :, 32:] -= R[:, r0:r1, r1:] @ X[:, r1:, r1:]
+            X[:, r0:r1, r0:] = Y[:, I] @ rhs
+        return X
+
     def _chol_qr(X):
         R = torch.linalg.cholesky(X.transpose(1, 2).contiguous() @ X, upper=True)
-        return torch.linalg.solve_triangular(R, X, upper=True, left=False)
+        return X @ _inv_upper(R)
 
     for key in sorted(groups):
         P = 64 * key
