@@ -15,6 +15,8 @@
 //   batch_fft_rows          circulant products, one row a workgroup
 //   k_batch_factor          one workgroup per system, largest first (ticket)
 //   k_batch_refine          one workgroup per system, largest first (ticket)
+//   k_batch_fallback        the systems still above tol: FP64 product, GENP
+//                           and refinement, one workgroup per system
 // The factor and refinement kernels are persistent: a grid of a few
 // workgroups per compute unit takes systems from a device ticket counter in
 // descending order of size until the queue is empty, so the large systems
