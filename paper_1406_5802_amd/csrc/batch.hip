@@ -15,8 +15,11 @@
 //   batch_fft_rows          circulant products, one row a workgroup
 //   k_batch_factor          one workgroup per system, largest first (ticket)
 //   k_batch_refine          one workgroup per system, largest first (ticket)
-//   k_batch_fallback        the systems still above tol: FP64 product, GENP
-//                           and refinement, one workgroup per system
+//   k_batch_mark_fallback   the systems still above tol are marked, then
+//   batch_gemm_f64,         their FP64 products over the whole device,
+//   batch_fft_rows<double>
+//   k_batch_factor64        FP64 GENP and refinement, one workgroup per
+//   k_batch_refine64        marked system, largest first (ticket)
 // The factor and refinement kernels are persistent: a grid of a few
 // workgroups per compute unit takes systems from a device ticket counter in
 // descending order of size until the queue is empty, so the large systems
@@ -661,72 +664,27 @@ hipError_t upload(T **dst, const std::vector<T> &src) {
 // A system whose FP32-preconditioned refinement has not reached tol within
 // max_iters inner iterations is solved again from FP64 factors (the usual
 // escape of mixed-precision solvers): M = A H in FP64 with the same H (the
-// Gaussian's FP32 values, or the circulant's first column), GENP in FP64 with
-// pivot blocks of 32, and the same GMRES refinement preconditioned with those
-// factors.  Its result records the fallback and counts both stages' iterations.
+// Gaussian's FP32 values, or the circulant by FFT), GENP in FP64 with pivot
+// blocks of 32, and the same GMRES refinement preconditioned with those
+// factors.  Its result records the fallback and counts both stages'
+// iterations.  The products run as whole-device launches over the marked
+// systems' tiles or rows; factorization and refinement take the marked
+// systems from the queue like the FP32 stage.
 
-// M = A H for one system in FP64 on the matrix cores, 32 x 32 tiles a wave, K
-// in steps of 4; the B operand is G (FP32 values) or, for a circulant,
-// H[k][j] = c[(k - j) mod n] from the first column c in LDS.
-__device__ void product64_system(const BatchDesc &s, const double *__restrict__ A,
-                                 const float *__restrict__ G, const double *cc, double *M) {
-    const int n = s.n, lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    const int tiles = (n + 31) / 32;
-    const bool gauss = s.kind == RMGE_MULT_GAUSSIAN;
-    for (int t = wave; t < tiles * tiles; t += kBatchThreads / 64) {
-        const int rb = 32 * (t / tiles), cb = 32 * (t % tiles);
-        v4d acc[2][2];
-#pragma unroll
-        for (int bi = 0; bi < 2; ++bi)
-#pragma unroll
-            for (int bj = 0; bj < 2; ++bj) acc[bi][bj] = v4d{0.0, 0.0, 0.0, 0.0};
-        for (int k0 = 0; k0 < n; k0 += 4) {
-            const int k = k0 + (lane >> 4);
-            double af[2], bf[2];
-#pragma unroll
-            for (int bi = 0; bi < 2; ++bi) {
-                const int row = rb + 16 * bi + (lane & 15);
-                af[bi] = load_if(A, static_cast<int64_t>(row) * n + k, row < n && k < n);
-            }
-#pragma unroll
-            for (int bj = 0; bj < 2; ++bj) {
-                const int col = cb + 16 * bj + (lane & 15);
-                const bool in = k < n && col < n;
-                if (gauss) {
-                    bf[bj] = static_cast<double>(load_if(G, static_cast<int64_t>(k) * n + col, in));
-                } else {
-                    int d = k - col;
-                    d = d < 0 ? d + n : d;
-                    bf[bj] = in ? cc[d] : 0.0;
-                }
-            }
-#pragma unroll
-            for (int bi = 0; bi < 2; ++bi)
-#pragma unroll
-                for (int bj = 0; bj < 2; ++bj)
-                    acc[bi][bj] = Mma<double>::step(af[bi], bf[bj], acc[bi][bj]);
-        }
-#pragma unroll
-        for (int bi = 0; bi < 2; ++bi)
-#pragma unroll
-            for (int bj = 0; bj < 2; ++bj)
-#pragma unroll
-                for (int q = 0; q < 4; ++q) {
-                    const int row = rb + 16 * bi + Mma<double>::row(lane, q);
-                    const int col = cb + 16 * bj + (lane & 15);
-                    if (row < n && col < n) M[static_cast<int64_t>(row) * n + col] = acc[bi][bj][q];
-                }
+// Mark the systems to redo (status NOT_CONVERGED after the FP32 stage).
+__global__ void k_batch_mark_fallback(int count, BatchOut out) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < count && out.status[i] == RMGE_NOT_CONVERGED) {
+        out.status[i] = RMGE_OK;
+        out.fp64[i] = 1;
     }
-    __syncthreads();
 }
 
-__global__ __launch_bounds__(kBatchThreads) void k_batch_fallback(
-    int count, const BatchDesc *__restrict__ d, const double *A, const double *B, double *X,
-    const float *g_pool, const double *c_pool, double *m64_pool, double *k_pool, RefineParams p,
-    BatchOut out) {
-    __shared__ double sm[kRefineShared];
+__global__ __launch_bounds__(kBatchThreads) void k_batch_factor64(int count,
+                                                                  const BatchDesc *__restrict__ d,
+                                                                  double *m64_pool, BatchOut out) {
     __shared__ double sd[32 * 33], sinv[32];
-    __shared__ int sflag, sq, sit;
+    __shared__ int sflag, sq;
     while (true) {
         if (threadIdx.x == 0) sq = atomicAdd(out.tickets + 6, 1);
         __syncthreads();
@@ -734,23 +692,31 @@ __global__ __launch_bounds__(kBatchThreads) void k_batch_fallback(
         __syncthreads();
         if (q >= count) return;
         const BatchDesc s = d[q];
-        if (out.status[s.sys] != RMGE_NOT_CONVERGED) continue;
-        double *cc = sm + 4 * kBatchMaxN;  // where the refinement keeps the first column too
-        if (s.kind != RMGE_MULT_GAUSSIAN)
-            for (int i = threadIdx.x; i < s.n; i += kBatchThreads) cc[i] = c_pool[s.g_off + i];
-        if (threadIdx.x == 0) {
-            sit = out.iters[s.sys];
-            out.status[s.sys] = RMGE_OK;
-            out.fp64[s.sys] = 1;
-        }
+        if (out.fp64[s.sys] == 0) continue;
+        factor_system<32, double>(m64_pool + s.m_off, s.n, out.status + s.sys, out.info + s.sys,
+                                  sd, sinv, &sflag);
         __syncthreads();
-        double *m = m64_pool + s.m_off;
-        product64_system(s, A + s.a_off, g_pool + s.g_off, cc, m);
-        factor_system<32, double>(m, s.n, out.status + s.sys, out.info + s.sys, sd, sinv, &sflag);
+    }
+}
+
+__global__ __launch_bounds__(kBatchThreads) void k_batch_refine64(
+    int count, const BatchDesc *__restrict__ d, const double *A, const double *B, double *X,
+    const float *g_pool, const double *c_pool, const double *m64_pool, double *k_pool,
+    RefineParams p, BatchOut out) {
+    __shared__ double sm[kRefineShared];
+    __shared__ int sq;
+    while (true) {
+        if (threadIdx.x == 0) sq = atomicAdd(out.tickets + 7, 1);
         __syncthreads();
-        if (sflag == 0)
-            refine_system<double>(s, A, B, X, m, g_pool, c_pool, k_pool + s.k_off, p, out, sm);
-        if (threadIdx.x == 0) out.iters[s.sys] += sit;
+        const int q = sq;
+        __syncthreads();
+        if (q >= count) return;
+        const BatchDesc s = d[q];
+        if (out.fp64[s.sys] == 0 || out.status[s.sys] != RMGE_OK) continue;
+        const int first_stage = threadIdx.x == 0 ? out.iters[s.sys] : 0;
+        refine_system<double>(s, A, B, X, m64_pool + s.m_off, g_pool, c_pool, k_pool + s.k_off,
+                              p, out, sm);
+        if (threadIdx.x == 0) out.iters[s.sys] += first_stage;
         __syncthreads();
     }
 }
@@ -776,11 +742,11 @@ struct rmge_batch {
     uint64_t *d_seed = nullptr;
     // Gaussian products
     int n_gauss = 0, total_tiles = 0;
-    int *d_tile_start = nullptr, *d_nsys_g = nullptr;
+    int *d_tile_start = nullptr, *d_nsys_g = nullptr, *d_sys_g = nullptr;
     int64_t *d_aoff_g = nullptr, *d_goff_g = nullptr, *d_moff_g = nullptr;
     // circulant spectra and products
     int n_circ = 0, total_rows = 0;
-    int *d_row_start = nullptr, *d_nsys_c = nullptr, *d_logl_c = nullptr;
+    int *d_row_start = nullptr, *d_nsys_c = nullptr, *d_logl_c = nullptr, *d_sys_c = nullptr;
     int64_t *d_aoff_c = nullptr, *d_moff_c = nullptr, *d_coff_c = nullptr, *d_hoff_c = nullptr,
             *d_hhoff_c = nullptr, *d_twoff = nullptr;
     double *tw_pool = nullptr;
@@ -801,7 +767,8 @@ namespace {
 void batch_free(rmge_batch *b) {
     if (!b) return;
     if (b->exec) (void)hipGraphExecDestroy(b->exec);
-    void *ptrs[] = {b->d_chunk_start, b->d_stream, b->d_cnt, b->d_poff, b->d_seed, b->d_tile_start,
+    void *ptrs[] = {b->d_sys_g, b->d_sys_c,
+                    b->d_chunk_start, b->d_stream, b->d_cnt, b->d_poff, b->d_seed, b->d_tile_start,
                     b->d_nsys_g, b->d_aoff_g, b->d_goff_g, b->d_moff_g, b->d_row_start,
                     b->d_nsys_c, b->d_logl_c, b->d_aoff_c, b->d_moff_c, b->d_coff_c, b->d_hoff_c,
                     b->d_hhoff_c, b->d_twoff, b->tw_pool, b->lu_pool, b->g_pool, b->c_pool,
@@ -840,9 +807,9 @@ hipError_t enqueue_products(rmge_batch *b, const double *A, hipStream_t s) {
                                 b->tw_pool, s));
     BATCH_TRY(batch_gemm_f32(b->n_gauss, b->total_tiles, b->d_tile_start, b->d_nsys_g,
                              b->d_aoff_g, b->d_goff_g, b->d_moff_g, A, b->g_pool, b->lu_pool, s));
-    return batch_fft_rows(b->n_circ, b->total_rows, b->d_row_start, b->d_nsys_c, b->d_logl_c,
-                          b->d_aoff_c, b->d_moff_c, b->d_hhoff_c, b->d_twoff, A, b->hh_pool,
-                          b->tw_pool, b->lu_pool, s);
+    return batch_fft_rows<float>(b->n_circ, b->total_rows, b->d_row_start, b->d_nsys_c, nullptr,
+                                 nullptr, b->d_logl_c, b->d_aoff_c, b->d_moff_c, b->d_hhoff_c,
+                                 b->d_twoff, A, b->hh_pool, b->tw_pool, b->lu_pool, s);
 }
 
 int grid_for(int count, int per_cu) {
@@ -888,7 +855,20 @@ hipError_t enqueue_refine(rmge_batch *b, const double *A, const double *B, doubl
 hipError_t enqueue_fallback(rmge_batch *b, const double *A, const double *B, double *X,
                             double tol, hipStream_t s) {
     RefineParams p{b->restart, b->max_iters, tol};
-    hipLaunchKernelGGL(k_batch_fallback, dim3(static_cast<unsigned>(grid_for(b->count, 2))),
+    hipLaunchKernelGGL(k_batch_mark_fallback, dim3(static_cast<unsigned>((b->count + 255) / 256)),
+                       dim3(256), 0, s, b->count, b->out);
+    BATCH_TRY(hipGetLastError());
+    BATCH_TRY(batch_gemm_f64(b->n_gauss, b->total_tiles, b->d_tile_start, b->d_nsys_g, b->d_sys_g,
+                             b->out.fp64, b->d_aoff_g, b->d_goff_g, b->d_moff_g, A, b->g_pool,
+                             b->m64_pool, s));
+    BATCH_TRY(batch_fft_rows<double>(b->n_circ, b->total_rows, b->d_row_start, b->d_nsys_c,
+                                     b->d_sys_c, b->out.fp64, b->d_logl_c, b->d_aoff_c,
+                                     b->d_moff_c, b->d_hhoff_c, b->d_twoff, A, b->hh_pool,
+                                     b->tw_pool, b->m64_pool, s));
+    hipLaunchKernelGGL(k_batch_factor64, dim3(static_cast<unsigned>(grid_for(b->count, 4))),
+                       dim3(kBatchThreads), 0, s, b->count, b->d_desc, b->m64_pool, b->out);
+    BATCH_TRY(hipGetLastError());
+    hipLaunchKernelGGL(k_batch_refine64, dim3(static_cast<unsigned>(grid_for(b->count, 3))),
                        dim3(kBatchThreads), 0, s, b->count, b->d_desc, A, B, X, b->g_pool,
                        b->c_pool, b->m64_pool, b->k_pool, p, b->out);
     return hipGetLastError();
@@ -918,8 +898,8 @@ rmge_status batch_build(rmge_batch *b) {
     std::stable_sort(order.begin(), order.end(),
                      [&](int x, int y) { return b->sys[x].n > b->sys[y].n; });
     int64_t lu_total = 0, g_total = 0, c_total = 0, h_total = 0, hh_total = 0, k_total = 0;
-    std::vector<int> chunk_start{0}, stream_of, tile_start{0}, nsys_g, row_start{0}, nsys_c,
-        logl_c;
+    std::vector<int> chunk_start{0}, stream_of, tile_start{0}, nsys_g, sys_g, row_start{0}, nsys_c,
+        sys_c, logl_c;
     std::vector<int64_t> cnt, poff, aoff_g, goff_g, moff_g, aoff_c, moff_c, coff_c, hoff_c, hhoff_c;
     std::vector<uint64_t> seed;
     for (int q = 0; q < count; ++q) {
@@ -945,6 +925,7 @@ rmge_status batch_build(rmge_batch *b) {
             const int64_t tiles = ((n + 63) / 64) * ((n + 63) / 64);
             tile_start.push_back(tile_start.back() + static_cast<int>(tiles));
             nsys_g.push_back(y.n);
+            sys_g.push_back(order[q]);
             aoff_g.push_back(y.a_off);
             goff_g.push_back(d.g_off);
             moff_g.push_back(d.m_off);
@@ -955,6 +936,7 @@ rmge_status batch_build(rmge_batch *b) {
             stream_of.push_back(2);
             const int64_t m = (n >= 2 && (n & (n - 1)) == 0) ? n : std::max<int64_t>(2, int64_t(1) << log2_int(2 * n - 1));
             nsys_c.push_back(y.n);
+            sys_c.push_back(order[q]);
             logl_c.push_back(log2_int(m / 2));
             aoff_c.push_back(y.a_off);
             moff_c.push_back(d.m_off);
@@ -996,10 +978,12 @@ rmge_status batch_build(rmge_batch *b) {
     chk(upload(&b->d_seed, seed));
     chk(upload(&b->d_tile_start, tile_start));
     chk(upload(&b->d_nsys_g, nsys_g));
+    chk(upload(&b->d_sys_g, sys_g));
     chk(upload(&b->d_aoff_g, aoff_g));
     chk(upload(&b->d_goff_g, goff_g));
     chk(upload(&b->d_moff_g, moff_g));
     chk(upload(&b->d_row_start, row_start));
+    chk(upload(&b->d_sys_c, sys_c));
     chk(upload(&b->d_nsys_c, nsys_c));
     chk(upload(&b->d_logl_c, logl_c));
     chk(upload(&b->d_aoff_c, aoff_c));

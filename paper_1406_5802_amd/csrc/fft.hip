@@ -498,13 +498,16 @@ __global__ __launch_bounds__(64) void k_batch_spectrum(
 
 // Rows of the products M_s = A_s C_s of all circulant systems: row r of the
 // flattened row space (row_start: prefix sums of n_s) is row r - row_start[s]
-// of system s; A in FP64, M in FP32, both ld = n_s.
+// of system s; A in FP64, M in FP32 (the batch's factors) or FP64 (the
+// fallback), both ld = n_s.  With flag != null only the systems whose flag
+// (flag[sys[s]]) is set are done; the other rows' workgroups return at once.
+template <typename TO>
 __global__ __launch_bounds__(64) void k_batch_fft_rows(
     int count, const int *__restrict__ row_start, const int *__restrict__ nsys,
-    const int *__restrict__ logl, const int64_t *__restrict__ a_off,
-    const int64_t *__restrict__ m_off, const int64_t *__restrict__ hh_off,
-    const int64_t *__restrict__ tw_off, const double *A, const cplx *hh_pool, const cplx *tw_pool,
-    float *M) {
+    const int *__restrict__ sys, const int *__restrict__ flag, const int *__restrict__ logl,
+    const int64_t *__restrict__ a_off, const int64_t *__restrict__ m_off,
+    const int64_t *__restrict__ hh_off, const int64_t *__restrict__ tw_off, const double *A,
+    const cplx *hh_pool, const cplx *tw_pool, TO *M) {
     extern __shared__ cplx sm[];
     const int r = blockIdx.x;
     int lo = 0, hi = count - 1;
@@ -512,10 +515,12 @@ __global__ __launch_bounds__(64) void k_batch_fft_rows(
         const int mid = (lo + hi + 1) >> 1;
         if (row_start[mid] <= r) lo = mid; else hi = mid - 1;
     }
-    const int s = lo, n = nsys[s], lg = logl[s];
+    const int s = lo;
+    if (flag != nullptr && flag[sys[s]] == 0) return;
+    const int n = nsys[s], lg = logl[s];
     const int64_t i = r - row_start[s];
-    batch_row_any<double, float>(lg, A + a_off[s] + i * n, n, tw_pool + tw_off[lg],
-                                 hh_pool + hh_off[s], 1, M + m_off[s] + i * n, nullptr, sm);
+    batch_row_any<double, TO>(lg, A + a_off[s] + i * n, n, tw_pool + tw_off[lg],
+                              hh_pool + hh_off[s], 1, M + m_off[s] + i * n, nullptr, sm);
 }
 
 int log2i(int L) {
@@ -593,18 +598,31 @@ hipError_t batch_fft_spectra(int count, const int *nsys, const int *logl, const 
     return hipGetLastError();
 }
 
+template <typename TO>
 hipError_t batch_fft_rows(int count, int total_rows, const int *row_start, const int *nsys,
-                          const int *logl, const int64_t *a_off, const int64_t *m_off,
-                          const int64_t *hh_off, const int64_t *tw_off, const double *A,
-                          const double *hh_pool, const double *tw_pool, float *M, hipStream_t s) {
+                          const int *sys, const int *flag, const int *logl, const int64_t *a_off,
+                          const int64_t *m_off, const int64_t *hh_off, const int64_t *tw_off,
+                          const double *A, const double *hh_pool, const double *tw_pool, TO *M,
+                          hipStream_t s) {
     if (count <= 0 || total_rows <= 0) return hipSuccess;
     const size_t lds = sizeof(cplx) * (1024 + 64 + 1);
-    hipLaunchKernelGGL(k_batch_fft_rows, dim3(static_cast<unsigned>(total_rows)), dim3(64), lds, s,
-                       count, row_start, nsys, logl, a_off, m_off, hh_off, tw_off, A,
-                       reinterpret_cast<const cplx *>(hh_pool),
+    hipLaunchKernelGGL(k_batch_fft_rows<TO>, dim3(static_cast<unsigned>(total_rows)), dim3(64),
+                       lds, s, count, row_start, nsys, sys, flag, logl, a_off, m_off, hh_off,
+                       tw_off, A, reinterpret_cast<const cplx *>(hh_pool),
                        reinterpret_cast<const cplx *>(tw_pool), M);
     return hipGetLastError();
 }
+
+template hipError_t batch_fft_rows<float>(int, int, const int *, const int *, const int *,
+                                          const int *, const int *, const int64_t *,
+                                          const int64_t *, const int64_t *, const int64_t *,
+                                          const double *, const double *, const double *, float *,
+                                          hipStream_t);
+template hipError_t batch_fft_rows<double>(int, int, const int *, const int *, const int *,
+                                           const int *, const int *, const int64_t *,
+                                           const int64_t *, const int64_t *, const int64_t *,
+                                           const double *, const double *, const double *,
+                                           double *, hipStream_t);
 
 hipError_t fft_embed(int kind, const double *params, int64_t n, int m, double *h, hipStream_t s) {
     if (!valid_m(m)) return hipErrorInvalidValue;

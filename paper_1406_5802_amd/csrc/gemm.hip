@@ -44,10 +44,11 @@ __device__ inline void tile_coords(int bid, int tiles_m, int tiles_n, int &tm, i
 }
 
 // One BM x BN output tile (tm, tn) of C = alpha A B + beta C with bounds checks.
-// T: arithmetic type, TA: storage type of A (double A may feed a float product).
-template <typename T, typename TA, int BM, int BN, int WGM, int WGN, int BK>
+// T: arithmetic type, TA / TB: storage types of A and B (a double A may feed a
+// float product, a float B a double one).
+template <typename T, typename TA, int BM, int BN, int WGM, int WGN, int BK, typename TB = T>
 __device__ inline void gemm_tile(int M, int N, int K, T alpha, const TA *A, int64_t lda,
-                                 const T *B, int64_t ldb, T beta, T *C, int64_t ldc,
+                                 const TB *B, int64_t ldb, T beta, T *C, int64_t ldc,
                                  double *absmax, int tm, int tn) {
     constexpr int NT = WGM * WGN * 64;
     constexpr int WM = BM / WGM, WN = BN / WGN;
@@ -85,7 +86,7 @@ __device__ inline void gemm_tile(int M, int N, int K, T alpha, const TA *A, int6
         for (int p = 0; p < B_PER; ++p) {
             const int e = tid + p * NT;
             const int k = k0 + e / BN, n = n0 + e % BN;
-            rb[p] = (k < K && n < N) ? B[static_cast<int64_t>(k) * ldb + n] : T(0);
+            rb[p] = (k < K && n < N) ? static_cast<T>(B[static_cast<int64_t>(k) * ldb + n]) : T(0);
         }
     };
     auto store = [&](int buf) {
@@ -203,6 +204,35 @@ __global__ __launch_bounds__(256, 2) void k_batch_gemm(int count, const int *__r
     gemm_tile<float, double, 64, 64, 2, 2, 16>(n, n, n, 1.0f, A + a_off[s], n, G + g_off[s], n,
                                                0.0f, M + m_off[s], n, nullptr, local / tiles,
                                                local % tiles);
+}
+
+// The same index space in FP64 for the systems that fall back to FP64 factors:
+// M_s = A_s G_s with G_s's FP32 values taken exactly as doubles, only for the
+// systems whose flag (flag[sys[s]], sys: the system's index in the caller's
+// order) is set; the other tiles' workgroups return at once.
+__global__ __launch_bounds__(256, 2) void k_batch_gemm64(int count,
+                                                         const int *__restrict__ tile_start,
+                                                         const int *__restrict__ nsys,
+                                                         const int *__restrict__ sys,
+                                                         const int *__restrict__ flag,
+                                                         const int64_t *__restrict__ a_off,
+                                                         const int64_t *__restrict__ g_off,
+                                                         const int64_t *__restrict__ m_off,
+                                                         const double *A, const float *G,
+                                                         double *M) {
+    const int t = blockIdx.x;
+    int lo = 0, hi = count - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (tile_start[mid] <= t) lo = mid; else hi = mid - 1;
+    }
+    const int s = lo;
+    if (flag[sys[s]] == 0) return;
+    const int n = nsys[s];
+    const int tiles = (n + 63) / 64, local = t - tile_start[s];
+    gemm_tile<double, double, 64, 64, 2, 2, 16, float>(n, n, n, 1.0, A + a_off[s], n,
+                                                       G + g_off[s], n, 0.0, M + m_off[s], n,
+                                                       nullptr, local / tiles, local % tiles);
 }
 
 // Interior fast path: M % 128 == N % 128 == K % 16 == 0, lda, ldb, ldc even.
@@ -1003,6 +1033,16 @@ hipError_t batch_gemm_f32(int count, int total_tiles, const int *tile_start, con
     if (count <= 0 || total_tiles <= 0) return hipSuccess;
     hipLaunchKernelGGL(k_batch_gemm, dim3(static_cast<unsigned>(total_tiles)), dim3(256), 0, s,
                        count, tile_start, nsys, a_off, g_off, m_off, A, G, M);
+    return hipGetLastError();
+}
+
+hipError_t batch_gemm_f64(int count, int total_tiles, const int *tile_start, const int *nsys,
+                          const int *sys, const int *flag, const int64_t *a_off,
+                          const int64_t *g_off, const int64_t *m_off, const double *A,
+                          const float *G, double *M, hipStream_t s) {
+    if (count <= 0 || total_tiles <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_batch_gemm64, dim3(static_cast<unsigned>(total_tiles)), dim3(256), 0, s,
+                       count, tile_start, nsys, sys, flag, a_off, g_off, m_off, A, G, M);
     return hipGetLastError();
 }
 

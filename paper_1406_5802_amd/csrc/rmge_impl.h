@@ -93,6 +93,13 @@ hipError_t update_bf16(int terms, int64_t M, int64_t N, int64_t K, const float *
 hipError_t batch_gemm_f32(int count, int total_tiles, const int *tile_start, const int *nsys,
                           const int64_t *a_off, const int64_t *g_off, const int64_t *m_off,
                           const double *A, const float *G, float *M, hipStream_t s);
+// The same in FP64 (G's FP32 values as doubles, M FP64) for the systems whose
+// flag[sys[s]] is nonzero (sys, flag: device arrays; sys maps the list to the
+// caller's system index).
+hipError_t batch_gemm_f64(int count, int total_tiles, const int *tile_start, const int *nsys,
+                          const int *sys, const int *flag, const int64_t *a_off,
+                          const int64_t *g_off, const int64_t *m_off, const double *A,
+                          const float *G, double *M, hipStream_t s);
 hipError_t gemm_f32_a64(int shape, int64_t M, int64_t N, int64_t K, float alpha, const double *A,
                         int64_t lda, const float *B, int64_t ldb, float beta, float *C,
                         int64_t ldc, const int *abort, hipStream_t s, double *absmax = nullptr);
@@ -258,12 +265,16 @@ hipError_t batch_fft_spectra(int count, const int *nsys, const int *logl, const 
                              const int64_t *h_off, const int64_t *hh_off, const int64_t *tw_off,
                              const double *c_pool, double *h_pool, double *hh_pool,
                              const double *tw_pool, hipStream_t s);
-// Rows of M_s = A_s C_s (A FP64 at a_off[s], M FP32 at m_off[s], ld = n_s) for
-// all circulant systems; row_start: count + 1 prefix sums of n_s.
+// Rows of M_s = A_s C_s (A FP64 at a_off[s], M of type TO (float or double) at
+// m_off[s], ld = n_s) for all circulant systems; row_start: count + 1 prefix
+// sums of n_s.  With flag != null, only the systems whose flag[sys[s]] is
+// nonzero (sys, flag: device arrays).
+template <typename TO>
 hipError_t batch_fft_rows(int count, int total_rows, const int *row_start, const int *nsys,
-                          const int *logl, const int64_t *a_off, const int64_t *m_off,
-                          const int64_t *hh_off, const int64_t *tw_off, const double *A,
-                          const double *hh_pool, const double *tw_pool, float *M, hipStream_t s);
+                          const int *sys, const int *flag, const int *logl, const int64_t *a_off,
+                          const int64_t *m_off, const int64_t *hh_off, const int64_t *tw_off,
+                          const double *A, const double *hh_pool, const double *tw_pool, TO *M,
+                          hipStream_t s);
 hipError_t fft_spectrum(const double *h, int m, const double *tw, double *hhat, hipStream_t s);
 template <typename TI, typename TO>
 hipError_t fft_rows(const TI *in, int64_t vstride_in, int64_t estride_in, int64_t count,
