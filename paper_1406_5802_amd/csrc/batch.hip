@@ -344,29 +344,45 @@ __device__ inline double block_reduce(double v, bool is_max, double *red) {
     return r;
 }
 
-// y = M x for an n x n row-major M (FP64 or FP32, ld n), x and y in LDS; one
-// wave a row, four rows in flight.  With rowsum != null, also the largest row
-// sum of |M| into *rowsum (thread 0's copy is the result).
+// y = M x for an n x n row-major M (FP64 or FP32, ld n), x and y in LDS: each
+// wave takes eight rows at a time, its lanes consecutive columns, two 64-column
+// chunks a round, so sixteen loads a lane are in flight (a single workgroup
+// streams its system's matrix: its loads in flight set the bandwidth it gets).
+// With rowsum != null, also the largest row sum of |M| into *rowsum (thread
+// 0's copy is the result).
 template <typename TM>
 __device__ void block_matvec(const TM *__restrict__ M, int n, const double *x, double *y,
                              double *rowsum, double *red) {
+    constexpr int RW = 8;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    constexpr int NW = kBatchThreads / 64;
     double worst = 0.0;
-    for (int r0 = 4 * wave; r0 < n; r0 += 16) {
-        double acc[4] = {0.0, 0.0, 0.0, 0.0}, asum[4] = {0.0, 0.0, 0.0, 0.0};
-        for (int c = lane; c < n; c += 64) {
-            const double xc = x[c];
+    for (int r0 = RW * wave; r0 < n; r0 += RW * NW) {
+        double acc[RW], asum[RW];
 #pragma unroll
-            for (int u = 0; u < 4; ++u) {
+        for (int u = 0; u < RW; ++u) acc[u] = asum[u] = 0.0;
+        for (int c0 = 0; c0 < n; c0 += 128) {
+            const int c1 = c0 + lane, c2 = c0 + 64 + lane;
+            const double x1 = c1 < n ? x[c1] : 0.0, x2 = c2 < n ? x[c2] : 0.0;
+            TM m1[RW], m2[RW];
+#pragma unroll
+            for (int u = 0; u < RW; ++u) {
                 const int r = r0 + u;
-                const double m = static_cast<double>(load_if(M, static_cast<int64_t>(r) * n + c,
-                                                             r < n));
-                acc[u] += m * xc;
-                asum[u] += fabs(m);
+                const int64_t base = static_cast<int64_t>(r) * n;
+                m1[u] = load_if(M, base + c1, r < n && c1 < n);
+                m2[u] = load_if(M, base + c2, r < n && c2 < n);
+            }
+#pragma unroll
+            for (int u = 0; u < RW; ++u) {
+                const double a1 = static_cast<double>(m1[u]), a2 = static_cast<double>(m2[u]);
+                acc[u] += a1 * x1;
+                acc[u] += a2 * x2;
+                asum[u] += fabs(a1);
+                asum[u] += fabs(a2);
             }
         }
 #pragma unroll
-        for (int u = 0; u < 4; ++u) {
+        for (int u = 0; u < RW; ++u) {
             const double v = wave_sum(acc[u]);
             if (rowsum) worst = fmax(worst, wave_sum(asum[u]));
             if (lane == 0 && r0 + u < n) y[r0 + u] = v;
@@ -425,12 +441,34 @@ __device__ void block_trsv(const TF *__restrict__ lu, int n, double *y) {
             if (in) y[b0 + lane] = yi;
         }
         __syncthreads();
+        // the rows not yet solved lose the block's contribution: 16 lanes a row
+        // (lane `sub` takes columns sub and sub + 16 of the block, so a row's
+        // 32 values are read by consecutive lanes), four rows a wave at a time
+        // and four such groups in flight, the row sums by shuffles in the group
         const int rlo = UPPER ? 0 : b0 + bs, rhi = UPPER ? b0 : n;
-        for (int r = rlo + tid; r < rhi; r += kBatchThreads) {
-            const TF *l1 = lu + static_cast<int64_t>(r) * n + b0;
-            double acc = 0.0;
-            for (int j = 0; j < bs; ++j) acc += static_cast<double>(l1[j]) * y[b0 + j];
-            y[r] -= acc;
+        const int sub = lane & 15, grp = lane >> 4;
+        const double y1 = sub < bs ? y[b0 + sub] : 0.0;
+        const double y2 = sub + 16 < bs ? y[b0 + sub + 16] : 0.0;
+        for (int base = rlo + 16 * wave; base < rhi; base += 16 * (kBatchThreads / 64)) {
+            double acc[4];
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+                const int r = base + 4 * k + grp;
+                const bool in = r < rhi;
+                const TF *l1 = lu + static_cast<int64_t>(in ? r : rlo) * n + b0;
+                acc[k] = static_cast<double>(load_if(l1, sub, in && sub < bs)) * y1 +
+                         static_cast<double>(load_if(l1, sub + 16, in && sub + 16 < bs)) * y2;
+            }
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+                double v = acc[k];
+                v += __shfl_xor(v, 8);
+                v += __shfl_xor(v, 4);
+                v += __shfl_xor(v, 2);
+                v += __shfl_xor(v, 1);
+                const int r = base + 4 * k + grp;
+                if (sub == 0 && r < rhi) y[r] -= v;
+            }
         }
         __syncthreads();
     }
@@ -480,6 +518,7 @@ __device__ void refine_system(const BatchDesc &s, const double *__restrict__ A,
     double *cs = gv + kBatchMaxRestart + 1, *sn = cs + kBatchMaxRestart;
     double *yv = sn + kBatchMaxRestart, *hv = yv + kBatchMaxRestart;  // hv: 2 x 32 dots
     double *red = hv + 2 * kBatchMaxRestart;  // [0, 8) reductions, [8], [9] scalars
+    double *part = red + 16;                  // per-wave dot products, 4 x (32 + 1)
     double *V = K, *Z = K + static_cast<int64_t>(R + 1) * n;
     const double *A_s = A + s.a_off;
     const double *cpar = cpool + s.g_off;
@@ -537,14 +576,35 @@ __device__ void refine_system(const BatchDesc &s, const double *__restrict__ A,
             for (int i = tid; i < n; i += kBatchThreads) zj[i] = ws[i];
             __syncthreads();
             block_matvec<double>(A_s, n, ws, ts, nullptr, red);  // ts = A z_j
-            // classical Gram-Schmidt, twice
+            // classical Gram-Schmidt, twice; the j + 1 dot products of a pass
+            // eight at a time (their loads in flight together), each summed
+            // over its wave, the waves' partial sums added after one barrier
             for (int pass = 0; pass < 2; ++pass) {
-                for (int i = 0; i <= j; ++i) {
-                    const double *vi = V + static_cast<int64_t>(i) * n;
-                    double d = 0.0;
-                    for (int e = tid; e < n; e += kBatchThreads) d += vi[e] * ts[e];
-                    d = block_reduce(d, false, red);
-                    if (tid == 0) hv[pass * kBatchMaxRestart + i] = d;
+                for (int i0 = 0; i0 <= j; i0 += 8) {
+                    double d[8];
+#pragma unroll
+                    for (int u = 0; u < 8; ++u) d[u] = 0.0;
+                    for (int e = tid; e < n; e += kBatchThreads) {
+                        const double te = ts[e];
+#pragma unroll
+                        for (int u = 0; u < 8; ++u)
+                            if (i0 + u <= j) d[u] += V[static_cast<int64_t>(i0 + u) * n + e] * te;
+                    }
+#pragma unroll
+                    for (int u = 0; u < 8; ++u) {
+                        if (i0 + u <= j) {
+                            const double w = wave_sum(d[u]);
+                            if ((tid & 63) == 0) part[(tid >> 6) * (kBatchMaxRestart + 1) + i0 + u] = w;
+                        }
+                    }
+                }
+                __syncthreads();
+                if (tid <= j) {
+                    double r = part[tid];
+#pragma unroll
+                    for (int w = 1; w < kBatchThreads / 64; ++w)
+                        r += part[w * (kBatchMaxRestart + 1) + tid];
+                    hv[pass * kBatchMaxRestart + tid] = r;
                 }
                 __syncthreads();
                 for (int e = tid; e < n; e += kBatchThreads) {
@@ -614,7 +674,7 @@ __device__ void refine_system(const BatchDesc &s, const double *__restrict__ A,
 
 constexpr int kRefineShared =
     5 * kBatchMaxN + (kBatchMaxRestart + 1) * kBatchMaxRestart + (kBatchMaxRestart + 1) +
-    5 * kBatchMaxRestart + 16;
+    5 * kBatchMaxRestart + 16 + (kBatchThreads / 64) * (kBatchMaxRestart + 1);
 
 __global__ __launch_bounds__(kBatchThreads) void k_batch_refine(
     int count, const BatchDesc *__restrict__ d, const double *A, const double *B, double *X,
