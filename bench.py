@@ -62,8 +62,8 @@ TRAFFIC_BF16 = {"n": 16384, "source": "k_gemm_bf16x2 + tile_coords (csrc/gemm.hi
 # n = 4096, the structured workload): profiles/k_fft_stockham_circulant_n4096_hbm_traffic.txt.  The
 # fingerprint covers the whole FFT source file.
 TRAFFIC_FFT = {"n": 4096, "source": "csrc/fft.hip",
-               "sha256": "e4403c6b81a3aa5ac5d64eb90d3814fc8f7827ad12ab6522384be8f2d243306a",
-               "fetch_kib": 132433.8, "write_kib": 131328.0}
+               "sha256": "2726bbd8fb0eb5868ecdcff8a428b02b211c312258a4b4503bd03c16ca538258",
+               "fetch_kib": 132395.1, "write_kib": 131328.0}
 
 
 def log(msg):

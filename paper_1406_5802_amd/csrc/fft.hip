@@ -124,6 +124,17 @@ __device__ inline void dft_reg(cplx *a, bool inv) {
 
 __device__ inline int lds_pad(int i) { return i + (i >> 4); }
 
+// A complex value to or from LDS as one 16-byte access (ds_read_b128 /
+// ds_write_b128): as two 8-byte halves, consecutive lanes' accesses 16 bytes
+// apart fall on every other bank pair and conflict two ways.
+__device__ inline cplx lds_get(const cplx *sm, int i) {
+    const double2 v = reinterpret_cast<const double2 *>(sm)[i];
+    return {v.x, v.y};
+}
+__device__ inline void lds_put(cplx *sm, int i, cplx v) {
+    reinterpret_cast<double2 *>(sm)[i] = double2{v.x, v.y};
+}
+
 // Radix of pass p (0-based) of a length-2^LOGL transform: 16 while four bits
 // remain, then the rest.
 template <int LOGL>
@@ -174,7 +185,7 @@ __device__ inline void pass_store(const cplx *a, int tid, cplx *sm) {
     for (int q = 0; q < Q; ++q) {
         const int j = tid + q * T, k = j & (NS - 1), base = (j / NS) * NS * R + k;
 #pragma unroll
-        for (int s = 0; s < R; ++s) sm[lds_pad(base + s * NS)] = a[q * R + s];
+        for (int s = 0; s < R; ++s) lds_put(sm, lds_pad(base + s * NS), a[q * R + s]);
     }
 }
 
@@ -187,7 +198,7 @@ __device__ inline void pass_load(cplx *a, int tid, const cplx *sm) {
     for (int q = 0; q < Q; ++q) {
         const int j = tid + q * T;
 #pragma unroll
-        for (int r = 0; r < R; ++r) a[q * R + r] = sm[lds_pad(j + r * (L / R))];
+        for (int r = 0; r < R; ++r) a[q * R + r] = lds_get(sm, lds_pad(j + r * (L / R)));
     }
 }
 
@@ -273,7 +284,7 @@ __device__ inline void fft_row_regs(cplx *a, int64_t n, const cplx *__restrict__
         for (int q = 0; q < V / RL; ++q)
 #pragma unroll
             for (int s2 = 0; s2 < RL; ++s2)
-                sm[lds_pad(tid + q * T + s2 * (L / RL))] = a[q * RL + s2];
+                lds_put(sm, lds_pad(tid + q * T + s2 * (L / RL)), a[q * RL + s2]);
     }
     __syncthreads();
     // pairs (f, L - f): untangle the real spectrum, apply the kernel, re-pack
@@ -284,7 +295,7 @@ __device__ inline void fft_row_regs(cplx *a, int64_t n, const cplx *__restrict__
         const int f = tid + qf * BD;
         if (f > L / 2) break;
         const int g = (L - f) & (L - 1);
-        const cplx Zf = sm[lds_pad(f)], Zg = sm[lds_pad(g)];
+        const cplx Zf = lds_get(sm, lds_pad(f)), Zg = lds_get(sm, lds_pad(g));
         const cplx e = cscale(Zf + cconj(Zg), 0.5);
         const cplx dd = Zf - cconj(Zg);
         const cplx o = {0.5 * dd.y, -0.5 * dd.x};  // -i/2 (Z_f - conj Z_{L-f})
@@ -308,10 +319,10 @@ __device__ inline void fft_row_regs(cplx *a, int64_t n, const cplx *__restrict__
         const cplx Yf = cmul(Xf, Hf), Yg = cmul(Xg, Hg);
         const cplx ep = cscale(Yf + cconj(Yg), 0.5);
         const cplx op = cscale(cmul(Yf - cconj(Yg), cconj(w)), 0.5);
-        sm[lds_pad(f)] = {ep.x - op.y, ep.y + op.x};  // E' + i O'
+        lds_put(sm, lds_pad(f), {ep.x - op.y, ep.y + op.x});  // E' + i O'
         if (f != 0 && g != f) {
             const cplx ec = cconj(ep), oc = cconj(op);
-            sm[lds_pad(g)] = {ec.x - oc.y, ec.y + oc.x};
+            lds_put(sm, lds_pad(g), {ec.x - oc.y, ec.y + oc.x});
         }
     }
     if (spec != nullptr) return;
