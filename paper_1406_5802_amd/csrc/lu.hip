@@ -419,6 +419,146 @@ __device__ inline void sub_block_inverse(bool upper, int lane, int q0, int sbq,
     }
 }
 
+// GENP of one pivot block (b <= 128) held in LDS, by panels of 16 columns, in
+// one launch of four waves.  Panel at column c0 (eq. eqgenp with a pivot block of
+// 16 inside the pivot block):
+//   (1) wave 0 eliminates the panel's 16 columns over rows c0 .. b - 1, two
+//       rows a lane in registers; the pivot row of step j is lane j's first
+//       row, its entries reach the other lanes by readlane, and the multiplier
+//       is formed with the pivot's reciprocal (no barrier inside the panel);
+//   (2) U12 = L11^{-1} A12 for the 16 rows of the panel, one thread a column,
+//       by substitution (L11's entries are LDS broadcasts);
+//   (3) A22 -= L21 U12 on the matrix cores, 16 x 16 tiles dealt to the waves.
+// The chain is 16 register steps a panel plus two short shared-memory phases,
+// instead of one cross-wave hand-off per column.  A zero or non-finite pivot
+// records its global index and stops the block (the later kernels see the
+// status and exit).  The block is written back in place.
+template <typename T>
+__global__ __launch_bounds__(256) void k_leaf_genp(T *a, int64_t lda, int b, int64_t k0,
+                                                   DevStatus *st) {
+    constexpr int LD = kLeaf + 1;
+    __shared__ T S[kLeaf * LD];
+    __shared__ int s_fail;
+    if (st->code != 0) return;  // an earlier pivot block broke down
+    __builtin_amdgcn_s_setprio(3);
+    const int tid = threadIdx.x, lane = tid & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+    if (tid == 0) s_fail = 0;
+    // the block into LDS: thread (tid & 127) takes a column, 32 rows a round,
+    // all sixteen of a thread's loads in flight together
+    const int lc = tid & 127, lr = tid >> 7;
+    for (int i0 = 0; i0 < b; i0 += 32) {
+        T v[16];
+#pragma unroll
+        for (int u = 0; u < 16; ++u) {
+            const int i = i0 + 2 * u + lr;
+            v[u] = load_if(a, static_cast<int64_t>(i) * lda + lc, i < b && lc < b);
+        }
+#pragma unroll
+        for (int u = 0; u < 16; ++u) {
+            const int i = i0 + 2 * u + lr;
+            if (i < b && lc < b) S[i * LD + lc] = v[u];
+        }
+    }
+    __syncthreads();
+    for (int c0 = 0; c0 < b; c0 += 16) {
+        const int w = min(16, b - c0);
+        if (wave == 0) {
+            const int r0 = c0 + lane, r1 = c0 + 64 + lane;
+            const bool v0 = r0 < b, v1 = r1 < b;
+            T x0[16], x1[16];
+#pragma unroll
+            for (int k = 0; k < 16; ++k) {
+                const bool kc = k < w;
+                x0[k] = (v0 && kc) ? S[r0 * LD + c0 + k] : T(0);
+                x1[k] = (v1 && kc) ? S[r1 * LD + c0 + k] : T(0);
+            }
+            int fail = 0;
+#pragma unroll
+            for (int j = 0; j < 16; ++j) {
+                if (j < w && fail == 0) {
+                    const T p = lane_value<T>(x0[j], j);
+                    if (is_bad(p)) {
+                        fail = 1;
+                        if (lane == 0) {
+                            st->info = k0 + c0 + j;
+                            st->code = (p == T(0)) ? 4 : 5;
+                            s_fail = 1;
+                        }
+                    } else {
+                        const T inv = T(1) / p;
+                        const T m0 = lane > j ? x0[j] * inv : T(0);
+                        const T m1 = x1[j] * inv;
+                        if (lane > j) x0[j] = m0;
+                        x1[j] = m1;
+#pragma unroll
+                        for (int k = j + 1; k < 16; ++k) {
+                            const T u = lane_value<T>(x0[k], j);
+                            x0[k] -= m0 * u;
+                            x1[k] -= m1 * u;
+                        }
+                    }
+                }
+                // keep each step's pivot-row reads next to their use (hoisted
+                // together they exhaust the scalar registers and spill)
+                __builtin_amdgcn_sched_barrier(0);
+            }
+#pragma unroll
+            for (int k = 0; k < 16; ++k) {
+                if (k < w) {
+                    if (v0) S[r0 * LD + c0 + k] = x0[k];
+                    if (v1) S[r1 * LD + c0 + k] = x1[k];
+                }
+            }
+        }
+        __syncthreads();
+        if (s_fail) break;
+        if (c0 + w >= b) break;  // w == 16 below
+        const int c1 = c0 + 16, rest = b - c1;
+        // (2) U12 <- L11^{-1} A12, one thread a column
+        if (tid < rest) {
+            const int col = c1 + tid;
+            T y[16];
+#pragma unroll
+            for (int i = 0; i < 16; ++i) y[i] = S[(c0 + i) * LD + col];
+#pragma unroll
+            for (int i = 1; i < 16; ++i)
+#pragma unroll
+                for (int k = 0; k < i; ++k) y[i] -= S[(c0 + i) * LD + c0 + k] * y[k];
+#pragma unroll
+            for (int i = 1; i < 16; ++i) S[(c0 + i) * LD + col] = y[i];
+        }
+        __syncthreads();
+        // (3) A22 -= L21 U12 on the matrix cores
+        const int tn = (rest + 15) / 16;
+        for (int t = wave; t < tn * tn; t += 4) {
+            const int rb = c1 + 16 * (t / tn), cb = c1 + 16 * (t % tn);
+            typename Mma<T>::acc acc;
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const int row = rb + Mma<T>::row(lane, q), col = cb + (lane & 15);
+                acc[q] = (row < b && col < b) ? S[row * LD + col] : T(0);
+            }
+#pragma unroll
+            for (int kk = 0; kk < 16; kk += 4) {
+                const int k = c0 + kk + (lane >> 4);
+                const int ar = rb + (lane & 15), bc = cb + (lane & 15);
+                const T av = ar < b ? -S[ar * LD + k] : T(0);
+                const T bv = bc < b ? S[k * LD + bc] : T(0);
+                acc = Mma<T>::step(av, bv, acc);
+            }
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const int row = rb + Mma<T>::row(lane, q), col = cb + (lane & 15);
+                if (row < b && col < b) S[row * LD + col] = acc[q];
+            }
+        }
+        __syncthreads();
+    }
+    for (int i = lr; i < b; i += 2)
+        if (lc < b) a[static_cast<int64_t>(i) * lda + lc] = S[i * LD + lc];
+}
+
 // Inverses of the 32 x 32 diagonal sub-blocks of factored diagonal blocks
 // (the off-diagonal coupling is applied by blocked substitution, so only these
 // small inverses are formed).  Workgroup g covers rows 128 g .. 128 g + 127 of
@@ -937,8 +1077,7 @@ hipError_t leaf_lu(T *a, int64_t lda, int b, T *Linv, T *Uinv, int64_t k0, DevSt
         hipLaunchKernelGGL((k_leaf_lu<T, true>), dim3(1), dim3(kLeafThreads), 0, s, a, lda, b, k0,
                            st, piv);
     else
-        hipLaunchKernelGGL((k_leaf_lu<T, false>), dim3(1), dim3(kLeafThreads), 0, s, a, lda, b, k0,
-                           st, piv);
+        hipLaunchKernelGGL(k_leaf_genp<T>, dim3(1), dim3(256), 0, s, a, lda, b, k0, st);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k_diag_inv<T>, dim3(1), dim3(512), 0, s, a, lda, b, Linv, Uinv, st);
