@@ -191,11 +191,17 @@ rmge_status rmge_solve(const rmge_factors *f, const double *B, int64_t nrhs, int
  * eta <= tol or after max_iters inner iterations for that right-hand side.
  * trans = 1 solves the adjoint system A^T x = b the same way (operator A^T,
  * preconditioner P^T L^{-T} U^{-T} H^T, eta with ||A||_1).
- * restart: 1..64.  tol > 0.  st->iters counts inner iterations over all
- * right-hand sides;
- * st->eta_hist holds eta at each outer check (first 17).  Returns
- * RMGE_NOT_CONVERGED if some right-hand side ends above tol.  Workspace:
- * (2 restart + 2) n doubles, kept by the handle. */
+ * restart: 1..64.  tol > 0.  With one right-hand side st->iters counts its
+ * inner iterations.  With 2..64 right-hand sides their Arnoldi processes
+ * advance together (one preconditioner application, one product with op(A)
+ * and one Gram-Schmidt pass a step for all of them; each column keeps its
+ * own rotations and stops, keeping its iterate, once it meets the
+ * estimate); st->iters then counts these joint steps and max_iters bounds
+ * them.  More than 64 right-hand sides are refined one at a time.
+ * st->eta_hist holds the worst eta at each outer check (first 17).  Returns
+ * RMGE_NOT_CONVERGED if some right-hand side ends above tol.  Workspace,
+ * kept by the handle: (2 restart + 2) n doubles for one right-hand side,
+ * (2 restart + 2) n nrhs + 256 (restart + 1) nrhs doubles for several. */
 rmge_status rmge_solve_gmres(const rmge_factors *f, int32_t trans, const double *B, int64_t nrhs,
                              int64_t ldb, double *X, int64_t ldx, int32_t max_iters,
                              int32_t restart, double tol, rmge_solve_stats *st);

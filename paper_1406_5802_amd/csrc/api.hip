@@ -85,6 +85,8 @@ struct rmge_factors {
     // vectors Z (restart), residual, partial sums and small device vectors
     double *kv = nullptr;
     int kv_restart = 0;
+    double *kb = nullptr;  // block Krylov workspace (several right-hand sides)
+    int64_t kb_words = 0;
     // host copies
     DevStatus host_st{-1, 0, 0};
     bool stats_done = false;
@@ -477,7 +479,7 @@ void free_handle(rmge_factors *f) {
     if (!f) return;
     void *ptrs[] = {f->lu, f->G, f->params, f->hker, f->hhat, f->tw, f->inv, f->sinv, f->binv,
                     f->piv, f->st, f->a32, f->a16, f->ht16, f->u16, f->wht, f->scal, f->wy, f->wx, f->wr,
-                    f->wnorm, f->wt, f->wsync, f->kv};
+                    f->wnorm, f->wt, f->wsync, f->kv, f->kb};
     for (void *p : ptrs)
         if (p) (void)hipFree(p);
     for (hipEvent_t &e : f->ev)
@@ -1031,6 +1033,214 @@ rmge_status run_gmres(rmge_factors *f, bool trans, const double *B, int64_t nrhs
     return all_ok ? RMGE_OK : RMGE_NOT_CONVERGED;
 }
 
+// Several right-hand sides at once (2 <= nrhs <= 64): the same restarted FGMRES
+// as run_gmres for every column, with the columns' Arnoldi processes advanced
+// together, so each iteration is one preconditioner application, one product
+// with op(A) and one Gram-Schmidt pass for all of them, and one host
+// synchronisation (for the columns' Givens rotations) instead of one per
+// column.  A column that has met the tolerance, or whose Krylov space stopped
+// growing, keeps its iterate: its basis vectors from then on are zero.
+template <typename T>
+rmge_status run_gmres_block(rmge_factors *f, bool trans, const double *B, int64_t m, int64_t ldb,
+                            double *X, int64_t ldx, int32_t max_iters, int32_t restart, double tol,
+                            rmge_solve_stats *st) {
+    rmge_status rs = ensure_solve_ws(f, m, trans);
+    if (rs != RMGE_OK) return rs;
+    const int64_t n = f->n;
+    const int R = restart;
+    const int mi = static_cast<int>(m);
+    const int64_t nm = n * m;
+    const int64_t words = (2 * static_cast<int64_t>(R) + 2) * nm + 256 * (R + 1) * m +
+                          (3 * static_cast<int64_t>(R) + 8) * m;
+    if (f->kb_words < words) {
+        if (f->kb) (void)hipFree(f->kb);
+        f->kb = nullptr;
+        f->kb_words = 0;
+        RMGE_TRY(hipMalloc(&f->kb, sizeof(double) * static_cast<size_t>(words)));
+        f->kb_words = words;
+    }
+    hipStream_t s = f->stream;
+    double *V = f->kb;                         // (R + 1) blocks n x m
+    double *Z = V + (R + 1) * nm;              // R blocks
+    double *W = Z + R * nm;                    // n x m
+    double *part = W + nm;                     // 256 (R + 1) m
+    double *d1 = part + 256 * (R + 1) * m;     // (R + 1) m: first Gram-Schmidt pass
+    double *d2 = d1 + (R + 1) * m;             // (R + 1) m: second pass
+    double *w2 = d2 + (R + 1) * m;             // m
+    double *scl = w2 + m;                      // m
+    double *yv = scl + m;                      // R m: update coefficients
+    double *nrm = yv + R * m;                  // 3 m: max norms of r, x, b
+    auto precond = [&](const double *src, int64_t lds, double *dst, int64_t ldd) {
+        return trans ? apply_adjoint<T>(f, src, lds, m, dst, ldd, 0.0)
+                     : apply_inverse<T>(f, src, lds, m, dst, ldd, 0.0);
+    };
+    // dst (n x m, ld m) = op(A) z (ld ldz), sixteen columns a launch
+    auto op = [&](const double *z, int64_t ldz, double *dst) -> hipError_t {
+        for (int64_t g = 0; g < m; g += 16) {
+            const int nr = static_cast<int>((m - g) < 16 ? (m - g) : 16);
+            const hipError_t e =
+                trans ? gemv_t<double, double, double>(n, n, f->A, f->lda, z + g, ldz, dst + g, m,
+                                                       nr, f->wt, s)
+                      : gemv_n<double, double, double>(n, n, 1.0, f->A, f->lda, z + g, ldz, 0.0,
+                                                       dst + g, m, nr, s);
+            if (e != hipSuccess) return e;
+        }
+        return hipSuccess;
+    };
+    RMGE_TRY(precond(B, ldb, X, ldx));
+    double anorm = 0.0;
+    {
+        double *slot = trans ? f->scal + 4 : f->scal + 3;
+        bool &done = trans ? f->anorm1_done : f->anorm_done;
+        double &val = trans ? f->anorm1 : f->anorm;
+        if (!done) {
+            RMGE_TRY(fill_f64(slot, 1, 0.0, s));
+            if (trans)
+                RMGE_TRY(norm_one(f->A, f->lda, n, f->wt, slot, s));
+            else
+                RMGE_TRY(norm_inf(f->A, f->lda, n, slot, s));
+            RMGE_TRY(hipMemcpyAsync(&val, slot, sizeof(double), hipMemcpyDeviceToHost, s));
+            RMGE_TRY(hipStreamSynchronize(s));
+            done = true;
+        }
+        anorm = val;
+    }
+    const size_t M = static_cast<size_t>(m);
+    std::vector<double> H(M * (R + 1) * R), cs(M * R), sn(M * R), g(M * (R + 1)), hy(M * R),
+        hh(M * (2 * (R + 1) + 1)), eta(M, 0.0), eta0(M, -1.0), tgt(M, 0.0), beta(M, 0.0),
+        sc(M, 0.0), hn(M), hst(3 * M);
+    std::vector<char> active(M, 0), live(M, 0);
+    int hist = 0, total = 0;
+    rmge_solve_stats loc{};
+    while (true) {
+        // W = B - op(A) X; per column eta and ||r||_2
+        RMGE_TRY(op(X, ldx, W));
+        RMGE_TRY((axpby_2d<double>(B, ldb, W, m, n, mi, -1.0, s)));
+        RMGE_TRY(fill_f64(nrm, 3 * m, 0.0, s));
+        RMGE_TRY(colmax_abs(W, m, n, mi, nrm, s));
+        RMGE_TRY(colmax_abs(X, ldx, n, mi, nrm + m, s));
+        RMGE_TRY(colmax_abs(B, ldb, n, mi, nrm + 2 * m, s));
+        RMGE_TRY(bdot(W, n, mi, 1, W, m, part, w2, false, s));
+        RMGE_TRY(hipMemcpyAsync(hst.data(), nrm, sizeof(double) * 3 * M, hipMemcpyDeviceToHost, s));
+        RMGE_TRY(hipMemcpyAsync(hn.data(), w2, sizeof(double) * M, hipMemcpyDeviceToHost, s));
+        RMGE_TRY(hipStreamSynchronize(s));
+        double worst = 0.0;
+        bool any = false;
+        for (size_t c = 0; c < M; ++c) {
+            const double scale = anorm * hst[M + c] + hst[2 * M + c];
+            eta[c] = hst[c] / scale;
+            if (eta0[c] < 0.0) eta0[c] = eta[c];
+            worst = (eta[c] > worst || eta[c] != eta[c]) ? eta[c] : worst;
+            beta[c] = std::sqrt(hn[c]);
+            active[c] = (eta[c] > tol && eta[c] == eta[c] && beta[c] > 0.0) ? 1 : 0;
+            tgt[c] = 0.5 * tol * scale;
+            any = any || active[c];
+        }
+        if (hist < 17) loc.eta_hist[hist++] = worst;
+        if (!any || total >= max_iters) break;
+        // V_0 = W / beta on the active columns, zero elsewhere
+        for (size_t c = 0; c < M; ++c) {
+            sc[c] = active[c] ? 1.0 / beta[c] : 0.0;
+            live[c] = active[c];
+        }
+        RMGE_TRY(hipMemcpyAsync(scl, sc.data(), sizeof(double) * M, hipMemcpyHostToDevice, s));
+        RMGE_TRY(bscale(V, W, m, n, mi, scl, s));
+        std::fill(g.begin(), g.end(), 0.0);
+        for (size_t c = 0; c < M; ++c) g[c * (R + 1)] = active[c] ? beta[c] : 0.0;
+        int k = 0;
+        for (int j = 0; j < R && total < max_iters; ++j) {
+            double *Vj = V + j * nm, *Zj = Z + j * nm, *Vn = V + (j + 1) * nm;
+            RMGE_TRY(precond(Vj, m, Zj, m));
+            RMGE_TRY(op(Zj, m, W));
+            RMGE_TRY(bdot(V, n, mi, j + 1, W, m, part, d1, false, s));
+            RMGE_TRY(blincomb(W, m, V, n, mi, j + 1, d1, -1.0, s));
+            RMGE_TRY(bdot(V, n, mi, j + 1, W, m, part, d2, false, s));
+            RMGE_TRY(blincomb(W, m, V, n, mi, j + 1, d2, -1.0, s));
+            RMGE_TRY(bdot(W, n, mi, 1, W, m, part, w2, false, s));
+            const size_t nd = static_cast<size_t>(j + 1) * M;
+            RMGE_TRY(hipMemcpyAsync(hh.data(), d1, sizeof(double) * nd, hipMemcpyDeviceToHost, s));
+            RMGE_TRY(hipMemcpyAsync(hh.data() + nd, d2, sizeof(double) * nd, hipMemcpyDeviceToHost,
+                                    s));
+            RMGE_TRY(hipMemcpyAsync(hn.data(), w2, sizeof(double) * M, hipMemcpyDeviceToHost, s));
+            RMGE_TRY(hipStreamSynchronize(s));
+            ++total;
+            k = j + 1;
+            bool more = false;
+            for (size_t c = 0; c < M; ++c) {
+                sc[c] = 0.0;
+                if (!live[c]) continue;
+                double *col = H.data() + (c * R + j) * (R + 1);
+                for (int i = 0; i <= j; ++i) col[i] = hh[i * M + c] + hh[nd + i * M + c];
+                const double hnext = std::sqrt(hn[c]);
+                col[j + 1] = hnext;
+                double *cc = cs.data() + c * R, *ss = sn.data() + c * R, *gc = g.data() + c * (R + 1);
+                for (int i = 0; i < j; ++i) {
+                    const double a = col[i], b = col[i + 1];
+                    col[i] = cc[i] * a + ss[i] * b;
+                    col[i + 1] = -ss[i] * a + cc[i] * b;
+                }
+                const double a = col[j], b = col[j + 1];
+                const double rr = std::hypot(a, b);
+                cc[j] = rr > 0.0 ? a / rr : 1.0;
+                ss[j] = rr > 0.0 ? b / rr : 0.0;
+                col[j] = rr;
+                col[j + 1] = 0.0;
+                gc[j + 1] = -ss[j] * gc[j];
+                gc[j] = cc[j] * gc[j];
+                const bool grow = hnext > 1e-300 * beta[c];
+                if (std::fabs(gc[j + 1]) <= tgt[c] || !grow) {
+                    live[c] = 0;  // this column stops here; its later vectors are zero
+                } else {
+                    sc[c] = 1.0 / hnext;
+                    more = true;
+                }
+            }
+            // the columns still running continue with V_{j+1} = W / hnext
+            RMGE_TRY(hipMemcpyAsync(scl, sc.data(), sizeof(double) * M, hipMemcpyHostToDevice, s));
+            RMGE_TRY(bscale(Vn, W, m, n, mi, scl, s));
+            if (!more) break;
+        }
+        if (k == 0) break;
+        // per column: R y = g over the steps it took, then X += Z y
+        std::fill(hy.begin(), hy.end(), 0.0);
+        for (size_t c = 0; c < M; ++c) {
+            if (!active[c]) continue;
+            // the steps this column took: up to where it stopped (its zero vectors after)
+            int kc = 0;
+            for (int i = 0; i < k; ++i)
+                if (H[(c * R + i) * (R + 1) + i] != 0.0) kc = i + 1; else break;
+            const double *gc = g.data() + c * (R + 1);
+            std::vector<double> y(static_cast<size_t>(kc), 0.0);
+            for (int i = kc - 1; i >= 0; --i) {
+                double t = gc[i];
+                for (int l = i + 1; l < kc; ++l) t -= H[(c * R + l) * (R + 1) + i] * y[l];
+                const double d = H[(c * R + i) * (R + 1) + i];
+                y[i] = d != 0.0 ? t / d : 0.0;
+            }
+            for (int i = 0; i < kc; ++i) hy[i * M + c] = y[i];
+        }
+        RMGE_TRY(hipMemcpyAsync(yv, hy.data(), sizeof(double) * k * M, hipMemcpyHostToDevice, s));
+        RMGE_TRY(blincomb(X, ldx, Z, n, mi, k, yv, 1.0, s));
+        // the Hessenberg columns of this cycle are rebuilt from zero next cycle
+        std::fill(H.begin(), H.end(), 0.0);
+    }
+    rs = solve_sync_error(f);
+    if (rs != RMGE_OK) return rs;
+    double w0 = 0.0, w1 = 0.0;
+    bool all_ok = true;
+    for (size_t c = 0; c < M; ++c) {
+        w0 = (eta0[c] > w0 || eta0[c] != eta0[c]) ? eta0[c] : w0;
+        w1 = (eta[c] > w1 || eta[c] != eta[c]) ? eta[c] : w1;
+        if (!(eta[c] <= tol)) all_ok = false;
+    }
+    loc.iters = total;
+    loc.eta0 = w0;
+    loc.eta = w1;
+    loc.converged = all_ok ? 1 : 0;
+    if (st) *st = loc;
+    return all_ok ? RMGE_OK : RMGE_NOT_CONVERGED;
+}
+
 rmge_status check_factor_args(const double *A, int64_t n, int64_t lda, int32_t kind,
                               int32_t block, int32_t prec, int32_t pivot = RMGE_PIVOT_NONE) {
     if (!A || n < 1 || lda < n || n > (int64_t(1) << 20)) return RMGE_EINVAL;
@@ -1163,6 +1373,12 @@ rmge_status rmge_solve_gmres(const rmge_factors *fc, int32_t trans, const double
         return RMGE_EINVAL;
     if (f->host_st.code == 4) return RMGE_ZERO_PIVOT;
     if (f->host_st.code == 5) return RMGE_NONFINITE;
+    if (nrhs > 1 && nrhs <= 64)
+        return (f->prec == RMGE_F32)
+                   ? run_gmres_block<float>(f, trans != 0, B, nrhs, ldb, X, ldx, max_iters,
+                                            restart, tol, st)
+                   : run_gmres_block<double>(f, trans != 0, B, nrhs, ldb, X, ldx, max_iters,
+                                             restart, tol, st);
     return (f->prec == RMGE_F32)
                ? run_gmres<float>(f, trans != 0, B, nrhs, ldb, X, ldx, max_iters, restart, tol, st)
                : run_gmres<double>(f, trans != 0, B, nrhs, ldb, X, ldx, max_iters, restart, tol,

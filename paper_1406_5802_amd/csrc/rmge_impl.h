@@ -199,6 +199,16 @@ hipError_t mdot(const double *V, int64_t n, int k, const double *w, double *part
 hipError_t lincomb(double *w, int64_t ldw, const double *V, int64_t n, int k, const double *h,
                    double sign, hipStream_t s);
 // dst[i] = alpha * src[i * lds].
+// Block Krylov helpers for m <= 64 right-hand sides at once: basis block j is
+// the n x m row-major matrix V + j n m.  bdot: h[j m + c] = V_j[:, c] . W[:, c]
+// for j < k (part: >= 256 k m doubles; deterministic); blincomb:
+// W[:, c] += sign sum_j h[j m + c] V_j[:, c]; bscale: dst = src diag(scale).
+hipError_t bdot(const double *V, int64_t n, int m, int k, const double *W, int64_t ldw,
+                double *part, double *h, bool accumulate, hipStream_t s);
+hipError_t blincomb(double *W, int64_t ldw, const double *V, int64_t n, int m, int k,
+                    const double *h, double sign, hipStream_t s);
+hipError_t bscale(double *dst, const double *src, int64_t lds, int64_t n, int m,
+                  const double *scale, hipStream_t s);
 hipError_t scale_copy(double *dst, const double *src, int64_t lds, int64_t n, double alpha,
                       hipStream_t s);
 // y = beta * y + alpha * M x  (rows of M; FP64 accumulation).  M: rows x cols (ldm),

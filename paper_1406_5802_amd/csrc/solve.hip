@@ -871,6 +871,77 @@ __global__ __launch_bounds__(256) void k_lincomb(double *w, int64_t ldw, const d
     }
 }
 
+// ---- block Krylov helpers: m right-hand sides at once, basis block j stored
+// as an n x m row-major matrix at V + j n m (column c of block j is vector j of
+// right-hand side c) ----
+
+// part[(chunk k + j) m + c] = sum over the chunk's rows r of V_j[r][c] W[r][c]
+// (thread t: column t mod mp, rows t / mp, t / mp + 256 / mp, ...; mp = the
+// next power of two >= m, mp <= 64; the partial sums of a column added in a
+// fixed order, so the result does not depend on scheduling).
+__global__ __launch_bounds__(256) void k_bdot_part(const double *V, int64_t n, int m, int mp,
+                                                   int k, const double *W, int64_t ldw,
+                                                   int64_t cs, double *part) {
+    __shared__ double red[256];
+    const int64_t i0 = static_cast<int64_t>(blockIdx.x) * cs;
+    const int64_t i1 = (i0 + cs) < n ? (i0 + cs) : n;
+    const int c = threadIdx.x & (mp - 1), g = threadIdx.x / mp, ng = 256 / mp;
+    for (int j = 0; j < k; ++j) {
+        const double *Vj = V + static_cast<int64_t>(j) * n * m;
+        double acc = 0.0;
+        if (c < m)
+            for (int64_t r = i0 + g; r < i1; r += ng) acc += Vj[r * m + c] * W[r * ldw + c];
+        red[threadIdx.x] = acc;
+        __syncthreads();
+        if (threadIdx.x < m) {
+            double sum = 0.0;
+            for (int q = 0; q < ng; ++q) sum += red[q * mp + threadIdx.x];
+            part[(static_cast<int64_t>(blockIdx.x) * k + j) * m + threadIdx.x] = sum;
+        }
+        __syncthreads();
+    }
+}
+
+// h[j m + c] = sum_chunk part[(chunk k + j) m + c] (+ h when accumulate), chunk order.
+__global__ void k_bdot_sum(const double *part, int chunks, int k, int m, double *h,
+                           int accumulate) {
+    const int e = blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= k * m) return;
+    double s = 0.0;
+    for (int q = 0; q < chunks; ++q) s += part[static_cast<int64_t>(q) * k * m + e];
+    h[e] = accumulate ? h[e] + s : s;
+}
+
+// W[r][c] += sign * sum_j h[j m + c] V_j[r][c]   (h on the device, k m <= kMaxBasis * 64)
+__global__ __launch_bounds__(256) void k_blincomb(double *W, int64_t ldw, const double *V,
+                                                  int64_t n, int m, int k, const double *h,
+                                                  double sign) {
+    __shared__ double hs[kMaxBasis * 64];
+    for (int e = threadIdx.x; e < k * m; e += blockDim.x) hs[e] = h[e];
+    __syncthreads();
+    const int64_t total = n * m;
+    for (int64_t e = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x; e < total;
+         e += static_cast<int64_t>(gridDim.x) * blockDim.x) {
+        const int64_t r = e / m;
+        const int c = static_cast<int>(e - r * m);
+        double acc = 0.0;
+        for (int j = 0; j < k; ++j) acc += V[static_cast<int64_t>(j) * n * m + e] * hs[j * m + c];
+        W[r * ldw + c] += sign * acc;
+    }
+}
+
+// dst[r][c] = scale[c] * src[r * lds + c]  (dst n x m, ld m; scale on the device)
+__global__ void k_bscale(double *dst, const double *src, int64_t lds, int64_t n, int m,
+                         const double *scale) {
+    const int64_t total = n * m;
+    for (int64_t e = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x; e < total;
+         e += static_cast<int64_t>(gridDim.x) * blockDim.x) {
+        const int64_t r = e / m;
+        const int c = static_cast<int>(e - r * m);
+        dst[e] = scale[c] * src[r * lds + c];
+    }
+}
+
 // dst[i] = alpha * src[i * lds]
 __global__ void k_scale_copy(double *dst, const double *src, int64_t lds, int64_t n, double alpha) {
     for (int64_t i = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x; i < n;
@@ -1162,6 +1233,38 @@ hipError_t lincomb(double *w, int64_t ldw, const double *V, int64_t n, int k, co
     if (k < 1 || k > kMaxBasis || n < 1) return hipErrorInvalidValue;
     hipLaunchKernelGGL(k_lincomb, dim3(grid_for(n, 256)), dim3(256), 0, s, w, ldw, V, n, k, h,
                        sign);
+    return hipGetLastError();
+}
+
+hipError_t bdot(const double *V, int64_t n, int m, int k, const double *W, int64_t ldw,
+                double *part, double *h, bool accumulate, hipStream_t s) {
+    if (k < 1 || k > kMaxBasis || n < 1 || m < 1 || m > 64) return hipErrorInvalidValue;
+    int mp = 1;
+    while (mp < m) mp <<= 1;
+    const int64_t chunks = (n + 255) / 256 < kMdotChunks ? (n + 255) / 256 : kMdotChunks;
+    const int64_t cs = (n + chunks - 1) / chunks;
+    hipLaunchKernelGGL(k_bdot_part, dim3(static_cast<unsigned>(chunks)), dim3(256), 0, s, V, n, m,
+                       mp, k, W, ldw, cs, part);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_bdot_sum, dim3((k * m + 255) / 256), dim3(256), 0, s, part,
+                       static_cast<int>(chunks), k, m, h, accumulate ? 1 : 0);
+    return hipGetLastError();
+}
+
+hipError_t blincomb(double *W, int64_t ldw, const double *V, int64_t n, int m, int k,
+                    const double *h, double sign, hipStream_t s) {
+    if (k < 1 || k > kMaxBasis || n < 1 || m < 1 || m > 64) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_blincomb, dim3(grid_for(n * m, 256)), dim3(256), 0, s, W, ldw, V, n, m, k,
+                       h, sign);
+    return hipGetLastError();
+}
+
+hipError_t bscale(double *dst, const double *src, int64_t lds, int64_t n, int m,
+                  const double *scale, hipStream_t s) {
+    if (n < 1 || m < 1) return hipSuccess;
+    hipLaunchKernelGGL(k_bscale, dim3(grid_for(n * m, 256)), dim3(256), 0, s, dst, src, lds, n, m,
+                       scale);
     return hipGetLastError();
 }
 

@@ -93,3 +93,34 @@ def test_gmres_adjoint_matches_oracle(rmge, kind, prec):
     Yo = np.linalg.solve(A.T, W)
     rel = np.linalg.norm(host(Y) - Yo) / np.linalg.norm(Yo)
     assert rel <= max(1e-10, 4 * kappa * n * np.finfo(float).eps), rel
+
+
+@pytest.mark.parametrize("kind,trans,nrhs", [(1, False, 17), (2, False, 16), (3, True, 5)])
+def test_gmres_block_matches_columns_alone(rmge, kind, trans, nrhs):
+    # several right-hand sides advance their Arnoldi processes together
+    # (one preconditioner application and one product with op(A) for all of
+    # them): each column must reach what the same refinement reaches for it
+    # alone, and the backward error recomputed here must meet the tolerance
+    import torch
+
+    n, kappa = 400, 1e3
+    A = workloads.conditioned(n, kappa, seed=91)
+    B = workloads.rhs(n, nrhs, seed=92)
+    f = rmge.factor(dev(A), kind=kind, seed=7, block=128, prec=rmge.F32, pivot=rmge.PIVOT_BLOCK)
+    assert f.ok
+    X, st = f.solve_gmres(dev(B), max_iters=300, restart=32, tol=1e-14, trans=trans)
+    assert st["converged"] and st["eta"] <= 1e-14, st
+    Xh = host(X)
+    Aop = A.T if trans else A
+    anorm = np.abs(Aop).sum(axis=1).max()
+    for c in range(nrhs):
+        x1, st1 = f.solve_gmres(dev(np.ascontiguousarray(B[:, c:c + 1])), max_iters=300,
+                                restart=32, tol=1e-14, trans=trans)
+        assert st1["converged"]
+        x = Xh[:, c]
+        r = B[:, c] - Aop @ x
+        eta = np.abs(r).max() / (anorm * np.abs(x).max() + np.abs(B[:, c]).max())
+        assert eta <= 1e-14, (c, eta)
+        rel = np.linalg.norm(x - host(x1)[:, 0]) / np.linalg.norm(host(x1))
+        assert rel <= max(1e-10, 2 * kappa * (eta + st1["eta"])), (c, rel)
+    torch.cuda.synchronize()
