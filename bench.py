@@ -794,7 +794,11 @@ def main():
                                 "fastest path with no pivoting that reaches it" % (n, kappa))
                    if kappa else ("n=%d i.i.d. Gaussian A, 1 RHS, eta<=1e-14" % n),
                    "n": n, "kappa": kappa, "seed": args.seed, "block": args.block, "nrhs": 1,
-                   "headline_path": head, "multiplier": PATHS[head][3].lower()},
+                   "headline_path": head, "multiplier": PATHS[head][3].lower(),
+                   "fp32_kappa_range": "at n=16384, FP32 GENP with FP64 FGMRES reached "
+                                       "eta<=1e-14 only for kappa <= ~50 in the 8-seed sweep "
+                                       "(bench.py --sweep 0-7, kappa in [1e1, 1e8]: u32xg 2/8, "
+                                       "u32g 1/8, f32g 0/8, b16g breaks down); FP64 GENP 8/8"},
         "roofline": lines[dominant],
         "rooflines": lines,
         "executed_tflops": round((flops + (2.0 * n ** 3 - n * n if PATHS[head][3] == "GAUSSIAN"

@@ -1036,6 +1036,31 @@ hipError_t batch_gemm_f32(int count, int total_tiles, const int *tile_start, con
     return hipGetLastError();
 }
 
+// Y = beta Y + alpha M X for a few right-hand sides (X: cols x nrhs FP64, nrhs <=
+// 16) as a skinny product on the FP64 matrix cores: 64 x 16 tiles of four 16 x
+// 16 waves, so the 16 columns of X staged in LDS serve 64 rows of M at a time
+// (a matrix-vector kernel re-reads all of X for every pair of rows).
+template <typename TM>
+hipError_t gemm_skinny(int64_t rows, int64_t cols, double alpha, const TM *Mat, int64_t ldm,
+                       const double *X, int64_t ldx, double beta, double *Y, int64_t ldy,
+                       int nrhs, hipStream_t s) {
+    if (rows <= 0 || nrhs <= 0) return hipSuccess;
+    if (rows > INT32_MAX || cols > INT32_MAX || nrhs > 16) return hipErrorInvalidValue;
+    const int64_t tiles = (rows + 63) / 64;
+    hipLaunchKernelGGL((k_gemm<double, TM, 64, 16, 4, 1, 16, 4>),
+                       dim3(static_cast<unsigned>(tiles)), dim3(256), 0, s,
+                       static_cast<int>(rows), nrhs, static_cast<int>(cols), alpha, Mat, ldm, X,
+                       ldx, beta, Y, ldy, nullptr, nullptr);
+    return hipGetLastError();
+}
+
+template hipError_t gemm_skinny<double>(int64_t, int64_t, double, const double *, int64_t,
+                                        const double *, int64_t, double, double *, int64_t, int,
+                                        hipStream_t);
+template hipError_t gemm_skinny<float>(int64_t, int64_t, double, const float *, int64_t,
+                                       const double *, int64_t, double, double *, int64_t, int,
+                                       hipStream_t);
+
 hipError_t batch_gemm_f64(int count, int total_tiles, const int *tile_start, const int *nsys,
                           const int *sys, const int *flag, const int64_t *a_off,
                           const int64_t *g_off, const int64_t *m_off, const double *A,

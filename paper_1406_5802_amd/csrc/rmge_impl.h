@@ -100,6 +100,12 @@ hipError_t batch_gemm_f64(int count, int total_tiles, const int *tile_start, con
                           const int *sys, const int *flag, const int64_t *a_off,
                           const int64_t *g_off, const int64_t *m_off, const double *A,
                           const float *G, double *M, hipStream_t s);
+// Y = beta Y + alpha M X on the FP64 matrix cores for 1 <= nrhs <= 16 right-hand
+// sides (M: rows x cols of TM = double or float, X: cols x nrhs FP64, ld ldx).
+template <typename TM>
+hipError_t gemm_skinny(int64_t rows, int64_t cols, double alpha, const TM *Mat, int64_t ldm,
+                       const double *X, int64_t ldx, double beta, double *Y, int64_t ldy,
+                       int nrhs, hipStream_t s);
 hipError_t gemm_f32_a64(int shape, int64_t M, int64_t N, int64_t K, float alpha, const double *A,
                         int64_t lda, const float *B, int64_t ldb, float beta, float *C,
                         int64_t ldc, const int *abort, hipStream_t s, double *absmax = nullptr);

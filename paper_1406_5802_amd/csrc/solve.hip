@@ -9,6 +9,7 @@
 // (k_trsv); coupling tiles are read as row segments (coalesced) for plain and
 // transposed factors alike.  Their critical path is the chain of 64-row
 // blocks, not HBM bandwidth.
+#include "mfma.h"
 #include "rmge_impl.h"
 
 namespace rmge {
@@ -51,6 +52,15 @@ __device__ inline void publish_value(double *p, double v) {
                        __HIP_MEMORY_SCOPE_AGENT);
 }
 
+// The last value a thread publishes for a row of several right-hand sides:
+// a release store, so a block that sees it (and then fences with acquire)
+// also sees the row's other values; waiting blocks poll only this one.
+__device__ inline void publish_last(double *p, double v) {
+    __hip_atomic_store(reinterpret_cast<unsigned long long *>(p),
+                       __builtin_bit_cast(unsigned long long, v), __ATOMIC_RELEASE,
+                       __HIP_MEMORY_SCOPE_AGENT);
+}
+
 // modes: 0 L y = b (unit lower, forward)    1 U y = b (upper, backward)
 //        2 U^T y = b (forward)              3 L^T y = b (unit upper, backward)
 // Dinv: the compact inverses of the 32 x 32 diagonal sub-blocks of the factor
@@ -64,7 +74,12 @@ __global__ __launch_bounds__(256) void k_trsv(const T *LU, int64_t ld, int64_t n
                                               int *sync) {
     constexpr bool forward = (MODE == 0 || MODE == 2);
     constexpr bool transposed = (MODE == 2 || MODE == 3);
-    __shared__ T Ts[transposed ? SB : 1][SB + 1];  // transposed modes stage the tile here
+    // with eight or more right-hand sides the coupling T_IJ y_J runs on the
+    // FP64 matrix cores: wave w takes rows 16 w .. 16 w + 15 of the block and a
+    // 16-column slab of right-hand sides, the tile staged in LDS in natural
+    // order (the lanes' operand layout differs from the load layout)
+    constexpr bool kMma = NR >= 8;
+    __shared__ T Ts[(transposed || kMma) ? SB : 1][SB + 1];  // staged tile (Ts[row][col])
     __shared__ T Dd[2][SW][SW + 1];                 // sub-block inverses, as applied
     __shared__ T Cp[SW][SW + 1];                    // first-solved sub-block -> second
     __shared__ double ys[SB][NR];
@@ -106,6 +121,15 @@ __global__ __launch_bounds__(256) void k_trsv(const T *LU, int64_t ld, int64_t n
     double acc[NR];
 #pragma unroll
     for (int c = 0; c < NR; ++c) acc[c] = 0.0;
+    typename Mma<double>::acc macc = {0.0, 0.0, 0.0, 0.0};
+    double bm[4];  // (MMA) this lane's entries of b_I: rows Mma row(lane, q), column lane & 15
+    if constexpr (kMma) {
+#pragma unroll
+        for (int qq = 0; qq < 4; ++qq) {
+            const int row = 16 * wave + Mma<double>::row(lane, qq), c = lane & 15;
+            bm[qq] = load_if(B, (I0 + row) * ldx + c, row < bI && c < nr);
+        }
+    }
 
     // T_IJ: rows of block I, columns of block J.  Plain modes: thread (r, q)
     // loads and keeps its own 16 elements.  Transposed modes: it loads 16
@@ -132,6 +156,9 @@ __global__ __launch_bounds__(256) void k_trsv(const T *LU, int64_t ld, int64_t n
         if (transposed) {
 #pragma unroll
             for (int i = 0; i < 16; ++i) Ts[16 * q + i][r] = cur[i];
+        } else if (kMma) {
+#pragma unroll
+            for (int i = 0; i < 16; ++i) Ts[r][16 * q + i] = cur[i];
         }
         const int64_t J0 = static_cast<int64_t>(J) * SB;
         const int bJ = static_cast<int>((n - J0) < SB ? (n - J0) : SB);
@@ -139,20 +166,28 @@ __global__ __launch_bounds__(256) void k_trsv(const T *LU, int64_t ld, int64_t n
             double v[NR];
             int spins = 0;
             const bool inl = lane < bJ;
+            const double *rowp = X + (J0 + (inl ? lane : 0)) * ldx;
             while (true) {
-                // one round: every entry's load issued before any is examined
-                // (clamped addresses, no load under a branch)
-                bool ready = true;
+                // wait on each row's last value (published last, with release),
+                // one load a lane a round: the waiting blocks' polls all land
+                // on the same few lines, so they are kept few
+                bool seen = false;
+                poll_value(rowp + (nr - 1), &seen);
+                if (__all(seen || !inl)) {
+                    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+                    // then the row's values, every load issued before any is
+                    // examined (clamped addresses, no load under a branch)
+                    bool ready = true;
 #pragma unroll
-                for (int c = 0; c < NR; ++c) {
-                    const bool in = inl && c < nr;
-                    bool ok;
-                    const double pv =
-                        poll_value(X + (J0 + (inl ? lane : 0)) * ldx + (c < nr ? c : 0), &ok);
-                    v[c] = in ? pv : 0.0;
-                    ready = ready && (ok || !in);
+                    for (int c = 0; c < NR; ++c) {
+                        const bool in = inl && c < nr;
+                        bool ok;
+                        const double pv = poll_value(rowp + (c < nr ? c : 0), &ok);
+                        v[c] = in ? pv : 0.0;
+                        ready = ready && (ok || !in);
+                    }
+                    if (__all(ready)) break;
                 }
-                if (__all(ready)) break;
                 const bool give_up =
                     (++spins > kSpinLimit) ||
                     __hip_atomic_load(err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0;
@@ -167,12 +202,23 @@ __global__ __launch_bounds__(256) void k_trsv(const T *LU, int64_t ld, int64_t n
         }
         __syncthreads();
         if (s_fail) break;
+        if constexpr (kMma) {
+            const int arow = 16 * wave + (lane & 15), bc = lane & 15;
 #pragma unroll
-        for (int i = 0; i < 16; ++i) {
-            const int k = 16 * q + i;
-            const double t = static_cast<double>(transposed ? Ts[r][k] : cur[i]);
+            for (int ks = 0; ks < SB / 4; ++ks) {
+                const int k = 4 * ks + (lane >> 4);
+                const double av = static_cast<double>(Ts[arow][k]);
+                const double bv = bc < NR ? ys[k][bc < NR ? bc : 0] : 0.0;
+                macc = Mma<double>::step(av, bv, macc);
+            }
+        } else {
 #pragma unroll
-            for (int c = 0; c < NR; ++c) acc[c] += t * ys[k][c];
+            for (int i = 0; i < 16; ++i) {
+                const int k = 16 * q + i;
+                const double t = static_cast<double>(transposed ? Ts[r][k] : cur[i]);
+#pragma unroll
+                for (int c = 0; c < NR; ++c) acc[c] += t * ys[k][c];
+            }
         }
         __syncthreads();
     }
@@ -180,87 +226,67 @@ __global__ __launch_bounds__(256) void k_trsv(const T *LU, int64_t ld, int64_t n
         if (tid == 0) atomicExch(err, 1);  // blocks waiting on this one see it and stop
         return;
     }
-    // s = b_I - sum_J T_IJ y_J: reduce the four column quarters of each row
+    // s = b_I - sum_J T_IJ y_J
+    if constexpr (kMma) {
 #pragma unroll
-    for (int c = 0; c < NR; ++c) {
-        acc[c] += __shfl_xor(acc[c], 1);
-        acc[c] += __shfl_xor(acc[c], 2);
-    }
-    if (q == 0) {
+        for (int qq = 0; qq < 4; ++qq) {
+            const int row = 16 * wave + Mma<double>::row(lane, qq), c = lane & 15;
+            if (c < NR) ys[row][c < NR ? c : 0] = (row < bI && c < nr) ? bm[qq] - macc[qq] : 0.0;
+        }
+    } else {
+        // reduce the four column quarters of each row
 #pragma unroll
-        for (int c = 0; c < NR; ++c)
-            ys[r][c] = (r < bI) ? bval[c] - acc[c] : 0.0;
+        for (int c = 0; c < NR; ++c) {
+            acc[c] += __shfl_xor(acc[c], 1);
+            acc[c] += __shfl_xor(acc[c], 2);
+        }
+        if (q == 0) {
+#pragma unroll
+            for (int c = 0; c < NR; ++c)
+                ys[r][c] = (r < bI) ? bval[c] - acc[c] : 0.0;
+        }
     }
     __syncthreads();
-    // diagonal block: first-solved sub-block f, then the other, g
+    // diagonal block: first-solved sub-block f, then the other, g:
+    //   x_f = D_f s_f;  s_g -= C x_f;  x_g = D_g s_g
+    // thread t computes entries (i, c) = (e / NR, e mod NR), e = t, t + 256, of
+    // the 32 x NR results, each a whole 32-term dot product (no cross-lane
+    // reduction: three chained shuffles per right-hand side set the pace here)
     const int f = forward ? 0 : 1, g = 1 - f;
-    const int i = tid >> 3, jq = tid & 7;  // row i of a 32-block, columns 4 jq .. 4 jq + 3
-    {
-        double p[NR];
+    constexpr int NP = (SW * NR + 255) / 256;
 #pragma unroll
-        for (int c = 0; c < NR; ++c) p[c] = 0.0;
-#pragma unroll
-        for (int u = 0; u < 4; ++u) {
-            const int j = 4 * jq + u;
-            const double d = static_cast<double>(Dd[f][i][j]);
-#pragma unroll
-            for (int c = 0; c < NR; ++c) p[c] += d * ys[SW * f + j][c];
-        }
-#pragma unroll
-        for (int c = 0; c < NR; ++c) {
-            p[c] += __shfl_xor(p[c], 1);
-            p[c] += __shfl_xor(p[c], 2);
-            p[c] += __shfl_xor(p[c], 4);
-        }
-        if (jq == 0) {
-#pragma unroll
-            for (int c = 0; c < NR; ++c) xs[SW * f + i][c] = p[c];
+    for (int pp = 0; pp < NP; ++pp) {
+        const int e = tid + 256 * pp;
+        if (e < SW * NR) {
+            const int i = e / NR, c = e % NR;
+            double v = 0.0;
+#pragma unroll 8
+            for (int j = 0; j < SW; ++j) v += static_cast<double>(Dd[f][i][j]) * ys[SW * f + j][c];
+            xs[SW * f + i][c] = v;
         }
     }
     __syncthreads();
-    {
-        double p[NR];
 #pragma unroll
-        for (int c = 0; c < NR; ++c) p[c] = 0.0;
-#pragma unroll
-        for (int u = 0; u < 4; ++u) {
-            const int j = 4 * jq + u;
-            const double cv = static_cast<double>(Cp[i][j]);
-#pragma unroll
-            for (int c = 0; c < NR; ++c) p[c] += cv * xs[SW * f + j][c];
-        }
-#pragma unroll
-        for (int c = 0; c < NR; ++c) {
-            p[c] += __shfl_xor(p[c], 1);
-            p[c] += __shfl_xor(p[c], 2);
-            p[c] += __shfl_xor(p[c], 4);
-        }
-        if (jq == 0) {
-#pragma unroll
-            for (int c = 0; c < NR; ++c) ys[SW * g + i][c] -= p[c];
+    for (int pp = 0; pp < NP; ++pp) {
+        const int e = tid + 256 * pp;
+        if (e < SW * NR) {
+            const int i = e / NR, c = e % NR;
+            double v = 0.0;
+#pragma unroll 8
+            for (int j = 0; j < SW; ++j) v += static_cast<double>(Cp[i][j]) * xs[SW * f + j][c];
+            ys[SW * g + i][c] -= v;
         }
     }
     __syncthreads();
-    {
-        double p[NR];
 #pragma unroll
-        for (int c = 0; c < NR; ++c) p[c] = 0.0;
-#pragma unroll
-        for (int u = 0; u < 4; ++u) {
-            const int j = 4 * jq + u;
-            const double d = static_cast<double>(Dd[g][i][j]);
-#pragma unroll
-            for (int c = 0; c < NR; ++c) p[c] += d * ys[SW * g + j][c];
-        }
-#pragma unroll
-        for (int c = 0; c < NR; ++c) {
-            p[c] += __shfl_xor(p[c], 1);
-            p[c] += __shfl_xor(p[c], 2);
-            p[c] += __shfl_xor(p[c], 4);
-        }
-        if (jq == 0) {
-#pragma unroll
-            for (int c = 0; c < NR; ++c) xs[SW * g + i][c] = p[c];
+    for (int pp = 0; pp < NP; ++pp) {
+        const int e = tid + 256 * pp;
+        if (e < SW * NR) {
+            const int i = e / NR, c = e % NR;
+            double v = 0.0;
+#pragma unroll 8
+            for (int j = 0; j < SW; ++j) v += static_cast<double>(Dd[g][i][j]) * ys[SW * g + j][c];
+            xs[SW * g + i][c] = v;
         }
     }
     __syncthreads();
@@ -269,11 +295,13 @@ __global__ __launch_bounds__(256) void k_trsv(const T *LU, int64_t ld, int64_t n
     if (tid < bI) {
         if (nr == NR) {
 #pragma unroll
-            for (int c = 0; c < NR; ++c) publish_value(X + (I0 + tid) * ldx + c, xs[tid][c]);
+            for (int c = 0; c < NR - 1; ++c) publish_value(X + (I0 + tid) * ldx + c, xs[tid][c]);
+            publish_last(X + (I0 + tid) * ldx + NR - 1, xs[tid][NR - 1]);
         } else {
 #pragma unroll
-            for (int c = 0; c < NR; ++c)
-                if (c < nr) publish_value(X + (I0 + tid) * ldx + c, xs[tid][c]);
+            for (int c = 0; c < NR - 1; ++c)
+                if (c < nr - 1) publish_value(X + (I0 + tid) * ldx + c, xs[tid][c]);
+            publish_last(X + (I0 + tid) * ldx + nr - 1, xs[tid][nr - 1]);
         }
     }
 }
@@ -1068,6 +1096,9 @@ hipError_t gemv_n(int64_t rows, int64_t cols, double alpha, const TM *Mat, int64
     else if (nrhs <= 4)
         hipLaunchKernelGGL((k_gemv_n<TM, TX, TY, 4>), dim3(static_cast<unsigned>(grid)), dim3(256),
                            0, s, rows, cols, alpha, Mat, ldm, x, ldx, beta, y, ldy, nrhs);
+    else if constexpr (sizeof(TX) == 8 && sizeof(TY) == 8)  // FP64 vectors: matrix cores
+        return gemm_skinny<TM>(rows, cols, alpha, Mat, ldm, reinterpret_cast<const double *>(x),
+                               ldx, beta, reinterpret_cast<double *>(y), ldy, nrhs, s);
     else
         hipLaunchKernelGGL((k_gemv_n<TM, TX, TY, 16>), dim3(static_cast<unsigned>(grid)),
                            dim3(256), 0, s, rows, cols, alpha, Mat, ldm, x, ldx, beta, y, ldy,
