@@ -249,47 +249,86 @@ __global__ __launch_bounds__(256) void k_trsv(const T *LU, int64_t ld, int64_t n
     __syncthreads();
     // diagonal block: first-solved sub-block f, then the other, g:
     //   x_f = D_f s_f;  s_g -= C x_f;  x_g = D_g s_g
-    // thread t computes entries (i, c) = (e / NR, e mod NR), e = t, t + 256, of
-    // the 32 x NR results, each a whole 32-term dot product (no cross-lane
-    // reduction: three chained shuffles per right-hand side set the pace here)
+    // (a few right-hand sides: thread t computes entries (i, c) = (e / NR,
+    // e mod NR), e = t, t + 256, of the 32 x NR results, each a whole 32-term
+    // dot product, no cross-lane reduction: chained shuffles per right-hand
+    // side set the pace when the four quarter-rows were reduced that way)
     const int f = forward ? 0 : 1, g = 1 - f;
-    constexpr int NP = (SW * NR + 255) / 256;
+    if constexpr (kMma) {
+        // on the matrix cores: waves 0 and 1 take rows 0 .. 15 and 16 .. 31 of
+        // the sub-block, lane & 15 a right-hand side
+        const int c = lane & 15, arow = 16 * wave + (lane & 15);
+        auto mm = [&](const T (&Mat)[SW][SW + 1], const double (*Vin)[NR]) {
+            typename Mma<double>::acc a4 = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
-    for (int pp = 0; pp < NP; ++pp) {
-        const int e = tid + 256 * pp;
-        if (e < SW * NR) {
-            const int i = e / NR, c = e % NR;
-            double v = 0.0;
-#pragma unroll 8
-            for (int j = 0; j < SW; ++j) v += static_cast<double>(Dd[f][i][j]) * ys[SW * f + j][c];
-            xs[SW * f + i][c] = v;
-        }
-    }
-    __syncthreads();
+            for (int ks = 0; ks < SW / 4; ++ks) {
+                const int k = 4 * ks + (lane >> 4);
+                const double av = static_cast<double>(Mat[arow][k]);
+                const double bv = c < NR ? Vin[k][c < NR ? c : 0] : 0.0;
+                a4 = Mma<double>::step(av, bv, a4);
+            }
+            return a4;
+        };
+        if (wave < 2) {
+            const auto v = mm(Dd[f], ys + SW * f);
 #pragma unroll
-    for (int pp = 0; pp < NP; ++pp) {
-        const int e = tid + 256 * pp;
-        if (e < SW * NR) {
-            const int i = e / NR, c = e % NR;
-            double v = 0.0;
-#pragma unroll 8
-            for (int j = 0; j < SW; ++j) v += static_cast<double>(Cp[i][j]) * xs[SW * f + j][c];
-            ys[SW * g + i][c] -= v;
+            for (int qq = 0; qq < 4; ++qq)
+                if (c < NR) xs[SW * f + 16 * wave + Mma<double>::row(lane, qq)][c < NR ? c : 0] = v[qq];
         }
-    }
-    __syncthreads();
+        __syncthreads();
+        if (wave < 2) {
+            const auto v = mm(Cp, xs + SW * f);
 #pragma unroll
-    for (int pp = 0; pp < NP; ++pp) {
-        const int e = tid + 256 * pp;
-        if (e < SW * NR) {
-            const int i = e / NR, c = e % NR;
-            double v = 0.0;
-#pragma unroll 8
-            for (int j = 0; j < SW; ++j) v += static_cast<double>(Dd[g][i][j]) * ys[SW * g + j][c];
-            xs[SW * g + i][c] = v;
+            for (int qq = 0; qq < 4; ++qq)
+                if (c < NR) ys[SW * g + 16 * wave + Mma<double>::row(lane, qq)][c < NR ? c : 0] -= v[qq];
         }
+        __syncthreads();
+        if (wave < 2) {
+            const auto v = mm(Dd[g], ys + SW * g);
+#pragma unroll
+            for (int qq = 0; qq < 4; ++qq)
+                if (c < NR) xs[SW * g + 16 * wave + Mma<double>::row(lane, qq)][c < NR ? c : 0] = v[qq];
+        }
+        __syncthreads();
+    } else {
+        constexpr int NP = (SW * NR + 255) / 256;
+#pragma unroll
+        for (int pp = 0; pp < NP; ++pp) {
+            const int e = tid + 256 * pp;
+            if (e < SW * NR) {
+                const int i = e / NR, c = e % NR;
+                double v = 0.0;
+#pragma unroll 8
+                for (int j = 0; j < SW; ++j) v += static_cast<double>(Dd[f][i][j]) * ys[SW * f + j][c];
+                xs[SW * f + i][c] = v;
+            }
+        }
+        __syncthreads();
+#pragma unroll
+        for (int pp = 0; pp < NP; ++pp) {
+            const int e = tid + 256 * pp;
+            if (e < SW * NR) {
+                const int i = e / NR, c = e % NR;
+                double v = 0.0;
+#pragma unroll 8
+                for (int j = 0; j < SW; ++j) v += static_cast<double>(Cp[i][j]) * xs[SW * f + j][c];
+                ys[SW * g + i][c] -= v;
+            }
+        }
+        __syncthreads();
+#pragma unroll
+        for (int pp = 0; pp < NP; ++pp) {
+            const int e = tid + 256 * pp;
+            if (e < SW * NR) {
+                const int i = e / NR, c = e % NR;
+                double v = 0.0;
+#pragma unroll 8
+                for (int j = 0; j < SW; ++j) v += static_cast<double>(Dd[g][i][j]) * ys[SW * g + j][c];
+                xs[SW * g + i][c] = v;
+            }
+        }
+        __syncthreads();
     }
-    __syncthreads();
     // (all right-hand sides store with no branch between the stores: at a
     // branch's join the compiler waits for every store issued before it)
     if (tid < bI) {
