@@ -684,7 +684,7 @@ def main():
                     help="precision: seeds LO-HI (kappa = 10^(1 + 7u) each), one JSON line with "
                          "each path's result per seed")
     ap.add_argument("--restart", type=int, default=16, help="batching: GMRES restart")
-    ap.add_argument("--batch-iters", type=int, default=32,
+    ap.add_argument("--batch-iters", type=int, default=16,
                     help="batching: GMRES iterations a system gets with FP32 factors before it "
                          "is solved again from FP64 factors")
     ap.add_argument("--n", type=int, default=None, help="16384 (precision) or 8192 "
