@@ -6,9 +6,12 @@
 // argument after eq. eqgenpin every choice of block sizes produces the same
 // Schur complements.  The host driver (api.hip) walks the matrix in panels of
 // `block` columns.  This file holds
-//   * k_leaf_lu: one pivot block of at most 128 x 128 factored by one
-//     workgroup with the block held in registers, pivot by pivot, plus the
-//     inverses of the 32 x 32 diagonal sub-blocks of its two triangular factors;
+//   * k_leaf_genp: one pivot block of at most 128 x 128 factored with no
+//     pivoting by one workgroup, the block in LDS, in panels of 16 columns;
+//   * k_leaf_lu: the same with partial pivoting inside the block (the block
+//     held in registers, pivot by pivot);
+//   * k_diag_inv: the inverses of the 32 x 32 diagonal sub-blocks of the two
+//     triangular factors of a factored block;
 //   * k_trsm_left / k_trsm_right: the off-diagonal blocks of eq. eqgenp,
 //     L_B^{-1} C and D U_B^{-1} (their product is D B^{-1} C), each done in
 //     place by blocked substitution on the matrix cores: the 32 x 32 diagonal
@@ -20,9 +23,9 @@
 // strongly nonsingular) or not finite stops the elimination; its global index
 // is recorded in the device status word and every later kernel exits early.
 //
-// Bound: the leaf is latency bound (b sequential pivot steps, one barrier
-// each); the solves are MFMA work of b^2 / 2 multiply-adds per strip column,
-// with b / 32 dependent sub-block steps per strip.
+// Bound: the leaves are latency bound (b sequential pivot steps); the solves
+// are MFMA work of b^2 / 2 multiply-adds per strip column, with b / 32
+// dependent sub-block steps per strip.
 #include "mfma.h"
 #include "rmge_impl.h"
 
@@ -419,143 +422,239 @@ __device__ inline void sub_block_inverse(bool upper, int lane, int q0, int sbq,
     }
 }
 
-// GENP of one pivot block (b <= 128) held in LDS, by panels of 16 columns, in
-// one launch of four waves.  Panel at column c0 (eq. eqgenp with a pivot block of
-// 16 inside the pivot block):
-//   (1) wave 0 eliminates the panel's 16 columns over rows c0 .. b - 1, two
-//       rows a lane in registers; the pivot row of step j is lane j's first
-//       row, its entries reach the other lanes by readlane, and the multiplier
-//       is formed with the pivot's reciprocal (no barrier inside the panel);
-//   (2) U12 = L11^{-1} A12 for the 16 rows of the panel, one thread a column,
-//       by substitution (L11's entries are LDS broadcasts);
-//   (3) A22 -= L21 U12 on the matrix cores, 16 x 16 tiles dealt to the waves.
-// The chain is 16 register steps a panel plus two short shared-memory phases,
-// instead of one cross-wave hand-off per column.  A zero or non-finite pivot
-// records its global index and stops the block (the later kernels see the
-// status and exit).  The block is written back in place.
+// Reciprocal of a pivot: the hardware estimate refined by Newton steps (two
+// for FP64, one for FP32), within an ulp or two of 1 / p.  Its dependent
+// chain is about half that of the IEEE division sequence, and it sits on
+// the critical path of every pivot step below.
+__device__ inline double pivot_recip(double p) {
+    double r = __builtin_amdgcn_rcp(p);
+    double e = __builtin_fma(-p, r, 1.0);
+    r = __builtin_fma(r, e, r);
+    e = __builtin_fma(-p, r, 1.0);
+    return __builtin_fma(r, e, r);
+}
+__device__ inline float pivot_recip(float p) {
+    const float r = __builtin_amdgcn_rcpf(p);
+    return __builtin_fmaf(r, __builtin_fmaf(-p, r, 1.0f), r);
+}
+
+// One wave's share of a 16-column panel of the LDS-resident pivot block
+// (rows c0 .. b - 1, columns c0 .. c0 + 15; eq. eqgenp with pivot blocks of 1).
+// Lanes 0..15 hold the panel's 16 pivot rows, lanes 16..63 the rows
+// c0 + 16 + 48 pw + (lane - 16) below them: every panel wave eliminates the
+// pivot rows itself, so no pivot row crosses between waves.  Pivot step j
+// reads the pivot row's entries from lane j (readlane), updates the next
+// pivot column first and starts that pivot's reciprocal before the rest of
+// the step's updates.  Multipliers are a_ij * (1 / a_jj).  A zero or
+// non-finite pivot is only recorded (bits of `bad`, `zero`); the block is
+// abandoned after the panel, and wave 0 (pw == 0), which also writes the
+// pivot rows, writes the first such pivot's global index to the status word.
 template <typename T>
-__global__ __launch_bounds__(256) void k_leaf_genp(T *a, int64_t lda, int b, int64_t k0,
-                                                   DevStatus *st) {
+__device__ __attribute__((always_inline)) inline void leaf_panel(T *S, int b, int c0, int lane,
+                                                                 int pw, DevStatus *st, int64_t k0,
+                                                                 int *s_fail) {
     constexpr int LD = kLeaf + 1;
+    int w = min(16, b - c0);
+    // Opaque to the optimiser at each call: the per-step lane masks are then
+    // formed inside the panel rather than hoisted out of the panel loop and
+    // held across it in scalar registers (which spills them).
+    asm volatile("" : "+v"(lane));
+    asm volatile("" : "+s"(w));
+    const int row = lane < 16 ? c0 + lane : c0 + 16 + 48 * pw + (lane - 16);
+    const bool valid = row < b;
+    T x[16];
+#pragma unroll
+    for (int k = 0; k < 16; ++k) x[k] = (valid && k < w) ? S[row * LD + c0 + k] : T(0);
+    // steps past the panel's width see zero columns and change nothing
+    unsigned bad = 0, zero = 0;
+    auto note = [&](int j, T p) {
+        bad |= (j < w && is_bad(p)) ? (1u << j) : 0u;
+        zero |= (p == T(0)) ? (1u << j) : 0u;
+    };
+    T p0 = lane_value<T>(x[0], 0);
+    note(0, p0);
+    T inv = pivot_recip(p0);
+#pragma unroll
+    for (int j = 0; j < 16; ++j) {
+        const T m = lane > j ? x[j] * inv : T(0);
+        x[j] = lane > j ? m : x[j];
+        T inv_next = T(0);
+        if (j + 1 < 16) {
+            x[j + 1] -= m * lane_value<T>(x[j + 1], j);
+            const T pn = lane_value<T>(x[j + 1], j + 1);
+            note(j + 1, pn);
+            inv_next = pivot_recip(pn);
+        }
+#pragma unroll
+        for (int k = j + 2; k < 16; ++k) x[k] -= m * lane_value<T>(x[k], j);
+        inv = inv_next;
+        // keep each step's pivot-row reads next to their use
+        __builtin_amdgcn_sched_barrier(0);
+    }
+    if (pw == 0 && bad != 0 && lane == 0) {
+        const int fj = __builtin_ctz(bad);
+        st->info = k0 + c0 + fj;
+        st->code = ((zero >> fj) & 1u) ? 4 : 5;
+        *s_fail = 1;
+    }
+    if (valid && (lane >= 16 || pw == 0)) {
+#pragma unroll
+        for (int k = 0; k < 16; ++k)
+            if (k < w) S[row * LD + c0 + k] = x[k];
+    }
+}
+
+// U12 = L11^{-1} A12 for one column of the 16 rows c0 .. c0 + 15 by
+// substitution (L11 unit lower, its entries LDS broadcasts): y holds the
+// column, sums in ascending k.  Substitution, not a product with an explicit
+// inverse of L11: without pivoting L11 may be ill conditioned, and the
+// explicit inverse would carry that into U12.
+template <typename T>
+__device__ inline void panel_row_solve(const T *S, int c0, int col, bool in, T (&y)[16]) {
+    constexpr int LD = kLeaf + 1;
+#pragma unroll
+    for (int i = 0; i < 16; ++i) y[i] = in ? S[(c0 + i) * LD + col] : T(0);
+#pragma unroll
+    for (int i = 1; i < 16; ++i)
+#pragma unroll
+        for (int k = 0; k < i; ++k) y[i] -= S[(c0 + i) * LD + c0 + k] * y[k];
+}
+
+// GENP of one pivot block (b <= 128) held in LDS, by eight waves in panels of
+// 16 columns (eq. eqgenp with pivot blocks of 16 inside the pivot block).
+// Panel p (columns c0 .. c0 + 15), once factored:
+//   phase 1 (all waves): U12 = L11^{-1} A12 for the next panel's 16 columns
+//     (every wave solves them itself, one column a lane) and the Schur update
+//     A22 -= L21 U12 of those columns, row tiles dealt to the waves;
+//   phase 2: the panel waves (leaf_panel) factor the next panel, while the
+//     other waves solve for U12 in the remaining column blocks and update them.
+// The updates run on the matrix cores in 16 x 16 tiles (K = 16).  Two
+// barriers a panel; the chain is the panel factorisation.  The block is
+// written back in place; after a breakdown the later kernels see the status
+// and exit.
+template <typename T>
+__global__ __launch_bounds__(512) void k_leaf_genp(T *a, int64_t lda, int b, int64_t k0,
+                                                   DevStatus *st) {
+    using acc_t = typename Mma<T>::acc;
+    constexpr int NW = 8, LD = kLeaf + 1;
     __shared__ T S[kLeaf * LD];
+    __shared__ T Us[NW][16][17];  // a wave's U12 block, transposed to operand layout
     __shared__ int s_fail;
     if (st->code != 0) return;  // an earlier pivot block broke down
     __builtin_amdgcn_s_setprio(3);
     const int tid = threadIdx.x, lane = tid & 63;
     const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
     if (tid == 0) s_fail = 0;
-    // the block into LDS: thread (tid & 127) takes a column, 32 rows a round,
-    // all sixteen of a thread's loads in flight together
+    // the block into LDS: thread (tid & 127) takes a column, four rows a
+    // round, sixteen loads of a thread in flight together
     const int lc = tid & 127, lr = tid >> 7;
-    for (int i0 = 0; i0 < b; i0 += 32) {
+    for (int i0 = 0; i0 < b; i0 += 64) {
         T v[16];
 #pragma unroll
         for (int u = 0; u < 16; ++u) {
-            const int i = i0 + 2 * u + lr;
+            const int i = i0 + 4 * u + lr;
             v[u] = load_if(a, static_cast<int64_t>(i) * lda + lc, i < b && lc < b);
         }
 #pragma unroll
         for (int u = 0; u < 16; ++u) {
-            const int i = i0 + 2 * u + lr;
+            const int i = i0 + 4 * u + lr;
             if (i < b && lc < b) S[i * LD + lc] = v[u];
         }
     }
     __syncthreads();
-    for (int c0 = 0; c0 < b; c0 += 16) {
-        const int w = min(16, b - c0);
-        if (wave == 0) {
-            const int r0 = c0 + lane, r1 = c0 + 64 + lane;
-            const bool v0 = r0 < b, v1 = r1 < b;
-            T x0[16], x1[16];
+    // waves that factor the panel at column c (48 rows below the pivot rows each)
+    auto panel_waves = [&](int c) {
+        const int below = b - c - 16;
+        return below <= 0 ? 1 : (below + 47) / 48;
+    };
+    if (wave < panel_waves(0)) leaf_panel<T>(S, b, 0, lane, wave, st, k0, &s_fail);
+    __syncthreads();
+    const int nbk = (b + 15) / 16;
+    const int lr16 = lane & 15, lk = lane >> 4;
+    for (int p = 0;; ++p) {
+        const int c0 = 16 * p, c1 = c0 + 16;
+        if (s_fail || c1 >= b) break;
+        // U12 rows of column block q (lane c < 16 holds its column c) into
+        // this wave's operand slab: bk[kk] = U12[4 kk + (lane >> 4)][lane & 15]
+        auto operands = [&](const T(&y)[16], T(&bk)[4]) {
+            if (lane < 16) {
 #pragma unroll
-            for (int k = 0; k < 16; ++k) {
-                const bool kc = k < w;
-                x0[k] = (v0 && kc) ? S[r0 * LD + c0 + k] : T(0);
-                x1[k] = (v1 && kc) ? S[r1 * LD + c0 + k] : T(0);
-            }
-            int fail = 0;
-#pragma unroll
-            for (int j = 0; j < 16; ++j) {
-                if (j < w && fail == 0) {
-                    const T p = lane_value<T>(x0[j], j);
-                    if (is_bad(p)) {
-                        fail = 1;
-                        if (lane == 0) {
-                            st->info = k0 + c0 + j;
-                            st->code = (p == T(0)) ? 4 : 5;
-                            s_fail = 1;
-                        }
-                    } else {
-                        const T inv = T(1) / p;
-                        const T m0 = lane > j ? x0[j] * inv : T(0);
-                        const T m1 = x1[j] * inv;
-                        if (lane > j) x0[j] = m0;
-                        x1[j] = m1;
-#pragma unroll
-                        for (int k = j + 1; k < 16; ++k) {
-                            const T u = lane_value<T>(x0[k], j);
-                            x0[k] -= m0 * u;
-                            x1[k] -= m1 * u;
-                        }
-                    }
-                }
-                // keep each step's pivot-row reads next to their use (hoisted
-                // together they exhaust the scalar registers and spill)
-                __builtin_amdgcn_sched_barrier(0);
+                for (int i = 0; i < 16; ++i) Us[wave][i][lane] = y[i];
             }
 #pragma unroll
-            for (int k = 0; k < 16; ++k) {
-                if (k < w) {
-                    if (v0) S[r0 * LD + c0 + k] = x0[k];
-                    if (v1) S[r1 * LD + c0 + k] = x1[k];
-                }
+            for (int kk = 0; kk < 4; ++kk) bk[kk] = Us[wave][4 * kk + lk][lr16];
+        };
+        // C[rt, q] -= L21[rt] U12[q] for one or two row tiles of block q
+        auto tiles = [&](int q, int rtA, int rtB, bool two, const T(&bk)[4]) {
+            const int col = 16 * q + lr16;
+            acc_t ca, cb;
+            T aa[4], ab[4];
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int rowA = 16 * rtA + Mma<T>::row(lane, r);
+                ca[r] = (rowA < b && col < b) ? S[rowA * LD + col] : T(0);
+                const int rowB = 16 * rtB + Mma<T>::row(lane, r);
+                cb[r] = (two && rowB < b && col < b) ? S[rowB * LD + col] : T(0);
             }
-        }
-        __syncthreads();
-        if (s_fail) break;
-        if (c0 + w >= b) break;  // w == 16 below
-        const int c1 = c0 + 16, rest = b - c1;
-        // (2) U12 <- L11^{-1} A12, one thread a column
-        if (tid < rest) {
-            const int col = c1 + tid;
-            T y[16];
+            const int arA = 16 * rtA + lr16, arB = 16 * rtB + lr16;
 #pragma unroll
-            for (int i = 0; i < 16; ++i) y[i] = S[(c0 + i) * LD + col];
+            for (int kk = 0; kk < 4; ++kk) {
+                const int k = c0 + 4 * kk + lk;
+                aa[kk] = arA < b ? -S[arA * LD + k] : T(0);
+                ab[kk] = (two && arB < b) ? -S[arB * LD + k] : T(0);
+            }
 #pragma unroll
-            for (int i = 1; i < 16; ++i)
+            for (int kk = 0; kk < 4; ++kk) {
+                ca = Mma<T>::step(aa[kk], bk[kk], ca);
+                cb = Mma<T>::step(ab[kk], bk[kk], cb);
+            }
 #pragma unroll
-                for (int k = 0; k < i; ++k) y[i] -= S[(c0 + i) * LD + c0 + k] * y[k];
+            for (int r = 0; r < 4; ++r) {
+                const int rowA = 16 * rtA + Mma<T>::row(lane, r);
+                if (rowA < b && col < b) S[rowA * LD + col] = ca[r];
+                const int rowB = 16 * rtB + Mma<T>::row(lane, r);
+                if (two && rowB < b && col < b) S[rowB * LD + col] = cb[r];
+            }
+        };
+        auto store_rows = [&](int col, const T(&y)[16]) {  // U12 column back, below row c0
 #pragma unroll
             for (int i = 1; i < 16; ++i) S[(c0 + i) * LD + col] = y[i];
+        };
+        // phase 1: the next panel's column block (every wave solves for its
+        // U12, wave w updates row tile p + 1 + w; at most 7 row tiles remain)
+        const int ncol = c1 + lr16;
+        T yn[16];
+        panel_row_solve<T>(S, c0, ncol, lane < 16 && ncol < b, yn);
+        {
+            T bk[4];
+            operands(yn, bk);
+            const int rt = p + 1 + wave;
+            if (rt < nbk) tiles(p + 1, rt, rt, false, bk);
         }
         __syncthreads();
-        // (3) A22 -= L21 U12 on the matrix cores
-        const int tn = (rest + 15) / 16;
-        for (int t = wave; t < tn * tn; t += 4) {
-            const int rb = c1 + 16 * (t / tn), cb = c1 + 16 * (t % tn);
-            typename Mma<T>::acc acc;
-#pragma unroll
-            for (int q = 0; q < 4; ++q) {
-                const int row = rb + Mma<T>::row(lane, q), col = cb + (lane & 15);
-                acc[q] = (row < b && col < b) ? S[row * LD + col] : T(0);
-            }
-#pragma unroll
-            for (int kk = 0; kk < 16; kk += 4) {
-                const int k = c0 + kk + (lane >> 4);
-                const int ar = rb + (lane & 15), bc = cb + (lane & 15);
-                const T av = ar < b ? -S[ar * LD + k] : T(0);
-                const T bv = bc < b ? S[k * LD + bc] : T(0);
-                acc = Mma<T>::step(av, bv, acc);
-            }
-#pragma unroll
-            for (int q = 0; q < 4; ++q) {
-                const int row = rb + Mma<T>::row(lane, q), col = cb + (lane & 15);
-                if (row < b && col < b) S[row * LD + col] = acc[q];
+        // phase 2 (wave 0 stores the next block's U12 only now: every wave
+        // read that block's rows c0 .. c0 + 15 in phase 1)
+        const int np = panel_waves(c1);
+        if (wave < np) {
+            if (wave == 0 && lane < 16 && ncol < b) store_rows(ncol, yn);
+            leaf_panel<T>(S, b, c1, lane, wave, st, k0, &s_fail);
+        } else {
+            // column blocks q >= p + 2 dealt to the update waves (at most 6
+            // blocks, at least 5 waves): solve for the block's U12, store it,
+            // update its row tiles two at a time
+            for (int q = p + 2 + (wave - np); q < nbk; q += NW - np) {
+                const int col = 16 * q + lr16;
+                T y[16];
+                panel_row_solve<T>(S, c0, col, lane < 16 && col < b, y);
+                if (lane < 16 && col < b) store_rows(col, y);
+                T bk[4];
+                operands(y, bk);
+                for (int rt = p + 1; rt < nbk; rt += 2) tiles(q, rt, rt + 1, rt + 1 < nbk, bk);
             }
         }
         __syncthreads();
     }
-    for (int i = lr; i < b; i += 2)
+    for (int i = lr; i < b; i += 4)
         if (lc < b) a[static_cast<int64_t>(i) * lda + lc] = S[i * LD + lc];
 }
 
@@ -1077,7 +1176,7 @@ hipError_t leaf_lu(T *a, int64_t lda, int b, T *Linv, T *Uinv, int64_t k0, DevSt
         hipLaunchKernelGGL((k_leaf_lu<T, true>), dim3(1), dim3(kLeafThreads), 0, s, a, lda, b, k0,
                            st, piv);
     else
-        hipLaunchKernelGGL(k_leaf_genp<T>, dim3(1), dim3(256), 0, s, a, lda, b, k0, st);
+        hipLaunchKernelGGL(k_leaf_genp<T>, dim3(1), dim3(512), 0, s, a, lda, b, k0, st);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k_diag_inv<T>, dim3(1), dim3(512), 0, s, a, lda, b, Linv, Uinv, st);
