@@ -379,49 +379,6 @@ __global__ __launch_bounds__(kLeafThreads) void k_leaf_lu(T *a, int64_t lda, int
     }
 }
 
-// Inverse of one 32 x 32 diagonal sub-block (rows q0 .. q0 + sbq - 1) of a
-// factored block, by substitution: lane c (< 32; lanes 32 .. 63 repeat 0 .. 31
-// and store nothing) holds column c of the packed factors in col[] (row k in
-// col[k], zero past the sub-block), computes column c of the inverse of U
-// (upper) or of the unit-lower L, reading the entries of factor row i from
-// the lanes that hold their columns, and stores it.  Compact output: row
-// 32 q + i of Linv / Uinv holds row i of sub-block q's inverse.
-// (row-oriented substitution, sums in ascending k: the order whose rounding
-// the blocked solves were validated with; a column sweep was measured to
-// leave larger errors in the U inverses of strongly growing factors)
-template <typename T>
-__device__ inline void sub_block_inverse(bool upper, int lane, int q0, int sbq,
-                                         const T (&col)[kSub], T *Linv, T *Uinv) {
-    const int c = lane & (kSub - 1);
-    T x[kSub];
-    if (upper) {
-        // x_c = 1 / u_cc, x_i = -(sum_{k=i+1..c} u_ik x_k) / u_ii, x_i = 0 for i > c
-#pragma unroll
-        for (int i = kSub - 1; i >= 0; --i) {
-            T sum = T(0);
-#pragma unroll
-            for (int k = i + 1; k < kSub; ++k) sum += lane_value<T>(col[i], k) * x[k];
-            const T d = (i <= c && i < sbq) ? T(1) / lane_value<T>(col[i], i) : T(0);
-            x[i] = (i == c) ? d : ((i < c) ? -sum * d : T(0));
-        }
-    } else {
-        // x_c = 1, x_i = -sum_{k=c..i-1} l_ik x_k, x_i = 0 for i < c
-#pragma unroll
-        for (int i = 0; i < kSub; ++i) {
-            T sum = T(0);
-#pragma unroll
-            for (int k = 0; k < i; ++k) sum += lane_value<T>(col[i], k) * x[k];
-            x[i] = (i == c) ? T(1) : ((i > c) ? -sum : T(0));
-        }
-    }
-    if (lane < kSub && c < sbq) {
-        T *out = upper ? Uinv : Linv;
-#pragma unroll
-        for (int k = 0; k < kSub; ++k)
-            if (k < sbq) out[static_cast<int64_t>(q0 + k) * kSub + c] = x[k];
-    }
-}
-
 // Reciprocal of a pivot: the hardware estimate refined by Newton steps (two
 // for FP64, one for FP32), within an ulp or two of 1 / p.  Its dependent
 // chain is about half that of the IEEE division sequence, and it sits on
@@ -662,11 +619,21 @@ __global__ __launch_bounds__(512) void k_leaf_genp(T *a, int64_t lda, int b, int
 // (the off-diagonal coupling is applied by blocked substitution, so only these
 // small inverses are formed).  Workgroup g covers rows 128 g .. 128 g + 127 of
 // the b x b block at `a`; wave w < nsub inverts U's sub-block w, wave nsub + w
-// the unit-lower L's.
+// the unit-lower L's.  A wave stages its sub-block in LDS (the identity past
+// the block's edge, so the sweeps need no bounds), and lane c (< 32; lanes
+// 32 .. 63 repeat 0 .. 31 and store nothing) forms column c of the inverse by
+// substitution, the factor's rows read as LDS broadcasts:
+//   U: x_i = (delta_ic - sum_{k > i} u_ik x_k) / u_ii, from the bottom row;
+//   L: x_i = delta_ic - sum_{k < i} l_ik x_k.
+// (Row-oriented, sums in ascending k: the order whose rounding the blocked
+// solves were validated with; a column sweep was measured to leave larger
+// errors in the U inverses of strongly growing factors.)  Compact output:
+// row 32 q + i of Linv / Uinv holds row i of sub-block q's inverse.
 template <typename T>
 __global__ __launch_bounds__(512, 1) void k_diag_inv(const T *a, int64_t lda, int b, T *Linv, T *Uinv,
                                                   const DevStatus *st) {
     if (st->code != 0) return;
+    __shared__ T Bs[8][kSub][kSub + 1];
     __builtin_amdgcn_s_setprio(3);
     const int64_t g0 = static_cast<int64_t>(blockIdx.x) * 4 * kSub;
     a += g0 * lda + g0;
@@ -678,14 +645,45 @@ __global__ __launch_bounds__(512, 1) void k_diag_inv(const T *a, int64_t lda, in
     const int nsub = (b + kSub - 1) / kSub;
     if (wave >= 2 * nsub) return;
     const bool upper = wave < nsub;
-    const int qd = upper ? wave : wave - nsub, q0 = qd * kSub;
+    const int q0 = (upper ? wave : wave - nsub) * kSub;
     const int sbq = (b - q0) < kSub ? (b - q0) : kSub;
-    const int c = lane & (kSub - 1);
-    T col[kSub];
+    const int c = lane & (kSub - 1), h = lane >> 5;
+    T(*B)[kSub + 1] = Bs[wave];
 #pragma unroll
-    for (int k = 0; k < kSub; ++k)
-        col[k] = load_if(a, static_cast<int64_t>(q0 + k) * lda + q0 + c, k < sbq && c < sbq);
-    sub_block_inverse<T>(upper, lane, q0, sbq, col, Linv, Uinv);
+    for (int k = 0; k < kSub; k += 2) {
+        const int r = k + h;
+        const T v = load_if(a, static_cast<int64_t>(q0 + r) * lda + q0 + c, r < sbq && c < sbq);
+        B[r][c] = (r < sbq && c < sbq) ? v : (r == c ? T(1) : T(0));
+    }
+    // (the wave reads only what it wrote: no barrier)
+    T x[kSub];
+    if (upper) {
+#pragma unroll
+        for (int i = kSub - 1; i >= 0; --i) {
+            // each row's reads next to their use (hoisted together, the 496
+            // entries would not fit in registers)
+            asm volatile("" ::: "memory");
+            T sum = T(0);
+#pragma unroll
+            for (int k = i + 1; k < kSub; ++k) sum += B[i][k] * x[k];
+            x[i] = ((c == i ? T(1) : T(0)) - sum) * (T(1) / B[i][i]);
+        }
+    } else {
+#pragma unroll
+        for (int i = 0; i < kSub; ++i) {
+            asm volatile("" ::: "memory");
+            T sum = T(0);
+#pragma unroll
+            for (int k = 0; k < i; ++k) sum += B[i][k] * x[k];
+            x[i] = (c == i ? T(1) : T(0)) - sum;
+        }
+    }
+    if (lane < kSub && c < sbq) {
+        T *out = upper ? Uinv : Linv;
+#pragma unroll
+        for (int k = 0; k < kSub; ++k)
+            if (k < sbq) out[static_cast<int64_t>(q0 + k) * kSub + c] = x[k];
+    }
 }
 
 // Blocked substitution on the matrix cores.  The pivot block's factors sit
