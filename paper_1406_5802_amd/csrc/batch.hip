@@ -740,7 +740,7 @@ __global__ void k_batch_mark_fallback(int count, BatchOut out) {
     }
 }
 
-__global__ __launch_bounds__(kBatchThreads) void k_batch_factor64(int count,
+__global__ __launch_bounds__(kBatchThreads, 2) void k_batch_factor64(int count,
                                                                   const BatchDesc *__restrict__ d,
                                                                   double *m64_pool, BatchOut out) {
     __shared__ double sd[32 * 33], sinv[32];
