@@ -18,25 +18,60 @@ from . import _rmge
 from ._rmge import RMGEError
 
 
+# Factorization handles of finished solves, kept for reuse by the next solve of
+# the same shape and options: a handle owns its n x n factors and workspaces,
+# and allocating and freeing them costs about as much as the factorization
+# itself at n = 8192 (rmge_refactor reuses them).  A handle is in this list only
+# while no solve holds it.
+_free: dict = {}
+_MAX_FREE = 2
+
+
+def _key(A, kind, block, prec, pivot):
+    return (A.shape[0], A.device.index, kind, block, prec, pivot)
+
+
+def _acquire(A, kind, seed, block, prec, pivot):
+    from . import Factors
+
+    idle = _free.get(_key(A, kind, block, prec, pivot))
+    if idle:
+        f = idle.pop()
+        f.refactor(A, seed=seed)
+        return f
+    return Factors(A, kind=kind, seed=seed, block=block, prec=prec, pivot=pivot)
+
+
+def _release(f, key):
+    f.A = None  # the handle no longer keeps the caller's matrix alive
+    idle = _free.setdefault(key, [])
+    if len(idle) < _MAX_FREE:
+        idle.append(f)
+    else:
+        f.close()
+
+
 class RmgeSolve(torch.autograd.Function):
     @staticmethod
     def forward(ctx, A, B, kind, seed, block, prec, pivot, tol, max_iters):
-        from . import F32, F32_BF16X2, Factors
+        from . import F32, F32_BF16X2
 
         A = A.detach().contiguous()
         B = B.detach().contiguous()
-        f = Factors(A, kind=kind, seed=seed, block=block, prec=prec, pivot=pivot)
+        key = _key(A, kind, block, prec, pivot)
+        f = _acquire(A, kind, seed, block, prec, pivot)
         if not f.ok:
-            f.close()
-            raise RMGEError(f.status, "RmgeSolve.forward (factor)")
+            status = f.status
+            _release(f, key)
+            raise RMGEError(status, "RmgeSolve.forward (factor)")
         if prec in (F32, F32_BF16X2):
             X, st = f.solve_gmres(B, max_iters=max_iters, restart=32, tol=tol)
         else:
             X, st = f.solve(B, max_refine=16, tol=tol)
         if not st["converged"]:
-            f.close()
+            _release(f, key)
             raise RMGEError(_rmge.RMGE_NOT_CONVERGED, "RmgeSolve.forward (solve)")
-        ctx.f = f
+        ctx.f, ctx.key = f, key
         ctx.prec, ctx.tol, ctx.max_iters = prec, tol, max_iters
         ctx.save_for_backward(X)
         return X
@@ -54,6 +89,8 @@ class RmgeSolve(torch.autograd.Function):
         else:
             GB, st = f.solve_adjoint_refined(gX, max_refine=16, tol=ctx.tol)
         if not st["converged"]:
+            _release(f, ctx.key)
+            ctx.f = None
             raise RMGEError(_rmge.RMGE_NOT_CONVERGED, "RmgeSolve.backward (adjoint)")
         grad_A = None
         if ctx.needs_input_grad[0]:
@@ -65,7 +102,7 @@ class RmgeSolve(torch.autograd.Function):
             if rc:
                 raise RMGEError(rc, "rmge_grad_A")
         grad_B = GB if ctx.needs_input_grad[1] else None
-        f.close()
+        _release(f, ctx.key)
         ctx.f = None
         return grad_A, grad_B, None, None, None, None, None, None, None
 
