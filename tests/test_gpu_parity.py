@@ -51,6 +51,15 @@ def host(t):
     return t.detach().cpu().numpy()
 
 
+def _eta(M, X, B):
+    """Largest normwise backward error max_j |B_j - M X_j| / (|M| |X_j| + |B_j|), 2-norms."""
+    X = X.reshape(X.shape[0], -1)
+    B = B.reshape(B.shape[0], -1)
+    nm = np.linalg.norm(M, 2)
+    r = np.linalg.norm(B - M @ X, axis=0)
+    return float(np.max(r / (nm * np.linalg.norm(X, axis=0) + np.linalg.norm(B, axis=0))))
+
+
 def _pair_radius(z):
     z = np.asarray(z)
     pad = (-z.size) % 4
@@ -234,7 +243,12 @@ def test_adjoint_matches_oracle(rmge, kind):
     fo = oracle.factor(A, kind, 4)
     Yo = oracle.solve_adjoint(fo, W)
     rel = np.linalg.norm(Y - Yo) / np.linalg.norm(Yo)
-    assert rel <= 1e-9, rel
+    # neither side refines: each solution's normwise backward error eta for
+    # A^T y = w bounds its forward error by 2 kappa eta (first order), so the
+    # two differ by at most 2 kappa (eta_g + eta_o), the rule of the header
+    kappa = np.linalg.cond(A)
+    bound = 2 * kappa * (_eta(A.T, Y, W) + _eta(A.T, Yo, W))
+    assert rel <= max(1e-10, bound), (rel, bound)
 
 
 @pytest.mark.parametrize("kind", [1, 2, 4])
