@@ -376,7 +376,7 @@ __device__ inline double block_reduce(double v, bool is_max, double *red) {
 // With rowsum != null, also the largest row sum of |M| into *rowsum (thread
 // 0's copy is the result).
 template <typename TM>
-__device__ void block_matvec(const TM *__restrict__ M, int n, const double *x, double *y,
+__device__ __attribute__((always_inline)) inline void block_matvec(const TM *__restrict__ M, int n, const double *x, double *y,
                              double *rowsum, double *red) {
     constexpr int RW = 8;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;

@@ -382,7 +382,7 @@ __device__ inline void fft_row_regs(cplx *a, int64_t n, const cplx *__restrict__
 }
 
 template <int LOGL, typename TI, typename TO>
-__device__ inline void fft_row(const TI *x, int64_t esi, int64_t n, const cplx *__restrict__ tw,
+__device__ __attribute__((always_inline)) inline void fft_row(const TI *x, int64_t esi, int64_t n, const cplx *__restrict__ tw,
                                const cplx *__restrict__ hhat, int conj, double beta, TO *y,
                                int64_t eso, cplx *spec, double *absmax, cplx *sm) {
     cplx a[16];
@@ -465,7 +465,7 @@ __device__ inline void batch_row(const TI *x, int64_t n, const cplx *tw, const c
 }
 
 template <typename TI, typename TO>
-__device__ inline void batch_row_any(int lg, const TI *x, int64_t n, const cplx *tw,
+__device__ __attribute__((always_inline)) inline void batch_row_any(int lg, const TI *x, int64_t n, const cplx *tw,
                                      const cplx *hh, int conj, TO *y, cplx *spec, cplx *sm) {
     switch (lg) {
     case 0: batch_row<0, TI, TO>(x, n, tw, hh, conj, y, spec, sm); break;

@@ -691,13 +691,15 @@ __global__ __launch_bounds__(512, 1) void k_diag_inv(const T *a, int64_t lda, in
 // 32 x 32 diagonal sub-blocks (compact: row 32 q + i, 32 columns).  One workgroup owns a 32-wide
 // strip of the panel and keeps it in MFMA accumulators, 16 x 16 tiles dealt
 // round-robin to its four waves.  Per diagonal sub-block i the two tiles of
-// rows i are published to LDS, multiplied by the sub-block inverse, published
-// again as X_i, and every wave subtracts (factor block) x X_i from its tiles
-// further along.
+// rows i are published to LDS, multiplied by the sub-block inverse (one
+// 16 x 16 tile of X_i a wave, back into LDS), and every wave subtracts
+// (factor block) x X_i from its tiles further along; X_i is final then and is
+// written out from LDS.  Three barriers a step.
 //
 // The substitution is a chain of b / 32 short steps, so operands are fetched
 // one step ahead (the next sub-block inverse and the next step's factor
-// operands), which hides their memory latency behind the current step.
+// operands), which hides their memory latency behind the current step, and
+// each phase reads all its LDS operands before its first product.
 //
 // LEFT:  C (b x count) <- L^{-1} P C, strips of 32 columns (row tiles dealt).
 // With `rowsrc` (pivoted blocks) row t of P C is row rowsrc[t] - rowbase of C:
@@ -717,30 +719,31 @@ __device__ inline void fetch_dinv(const T *Dinv, int b, int q, int tid, T (&d)[4
         d[m] = Dinv[dinv_in(b, q, e) ? q * kSub * static_cast<int64_t>(kSub) + e : 0];
     }
 }
-template <typename T>
-__device__ inline void store_dinv(T (&Ds)[kSub][kSub + 1], int b, int q, int tid, const T (&d)[4]) {
-#pragma unroll
-    for (int m = 0; m < 4; ++m) {
-        const int e = tid + 256 * m;
-        Ds[e / kSub][e % kSub] = dinv_in(b, q, e) ? d[m] : T(0);
-    }
-}
 
-// Strip `blk` (columns 32 blk ..) of the left solve, one workgroup of 256 threads.
+// Strip `blk` (columns 32 blk ..) of the left solve, one workgroup of 256
+// threads.  Step i's factor panel L[32 i + 32 ..][32 i .. 32 i + 31] is read
+// row by row (coalesced) one step ahead into registers and staged in LDS; the
+// four waves each apply the sub-block inverse to one 16 x 16 tile of rows i,
+// and X_i goes to memory from LDS at the start of the next step.
 template <typename T>
-__device__ inline void trsm_left_strip(const T *lu, int64_t ld, int b, T *C, int64_t ldc,
+__device__ __attribute__((always_inline)) inline void trsm_left_strip(const T *lu, int64_t ld, int b, T *C, int64_t ldc,
                                        int64_t count, const T *Dinv, const int *rowsrc,
                                        int64_t rowbase, int64_t blk) {
     using acc_t = typename Mma<T>::acc;
     constexpr int BN = 32;
-    __shared__ T Xs[kSub][BN + 1];
-    __shared__ T Ds[kSub][kSub + 1];
+    constexpr int PR = kMaxBlock - kSub;  // rows of a step's factor panel, at most
+    constexpr int PL = PR * kSub / 256;   // its elements a thread stages
+    // row strides: a 16 x 4 operand read (rows by lane & 15, columns by
+    // lane >> 4) is bank-conflict free at 34, a 4 x 16 one at 48
+    __shared__ T Xa[kSub][48];            // rows of sub-block i of the strip (before)
+    __shared__ T Xb[kSub][48];            // X_i (after)
+    __shared__ T Ds[kSub][34];
+    __shared__ T Ls[PR][34];              // L[i0 + 32 + p][i0 + c]
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int lo = lane & 15, hi = lane >> 4;
     const int64_t c0 = blk * BN;
     const int wcols = static_cast<int>((count - c0) < BN ? (count - c0) : BN);
     const int nrt = (b + 15) / 16;
-    // source rows of this thread's accumulator rows (all index loads first)
     int64_t src[4][4];
     if (rowsrc) {
 #pragma unroll
@@ -768,30 +771,44 @@ __device__ inline void trsm_left_strip(const T *lu, int64_t ld, int b, T *C, int
                 const bool in = t < nrt && row < b && col < wcols;
                 acc[u][j][r] = load_if(C, src[u][r] * ldc + c0 + col, in);
             }
-    // step i's factor operands L[row][32 i + k] for the row tiles below
-    // sub-block i, loaded raw (clamped address) and masked and negated where
-    // they are used, so a load still in flight is never copied or selected
-    auto fetch_f = [&](int i, T (&f)[4][kSub / 4]) {
-        const int i0 = i * kSub, sb = (b - i0) < kSub ? (b - i0) : kSub;
+    // step i's factor panel, row-major and coalesced: element tid + 256 m is
+    // row (tid >> 5) + 8 m, column tid & 31 (raw loads, masked when staged)
+    const int pc = tid & 31, pr = tid >> 5;
+    T pf[PL], d[4];
+    auto fetch_panel = [&](int i) {
+        const int i0 = i * kSub, rows = b - i0 - kSub;
+        const T *base = lu + (i0 + kSub + pr) * ld + i0 + pc;
 #pragma unroll
-        for (int u = 0; u < 4; ++u) {
-            const int t = wave + 4 * u, row = 16 * t + lo;
-            const bool below = t >= 2 * i + 2 && t < nrt && row < b;
-#pragma unroll
-            for (int kq = 0; kq < kSub / 4; ++kq) {
-                const int k = 4 * kq + hi;
-                f[u][kq] = lu[(below && k < sb) ? row * ld + i0 + k : 0];
-            }
+        for (int m = 0; m < PL; ++m) {
+            const int p = pr + 8 * m;
+            pf[m] = *(p < rows ? base + 8 * m * ld : lu);
         }
     };
-    // sub-block step i with its operands in (f, d); the next step's are
-    // fetched into (fn, dn).  Steps alternate between two register sets.
-    auto step = [&](int i, const T (&f)[4][kSub / 4], T (&fn)[4][kSub / 4], const T (&d)[4],
-                    T (&dn)[4]) {
-        const int i0 = i * kSub, sb = (b - i0) < kSub ? (b - i0) : kSub;
-        fetch_f(i + 1, fn);
-        fetch_dinv(Dinv, b, i + 1, tid, dn);
-        store_dinv(Ds, b, i, tid, d);
+    auto store_x = [&](int i) {  // X_i (in Xb) to rows 32 i .. of the strip
+        const int i0 = i * kSub;
+#pragma unroll
+        for (int m = 0; m < 4; ++m) {
+            const int e = tid + 256 * m, row = e >> 5, col = e & 31;
+            if (i0 + row < b && col < wcols) C[(i0 + row) * ldc + c0 + col] = Xb[row][col];
+        }
+    };
+    fetch_dinv(Dinv, b, 0, tid, d);
+    fetch_panel(0);
+    const int nsub = (b + kSub - 1) / kSub;
+    for (int i = 0; i < nsub; ++i) {
+        const int i0 = i * kSub, rows = b - i0 - kSub;
+        // publish: the sub-block inverse, the factor panel, rows i of the strip,
+        // and the previous step's result to memory
+        #pragma unroll
+        for (int m = 0; m < 4; ++m) {
+            const int e = tid + 256 * m;
+            Ds[e / kSub][e % kSub] = dinv_in(b, i, e) ? d[m] : T(0);
+        }
+#pragma unroll
+        for (int m = 0; m < PL; ++m) {
+            const int p = pr + 8 * m;
+            Ls[p][pc] = p < rows ? pf[m] : T(0);
+        }
 #pragma unroll
         for (int u = 0; u < 4; ++u) {
             const int t = wave + 4 * u;
@@ -800,86 +817,75 @@ __device__ inline void trsm_left_strip(const T *lu, int64_t ld, int b, T *C, int
                 for (int j = 0; j < 2; ++j)
 #pragma unroll
                     for (int r = 0; r < 4; ++r)
-                        Xs[16 * (t - 2 * i) + Mma<T>::row(lane, r)][16 * j + lo] = acc[u][j][r];
+                        Xa[16 * (t - 2 * i) + Mma<T>::row(lane, r)][16 * j + lo] = acc[u][j][r];
         }
+        if (i > 0) store_x(i - 1);
         __syncthreads();
-        acc_t xn[2];
-        int mine = -1;
+        if (i + 1 < nsub) {
+            fetch_dinv(Dinv, b, i + 1, tid, d);
+            fetch_panel(i + 1);
+        }
+        {  // X_i = D_i^{-1} (rows i): wave w takes row tile w & 1, column tile w >> 1
+            const int q = wave & 1, j = wave >> 1;
+            T da[kSub / 4], xa[kSub / 4];
 #pragma unroll
-        for (int u = 0; u < 4; ++u) {
-            const int t = wave + 4 * u;
-            if (t == 2 * i || t == 2 * i + 1) {
-                mine = u;
-#pragma unroll
-                for (int j = 0; j < 2; ++j) {
-                    acc_t x = acc_t{0, 0, 0, 0};
-#pragma unroll
-                    for (int kk = 0; kk < kSub; kk += 4)
-                        x = Mma<T>::step(Ds[16 * (t - 2 * i) + lo][kk + hi], Xs[kk + hi][16 * j + lo],
-                                         x);
-                    xn[j] = x;
-                }
+            for (int kq = 0; kq < kSub / 4; ++kq) {
+                da[kq] = Ds[16 * q + lo][4 * kq + hi];
+                xa[kq] = Xa[4 * kq + hi][16 * j + lo];
             }
+            acc_t x = acc_t{0, 0, 0, 0};
+#pragma unroll
+            for (int kq = 0; kq < kSub / 4; ++kq) x = Mma<T>::step(da[kq], xa[kq], x);
+#pragma unroll
+            for (int r = 0; r < 4; ++r) Xb[16 * q + Mma<T>::row(lane, r)][16 * j + lo] = x[r];
         }
         __syncthreads();
-        if (mine >= 0) {
-            const int t = wave + 4 * mine;
+        {
+            // every operand of the step is read before the first product: the
+            // rows of inactive tiles are clamped into the panel and not used
+            T xb[kSub / 4][2], fv[4][kSub / 4];
 #pragma unroll
-            for (int j = 0; j < 2; ++j) {
+            for (int kq = 0; kq < kSub / 4; ++kq)
 #pragma unroll
-                for (int u = 0; u < 4; ++u)
-                    if (u == mine) acc[u][j] = xn[j];
+                for (int j = 0; j < 2; ++j) xb[kq][j] = Xb[4 * kq + hi][16 * j + lo];
 #pragma unroll
-                for (int r = 0; r < 4; ++r)
-                    Xs[16 * (t - 2 * i) + Mma<T>::row(lane, r)][16 * j + lo] = xn[j][r];
+            for (int u = 0; u < 4; ++u) {
+                const int t = wave + 4 * u, pt = 16 * (t - 2 * i - 2);
+                const int p = (pt < 0 ? 0 : (pt > PR - 16 ? PR - 16 : pt)) + lo;
+#pragma unroll
+                for (int kq = 0; kq < kSub / 4; ++kq) fv[u][kq] = Ls[p][4 * kq + hi];
             }
-        }
-        __syncthreads();
 #pragma unroll
-        for (int u = 0; u < 4; ++u) {
-            const int t = wave + 4 * u;
-            if (t >= 2 * i + 2 && t < nrt) {
-                const bool rin = 16 * t + lo < b;
-#pragma unroll
-                for (int kq = 0; kq < kSub / 4; ++kq) {
-                    const int k = 4 * kq + hi;
-                    const T fv = (rin && k < sb) ? -f[u][kq] : T(0);
-#pragma unroll
-                    for (int j = 0; j < 2; ++j)
-                        acc[u][j] = Mma<T>::step(fv, Xs[k][16 * j + lo], acc[u][j]);
-                }
-            }
-        }
-        __syncthreads();
-    };
-    T fa[4][kSub / 4], fb[4][kSub / 4], da[4], db[4];
-    fetch_dinv(Dinv, b, 0, tid, da);
-    fetch_f(0, fa);
-    for (int i = 0; kSub * i < b; i += 2) {
-        step(i, fa, fb, da, db);
-        if (kSub * (i + 1) < b) step(i + 1, fb, fa, db, da);
-    }
-#pragma unroll
-    for (int u = 0; u < 4; ++u)
-#pragma unroll
-        for (int j = 0; j < 2; ++j)
-#pragma unroll
-            for (int r = 0; r < 4; ++r) {
+            for (int u = 0; u < 4; ++u) {
                 const int t = wave + 4 * u;
-                const int row = 16 * t + Mma<T>::row(lane, r), col = 16 * j + lo;
-                if (t < nrt && row < b && col < wcols) C[row * ldc + c0 + col] = acc[u][j][r];
+                if (t >= 2 * i + 2 && t < nrt) {
+#pragma unroll
+                    for (int kq = 0; kq < kSub / 4; ++kq)
+#pragma unroll
+                        for (int j = 0; j < 2; ++j)
+                            acc[u][j] = Mma<T>::step(-fv[u][kq], xb[kq][j], acc[u][j]);
+                }
             }
+        }
+        __syncthreads();
+    }
+    store_x(nsub - 1);
 }
 
 // RIGHT: C (count x b) <- C U^{-1}, strips of 32 rows (column tiles dealt).
-// Strip `blk` (rows 32 blk ..), one workgroup of 256 threads.
+// Strip `blk` (rows 32 blk ..), one workgroup of 256 threads; the factor rows
+// of step j are read one step ahead straight into the operand registers (four
+// rows of 16 consecutive columns a load), the rest as on the left.
 template <typename T>
-__device__ inline void trsm_right_strip(const T *lu, int64_t ld, int b, T *C, int64_t ldc,
+__device__ __attribute__((always_inline)) inline void trsm_right_strip(const T *lu, int64_t ld, int b, T *C, int64_t ldc,
                                         int64_t count, const T *Dinv, int64_t blk) {
     using acc_t = typename Mma<T>::acc;
     constexpr int BM = 32;
-    __shared__ T Xs[BM][kSub + 1];
-    __shared__ T Ds[kSub][kSub + 1];
+    // row strides: a 16 x 4 operand read (rows by lane & 15, columns by
+    // lane >> 4) is bank-conflict free at 34, a 4 x 16 one at 48
+    __shared__ T Xa[BM][34];   // columns of sub-block j of the strip (before)
+    __shared__ T Xb[BM][34];   // X_j (after)
+    __shared__ T Ds[kSub][48];
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int lo = lane & 15, hi = lane >> 4;
     const int64_t r0 = blk * BM;
@@ -896,9 +902,6 @@ __device__ inline void trsm_right_strip(const T *lu, int64_t ld, int b, T *C, in
                 const int row = 16 * q + Mma<T>::row(lane, r), col = 16 * c + lo;
                 acc[u][q][r] = load_if(C, (r0 + row) * ldc + col, c < nct && row < wrows && col < b);
             }
-    // step j's factor operands U[32 j + k][col] for the column tiles right
-    // of sub-block j, loaded raw (clamped address) and masked and negated
-    // where they are used
     auto fetch_f = [&](int j, T (&f)[4][kSub / 4]) {
         const int j0 = j * kSub, sb = (b - j0) < kSub ? (b - j0) : kSub;
 #pragma unroll
@@ -912,12 +915,22 @@ __device__ inline void trsm_right_strip(const T *lu, int64_t ld, int b, T *C, in
             }
         }
     };
+    auto store_x = [&](int j) {  // X_j (in Xb) to columns 32 j .. of the strip
+        const int j0 = j * kSub;
+#pragma unroll
+        for (int m = 0; m < 4; ++m) {
+            const int e = tid + 256 * m, row = e >> 5, col = e & 31;
+            if (row < wrows && j0 + col < b) C[(r0 + row) * ldc + j0 + col] = Xb[row][col];
+        }
+    };
     auto step = [&](int j, const T (&f)[4][kSub / 4], T (&fn)[4][kSub / 4], const T (&d)[4],
-                    T (&dn)[4]) {
+                    T (&dn)[4], bool last) {
         const int j0 = j * kSub, sb = (b - j0) < kSub ? (b - j0) : kSub;
-        fetch_f(j + 1, fn);
-        fetch_dinv(Dinv, b, j + 1, tid, dn);
-        store_dinv(Ds, b, j, tid, d);
+#pragma unroll
+        for (int m = 0; m < 4; ++m) {
+            const int e = tid + 256 * m;
+            Ds[e / kSub][e % kSub] = dinv_in(b, j, e) ? d[m] : T(0);
+        }
 #pragma unroll
         for (int u = 0; u < 4; ++u) {
             const int c = wave + 4 * u;
@@ -926,53 +939,48 @@ __device__ inline void trsm_right_strip(const T *lu, int64_t ld, int b, T *C, in
                 for (int q = 0; q < 2; ++q)
 #pragma unroll
                     for (int r = 0; r < 4; ++r)
-                        Xs[16 * q + Mma<T>::row(lane, r)][16 * (c - 2 * j) + lo] = acc[u][q][r];
+                        Xa[16 * q + Mma<T>::row(lane, r)][16 * (c - 2 * j) + lo] = acc[u][q][r];
         }
+        if (j > 0) store_x(j - 1);
         __syncthreads();
-        acc_t xn[2];
-        int mine = -1;
+        if (!last) {
+            fetch_f(j + 1, fn);
+            fetch_dinv(Dinv, b, j + 1, tid, dn);
+        }
+        {  // X_j = (columns j) U_jj^{-1}: wave w takes row tile w & 1, column tile w >> 1
+            const int q = wave & 1, cc = wave >> 1;
+            T xa[kSub / 4], da[kSub / 4];
 #pragma unroll
-        for (int u = 0; u < 4; ++u) {
-            const int c = wave + 4 * u;
-            if (c == 2 * j || c == 2 * j + 1) {
-                mine = u;
-#pragma unroll
-                for (int q = 0; q < 2; ++q) {
-                    acc_t x = acc_t{0, 0, 0, 0};
-#pragma unroll
-                    for (int kk = 0; kk < kSub; kk += 4)
-                        x = Mma<T>::step(Xs[16 * q + lo][kk + hi], Ds[kk + hi][16 * (c - 2 * j) + lo],
-                                         x);
-                    xn[q] = x;
-                }
+            for (int kq = 0; kq < kSub / 4; ++kq) {
+                xa[kq] = Xa[16 * q + lo][4 * kq + hi];
+                da[kq] = Ds[4 * kq + hi][16 * cc + lo];
             }
+            acc_t x = acc_t{0, 0, 0, 0};
+#pragma unroll
+            for (int kq = 0; kq < kSub / 4; ++kq) x = Mma<T>::step(xa[kq], da[kq], x);
+#pragma unroll
+            for (int r = 0; r < 4; ++r) Xb[16 * q + Mma<T>::row(lane, r)][16 * cc + lo] = x[r];
         }
         __syncthreads();
-        if (mine >= 0) {
-            const int c = wave + 4 * mine;
+        {
+            T xb[2][kSub / 4];
 #pragma unroll
-            for (int q = 0; q < 2; ++q) {
+            for (int q = 0; q < 2; ++q)
 #pragma unroll
-                for (int u = 0; u < 4; ++u)
-                    if (u == mine) acc[u][q] = xn[q];
+                for (int kq = 0; kq < kSub / 4; ++kq) xb[q][kq] = Xb[16 * q + lo][4 * kq + hi];
 #pragma unroll
-                for (int r = 0; r < 4; ++r)
-                    Xs[16 * q + Mma<T>::row(lane, r)][16 * (c - 2 * j) + lo] = xn[q][r];
-            }
-        }
-        __syncthreads();
+            for (int u = 0; u < 4; ++u) {
+                const int c = wave + 4 * u;
+                if (c >= 2 * j + 2 && c < nct) {
+                    const bool cin = 16 * c + lo < b;
 #pragma unroll
-        for (int u = 0; u < 4; ++u) {
-            const int c = wave + 4 * u;
-            if (c >= 2 * j + 2 && c < nct) {
-                const bool cin = 16 * c + lo < b;
+                    for (int kq = 0; kq < kSub / 4; ++kq) {
+                        const int k = 4 * kq + hi;
+                        const T fv = (cin && k < sb) ? -f[u][kq] : T(0);
 #pragma unroll
-                for (int kq = 0; kq < kSub / 4; ++kq) {
-                    const int k = 4 * kq + hi;
-                    const T fv = (cin && k < sb) ? -f[u][kq] : T(0);
-#pragma unroll
-                    for (int q = 0; q < 2; ++q)
-                        acc[u][q] = Mma<T>::step(Xs[16 * q + lo][k], fv, acc[u][q]);
+                        for (int q = 0; q < 2; ++q)
+                            acc[u][q] = Mma<T>::step(xb[q][kq], fv, acc[u][q]);
+                    }
                 }
             }
         }
@@ -981,20 +989,12 @@ __device__ inline void trsm_right_strip(const T *lu, int64_t ld, int b, T *C, in
     T fa[4][kSub / 4], fb[4][kSub / 4], da[4], db[4];
     fetch_dinv(Dinv, b, 0, tid, da);
     fetch_f(0, fa);
-    for (int j = 0; kSub * j < b; j += 2) {
-        step(j, fa, fb, da, db);
-        if (kSub * (j + 1) < b) step(j + 1, fb, fa, db, da);
+    const int nsub = (b + kSub - 1) / kSub;
+    for (int j = 0; j < nsub; j += 2) {
+        step(j, fa, fb, da, db, j + 1 >= nsub);
+        if (j + 1 < nsub) step(j + 1, fb, fa, db, da, j + 2 >= nsub);
     }
-#pragma unroll
-    for (int u = 0; u < 4; ++u)
-#pragma unroll
-        for (int q = 0; q < 2; ++q)
-#pragma unroll
-            for (int r = 0; r < 4; ++r) {
-                const int c = wave + 4 * u;
-                const int row = 16 * q + Mma<T>::row(lane, r), col = 16 * c + lo;
-                if (c < nct && row < wrows && col < b) C[(r0 + row) * ldc + col] = acc[u][q][r];
-            }
+    store_x(nsub - 1);
 }
 
 // (FP64 holds a step's operands in flight at one workgroup per CU)
