@@ -722,7 +722,7 @@ __device__ inline void fetch_dinv(const T *Dinv, int b, int q, int tid, T (&d)[4
 
 // Strip `blk` (columns 32 blk ..) of the left solve, one workgroup of 256
 // threads.  Step i's factor panel L[32 i + 32 ..][32 i .. 32 i + 31] is read
-// row by row (coalesced) one step ahead into registers and staged in LDS; the
+// row by row, 16 bytes a load, one step ahead into registers and staged in LDS; the
 // four waves each apply the sub-block inverse to one 16 x 16 tile of rows i,
 // and X_i goes to memory from LDS at the start of the next step.
 template <typename T>
@@ -732,7 +732,10 @@ __device__ __attribute__((always_inline)) inline void trsm_left_strip(const T *l
     using acc_t = typename Mma<T>::acc;
     constexpr int BN = 32;
     constexpr int PR = kMaxBlock - kSub;  // rows of a step's factor panel, at most
-    constexpr int PL = PR * kSub / 256;   // its elements a thread stages
+    constexpr int PV = 16 / sizeof(T);    // elements of one 16-byte load
+    constexpr int PG = kSub / PV;         // 16-byte groups of a panel row
+    constexpr int PL = PR * PG / 256;     // groups a thread stages
+    using vec_t = T __attribute__((ext_vector_type(PV)));
     // row strides: a 16 x 4 operand read (rows by lane & 15, columns by
     // lane >> 4) is bank-conflict free at 34, a 4 x 16 one at 48
     __shared__ T Xa[kSub][48];            // rows of sub-block i of the strip (before)
@@ -771,17 +774,21 @@ __device__ __attribute__((always_inline)) inline void trsm_left_strip(const T *l
                 const bool in = t < nrt && row < b && col < wcols;
                 acc[u][j][r] = load_if(C, src[u][r] * ldc + c0 + col, in);
             }
-    // step i's factor panel, row-major and coalesced: element tid + 256 m is
-    // row (tid >> 5) + 8 m, column tid & 31 (raw loads, masked when staged)
-    const int pc = tid & 31, pr = tid >> 5;
-    T pf[PL], d[4];
+    // step i's factor panel, row-major and coalesced, 16 bytes a load: load m
+    // of a thread is group tid % PG of panel row tid / PG + (256 / PG) m
+    constexpr int PS = 256 / PG;
+    const int pc = PV * (tid % PG), pr = tid / PG;
+    vec_t pf[PL];
+    T d[4];
     auto fetch_panel = [&](int i) {
         const int i0 = i * kSub, rows = b - i0 - kSub;
-        const T *base = lu + (i0 + kSub + pr) * ld + i0 + pc;
+        if (rows <= 0) return;  // no panel (the staging stores zeros)
+        // rows past the panel load its first row instead and are zeroed when staged
+        const T *top = lu + (i0 + kSub) * ld + i0 + pc, *base = top + pr * ld;
 #pragma unroll
         for (int m = 0; m < PL; ++m) {
-            const int p = pr + 8 * m;
-            pf[m] = *(p < rows ? base + 8 * m * ld : lu);
+            const int p = pr + PS * m;
+            __builtin_memcpy(&pf[m], p < rows ? base + PS * m * ld : top, sizeof(vec_t));
         }
     };
     auto store_x = [&](int i) {  // X_i (in Xb) to rows 32 i .. of the strip
@@ -806,8 +813,9 @@ __device__ __attribute__((always_inline)) inline void trsm_left_strip(const T *l
         }
 #pragma unroll
         for (int m = 0; m < PL; ++m) {
-            const int p = pr + 8 * m;
-            Ls[p][pc] = p < rows ? pf[m] : T(0);
+            const int p = pr + PS * m;
+            const vec_t v = p < rows ? pf[m] : vec_t(0);
+            __builtin_memcpy(&Ls[p][pc], &v, sizeof(vec_t));
         }
 #pragma unroll
         for (int u = 0; u < 4; ++u) {
@@ -902,16 +910,18 @@ __device__ __attribute__((always_inline)) inline void trsm_right_strip(const T *
                 const int row = 16 * q + Mma<T>::row(lane, r), col = 16 * c + lo;
                 acc[u][q][r] = load_if(C, (r0 + row) * ldc + col, c < nct && row < wrows && col < b);
             }
+    // step j's factor rows U[32 j + k][16 c + lo] for the column tiles right of
+    // sub-block j (all 32 of its rows are then inside the block); a column past
+    // the block reads the block's last one and is masked where it is used
     auto fetch_f = [&](int j, T (&f)[4][kSub / 4]) {
-        const int j0 = j * kSub, sb = (b - j0) < kSub ? (b - j0) : kSub;
+        const int j0 = j * kSub;
 #pragma unroll
         for (int u = 0; u < 4; ++u) {
             const int c = wave + 4 * u, col = 16 * c + lo;
-            const bool right = c >= 2 * j + 2 && c < nct && col < b;
+            if (c >= 2 * j + 2 && c < nct) {
+                const T *p = lu + (j0 + hi) * ld + (col < b ? col : b - 1);
 #pragma unroll
-            for (int kq = 0; kq < kSub / 4; ++kq) {
-                const int k = 4 * kq + hi;
-                f[u][kq] = lu[(right && k < sb) ? (j0 + k) * ld + col : 0];
+                for (int kq = 0; kq < kSub / 4; ++kq) f[u][kq] = p[4 * kq * ld];
             }
         }
     };
