@@ -96,7 +96,11 @@ struct rmge_factors {
     hipEvent_t ev[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};
     hipStream_t side = nullptr;  // look-ahead stream (default priority)
     hipStream_t main = nullptr;  // set when the side stream owns reserved CUs
+    hipStream_t aux = nullptr;   // the reserved CUs' share of a Schur update
+    int cus_main = 0, cus_side = 0;
+    double aux_scale = 0.0;  // safety factor on the reserved CUs' share (0: none)
     hipEvent_t ev_narrow = nullptr, ev_panel = nullptr, ev_fork = nullptr, ev_join = nullptr;
+    hipEvent_t ev_aux = nullptr;
     // the bulk Schur updates' device time: an event pair around each launch
     // (created when the factorization has at most kUpdEvents steps)
     std::vector<hipEvent_t> upd_ev;
@@ -107,7 +111,11 @@ namespace {
 
 constexpr int kSub = 32;      // rows of the inverted diagonal sub-blocks
 constexpr int kUpdEvents = 512;  // steps of a factorization whose updates are timed
-constexpr int kSideCUs = 8;   // compute units reserved for the look-ahead stream
+// Compute units reserved for the look-ahead stream.  A queue masked to 248 of
+// the 256 units dispatches one-round grids as if it had 224 (the mask is
+// evened out over the 32 shader arrays), so reserving 32 costs the main
+// stream no more than reserving 8.
+constexpr int kSideCUs = 32;
 // Split-BF16 handles: trailing blocks of at least this many rows take the
 // three-term BF16 Schur update (smaller ones fill too few 256 x 256 tiles to
 // beat the FP32 kernels)
@@ -255,6 +263,29 @@ hipError_t factor_pivot_block(rmge_factors *f, T *a, int b, int64_t k0, T *Linv,
     return hipSuccess;
 }
 
+// Columns of a wide Schur update (r rows, w columns, depth b) handed to the
+// reserved compute units.  They are free once the side stream has factored the
+// next pivot block, about t_side after the narrow update; with Cm main and Cs
+// reserved units the two parts end together when the reserved share is
+// Cs / (Cm + Cs) * (1 - t_side / T), T the update's time on the main units
+// alone.  Rates and t_side are nominal (measured on the update kernels and
+// the pivot-block chain at block 256); aux_scale keeps the share on the safe
+// side, since the main stream waits for the reserved part.  (The two parts
+// share L2 and HBM bandwidth, so the main part slows a little while both run.)
+template <typename T>
+int64_t aux_columns(const rmge_factors *f, int64_t r, int64_t w, int b) {
+    if (f->aux == nullptr || f->aux_scale <= 0.0 || f->cus_side <= 0 || f->cus_main <= 0) return 0;
+    const double per_cu = sizeof(T) == 8 ? 2.3e11 : 4.4e11;  // update flop/s per compute unit
+    const double t_side = (sizeof(T) == 8 ? 220e-6 : 160e-6) * b / 256.0;
+    const double t_full = 2.0 * static_cast<double>(r) * static_cast<double>(w) * b /
+                          (per_cu * f->cus_main);
+    if (t_full <= t_side) return 0;
+    const double share = f->aux_scale * f->cus_side / static_cast<double>(f->cus_main + f->cus_side) *
+                         (1.0 - t_side / t_full);
+    const int64_t wa = static_cast<int64_t>(share * static_cast<double>(w)) / 128 * 128;
+    return wa < 128 ? 0 : (wa > w ? w : wa);
+}
+
 // Right-looking block elimination with no pivoting (eq. eqgenp applied to
 // pivot blocks of f->block columns) with one panel of look-ahead.  Step k:
 //   main stream:  (once the side stream has factored pivot block k)
@@ -268,6 +299,9 @@ hipError_t factor_pivot_block(rmge_factors *f, T *a, int b, int64_t k0, T *Linv,
 // reserved compute units (CU masks, same priority), because a wide update
 // keeps every register file of the others full and would starve it.
 // The update E - (D U_B^{-1})(L_B^{-1} C) is E - D B^{-1} C of eq. eqgenp.
+// Once the next pivot block is factored the reserved units are idle, so an
+// aux stream on them takes the last columns of the wide update (aux_columns);
+// the main stream waits for that part before the next step.
 // Pivoted variant: P_B B = L_B U_B inside the pivot block, the block row is
 // read through P_B (L_B^{-1} P_B C), the rows below are untouched, and one
 // pass at the end applies the exchanges to the multipliers left of each block.
@@ -293,9 +327,14 @@ hipError_t genp_blocked(rmge_factors *f) {
     HIP_TRY(factor_pivot_block<T>(f, a, static_cast<int>(n < nb ? n : nb), 0, Linv(0), Uinv(0),
                                   s0));
     int64_t step = 0;
+    bool aux_pending = false;  // the reserved units' part of the last wide update
     for (int64_t k = 0; k < n; k += nb, ++step) {
         const int b = static_cast<int>((n - k) < nb ? (n - k) : nb);
         if (k > 0) HIP_TRY(hipStreamWaitEvent(s0, f->ev_panel, 0));
+        if (aux_pending) {
+            HIP_TRY(hipStreamWaitEvent(s0, f->ev_aux, 0));
+            aux_pending = false;
+        }
         if (k + b >= n) break;
         const int64_t r = n - k - b;
         const int bn = static_cast<int>(r < nb ? r : nb);  // next panel width
@@ -312,21 +351,32 @@ hipError_t genp_blocked(rmge_factors *f) {
         HIP_TRY(hipEventRecord(f->ev_panel, s1));
         const bool bf16_upd = sizeof(T) == 4 && f->u16 != nullptr &&
                               (f->upd_terms == 1 || r >= kSplitUpdateMin);
-        const bool timed = r > bn && 2 * step + 1 < static_cast<int64_t>(f->upd_ev.size());
+        // columns bn .. bn + wm - 1 on the main stream, the last wa on the reserved units
+        const int64_t wa = (r > bn && !bf16_upd) ? aux_columns<T>(f, r, r - bn, b) : 0;
+        const int64_t wm = r - bn - wa;
+        if (wa > 0) {
+            HIP_TRY(hipStreamWaitEvent(f->aux, f->ev_panel, 0));
+            HIP_TRY(Prec<T>::gemm(kGemmUpdate, r, wa, b, T(-1), a21, ld, a12 + bn + wm, ld, T(1),
+                                  a22 + bn + wm, ld, abort, f->aux));
+            HIP_TRY(hipEventRecord(f->ev_aux, f->aux));
+            aux_pending = true;
+        }
+        const bool timed = wm > 0 && 2 * step + 1 < static_cast<int64_t>(f->upd_ev.size());
         if (timed) {
             HIP_TRY(hipEventRecord(f->upd_ev[2 * step], s0));
-            f->upd_flops += 2.0 * static_cast<double>(r) * static_cast<double>(r - bn) * b;
+            f->upd_flops += 2.0 * static_cast<double>(r) * static_cast<double>(wm) * b;
         }
-        if (r > bn && bf16_upd)
-            HIP_TRY(update_bf16(f->upd_terms, r, r - bn, b, reinterpret_cast<const float *>(a21),
+        if (wm > 0 && bf16_upd)
+            HIP_TRY(update_bf16(f->upd_terms, r, wm, b, reinterpret_cast<const float *>(a21),
                                 ld, reinterpret_cast<const float *>(a12 + bn), ld,
                                 reinterpret_cast<float *>(a22 + bn), ld, f->u16, f->uldk,
                                 f->urows, abort, s0));
-        else if (r > bn)
-            HIP_TRY(Prec<T>::gemm(kGemmUpdate, r, r - bn, b, T(-1), a21, ld, a12 + bn, ld, T(1),
+        else if (wm > 0)
+            HIP_TRY(Prec<T>::gemm(kGemmUpdate, r, wm, b, T(-1), a21, ld, a12 + bn, ld, T(1),
                                   a22 + bn, ld, abort, s0));
         if (timed) HIP_TRY(hipEventRecord(f->upd_ev[2 * step + 1], s0));
     }
+    if (aux_pending) HIP_TRY(hipStreamWaitEvent(s0, f->ev_aux, 0));
     if (f->pivot) HIP_TRY(permute_left<T>(a, ld, n, nb, f->piv, abort, s0));
     if (f->main) {
         HIP_TRY(hipEventRecord(f->ev_join, s0));
@@ -484,12 +534,13 @@ void free_handle(rmge_factors *f) {
         if (p) (void)hipFree(p);
     for (hipEvent_t &e : f->ev)
         if (e) (void)hipEventDestroy(e);
-    for (hipEvent_t e : {f->ev_narrow, f->ev_panel, f->ev_fork, f->ev_join})
+    for (hipEvent_t e : {f->ev_narrow, f->ev_panel, f->ev_fork, f->ev_join, f->ev_aux})
         if (e) (void)hipEventDestroy(e);
     for (hipEvent_t e : f->upd_ev)
         if (e) (void)hipEventDestroy(e);
     if (f->side) (void)hipStreamDestroy(f->side);
     if (f->main) (void)hipStreamDestroy(f->main);
+    if (f->aux) (void)hipStreamDestroy(f->aux);
     delete f;
 }
 
@@ -556,6 +607,12 @@ rmge_status alloc_handle(rmge_factors *f) {
         for (int c = 0; c < ncu; ++c) (c < side_cus ? ms : mm)[c / 32] |= 1u << (c % 32);
         RMGE_TRY(hipExtStreamCreateWithCUMask(&f->side, static_cast<uint32_t>(ms.size()), ms.data()));
         RMGE_TRY(hipExtStreamCreateWithCUMask(&f->main, static_cast<uint32_t>(mm.size()), mm.data()));
+        RMGE_TRY(hipExtStreamCreateWithCUMask(&f->aux, static_cast<uint32_t>(ms.size()), ms.data()));
+        RMGE_TRY(hipEventCreateWithFlags(&f->ev_aux, hipEventDisableTiming));
+        f->cus_side = side_cus;
+        f->cus_main = ncu - side_cus;
+        f->aux_scale = 0.9;  // RMGE_AUX_SCALE overrides (0: the main stream does every update)
+        if (const char *env = std::getenv("RMGE_AUX_SCALE")) f->aux_scale = std::atof(env);
     } else {
         RMGE_TRY(hipStreamCreateWithFlags(&f->side, hipStreamNonBlocking));
     }
