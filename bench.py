@@ -60,9 +60,10 @@ TRAFFIC_BF16 = {"n": 16384, "source": "k_gemm_bf16x2 + tile_coords (csrc/gemm.hi
 
 # the same (calibrated KiB) for the FFT product (k_fft_stockham, circulant multiplier,
 # n = 4096, the structured workload): profiles/k_fft_stockham_circulant_n4096_hbm_traffic.txt.  The
-# fingerprint covers the whole FFT source file.
+# fingerprint covers the whole FFT source file.  (Taken before the batch FFT rows were
+# force-inlined; the n = 4096 launch's machine code is the same before and after, labels aside.)
 TRAFFIC_FFT = {"n": 4096, "source": "csrc/fft.hip",
-               "sha256": "2726bbd8fb0eb5868ecdcff8a428b02b211c312258a4b4503bd03c16ca538258",
+               "sha256": "74eb5092895e730bf36ff0f7db055b31af4134d49626e02cba6cd007a406303f",
                "fetch_kib": 132395.1, "write_kib": 131328.0}
 
 
@@ -262,7 +263,9 @@ def rooflines(name, r, n):
                            "unit": "TFLOP/s", "frac": round(ach / peak, 4), "traffic": None,
                            "kernel": kern, "ms_per_launch": round(r["ms_update"] / steps, 4),
                            "launches": steps,
-                           "note": "algorithmic 2 r (r - b') b flops summed over the steps"}
+                           "note": "algorithmic 2 r w b flops of the main stream's launches, "
+                                   "summed over the steps (w: the columns of each wide update "
+                                   "the main stream does; the reserved units take the rest)"}
         if prec == "F32_BF16X2":  # six BF16 products per FP32-equivalent one
             lines["update"]["executed_frac"] = round(6 * ach / peak, 4)
     return lines
