@@ -71,6 +71,7 @@ struct rmge_factors {
     int64_t sinv_rows = 0;
     double *binv = nullptr;  // block inverses: L part, then U part (binv_rows rows each)
     int64_t binv_rows = 0;
+    bool binv_done = false;  // formed by the first one-RHS solve after a factorization
     int *piv = nullptr;  // pivoted variant: P M = L U with row t = row piv[t] of M
     DevStatus *st = nullptr;
     double *scal = nullptr;  // [0] max|U| [1] min|u_kk| [2] max|M| [3] ||A||_inf [4] ||A||_1
@@ -488,10 +489,7 @@ rmge_status run_factor(rmge_factors *f) {
         T *sl = static_cast<T *>(f->sinv);
         RMGE_TRY(diag_inverses<T>(static_cast<const T *>(f->lu), f->ld, f->n, sl,
                                   sl + f->sinv_rows * kSub, f->st, s));
-        double *bv = f->binv;
-        const int64_t part = f->binv_rows * 128;
-        RMGE_TRY(block_inverses128<T>(static_cast<const T *>(f->lu), f->ld, f->n, bv, bv + part,
-                                      bv + 2 * part, bv + 3 * part, s));
+        f->binv_done = false;  // the 128-row block inverses wait for a one-RHS solve
     }
     RMGE_TRY(hipMemcpyAsync(&f->host_st, f->st, sizeof(DevStatus), hipMemcpyDeviceToHost, s));
     RMGE_TRY(hipStreamSynchronize(s));
@@ -677,6 +675,11 @@ hipError_t tri_solves(rmge_factors *f, int64_t nrhs, bool adjoint) {
     const T *dfirst = adjoint ? Uinv : Linv, *dsecond = adjoint ? Linv : Uinv;
     if (nrhs == 1 && !adjoint) {  // 128-row blocks with the FP64 block inverses
         const int64_t part = f->binv_rows * 128;
+        if (!f->binv_done) {  // once per factorization, in stream order after it
+            HIP_TRY(block_inverses128<T>(lu, ld, n, f->binv, f->binv + part, f->binv + 2 * part,
+                                         f->binv + 3 * part, s));
+            f->binv_done = true;
+        }
         const double *bl = f->binv, *bu = bl + part, *wl = bl + 2 * part, *wu = bl + 3 * part;
         HIP_TRY(trsv128<T>(0, lu, ld, n, bl, wl, Y, X, 1, f->wsync, s));
         return trsv128<T>(1, lu, ld, n, bu, wu, X, Y, 1, f->wsync, s);
