@@ -502,19 +502,19 @@ __global__ __launch_bounds__(512) void k_leaf_genp(T *a, int64_t lda, int b, int
     const int tid = threadIdx.x, lane = tid & 63;
     const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
     if (tid == 0) s_fail = 0;
-    // the block into LDS: thread (tid & 127) takes a column, four rows a
-    // round, sixteen loads of a thread in flight together
+    // the block into LDS: thread (tid & 127) takes a column, rows lr, lr + 4,
+    // ..., all 32 of its loads in flight together (one memory round trip)
     const int lc = tid & 127, lr = tid >> 7;
-    for (int i0 = 0; i0 < b; i0 += 64) {
-        T v[16];
+    {
+        T v[kLeaf / 4];
 #pragma unroll
-        for (int u = 0; u < 16; ++u) {
-            const int i = i0 + 4 * u + lr;
+        for (int u = 0; u < kLeaf / 4; ++u) {
+            const int i = 4 * u + lr;
             v[u] = load_if(a, static_cast<int64_t>(i) * lda + lc, i < b && lc < b);
         }
 #pragma unroll
-        for (int u = 0; u < 16; ++u) {
-            const int i = i0 + 4 * u + lr;
+        for (int u = 0; u < kLeaf / 4; ++u) {
+            const int i = 4 * u + lr;
             if (i < b && lc < b) S[i * LD + lc] = v[u];
         }
     }
