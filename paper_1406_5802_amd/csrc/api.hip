@@ -404,9 +404,12 @@ hipError_t draw_multiplier(rmge_factors *f) {
         return hipSuccess;
     default: {
         if (f->kind == RMGE_MULT_UNITARY_CIRCULANT) {
-            // phases into the second half of params, the first column into the first
+            // phases into the second half of params; with period m = n the
+            // spectrum follows from them directly, else the first column goes
+            // into the first half and is transformed like any circulant's
             HIP_TRY(launch_uniforms_f64(f->params + n, n, f->seed,
                                         static_cast<uint64_t>(f->kind), s));
+            if (f->m == n) return unitary_spectrum(f->params + n, n, f->hhat, s);
             HIP_TRY(unitary_column(f->params + n, n, f->params, s));
         } else {
             HIP_TRY(launch_normals_f64(f->params, f->kind == RMGE_MULT_CIRCULANT ? n : 2 * n - 1,

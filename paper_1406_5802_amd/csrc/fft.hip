@@ -453,6 +453,25 @@ __global__ __launch_bounds__(256) void k_unitary_column(const double *__restrict
     c[k] = v * inv_n;
 }
 
+// The unitary circulant's half spectrum straight from its phases, for the
+// period m = n (a power of two).  Pairing u_f = e^{2 pi i phi_f} with its
+// conjugate partner as in the column formula above (Section 6, Example exunc)
+// makes the column c = (1/n) sum_f u_f e^{-2 pi i f k / n}, whose DFT is
+// conj(u_f): hhat_f = e^{-2 pi i phi_f} for 0 < f < n/2, and the real
+// hhat_0 = s_0, hhat_{n/2} = s_{n/2} (+1 for a phase below 1/2, else -1).
+__global__ __launch_bounds__(256) void k_unitary_spectrum(const double *__restrict__ phi, int L,
+                                                          cplx *__restrict__ hhat) {
+    for (int f = blockIdx.x * blockDim.x + threadIdx.x; f <= L; f += gridDim.x * blockDim.x) {
+        if (f == 0 || f == L) {
+            hhat[f] = {phi[f] < 0.5 ? 1.0 : -1.0, 0.0};
+        } else {
+            double sn, cs;
+            sincospi(2.0 * phi[f], &sn, &cs);
+            hhat[f] = {cs, -sn};
+        }
+    }
+}
+
 // ---------------------------------------------------------------- batches
 // Circulant multipliers of many systems (n_s <= 1024, so m_s <= 2048 and a
 // row fits one wave).  logl[s] = log2(m_s / 2); the twiddle table of period
@@ -587,6 +606,14 @@ hipError_t fft_twiddles(int m, double *tw, hipStream_t s) {
     const int L = m / 2;
     hipLaunchKernelGGL(k_twiddles, dim3((L + 256) / 256), dim3(256), 0, s, L,
                        reinterpret_cast<cplx *>(tw));
+    return hipGetLastError();
+}
+
+hipError_t unitary_spectrum(const double *phi, int64_t n, double *hhat, hipStream_t s) {
+    if (n < 2 || n > 16384 || (n & (n - 1)) != 0) return hipErrorInvalidValue;
+    const int L = static_cast<int>(n / 2);
+    hipLaunchKernelGGL(k_unitary_spectrum, dim3(static_cast<unsigned>((L + 256) / 256)), dim3(256),
+                       0, s, phi, L, reinterpret_cast<cplx *>(hhat));
     return hipGetLastError();
 }
 

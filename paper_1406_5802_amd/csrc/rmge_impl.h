@@ -272,6 +272,9 @@ hipError_t fft_twiddles(int m, double *tw, hipStream_t s);
 // u_{n/2} = +1 if their phase is below 1/2 else -1; c = Omega^{-1} u,
 // c_k = (1/n) sum_j u_j e^{-2 pi i j k / n}.
 hipError_t unitary_column(const double *phi, int64_t n, double *c, hipStream_t s);
+// The unitary circulant's half spectrum (m = n, a power of two, 2 <= n <= 16384)
+// in closed form from its n phases: n/2 + 1 complex values into hhat.
+hipError_t unitary_spectrum(const double *phi, int64_t n, double *hhat, hipStream_t s);
 hipError_t fft_embed(int kind, const double *params, int64_t n, int m, double *h, hipStream_t s);
 // Circulant multipliers of a batch (orders n_s <= 1024, periods m_s = 2^(logl_s + 1)
 // <= 2048): per system, the period-m kernel h (h_pool + h_off[s]) from the first

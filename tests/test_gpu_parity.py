@@ -120,10 +120,12 @@ def test_precondition_matches_oracle(rmge, kind, n):
     _check_product(kind, n, A, M, 77)
 
 
-@pytest.mark.parametrize("kind,n", [(3, 1100), (2, 4096), (4, 3000), (2, 700), (3, 4000)])
+@pytest.mark.parametrize("kind,n", [(3, 1100), (2, 4096), (4, 3000), (2, 700), (3, 4000),
+                                    (4, 4096), (4, 16384)])
 def test_precondition_multiwave_rows(rmge, kind, n):
-    # periods m = 4096 .. 8192: one row spans several waves of a workgroup;
-    # 16 sampled rows against the oracle's plain product
+    # periods m = 4096 .. 16384: one row spans several waves of a workgroup;
+    # 16 sampled rows against the oracle's plain product (the unitary kind at a
+    # power of two takes its spectrum in closed form from the phases)
     A = np.random.default_rng(n).standard_normal((n, n)) / np.sqrt(n)
     M = host(rmge.precondition(dev(A), kind, seed=31))
     rows = np.random.default_rng(n + 1).integers(0, n, 16)
