@@ -744,19 +744,20 @@ rmge_status residual_eta(rmge_factors *f, const double *B, int64_t ldb, int64_t 
     hipStream_t s = f->stream;
     double *R = f->wr, *nrm = f->wnorm;
     RMGE_TRY((convert_2d<double, double>(B, ldb, R, nrhs, n, nrhs, s)));
+    // ||A||_inf, once per factorization: from the residual's own reads of A
+    // when its product takes at most four right-hand sides, else a pass of its own
+    const bool fuse_norm = !f->anorm_done && nrhs <= 4;
+    if (!f->anorm_done) RMGE_TRY(fill_f64(f->scal + 3, 1, 0.0, s));
     for (int64_t g = 0; g < nrhs; g += 16) {
         const int nr = static_cast<int>((nrhs - g) < 16 ? (nrhs - g) : 16);
         RMGE_TRY((gemv_n<double, double, double>(n, n, -1.0, f->A, f->lda, X + g, ldx, 1.0, R + g,
-                                                 nrhs, nr, s)));
+                                                 nrhs, nr, s, fuse_norm ? f->scal + 3 : nullptr)));
     }
     RMGE_TRY(fill_f64(nrm, 3 * nrhs, 0.0, s));
     RMGE_TRY(colmax_abs(R, nrhs, n, static_cast<int>(nrhs), nrm, s));
     RMGE_TRY(colmax_abs(X, ldx, n, static_cast<int>(nrhs), nrm + nrhs, s));
     RMGE_TRY(colmax_abs(B, ldb, n, static_cast<int>(nrhs), nrm + 2 * nrhs, s));
-    if (!f->anorm_done) {
-        RMGE_TRY(fill_f64(f->scal + 3, 1, 0.0, s));
-        RMGE_TRY(norm_inf(f->A, f->lda, n, f->scal + 3, s));
-    }
+    if (!f->anorm_done && !fuse_norm) RMGE_TRY(norm_inf(f->A, f->lda, n, f->scal + 3, s));
     std::vector<double> h(static_cast<size_t>(3 * nrhs));
     RMGE_TRY(hipMemcpyAsync(h.data(), nrm, sizeof(double) * 3 * nrhs, hipMemcpyDeviceToHost, s));
     if (!f->anorm_done)

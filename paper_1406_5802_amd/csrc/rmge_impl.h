@@ -218,11 +218,12 @@ hipError_t bscale(double *dst, const double *src, int64_t lds, int64_t n, int m,
 hipError_t scale_copy(double *dst, const double *src, int64_t lds, int64_t n, double alpha,
                       hipStream_t s);
 // y = beta * y + alpha * M x  (rows of M; FP64 accumulation).  M: rows x cols (ldm),
-// x: cols x nrhs (ldx), y: rows x nrhs (ldy).
+// x: cols x nrhs (ldx), y: rows x nrhs (ldy).  rowmax (nrhs <= 4 only): also
+// max(*rowmax, ||M||_inf) into *rowmax, from the same reads of M.
 template <typename TM, typename TX, typename TY>
 hipError_t gemv_n(int64_t rows, int64_t cols, double alpha, const TM *Mat, int64_t ldm,
                   const TX *x, int64_t ldx, double beta, TY *y, int64_t ldy, int nrhs,
-                  hipStream_t s);
+                  hipStream_t s, double *rowmax = nullptr);
 // y = M^T x (two passes, deterministic).  work: >= ceil(rows/256) * cols * nrhs doubles.
 template <typename TM, typename TX, typename TY>
 hipError_t gemv_t(int64_t rows, int64_t cols, const TM *Mat, int64_t ldm, const TX *x,

@@ -708,17 +708,24 @@ __global__ void k_trsv_prep(double *X, int64_t ldx, int64_t n, int nr, int *sync
         X[(e / nr) * ldx + e % nr] = __builtin_bit_cast(double, kMark);
 }
 
-// y = beta y + alpha M x, FP64 accumulation; one wave per two rows.
+__device__ inline void atomic_max_nonneg(double *addr, double v) {
+    atomicMax(reinterpret_cast<unsigned long long *>(addr),
+              static_cast<unsigned long long>(__double_as_longlong(v)));
+}
+
+// y = beta y + alpha M x, FP64 accumulation; one wave per two rows.  With
+// rowmax != null also the largest row sum of |M| (||M||_inf) into *rowmax,
+// from the same reads.
 template <typename TM, typename TX, typename TY, int NR>
 __global__ __launch_bounds__(256) void k_gemv_n(int64_t rows, int64_t cols, double alpha,
                                                 const TM *__restrict__ Mat, int64_t ldm,
                                                 const TX *__restrict__ x, int64_t ldx, double beta,
-                                                TY *y, int64_t ldy, int nrhs) {
+                                                TY *y, int64_t ldy, int nrhs, double *rowmax) {
     const int lane = threadIdx.x & 63;
     const int64_t row0 = (static_cast<int64_t>(blockIdx.x) * 4 + (threadIdx.x >> 6)) * 2;
     if (row0 >= rows) return;
     const bool two = row0 + 1 < rows;
-    double a0[NR], a1[NR];
+    double a0[NR], a1[NR], s0 = 0.0, s1 = 0.0;
 #pragma unroll
     for (int r = 0; r < NR; ++r) a0[r] = a1[r] = 0.0;
     const TM *m0 = Mat + row0 * ldm;
@@ -730,6 +737,11 @@ __global__ __launch_bounds__(256) void k_gemv_n(int64_t rows, int64_t cols, doub
         for (int u = 0; u < 4; ++u) {
             p0[u] = static_cast<double>(m0[c + 64 * u]);
             p1[u] = static_cast<double>(m1[c + 64 * u]);
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            s0 += fabs(p0[u]);
+            s1 += fabs(p1[u]);
         }
         // (right-hand sides past nrhs read x[0] and accumulate zeros: no
         // load sits under a branch)
@@ -745,6 +757,8 @@ __global__ __launch_bounds__(256) void k_gemv_n(int64_t rows, int64_t cols, doub
     }
     for (; c < cols; c += 64) {
         const double p0 = static_cast<double>(m0[c]), p1 = static_cast<double>(m1[c]);
+        s0 += fabs(p0);
+        s1 += fabs(p1);
 #pragma unroll
         for (int r = 0; r < NR; ++r) {
             const double xv = static_cast<double>(load_if(x, c * ldx + r, r == 0 || r < nrhs));
@@ -758,6 +772,13 @@ __global__ __launch_bounds__(256) void k_gemv_n(int64_t rows, int64_t cols, doub
             a0[r] += __shfl_xor(a0[r], off);
             a1[r] += __shfl_xor(a1[r], off);
         }
+    }
+    if (rowmax != nullptr) {
+        for (int off = 32; off > 0; off >>= 1) {
+            s0 += __shfl_xor(s0, off);
+            s1 += __shfl_xor(s1, off);
+        }
+        if (lane == 0) atomic_max_nonneg(rowmax, two ? fmax(s0, s1) : s0);
     }
     if (lane == 0) {
 #pragma unroll
@@ -815,11 +836,6 @@ __global__ void k_gemv_t_sum(int64_t chunks, int64_t cols, const double *work, T
         for (int64_t k = 0; k < chunks; ++k) s += work[(k * cols + c) * nrhs + r];
         y[c * ldy + r] = static_cast<TY>(s);
     }
-}
-
-__device__ inline void atomic_max_nonneg(double *addr, double v) {
-    atomicMax(reinterpret_cast<unsigned long long *>(addr),
-              static_cast<unsigned long long>(__double_as_longlong(v)));
 }
 
 // norms[r] = max(norms[r], max_i |v[i][r]|); grid.y = r.
@@ -1125,23 +1141,23 @@ hipError_t trsv128(int mode, const T *LU, int64_t ld, int64_t n, const double *D
 template <typename TM, typename TX, typename TY>
 hipError_t gemv_n(int64_t rows, int64_t cols, double alpha, const TM *Mat, int64_t ldm,
                   const TX *x, int64_t ldx, double beta, TY *y, int64_t ldy, int nrhs,
-                  hipStream_t s) {
+                  hipStream_t s, double *rowmax) {
     if (rows <= 0 || nrhs <= 0) return hipSuccess;
-    if (nrhs > 16) return hipErrorInvalidValue;
+    if (nrhs > 16 || (rowmax != nullptr && nrhs > 4)) return hipErrorInvalidValue;
     const int64_t grid = (rows + 7) / 8;
     if (nrhs == 1)
         hipLaunchKernelGGL((k_gemv_n<TM, TX, TY, 1>), dim3(static_cast<unsigned>(grid)), dim3(256),
-                           0, s, rows, cols, alpha, Mat, ldm, x, ldx, beta, y, ldy, nrhs);
+                           0, s, rows, cols, alpha, Mat, ldm, x, ldx, beta, y, ldy, nrhs, rowmax);
     else if (nrhs <= 4)
         hipLaunchKernelGGL((k_gemv_n<TM, TX, TY, 4>), dim3(static_cast<unsigned>(grid)), dim3(256),
-                           0, s, rows, cols, alpha, Mat, ldm, x, ldx, beta, y, ldy, nrhs);
+                           0, s, rows, cols, alpha, Mat, ldm, x, ldx, beta, y, ldy, nrhs, rowmax);
     else if constexpr (sizeof(TX) == 8 && sizeof(TY) == 8)  // FP64 vectors: matrix cores
         return gemm_skinny<TM>(rows, cols, alpha, Mat, ldm, reinterpret_cast<const double *>(x),
                                ldx, beta, reinterpret_cast<double *>(y), ldy, nrhs, s);
     else
         hipLaunchKernelGGL((k_gemv_n<TM, TX, TY, 16>), dim3(static_cast<unsigned>(grid)),
                            dim3(256), 0, s, rows, cols, alpha, Mat, ldm, x, ldx, beta, y, ldy,
-                           nrhs);
+                           nrhs, nullptr);
     return hipGetLastError();
 }
 
@@ -1377,13 +1393,13 @@ template hipError_t trsv_full<float>(int, const float *, int64_t, int64_t, const
                                      const double *, double *, int64_t, int, int *, hipStream_t);
 template hipError_t gemv_n<double, double, double>(int64_t, int64_t, double, const double *,
                                                    int64_t, const double *, int64_t, double,
-                                                   double *, int64_t, int, hipStream_t);
+                                                   double *, int64_t, int, hipStream_t, double *);
 template hipError_t gemv_n<float, float, double>(int64_t, int64_t, double, const float *, int64_t,
                                                  const float *, int64_t, double, double *, int64_t,
-                                                 int, hipStream_t);
+                                                 int, hipStream_t, double *);
 template hipError_t gemv_n<float, double, double>(int64_t, int64_t, double, const float *,
                                                   int64_t, const double *, int64_t, double,
-                                                  double *, int64_t, int, hipStream_t);
+                                                  double *, int64_t, int, hipStream_t, double *);
 template hipError_t gemv_t<double, double, double>(int64_t, int64_t, const double *, int64_t,
                                                    const double *, int64_t, double *, int64_t, int,
                                                    double *, hipStream_t);
