@@ -12,7 +12,7 @@
 //     held in registers, pivot by pivot);
 //   * k_diag_inv: the inverses of the 32 x 32 diagonal sub-blocks of the two
 //     triangular factors of a factored block;
-//   * k_trsm_left / k_trsm_right: the off-diagonal blocks of eq. eqgenp,
+//   * k_trsm_pair: the off-diagonal blocks of eq. eqgenp,
 //     L_B^{-1} C and D U_B^{-1} (their product is D B^{-1} C), each done in
 //     place by blocked substitution on the matrix cores: the 32 x 32 diagonal
 //     sub-blocks are applied through their inverses, the rest as plain
@@ -1007,35 +1007,18 @@ __device__ __attribute__((always_inline)) inline void trsm_right_strip(const T *
     store_x(nsub - 1);
 }
 
-// (FP64 holds a step's operands in flight at one workgroup per CU)
-template <typename T>
-__global__ __launch_bounds__(256, sizeof(T) == 8 ? 1 : 2) void k_trsm_left(
-    const T *lu, int64_t ld, int b, T *C, int64_t ldc, int64_t count, const T *Dinv,
-    const int *abort, const int *rowsrc, int64_t rowbase) {
-    if (abort != nullptr && *abort != 0) return;
-    __builtin_amdgcn_s_setprio(2);  // on the panel's critical path, beside the update GEMM
-    trsm_left_strip<T>(lu, ld, b, C, ldc, count, Dinv, rowsrc, rowbase, blockIdx.x);
-}
-
-template <typename T>
-__global__ __launch_bounds__(256, sizeof(T) == 8 ? 1 : 2) void k_trsm_right(
-    const T *lu, int64_t ld, int b, T *C, int64_t ldc, int64_t count, const T *Dinv,
-    const int *abort) {
-    if (abort != nullptr && *abort != 0) return;
-    __builtin_amdgcn_s_setprio(2);
-    trsm_right_strip<T>(lu, ld, b, C, ldc, count, Dinv, blockIdx.x);
-}
-
 // Both solves of one pivot block in one launch (they touch disjoint blocks
 // and only read the factors): workgroups below `nl` take the strips of
-// L_B^{-1} P Cl, the others those of Cr U_B^{-1}.
+// L_B^{-1} P Cl, the others those of Cr U_B^{-1}.  FP64 keeps a step's
+// operands in flight at one workgroup per CU (the left solve's staged panel
+// also fills most of the LDS); FP32 fits two.
 template <typename T>
 __global__ __launch_bounds__(256, sizeof(T) == 8 ? 1 : 2) void k_trsm_pair(
     const T *lu, int64_t ld, int b, T *Cl, int64_t ldcl, int64_t countl, const T *Linv,
     const int *rowsrc, int64_t rowbase, T *Cr, int64_t ldcr, int64_t countr, const T *Uinv,
     const int *abort, int64_t nl) {
     if (*abort != 0) return;
-    __builtin_amdgcn_s_setprio(2);
+    __builtin_amdgcn_s_setprio(2);  // on the panel's critical path, beside the update GEMM
     const int64_t g = blockIdx.x;
     if (g < nl)
         trsm_left_strip<T>(lu, ld, b, Cl, ldcl, countl, Linv, rowsrc, rowbase, g);
@@ -1203,23 +1186,6 @@ hipError_t diag_inverses(const T *a, int64_t lda, int64_t n, T *Linv, T *Uinv, c
 }
 
 template <typename T>
-hipError_t trsm(int side, const T *lu, int64_t ld, int b, T *C, int64_t ldc, int64_t count,
-                const T *Dinv, const int *abort, hipStream_t s, const int *rowsrc,
-                int64_t rowbase) {
-    if (b < 1 || b > kMaxBlock) return hipErrorInvalidValue;
-    if (count <= 0) return hipSuccess;
-    if (side != 0 && rowsrc) return hipErrorInvalidValue;
-    const unsigned grid = static_cast<unsigned>((count + 31) / 32);
-    if (side == 0)
-        hipLaunchKernelGGL(k_trsm_left<T>, dim3(grid), dim3(256), 0, s, lu, ld, b, C, ldc, count,
-                           Dinv, abort, rowsrc, rowbase);
-    else
-        hipLaunchKernelGGL(k_trsm_right<T>, dim3(grid), dim3(256), 0, s, lu, ld, b, C, ldc, count,
-                           Dinv, abort);
-    return hipGetLastError();
-}
-
-template <typename T>
 hipError_t trsm_pair(const T *lu, int64_t ld, int b, T *Cl, int64_t ldcl, int64_t countl,
                      const T *Linv, const int *rowsrc, int64_t rowbase, T *Cr, int64_t ldcr,
                      int64_t countr, const T *Uinv, const int *abort, hipStream_t s) {
@@ -1298,10 +1264,6 @@ template hipError_t diag_inverses<double>(const double *, int64_t, int64_t, doub
                                           const DevStatus *, hipStream_t);
 template hipError_t diag_inverses<float>(const float *, int64_t, int64_t, float *, float *,
                                          const DevStatus *, hipStream_t);
-template hipError_t trsm<double>(int, const double *, int64_t, int, double *, int64_t, int64_t,
-                                 const double *, const int *, hipStream_t, const int *, int64_t);
-template hipError_t trsm<float>(int, const float *, int64_t, int, float *, int64_t, int64_t,
-                                const float *, const int *, hipStream_t, const int *, int64_t);
 template hipError_t trsm_pair<double>(const double *, int64_t, int, double *, int64_t, int64_t,
                                       const double *, const int *, int64_t, double *, int64_t,
                                       int64_t, const double *, const int *, hipStream_t);

@@ -130,17 +130,11 @@ hipError_t diag_inverses(const T *a, int64_t lda, int64_t n, T *Linv, T *Uinv, c
                          hipStream_t s);
 // In-place triangular solves with the factored pivot block at `lu` (width
 // b <= kMaxBlock), by blocked substitution with the compact 32 x 32 diagonal
-// inverses in Dinv:
-//   side 0: C (b x count, ldc) <- L^{-1} P C    (Dinv = Linv; row t of P C is
-//           row rowsrc[t] - rowbase of C, or row t when rowsrc is null)
-//   side 1: C (count x b, ldc) <- C U^{-1}      (Dinv = Uinv; rowsrc must be null)
-template <typename T>
-hipError_t trsm(int side, const T *lu, int64_t ld, int b, T *C, int64_t ldc, int64_t count,
-                const T *Dinv, const int *abort, hipStream_t s, const int *rowsrc = nullptr,
-                int64_t rowbase = 0);
-// Both of the above for one pivot block in a single launch: Cl (b x countl)
-// <- L^{-1} P Cl and Cr (countr x b) <- Cr U^{-1}.  The two blocks must not
-// overlap; abort must not be null.
+// inverses Linv / Uinv, both in one launch:
+//   Cl (b x countl, ldcl) <- L^{-1} P Cl   (row t of P Cl is row rowsrc[t] -
+//                                          rowbase of Cl, or row t when rowsrc is null)
+//   Cr (countr x b, ldcr) <- Cr U^{-1}
+// The two blocks must not overlap; abort must not be null.
 template <typename T>
 hipError_t trsm_pair(const T *lu, int64_t ld, int b, T *Cl, int64_t ldcl, int64_t countl,
                      const T *Linv, const int *rowsrc, int64_t rowbase, T *Cr, int64_t ldcr,
