@@ -145,7 +145,11 @@ typedef struct {
 /* Factor A H = L U with the defaults: FP64, lda = n, default stream.
  * A: device, n x n row-major.  kind: rmge_mult.  seed: the multiplier's
  * random-number seed.  block: panel width, 1..256 (0 selects 256; 1 is
- * column-by-column GENP).  On success *out receives a new handle. */
+ * column-by-column GENP).  On success *out receives a new handle.
+ * Environment, read when a handle is created: RMGE_SIDE_CUS, the compute
+ * units reserved for the look-ahead stream (default 32; 0: none, one shared
+ * pool); RMGE_AUX_SCALE, the safety factor on their share of each wide Schur
+ * update once the next pivot block is factored (default 0.9; 0: none). */
 rmge_status rmge_factor(const double *A, int64_t n, int32_t kind, uint64_t seed, int32_t block,
                         rmge_factors **out);
 
@@ -246,11 +250,13 @@ rmge_status rmge_factor_times(const rmge_factors *f, double *ms3);
 
 /* The bulk Schur updates of the last factorization (eq. eqgenp: the trailing
  * block's update by the panel beyond the next pivot block, one launch per
- * step): their summed device time in ms (HIP events around each launch on
- * the elimination's stream; 0 when the factorization had more than 512 steps
- * or broke down) and their algorithmic flops, sum of 2 r (r - b') b over the
- * steps (r trailing rows, b' the next panel's width, b this step's).  Host
- * only; no device work. */
+ * step on the elimination's main stream): their summed device time in ms
+ * (HIP events around each of those launches; 0 when the factorization had
+ * more than 512 steps or broke down) and their algorithmic flops, sum of
+ * 2 r w b over the steps (r trailing rows, w the columns the main stream's
+ * launch updates: the r - b' beyond the next panel of width b', less the
+ * last columns given to the reserved compute units; b this step's width).
+ * Host only; no device work. */
 rmge_status rmge_factor_update_time(const rmge_factors *f, double *ms, double *flops);
 
 /* Copy the packed factors (unit L strictly below the diagonal, U on and above)
