@@ -111,8 +111,9 @@ class Factors:
         return {"ms_multiplier": ms[0], "ms_product": ms[1], "ms_factor": ms[2]}
 
     def update_time(self):
-        """(ms, flops) of the last factorization's bulk Schur updates (HIP events
-        around each launch), with no device work."""
+        """(ms, flops) of the last factorization's bulk Schur updates on the main
+        stream (HIP events around each launch; the columns handed to the
+        reserved compute units are not counted), with no device work."""
         rc, ms, fl = _rmge.rmge_factor_update_time(self._h)
         if rc:
             raise RMGEError(rc, "rmge_factor_update_time")
