@@ -149,7 +149,7 @@ typedef struct {
  * Environment, read when a handle is created: RMGE_SIDE_CUS, the compute
  * units reserved for the look-ahead stream (default 32; 0: none, one shared
  * pool); RMGE_AUX_SCALE, the safety factor on their share of each wide Schur
- * update once the next pivot block is factored (default 0.9; 0: none). */
+ * update once the next pivot block is factored (default 1.0; 0: none). */
 rmge_status rmge_factor(const double *A, int64_t n, int32_t kind, uint64_t seed, int32_t block,
                         rmge_factors **out);
 

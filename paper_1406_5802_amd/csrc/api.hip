@@ -270,9 +270,10 @@ hipError_t factor_pivot_block(rmge_factors *f, T *a, int b, int64_t k0, T *Linv,
 // reserved units the two parts end together when the reserved share is
 // Cs / (Cm + Cs) * (1 - t_side / T), T the update's time on the main units
 // alone.  Rates and t_side are nominal (measured on the update kernels and
-// the pivot-block chain at block 256); aux_scale keeps the share on the safe
-// side, since the main stream waits for the reserved part.  (The two parts
-// share L2 and HBM bandwidth, so the main part slows a little while both run.)
+// the pivot-block chain at block 256); aux_scale scales the share (1 measured
+// best against 0.9 and 1.1; the main stream waits for the reserved part, so a
+// share too large costs more than one too small).  The two parts share L2 and
+// HBM bandwidth, so the main part slows a little while both run.
 template <typename T>
 int64_t aux_columns(const rmge_factors *f, int64_t r, int64_t w, int b) {
     if (f->aux == nullptr || f->aux_scale <= 0.0 || f->cus_side <= 0 || f->cus_main <= 0) return 0;
@@ -612,7 +613,7 @@ rmge_status alloc_handle(rmge_factors *f) {
         RMGE_TRY(hipEventCreateWithFlags(&f->ev_aux, hipEventDisableTiming));
         f->cus_side = side_cus;
         f->cus_main = ncu - side_cus;
-        f->aux_scale = 0.9;  // RMGE_AUX_SCALE overrides (0: the main stream does every update)
+        f->aux_scale = 1.0;  // RMGE_AUX_SCALE overrides (0: the main stream does every update)
         if (const char *env = std::getenv("RMGE_AUX_SCALE")) f->aux_scale = std::atof(env);
     } else {
         RMGE_TRY(hipStreamCreateWithFlags(&f->side, hipStreamNonBlocking));
